@@ -1,0 +1,156 @@
+/*
+ * pme.h -- C ABI of the MI355X (gfx950) differentiable particle-mesh Ewald
+ * for per-atom charges q and point dipoles mu.
+ *
+ * What is computed (paper: "Differentiable Particle-Mesh Ewald with Cartesian
+ * Tensor Message Passing ...", Sec. 2.3):
+ *
+ *   rho(n)  = sum_i sum_stencil [ q_i W + sum_a N_a (mu_i . C^-1[:,a]) dW/dx_a ]
+ *                                                       (Eq. charge_dipole_assign)
+ *             W = M_p(x_x - n_x) M_p(x_y - n_y) M_p(x_z - n_z), x = N * frac(r C^-1),
+ *             M_p the centered cardinal B-spline of order p (Sec. 2.3.2, Eq. w3d)
+ *   phi     = IDFT[ g(k) DFT[rho] ]  (unnormalised inverse, real part)
+ *             g = 4 pi/|k|^2 exp(-|k|^2/4a^2) / |B(n)|^(2 gamma), g(0) = 0,
+ *             B(n) = prod_a sinc^p(n_a/N_a), k = sum_a n_a b_a, b = 2 pi C^-T
+ *                                      (Eqs. fft, Bk, influence, green, potential_k,
+ *                                       ifft)
+ *   E_recip = (1/2V) sum_n rho(n) phi(n)                     (Eq. energy_recip)
+ *   E_self  = -a/sqrt(pi) sum q^2 - 2a^3/(3 sqrt(pi)) sum |mu|^2
+ *                                                  (Eqs. self_q, self_mu)
+ *   E^lr    = E_recip + E_self                               (Eq. E_lr_total)
+ *
+ * and its exact derivatives (what autograd of the paper's pipeline yields,
+ * Sec. 2.3.5 and Eq. forces): dE/dr, dE/dq, dE/dmu, and the Hessian-vector
+ * product, which is also the force-loss double backward of training
+ * (Eq. loss).
+ *
+ * Units: positions in Angstrom, q in e, mu in e*Angstrom; energies are
+ * e^2/Angstrom times `prefactor` (14.3996454784 gives eV).
+ *
+ * Conventions for every call:
+ *   - Device pointers are HIP device memory (hipMalloc / torch CUDA tensors),
+ *     contiguous, float32 unless stated; the caller owns them and keeps them
+ *     alive until the stream work completes.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *   - No call synchronises the stream except pme_status.  Device-detected
+ *     problems (non-finite positions or box) are reported by pme_status.
+ *   - Outputs are overwritten, never accumulated.  A NULL output is skipped.
+ *   - A plan owns all of its workspaces; it is not thread safe and must not be
+ *     used by two streams at once.
+ *   - Return codes are PME_OK or a negative PME_E* value; pme_strerror maps
+ *     them to text.  Host-side checks run before anything is launched, so a
+ *     failed call leaves the outputs untouched.
+ */
+#ifndef PME_MI355X_H
+#define PME_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define PME_OK          0
+#define PME_EINVAL     -1   /* NULL required pointer, n < 0, bad flag or strategy */
+#define PME_EORDER     -2   /* assignment order p outside 1..7                    */
+#define PME_EMESH      -3   /* a mesh dimension is not 5-smooth or outside 2..1024 */
+#define PME_EALPHA     -4   /* alpha <= 0, non-finite alpha/gamma/prefactor, gamma < 0 */
+#define PME_ECAPACITY  -5   /* n > max_atoms of the plan                          */
+#define PME_ENOMEM     -6   /* device allocation failed                           */
+#define PME_EHIP       -7   /* a HIP runtime call failed (see pme_last_hip_error) */
+#define PME_ENONFINITE -8   /* device saw NaN/Inf in positions or box (pme_status) */
+
+/* ---- plan flags ------------------------------------------------------ */
+/* Keep phi (the potential mesh) of the last pme_forward; a following
+ * pme_backward with the same (pos, q, mu, box) then reuses it instead of
+ * recomputing it.  The caller asserts the inputs are unchanged. */
+#define PME_F_KEEP_PHI  1
+
+/* ---- mesh strategies for pme_mesh_dims (Sec. 2.3.1) ------------------- */
+#define PME_MESH_POW2    0   /* N = 2^ceil(log2 N_target)                       */
+#define PME_MESH_SMOOTH  1   /* smallest N >= N_target with factors {2,3,5}      */
+#define PME_MESH_CEIL    2   /* N = N_target (may be rejected by pme_plan_create) */
+
+typedef struct pme_plan_s* pme_plan_t;
+
+typedef struct {
+    int32_t mesh[3];          /* N_x, N_y, N_z: 5-smooth, each in 2..1024        */
+    int32_t order;            /* assignment order p, 1..7                         */
+    int32_t max_atoms;        /* capacity of the workspaces, >= 1                 */
+    int32_t flags;            /* PME_F_* bits                                     */
+    double  alpha;            /* Ewald splitting parameter [1/Angstrom], > 0      */
+    double  influence_power;  /* gamma of Eq. influence, >= 0 (1 = default,
+                                 0 = no assignment deconvolution)                 */
+    double  prefactor;        /* energy unit factor (1, or 14.3996454784 for eV)  */
+} pme_desc_t;
+
+/* Eq. mesh_target, N_a = ceil(2 |a_a| / spacing + 1), mapped by `strategy`
+ * (PME_MESH_*).  box: host, 3x3 row-major, rows are the lattice vectors.
+ * out: host int32[3].  Returns PME_OK or PME_EINVAL (spacing <= 0, singular
+ * box, unknown strategy, or a dimension above 2^30). */
+int pme_mesh_dims(const double box[9], double spacing, int strategy, int32_t out[3]);
+
+/* Validate `desc` and allocate every workspace of a plan on the current HIP
+ * device (meshes, spectrum, atom bins, FFT tables, deconvolution tables).
+ * *out receives the plan (NULL on failure). */
+int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out);
+
+/* Release a plan and its device memory (synchronises the device first).
+ * NULL is ignored. */
+void pme_plan_destroy(pme_plan_t plan);
+
+/* Device bytes held by the plan's workspaces. */
+int64_t pme_plan_workspace_bytes(pme_plan_t plan);
+
+/* Forward evaluation (Secs. 2.3.2-2.3.5).
+ *   n                atoms, 0 <= n <= max_atoms
+ *   pos              device float[n*3], Cartesian, any periodic image
+ *   q                device float[n] or NULL (all charges zero)
+ *   mu               device float[n*3] or NULL (all dipoles zero)
+ *   box              device double[9], row-major, rows a_x, a_y, a_z
+ *   energy           device double[3] or NULL: E_recip, E_self_q, E_self_mu
+ *                    (their sum is E^lr), each times prefactor
+ *   dE_dpos          device float[n*3] or NULL  (forces are -dE_dpos)
+ *   dE_dq            device float[n]   or NULL
+ *   dE_dmu           device float[n*3] or NULL
+ */
+int pme_forward(pme_plan_t plan, void* stream, int32_t n,
+                const float* pos, const float* q, const float* mu, const double* box,
+                double* energy, float* dE_dpos, float* dE_dq, float* dE_dmu);
+
+/* Hessian-vector product of E^lr in (r, q, mu): with the gradient
+ * (dE/dr, dE/dq, dE/dmu) of pme_forward and cotangents (v_pos, v_q, v_mu)
+ * on it, returns H v, which equals the vector-Jacobian product of the
+ * gradient because H is symmetric.  With v_q = v_mu = 0 and v_pos = -dL/dF it
+ * is the double backward of a force loss L(F).
+ *   v_pos, v_q, v_mu device cotangents (shapes as pos, q, mu) or NULL (= 0)
+ *   g_pos, g_q, g_mu device outputs (shapes as pos, q, mu) or NULL (skip)
+ * With PME_F_KEEP_PHI the potential of the last pme_forward is reused, else it
+ * is recomputed from (pos, q, mu, box). */
+int pme_backward(pme_plan_t plan, void* stream, int32_t n,
+                 const float* pos, const float* q, const float* mu, const double* box,
+                 const float* v_pos, const float* v_q, const float* v_mu,
+                 float* g_pos, float* g_q, float* g_mu);
+
+/* Synchronise `stream`, then return PME_ENONFINITE if any kernel of this plan
+ * saw a non-finite position or box since the last pme_status call, or
+ * PME_EHIP if the stream reported an error; else PME_OK.  Clears the flag. */
+int pme_status(pme_plan_t plan, void* stream);
+
+/* Text for a return code. */
+const char* pme_strerror(int code);
+
+/* Text of the last HIP runtime error seen by the library (thread-local). */
+const char* pme_last_hip_error(void);
+
+/* Device pointer of the potential mesh phi (float[N_x*N_y*N_z], z fastest)
+ * left by the last pme_forward, and of the density rho it was built from.
+ * For inspection and tests; valid until the plan is destroyed. */
+const float* pme_plan_phi(pme_plan_t plan);
+const float* pme_plan_rho(pme_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PME_MI355X_H */

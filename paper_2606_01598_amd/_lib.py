@@ -1,0 +1,98 @@
+"""ctypes loader of libpme.so: the C ABI declared in include/pme.h.
+
+Argument marshalling only.  The library must have been built in-tree
+(``python -m paper_2606_01598_amd.build``); without it every entry point
+raises, there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpme.so")
+
+PME_OK = 0
+PME_EINVAL = -1
+PME_EORDER = -2
+PME_EMESH = -3
+PME_EALPHA = -4
+PME_ECAPACITY = -5
+PME_ENOMEM = -6
+PME_EHIP = -7
+PME_ENONFINITE = -8
+
+PME_F_KEEP_PHI = 1
+
+PME_MESH_POW2 = 0
+PME_MESH_SMOOTH = 1
+PME_MESH_CEIL = 2
+
+# every symbol include/pme.h declares
+EXPORTS = ("pme_mesh_dims", "pme_plan_create", "pme_plan_destroy", "pme_plan_workspace_bytes",
+           "pme_forward", "pme_backward", "pme_status", "pme_strerror", "pme_last_hip_error",
+           "pme_plan_phi", "pme_plan_rho")
+
+
+class PMEDesc(ctypes.Structure):
+    _fields_ = [("mesh", ctypes.c_int32 * 3),
+                ("order", ctypes.c_int32),
+                ("max_atoms", ctypes.c_int32),
+                ("flags", ctypes.c_int32),
+                ("alpha", ctypes.c_double),
+                ("influence_power", ctypes.c_double),
+                ("prefactor", ctypes.c_double)]
+
+
+class PMEError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(msg)
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libpme.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2606_01598_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    lib.pme_mesh_dims.argtypes = [ctypes.POINTER(f64), f64, ctypes.c_int, ctypes.POINTER(i32)]
+    lib.pme_mesh_dims.restype = ctypes.c_int
+    lib.pme_plan_create.argtypes = [ctypes.POINTER(PMEDesc), ctypes.POINTER(vp)]
+    lib.pme_plan_create.restype = ctypes.c_int
+    lib.pme_plan_destroy.argtypes = [vp]
+    lib.pme_plan_destroy.restype = None
+    lib.pme_plan_workspace_bytes.argtypes = [vp]
+    lib.pme_plan_workspace_bytes.restype = ctypes.c_int64
+    lib.pme_forward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pme_forward.restype = ctypes.c_int
+    lib.pme_backward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pme_backward.restype = ctypes.c_int
+    lib.pme_status.argtypes = [vp, vp]
+    lib.pme_status.restype = ctypes.c_int
+    lib.pme_strerror.argtypes = [ctypes.c_int]
+    lib.pme_strerror.restype = ctypes.c_char_p
+    lib.pme_last_hip_error.argtypes = []
+    lib.pme_last_hip_error.restype = ctypes.c_char_p
+    lib.pme_plan_phi.argtypes = [vp]
+    lib.pme_plan_phi.restype = vp
+    lib.pme_plan_rho.argtypes = [vp]
+    lib.pme_plan_rho.restype = vp
+    _lib = lib
+    return lib
+
+
+def check(rc: int) -> None:
+    if rc != PME_OK:
+        lib = load()
+        msg = lib.pme_strerror(rc).decode()
+        if rc == PME_EHIP:
+            msg += ": " + lib.pme_last_hip_error().decode()
+        raise PMEError(rc, msg)

@@ -1,0 +1,322 @@
+// C ABI of the PME library: plan construction (Sec. 2.3.1 mesh helper, FFT radix
+// plans, twiddles, the 1D deconvolution factors of Eqs. Bk and influence, atom
+// bins and spread tiles), and the forward / backward call sequences.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/pme.h"
+#include "kernels.h"
+
+using pme::DevPlan;
+
+struct pme_plan_s {
+  pme_desc_t desc;
+  DevPlan d;
+  int64_t bytes;
+  int max_atoms;
+  bool phi_valid;
+};
+
+namespace {
+
+thread_local char g_hip_err[256] = "";
+
+int hip_fail(hipError_t e) {
+  snprintf(g_hip_err, sizeof(g_hip_err), "%s", hipGetErrorString(e));
+  return PME_EHIP;
+}
+
+bool five_smooth(long m) {
+  if (m < 1) return false;
+  for (long f : {2L, 3L, 5L})
+    while (m % f == 0) m /= f;
+  return m == 1;
+}
+
+// radix schedule for a 1D length: 4s first, then 2, 3s, 5s
+bool radix_plan(int N, pme::AxisPlan& ax) {
+  ax.N = N;
+  ax.nst = 0;
+  int n = N;
+  auto push = [&](int r) {
+    if (ax.nst >= pme::kMaxStages) return false;
+    ax.rad[ax.nst++] = r;
+    n /= r;
+    return true;
+  };
+  while (n % 4 == 0) if (!push(4)) return false;
+  while (n % 2 == 0) if (!push(2)) return false;
+  while (n % 3 == 0) if (!push(3)) return false;
+  while (n % 5 == 0) if (!push(5)) return false;
+  return n == 1;
+}
+
+int pick_bin(int N) {
+  for (int c : {4, 5, 3, 6, 2})
+    if (N % c == 0) return c;
+  return N;
+}
+
+double sinc(double x) { return x == 0.0 ? 1.0 : sin(M_PI * x) / (M_PI * x); }
+
+template <class T>
+hipError_t dev_alloc(T** p, size_t count, int64_t& bytes) {
+  const size_t b = sizeof(T) * (count ? count : 1);
+  bytes += int64_t(b);
+  return hipMalloc(reinterpret_cast<void**>(p), b);
+}
+
+void free_plan(pme_plan_s* pl) {
+  DevPlan& d = pl->d;
+  void* ptrs[] = {d.count, d.ovf_count, d.rec, d.ovf_rec, d.twiddle[0], d.twiddle[1],
+                  d.twiddle[2], d.deconv[0], d.deconv[1], d.deconv[2], d.rho, d.spec, d.phi,
+                  d.epart, d.spart, d.status};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete pl;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* pme_strerror(int code) {
+  switch (code) {
+    case PME_OK: return "ok";
+    case PME_EINVAL: return "invalid argument (NULL required pointer, n < 0 or bad flag)";
+    case PME_EORDER: return "assignment order must be in 1..7";
+    case PME_EMESH: return "mesh dimensions must be 5-smooth and within 2..1024";
+    case PME_EALPHA: return "alpha must be > 0 and finite; gamma >= 0; prefactor finite";
+    case PME_ECAPACITY: return "more atoms than the plan's max_atoms";
+    case PME_ENOMEM: return "device allocation failed";
+    case PME_EHIP: return "HIP runtime error";
+    case PME_ENONFINITE: return "non-finite position or box seen on the device";
+    default: return "unknown error";
+  }
+}
+
+const char* pme_last_hip_error(void) { return g_hip_err; }
+
+int pme_mesh_dims(const double box[9], double spacing, int strategy, int32_t out[3]) {
+  if (!box || !out || !(spacing > 0.0) || !isfinite(spacing)) return PME_EINVAL;
+  const double det = box[0] * (box[4] * box[8] - box[5] * box[7]) -
+                     box[1] * (box[3] * box[8] - box[5] * box[6]) +
+                     box[2] * (box[3] * box[7] - box[4] * box[6]);
+  if (!isfinite(det) || det == 0.0) return PME_EINVAL;
+  for (int a = 0; a < 3; ++a) {
+    const double len = sqrt(box[3 * a] * box[3 * a] + box[3 * a + 1] * box[3 * a + 1] +
+                            box[3 * a + 2] * box[3 * a + 2]);
+    const double t = ceil(2.0 * len / spacing + 1.0);
+    if (!(t < 1073741824.0)) return PME_EINVAL;
+    long n = long(t);
+    if (strategy == PME_MESH_POW2) {
+      long m = 1;
+      while (m < n) m <<= 1;
+      n = m;
+    } else if (strategy == PME_MESH_SMOOTH) {
+      while (!five_smooth(n)) ++n;
+    } else if (strategy != PME_MESH_CEIL) {
+      return PME_EINVAL;
+    }
+    if (n > 1073741824L) return PME_EINVAL;
+    out[a] = int32_t(n);
+  }
+  return PME_OK;
+}
+
+int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
+  if (!desc || !out) return PME_EINVAL;
+  *out = nullptr;
+  if (desc->order < 1 || desc->order > 7) return PME_EORDER;
+  for (int a = 0; a < 3; ++a)
+    if (desc->mesh[a] < 2 || desc->mesh[a] > 1024 || !five_smooth(desc->mesh[a])) return PME_EMESH;
+  if (!(desc->alpha > 0.0) || !isfinite(desc->alpha) || !(desc->influence_power >= 0.0) ||
+      !isfinite(desc->influence_power) || !isfinite(desc->prefactor))
+    return PME_EALPHA;
+  if (desc->max_atoms < 1 || (desc->flags & ~PME_F_KEEP_PHI)) return PME_EINVAL;
+
+  pme_plan_s* pl = new (std::nothrow) pme_plan_s();
+  if (!pl) return PME_ENOMEM;
+  memset(&pl->d, 0, sizeof(pl->d));
+  pl->desc = *desc;
+  pl->bytes = 0;
+  pl->max_atoms = desc->max_atoms;
+  pl->phi_valid = false;
+  DevPlan& d = pl->d;
+  const int p = desc->order;
+  for (int a = 0; a < 3; ++a) d.N[a] = desc->mesh[a];
+  d.H = d.N[2] / 2 + 1;
+  d.p = p;
+  d.alpha = desc->alpha;
+  d.prefactor = desc->prefactor;
+  const long M = long(d.N[0]) * d.N[1] * d.N[2];
+
+  // bins and tiles
+  long nbins = 1;
+  for (int a = 0; a < 3; ++a) {
+    d.B[a] = pick_bin(d.N[a]);
+    d.nb[a] = d.N[a] / d.B[a];
+    nbins *= d.nb[a];
+    d.T[a] = d.N[a] < 8 ? d.N[a] : 8;
+    d.nt[a] = (d.N[a] + d.T[a] - 1) / d.T[a];
+  }
+  {
+    long range = 1;
+    for (int a = 0; a < 3; ++a) {
+      long k = (d.T[a] + p - 1 + d.B[a] - 1) / d.B[a] + 1;
+      range *= (k < d.nb[a] ? k : d.nb[a]);
+    }
+    if (range > pme::kMaxBinRange) { free_plan(pl); return PME_EMESH; }
+  }
+  {
+    const double per_bin = double(desc->max_atoms) * d.B[0] * d.B[1] * d.B[2] / double(M);
+    long cap = long(ceil(2.0 * per_bin)) + 8;
+    if (cap > 64) cap = 64;
+    d.cap = int(cap);
+  }
+  // FFT layout
+  for (int a = 0; a < 3; ++a)
+    if (!radix_plan(d.N[a], d.ax[a])) { free_plan(pl); return PME_EMESH; }
+  {
+    int rp = 4096 / d.N[2];
+    rp &= ~1;
+    if (rp < 2) rp = 2;
+    if (rp > 64) rp = 64;
+    d.rows_per_block = rp;
+    const int nmax = d.N[0] > d.N[1] ? d.N[0] : d.N[1];
+    int kt = (8000 - nmax) / (2 * (nmax + 1));
+    if (kt > 8) kt = 8;
+    if (kt < 1) kt = 1;
+    if (kt > d.H) kt = d.H;
+    d.ktile = kt;
+  }
+
+  hipError_t e = hipSuccess;
+  int64_t& by = pl->bytes;
+  auto ok = [&](hipError_t r) { if (r != hipSuccess && e == hipSuccess) e = r; };
+  ok(dev_alloc(&d.count, size_t(nbins), by));
+  ok(dev_alloc(&d.ovf_count, 1, by));
+  ok(dev_alloc(&d.rec, size_t(nbins) * d.cap * 16, by));
+  ok(dev_alloc(&d.ovf_rec, size_t(desc->max_atoms) * 16, by));
+  for (int a = 0; a < 3; ++a) {
+    ok(dev_alloc(&d.twiddle[a], size_t(d.N[a]), by));
+    ok(dev_alloc(&d.deconv[a], size_t(d.N[a]), by));
+  }
+  ok(dev_alloc(&d.rho, size_t(M), by));
+  ok(dev_alloc(&d.spec, size_t(d.N[0]) * d.N[1] * d.H, by));
+  ok(dev_alloc(&d.phi, size_t(M), by));
+  ok(dev_alloc(&d.epart, size_t(pme::fftx_blocks(d)), by));
+  ok(dev_alloc(&d.spart, size_t(2 * pme::bin_blocks(desc->max_atoms)), by));
+  ok(dev_alloc(&d.status, 1, by));
+  if (e != hipSuccess) {
+    free_plan(pl);
+    return e == hipErrorOutOfMemory ? PME_ENOMEM : hip_fail(e);
+  }
+  // tables (host FP64, stored FP32)
+  for (int a = 0; a < 3; ++a) {
+    const int N = d.N[a];
+    float2* tw = new float2[N];
+    float* dc = new float[N];
+    for (int t = 0; t < N; ++t) {
+      const double ang = -2.0 * M_PI * double(t) / double(N);
+      tw[t] = make_float2(float(cos(ang)), float(sin(ang)));
+      const int f = (t >= (N + 1) / 2) ? t - N : t;
+      const double b = pow(fabs(sinc(double(f) / N)), double(p));
+      dc[t] = float(pow(b, -2.0 * desc->influence_power));
+    }
+    ok(hipMemcpy(d.twiddle[a], tw, sizeof(float2) * N, hipMemcpyHostToDevice));
+    ok(hipMemcpy(d.deconv[a], dc, sizeof(float) * N, hipMemcpyHostToDevice));
+    delete[] tw;
+    delete[] dc;
+  }
+  ok(hipMemset(d.count, 0, sizeof(int) * nbins));
+  ok(hipMemset(d.ovf_count, 0, sizeof(int)));
+  ok(hipMemset(d.status, 0, sizeof(int)));
+  ok(hipMemset(d.phi, 0, sizeof(float) * M));
+  ok(hipDeviceSynchronize());
+  if (e != hipSuccess) {
+    free_plan(pl);
+    return hip_fail(e);
+  }
+  *out = pl;
+  return PME_OK;
+}
+
+void pme_plan_destroy(pme_plan_t plan) {
+  if (!plan) return;
+  (void)hipDeviceSynchronize();
+  free_plan(plan);
+}
+
+int64_t pme_plan_workspace_bytes(pme_plan_t plan) { return plan ? plan->bytes : 0; }
+
+const float* pme_plan_phi(pme_plan_t plan) { return plan ? plan->d.phi : nullptr; }
+const float* pme_plan_rho(pme_plan_t plan) { return plan ? plan->d.rho : nullptr; }
+
+int pme_forward(pme_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
+                const float* mu, const double* box, double* energy, float* dE_dpos,
+                float* dE_dq, float* dE_dmu) {
+  if (!plan || n < 0 || !box || (n > 0 && !pos)) return PME_EINVAL;
+  if (n > plan->max_atoms) return PME_ECAPACITY;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DevPlan& d = plan->d;
+  hipError_t e;
+  plan->phi_valid = false;
+  if ((e = pme::launch_bin(d, s, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
+                           energy != nullptr)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_spread(d, s, false)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_gather(d, s, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu,
+                              pme::bin_blocks(n))) != hipSuccess)
+    return hip_fail(e);
+  plan->phi_valid = true;
+  return PME_OK;
+}
+
+int pme_backward(pme_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
+                 const float* mu, const double* box, const float* v_pos, const float* v_q,
+                 const float* v_mu, float* g_pos, float* g_q, float* g_mu) {
+  if (!plan || n < 0 || !box || (n > 0 && !pos)) return PME_EINVAL;
+  if (n > plan->max_atoms) return PME_ECAPACITY;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DevPlan& d = plan->d;
+  hipError_t e;
+  if (!((plan->desc.flags & PME_F_KEEP_PHI) && plan->phi_valid)) {
+    if ((e = pme::launch_bin(d, s, n, pos, q, mu, box, nullptr, nullptr, nullptr, false, false)) !=
+        hipSuccess)
+      return hip_fail(e);
+    if ((e = pme::launch_spread(d, s, false)) != hipSuccess) return hip_fail(e);
+    if ((e = pme::launch_convolve(d, s, box, d.phi, false)) != hipSuccess) return hip_fail(e);
+    plan->phi_valid = true;
+  }
+  if ((e = pme::launch_bin(d, s, n, pos, q, mu, box, v_pos, v_q, v_mu, true, false)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_spread(d, s, true)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_convolve(d, s, box, d.rho, false)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_gather_hvp(d, s, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q, g_mu)) !=
+      hipSuccess)
+    return hip_fail(e);
+  return PME_OK;
+}
+
+int pme_status(pme_plan_t plan, void* stream) {
+  if (!plan) return PME_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e);
+  int flag = 0;
+  if ((e = hipMemcpy(&flag, plan->d.status, sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess)
+    return hip_fail(e);
+  if (flag) {
+    if ((e = hipMemset(plan->d.status, 0, sizeof(int))) != hipSuccess) return hip_fail(e);
+    return PME_ENONFINITE;
+  }
+  return PME_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,391 @@
+// The mesh operator K of Secs. 2.3.3-2.3.4: real-to-complex 3D DFT of the density
+// (Eq. fft), multiplication by g(k) = G(k) C(n) (Eqs. green, influence,
+// potential_k) and the unnormalised complex-to-real inverse (Eq. ifft), plus the
+// k-space form of the reciprocal energy (Eq. energy_recip):
+//     E_recip = (1/2V) sum_n rho phi = (1/2V) sum_k g(k) |rho~(k)|^2.
+//
+// Five LDS-staged passes over the half spectrum spec[x][y][kz], kz < N_z/2+1:
+//   z  R2C   rows of N_z reals, two rows packed into one complex pencil
+//   y  fwd   pencils along y, a tile of kz columns per workgroup
+//   x  fused forward FFT along x, x g(k), energy partial, inverse FFT along x
+//   y  inv
+//   z  C2R   two Hermitian rows unpacked into one complex pencil
+// Each 1D transform is a mixed-radix (2, 3, 4, 5) Stockham autosort over LDS
+// ping-pong buffers; twiddles come from a per-axis table staged into LDS.
+//
+// Readings: signed frequency indices in fftfreq order (Nyquist at -N/2); the
+// Nyquist bins of a non-orthogonal cell use the mean of g over the bin and its
+// Hermitian partner, which makes the half-spectrum product equal the real part of
+// the full complex product (the real-to-complex semantics).
+#include "kernels.h"
+#include "pme_common.h"
+
+namespace pme {
+namespace {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+// multiply by i*s (s = +-1)
+__device__ __forceinline__ float2 imul(float2 a, float s) { return make_float2(-s * a.y, s * a.x); }
+
+// One radix-R Stockham butterfly of a pencil: inputs in[j + r N/R], outputs
+// out[(j/Ns) Ns R + k + r Ns], k = j mod Ns, twiddle w^(r k), w = e^{s 2 pi i/(Ns R)}.
+template <int R>
+__device__ __forceinline__ void butterfly(const float2* __restrict__ in, float2* __restrict__ out,
+                                          int j, int N, int Ns, const float2* __restrict__ tw,
+                                          float s) {
+  const int NR = N / R;
+  const int k = j % Ns;
+  const int step = N / (Ns * R);
+  float2 v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = in[j + r * NR];
+#pragma unroll
+  for (int r = 1; r < R; ++r) {
+    int t = (r * k * step) % N;
+    float2 w = tw[t];
+    w.y *= -s;        // table holds e^{-2 pi i t/N}; s = -1 forward, +1 inverse
+    v[r] = cmul(v[r], w);
+  }
+  float2 y[R];
+  if (R == 2) {
+    y[0] = cadd(v[0], v[1]);
+    y[1] = csub(v[0], v[1]);
+  } else if (R == 3) {
+    const float c = -0.5f, sn = 0.86602540378443864676f;
+    const float2 t1 = cadd(v[1], v[2]);
+    const float2 t2 = make_float2(v[0].x + c * t1.x, v[0].y + c * t1.y);
+    const float2 t3 = imul(csub(v[1], v[2]), s * sn);
+    y[0] = cadd(v[0], t1);
+    y[1] = cadd(t2, t3);
+    y[2] = csub(t2, t3);
+  } else if (R == 4) {
+    const float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
+    const float2 c = cadd(v[1], v[3]), d = imul(csub(v[1], v[3]), s);
+    y[0] = cadd(a, c);
+    y[1] = cadd(b, d);
+    y[2] = csub(a, c);
+    y[3] = csub(b, d);
+  } else if (R == 5) {
+    const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
+    const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+    const float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
+    const float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
+    const float2 a1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
+    const float2 a2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
+    const float2 b1 = imul(make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y), s);
+    const float2 b2 = imul(make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y), s);
+    y[0] = cadd(v[0], cadd(t1, t2));
+    y[1] = cadd(a1, b1);
+    y[4] = csub(a1, b1);
+    y[2] = cadd(a2, b2);
+    y[3] = csub(a2, b2);
+  }
+  const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) out[base + r * Ns] = y[r];
+}
+
+// Transform npen pencils (stride ps) held in x; returns the buffer holding the result.
+__device__ float2* lds_fft(float2* x, float2* y, int npen, int ps, const AxisPlan& ax,
+                           const float2* tw, float s) {
+  const int N = ax.N;
+  int Ns = 1;
+  for (int st = 0; st < ax.nst; ++st) {
+    const int R = ax.rad[st];
+    const int NR = N / R;
+    const int total = npen * NR;
+    for (int t = threadIdx.x; t < total; t += blockDim.x) {
+      const int pen = t / NR, j = t - pen * NR;
+      const float2* in = x + pen * ps;
+      float2* out = y + pen * ps;
+      switch (R) {
+        case 2: butterfly<2>(in, out, j, N, Ns, tw, s); break;
+        case 3: butterfly<3>(in, out, j, N, Ns, tw, s); break;
+        case 4: butterfly<4>(in, out, j, N, Ns, tw, s); break;
+        default: butterfly<5>(in, out, j, N, Ns, tw, s); break;
+      }
+    }
+    __syncthreads();
+    float2* t = x; x = y; y = t;
+    Ns *= R;
+  }
+  return x;
+}
+
+__device__ __forceinline__ void load_twiddles(float2* dst, const float2* src, int N) {
+  for (int t = threadIdx.x; t < N; t += blockDim.x) dst[t] = src[t];
+}
+
+struct ZArgs {
+  AxisPlan ax;
+  const float2* tw;
+  int rows;        // N_x N_y
+  int H;
+  int rp;          // rows per block (even)
+  const float* src;
+  float2* spec;
+  float* dst;
+  int* count;      // bin counters reset here (may be null)
+  int* ovf_count;
+  int ncount;
+};
+
+// z pass, real to complex
+__global__ void __launch_bounds__(256) k_fftz_r2c(ZArgs a) {
+  extern __shared__ float2 sm[];
+  const int N = a.ax.N, H = a.H;
+  float2* tw = sm;
+  float2* X = tw + N;
+  float2* Y = X + (a.rp / 2) * N;
+  const int r0 = blockIdx.x * a.rp;
+  load_twiddles(tw, a.tw, N);
+  const int np = a.rp / 2;
+  for (int e = threadIdx.x; e < np * N; e += blockDim.x) {
+    const int c = e / N, m = e - c * N;
+    const int ra = r0 + 2 * c, rb = ra + 1;
+    X[e] = make_float2(ra < a.rows ? a.src[size_t(ra) * N + m] : 0.0f,
+                       rb < a.rows ? a.src[size_t(rb) * N + m] : 0.0f);
+  }
+  __syncthreads();
+  const float2* Z = lds_fft(X, Y, np, N, a.ax, tw, -1.0f);
+  for (int e = threadIdx.x; e < a.rp * H; e += blockDim.x) {
+    const int rr = e / H, k = e - rr * H;
+    const int row = r0 + rr;
+    if (row >= a.rows) continue;
+    const int c = rr >> 1;
+    const float2 zk = Z[c * N + k];
+    const float2 zn = Z[c * N + (k ? N - k : 0)];
+    float2 v;
+    if ((rr & 1) == 0) v = make_float2(0.5f * (zk.x + zn.x), 0.5f * (zk.y - zn.y));
+    else v = make_float2(0.5f * (zk.y + zn.y), -0.5f * (zk.x - zn.x));
+    a.spec[size_t(row) * H + k] = v;
+  }
+  if (a.count) {
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int e = gid; e < a.ncount; e += gridDim.x * blockDim.x) a.count[e] = 0;
+    if (gid == 0) *a.ovf_count = 0;
+  }
+}
+
+// z pass, complex to real
+__global__ void __launch_bounds__(256) k_fftz_c2r(ZArgs a) {
+  extern __shared__ float2 sm[];
+  const int N = a.ax.N, H = a.H;
+  float2* tw = sm;
+  float2* S = tw + N;
+  float2* X = S + a.rp * H;
+  float2* Y = X + (a.rp / 2) * N;
+  const int r0 = blockIdx.x * a.rp;
+  load_twiddles(tw, a.tw, N);
+  for (int e = threadIdx.x; e < a.rp * H; e += blockDim.x) {
+    const int rr = e / H;
+    S[e] = (r0 + rr < a.rows) ? a.spec[size_t(r0) * H + e] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int np = a.rp / 2;
+  const bool even = (N & 1) == 0;
+  for (int e = threadIdx.x; e < np * N; e += blockDim.x) {
+    const int c = e / N, m = e - c * N;
+    float2 A, B;
+    if (m < H) {
+      A = S[(2 * c) * H + m];
+      B = S[(2 * c + 1) * H + m];
+    } else {
+      A = S[(2 * c) * H + N - m];
+      B = S[(2 * c + 1) * H + N - m];
+      A.y = -A.y;
+      B.y = -B.y;
+    }
+    if (m == 0 || (even && m == N / 2)) { A.y = 0.0f; B.y = 0.0f; }
+    X[e] = make_float2(A.x - B.y, A.y + B.x);
+  }
+  __syncthreads();
+  const float2* Z = lds_fft(X, Y, np, N, a.ax, tw, +1.0f);
+  for (int e = threadIdx.x; e < np * N; e += blockDim.x) {
+    const int c = e / N, m = e - c * N;
+    const int ra = r0 + 2 * c, rb = ra + 1;
+    const float2 z = Z[e];
+    if (ra < a.rows) a.dst[size_t(ra) * N + m] = z.x;
+    if (rb < a.rows) a.dst[size_t(rb) * N + m] = z.y;
+  }
+}
+
+struct YArgs {
+  AxisPlan ax;
+  const float2* tw;
+  int Ny, H, kt;
+  float2* spec;
+  float sign;
+};
+
+// y pass: block = (x, tile of kz columns)
+__global__ void __launch_bounds__(256) k_ffty(YArgs a) {
+  extern __shared__ float2 sm[];
+  const int N = a.ax.N, H = a.H, kt = a.kt;
+  const int ps = N + 1;
+  float2* tw = sm;
+  float2* X = tw + N;
+  float2* Y = X + kt * ps;
+  const int ntk = (H + kt - 1) / kt;
+  const int x = blockIdx.x / ntk, kz0 = (blockIdx.x - x * ntk) * kt;
+  load_twiddles(tw, a.tw, N);
+  float2* base = a.spec + size_t(x) * a.Ny * H;
+  for (int e = threadIdx.x; e < N * kt; e += blockDim.x) {
+    const int yy = e / kt, l = e - yy * kt;
+    const int kz = kz0 + l;
+    X[l * ps + yy] = (kz < H) ? base[size_t(yy) * H + kz] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const float2* Z = lds_fft(X, Y, kt, ps, a.ax, tw, a.sign);
+  for (int e = threadIdx.x; e < N * kt; e += blockDim.x) {
+    const int yy = e / kt, l = e - yy * kt;
+    const int kz = kz0 + l;
+    if (kz < H) base[size_t(yy) * H + kz] = Z[l * ps + yy];
+  }
+}
+
+struct XArgs {
+  AxisPlan ax;
+  const float2* tw;
+  int N[3];
+  int H, kt;
+  float2* spec;
+  const double* box;
+  const float* dcx;
+  const float* dcy;
+  const float* dcz;
+  float alpha;
+  double* epart;   // may be null
+};
+
+__device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) / 2) ? k - N : k; }
+
+// x pass fused with the influence function
+__global__ void __launch_bounds__(256) k_fftx_fused(XArgs a) {
+  extern __shared__ float2 sm[];
+  __shared__ double red[8];
+  const int Nx = a.N[0], Ny = a.N[1], Nz = a.N[2], H = a.H, kt = a.kt;
+  const int ps = Nx + 1;
+  float2* tw = sm;
+  float2* X = tw + Nx;
+  float2* Y = X + kt * ps;
+  const int ntk = (H + kt - 1) / kt;
+  const int y = blockIdx.x / ntk, kz0 = (blockIdx.x - y * ntk) * kt;
+  load_twiddles(tw, a.tw, Nx);
+  const size_t xstride = size_t(Ny) * H;
+  float2* base = a.spec + size_t(y) * H;
+  for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
+    const int xx = e / kt, l = e - xx * kt;
+    const int kz = kz0 + l;
+    X[l * ps + xx] = (kz < H) ? base[xx * xstride + kz] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  float2* Z = lds_fft(X, Y, kt, ps, a.ax, tw, -1.0f);
+  float2* W = (Z == X) ? Y : X;
+  // reciprocal metric M_ab = b_a . b_b, b_a = 2 pi C^-1[:, a]
+  const Cell c = cell_from_box(a.box);
+  float M[3][3];
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      double s = 0.0;
+#pragma unroll
+      for (int g = 0; g < 3; ++g) s += c.inv[3 * g + p] * c.inv[3 * g + q];
+      M[p][q] = float(4.0 * M_PI * M_PI * s);
+    }
+  const float inv4a2 = 1.0f / (4.0f * a.alpha * a.alpha);
+  const int fy = signed_freq(y, Ny);
+  const bool nyq_y = ((Ny & 1) == 0) && (fy == -Ny / 2);
+  double e_acc = 0.0;
+  for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
+    const int l = e / Nx, i = e - l * Nx;
+    const int kz = kz0 + l;
+    float2 v = Z[l * ps + i];
+    if (kz < H) {
+      const int fx = signed_freq(i, Nx);
+      const int fz = signed_freq(kz, Nz);
+      const float ffx = float(fx), ffy = float(fy), ffz = float(fz);
+      const float k2 = M[0][0] * ffx * ffx + M[1][1] * ffy * ffy + M[2][2] * ffz * ffz +
+                       2.0f * (M[0][1] * ffx * ffy + M[0][2] * ffx * ffz + M[1][2] * ffy * ffz);
+      float g = 0.0f;
+      if (fx != 0 || fy != 0 || fz != 0) {
+        g = 4.0f * float(M_PI) / k2 * __expf(-k2 * inv4a2);
+        const bool nx = ((Nx & 1) == 0) && (fx == -Nx / 2);
+        const bool nz = ((Nz & 1) == 0) && (fz == -Nz / 2);
+        if (nx || nyq_y || nz) {
+          // Hermitian partner: non-Nyquist components change sign
+          const float px = nx ? ffx : -ffx, py = nyq_y ? ffy : -ffy, pz = nz ? ffz : -ffz;
+          const float k2p = M[0][0] * px * px + M[1][1] * py * py + M[2][2] * pz * pz +
+                            2.0f * (M[0][1] * px * py + M[0][2] * px * pz + M[1][2] * py * pz);
+          if (k2p != k2) g = 0.5f * (g + 4.0f * float(M_PI) / k2p * __expf(-k2p * inv4a2));
+        }
+        g *= a.dcx[i] * a.dcy[y] * a.dcz[kz];
+      }
+      const float wgt = (kz == 0 || (((Nz & 1) == 0) && kz == Nz / 2)) ? 1.0f : 2.0f;
+      e_acc += double(wgt * g) * (double(v.x) * v.x + double(v.y) * v.y);
+      v.x *= g;
+      v.y *= g;
+    }
+    Z[l * ps + i] = v;
+  }
+  __syncthreads();
+  const float2* R = lds_fft(Z, W, kt, ps, a.ax, tw, +1.0f);
+  for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
+    const int xx = e / kt, l = e - xx * kt;
+    const int kz = kz0 + l;
+    if (kz < H) base[xx * xstride + kz] = R[l * ps + xx];
+  }
+  if (a.epart) {
+    const double s = block_sum(e_acc, red);
+    if (threadIdx.x == 0) a.epart[blockIdx.x] = s;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
+                           bool energy) {
+  const int rows = d.N[0] * d.N[1];
+  ZArgs z;
+  z.ax = d.ax[2]; z.tw = d.twiddle[2]; z.rows = rows; z.H = d.H; z.rp = d.rows_per_block;
+  z.src = d.rho; z.spec = d.spec; z.dst = out;
+  z.count = d.count; z.ovf_count = d.ovf_count; z.ncount = d.nb[0] * d.nb[1] * d.nb[2];
+  const int zb = fftz_blocks(d);
+  const size_t zsh_f = sizeof(float2) * (d.N[2] + d.rows_per_block * d.N[2]);
+  hipLaunchKernelGGL(k_fftz_r2c, dim3(zb), dim3(256), zsh_f, s, z);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+
+  YArgs y;
+  y.ax = d.ax[1]; y.tw = d.twiddle[1]; y.Ny = d.N[1]; y.H = d.H; y.kt = d.ktile; y.spec = d.spec;
+  const size_t ysh = sizeof(float2) * (d.N[1] + 2 * d.ktile * (d.N[1] + 1));
+  y.sign = -1.0f;
+  hipLaunchKernelGGL(k_ffty, dim3(ffty_blocks(d)), dim3(256), ysh, s, y);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+
+  XArgs x;
+  x.ax = d.ax[0]; x.tw = d.twiddle[0];
+  for (int k = 0; k < 3; ++k) x.N[k] = d.N[k];
+  x.H = d.H; x.kt = d.ktile; x.spec = d.spec; x.box = box;
+  x.dcx = d.deconv[0]; x.dcy = d.deconv[1]; x.dcz = d.deconv[2];
+  x.alpha = float(d.alpha);
+  x.epart = energy ? d.epart : nullptr;
+  const size_t xsh = sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1));
+  hipLaunchKernelGGL(k_fftx_fused, dim3(fftx_blocks(d)), dim3(256), xsh, s, x);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+
+  y.sign = +1.0f;
+  hipLaunchKernelGGL(k_ffty, dim3(ffty_blocks(d)), dim3(256), ysh, s, y);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
+
+  const size_t zsh_i = sizeof(float2) * (d.N[2] + d.rows_per_block * d.H + d.rows_per_block * d.N[2]);
+  hipLaunchKernelGGL(k_fftz_c2r, dim3(zb), dim3(256), zsh_i, s, z);
+  return hipGetLastError();
+}
+
+}  // namespace pme

@@ -1,0 +1,81 @@
+// Host-side launchers of the PME kernels and the plan data they read.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pme {
+
+constexpr int kMaxStages = 16;
+constexpr int kMaxBinRange = 2048;   // bins a spread tile may scan (LDS scan array)
+constexpr int kListCap = 128;        // atoms staged per spread round
+
+struct AxisPlan {          // 1D mixed-radix FFT of length N
+  int N;
+  int nst;
+  int rad[kMaxStages];
+};
+
+struct DevPlan {
+  int N[3];                // mesh dims
+  int H;                   // N_z/2 + 1 (half spectrum along z)
+  int p;                   // assignment order
+  double alpha;
+  double prefactor;
+  // atom bins: bins of B[a] mesh cells along axis a (B[a] divides N[a])
+  int B[3];
+  int nb[3];
+  int cap;                 // records per bin
+  int* count;              // [nbins]
+  int* ovf_count;          // [1]
+  float* rec;              // [nbins * cap * 16] records (16 words each)
+  float* ovf_rec;          // [max_atoms * 16]
+  // spread tiles
+  int T[3];
+  int nt[3];
+  // FFT
+  AxisPlan ax[3];
+  float2* twiddle[3];      // e^{-2 pi i t / N_a}, t < N_a
+  float* deconv[3];        // |sinc(f/N_a)|^{-2 gamma p}, signed f
+  int rows_per_block;      // z-pass rows per block (even)
+  int ktile;               // half-spectrum z columns per y/x-pass block
+  // meshes
+  float* rho;              // [M] density (also the tangent density / its potential)
+  float2* spec;            // [N_x N_y H]
+  float* phi;              // [M]
+  // reductions
+  double* epart;           // [x-pass blocks]
+  double* spart;           // [2 * bin blocks]
+  int* status;             // bit 0: non-finite input seen
+};
+
+inline int fftx_blocks(const DevPlan& d) { return d.N[1] * ((d.H + d.ktile - 1) / d.ktile); }
+inline int ffty_blocks(const DevPlan& d) { return d.N[0] * ((d.H + d.ktile - 1) / d.ktile); }
+inline int fftz_blocks(const DevPlan& d) {
+  const int rows = d.N[0] * d.N[1];
+  return (rows + d.rows_per_block - 1) / d.rows_per_block;
+}
+inline int bin_blocks(int n) { return n > 0 ? (n + 255) / 256 : 1; }
+
+// Binning: stencil anchor, bin slot, per-atom record (forward: q and the x-space
+// dipole; tangent: the 10 monomial coefficients of the tangent density).
+hipError_t launch_bin(const DevPlan& d, hipStream_t s, int n, const float* pos, const float* q,
+                      const float* mu, const double* box, const float* v_pos, const float* v_q,
+                      const float* v_mu, bool tangent, bool self_sums);
+// Owner-computes spread of the binned records into d.rho.
+hipError_t launch_spread(const DevPlan& d, hipStream_t s, bool tangent);
+// rho -> spec -> (x g) -> out, the mesh operator K; energy partials when wanted.
+// Also resets the bin counters (the spread is their last reader).
+hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
+                           bool energy);
+// Gradient gather (+ energy finalisation).
+hipError_t launch_gather(const DevPlan& d, hipStream_t s, int n, const float* pos,
+                         const float* q, const float* mu, const double* box, double* energy,
+                         float* dE_dpos, float* dE_dq, float* dE_dmu, int n_spart);
+// Hessian-vector product gather from phi (d.phi) and psi (d.rho).
+hipError_t launch_gather_hvp(const DevPlan& d, hipStream_t s, int n, const float* pos,
+                             const float* q, const float* mu, const double* box,
+                             const float* v_pos, const float* v_q, const float* v_mu,
+                             float* g_pos, float* g_q, float* g_mu);
+
+}  // namespace pme

@@ -1,0 +1,201 @@
+// Shared device-side definitions of the PME kernels (gfx950).
+//
+// * B-spline assignment weights (Sec. 2.3.2, Eq. w3d): W^(p) is the centered
+//   cardinal B-spline M_p(t) = N_p(t + p/2), N_p the cardinal B-spline on
+//   [0, p].  On each unit interval N_p is a polynomial; its pieces follow from
+//   the recursion N_p(s) = [s N_{p-1}(s) + (p - s) N_{p-1}(s - 1)] / (p - 1),
+//   evaluated here at compile time into per-piece coefficient tables, with the
+//   derivative tables folded in (coefficient * k!/(k-d)!).
+// * Stencil convention: for an atom at mesh coordinate x the anchor is
+//   b = floor(x) (even p) or floor(x + 1/2) (odd p, the round() of the paper),
+//   f = x + delta - b in [0, 1), and stencil point j = 0..p-1 sits at mesh
+//   index b - floor((p-1)/2) + j with weight N_p(f + p - 1 - j), i.e. the
+//   polynomial piece p-1-j evaluated at f.
+// * Cell geometry (Sec. 2.3.1) is recomputed in FP64 from the device box in
+//   every kernel, so a captured graph can be replayed with a new box.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define PME_MAX_ORDER 7
+
+namespace pme {
+
+// ---------------------------------------------------------------------------
+// compile-time spline tables
+// ---------------------------------------------------------------------------
+struct SplineTables {
+  // coef[off(p) + (d*p + piece)*p + k]: k-th coefficient of the d-th derivative
+  // of piece `piece` of N_p, as a polynomial in f (powers f^(k-d), k >= d).
+  float coef[4 * (1 + 4 + 9 + 16 + 25 + 36 + 49)];
+};
+
+constexpr int spline_offset(int p) {
+  int off = 0;
+  for (int q = 1; q < p; ++q) off += 4 * q * q;
+  return off;
+}
+
+constexpr SplineTables make_spline_tables() {
+  SplineTables t{};
+  double a[PME_MAX_ORDER][PME_MAX_ORDER] = {};   // pieces of N_p, a[piece][power]
+  double b[PME_MAX_ORDER][PME_MAX_ORDER] = {};
+  a[0][0] = 1.0;                                  // N_1 = 1 on [0, 1)
+  for (int p = 1; p <= PME_MAX_ORDER; ++p) {
+    if (p > 1) {
+      for (int j = 0; j < PME_MAX_ORDER; ++j)
+        for (int k = 0; k < PME_MAX_ORDER; ++k) b[j][k] = 0.0;
+      for (int j = 0; j < p; ++j) {
+        if (j < p - 1)                       // (j + f) * piece j of N_{p-1}
+          for (int k = 0; k < p - 1; ++k) {
+            b[j][k] += j * a[j][k];
+            b[j][k + 1] += a[j][k];
+          }
+        if (j >= 1)                          // (p - j - f) * piece j-1 of N_{p-1}
+          for (int k = 0; k < p - 1; ++k) {
+            b[j][k] += (p - j) * a[j - 1][k];
+            b[j][k + 1] -= a[j - 1][k];
+          }
+      }
+      for (int j = 0; j < p; ++j)
+        for (int k = 0; k < p; ++k) a[j][k] = b[j][k] / (p - 1);
+    }
+    const int off = spline_offset(p);
+    for (int d = 0; d < 4; ++d)
+      for (int pc = 0; pc < p; ++pc)
+        for (int k = 0; k < p; ++k) {
+          double fall = 1.0;
+          for (int m = 0; m < d; ++m) fall *= (k - m);
+          t.coef[off + (d * p + pc) * p + k] = (k >= d) ? float(a[pc][k] * fall) : 0.0f;
+        }
+  }
+  return t;
+}
+
+static __constant__ SplineTables c_spline = make_spline_tables();
+
+// w[d][j], d = 0..D: d-th derivative (w.r.t. the mesh coordinate) of the weight of
+// stencil point j.
+template <int P, int D>
+__device__ __forceinline__ void spline_weights(float f, float (&w)[D + 1][P]) {
+  constexpr int off = spline_offset(P);
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int pc = P - 1 - j;
+#pragma unroll
+    for (int d = 0; d <= D; ++d) {
+      if (d > P - 1) {
+        w[d][j] = 0.0f;
+        continue;
+      }
+      const float* c = &c_spline.coef[off + (d * P + pc) * P];
+      float acc = c[P - 1];
+#pragma unroll
+      for (int k = P - 2; k >= d; --k) acc = fmaf(acc, f, c[k]);
+      w[d][j] = acc;
+    }
+  }
+}
+
+// Weights of one stencil point j (runtime, wave-uniform) for derivative orders 0..D.
+template <int P, int D>
+__device__ __forceinline__ void spline_weight_at(int j, float f, float (&w)[D + 1]) {
+  constexpr int off = spline_offset(P);
+  const int pc = P - 1 - j;
+#pragma unroll
+  for (int d = 0; d <= D; ++d) {
+    if (d > P - 1) {
+      w[d] = 0.0f;
+      continue;
+    }
+    const float* c = &c_spline.coef[off + (d * P + pc) * P];
+    float acc = c[P - 1];
+#pragma unroll
+    for (int k = P - 2; k >= d; --k) acc = fmaf(acc, f, c[k]);
+    w[d] = acc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// cell geometry
+// ---------------------------------------------------------------------------
+struct Cell {
+  double inv[9];   // C^-1, row-major: inv[3*b + a] = (C^-1)[b][a]
+  double vol;      // |det C|
+  bool ok;         // finite and non-singular
+};
+
+__device__ __forceinline__ Cell cell_from_box(const double* __restrict__ box) {
+  Cell c;
+  const double a00 = box[0], a01 = box[1], a02 = box[2];
+  const double a10 = box[3], a11 = box[4], a12 = box[5];
+  const double a20 = box[6], a21 = box[7], a22 = box[8];
+  const double c00 = a11 * a22 - a12 * a21, c01 = a02 * a21 - a01 * a22, c02 = a01 * a12 - a02 * a11;
+  const double c10 = a12 * a20 - a10 * a22, c11 = a00 * a22 - a02 * a20, c12 = a02 * a10 - a00 * a12;
+  const double c20 = a10 * a21 - a11 * a20, c21 = a01 * a20 - a00 * a21, c22 = a00 * a11 - a01 * a10;
+  const double det = a00 * c00 + a01 * c10 + a02 * c20;
+  c.ok = isfinite(det) && det != 0.0;
+  const double id = c.ok ? 1.0 / det : 0.0;
+  c.inv[0] = c00 * id; c.inv[1] = c01 * id; c.inv[2] = c02 * id;
+  c.inv[3] = c10 * id; c.inv[4] = c11 * id; c.inv[5] = c12 * id;
+  c.inv[6] = c20 * id; c.inv[7] = c21 * id; c.inv[8] = c22 * id;
+  c.vol = fabs(det);
+  return c;
+}
+
+// J[a][b] = d x_a / d r_b = N_a (C^-1)[b][a]  (float, row-major)
+__device__ __forceinline__ void jacobian(const Cell& c, const int (&N)[3], float (&J)[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) J[a][b] = float(N[a] * c.inv[3 * b + a]);
+}
+
+// Stencil anchor and offset of one atom along the three axes.  Returns false for a
+// non-finite position.  base[a] in [0, N_a), f[a] in [0, 1).
+template <int P>
+__device__ __forceinline__ bool atom_stencil(const float* __restrict__ pos, int i, const Cell& c,
+                                             const int (&N)[3], int (&base)[3], float (&f)[3]) {
+  const double r0 = pos[3 * i], r1 = pos[3 * i + 1], r2 = pos[3 * i + 2];
+  bool ok = isfinite(r0) && isfinite(r1) && isfinite(r2) && c.ok;
+  constexpr double delta = (P & 1) ? 0.5 : 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double s = r0 * c.inv[a] + r1 * c.inv[3 + a] + r2 * c.inv[6 + a];
+    s -= floor(s);
+    double x = s * N[a] + delta;
+    double fb = floor(x);
+    int b = ok ? int(fb) : 0;
+    float fr = ok ? float(x - fb) : 0.0f;
+    if (fr >= 1.0f) { fr = 0.0f; b += 1; }
+    if (b >= N[a]) b -= N[a];
+    if (b < 0) b += N[a];
+    if (b < 0 || b >= N[a]) { b = 0; ok = false; }
+    base[a] = b;
+    f[a] = fr;
+  }
+  return ok;
+}
+
+// m mod N in [0, N) for any int m
+__device__ __forceinline__ int wrapn(int m, int N) {
+  m %= N;
+  return (m < 0) ? m + N : m;
+}
+
+// block-wide sum of a double (blockDim.x a multiple of 64, at most 1024)
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < int(blockDim.x >> 6); ++w) s += scratch[w];
+  __syncthreads();
+  return s;   // valid in thread 0
+}
+
+}  // namespace pme

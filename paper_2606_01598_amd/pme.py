@@ -1,0 +1,225 @@
+"""Python binding of the PME library with the same names as the C ABI.
+
+Tensors are torch CUDA (HIP) tensors: float32 contiguous for atoms, float64
+(3, 3) for the cell.  Every step of the computation runs in the library's HIP
+kernels; this module only checks shapes and passes pointers and the current
+stream.
+
+* ``mesh_dims(box, spacing, strategy)``        -- Eq. mesh_target + strategies
+* ``Plan``                                     -- pme_plan_create / destroy
+* ``Plan.forward(...)``                        -- pme_forward
+* ``Plan.backward(...)``                       -- pme_backward (Hessian-vector product)
+* ``pme_energy(pos, q, mu, box, plan)``        -- E^lr as a differentiable torch op
+  (first and second order: forces inside a loss, trained with create_graph)
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+
+EV_PER_E2_ANGSTROM = 14.3996454784
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def mesh_dims(box, spacing: float, strategy: str = "smooth"):
+    """Mesh dimensions of Eq. mesh_target mapped by 'pow2' | 'smooth' | 'ceil'."""
+    lib = _lib.load()
+    codes = {"pow2": _lib.PME_MESH_POW2, "smooth": _lib.PME_MESH_SMOOTH, "ceil": _lib.PME_MESH_CEIL}
+    if strategy not in codes:
+        raise ValueError(strategy)
+    b = (ctypes.c_double * 9)(*[float(x) for x in torch.as_tensor(box, dtype=torch.float64).reshape(-1).tolist()])
+    out = (ctypes.c_int32 * 3)()
+    _lib.check(lib.pme_mesh_dims(b, float(spacing), codes[strategy], out))
+    return tuple(int(x) for x in out)
+
+
+def _atoms(name, t, n, cols, device):
+    if t is None:
+        return None
+    if not (isinstance(t, torch.Tensor) and t.device.type == "cuda"):
+        raise TypeError(f"{name} must be a CUDA tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    shape = (n, cols) if cols else (n,)
+    if tuple(t.shape) != shape:
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {shape}")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t
+
+
+class Plan:
+    """A PME plan: mesh, order, alpha and the device workspaces (pme_plan_create)."""
+
+    def __init__(self, mesh, order: int, alpha: float, max_atoms: int, influence_power: float = 1.0,
+                 prefactor: float = 1.0, keep_phi: bool = True, device=None):
+        self._lib = _lib.load()
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        d = _lib.PMEDesc()
+        for k in range(3):
+            d.mesh[k] = int(mesh[k])
+        d.order = int(order)
+        d.max_atoms = int(max_atoms)
+        d.flags = _lib.PME_F_KEEP_PHI if keep_phi else 0
+        d.alpha = float(alpha)
+        d.influence_power = float(influence_power)
+        d.prefactor = float(prefactor)
+        self.desc = d
+        self.mesh = tuple(int(m) for m in mesh)
+        self.order = int(order)
+        self.alpha = float(alpha)
+        self.max_atoms = int(max_atoms)
+        self.prefactor = float(prefactor)
+        self.influence_power = float(influence_power)
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _lib.check(self._lib.pme_plan_create(ctypes.byref(d), ctypes.byref(handle)))
+        self.handle = handle
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            self._lib.pme_plan_destroy(h)
+            self.handle = None
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self._lib.pme_plan_workspace_bytes(self.handle))
+
+    def _check_common(self, pos, q, mu, box):
+        if not (isinstance(pos, torch.Tensor) and pos.dim() == 2 and pos.shape[1] == 3):
+            raise ValueError("pos must be (N, 3)")
+        n = int(pos.shape[0])
+        _atoms("pos", pos, n, 3, self.device)
+        _atoms("q", q, n, 0, self.device)
+        _atoms("mu", mu, n, 3, self.device)
+        if not (isinstance(box, torch.Tensor) and box.device == self.device
+                and box.dtype == torch.float64 and box.is_contiguous() and box.numel() == 9):
+            raise TypeError("box must be a contiguous float64 (3, 3) tensor on the plan's device")
+        return n
+
+    def forward(self, pos, q, mu, box, energy=True, dE_dpos=True, dE_dq=True, dE_dmu=True,
+                out=None):
+        """pme_forward.  Returns dict(energy (3,) f64, dE_dpos, dE_dq, dE_dmu) of the
+        requested outputs; ``out`` may supply preallocated tensors with those keys."""
+        n = self._check_common(pos, q, mu, box)
+        out = {} if out is None else dict(out)
+        dev = self.device
+        if energy and "energy" not in out:
+            out["energy"] = torch.empty(3, dtype=torch.float64, device=dev)
+        if dE_dpos and "dE_dpos" not in out:
+            out["dE_dpos"] = torch.empty(n, 3, dtype=torch.float32, device=dev)
+        if dE_dq and "dE_dq" not in out:
+            out["dE_dq"] = torch.empty(n, dtype=torch.float32, device=dev)
+        if dE_dmu and "dE_dmu" not in out:
+            out["dE_dmu"] = torch.empty(n, 3, dtype=torch.float32, device=dev)
+        rc = self._lib.pme_forward(self.handle, _stream(), n, _ptr(pos), _ptr(q), _ptr(mu), _ptr(box),
+                                   _ptr(out.get("energy")), _ptr(out.get("dE_dpos")),
+                                   _ptr(out.get("dE_dq")), _ptr(out.get("dE_dmu")))
+        _lib.check(rc)
+        return out
+
+    def backward(self, pos, q, mu, box, v_pos=None, v_q=None, v_mu=None, g_pos=True, g_q=True,
+                 g_mu=True, out=None):
+        """pme_backward: Hessian-vector product H (v_pos, v_q, v_mu).  Returns dict."""
+        n = self._check_common(pos, q, mu, box)
+        _atoms("v_pos", v_pos, n, 3, self.device)
+        _atoms("v_q", v_q, n, 0, self.device)
+        _atoms("v_mu", v_mu, n, 3, self.device)
+        out = {} if out is None else dict(out)
+        dev = self.device
+        if g_pos and "g_pos" not in out:
+            out["g_pos"] = torch.empty(n, 3, dtype=torch.float32, device=dev)
+        if g_q and "g_q" not in out:
+            out["g_q"] = torch.empty(n, dtype=torch.float32, device=dev)
+        if g_mu and "g_mu" not in out:
+            out["g_mu"] = torch.empty(n, 3, dtype=torch.float32, device=dev)
+        rc = self._lib.pme_backward(self.handle, _stream(), n, _ptr(pos), _ptr(q), _ptr(mu), _ptr(box),
+                                    _ptr(v_pos), _ptr(v_q), _ptr(v_mu), _ptr(out.get("g_pos")),
+                                    _ptr(out.get("g_q")), _ptr(out.get("g_mu")))
+        _lib.check(rc)
+        return out
+
+    def status(self) -> None:
+        """pme_status: synchronise and raise on device-detected errors."""
+        _lib.check(self._lib.pme_status(self.handle, _stream()))
+
+    def phi(self) -> torch.Tensor:
+        """Copy of the potential mesh of the last forward (N_x, N_y, N_z)."""
+        return self._mesh_copy(self._lib.pme_plan_phi(self.handle))
+
+    def rho(self) -> torch.Tensor:
+        """Copy of the last density spread (forward density or tangent density)."""
+        return self._mesh_copy(self._lib.pme_plan_rho(self.handle))
+
+    def _mesh_copy(self, ptr) -> torch.Tensor:
+        out = torch.empty(self.mesh, dtype=torch.float32, device=self.device)
+        torch.cuda.current_stream().synchronize()
+        nbytes = out.numel() * 4
+        import ctypes as ct
+        hip = ct.CDLL("libamdhip64.so")
+        hip.hipMemcpy.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_size_t, ct.c_int]
+        rc = hip.hipMemcpy(ct.c_void_p(out.data_ptr()), ct.c_void_p(ptr), nbytes, 3)
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpy failed ({rc})")
+        return out
+
+
+# -----------------------------------------------------------------------------
+# autograd: E^lr(pos, q, mu) with hand-written first and second derivatives
+# -----------------------------------------------------------------------------
+
+class _PMEGrad(torch.autograd.Function):
+    """(dE/dpos, dE/dq, dE/dmu) as a differentiable function of (pos, q, mu).
+
+    Its backward is the Hessian-vector product of pme_backward, which is what a
+    force loss needs when the forces were taken with create_graph=True.
+    """
+
+    @staticmethod
+    def forward(ctx, pos, q, mu, box, plan, g_pos, g_q, g_mu):
+        ctx.plan = plan
+        ctx.save_for_backward(pos, q, mu, box)
+        return g_pos, g_q, g_mu
+
+    @staticmethod
+    def backward(ctx, v_pos, v_q, v_mu):
+        pos, q, mu, box = ctx.saved_tensors
+        plan = ctx.plan
+        v = [None if t is None else t.contiguous().float() for t in (v_pos, v_q, v_mu)]
+        r = plan.backward(pos.detach(), q.detach(), mu.detach(), box, *v)
+        return r["g_pos"], r["g_q"], r["g_mu"], None, None, None, None, None
+
+
+class _PMEEnergy(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, pos, q, mu, box, plan):
+        r = plan.forward(pos.detach(), q.detach(), mu.detach(), box)
+        ctx.plan = plan
+        ctx.save_for_backward(pos, q, mu, box, r["dE_dpos"], r["dE_dq"], r["dE_dmu"])
+        return r["energy"].sum()
+
+    @staticmethod
+    def backward(ctx, gE):
+        pos, q, mu, box, gp, gq, gm = ctx.saved_tensors
+        if torch.is_grad_enabled():
+            gp, gq, gm = _PMEGrad.apply(pos, q, mu, box, ctx.plan, gp, gq, gm)
+        s = gE.to(torch.float32)
+        return gp * s, gq * s, gm * s, None, None
+
+
+def pme_energy(pos: torch.Tensor, q: torch.Tensor, mu: torch.Tensor, box: torch.Tensor,
+               plan: Plan) -> torch.Tensor:
+    """E^lr (float64 scalar) with gradients to pos, q and mu; differentiable twice."""
+    return _PMEEnergy.apply(pos, q, mu, box, plan)

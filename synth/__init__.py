@@ -80,7 +80,13 @@ def _rsa(n: int, L: float, dmin: float, rng: np.random.Generator) -> np.ndarray:
     count = 0
     d2 = dmin * dmin
     offs = np.array([[i, j, k] for i in (-1, 0, 1) for j in (-1, 0, 1) for k in (-1, 0, 1)])
+    idle = 0
+    if n * (math.pi / 6.0) * dmin ** 3 > 0.36 * L ** 3:
+        raise ValueError("random sequential addition cannot reach this packing fraction")
     while count < n:
+        idle += 1
+        if idle > 2000:
+            raise RuntimeError("random sequential addition jammed")
         need = n - count
         batch = int(min(max(64, need * 1.3 + 16), 1024))
         cand = rng.uniform(0.0, L, (batch, 3))
@@ -114,6 +120,7 @@ def _rsa(n: int, L: float, dmin: float, rng: np.random.Generator) -> np.ndarray:
             fill[cx, cy, cz] += 1
             pts[count] = cand[i]
             count += 1
+            idle = 0
     return pts
 
 

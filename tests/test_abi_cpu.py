@@ -1,0 +1,109 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, maps return codes to text, computes mesh dimensions (Eq.
+mesh_target and the three strategies of Sec. 2.3.1) like the oracle, and
+rejects invalid plan descriptors before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import pme as opme
+from paper_2606_01598_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib_or_skip():
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libpme.so is not built: run `python -m paper_2606_01598_amd.build`")
+    return _lib.load()
+
+
+def test_header_declarations_are_exported():
+    lib = _lib_or_skip()
+    header = open(os.path.join(ROOT, "include", "pme.h")).read()
+    declared = set(re.findall(r"\b(pme_[a-z_]+)\s*\(", header))
+    assert declared == set(_lib.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_strerror_codes():
+    lib = _lib_or_skip()
+    for code in range(-8, 1):
+        assert lib.pme_strerror(code).decode() != "unknown error"
+    assert lib.pme_strerror(-99).decode() == "unknown error"
+
+
+@pytest.mark.parametrize("strategy,code", [("pow2", 0), ("smooth", 1), ("ceil", 2)])
+def test_mesh_dims_matches_oracle(strategy, code):
+    lib = _lib_or_skip()
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        box = np.diag(rng.uniform(5, 80, 3))
+        box[1, 0] = rng.uniform(-2, 2)
+        box[2, :2] = rng.uniform(-2, 2, 2)
+        spacing = float(rng.uniform(0.3, 2.0))
+        out = (ctypes.c_int32 * 3)()
+        b = (ctypes.c_double * 9)(*box.ravel())
+        assert lib.pme_mesh_dims(b, spacing, code, out) == 0
+        assert tuple(out) == opme.mesh_dims(box, spacing, strategy)
+
+
+def test_mesh_dims_rejects_bad_input():
+    lib = _lib_or_skip()
+    out = (ctypes.c_int32 * 3)()
+    good = (ctypes.c_double * 9)(*np.eye(3).ravel() * 10)
+    sing = (ctypes.c_double * 9)(*np.zeros(9))
+    assert lib.pme_mesh_dims(good, 0.0, 1, out) == _lib.PME_EINVAL
+    assert lib.pme_mesh_dims(good, 1.0, 7, out) == _lib.PME_EINVAL
+    assert lib.pme_mesh_dims(sing, 1.0, 1, out) == _lib.PME_EINVAL
+
+
+def _desc(**kw):
+    d = _lib.PMEDesc()
+    mesh = kw.get("mesh", (16, 16, 16))
+    for k in range(3):
+        d.mesh[k] = mesh[k]
+    d.order = kw.get("order", 4)
+    d.max_atoms = kw.get("max_atoms", 64)
+    d.flags = kw.get("flags", 0)
+    d.alpha = kw.get("alpha", 0.3)
+    d.influence_power = kw.get("gamma", 1.0)
+    d.prefactor = kw.get("prefactor", 1.0)
+    return d
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(order=0), _lib.PME_EORDER),
+    (dict(order=8), _lib.PME_EORDER),
+    (dict(mesh=(16, 16, 7)), _lib.PME_EMESH),
+    (dict(mesh=(1, 16, 16)), _lib.PME_EMESH),
+    (dict(mesh=(16, 2048, 16)), _lib.PME_EMESH),
+    (dict(alpha=0.0), _lib.PME_EALPHA),
+    (dict(alpha=float("nan")), _lib.PME_EALPHA),
+    (dict(gamma=-1.0), _lib.PME_EALPHA),
+    (dict(prefactor=float("inf")), _lib.PME_EALPHA),
+    (dict(max_atoms=0), _lib.PME_EINVAL),
+    (dict(flags=8), _lib.PME_EINVAL),
+])
+def test_plan_create_validation(kw, code):
+    lib = _lib_or_skip()
+    h = ctypes.c_void_p()
+    d = _desc(**kw)
+    assert lib.pme_plan_create(ctypes.byref(d), ctypes.byref(h)) == code
+    assert not h.value
+
+
+def test_null_arguments():
+    lib = _lib_or_skip()
+    h = ctypes.c_void_p()
+    assert lib.pme_plan_create(None, ctypes.byref(h)) == _lib.PME_EINVAL
+    assert lib.pme_forward(None, None, 0, None, None, None, None, None, None, None, None) == _lib.PME_EINVAL
+    assert lib.pme_backward(None, None, 0, None, None, None, None, None, None, None, None, None,
+                            None) == _lib.PME_EINVAL
+    assert lib.pme_status(None, None) == _lib.PME_EINVAL
+    lib.pme_plan_destroy(None)
+    assert lib.pme_plan_workspace_bytes(None) == 0

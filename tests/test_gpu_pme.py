@@ -1,0 +1,242 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Bar: relative energy error <= 1e-5 (E_recip and E^lr), and for every per-atom
+output ||gpu - oracle||_rms / ||oracle||_rms <= 1e-4 (dE/dr, dE/dq, dE/dmu and
+the three Hessian-vector-product outputs).  Inputs are seeded synthetic frames;
+the oracle sees the same float32-rounded positions, charges and dipoles.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import (E_REL_TOL, RMS_REL_TOL, dev, f32, host, oracle_forward, oracle_hvp, rel,
+                      rms_rel, to_dev)
+from oracle import pme as opme
+
+pytestmark = pytest.mark.gpu
+
+
+def _plan(mesh, p, alpha, n, **kw):
+    from paper_2606_01598_amd.pme import Plan
+    return Plan(mesh, p, alpha, max_atoms=max(1, n), **kw)
+
+
+def _check_forward(frame, mesh, p, alpha, gamma=1.0, with_q=True, with_mu=True, label="",
+                   force_floor=0.0):
+    plan = _plan(mesh, p, alpha, frame.n, influence_power=gamma)
+    pos, q, mu, box = to_dev(frame, with_q, with_mu)
+    out = plan.forward(pos, q, mu, box)
+    plan.status()
+    ref = oracle_forward(frame, mesh, p, alpha, gamma, with_q=with_q, with_mu=with_mu)
+    e = host(out["energy"])
+    errs = {
+        "E_recip": rel(e[0], ref.e_recip),
+        "E_lr": rel(e.sum(), ref.energy),
+        "dE_dpos": rms_rel(host(out["dE_dpos"]), ref.dE_dpos, force_floor),
+    }
+    if with_q:
+        errs["dE_dq"] = rms_rel(host(out["dE_dq"]), ref.dE_dq)
+    if with_mu:
+        errs["dE_dmu"] = rms_rel(host(out["dE_dmu"]), ref.dE_dmu)
+    print(label, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    assert errs["E_recip"] <= E_REL_TOL and errs["E_lr"] <= E_REL_TOL
+    for k in ("dE_dpos", "dE_dq", "dE_dmu"):
+        if k in errs:
+            assert errs[k] <= RMS_REL_TOL, (k, errs[k])
+    assert rel(e[1], ref.e_self_q) < 1e-12 or (not with_q)
+    return plan, out, ref
+
+
+def test_density_and_potential_config1():
+    f = synth.rocksalt()
+    plan = _plan((16, 16, 16), 4, 0.3, f.n)
+    pos, q, mu, box = to_dev(f)
+    plan.forward(pos, q, mu, box)
+    ref = oracle_forward(f, (16, 16, 16), 4, 0.3)
+    rho, phi = host(plan.rho()), host(plan.phi())
+    print("rho", np.abs(rho - ref.rho).max(), "phi", rms_rel(phi, ref.phi), flush=True)
+    assert np.abs(rho - ref.rho).max() <= 1e-6 * np.abs(ref.rho).max()
+    assert rms_rel(phi, ref.phi) <= 1e-5
+
+
+def test_forward_config1_rocksalt_charges():
+    # 64 ions, p = 4, mesh 16^3, alpha = 0.30
+    _check_forward(synth.rocksalt(), (16, 16, 16), 4, 0.3, with_mu=False, label="cfg1")
+
+
+def test_forward_config2_molten_charges_dipoles():
+    f = synth.molten_box(1000, 1, L=31.5)
+    _check_forward(f, (32, 32, 32), 6, 0.3, label="cfg2")
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7])
+def test_forward_all_orders_ragged_mesh(p):
+    # non-cubic mesh with odd factors: tiles and FFT radices 2, 3, 4, 5 all ragged
+    f = synth.molten_box(300, 10 + p, L=20.0)
+    _check_forward(f, (18, 20, 25), p, 0.35, label=f"p{p}")
+
+
+@pytest.mark.parametrize("mesh,p", [((4, 4, 4), 6), ((2, 3, 5), 4), ((6, 6, 6), 7), ((45, 27, 16), 5),
+                                    ((64, 50, 30), 6)])
+def test_forward_small_and_odd_meshes(mesh, p):
+    f = synth.molten_box(120, 21, L=15.0)
+    _check_forward(f, mesh, p, 0.4, label=f"mesh{mesh}")
+
+
+def test_forward_triclinic_cell():
+    f = synth.triclinic_cell(n=40)
+    _check_forward(f, (20, 18, 24), 6, 0.45, label="triclinic")
+
+
+def test_forward_gamma0_and_prefactor():
+    f = synth.molten_box(200, 3, L=18.0)
+    _check_forward(f, (20, 20, 20), 5, 0.35, gamma=0.0, label="gamma0")
+    plan = _plan((20, 20, 20), 5, 0.35, f.n, prefactor=14.3996454784)
+    pos, q, mu, box = to_dev(f)
+    out = plan.forward(pos, q, mu, box)
+    ref = oracle_forward(f, (20, 20, 20), 5, 0.35, prefactor=14.3996454784)
+    assert rel(host(out["energy"]).sum(), ref.energy) <= E_REL_TOL
+    assert rms_rel(host(out["dE_dpos"]), ref.dE_dpos) <= RMS_REL_TOL
+
+
+def test_positions_outside_the_cell():
+    f = synth.molten_box(200, 5, L=18.0)
+    g = synth.Frame(pos=f.pos + np.array([3, -2, 5]) * 18.0 + 0.0, q=f.q, mu=f.mu, box=f.box)
+    _check_forward(g, (20, 20, 20), 6, 0.35, label="images")
+
+
+def test_empty_and_single_atom():
+    plan = _plan((16, 16, 16), 6, 0.3, 4)
+    box = torch.eye(3, dtype=torch.float64, device=dev()) * 12.0
+    z = torch.zeros(0, 3, dtype=torch.float32, device=dev())
+    out = plan.forward(z, torch.zeros(0, device=dev()), z.clone(), box)
+    plan.status()
+    assert np.all(host(out["energy"]) == 0.0)
+    one = synth.Frame(pos=np.array([[1.0, 2.0, 3.0]]), q=np.array([0.7]),
+                      mu=np.array([[0.1, -0.2, 0.3]]), box=np.eye(3) * 12.0)
+    # the exact force on a lone atom is only the mesh self-force (~5e-7 here):
+    # measure the error against the force scale q^2 alpha^2 instead
+    _check_forward(one, (16, 16, 16), 6, 0.3, label="one", force_floor=0.7 ** 2 * 0.3 ** 2)
+
+
+def test_hvp_config2():
+    f = synth.molten_box(1000, 1, L=31.5)
+    mesh, p, a = (32, 32, 32), 6, 0.3
+    plan = _plan(mesh, p, a, f.n)
+    pos, q, mu, box = to_dev(f)
+    plan.forward(pos, q, mu, box)
+    v = synth.random_cotangents(f.n, 5, scale_r=0.1)
+    vt = [torch.tensor(x, dtype=torch.float32, device=dev()) for x in v]
+    out = plan.backward(pos, q, mu, box, *vt)
+    ref = oracle_hvp(f, mesh, p, a, v)
+    errs = [rms_rel(host(out[k]), r) for k, r in zip(("g_pos", "g_q", "g_mu"), ref)]
+    print("hvp", [f"{e:.2e}" for e in errs], flush=True)
+    assert max(errs) <= RMS_REL_TOL
+
+
+@pytest.mark.parametrize("p,mesh", [(4, (18, 20, 25)), (5, (16, 16, 16)), (7, (20, 20, 20))])
+def test_hvp_orders_and_recompute(p, mesh):
+    f = synth.molten_box(200, 30 + p, L=17.0)
+    v = synth.random_cotangents(f.n, p, scale_r=0.2, scale_mu=0.5)
+    ref = oracle_hvp(f, mesh, p, 0.4, v)
+    vt = [torch.tensor(x, dtype=torch.float32, device=dev()) for x in v]
+    for keep in (True, False):
+        plan = _plan(mesh, p, 0.4, f.n, keep_phi=keep)
+        pos, q, mu, box = to_dev(f)
+        if keep:
+            plan.forward(pos, q, mu, box)
+        out = plan.backward(pos, q, mu, box, *vt)
+        errs = [rms_rel(host(out[k]), r) for k, r in zip(("g_pos", "g_q", "g_mu"), ref)]
+        print("hvp", p, keep, [f"{e:.2e}" for e in errs], flush=True)
+        assert max(errs) <= RMS_REL_TOL
+
+
+def test_force_loss_double_backward_through_autograd():
+    from paper_2606_01598_amd.pme import pme_energy
+    f = synth.molten_box(400, 8, L=23.0)
+    mesh, p, a = (24, 24, 24), 6, 0.35
+    plan = _plan(mesh, p, a, f.n)
+    pos, q, mu, box = to_dev(f)
+    q.requires_grad_(True)
+    mu.requires_grad_(True)
+    pos.requires_grad_(True)
+    E = pme_energy(pos, q, mu, box, plan)
+    F = -torch.autograd.grad(E, pos, create_graph=True)[0]
+    Fref = torch.tensor(np.random.default_rng(2).normal(0, 0.05, (f.n, 3)), dtype=torch.float32,
+                        device=dev())
+    loss = ((F - Fref) ** 2).mean()
+    gq, gmu = torch.autograd.grad(loss, (q, mu))
+    # oracle: dL/dF = 2 (F - Fref)/(3N); v_r = -dL/dF; the (q, mu) parts of H v_r
+    ref = oracle_forward(f, mesh, p, a)
+    vr = -2.0 * (-ref.dE_dpos - f32(host(Fref))) / (3 * f.n)
+    hq = opme.hvp(f32(f.pos), f32(f.q), f32(f.mu), f.box, mesh, p, a, v_pos=vr)
+    e1, e2 = rms_rel(host(gq), hq[1]), rms_rel(host(gmu), hq[2])
+    print("force-loss grads", e1, e2, flush=True)
+    assert e1 <= RMS_REL_TOL and e2 <= RMS_REL_TOL
+
+
+def test_finite_differences_config2():
+    """FP32 GPU gradients against central differences of the GPU energy."""
+    f = synth.molten_box(1000, 1, L=31.5)
+    mesh, p, a = (32, 32, 32), 6, 0.3
+    plan = _plan(mesh, p, a, f.n)
+    pos, q, mu, box = to_dev(f)
+    out = plan.forward(pos, q, mu, box)
+    E = lambda P, Q, M: float(host(plan.forward(P, Q, M, box, dE_dpos=False, dE_dq=False,
+                                                  dE_dmu=False)["energy"]).sum())
+    rng = np.random.default_rng(3)
+    # along q and mu the energy is quadratic: a large step is exact up to rounding
+    dq = torch.tensor(rng.normal(0, 0.5, f.n), dtype=torch.float32, device=dev())
+    dm = torch.tensor(rng.normal(0, 0.05, (f.n, 3)), dtype=torch.float32, device=dev())
+    fdq = (E(pos, q + dq, mu) - E(pos, q - dq, mu)) / 2
+    fdm = (E(pos, q, mu + dm) - E(pos, q, mu - dm)) / 2
+    assert rel(fdq, float((out["dE_dq"] * dq).sum())) < 1e-3
+    assert rel(fdm, float((out["dE_dmu"] * dm).sum())) < 1e-3
+    d = torch.tensor(rng.normal(0, 1, (f.n, 3)), dtype=torch.float32, device=dev())
+    d /= d.norm()
+    an = float((out["dE_dpos"] * d).sum())
+    best = min(rel((E(pos + h * d, q, mu) - E(pos - h * d, q, mu)) / (2 * h), an)
+               for h in (1e-1, 3e-2, 1e-2, 3e-3))
+    print("fd r", best, flush=True)
+    assert best < 1e-3
+
+
+def test_capacity_and_nonfinite_errors():
+    from paper_2606_01598_amd import _lib
+    f = synth.molten_box(100, 4, L=15.0)
+    plan = _plan((16, 16, 16), 6, 0.3, 50)
+    pos, q, mu, box = to_dev(f)
+    with pytest.raises(_lib.PMEError) as ei:
+        plan.forward(pos, q, mu, box)
+    assert ei.value.code == _lib.PME_ECAPACITY
+    plan2 = _plan((16, 16, 16), 6, 0.3, f.n)
+    bad = pos.clone()
+    bad[7, 1] = float("nan")
+    plan2.forward(bad, q, mu, box)
+    with pytest.raises(_lib.PMEError) as ei:
+        plan2.status()
+    assert ei.value.code == _lib.PME_ENONFINITE
+    # the flag clears and a good call succeeds afterwards
+    plan2.forward(pos, q, mu, box)
+    plan2.status()
+
+
+def test_overflowing_bins_still_exact():
+    # all atoms crowded into a few mesh cells: bins overflow into the list
+    rng = np.random.default_rng(9)
+    n = 300
+    pos = 5.0 + rng.uniform(0, 1.5, (n, 3))
+    q = rng.normal(0, 1, n)
+    q -= q.mean()
+    f = synth.Frame(pos=pos, q=q, mu=rng.normal(0, 0.1, (n, 3)), box=np.eye(3) * 16.0)
+    _check_forward(f, (16, 16, 16), 6, 0.3, label="crowded")
+
+
+def test_config3_32k_full_parity():
+    """The 32k-ion, 100^3, p = 6 workload timed by the benchmark, in the same launch
+    configuration, against the oracle on every atom."""
+    f = synth.molten_box(32000, 3)
+    _check_forward(f, (100, 100, 100), 6, 0.3, label="32k")
