@@ -18,6 +18,7 @@ struct pme_plan_s {
   int64_t bytes;
   int max_atoms;
   bool phi_valid;
+  int set;        // counter set of the next binning (alternates)
 };
 
 namespace {
@@ -36,14 +37,28 @@ bool five_smooth(long m) {
   return m == 1;
 }
 
-// radix schedule for a 1D length: 4s first, then 2, 3s, 5s
+pme::FastDiv fast_div(int d) {
+  pme::FastDiv f;
+  f.d = uint32_t(d);
+  f.m = d <= 1 ? 0u : uint32_t(((uint64_t(1) << 32) + uint64_t(d) - 1) / uint64_t(d));
+  return f;
+}
+
+// radix schedule for a 1D length: 4s first, then 2, 3s, 5s; per-stage constants
 bool radix_plan(int N, pme::AxisPlan& ax) {
   ax.N = N;
   ax.nst = 0;
-  int n = N;
+  int n = N, Ns = 1;
   auto push = [&](int r) {
     if (ax.nst >= pme::kMaxStages) return false;
-    ax.rad[ax.nst++] = r;
+    pme::FFTStage& st = ax.st[ax.nst++];
+    st.R = r;
+    st.Ns = Ns;
+    st.NR = N / r;
+    st.step = N / (Ns * r);
+    st.ns = fast_div(Ns);
+    st.nr = fast_div(N / r);
+    Ns *= r;
     n /= r;
     return true;
   };
@@ -71,9 +86,10 @@ hipError_t dev_alloc(T** p, size_t count, int64_t& bytes) {
 
 void free_plan(pme_plan_s* pl) {
   DevPlan& d = pl->d;
-  void* ptrs[] = {d.count, d.ovf_count, d.rec, d.ovf_rec, d.twiddle[0], d.twiddle[1],
-                  d.twiddle[2], d.deconv[0], d.deconv[1], d.deconv[2], d.rho, d.spec, d.phi,
-                  d.epart, d.spart, d.status};
+  void* ptrs[] = {d.count[0], d.count[1], d.ovf_count[0], d.ovf_count[1], d.cmax[0],
+                  d.cmax[1], d.rec, d.ovf_rec, d.twiddle[0], d.twiddle[1], d.twiddle[2],
+                  d.deconv[0], d.deconv[1], d.deconv[2], d.rho, d.spec, d.phi, d.epart,
+                  d.spart, d.status};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete pl;
@@ -145,6 +161,7 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   pl->bytes = 0;
   pl->max_atoms = desc->max_atoms;
   pl->phi_valid = false;
+  pl->set = 0;
   DevPlan& d = pl->d;
   const int p = desc->order;
   for (int a = 0; a < 3; ++a) d.N[a] = desc->mesh[a];
@@ -154,23 +171,38 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   d.prefactor = desc->prefactor;
   const long M = long(d.N[0]) * d.N[1] * d.N[2];
 
-  // bins and tiles
+  // bins of B cells and mesh tiles of T = k B cells (targets 8 x 8 x 16)
   long nbins = 1;
+  const int target[3] = {8, 8, 16};
   for (int a = 0; a < 3; ++a) {
     d.B[a] = pick_bin(d.N[a]);
     d.nb[a] = d.N[a] / d.B[a];
     nbins *= d.nb[a];
-    d.T[a] = d.N[a] < 8 ? d.N[a] : 8;
-    d.nt[a] = (d.N[a] + d.T[a] - 1) / d.T[a];
+    int k = (target[a] + d.B[a] / 2) / d.B[a];
+    if (k < 1) k = 1;
+    if (k > d.nb[a]) k = d.nb[a];
+    d.T[a] = k * d.B[a];
   }
-  {
-    long range = 1;
+  // shrink tiles until the spread tile, the scanned bin range, the gather's own
+  // bins and its LDS field region fit their bounds
+  for (;;) {
+    long range = 1, own = 1, region = 2;
     for (int a = 0; a < 3; ++a) {
       long k = (d.T[a] + p - 1 + d.B[a] - 1) / d.B[a] + 1;
       range *= (k < d.nb[a] ? k : d.nb[a]);
+      own *= d.T[a] / d.B[a];
+      region *= d.T[a] + p - 1;
     }
-    if (range > pme::kMaxBinRange) { free_plan(pl); return PME_EMESH; }
+    const long tpad = long(d.T[0]) * d.T[1] * (d.T[2] + 1);
+    if (range <= pme::kMaxBinRange && own <= 256 && tpad <= pme::kTileLds && region * 4 <= 65536)
+      break;
+    int big = 0;
+    for (int a = 1; a < 3; ++a)
+      if (d.T[a] / d.B[a] > d.T[big] / d.B[big]) big = a;
+    if (d.T[big] == d.B[big]) { free_plan(pl); return PME_EMESH; }
+    d.T[big] -= d.B[big];
   }
+  for (int a = 0; a < 3; ++a) d.nt[a] = (d.N[a] + d.T[a] - 1) / d.T[a];
   {
     const double per_bin = double(desc->max_atoms) * d.B[0] * d.B[1] * d.B[2] / double(M);
     long cap = long(ceil(2.0 * per_bin)) + 8;
@@ -181,14 +213,14 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   for (int a = 0; a < 3; ++a)
     if (!radix_plan(d.N[a], d.ax[a])) { free_plan(pl); return PME_EMESH; }
   {
-    int rp = 4096 / d.N[2];
-    rp &= ~1;
-    if (rp < 2) rp = 2;
-    if (rp > 64) rp = 64;
-    d.rows_per_block = rp;
+    // one-wave FFT workgroups: about 256 complex points each
+    int pairs = (256 + d.N[2] - 1) / d.N[2];
+    if (pairs > 32) pairs = 32;
+    d.rows_per_block = 2 * pairs;
     const int nmax = d.N[0] > d.N[1] ? d.N[0] : d.N[1];
-    int kt = (8000 - nmax) / (2 * (nmax + 1));
-    if (kt > 8) kt = 8;
+    int kt = nmax <= 64 ? 16 : (nmax <= 160 ? 8 : 4);
+    const int lds_cap = (7000 - nmax) / (2 * (nmax + 1));
+    if (kt > lds_cap) kt = lds_cap;
     if (kt < 1) kt = 1;
     if (kt > d.H) kt = d.H;
     d.ktile = kt;
@@ -197,8 +229,11 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   hipError_t e = hipSuccess;
   int64_t& by = pl->bytes;
   auto ok = [&](hipError_t r) { if (r != hipSuccess && e == hipSuccess) e = r; };
-  ok(dev_alloc(&d.count, size_t(nbins), by));
-  ok(dev_alloc(&d.ovf_count, 1, by));
+  for (int k = 0; k < 2; ++k) {
+    ok(dev_alloc(&d.count[k], size_t(nbins), by));
+    ok(dev_alloc(&d.ovf_count[k], 1, by));
+    ok(dev_alloc(&d.cmax[k], 1, by));
+  }
   ok(dev_alloc(&d.rec, size_t(nbins) * d.cap * 16, by));
   ok(dev_alloc(&d.ovf_rec, size_t(desc->max_atoms) * 16, by));
   for (int a = 0; a < 3; ++a) {
@@ -232,8 +267,11 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
     delete[] tw;
     delete[] dc;
   }
-  ok(hipMemset(d.count, 0, sizeof(int) * nbins));
-  ok(hipMemset(d.ovf_count, 0, sizeof(int)));
+  for (int k = 0; k < 2; ++k) {
+    ok(hipMemset(d.count[k], 0, sizeof(int) * nbins));
+    ok(hipMemset(d.ovf_count[k], 0, sizeof(int)));
+    ok(hipMemset(d.cmax[k], 0, sizeof(unsigned)));
+  }
   ok(hipMemset(d.status, 0, sizeof(int)));
   ok(hipMemset(d.phi, 0, sizeof(float) * M));
   ok(hipDeviceSynchronize());
@@ -265,13 +303,15 @@ int pme_forward(pme_plan_t plan, void* stream, int32_t n, const float* pos, cons
   const DevPlan& d = plan->d;
   hipError_t e;
   plan->phi_valid = false;
-  if ((e = pme::launch_bin(d, s, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
+  const int set = plan->set;
+  plan->set ^= 1;
+  if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
                            energy != nullptr)) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_spread(d, s, false)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_spread(d, s, set, false)) != hipSuccess) return hip_fail(e);
   if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr)) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_gather(d, s, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu,
+  if ((e = pme::launch_gather(d, s, set, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu,
                               pme::bin_blocks(n))) != hipSuccess)
     return hip_fail(e);
   plan->phi_valid = true;
@@ -287,19 +327,24 @@ int pme_backward(pme_plan_t plan, void* stream, int32_t n, const float* pos, con
   const DevPlan& d = plan->d;
   hipError_t e;
   if (!((plan->desc.flags & PME_F_KEEP_PHI) && plan->phi_valid)) {
-    if ((e = pme::launch_bin(d, s, n, pos, q, mu, box, nullptr, nullptr, nullptr, false, false)) !=
-        hipSuccess)
+    const int set = plan->set;
+    plan->set ^= 1;
+    if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
+                             false)) != hipSuccess)
       return hip_fail(e);
-    if ((e = pme::launch_spread(d, s, false)) != hipSuccess) return hip_fail(e);
+    if ((e = pme::launch_spread(d, s, set, false)) != hipSuccess) return hip_fail(e);
     if ((e = pme::launch_convolve(d, s, box, d.phi, false)) != hipSuccess) return hip_fail(e);
     plan->phi_valid = true;
   }
-  if ((e = pme::launch_bin(d, s, n, pos, q, mu, box, v_pos, v_q, v_mu, true, false)) != hipSuccess)
-    return hip_fail(e);
-  if ((e = pme::launch_spread(d, s, true)) != hipSuccess) return hip_fail(e);
-  if ((e = pme::launch_convolve(d, s, box, d.rho, false)) != hipSuccess) return hip_fail(e);
-  if ((e = pme::launch_gather_hvp(d, s, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q, g_mu)) !=
+  const int set = plan->set;
+  plan->set ^= 1;
+  if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, v_pos, v_q, v_mu, true, false)) !=
       hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_spread(d, s, set, true)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_convolve(d, s, box, d.rho, false)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_gather_hvp(d, s, set, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q,
+                                  g_mu)) != hipSuccess)
     return hip_fail(e);
   return PME_OK;
 }

@@ -32,21 +32,19 @@ __device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(
 __device__ __forceinline__ float2 imul(float2 a, float s) { return make_float2(-s * a.y, s * a.x); }
 
 // One radix-R Stockham butterfly of a pencil: inputs in[j + r N/R], outputs
-// out[(j/Ns) Ns R + k + r Ns], k = j mod Ns, twiddle w^(r k), w = e^{s 2 pi i/(Ns R)}.
+// out[(j/Ns) Ns R + k + r Ns], k = j mod Ns, twiddle w^(r k), w = e^{s 2 pi i/(Ns R)}
+// (table index r k N/(Ns R) < N).
 template <int R>
 __device__ __forceinline__ void butterfly(const float2* __restrict__ in, float2* __restrict__ out,
-                                          int j, int N, int Ns, const float2* __restrict__ tw,
-                                          float s) {
-  const int NR = N / R;
-  const int k = j % Ns;
-  const int step = N / (Ns * R);
+                                          int j, int k, int jq, const FFTStage& st,
+                                          const float2* __restrict__ tw, float s) {
   float2 v[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = in[j + r * NR];
+  for (int r = 0; r < R; ++r) v[r] = in[j + r * st.NR];
+  const int tstep = k * st.step;
 #pragma unroll
   for (int r = 1; r < R; ++r) {
-    int t = (r * k * step) % N;
-    float2 w = tw[t];
+    float2 w = tw[r * tstep];
     w.y *= -s;        // table holds e^{-2 pi i t/N}; s = -1 forward, +1 inverse
     v[r] = cmul(v[r], w);
   }
@@ -84,40 +82,73 @@ __device__ __forceinline__ void butterfly(const float2* __restrict__ in, float2*
     y[2] = cadd(a2, b2);
     y[3] = csub(a2, b2);
   }
-  const int base = (j / Ns) * Ns * R + k;
+  const int base = jq * st.Ns * R + k;
 #pragma unroll
-  for (int r = 0; r < R; ++r) out[base + r * Ns] = y[r];
+  for (int r = 0; r < R; ++r) out[base + r * st.Ns] = y[r];
 }
 
 // Transform npen pencils (stride ps) held in x; returns the buffer holding the result.
 __device__ float2* lds_fft(float2* x, float2* y, int npen, int ps, const AxisPlan& ax,
                            const float2* tw, float s) {
-  const int N = ax.N;
-  int Ns = 1;
-  for (int st = 0; st < ax.nst; ++st) {
-    const int R = ax.rad[st];
-    const int NR = N / R;
-    const int total = npen * NR;
+  for (int sti = 0; sti < ax.nst; ++sti) {
+    const FFTStage& st = ax.st[sti];
+    const int total = npen * st.NR;
     for (int t = threadIdx.x; t < total; t += blockDim.x) {
-      const int pen = t / NR, j = t - pen * NR;
+      const int pen = int(fdiv(uint32_t(t), st.nr));
+      const int j = t - pen * st.NR;
+      const int jq = int(fdiv(uint32_t(j), st.ns));
+      const int k = j - jq * st.Ns;
       const float2* in = x + pen * ps;
       float2* out = y + pen * ps;
-      switch (R) {
-        case 2: butterfly<2>(in, out, j, N, Ns, tw, s); break;
-        case 3: butterfly<3>(in, out, j, N, Ns, tw, s); break;
-        case 4: butterfly<4>(in, out, j, N, Ns, tw, s); break;
-        default: butterfly<5>(in, out, j, N, Ns, tw, s); break;
+      switch (st.R) {
+        case 2: butterfly<2>(in, out, j, k, jq, st, tw, s); break;
+        case 3: butterfly<3>(in, out, j, k, jq, st, tw, s); break;
+        case 4: butterfly<4>(in, out, j, k, jq, st, tw, s); break;
+        default: butterfly<5>(in, out, j, k, jq, st, tw, s); break;
       }
     }
     __syncthreads();
     float2* t = x; x = y; y = t;
-    Ns *= R;
   }
   return x;
 }
 
-__device__ __forceinline__ void load_twiddles(float2* dst, const float2* src, int N) {
-  for (int t = threadIdx.x; t < N; t += blockDim.x) dst[t] = src[t];
+// Twiddle table held in registers between its load and its LDS store, so that its
+// loads are in flight together with the data loads (N <= 16 * kFFTThreads).
+struct Twiddles {
+  float2 v[16];
+  __device__ __forceinline__ void load(const float2* src, int N) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = threadIdx.x + u * kFFTThreads;
+      if (t < N) v[u] = src[t];
+    }
+  }
+  __device__ __forceinline__ void store(float2* dst, int N) const {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = threadIdx.x + u * kFFTThreads;
+      if (t < N) dst[t] = v[u];
+    }
+  }
+};
+
+// Global -> LDS copy with U loads in flight per thread before the LDS stores.
+template <int U, class T, class Ld, class St>
+__device__ __forceinline__ void staged_copy(int total, Ld ld, St st) {
+  for (int e0 = threadIdx.x; e0 < total; e0 += U * blockDim.x) {
+    T v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e < total) v[u] = ld(e);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e < total) st(e, v[u]);
+    }
+  }
 }
 
 struct ZArgs {
@@ -126,30 +157,33 @@ struct ZArgs {
   int rows;        // N_x N_y
   int H;
   int rp;          // rows per block (even)
+  FastDiv nd;      // division by N_z
   const float* src;
   float2* spec;
   float* dst;
-  int* count;      // bin counters reset here (may be null)
-  int* ovf_count;
-  int ncount;
 };
 
 // z pass, real to complex
-__global__ void __launch_bounds__(256) k_fftz_r2c(ZArgs a) {
+__global__ void __launch_bounds__(kFFTThreads) k_fftz_r2c(ZArgs a) {
   extern __shared__ float2 sm[];
   const int N = a.ax.N, H = a.H;
   float2* tw = sm;
   float2* X = tw + N;
   float2* Y = X + (a.rp / 2) * N;
   const int r0 = blockIdx.x * a.rp;
-  load_twiddles(tw, a.tw, N);
+  Twiddles twr;
+  twr.load(a.tw, N);
   const int np = a.rp / 2;
-  for (int e = threadIdx.x; e < np * N; e += blockDim.x) {
-    const int c = e / N, m = e - c * N;
-    const int ra = r0 + 2 * c, rb = ra + 1;
-    X[e] = make_float2(ra < a.rows ? a.src[size_t(ra) * N + m] : 0.0f,
-                       rb < a.rows ? a.src[size_t(rb) * N + m] : 0.0f);
-  }
+  staged_copy<16, float2>(
+      np * N,
+      [&](int e) {
+        const int c = int(fdiv(uint32_t(e), a.nd)), m = e - c * N;
+        const int ra = r0 + 2 * c, rb = ra + 1;
+        return make_float2(ra < a.rows ? a.src[size_t(ra) * N + m] : 0.0f,
+                           rb < a.rows ? a.src[size_t(rb) * N + m] : 0.0f);
+      },
+      [&](int e, float2 v) { X[e] = v; });
+  twr.store(tw, N);
   __syncthreads();
   const float2* Z = lds_fft(X, Y, np, N, a.ax, tw, -1.0f);
   for (int e = threadIdx.x; e < a.rp * H; e += blockDim.x) {
@@ -164,15 +198,10 @@ __global__ void __launch_bounds__(256) k_fftz_r2c(ZArgs a) {
     else v = make_float2(0.5f * (zk.y + zn.y), -0.5f * (zk.x - zn.x));
     a.spec[size_t(row) * H + k] = v;
   }
-  if (a.count) {
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int e = gid; e < a.ncount; e += gridDim.x * blockDim.x) a.count[e] = 0;
-    if (gid == 0) *a.ovf_count = 0;
-  }
 }
 
 // z pass, complex to real
-__global__ void __launch_bounds__(256) k_fftz_c2r(ZArgs a) {
+__global__ void __launch_bounds__(kFFTThreads) k_fftz_c2r(ZArgs a) {
   extern __shared__ float2 sm[];
   const int N = a.ax.N, H = a.H;
   float2* tw = sm;
@@ -180,11 +209,13 @@ __global__ void __launch_bounds__(256) k_fftz_c2r(ZArgs a) {
   float2* X = S + a.rp * H;
   float2* Y = X + (a.rp / 2) * N;
   const int r0 = blockIdx.x * a.rp;
-  load_twiddles(tw, a.tw, N);
-  for (int e = threadIdx.x; e < a.rp * H; e += blockDim.x) {
-    const int rr = e / H;
-    S[e] = (r0 + rr < a.rows) ? a.spec[size_t(r0) * H + e] : make_float2(0.f, 0.f);
-  }
+  Twiddles twr;
+  twr.load(a.tw, N);
+  const int nvalid = min(a.rp, a.rows - r0) * H;
+  staged_copy<16, float2>(
+      a.rp * H, [&](int e) { return e < nvalid ? a.spec[size_t(r0) * H + e] : make_float2(0.f, 0.f); },
+      [&](int e, float2 v) { S[e] = v; });
+  twr.store(tw, N);
   __syncthreads();
   const int np = a.rp / 2;
   const bool even = (N & 1) == 0;
@@ -218,12 +249,13 @@ struct YArgs {
   AxisPlan ax;
   const float2* tw;
   int Ny, H, kt;
+  FastDiv ktd;
   float2* spec;
   float sign;
 };
 
 // y pass: block = (x, tile of kz columns)
-__global__ void __launch_bounds__(256) k_ffty(YArgs a) {
+__global__ void __launch_bounds__(kFFTThreads) k_ffty(YArgs a) {
   extern __shared__ float2 sm[];
   const int N = a.ax.N, H = a.H, kt = a.kt;
   const int ps = N + 1;
@@ -232,13 +264,21 @@ __global__ void __launch_bounds__(256) k_ffty(YArgs a) {
   float2* Y = X + kt * ps;
   const int ntk = (H + kt - 1) / kt;
   const int x = blockIdx.x / ntk, kz0 = (blockIdx.x - x * ntk) * kt;
-  load_twiddles(tw, a.tw, N);
+  Twiddles twr;
+  twr.load(a.tw, N);
   float2* base = a.spec + size_t(x) * a.Ny * H;
-  for (int e = threadIdx.x; e < N * kt; e += blockDim.x) {
-    const int yy = e / kt, l = e - yy * kt;
-    const int kz = kz0 + l;
-    X[l * ps + yy] = (kz < H) ? base[size_t(yy) * H + kz] : make_float2(0.f, 0.f);
-  }
+  staged_copy<16, float2>(
+      N * kt,
+      [&](int e) {
+        const int yy = int(fdiv(uint32_t(e), a.ktd)), l = e - yy * kt;
+        const int kz = kz0 + l;
+        return (kz < H) ? base[size_t(yy) * H + kz] : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) {
+        const int yy = int(fdiv(uint32_t(e), a.ktd)), l = e - yy * kt;
+        X[l * ps + yy] = v;
+      });
+  twr.store(tw, N);
   __syncthreads();
   const float2* Z = lds_fft(X, Y, kt, ps, a.ax, tw, a.sign);
   for (int e = threadIdx.x; e < N * kt; e += blockDim.x) {
@@ -253,6 +293,7 @@ struct XArgs {
   const float2* tw;
   int N[3];
   int H, kt;
+  FastDiv ktd;
   float2* spec;
   const double* box;
   const float* dcx;
@@ -265,7 +306,7 @@ struct XArgs {
 __device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) / 2) ? k - N : k; }
 
 // x pass fused with the influence function
-__global__ void __launch_bounds__(256) k_fftx_fused(XArgs a) {
+__global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
   extern __shared__ float2 sm[];
   __shared__ double red[8];
   const int Nx = a.N[0], Ny = a.N[1], Nz = a.N[2], H = a.H, kt = a.kt;
@@ -275,14 +316,22 @@ __global__ void __launch_bounds__(256) k_fftx_fused(XArgs a) {
   float2* Y = X + kt * ps;
   const int ntk = (H + kt - 1) / kt;
   const int y = blockIdx.x / ntk, kz0 = (blockIdx.x - y * ntk) * kt;
-  load_twiddles(tw, a.tw, Nx);
+  Twiddles twr;
+  twr.load(a.tw, Nx);
   const size_t xstride = size_t(Ny) * H;
   float2* base = a.spec + size_t(y) * H;
-  for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
-    const int xx = e / kt, l = e - xx * kt;
-    const int kz = kz0 + l;
-    X[l * ps + xx] = (kz < H) ? base[xx * xstride + kz] : make_float2(0.f, 0.f);
-  }
+  staged_copy<16, float2>(
+      Nx * kt,
+      [&](int e) {
+        const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
+        const int kz = kz0 + l;
+        return (kz < H) ? base[xx * xstride + kz] : make_float2(0.f, 0.f);
+      },
+      [&](int e, float2 v) {
+        const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
+        X[l * ps + xx] = v;
+      });
+  twr.store(tw, Nx);
   __syncthreads();
   float2* Z = lds_fft(X, Y, kt, ps, a.ax, tw, -1.0f);
   float2* W = (Z == X) ? Y : X;
@@ -314,7 +363,7 @@ __global__ void __launch_bounds__(256) k_fftx_fused(XArgs a) {
                        2.0f * (M[0][1] * ffx * ffy + M[0][2] * ffx * ffz + M[1][2] * ffy * ffz);
       float g = 0.0f;
       if (fx != 0 || fy != 0 || fz != 0) {
-        g = 4.0f * float(M_PI) / k2 * __expf(-k2 * inv4a2);
+        g = 4.0f * float(M_PI) / k2 * expf(-k2 * inv4a2);
         const bool nx = ((Nx & 1) == 0) && (fx == -Nx / 2);
         const bool nz = ((Nz & 1) == 0) && (fz == -Nz / 2);
         if (nx || nyq_y || nz) {
@@ -322,7 +371,7 @@ __global__ void __launch_bounds__(256) k_fftx_fused(XArgs a) {
           const float px = nx ? ffx : -ffx, py = nyq_y ? ffy : -ffy, pz = nz ? ffz : -ffz;
           const float k2p = M[0][0] * px * px + M[1][1] * py * py + M[2][2] * pz * pz +
                             2.0f * (M[0][1] * px * py + M[0][2] * px * pz + M[1][2] * py * pz);
-          if (k2p != k2) g = 0.5f * (g + 4.0f * float(M_PI) / k2p * __expf(-k2p * inv4a2));
+          if (k2p != k2) g = 0.5f * (g + 4.0f * float(M_PI) / k2p * expf(-k2p * inv4a2));
         }
         g *= a.dcx[i] * a.dcy[y] * a.dcz[kz];
       }
@@ -346,6 +395,13 @@ __global__ void __launch_bounds__(256) k_fftx_fused(XArgs a) {
   }
 }
 
+FastDiv host_fastdiv(int d) {
+  FastDiv f;
+  f.d = uint32_t(d);
+  f.m = d <= 1 ? 0u : uint32_t(((uint64_t(1) << 32) + uint64_t(d) - 1) / uint64_t(d));
+  return f;
+}
+
 }  // namespace
 
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
@@ -354,37 +410,38 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   ZArgs z;
   z.ax = d.ax[2]; z.tw = d.twiddle[2]; z.rows = rows; z.H = d.H; z.rp = d.rows_per_block;
   z.src = d.rho; z.spec = d.spec; z.dst = out;
-  z.count = d.count; z.ovf_count = d.ovf_count; z.ncount = d.nb[0] * d.nb[1] * d.nb[2];
+  z.nd = host_fastdiv(d.N[2]);
   const int zb = fftz_blocks(d);
   const size_t zsh_f = sizeof(float2) * (d.N[2] + d.rows_per_block * d.N[2]);
-  hipLaunchKernelGGL(k_fftz_r2c, dim3(zb), dim3(256), zsh_f, s, z);
+  hipLaunchKernelGGL(k_fftz_r2c, dim3(zb), dim3(kFFTThreads), zsh_f, s, z);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
 
   YArgs y;
   y.ax = d.ax[1]; y.tw = d.twiddle[1]; y.Ny = d.N[1]; y.H = d.H; y.kt = d.ktile; y.spec = d.spec;
+  y.ktd = host_fastdiv(d.ktile);
   const size_t ysh = sizeof(float2) * (d.N[1] + 2 * d.ktile * (d.N[1] + 1));
   y.sign = -1.0f;
-  hipLaunchKernelGGL(k_ffty, dim3(ffty_blocks(d)), dim3(256), ysh, s, y);
+  hipLaunchKernelGGL(k_ffty, dim3(ffty_blocks(d)), dim3(kFFTThreads), ysh, s, y);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
   XArgs x;
   x.ax = d.ax[0]; x.tw = d.twiddle[0];
   for (int k = 0; k < 3; ++k) x.N[k] = d.N[k];
-  x.H = d.H; x.kt = d.ktile; x.spec = d.spec; x.box = box;
+  x.H = d.H; x.kt = d.ktile; x.ktd = host_fastdiv(d.ktile); x.spec = d.spec; x.box = box;
   x.dcx = d.deconv[0]; x.dcy = d.deconv[1]; x.dcz = d.deconv[2];
   x.alpha = float(d.alpha);
   x.epart = energy ? d.epart : nullptr;
   const size_t xsh = sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1));
-  hipLaunchKernelGGL(k_fftx_fused, dim3(fftx_blocks(d)), dim3(256), xsh, s, x);
+  hipLaunchKernelGGL(k_fftx_fused, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
   y.sign = +1.0f;
-  hipLaunchKernelGGL(k_ffty, dim3(ffty_blocks(d)), dim3(256), ysh, s, y);
+  hipLaunchKernelGGL(k_ffty, dim3(ffty_blocks(d)), dim3(kFFTThreads), ysh, s, y);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
   const size_t zsh_i = sizeof(float2) * (d.N[2] + d.rows_per_block * d.H + d.rows_per_block * d.N[2]);
-  hipLaunchKernelGGL(k_fftz_c2r, dim3(zb), dim3(256), zsh_i, s, z);
+  hipLaunchKernelGGL(k_fftz_c2r, dim3(zb), dim3(kFFTThreads), zsh_i, s, z);
   return hipGetLastError();
 }
 

@@ -1,6 +1,13 @@
 // Gradient gather (Eqs. energy_recip, self_q, self_mu, E_lr_total, forces) and
 // the Hessian-vector product gather.
 //
+// One workgroup per mesh tile: it stages the potential (and the tangent
+// potential) over the tile plus the stencil halo in LDS, takes the atoms whose
+// stencil anchor lies in the tile from the bins, and gives each atom p lanes of a
+// wavefront (one x-plane of the stencil each).  The lanes' partial stencil sums are
+// combined with wavefront shuffles.  The gathers are the last readers of the atom
+// bins of its counter set; the next binning clears that set.
+//
 // For atom i with stencil weights W (and x-space derivatives d_a W), the
 // derivatives of E^lr = (1/2V) rho^T K rho + E_self are stencil sums of the
 // potential phi = K rho:
@@ -45,7 +52,18 @@ struct GArgs {
   int n_spart;
   double alpha;
   double prefactor;
+  int B[3];
+  int nb[3];
+  int cap;
+  const int* count;
+  const int* ovf_count;
+  const float* rec;
+  const float* ovf_rec;
+  int T[3];
+  int nt[3];
 };
+
+constexpr int kMaxOwnBins = 256;
 
 __device__ void finalize_energy(const GArgs& a, const Cell& c) {
   __shared__ double red[8];
@@ -84,254 +102,422 @@ __device__ __forceinline__ void st3(float* p, int i, float3 v) {
   if (p) { p[3 * i] = v.x; p[3 * i + 1] = v.y; p[3 * i + 2] = v.z; }
 }
 
+// Sum over the P consecutive lanes of a group; the total lands on the group's first lane.
+template <int P>
+__device__ __forceinline__ float group_sum(float v, int ix) {
+#pragma unroll
+  for (int off = 1; off < P; off <<= 1) {
+    const float o = __shfl_down(v, off, 64);
+    if (ix + off < P) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ FastDiv make_fastdiv(int d) {
+  FastDiv f;
+  f.d = uint32_t(d);
+  f.m = d <= 1 ? 0u : uint32_t(((1ull << 32) + uint64_t(d) - 1) / uint64_t(d));
+  return f;
+}
+
+// Tile setup shared by both gathers: LDS staging of the field(s) over the tile plus
+// halo, and the occupied-slot counts of the tile's own bins (s_off[0..nown)) and of
+// the overflow list (s_off[nown]); all loads are issued before the first wait.
+template <int P, bool TWO>
+__device__ __forceinline__ void stage_tile(const GArgs& a, float* sm, int (&t0)[3], int (&T)[3],
+                                           int (&E)[3], int* s_off, int* s_bin, int& nown) {
+  constexpr int lo = (P - 1) / 2;
+  {
+    int t = blockIdx.x;
+    const int tz = t % a.nt[2];
+    t /= a.nt[2];
+    const int ty = t % a.nt[1];
+    const int tx = t / a.nt[1];
+    const int tc[3] = {tx, ty, tz};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      t0[ax] = tc[ax] * a.T[ax];
+      T[ax] = min(a.T[ax], a.N[ax] - t0[ax]);
+      E[ax] = T[ax] + P - 1;
+    }
+  }
+  int nbo[3], kb0[3];
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    nbo[ax] = T[ax] / a.B[ax];
+    kb0[ax] = t0[ax] / a.B[ax];
+  }
+  nown = nbo[0] * nbo[1] * nbo[2];
+  for (int e = threadIdx.x; e < nown; e += blockDim.x) {
+    const int kz = e % nbo[2], ky = (e / nbo[2]) % nbo[1], kx = e / (nbo[1] * nbo[2]);
+    const int bin = ((kb0[0] + kx) * a.nb[1] + kb0[1] + ky) * a.nb[2] + kb0[2] + kz;
+    s_bin[e] = bin;
+    s_off[e] = min(a.count[bin], a.cap);
+  }
+  if (threadIdx.x == 0) {
+    s_bin[nown] = -1;
+    s_off[nown] = *a.ovf_count;
+  }
+  const int EV = E[0] * E[1] * E[2];
+  const FastDiv d2 = make_fastdiv(E[2]), d1 = make_fastdiv(E[1]);
+  const bool small = (a.N[0] < P) || (a.N[1] < P) || (a.N[2] < P);
+  constexpr int U = 16;   // loads kept in flight per thread
+  for (int e0 = threadIdx.x; e0 < EV; e0 += U * blockDim.x) {
+    float vphi[U], vpsi[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * blockDim.x;
+      const int ec = min(e, EV - 1);
+      const int r = int(fdiv(uint32_t(ec), d2)), ez = ec - r * E[2];
+      const int ex = int(fdiv(uint32_t(r), d1)), ey = r - ex * E[1];
+      int mx = t0[0] - lo + ex, my = t0[1] - lo + ey, mz = t0[2] - lo + ez;
+      if (small) {
+        mx = wrapn(mx, a.N[0]); my = wrapn(my, a.N[1]); mz = wrapn(mz, a.N[2]);
+      } else {
+        mx = (mx < 0) ? mx + a.N[0] : ((mx >= a.N[0]) ? mx - a.N[0] : mx);
+        my = (my < 0) ? my + a.N[1] : ((my >= a.N[1]) ? my - a.N[1] : my);
+        mz = (mz < 0) ? mz + a.N[2] : ((mz >= a.N[2]) ? mz - a.N[2] : mz);
+      }
+      const size_t g = (size_t(mx) * a.N[1] + my) * a.N[2] + mz;
+      vphi[u] = a.phi[g];
+      if (TWO) vpsi[u] = a.psi[g];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * blockDim.x;
+      if (e < EV) {
+        sm[e] = vphi[u];
+        if (TWO) sm[EV + e] = vpsi[u];
+      }
+    }
+  }
+  __syncthreads();
+  // exclusive scan of s_off[0..nown] (wavefront 0)
+  if (threadIdx.x < 64) {
+    const int tid = threadIdx.x;
+    const int len = nown + 1;
+    const int seg = (len + 63) / 64;
+    const int s0 = min(tid * seg, len), s1 = min(s0 + seg, len);
+    int acc = 0;
+    for (int e = s0; e < s1; ++e) acc += s_off[e];
+    int incl = acc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (tid >= o) incl += v;
+    }
+    int run = incl - acc;
+    for (int e = s0; e < s1; ++e) { const int v = s_off[e]; s_off[e] = run; run += v; }
+    if (tid == 63) s_off[len] = incl;
+  }
+  __syncthreads();
+}
+
+// Record of item `item` of the tile's slot space and whether the tile owns the atom
+// (own-bin records always; overflow records when their anchor lies in the tile).
+__device__ __forceinline__ const float4* item_record(const GArgs& a, int item, int nown,
+                                                     const int* s_off, const int* s_bin,
+                                                     const int (&t0)[3], const int (&T)[3],
+                                                     bool& owned) {
+  int lo_i = 0, hi_i = nown;
+  while (lo_i < hi_i) {
+    const int mid = (lo_i + hi_i + 1) >> 1;
+    if (s_off[mid] <= item) lo_i = mid; else hi_i = mid - 1;
+  }
+  const int bin = s_bin[lo_i];
+  const int slot = item - s_off[lo_i];
+  const float4* r = reinterpret_cast<const float4*>(
+      (bin >= 0) ? a.rec + (size_t(bin) * a.cap + slot) * kRecWords
+                 : a.ovf_rec + size_t(slot) * kRecWords);
+  owned = true;
+  if (bin < 0) {
+    const int pk = __float_as_int(r[0].w);
+    const int b0 = pk & 1023, b1 = (pk >> 10) & 1023, b2 = (pk >> 20) & 1023;
+    owned = b0 >= t0[0] && b0 < t0[0] + T[0] && b1 >= t0[1] && b1 < t0[1] + T[1] &&
+            b2 >= t0[2] && b2 < t0[2] + T[2];
+  }
+  return r;
+}
+
 template <int P>
 __global__ void __launch_bounds__(256) k_gather(GArgs a) {
-  constexpr int lo = (P - 1) / 2;
+  extern __shared__ float sm[];
+  __shared__ int s_off[kMaxOwnBins + 2];
+  __shared__ int s_bin[kMaxOwnBins + 1];
+  constexpr int APW = 64 / P;
   const Cell c = cell_from_box(a.box);
   if (blockIdx.x == 0 && a.energy) finalize_energy(a, c);
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.n) return;
-  int base[3];
-  float f[3];
-  const bool ok = atom_stencil<P>(a.pos, i, c, a.N, base, f);
-  if (!ok) {
-    const float nan = __int_as_float(0x7fc00000);
-    st3(a.o_pos, i, make_float3(nan, nan, nan));
-    st3(a.o_mu, i, make_float3(nan, nan, nan));
-    if (a.o_q) a.o_q[i] = nan;
-    return;
-  }
-  float wy[3][P], wz[3][P];
-  spline_weights<P, 2>(f[1], wy);
-  spline_weights<P, 2>(f[2], wz);
-  const int Ny = a.N[1], Nz = a.N[2];
-  int zi[P];
-#pragma unroll
-  for (int k = 0; k < P; ++k) zi[k] = wrapn(base[2] - lo + k, Nz);
-  // S: 000, 100, 010, 001, 200, 020, 002, 110, 101, 011
-  float S000 = 0, S100 = 0, S010 = 0, S001 = 0, S200 = 0, S020 = 0, S002 = 0, S110 = 0, S101 = 0,
-        S011 = 0;
-#pragma unroll 1
-  for (int ix = 0; ix < P; ++ix) {
-    float wx[3];
-    spline_weight_at<P, 2>(ix, f[0], wx);
-    const int mx = wrapn(base[0] - lo + ix, a.N[0]);
-    float Y00 = 0, Y01 = 0, Y02 = 0, Y10 = 0, Y11 = 0, Y20 = 0;
-#pragma unroll
-    for (int iy = 0; iy < P; ++iy) {
-      const int my = wrapn(base[1] - lo + iy, Ny);
-      const float* row = a.phi + (size_t(mx) * Ny + my) * Nz;
-      float z0 = 0, z1 = 0, z2 = 0;
-#pragma unroll
-      for (int iz = 0; iz < P; ++iz) {
-        const float v = row[zi[iz]];
-        z0 = fmaf(v, wz[0][iz], z0);
-        z1 = fmaf(v, wz[1][iz], z1);
-        z2 = fmaf(v, wz[2][iz], z2);
-      }
-      Y00 = fmaf(wy[0][iy], z0, Y00);
-      Y01 = fmaf(wy[0][iy], z1, Y01);
-      Y02 = fmaf(wy[0][iy], z2, Y02);
-      Y10 = fmaf(wy[1][iy], z0, Y10);
-      Y11 = fmaf(wy[1][iy], z1, Y11);
-      Y20 = fmaf(wy[2][iy], z0, Y20);
-    }
-    S000 = fmaf(wx[0], Y00, S000);
-    S001 = fmaf(wx[0], Y01, S001);
-    S002 = fmaf(wx[0], Y02, S002);
-    S010 = fmaf(wx[0], Y10, S010);
-    S011 = fmaf(wx[0], Y11, S011);
-    S020 = fmaf(wx[0], Y20, S020);
-    S100 = fmaf(wx[1], Y00, S100);
-    S101 = fmaf(wx[1], Y01, S101);
-    S110 = fmaf(wx[1], Y10, S110);
-    S200 = fmaf(wx[2], Y00, S200);
-  }
+  int t0[3], T[3], E[3], nown;
+  stage_tile<P, false>(a, sm, t0, T, E, s_off, s_bin, nown);
+  const int total = s_off[nown + 1];
   float J[3][3];
   jacobian(c, a.N, J);
   const float iv = float(1.0 / c.vol);
   const float pf = float(a.prefactor);
-  const float q = a.q ? a.q[i] : 0.0f;
-  const float3 mu = ld3(a.mu, i);
-  const float3 d = jmul(J, mu);
-  const float3 G = make_float3(S100, S010, S001);
-  const float3 Hd = make_float3(S200 * d.x + S110 * d.y + S101 * d.z,
-                                S110 * d.x + S020 * d.y + S011 * d.z,
-                                S101 * d.x + S011 * d.y + S002 * d.z);
   const float cq = float(2.0 * a.alpha / sqrt(M_PI));
   const float cm = float(4.0 * a.alpha * a.alpha * a.alpha / (3.0 * sqrt(M_PI)));
-  if (a.o_q) a.o_q[i] = pf * (S000 * iv - cq * q);
-  if (a.o_mu) {
-    const float3 g = jtmul(J, G);
-    st3(a.o_mu, i, make_float3(pf * (g.x * iv - cm * mu.x), pf * (g.y * iv - cm * mu.y),
-                               pf * (g.z * iv - cm * mu.z)));
-  }
-  if (a.o_pos) {
-    const float3 g = jtmul(J, make_float3(q * G.x + Hd.x, q * G.y + Hd.y, q * G.z + Hd.z));
-    st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gslot = lane / P, ix = lane - gslot * P;
+  for (int b0 = 0; b0 < total; b0 += 4 * APW) {
+    const int item = b0 + wave * APW + gslot;
+    bool active = (gslot < APW) && (item < total);
+    float S000 = 0, S100 = 0, S010 = 0, S001 = 0, S200 = 0, S020 = 0, S002 = 0, S110 = 0,
+          S101 = 0, S011 = 0;
+    int atom = 0;
+    float q = 0.f;
+    float3 mu = make_float3(0.f, 0.f, 0.f);
+    if (active) {
+      bool owned;
+      const float4* r = item_record(a, item, nown, s_off, s_bin, t0, T, owned);
+      active = owned;
+      const float4 h = r[0], rq = r[1], rm = r[2], ri = r[3];
+      atom = __float_as_int(ri.w);
+      q = rq.x;
+      mu = make_float3(rm.x, rm.y, rm.z);
+      if (active) {
+        const int pk = __float_as_int(h.w);
+        const int lx = (pk & 1023) - t0[0] + ix;
+        const int yb = ((pk >> 10) & 1023) - t0[1], zb = ((pk >> 20) & 1023) - t0[2];
+        float wy[3][P], wz[3][P], wx[3];
+        spline_weights<P, 2>(h.y, wy);
+        spline_weights<P, 2>(h.z, wz);
+        spline_weight_at<P, 2>(ix, h.x, wx);
+        const float* plane = sm + (lx * E[1] + yb) * E[2] + zb;
+        float Y00 = 0, Y01 = 0, Y02 = 0, Y10 = 0, Y11 = 0, Y20 = 0;
+#pragma unroll
+        for (int iy = 0; iy < P; ++iy) {
+          const float* row = plane + iy * E[2];
+          float z0 = 0, z1 = 0, z2 = 0;
+#pragma unroll
+          for (int iz = 0; iz < P; ++iz) {
+            const float v = row[iz];
+            z0 = fmaf(v, wz[0][iz], z0);
+            z1 = fmaf(v, wz[1][iz], z1);
+            z2 = fmaf(v, wz[2][iz], z2);
+          }
+          Y00 = fmaf(wy[0][iy], z0, Y00);
+          Y01 = fmaf(wy[0][iy], z1, Y01);
+          Y02 = fmaf(wy[0][iy], z2, Y02);
+          Y10 = fmaf(wy[1][iy], z0, Y10);
+          Y11 = fmaf(wy[1][iy], z1, Y11);
+          Y20 = fmaf(wy[2][iy], z0, Y20);
+        }
+        S000 = wx[0] * Y00; S001 = wx[0] * Y01; S002 = wx[0] * Y02;
+        S010 = wx[0] * Y10; S011 = wx[0] * Y11; S020 = wx[0] * Y20;
+        S100 = wx[1] * Y00; S101 = wx[1] * Y01; S110 = wx[1] * Y10;
+        S200 = wx[2] * Y00;
+      }
+    }
+    S000 = group_sum<P>(S000, ix); S100 = group_sum<P>(S100, ix);
+    S010 = group_sum<P>(S010, ix); S001 = group_sum<P>(S001, ix);
+    S200 = group_sum<P>(S200, ix); S020 = group_sum<P>(S020, ix);
+    S002 = group_sum<P>(S002, ix); S110 = group_sum<P>(S110, ix);
+    S101 = group_sum<P>(S101, ix); S011 = group_sum<P>(S011, ix);
+    if (active && ix == 0) {
+      const int i = atom;
+      const float3 d = jmul(J, mu);
+      const float3 G = make_float3(S100, S010, S001);
+      const float3 Hd = make_float3(S200 * d.x + S110 * d.y + S101 * d.z,
+                                    S110 * d.x + S020 * d.y + S011 * d.z,
+                                    S101 * d.x + S011 * d.y + S002 * d.z);
+      if (a.o_q) a.o_q[i] = pf * (S000 * iv - cq * q);
+      if (a.o_mu) {
+        const float3 g = jtmul(J, G);
+        st3(a.o_mu, i, make_float3(pf * (g.x * iv - cm * mu.x), pf * (g.y * iv - cm * mu.y),
+                                   pf * (g.z * iv - cm * mu.z)));
+      }
+      if (a.o_pos) {
+        const float3 g = jtmul(J, make_float3(q * G.x + Hd.x, q * G.y + Hd.y, q * G.z + Hd.z));
+        st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+      }
+    }
   }
 }
 
 template <int P>
 __global__ void __launch_bounds__(256) k_gather_hvp(GArgs a) {
-  constexpr int lo = (P - 1) / 2;
+  extern __shared__ float sm[];
+  __shared__ int s_off[kMaxOwnBins + 2];
+  __shared__ int s_bin[kMaxOwnBins + 1];
+  constexpr int APW = 64 / P;
   const Cell c = cell_from_box(a.box);
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= a.n) return;
-  int base[3];
-  float f[3];
-  const bool ok = atom_stencil<P>(a.pos, i, c, a.N, base, f);
-  if (!ok) {
-    const float nan = __int_as_float(0x7fc00000);
-    st3(a.o_pos, i, make_float3(nan, nan, nan));
-    st3(a.o_mu, i, make_float3(nan, nan, nan));
-    if (a.o_q) a.o_q[i] = nan;
-    return;
-  }
-  float wy[4][P], wz[4][P];
-  spline_weights<P, 3>(f[1], wy);
-  spline_weights<P, 3>(f[2], wz);
-  const int Ny = a.N[1], Nz = a.N[2];
-  int zi[P];
-#pragma unroll
-  for (int k = 0; k < P; ++k) zi[k] = wrapn(base[2] - lo + k, Nz);
-  // phi sums S_abc, 1 <= a+b+c <= 3; psi sums P_abc, a+b+c <= 2
-  float S[4][4][4];
-  float Q[3][3][3];
-#pragma unroll
-  for (int x = 0; x < 4; ++x)
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-#pragma unroll
-      for (int z = 0; z < 4; ++z) S[x][y][z] = 0.0f;
-#pragma unroll
-  for (int x = 0; x < 3; ++x)
-#pragma unroll
-    for (int y = 0; y < 3; ++y)
-#pragma unroll
-      for (int z = 0; z < 3; ++z) Q[x][y][z] = 0.0f;
-#pragma unroll 1
-  for (int ix = 0; ix < P; ++ix) {
-    float wx[4];
-    spline_weight_at<P, 3>(ix, f[0], wx);
-    const int mx = wrapn(base[0] - lo + ix, a.N[0]);
-    float Ys[4][4], Yq[3][3];
-#pragma unroll
-    for (int y = 0; y < 4; ++y)
-#pragma unroll
-      for (int z = 0; z < 4; ++z) Ys[y][z] = 0.0f;
-#pragma unroll
-    for (int y = 0; y < 3; ++y)
-#pragma unroll
-      for (int z = 0; z < 3; ++z) Yq[y][z] = 0.0f;
-#pragma unroll
-    for (int iy = 0; iy < P; ++iy) {
-      const int my = wrapn(base[1] - lo + iy, Ny);
-      const size_t roff = (size_t(mx) * Ny + my) * Nz;
-      const float* rphi = a.phi + roff;
-      const float* rpsi = a.psi + roff;
-      float zs[4] = {0, 0, 0, 0}, zq[3] = {0, 0, 0};
-#pragma unroll
-      for (int iz = 0; iz < P; ++iz) {
-        const float v = rphi[zi[iz]], u = rpsi[zi[iz]];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) zs[k] = fmaf(v, wz[k][iz], zs[k]);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) zq[k] = fmaf(u, wz[k][iz], zq[k]);
-      }
-#pragma unroll
-      for (int b = 0; b < 4; ++b)
-#pragma unroll
-        for (int k = 0; k + b < 4; ++k) Ys[b][k] = fmaf(wy[b][iy], zs[k], Ys[b][k]);
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int k = 0; k + b < 3; ++k) Yq[b][k] = fmaf(wy[b][iy], zq[k], Yq[b][k]);
-    }
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int b = 0; b + x < 4; ++b)
-#pragma unroll
-        for (int k = 0; k + b + x < 4; ++k) S[x][b][k] = fmaf(wx[x], Ys[b][k], S[x][b][k]);
-#pragma unroll
-    for (int x = 0; x < 3; ++x)
-#pragma unroll
-      for (int b = 0; b + x < 3; ++b)
-#pragma unroll
-        for (int k = 0; k + b + x < 3; ++k) Q[x][b][k] = fmaf(wx[x], Yq[b][k], Q[x][b][k]);
-  }
+  int t0[3], T[3], E[3], nown;
+  stage_tile<P, true>(a, sm, t0, T, E, s_off, s_bin, nown);
+  const int EV = E[0] * E[1] * E[2];
+  const int total = s_off[nown + 1];
   float J[3][3];
   jacobian(c, a.N, J);
   const float iv = float(1.0 / c.vol);
   const float pf = float(a.prefactor);
-  const float q = a.q ? a.q[i] : 0.0f;
-  const float3 mu = ld3(a.mu, i);
-  const float vq = a.v_q ? a.v_q[i] : 0.0f;
-  const float3 vr = ld3(a.v_pos, i);
-  const float3 vm = ld3(a.v_mu, i);
-  const float3 d3 = jmul(J, mu);
-  const float3 v3 = jmul(J, vr);
-  const float3 w3 = jmul(J, make_float3(vm.x + q * vr.x, vm.y + q * vr.y, vm.z + q * vr.z));
-  const float d[3] = {d3.x, d3.y, d3.z}, v[3] = {v3.x, v3.y, v3.z}, w[3] = {w3.x, w3.y, w3.z};
-  // index helpers: unit multi-indices
-  float S1[3], P1[3], S2[3][3], P2[3][3];
-#pragma unroll
-  for (int x = 0; x < 3; ++x) {
-    const int ex[3] = {x == 0, x == 1, x == 2};
-    S1[x] = S[ex[0]][ex[1]][ex[2]];
-    P1[x] = Q[ex[0]][ex[1]][ex[2]];
-#pragma unroll
-    for (int y = 0; y < 3; ++y) {
-      const int e0 = ex[0] + (y == 0), e1 = ex[1] + (y == 1), e2 = ex[2] + (y == 2);
-      S2[x][y] = S[e0][e1][e2];
-      P2[x][y] = Q[e0][e1][e2];
-    }
-  }
-  float T3[3] = {0, 0, 0};   // S3(d, v, .)
-#pragma unroll
-  for (int x = 0; x < 3; ++x)
-#pragma unroll
-    for (int y = 0; y < 3; ++y)
-#pragma unroll
-      for (int z = 0; z < 3; ++z) {
-        const int e0 = (x == 0) + (y == 0) + (z == 0);
-        const int e1 = (x == 1) + (y == 1) + (z == 1);
-        const int e2 = (x == 2) + (y == 2) + (z == 2);
-        T3[z] = fmaf(d[x] * v[y], S[e0][e1][e2], T3[z]);
-      }
-  const float P0 = Q[0][0][0];
   const float cq = float(2.0 * a.alpha / sqrt(M_PI));
   const float cm = float(4.0 * a.alpha * a.alpha * a.alpha / (3.0 * sqrt(M_PI)));
-  if (a.o_q) {
-    const float s = P0 + S1[0] * v[0] + S1[1] * v[1] + S1[2] * v[2];
-    a.o_q[i] = pf * (s * iv - cq * vq);
-  }
-  if (a.o_mu) {
-    float u[3];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gslot = lane / P, ix = lane - gslot * P;
+  {   // atoms in groups of 4 wavefronts x APW
+    for (int b0 = 0; b0 < total; b0 += 4 * APW) {
+      const int item = b0 + wave * APW + gslot;
+      bool active = (gslot < APW) && (item < total);
+      // phi sums S_abc (1 <= a+b+c <= 3) and psi sums Q_abc (a+b+c <= 2)
+      float S[4][4][4];
+      float Q[3][3][3];
 #pragma unroll
-    for (int x = 0; x < 3; ++x) u[x] = P1[x] + S2[x][0] * v[0] + S2[x][1] * v[1] + S2[x][2] * v[2];
-    const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
-    st3(a.o_mu, i, make_float3(pf * (g.x * iv - cm * vm.x), pf * (g.y * iv - cm * vm.y),
-                               pf * (g.z * iv - cm * vm.z)));
-  }
-  if (a.o_pos) {
-    float u[3];
+      for (int x = 0; x < 4; ++x)
 #pragma unroll
-    for (int x = 0; x < 3; ++x)
-      u[x] = q * P1[x] + P2[x][0] * d[0] + P2[x][1] * d[1] + P2[x][2] * d[2] + vq * S1[x] +
-             S2[x][0] * w[0] + S2[x][1] * w[1] + S2[x][2] * w[2] + T3[x];
-    const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
-    st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+          for (int z = 0; z < 4; ++z) S[x][y][z] = 0.0f;
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+#pragma unroll
+          for (int z = 0; z < 3; ++z) Q[x][y][z] = 0.0f;
+      int atom = 0;
+      float q = 0.f, vq = 0.f;
+      float3 mu = make_float3(0.f, 0.f, 0.f), vr = mu, vm = mu;
+      float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (active) {
+        bool owned;
+        const float4* r = item_record(a, item, nown, s_off, s_bin, t0, T, owned);
+        active = owned;
+        h = r[0];
+        atom = __float_as_int(r[3].w);
+        // per-atom inputs fetched before the stencil work so their latency overlaps it
+        q = a.q ? a.q[atom] : 0.0f;
+        mu = ld3(a.mu, atom);
+        vq = a.v_q ? a.v_q[atom] : 0.0f;
+        vr = ld3(a.v_pos, atom);
+        vm = ld3(a.v_mu, atom);
+      }
+      if (active) {
+        const int pk = __float_as_int(h.w);
+        const int lx = (pk & 1023) - t0[0] + ix;
+        const int yb = ((pk >> 10) & 1023) - t0[1], zb = ((pk >> 20) & 1023) - t0[2];
+        float wy[4][P], wz[4][P], wx[4];
+        spline_weights<P, 3>(h.y, wy);
+        spline_weights<P, 3>(h.z, wz);
+        spline_weight_at<P, 3>(ix, h.x, wx);
+        const float* pphi = sm + (lx * E[1] + yb) * E[2] + zb;
+        const float* ppsi = pphi + EV;
+        float Ys[4][4], Yq[3][3];
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+#pragma unroll
+          for (int z = 0; z < 4; ++z) Ys[y][z] = 0.0f;
+#pragma unroll
+        for (int y = 0; y < 3; ++y)
+#pragma unroll
+          for (int z = 0; z < 3; ++z) Yq[y][z] = 0.0f;
+#pragma unroll
+        for (int iy = 0; iy < P; ++iy) {
+          float zs[4] = {0, 0, 0, 0}, zq[3] = {0, 0, 0};
+#pragma unroll
+          for (int iz = 0; iz < P; ++iz) {
+            const float v = pphi[iy * E[2] + iz], u = ppsi[iy * E[2] + iz];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) zs[k] = fmaf(v, wz[k][iz], zs[k]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) zq[k] = fmaf(u, wz[k][iz], zq[k]);
+          }
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int k = 0; k + b < 4; ++k) Ys[b][k] = fmaf(wy[b][iy], zs[k], Ys[b][k]);
+#pragma unroll
+          for (int b = 0; b < 3; ++b)
+#pragma unroll
+            for (int k = 0; k + b < 3; ++k) Yq[b][k] = fmaf(wy[b][iy], zq[k], Yq[b][k]);
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+          for (int b = 0; b + x < 4; ++b)
+#pragma unroll
+            for (int k = 0; k + b + x < 4; ++k) S[x][b][k] = wx[x] * Ys[b][k];
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+          for (int b = 0; b + x < 3; ++b)
+#pragma unroll
+            for (int k = 0; k + b + x < 3; ++k) Q[x][b][k] = wx[x] * Yq[b][k];
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int b = 0; b + x < 4; ++b)
+#pragma unroll
+          for (int k = 0; k + b + x < 4; ++k)
+            if (x + b + k >= 1) S[x][b][k] = group_sum<P>(S[x][b][k], ix);
+#pragma unroll
+      for (int x = 0; x < 3; ++x)
+#pragma unroll
+        for (int b = 0; b + x < 3; ++b)
+#pragma unroll
+          for (int k = 0; k + b + x < 3; ++k) Q[x][b][k] = group_sum<P>(Q[x][b][k], ix);
+      if (active && ix == 0) {
+        const int i = atom;
+        const float3 d3 = jmul(J, mu);
+        const float3 v3 = jmul(J, vr);
+        const float3 w3 = jmul(J, make_float3(vm.x + q * vr.x, vm.y + q * vr.y, vm.z + q * vr.z));
+        const float d[3] = {d3.x, d3.y, d3.z}, v[3] = {v3.x, v3.y, v3.z}, w[3] = {w3.x, w3.y, w3.z};
+        float S1[3], P1[3], S2[3][3], P2[3][3];
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+          const int ex[3] = {x == 0, x == 1, x == 2};
+          S1[x] = S[ex[0]][ex[1]][ex[2]];
+          P1[x] = Q[ex[0]][ex[1]][ex[2]];
+#pragma unroll
+          for (int y = 0; y < 3; ++y) {
+            const int e0 = ex[0] + (y == 0), e1 = ex[1] + (y == 1), e2 = ex[2] + (y == 2);
+            S2[x][y] = S[e0][e1][e2];
+            P2[x][y] = Q[e0][e1][e2];
+          }
+        }
+        float T3[3] = {0, 0, 0};   // S3(d, v, .)
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+          for (int y = 0; y < 3; ++y)
+#pragma unroll
+            for (int z = 0; z < 3; ++z) {
+              const int e0 = (x == 0) + (y == 0) + (z == 0);
+              const int e1 = (x == 1) + (y == 1) + (z == 1);
+              const int e2 = (x == 2) + (y == 2) + (z == 2);
+              T3[z] = fmaf(d[x] * v[y], S[e0][e1][e2], T3[z]);
+            }
+        const float P0 = Q[0][0][0];
+        if (a.o_q) {
+          const float sq = P0 + S1[0] * v[0] + S1[1] * v[1] + S1[2] * v[2];
+          a.o_q[i] = pf * (sq * iv - cq * vq);
+        }
+        if (a.o_mu) {
+          float u[3];
+#pragma unroll
+          for (int x = 0; x < 3; ++x) u[x] = P1[x] + S2[x][0] * v[0] + S2[x][1] * v[1] + S2[x][2] * v[2];
+          const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
+          st3(a.o_mu, i, make_float3(pf * (g.x * iv - cm * vm.x), pf * (g.y * iv - cm * vm.y),
+                                     pf * (g.z * iv - cm * vm.z)));
+        }
+        if (a.o_pos) {
+          float u[3];
+#pragma unroll
+          for (int x = 0; x < 3; ++x)
+            u[x] = q * P1[x] + P2[x][0] * d[0] + P2[x][1] * d[1] + P2[x][2] * d[2] + vq * S1[x] +
+                   S2[x][0] * w[0] + S2[x][1] * w[1] + S2[x][2] * w[2] + T3[x];
+          const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
+          st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+        }
+      }
+    }
   }
 }
 
 template <bool HVP>
-hipError_t gather_dispatch(int p, dim3 g, hipStream_t s, const GArgs& a) {
+hipError_t gather_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const GArgs& a) {
 #define PME_G(P)                                                                  \
   case P:                                                                         \
-    if (HVP) hipLaunchKernelGGL(k_gather_hvp<P>, g, dim3(256), 0, s, a);          \
-    else hipLaunchKernelGGL(k_gather<P>, g, dim3(256), 0, s, a);                   \
+    if (HVP) hipLaunchKernelGGL(k_gather_hvp<P>, g, dim3(256), sh, s, a);         \
+    else hipLaunchKernelGGL(k_gather<P>, g, dim3(256), sh, s, a);                  \
     break;
   switch (p) {
     PME_G(1) PME_G(2) PME_G(3) PME_G(4) PME_G(5) PME_G(6) PME_G(7)
@@ -341,35 +527,45 @@ hipError_t gather_dispatch(int p, dim3 g, hipStream_t s, const GArgs& a) {
   return hipGetLastError();
 }
 
-}  // namespace
-
-hipError_t launch_gather(const DevPlan& d, hipStream_t s, int n, const float* pos,
-                         const float* q, const float* mu, const double* box, double* energy,
-                         float* dE_dpos, float* dE_dq, float* dE_dmu, int n_spart) {
+GArgs base_args(const DevPlan& d, int set, int n, const float* pos, const float* q,
+                const float* mu, const double* box) {
   GArgs a{};
   a.n = n; a.pos = pos; a.q = q; a.mu = mu; a.box = box;
-  for (int k = 0; k < 3; ++k) a.N[k] = d.N[k];
+  for (int k = 0; k < 3; ++k) {
+    a.N[k] = d.N[k]; a.B[k] = d.B[k]; a.nb[k] = d.nb[k]; a.T[k] = d.T[k]; a.nt[k] = d.nt[k];
+  }
   a.phi = d.phi;
+  a.alpha = d.alpha; a.prefactor = d.prefactor;
+  a.cap = d.cap; a.count = d.count[set]; a.ovf_count = d.ovf_count[set];
+  a.rec = d.rec; a.ovf_rec = d.ovf_rec;
+  return a;
+}
+
+size_t region_bytes(const DevPlan& d, int fields) {
+  return sizeof(float) * size_t(fields) * (d.T[0] + d.p - 1) * (d.T[1] + d.p - 1) * (d.T[2] + d.p - 1);
+}
+
+}  // namespace
+
+hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
+                         const float* q, const float* mu, const double* box, double* energy,
+                         float* dE_dpos, float* dE_dq, float* dE_dmu, int n_spart) {
+  GArgs a = base_args(d, set, n, pos, q, mu, box);
   a.o_pos = dE_dpos; a.o_q = dE_dq; a.o_mu = dE_dmu;
   a.energy = energy; a.epart = d.epart; a.n_epart = fftx_blocks(d);
   a.spart = d.spart; a.n_spart = n_spart;
-  a.alpha = d.alpha; a.prefactor = d.prefactor;
-  return gather_dispatch<false>(d.p, dim3(bin_blocks(n)), s, a);
+  return gather_dispatch<false>(d.p, dim3(d.nt[0] * d.nt[1] * d.nt[2]), region_bytes(d, 1), s, a);
 }
 
-hipError_t launch_gather_hvp(const DevPlan& d, hipStream_t s, int n, const float* pos,
+hipError_t launch_gather_hvp(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                              const float* q, const float* mu, const double* box,
                              const float* v_pos, const float* v_q, const float* v_mu,
                              float* g_pos, float* g_q, float* g_mu) {
-  if (n == 0) return hipSuccess;
-  GArgs a{};
-  a.n = n; a.pos = pos; a.q = q; a.mu = mu; a.box = box;
-  for (int k = 0; k < 3; ++k) a.N[k] = d.N[k];
-  a.phi = d.phi; a.psi = d.rho;
+  GArgs a = base_args(d, set, n, pos, q, mu, box);
+  a.psi = d.rho;
   a.v_pos = v_pos; a.v_q = v_q; a.v_mu = v_mu;
   a.o_pos = g_pos; a.o_q = g_q; a.o_mu = g_mu;
-  a.alpha = d.alpha; a.prefactor = d.prefactor;
-  return gather_dispatch<true>(d.p, dim3(bin_blocks(n)), s, a);
+  return gather_dispatch<true>(d.p, dim3(d.nt[0] * d.nt[1] * d.nt[2]), region_bytes(d, 2), s, a);
 }
 
 }  // namespace pme

@@ -7,14 +7,37 @@
 namespace pme {
 
 constexpr int kMaxStages = 16;
-constexpr int kMaxBinRange = 2048;   // bins a spread tile may scan (LDS scan array)
-constexpr int kListCap = 128;        // atoms staged per spread round
+constexpr int kMaxBinRange = 512;    // bins a spread tile may scan (LDS count array)
+constexpr int kTileLds = 1536;       // max padded spread-tile points: T_x T_y (T_z + 1)
+constexpr int kRecWords = 16;        // words per atom record
+
+// n / d for 0 <= n < 2^17 and 1 <= d <= 4096 by a multiply-high:
+// m = ceil(2^32 / d) (d = 1 is passed through).
+struct FastDiv {
+  uint32_t d;
+  uint32_t m;
+};
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
+  return f.d == 1 ? n : __umulhi(n, f.m);
+}
+
+struct FFTStage {          // one Stockham stage: radix R after Ns = product of earlier radices
+  int R;
+  int Ns;
+  int NR;                  // N / R
+  int step;                // N / (Ns R): twiddle stride
+  FastDiv ns;
+  FastDiv nr;
+};
 
 struct AxisPlan {          // 1D mixed-radix FFT of length N
   int N;
   int nst;
-  int rad[kMaxStages];
+  FFTStage st[kMaxStages];
 };
+
+constexpr int kFFTThreads = 64;   // one wavefront per FFT workgroup
 
 struct DevPlan {
   int N[3];                // mesh dims
@@ -26,11 +49,14 @@ struct DevPlan {
   int B[3];
   int nb[3];
   int cap;                 // records per bin
-  int* count;              // [nbins]
-  int* ovf_count;          // [1]
+  // two counter sets used alternately by successive binnings; a binning clears the
+  // other set, so no kernel has to clear the set it reads
+  int* count[2];           // [nbins] atoms per bin
+  int* ovf_count[2];       // [1] atoms in the overflow list
+  unsigned* cmax[2];       // [1] max over atoms of sum |assignment coefficients| (float bits)
   float* rec;              // [nbins * cap * 16] records (16 words each)
   float* ovf_rec;          // [max_atoms * 16]
-  // spread tiles
+  // mesh tiles shared by the spread and the gathers (T[a] a multiple of B[a])
   int T[3];
   int nt[3];
   // FFT
@@ -38,7 +64,7 @@ struct DevPlan {
   float2* twiddle[3];      // e^{-2 pi i t / N_a}, t < N_a
   float* deconv[3];        // |sinc(f/N_a)|^{-2 gamma p}, signed f
   int rows_per_block;      // z-pass rows per block (even)
-  int ktile;               // half-spectrum z columns per y/x-pass block
+  int ktile;               // half-spectrum z columns per y/x-pass block (y and x pass)
   // meshes
   float* rho;              // [M] density (also the tangent density / its potential)
   float2* spec;            // [N_x N_y H]
@@ -59,21 +85,20 @@ inline int bin_blocks(int n) { return n > 0 ? (n + 255) / 256 : 1; }
 
 // Binning: stencil anchor, bin slot, per-atom record (forward: q and the x-space
 // dipole; tangent: the 10 monomial coefficients of the tangent density).
-hipError_t launch_bin(const DevPlan& d, hipStream_t s, int n, const float* pos, const float* q,
-                      const float* mu, const double* box, const float* v_pos, const float* v_q,
-                      const float* v_mu, bool tangent, bool self_sums);
-// Owner-computes spread of the binned records into d.rho.
-hipError_t launch_spread(const DevPlan& d, hipStream_t s, bool tangent);
+hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
+                      const float* q, const float* mu, const double* box, const float* v_pos,
+                      const float* v_q, const float* v_mu, bool tangent, bool self_sums);
+// Owner-computes spread of the binned records (counter set `set`) into d.rho.
+hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent);
 // rho -> spec -> (x g) -> out, the mesh operator K; energy partials when wanted.
-// Also resets the bin counters (the spread is their last reader).
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
                            bool energy);
-// Gradient gather (+ energy finalisation).
-hipError_t launch_gather(const DevPlan& d, hipStream_t s, int n, const float* pos,
+// Gradient gather (+ energy finalisation) over the atoms binned in counter set `set`.
+hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                          const float* q, const float* mu, const double* box, double* energy,
                          float* dE_dpos, float* dE_dq, float* dE_dmu, int n_spart);
 // Hessian-vector product gather from phi (d.phi) and psi (d.rho).
-hipError_t launch_gather_hvp(const DevPlan& d, hipStream_t s, int n, const float* pos,
+hipError_t launch_gather_hvp(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                              const float* q, const float* mu, const double* box,
                              const float* v_pos, const float* v_q, const float* v_mu,
                              float* g_pos, float* g_q, float* g_mu);

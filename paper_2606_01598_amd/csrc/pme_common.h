@@ -184,6 +184,19 @@ __device__ __forceinline__ int wrapn(int m, int N) {
   return (m < 0) ? m + N : m;
 }
 
+// Stream compaction within a wavefront: every lane calls it; lanes with pred get
+// consecutive slots of *counter (one LDS atomic per wavefront), others get -1.
+__device__ __forceinline__ int wave_compact(bool pred, int* counter) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0ull) return -1;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(m));
+  base = __shfl(base, leader, 64);
+  return pred ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
+
 // block-wide sum of a double (blockDim.x a multiple of 64, at most 1024)
 __device__ __forceinline__ double block_sum(double v, double* scratch) {
 #pragma unroll

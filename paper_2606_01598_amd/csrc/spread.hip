@@ -6,23 +6,27 @@
 //    anchor b and offset f (Sec. 2.3.2), and the monomial coefficients of what it
 //    assigns, c_abc, such that the value it adds at stencil point (i, j, k) is
 //        sum_abc c_abc W_x^(a)[i] W_y^(b)[j] W_z^(c)[k]
-//    (forward: c_000 = q, c_100..c_001 = N_a (mu . C^-1[:,a]); tangent: degree <= 2,
-//    see tangent_coefs).  It files a 16-word record into a fixed-capacity bin of
-//    B_x x B_y x B_z anchors (overflow goes to a list) and, for the forward,
-//    block partial sums of q^2 and |mu|^2 for the self terms (Eqs. self_q, self_mu).
-//  * k_spread: one workgroup owns one mesh tile.  It scans the bins whose anchors
-//    can reach the tile, stages the overlapping atoms' weights in LDS, accumulates
-//    their contributions with LDS float adds, and writes the tile back with plain
+//    (forward: c_000 = q, c_100..c_001 = N_a (mu . C^-1[:,a]); tangent: degree <= 2).
+//    It files a 16-word record into a fixed-capacity bin of B_x x B_y x B_z anchors
+//    (overflow goes to a list), reduces the largest coefficient sum (the fixed-point
+//    scale of the spread) and, for the forward, block partial sums of q^2 and |mu|^2
+//    for the self terms (Eqs. self_q, self_mu).  It also clears the other counter set.
+//  * k_spread: one workgroup owns one mesh tile.  It enumerates the occupied record
+//    slots of the bins whose anchors can reach the tile, stages the overlapping
+//    atoms' weights in LDS, accumulates their contributions into an LDS tile in
+//    64-bit fixed point with integer LDS adds (exact and order independent; LDS
+//    float atomics are slow on gfx950), and writes the tile back with plain
 //    coalesced stores.  Halo contributions are computed by every tile they touch
 //    instead of being flushed with global atomics, so the mesh needs no clearing
 //    and no global read-modify-write.
+//
+// Record layout (16 words): f_x f_y f_z anchor | c0 c1 c2 c3 | forward: mu_x mu_y mu_z -,
+// tangent: c4 c5 c6 c7 | tangent: c8 c9 - atom, forward: - - - atom.
 #include "kernels.h"
 #include "pme_common.h"
 
 namespace pme {
 namespace {
-
-constexpr int kRecW = 16;   // record words: f[3], packed base, coefs[<=10], pad
 
 struct BinArgs {
   int n;
@@ -37,8 +41,13 @@ struct BinArgs {
   int B[3];
   int nb[3];
   int cap;
-  int* count;
+  int* count;          // this binning's counters
   int* ovf_count;
+  unsigned* cmax;
+  int* count_other;    // the other set, cleared here
+  int* ovf_other;
+  unsigned* cmax_other;
+  int nbins;
   float* rec;
   float* ovf_rec;
   double* spart;
@@ -59,6 +68,15 @@ __device__ __forceinline__ float3 jmul(const float (&J)[3][3], float3 v) {
 template <int P, bool TANGENT>
 __global__ void __launch_bounds__(256) k_bin(BinArgs a) {
   __shared__ double red[8];
+  __shared__ unsigned s_cmax;
+  if (threadIdx.x == 0) s_cmax = 0u;
+  // clear the other counter set for the next binning
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < a.nbins; e += gridDim.x * 256) a.count_other[e] = 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    *a.ovf_other = 0;
+    *a.cmax_other = 0u;
+  }
+  __syncthreads();
   const int i = blockIdx.x * 256 + threadIdx.x;
   const Cell c = cell_from_box(a.box);
   double sq = 0.0, smu = 0.0;
@@ -77,10 +95,8 @@ __global__ void __launch_bounds__(256) k_bin(BinArgs a) {
       jacobian(c, a.N, J);
       const float3 d = jmul(J, mu);
       float co[10];
-      int nc;
       if (!TANGENT) {
         co[0] = q; co[1] = d.x; co[2] = d.y; co[3] = d.z;
-        nc = 4;
       } else {
         // rho_dot = v_q W + w.grad_x W + d^T (grad_x grad_x W) v,
         // w = J (v_mu + q v_r), v = J v_r, d = J mu
@@ -95,27 +111,37 @@ __global__ void __launch_bounds__(256) k_bin(BinArgs a) {
         co[7] = d.x * v.y + d.y * v.x;                               // 110
         co[8] = d.x * v.z + d.z * v.x;                               // 101
         co[9] = d.y * v.z + d.z * v.y;                               // 011
-        nc = 10;
       }
+      constexpr int nc = TANGENT ? 10 : 4;
+      float amax = 0.0f;
+#pragma unroll
+      for (int k = 0; k < nc; ++k) amax += fabsf(co[k]);
+      if (isfinite(amax)) atomicMax(&s_cmax, __float_as_uint(amax));
+      else atomicOr(a.status, 1);
       const int bin = ((base[0] / a.B[0]) * a.nb[1] + base[1] / a.B[1]) * a.nb[2] + base[2] / a.B[2];
       const int slot = atomicAdd(&a.count[bin], 1);
       float* dst;
       if (slot < a.cap) {
-        dst = a.rec + (size_t(bin) * a.cap + slot) * kRecW;
+        dst = a.rec + (size_t(bin) * a.cap + slot) * kRecWords;
       } else {
         const int o = atomicAdd(a.ovf_count, 1);
-        dst = a.ovf_rec + size_t(o) * kRecW;
+        dst = a.ovf_rec + size_t(o) * kRecWords;
       }
       float4* d4 = reinterpret_cast<float4*>(dst);
       d4[0] = make_float4(f[0], f[1], f[2],
                           __int_as_float(base[0] | (base[1] << 10) | (base[2] << 20)));
       d4[1] = make_float4(co[0], co[1], co[2], co[3]);
-      if (nc == 10) {
+      if (TANGENT) {
         d4[2] = make_float4(co[4], co[5], co[6], co[7]);
-        d4[3] = make_float4(co[8], co[9], 0.f, 0.f);
+        d4[3] = make_float4(co[8], co[9], 0.f, __int_as_float(i));
+      } else {
+        d4[2] = make_float4(mu.x, mu.y, mu.z, 0.f);
+        d4[3] = make_float4(0.f, 0.f, 0.f, __int_as_float(i));
       }
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && s_cmax) atomicMax(a.cmax, s_cmax);
   if (!TANGENT && a.spart) {
     const double s1 = block_sum(sq, red);
     const double s2 = block_sum(smu, red);
@@ -133,6 +159,7 @@ struct SpreadArgs {
   int cap;
   const int* count;
   const int* ovf_count;
+  const unsigned* cmax;
   const float* rec;
   const float* ovf_rec;
   int T[3];
@@ -140,204 +167,252 @@ struct SpreadArgs {
   float* rho;
 };
 
-constexpr int kTileMax = 1024;
+// m mod N for m in [-N, 2N)
+__device__ __forceinline__ int wrap1(int m, int N) {
+  return (m < 0) ? m + N : ((m >= N) ? m - N : m);
+}
 
-// Bitmask of the stencil points j whose wrapped mesh index falls in [t0, t0+T),
-// and the tile-local coordinate of each.
+// Does the stencil of an atom anchored at b reach the tile [t0, t0+T) along one axis?
 template <int P>
-__device__ __forceinline__ int axis_overlap(int b, int t0, int T, int N, int (&loc)[P]) {
+__device__ __forceinline__ bool axis_hits(int b, int t0, int T, int N) {
   constexpr int lo = (P - 1) / 2;
-  int mask = 0;
+  if (N < P) return true;                       // the stencil covers every residue
+  const int m0 = b - lo, m1 = m0 + P - 1;
+  const int e = t0 + T;
+  return (m1 >= t0 && m0 < e) || (m1 - N >= t0 && m0 - N < e) || (m1 + N >= t0 && m0 + N < e);
+}
+
+// Tile-local coordinate of each stencil point (-1 outside the tile), packed as bytes.
+template <int P>
+__device__ __forceinline__ void axis_locs(int b, int t0, int T, int N, int& w0, int& w1) {
+  constexpr int lo = (P - 1) / 2;
+  uint32_t p0 = 0, p1 = 0;
 #pragma unroll
   for (int j = 0; j < P; ++j) {
-    const int l = wrapn(b - lo + j, N) - t0;
-    loc[j] = l;
-    if (l >= 0 && l < T) mask |= 1 << j;
+    const int m = (N >= P) ? wrap1(b - lo + j, N) : wrapn(b - lo + j, N);
+    const int l = m - t0;
+    const uint32_t byte = (l >= 0 && l < T) ? uint32_t(l) : 0xffu;
+    if (j < 4) p0 |= byte << (8 * j); else p1 |= byte << (8 * (j - 4));
   }
-  return mask;
+  w0 = int(p0);
+  w1 = int(p1);
+}
+
+__device__ __forceinline__ int loc_of(int w0, int w1, int j) {
+  const int w = (j < 4) ? w0 : w1;
+  return int(int8_t((w >> (8 * (j & 3))) & 0xff));
 }
 
 template <int P, int DEG>
 __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
   constexpr int NC = (DEG == 1) ? 4 : 10;
-  constexpr int D = DEG;                    // highest weight derivative needed
+  constexpr int D = DEG;                      // highest weight derivative needed
+  constexpr int CH = 128;                     // atoms staged per round
+  constexpr int NW = 3 * (D + 1) * P;         // weights w[axis][d][j]
+  constexpr int ES = (NW + NC + 6) | 1;       // odd entry stride (LDS banks)
   constexpr int lo = (P - 1) / 2;
-  // staged atom: weights w[axis][d][j], coefs, base, masks
-  constexpr int kEnt = 3 * (D + 1) * P + NC + 2;
-  __shared__ float s_tile[kTileMax];
+  __shared__ unsigned long long s_tile[kTileLds];
   __shared__ int s_off[kMaxBinRange + 2];
   __shared__ int s_bin[kMaxBinRange + 1];
-  __shared__ float s_list[kListCap * kEnt];
-  __shared__ int s_nlist;
-  __shared__ int s_part[256];
+  __shared__ float s_ent[CH * ES];
+  __shared__ int s_n;
 
   const int tid = threadIdx.x;
-  int tcoord[3];
+  int t0[3], T[3];
   {
     int t = blockIdx.x;
-    tcoord[2] = t % a.nt[2]; t /= a.nt[2];
-    tcoord[1] = t % a.nt[1];
-    tcoord[0] = t / a.nt[1];
-  }
-  int t0[3], T[3];
+    const int tz = t % a.nt[2];
+    t /= a.nt[2];
+    const int ty = t % a.nt[1];
+    const int tx = t / a.nt[1];
+    const int tc[3] = {tx, ty, tz};
 #pragma unroll
-  for (int ax = 0; ax < 3; ++ax) {
-    t0[ax] = tcoord[ax] * a.T[ax];
-    T[ax] = min(a.T[ax], a.N[ax] - t0[ax]);
+    for (int ax = 0; ax < 3; ++ax) {
+      t0[ax] = tc[ax] * a.T[ax];
+      T[ax] = min(a.T[ax], a.N[ax] - t0[ax]);
+    }
   }
-  const int tvol = T[0] * T[1] * T[2];
-  for (int e = tid; e < tvol; e += 256) s_tile[e] = 0.0f;
-
-  // bins whose anchors b can reach the tile: b in [t0 + lo - P + 1, t0 + T - 1 + lo]
+  // bins whose anchors can reach the tile: b in [t0 + lo - P + 1, t0 + T - 1 + lo]
   int kmin[3], nk[3];
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
     const int bmin = t0[ax] + lo - P + 1, bmax = t0[ax] + T[ax] - 1 + lo;
-    const int k0 = (bmin >= 0) ? bmin / a.B[ax] : -((-bmin + a.B[ax] - 1) / a.B[ax]);
-    const int k1 = (bmax >= 0) ? bmax / a.B[ax] : -((-bmax + a.B[ax] - 1) / a.B[ax]);
+    const int B = a.B[ax];
+    const int k0 = (bmin >= 0) ? bmin / B : -((-bmin + B - 1) / B);
+    const int k1 = (bmax >= 0) ? bmax / B : -((-bmax + B - 1) / B);
     nk[ax] = k1 - k0 + 1;
     kmin[ax] = k0;
     if (nk[ax] >= a.nb[ax]) { nk[ax] = a.nb[ax]; kmin[ax] = 0; }
   }
-  const int nbr = nk[0] * nk[1] * nk[2];     // <= kMaxBinRange (host guarantees)
+  const int nbr = nk[0] * nk[1] * nk[2];      // <= kMaxBinRange (host guarantees)
   for (int e = tid; e < nbr; e += 256) {
     const int kz = e % nk[2], ky = (e / nk[2]) % nk[1], kx = e / (nk[1] * nk[2]);
-    int bx = (kmin[0] + kx) % a.nb[0]; bx += (bx < 0) ? a.nb[0] : 0;
-    int by = (kmin[1] + ky) % a.nb[1]; by += (by < 0) ? a.nb[1] : 0;
-    int bz = (kmin[2] + kz) % a.nb[2]; bz += (bz < 0) ? a.nb[2] : 0;
+    const int bx = wrapn(kmin[0] + kx, a.nb[0]);
+    const int by = wrapn(kmin[1] + ky, a.nb[1]);
+    const int bz = wrapn(kmin[2] + kz, a.nb[2]);
     const int bin = (bx * a.nb[1] + by) * a.nb[2] + bz;
     s_bin[e] = bin;
     s_off[e] = min(a.count[bin], a.cap);
   }
   if (tid == 0) {
-    s_bin[nbr] = -1;                           // pseudo-bin: the overflow list
+    s_bin[nbr] = -1;                          // pseudo-bin: the overflow list
     s_off[nbr] = *a.ovf_count;
-    s_nlist = 0;
   }
-  __syncthreads();
-  // exclusive scan of s_off[0..nbr]: each thread scans a contiguous segment
+  // each contribution is bounded by 8 sum_k |c_k| <= 8 cmax: scale it to <= 2^40
+  float scale = 1.0f;
   {
+    const float cm = __uint_as_float(*a.cmax);
+    if (cm > 0.0f && isfinite(cm)) scale = ldexpf(1.0f, 40 - (ilogbf(8.0f * cm) + 1));
+  }
+  const int TZP = T[2] + 1;                   // padded z stride of the LDS tile
+  const int tpad = T[0] * T[1] * TZP;
+  for (int e = tid; e < tpad; e += 256) s_tile[e] = 0ull;
+  __syncthreads();
+  // exclusive scan of the occupied slot counts (wavefront 0)
+  if (tid < 64) {
     const int len = nbr + 1;
-    const int seg = (len + 255) / 256;
+    const int seg = (len + 63) / 64;
     const int s0 = min(tid * seg, len), s1 = min(s0 + seg, len);
     int acc = 0;
     for (int e = s0; e < s1; ++e) acc += s_off[e];
-    s_part[tid] = acc;
-    __syncthreads();
-    if (tid == 0) {
-      int run = 0;
-      for (int w = 0; w < 256; ++w) { const int v = s_part[w]; s_part[w] = run; run += v; }
+    int incl = acc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (tid >= o) incl += v;
     }
-    __syncthreads();
-    int run = s_part[tid];
+    int run = incl - acc;
     for (int e = s0; e < s1; ++e) { const int v = s_off[e]; s_off[e] = run; run += v; }
-    if (tid == 255) s_off[len] = run;
-    __syncthreads();
+    if (tid == 63) s_off[len] = incl;
   }
+  __syncthreads();
   const int total = s_off[nbr + 1];
 
-  for (int r0 = 0; r0 < total; r0 += kListCap) {
-    // stage overlapping atoms of this round
+  for (int r0 = 0; r0 < total; r0 += CH) {
+    if (tid == 0) s_n = 0;
+    __syncthreads();
+    // 1. load the round's records, keep those whose stencil reaches the tile, stage
+    //    their weights, tile-local coordinates and coefficients
     const int item = r0 + tid;
-    if (tid < kListCap && item < total) {
-      int lo_i = 0, hi_i = nbr;                 // largest bin index with s_off <= item
+    bool hit = false;
+    float4 h = make_float4(0.f, 0.f, 0.f, 0.f), c0v = h, c1v = h, c2v = h;
+    if (tid < CH && item < total) {
+      int lo_i = 0, hi_i = nbr;                 // largest bin with s_off <= item
       while (lo_i < hi_i) {
         const int mid = (lo_i + hi_i + 1) >> 1;
         if (s_off[mid] <= item) lo_i = mid; else hi_i = mid - 1;
       }
       const int bin = s_bin[lo_i];
       const int slot = item - s_off[lo_i];
-      const float* src = (bin >= 0) ? a.rec + (size_t(bin) * a.cap + slot) * kRecW
-                                    : a.ovf_rec + size_t(slot) * kRecW;
-      const float4 h = reinterpret_cast<const float4*>(src)[0];
+      const float4* r = reinterpret_cast<const float4*>(
+          (bin >= 0) ? a.rec + (size_t(bin) * a.cap + slot) * kRecWords
+                     : a.ovf_rec + size_t(slot) * kRecWords);
+      h = r[0];
+      c0v = r[1];
+      if (NC == 10) {
+        c1v = r[2];
+        c2v = r[3];
+      }
+      const int pk = __float_as_int(h.w);
+      hit = axis_hits<P>(pk & 1023, t0[0], T[0], a.N[0]) &&
+            axis_hits<P>((pk >> 10) & 1023, t0[1], T[1], a.N[1]) &&
+            axis_hits<P>((pk >> 20) & 1023, t0[2], T[2], a.N[2]);
+    }
+    const int k = wave_compact(hit, &s_n);
+    if (hit) {
       const int pk = __float_as_int(h.w);
       const int b[3] = {pk & 1023, (pk >> 10) & 1023, (pk >> 20) & 1023};
-      int lx[P], ly[P], lz[P];
-      const int mx = axis_overlap<P>(b[0], t0[0], T[0], a.N[0], lx);
-      const int my = axis_overlap<P>(b[1], t0[1], T[1], a.N[1], ly);
-      const int mz = axis_overlap<P>(b[2], t0[2], T[2], a.N[2], lz);
-      if (mx && my && mz) {
-        const int e = atomicAdd(&s_nlist, 1);
-        float* ent = s_list + e * kEnt;
-        const float fr[3] = {h.x, h.y, h.z};
+      const float fr[3] = {h.x, h.y, h.z};
+      float* ent = s_ent + k * ES;
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) {
-          float w[D + 1][P];
-          spline_weights<P, D>(fr[ax], w);
+      for (int ax = 0; ax < 3; ++ax) {
+        float w[D + 1][P];
+        spline_weights<P, D>(fr[ax], w);
 #pragma unroll
-          for (int d = 0; d <= D; ++d)
+        for (int d = 0; d <= D; ++d)
 #pragma unroll
-            for (int j = 0; j < P; ++j) ent[(ax * (D + 1) + d) * P + j] = w[d][j];
-        }
-        const float4* s4 = reinterpret_cast<const float4*>(src) + 1;
-        float co[12];
-        const float4 c0 = s4[0];
-        co[0] = c0.x; co[1] = c0.y; co[2] = c0.z; co[3] = c0.w;
-        if (NC == 10) {
-          const float4 c1 = s4[1], c2 = s4[2];
-          co[4] = c1.x; co[5] = c1.y; co[6] = c1.z; co[7] = c1.w;
-          co[8] = c2.x; co[9] = c2.y;
-        }
-#pragma unroll
-        for (int k = 0; k < NC; ++k) ent[3 * (D + 1) * P + k] = co[k];
-        ent[3 * (D + 1) * P + NC] = __int_as_float(pk);
-        ent[3 * (D + 1) * P + NC + 1] = __int_as_float(mx | (my << 8) | (mz << 16));
+          for (int j = 0; j < P; ++j) ent[(ax * (D + 1) + d) * P + j] = w[d][j];
+        int l0, l1;
+        axis_locs<P>(b[ax], t0[ax], T[ax], a.N[ax], l0, l1);
+        ent[NW + NC + 2 * ax] = __int_as_float(l0);
+        ent[NW + NC + 2 * ax + 1] = __int_as_float(l1);
+      }
+      ent[NW + 0] = c0v.x; ent[NW + 1] = c0v.y; ent[NW + 2] = c0v.z; ent[NW + 3] = c0v.w;
+      if (NC == 10) {
+        ent[NW + 4] = c1v.x; ent[NW + 5] = c1v.y; ent[NW + 6] = c1v.z; ent[NW + 7] = c1v.w;
+        ent[NW + 8] = c2v.x; ent[NW + 9] = c2v.y;
       }
     }
     __syncthreads();
-    // accumulate: one task per (atom, x-point, y-point) column of the stencil
-    const int nl = s_nlist;
-    for (int t = tid; t < nl * P * P; t += 256) {
-      const int e = t / (P * P), cc = t - e * (P * P);
-      const int ix = cc / P, iy = cc - ix * P;
-      const float* ent = s_list + e * kEnt;
-      const int masks = __float_as_int(ent[3 * (D + 1) * P + NC + 1]);
-      if (!((masks >> ix) & 1) || !((masks >> (8 + iy)) & 1)) continue;
-      const int pk = __float_as_int(ent[3 * (D + 1) * P + NC]);
-      const int mz = (masks >> 16) & 255;
-      const float* wx = ent;                       // wx[d*P + j]
-      const float* wy = ent + (D + 1) * P;
-      const float* wz = ent + 2 * (D + 1) * P;
-      const float* co = ent + 3 * (D + 1) * P;
-      float c0, c1, c2 = 0.0f;
+    // 2. accumulate: one task per (atom, x-plane of its stencil)
+    const int ntask = s_n * P;
+    for (int t = tid; t < ntask; t += 256) {
+      const int e = t / P, ix = t - e * P;
+      const float* ent = s_ent + e * ES;
+      const int lx = loc_of(__float_as_int(ent[NW + NC]), __float_as_int(ent[NW + NC + 1]), ix);
+      if (lx < 0) continue;
+      const int ly0 = __float_as_int(ent[NW + NC + 2]), ly1 = __float_as_int(ent[NW + NC + 3]);
+      const int lz0 = __float_as_int(ent[NW + NC + 4]), lz1 = __float_as_int(ent[NW + NC + 5]);
+      float wz[D + 1][P];
+#pragma unroll
+      for (int d = 0; d <= D; ++d)
+#pragma unroll
+        for (int j = 0; j < P; ++j) wz[d][j] = ent[(2 * (D + 1) + d) * P + j];
+      float x[D + 1];
+#pragma unroll
+      for (int d = 0; d <= D; ++d) x[d] = ent[d * P + ix];
+      float co[NC];
+#pragma unroll
+      for (int kk = 0; kk < NC; ++kk) co[kk] = ent[NW + kk];
+      // this x-plane's coefficients of the (y, z) derivative monomials
+      float ax0, az1, az2 = 0.f, ay1, ay2 = 0.f, ayz = 0.f;
       if (DEG == 1) {
-        const float x0 = wx[ix], x1 = wx[P + ix], y0 = wy[iy], y1 = wy[P + iy];
-        c0 = co[0] * x0 * y0 + co[1] * x1 * y0 + co[2] * x0 * y1;
-        c1 = co[3] * x0 * y0;
+        ax0 = co[0] * x[0] + co[1] * x[1];   // W_y W_z
+        ay1 = co[2] * x[0];                  // W_y' W_z
+        az1 = co[3] * x[0];                  // W_y W_z'
       } else {
-        const float x0 = wx[ix], x1 = wx[P + ix], x2 = wx[2 * P + ix];
-        const float y0 = wy[iy], y1 = wy[P + iy], y2 = wy[2 * P + iy];
-        c0 = co[0] * x0 * y0 + co[1] * x1 * y0 + co[2] * x0 * y1 + co[4] * x2 * y0 +
-             co[5] * x0 * y2 + co[7] * x1 * y1;
-        c1 = co[3] * x0 * y0 + co[8] * x1 * y0 + co[9] * x0 * y1;
-        c2 = co[6] * x0 * y0;
+        ax0 = co[0] * x[0] + co[1] * x[1] + co[4] * x[2];
+        ay1 = co[2] * x[0] + co[7] * x[1];
+        az1 = co[3] * x[0] + co[8] * x[1];
+        ay2 = co[5] * x[0];
+        az2 = co[6] * x[0];
+        ayz = co[9] * x[0];
       }
-      int lxy;
-      {
-        const int bx = pk & 1023, by = (pk >> 10) & 1023, bz = (pk >> 20) & 1023;
-        int m = wrapn(bx - lo + ix, a.N[0]) - t0[0];
-        int n = wrapn(by - lo + iy, a.N[1]) - t0[1];
-        lxy = (m * T[1] + n) * T[2];
-        int zb = bz - lo;
+      const int rowx = lx * T[1];
+#pragma unroll
+      for (int iy = 0; iy < P; ++iy) {
+        const int ly = loc_of(ly0, ly1, iy);
+        if (ly < 0) continue;
+        const float y0 = ent[(D + 1) * P + iy], y1 = ent[(D + 1) * P + P + iy];
+        float c0 = ax0 * y0 + ay1 * y1, c1 = az1 * y0, c2 = 0.f;
+        if (DEG == 2) {
+          const float y2 = ent[(D + 1) * P + 2 * P + iy];
+          c0 += ay2 * y2;
+          c1 += ayz * y1;
+          c2 = az2 * y0;
+        }
+        unsigned long long* row = s_tile + (rowx + ly) * TZP;
 #pragma unroll
         for (int iz = 0; iz < P; ++iz) {
-          if (!((mz >> iz) & 1)) continue;
-          const int lz = wrapn(zb + iz, a.N[2]) - t0[2];
-          float v = c0 * wz[iz] + c1 * wz[P + iz];
-          if (DEG == 2) v += c2 * wz[2 * P + iz];
-          atomicAdd(&s_tile[lxy + lz], v);
+          const int lz = loc_of(lz0, lz1, iz);
+          if (lz < 0) continue;
+          float v = c0 * wz[0][iz] + c1 * wz[1][iz];
+          if (DEG == 2) v += c2 * wz[2][iz];
+          atomicAdd(row + lz, (unsigned long long)__float2ll_rn(v * scale));
         }
       }
     }
-    __syncthreads();
-    if (tid == 0) s_nlist = 0;
     __syncthreads();
   }
 
-  // write the tile (z rows contiguous)
+  // 3. write the tile back (plain stores; every point is owned by this tile)
+  const float inv_scale = 1.0f / scale;
+  const int tvol = T[0] * T[1] * T[2];
   for (int e = tid; e < tvol; e += 256) {
-    const int lz = e % T[2], ly = (e / T[2]) % T[1], lx = e / (T[1] * T[2]);
-    a.rho[(size_t(t0[0] + lx) * a.N[1] + (t0[1] + ly)) * a.N[2] + t0[2] + lz] = s_tile[e];
+    const int lz = e % T[2], r = e / T[2];
+    const int ly = r % T[1], lx = r / T[1];
+    a.rho[(size_t(t0[0] + lx) * a.N[1] + (t0[1] + ly)) * a.N[2] + t0[2] + lz] =
+        __ll2float_rn((long long)s_tile[r * TZP + lz]) * inv_scale;
   }
 }
 
@@ -373,14 +448,18 @@ hipError_t spread_dispatch(int p, dim3 g, hipStream_t s, const SpreadArgs& a) {
 
 }  // namespace
 
-hipError_t launch_bin(const DevPlan& d, hipStream_t s, int n, const float* pos, const float* q,
-                      const float* mu, const double* box, const float* v_pos, const float* v_q,
-                      const float* v_mu, bool tangent, bool self_sums) {
+hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
+                      const float* q, const float* mu, const double* box, const float* v_pos,
+                      const float* v_q, const float* v_mu, bool tangent, bool self_sums) {
   BinArgs a;
   a.n = n; a.pos = pos; a.q = q; a.mu = mu; a.box = box;
   a.v_pos = v_pos; a.v_q = v_q; a.v_mu = v_mu;
   for (int k = 0; k < 3; ++k) { a.N[k] = d.N[k]; a.B[k] = d.B[k]; a.nb[k] = d.nb[k]; }
-  a.cap = d.cap; a.count = d.count; a.ovf_count = d.ovf_count;
+  a.cap = d.cap;
+  a.count = d.count[set]; a.ovf_count = d.ovf_count[set]; a.cmax = d.cmax[set];
+  a.count_other = d.count[1 - set]; a.ovf_other = d.ovf_count[1 - set];
+  a.cmax_other = d.cmax[1 - set];
+  a.nbins = d.nb[0] * d.nb[1] * d.nb[2];
   a.rec = d.rec; a.ovf_rec = d.ovf_rec;
   a.spart = self_sums ? d.spart : nullptr;
   a.status = d.status;
@@ -388,12 +467,13 @@ hipError_t launch_bin(const DevPlan& d, hipStream_t s, int n, const float* pos, 
   return tangent ? bin_dispatch<true>(d.p, g, s, a) : bin_dispatch<false>(d.p, g, s, a);
 }
 
-hipError_t launch_spread(const DevPlan& d, hipStream_t s, bool tangent) {
+hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent) {
   SpreadArgs a;
   for (int k = 0; k < 3; ++k) {
     a.N[k] = d.N[k]; a.B[k] = d.B[k]; a.nb[k] = d.nb[k]; a.T[k] = d.T[k]; a.nt[k] = d.nt[k];
   }
-  a.cap = d.cap; a.count = d.count; a.ovf_count = d.ovf_count;
+  a.cap = d.cap;
+  a.count = d.count[set]; a.ovf_count = d.ovf_count[set]; a.cmax = d.cmax[set];
   a.rec = d.rec; a.ovf_rec = d.ovf_rec; a.rho = d.rho;
   const dim3 g(d.nt[0] * d.nt[1] * d.nt[2]);
   return tangent ? spread_dispatch<2>(d.p, g, s, a) : spread_dispatch<1>(d.p, g, s, a);
