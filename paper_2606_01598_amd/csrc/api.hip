@@ -213,8 +213,15 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   for (int a = 0; a < 3; ++a)
     if (!radix_plan(d.N[a], d.ax[a])) { free_plan(pl); return PME_EMESH; }
   {
-    // one-wave FFT workgroups: about 256 complex points each
-    int pairs = (256 + d.N[2] - 1) / d.N[2];
+    // slab mode when a y-z plane of the half spectrum (two LDS buffers) fits
+    const long npairs = (d.N[1] + 1) / 2;
+    long buf = npairs * d.N[2];
+    if (long(d.H) * (d.N[1] + 1) > buf) buf = long(d.H) * (d.N[1] + 1);
+    const long slab_bytes = long(sizeof(float2)) * (2 * buf + d.N[1] + d.N[2]);
+    d.slab = slab_bytes <= pme::kSlabLdsMax;
+    d.slab_lds = size_t(slab_bytes);
+    // pencil passes: about 1024 complex points per workgroup
+    int pairs = (1024 + d.N[2] - 1) / d.N[2];
     if (pairs > 32) pairs = 32;
     d.rows_per_block = 2 * pairs;
     const int nmax = d.N[0] > d.N[1] ? d.N[0] : d.N[1];
@@ -274,6 +281,7 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   }
   ok(hipMemset(d.status, 0, sizeof(int)));
   ok(hipMemset(d.phi, 0, sizeof(float) * M));
+  if (d.slab) ok(pme::enable_slab_lds(d.slab_lds));
   ok(hipDeviceSynchronize());
   if (e != hipSuccess) {
     free_plan(pl);

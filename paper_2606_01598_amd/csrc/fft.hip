@@ -4,12 +4,14 @@
 // k-space form of the reciprocal energy (Eq. energy_recip):
 //     E_recip = (1/2V) sum_n rho phi = (1/2V) sum_k g(k) |rho~(k)|^2.
 //
-// Five LDS-staged passes over the half spectrum spec[x][y][kz], kz < N_z/2+1:
-//   z  R2C   rows of N_z reals, two rows packed into one complex pencil
-//   y  fwd   pencils along y, a tile of kz columns per workgroup
-//   x  fused forward FFT along x, x g(k), energy partial, inverse FFT along x
-//   y  inv
-//   z  C2R   two Hermitian rows unpacked into one complex pencil
+// LDS-staged passes over the half spectrum spec[x][y][kz], kz < N_z/2+1.  When a
+// y-z plane of the half spectrum fits in LDS (slab mode) there are three:
+//   slab fwd  one x-plane per workgroup: z R2C (two real rows packed into one
+//             complex pencil) then y FFT, in LDS
+//   x         fused forward FFT along x, x g(k), energy partial, inverse FFT along x
+//   slab inv  y inverse FFT then z C2R (two Hermitian rows unpacked into one
+//             complex pencil), in LDS
+// Otherwise five pencil passes: z R2C, y fwd, x fused, y inv, z C2R.
 // Each 1D transform is a mixed-radix (2, 3, 4, 5) Stockham autosort over LDS
 // ping-pong buffers; twiddles come from a per-axis table staged into LDS.
 //
@@ -114,20 +116,22 @@ __device__ float2* lds_fft(float2* x, float2* y, int npen, int ps, const AxisPla
 }
 
 // Twiddle table held in registers between its load and its LDS store, so that its
-// loads are in flight together with the data loads (N <= 16 * kFFTThreads).
+// loads are in flight together with the data loads (N <= 1024).
+template <int NT>
 struct Twiddles {
-  float2 v[16];
+  static constexpr int U = (1024 + NT - 1) / NT;
+  float2 v[U];
   __device__ __forceinline__ void load(const float2* src, int N) {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int t = threadIdx.x + u * kFFTThreads;
+    for (int u = 0; u < U; ++u) {
+      const int t = threadIdx.x + u * NT;
       if (t < N) v[u] = src[t];
     }
   }
   __device__ __forceinline__ void store(float2* dst, int N) const {
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int t = threadIdx.x + u * kFFTThreads;
+    for (int u = 0; u < U; ++u) {
+      const int t = threadIdx.x + u * NT;
       if (t < N) dst[t] = v[u];
     }
   }
@@ -171,7 +175,7 @@ __global__ void __launch_bounds__(kFFTThreads) k_fftz_r2c(ZArgs a) {
   float2* X = tw + N;
   float2* Y = X + (a.rp / 2) * N;
   const int r0 = blockIdx.x * a.rp;
-  Twiddles twr;
+  Twiddles<kFFTThreads> twr;
   twr.load(a.tw, N);
   const int np = a.rp / 2;
   staged_copy<16, float2>(
@@ -209,7 +213,7 @@ __global__ void __launch_bounds__(kFFTThreads) k_fftz_c2r(ZArgs a) {
   float2* X = S + a.rp * H;
   float2* Y = X + (a.rp / 2) * N;
   const int r0 = blockIdx.x * a.rp;
-  Twiddles twr;
+  Twiddles<kFFTThreads> twr;
   twr.load(a.tw, N);
   const int nvalid = min(a.rp, a.rows - r0) * H;
   staged_copy<16, float2>(
@@ -245,6 +249,123 @@ __global__ void __launch_bounds__(kFFTThreads) k_fftz_c2r(ZArgs a) {
   }
 }
 
+struct SlabArgs {
+  AxisPlan ay, az;
+  const float2* twy;
+  const float2* twz;
+  int H;
+  FastDiv nzd, hd;   // division by N_z and by H
+  const float* src;  // real mesh (forward input)
+  float2* spec;
+  float* dst;        // real mesh (inverse output)
+};
+
+__device__ __forceinline__ void slab_layout(const SlabArgs& a, float2* sm, float2*& twz,
+                                            float2*& twy, float2*& A, float2*& B) {
+  const int Ny = a.ay.N, Nz = a.az.N;
+  const int npairs = (Ny + 1) / 2;
+  const int buf = max(npairs * Nz, a.H * (Ny + 1));
+  twz = sm;
+  twy = twz + Nz;
+  A = twy + Ny;
+  B = A + buf;
+}
+
+// forward slab: rho[x] -> z R2C -> y FFT -> spec[x]
+__global__ void __launch_bounds__(kSlabThreads) k_slab_fwd(SlabArgs a) {
+  extern __shared__ float2 sm[];
+  const int Ny = a.ay.N, Nz = a.az.N, H = a.H;
+  const int npairs = (Ny + 1) / 2;
+  float2 *twz, *twy, *A, *B;
+  slab_layout(a, sm, twz, twy, A, B);
+  const int x = blockIdx.x;
+  Twiddles<kSlabThreads> tz, ty;
+  tz.load(a.twz, Nz);
+  ty.load(a.twy, Ny);
+  const float* src = a.src + size_t(x) * Ny * Nz;
+  float* Af = reinterpret_cast<float*>(A);
+  staged_copy<8, float>(
+      Ny * Nz, [&](int e) { return src[e]; },
+      [&](int e, float v) {
+        const int y = int(fdiv(uint32_t(e), a.nzd)), m = e - y * Nz;
+        Af[2 * ((y >> 1) * Nz + m) + (y & 1)] = v;
+      });
+  if (Ny & 1)   // odd row count: the last pencil's imaginary row is zero
+    for (int m = threadIdx.x; m < Nz; m += blockDim.x) Af[2 * ((Ny >> 1) * Nz + m) + 1] = 0.0f;
+  tz.store(twz, Nz);
+  ty.store(twy, Ny);
+  __syncthreads();
+  float2* Z = lds_fft(A, B, npairs, Nz, a.az, twz, -1.0f);
+  float2* O = (Z == A) ? B : A;
+  const int ps = Ny + 1;
+  for (int e = threadIdx.x; e < Ny * H; e += blockDim.x) {
+    const int y = int(fdiv(uint32_t(e), a.hd)), k = e - y * H;
+    const int c = y >> 1;
+    const float2 zk = Z[c * Nz + k];
+    const float2 zn = Z[c * Nz + (k ? Nz - k : 0)];
+    O[k * ps + y] = ((y & 1) == 0) ? make_float2(0.5f * (zk.x + zn.x), 0.5f * (zk.y - zn.y))
+                                   : make_float2(0.5f * (zk.y + zn.y), -0.5f * (zk.x - zn.x));
+  }
+  __syncthreads();
+  const float2* R = lds_fft(O, Z, H, ps, a.ay, twy, -1.0f);
+  float2* dst = a.spec + size_t(x) * Ny * H;
+  for (int e = threadIdx.x; e < Ny * H; e += blockDim.x) {
+    const int y = int(fdiv(uint32_t(e), a.hd)), k = e - y * H;
+    dst[e] = R[k * ps + y];
+  }
+}
+
+// inverse slab: spec[x] -> y inverse FFT -> z C2R -> out[x]
+__global__ void __launch_bounds__(kSlabThreads) k_slab_inv(SlabArgs a) {
+  extern __shared__ float2 sm[];
+  const int Ny = a.ay.N, Nz = a.az.N, H = a.H;
+  const int npairs = (Ny + 1) / 2;
+  float2 *twz, *twy, *A, *B;
+  slab_layout(a, sm, twz, twy, A, B);
+  const int x = blockIdx.x;
+  Twiddles<kSlabThreads> tz, ty;
+  tz.load(a.twz, Nz);
+  ty.load(a.twy, Ny);
+  const int ps = Ny + 1;
+  const float2* src = a.spec + size_t(x) * Ny * H;
+  staged_copy<8, float2>(
+      Ny * H, [&](int e) { return src[e]; },
+      [&](int e, float2 v) {
+        const int y = int(fdiv(uint32_t(e), a.hd)), k = e - y * H;
+        A[k * ps + y] = v;
+      });
+  tz.store(twz, Nz);
+  ty.store(twy, Ny);
+  __syncthreads();
+  float2* R = lds_fft(A, B, H, ps, a.ay, twy, +1.0f);
+  float2* O = (R == A) ? B : A;
+  const bool even = (Nz & 1) == 0;
+  for (int e = threadIdx.x; e < npairs * Nz; e += blockDim.x) {
+    const int c = int(fdiv(uint32_t(e), a.nzd)), m = e - c * Nz;
+    const int ya = 2 * c, yb = ya + 1;
+    float2 Av, Bv;
+    if (m < H) {
+      Av = R[m * ps + ya];
+      Bv = (yb < Ny) ? R[m * ps + yb] : make_float2(0.f, 0.f);
+    } else {
+      Av = R[(Nz - m) * ps + ya];
+      Bv = (yb < Ny) ? R[(Nz - m) * ps + yb] : make_float2(0.f, 0.f);
+      Av.y = -Av.y;
+      Bv.y = -Bv.y;
+    }
+    if (m == 0 || (even && m == Nz / 2)) { Av.y = 0.0f; Bv.y = 0.0f; }
+    O[e] = make_float2(Av.x - Bv.y, Av.y + Bv.x);
+  }
+  __syncthreads();
+  const float2* Z = lds_fft(O, R, npairs, Nz, a.az, twz, +1.0f);
+  float* dst = a.dst + size_t(x) * Ny * Nz;
+  for (int e = threadIdx.x; e < Ny * Nz; e += blockDim.x) {
+    const int y = int(fdiv(uint32_t(e), a.nzd)), m = e - y * Nz;
+    const float2 v = Z[(y >> 1) * Nz + m];
+    dst[e] = (y & 1) ? v.y : v.x;
+  }
+}
+
 struct YArgs {
   AxisPlan ax;
   const float2* tw;
@@ -264,7 +385,7 @@ __global__ void __launch_bounds__(kFFTThreads) k_ffty(YArgs a) {
   float2* Y = X + kt * ps;
   const int ntk = (H + kt - 1) / kt;
   const int x = blockIdx.x / ntk, kz0 = (blockIdx.x - x * ntk) * kt;
-  Twiddles twr;
+  Twiddles<kFFTThreads> twr;
   twr.load(a.tw, N);
   float2* base = a.spec + size_t(x) * a.Ny * H;
   staged_copy<16, float2>(
@@ -316,7 +437,7 @@ __global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
   float2* Y = X + kt * ps;
   const int ntk = (H + kt - 1) / kt;
   const int y = blockIdx.x / ntk, kz0 = (blockIdx.x - y * ntk) * kt;
-  Twiddles twr;
+  Twiddles<kFFTThreads> twr;
   twr.load(a.tw, Nx);
   const size_t xstride = size_t(Ny) * H;
   float2* base = a.spec + size_t(y) * H;
@@ -406,6 +527,29 @@ FastDiv host_fastdiv(int d) {
 
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
                            bool energy) {
+  hipError_t err;
+  XArgs x;
+  x.ax = d.ax[0]; x.tw = d.twiddle[0];
+  for (int k = 0; k < 3; ++k) x.N[k] = d.N[k];
+  x.H = d.H; x.kt = d.ktile; x.ktd = host_fastdiv(d.ktile); x.spec = d.spec; x.box = box;
+  x.dcx = d.deconv[0]; x.dcy = d.deconv[1]; x.dcz = d.deconv[2];
+  x.alpha = float(d.alpha);
+  x.epart = energy ? d.epart : nullptr;
+  const size_t xsh = sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1));
+
+  if (d.slab) {
+    SlabArgs sa;
+    sa.ay = d.ax[1]; sa.az = d.ax[2]; sa.twy = d.twiddle[1]; sa.twz = d.twiddle[2];
+    sa.H = d.H; sa.nzd = host_fastdiv(d.N[2]); sa.hd = host_fastdiv(d.H);
+    sa.src = d.rho; sa.spec = d.spec; sa.dst = out;
+    hipLaunchKernelGGL(k_slab_fwd, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(k_fftx_fused, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    hipLaunchKernelGGL(k_slab_inv, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
+    return hipGetLastError();
+  }
+
   const int rows = d.N[0] * d.N[1];
   ZArgs z;
   z.ax = d.ax[2]; z.tw = d.twiddle[2]; z.rows = rows; z.H = d.H; z.rp = d.rows_per_block;
@@ -414,8 +558,7 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   const int zb = fftz_blocks(d);
   const size_t zsh_f = sizeof(float2) * (d.N[2] + d.rows_per_block * d.N[2]);
   hipLaunchKernelGGL(k_fftz_r2c, dim3(zb), dim3(kFFTThreads), zsh_f, s, z);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
+  if ((err = hipGetLastError()) != hipSuccess) return err;
 
   YArgs y;
   y.ax = d.ax[1]; y.tw = d.twiddle[1]; y.Ny = d.N[1]; y.H = d.H; y.kt = d.ktile; y.spec = d.spec;
@@ -425,14 +568,6 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   hipLaunchKernelGGL(k_ffty, dim3(ffty_blocks(d)), dim3(kFFTThreads), ysh, s, y);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
-  XArgs x;
-  x.ax = d.ax[0]; x.tw = d.twiddle[0];
-  for (int k = 0; k < 3; ++k) x.N[k] = d.N[k];
-  x.H = d.H; x.kt = d.ktile; x.ktd = host_fastdiv(d.ktile); x.spec = d.spec; x.box = box;
-  x.dcx = d.deconv[0]; x.dcy = d.deconv[1]; x.dcz = d.deconv[2];
-  x.alpha = float(d.alpha);
-  x.epart = energy ? d.epart : nullptr;
-  const size_t xsh = sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1));
   hipLaunchKernelGGL(k_fftx_fused, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
@@ -443,6 +578,14 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   const size_t zsh_i = sizeof(float2) * (d.N[2] + d.rows_per_block * d.H + d.rows_per_block * d.N[2]);
   hipLaunchKernelGGL(k_fftz_c2r, dim3(zb), dim3(kFFTThreads), zsh_i, s, z);
   return hipGetLastError();
+}
+
+hipError_t enable_slab_lds(size_t bytes) {
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_slab_fwd),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_slab_inv),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
 }
 
 }  // namespace pme

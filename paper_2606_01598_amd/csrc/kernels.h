@@ -37,7 +37,9 @@ struct AxisPlan {          // 1D mixed-radix FFT of length N
   FFTStage st[kMaxStages];
 };
 
-constexpr int kFFTThreads = 64;   // one wavefront per FFT workgroup
+constexpr int kFFTThreads = 256;    // pencil-pass workgroup
+constexpr int kSlabThreads = 512;   // slab-pass workgroup (one x-plane)
+constexpr int kSlabLdsMax = 160 * 1024 - 2048;
 
 struct DevPlan {
   int N[3];                // mesh dims
@@ -63,6 +65,8 @@ struct DevPlan {
   AxisPlan ax[3];
   float2* twiddle[3];      // e^{-2 pi i t / N_a}, t < N_a
   float* deconv[3];        // |sinc(f/N_a)|^{-2 gamma p}, signed f
+  bool slab;               // y-z planes transformed in LDS (z and y passes fused)
+  size_t slab_lds;         // dynamic LDS bytes of a slab workgroup
   int rows_per_block;      // z-pass rows per block (even)
   int ktile;               // half-spectrum z columns per y/x-pass block (y and x pass)
   // meshes
@@ -93,6 +97,8 @@ hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent)
 // rho -> spec -> (x g) -> out, the mesh operator K; energy partials when wanted.
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
                            bool energy);
+// Allow slab workgroups `bytes` of dynamic LDS (above the 64 KiB default).
+hipError_t enable_slab_lds(size_t bytes);
 // Gradient gather (+ energy finalisation) over the atoms binned in counter set `set`.
 hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                          const float* q, const float* mu, const double* box, double* energy,

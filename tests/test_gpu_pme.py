@@ -86,6 +86,32 @@ def test_forward_small_and_odd_meshes(mesh, p):
     _check_forward(f, mesh, p, 0.4, label=f"mesh{mesh}")
 
 
+def _random_frame(n, box, seed):
+    rng = np.random.default_rng(seed)
+    frac = rng.uniform(0, 1, (n, 3))
+    q = rng.normal(0, 1, n)
+    q -= q.mean()
+    return synth.Frame(pos=frac @ box, q=q, mu=rng.normal(0, 0.1, (n, 3)), box=box)
+
+
+def test_pencil_mode_mesh_forward_and_hvp():
+    # a y-z half-spectrum plane too large for LDS: five pencil passes instead of slabs
+    box = np.diag([12.0, 80.0, 75.0])
+    f = _random_frame(400, box, 17)
+    mesh, p, a = (12, 160, 150), 5, 0.45
+    _check_forward(f, mesh, p, a, label="pencil")
+    plan = _plan(mesh, p, a, f.n)
+    pos, q, mu, box_t = to_dev(f)
+    plan.forward(pos, q, mu, box_t)
+    v = synth.random_cotangents(f.n, 3, scale_r=0.1)
+    vt = [torch.tensor(x, dtype=torch.float32, device=dev()) for x in v]
+    out = plan.backward(pos, q, mu, box_t, *vt)
+    ref = oracle_hvp(f, mesh, p, a, v)
+    errs = [rms_rel(host(out[k]), r) for k, r in zip(("g_pos", "g_q", "g_mu"), ref)]
+    print("pencil hvp", [f"{e:.2e}" for e in errs], flush=True)
+    assert max(errs) <= RMS_REL_TOL
+
+
 def test_forward_triclinic_cell():
     f = synth.triclinic_cell(n=40)
     _check_forward(f, (20, 18, 24), 6, 0.45, label="triclinic")
