@@ -4,13 +4,34 @@ One step = pme_forward (E^lr, dE/dr, dE/dq, dE/dmu) + pme_backward (Hessian-vect
 product with generic cotangents v_r, v_q, v_mu), inputs resident in HBM, on the
 32,000-ion molten-salt box (L = 100.006 A, mesh 100^3, p = 6, alpha = 0.30 1/A).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 32k|8k|128k|1m]
 
 Prints one JSON line.  Work is fixed per GPU ("weak" scaling); only N = 1 runs.
+
+Besides the whole-step rate the line carries
+  * "kernels_us": the average launch duration of every kernel kind over a short
+    pass after the warm-up, from HIP events that the launches themselves stamp
+    with their kernel's begin and end (pme_plan_timer);
+  * "roofline": the dominant kernel (largest time per step), timed the same way
+    over the timed region itself, against the HBM peak, with its
+    algorithmic bytes per launch (ALG_BYTES below) and, when a counter summary
+    for the current sources exists, its measured HBM traffic per launch;
+  * "cpu_baseline": the FP64 oracle timed on the host cores on a bounded sample.
+
+Counter summary (traffic):
+    rocprofv3 --pmc FETCH_SIZE -d D1 -o run -- python bench.py --steps 3 --warmup 2 \\
+        --cpu-baseline 0 --copy-calibration 1
+    rocprofv3 --pmc WRITE_SIZE -d D2 -o run -- python bench.py (same arguments)
+    python bench.py --traffic-summary D1/run_counter_collection.csv \\
+        D2/run_counter_collection.csv
+writes profiles/<kernel>_<workload>_traffic.txt, which the next bench run reads.
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -28,7 +49,46 @@ WORKLOADS = {
     "1m": (1000000, 5, (320, 320, 320), 6, 0.30),
 }
 
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+COPY_BYTES = 256 << 20         # calibration copy for the byte counters
+
+# Kernel symbol (as a profiler prints it) of each launch-timer kind, slab FFT layout.
+KERNEL_SYMBOL = {
+    "bin": "k_bin<6, false>", "bin_tangent": "k_bin<6, true>",
+    "spread": "k_spread<6, 1>", "spread_tangent": "k_spread<6, 2>",
+    "fft_r2c": "k_slab_fwd", "fft_x": "k_fftx_fused", "fft_c2r": "k_slab_inv",
+    "gather": "k_gather<6>", "gather_hvp": "k_gather_hvp<6>",
+}
+
+
+def alg_bytes(kind: str, n: int, m: int) -> int:
+    """Algorithmic HBM bytes of one launch: the method's arrays (FP32) that the
+    step must read or write, split over the kernels that touch them.  Summed over a
+    forward + backward step this is 224 B per atom + 36 B per mesh point:
+      bin            pos, q, mu in                               28 n
+      bin_tangent    pos, q, mu, v_pos, v_q, v_mu in             56 n
+      spread(_tan.)  rho (or the tangent density) out            4 M
+      fft_r2c        density in                                  4 M
+      fft_x          (intermediate spectrum only)                0
+      fft_c2r        potential out                               4 M
+      gather         pos, q, mu in; 3 gradients out; phi in      56 n + 4 M
+      gather_hvp     6 inputs in; 3 outputs; phi and psi in      84 n + 8 M
+    """
+    table = {"bin": 28 * n, "bin_tangent": 56 * n, "spread": 4 * m, "spread_tangent": 4 * m,
+             "fft_r2c": 4 * m, "fft_x": 0, "fft_c2r": 4 * m, "gather": 56 * n + 4 * m,
+             "gather_hvp": 84 * n + 8 * m}
+    return table[kind]
+
+
+def source_digest() -> str:
+    """Digest of the HIP sources: a traffic summary is valid only for the kernels
+    it was measured on."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2606_01598_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def _args(argv=None):
@@ -40,22 +100,31 @@ def _args(argv=None):
     ap.add_argument("--cpu-baseline", type=int, default=1,
                     help="0 skips the oracle timing on the host")
     ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--breakdown-steps", type=int, default=10)
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="1 also runs a device copy of 256 MiB (byte-counter calibration)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the counter summary of the dominant kernel and exit")
+    ap.add_argument("--kernel", default=None, help="kernel kind for --traffic-summary")
     return ap.parse_args(argv)
 
 
 def main(argv=None):
     args = _args(argv)
+    if args.traffic_summary:
+        return traffic_summary(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         return 2
-    import numpy as np
     import torch
 
     import synth
+    from paper_2606_01598_amd import _lib
     from paper_2606_01598_amd.pme import Plan
 
     n, seed, mesh, p, alpha = WORKLOADS[args.workload]
+    m = mesh[0] * mesh[1] * mesh[2]
     frame = synth.molten_box(n, seed)
     dev = torch.device("cuda", 0)
     pos = torch.tensor(frame.pos, dtype=torch.float32, device=dev)
@@ -79,15 +148,46 @@ def main(argv=None):
         step()
     plan.status()
     torch.cuda.synchronize()
+
+    # per-kind launch durations (short pass, one kind at a time)
+    kernels_us, per_step_us = {}, {}
+    for kind in _lib.KERNEL_KINDS:
+        plan.timer(kind)
+        for _ in range(args.breakdown_steps):
+            step()
+        launches, ms = plan.timer_read()
+        if launches:
+            kernels_us[kind] = round(1e3 * ms / launches, 3)
+            per_step_us[kind] = 1e3 * ms / args.breakdown_steps
+    plan.timer(None)
+    dominant = max((k for k in per_step_us if alg_bytes(k, n, m) > 0),
+                   key=lambda k: per_step_us[k])
+
+    # timed region; the dominant kernel's launches are bracketed by HIP events
+    plan.timer(dominant)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    launches, dom_ms = plan.timer_read()
+    plan.timer(None)
     plan.status()
     ms = (t1 - t0) * 1e3 / args.steps
     value = n * args.steps / (t1 - t0) / 1e6
 
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    dur_s = dom_ms / launches / 1e3
+    ab = alg_bytes(dominant, n, m)
+    achieved = ab / dur_s / 1e9
+    traffic = read_traffic(dominant, args.workload)
     line = {
         "metric": "PME q+mu fwd+bwd Matom-steps/s @32k atoms",
         "value": value,
@@ -105,6 +205,13 @@ def main(argv=None):
                                f"cubic L={frame.box[0, 0]:.3f} A, mesh {mesh[0]}x{mesh[1]}x{mesh[2]}, "
                                f"p={p}, alpha={alpha}, forward + Hessian-vector product",
                    "atoms": n, "mesh": list(mesh), "order": p, "alpha": alpha},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
+                     "traffic": traffic, "kernel": KERNEL_SYMBOL[dominant], "kind": dominant,
+                     "alg_bytes_per_launch": ab, "avg_launch_us": round(dur_s * 1e6, 3),
+                     "launches": launches},
+        "kernels_us": kernels_us,
+        "step_model_bytes": 224 * n + 36 * m,
     }
     if args.cpu_baseline and args.workload == "32k":
         line["cpu_baseline"] = cpu_baseline(frame, mesh, p, alpha, v, args.cpu_steps)
@@ -112,12 +219,110 @@ def main(argv=None):
     return 0
 
 
+def _traffic_path(kind: str, workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{kind}_{workload}_traffic.txt")
+
+
+def read_traffic(kind: str, workload: str):
+    """HBM bytes per launch of `kind` from its committed counter summary, or None
+    when there is none or it was taken on other kernel sources."""
+    path = _traffic_path(kind, workload)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for ln in fh:
+            if ":" in ln:
+                k, _, v = ln.partition(":")
+                vals[k.strip()] = v.strip()
+    if vals.get("sources") != source_digest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def _counter_means(path: str, counter: str):
+    """Mean per-dispatch value (KiB) of `counter` for every kernel in a rocprofv3
+    counter-collection CSV.  For the copy kernel only the dispatches of the largest
+    grid (the calibration copy) are kept."""
+    rows = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Counter_Name") == counter:
+                rows.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    copy_grid = max([g for k, g, _ in rows if "copyBuffer" in k], default=0)
+    sums, cnt = {}, {}
+    for k, g, v in rows:
+        if "copyBuffer" in k and g != copy_grid:
+            continue
+        sums[k] = sums.get(k, 0.0) + v
+        cnt[k] = cnt.get(k, 0) + 1
+    return {k: (sums[k] / cnt[k], cnt[k]) for k in sums}
+
+
+def traffic_summary(args) -> int:
+    fetch = _counter_means(args.traffic_summary[0], "FETCH_SIZE")
+    write = _counter_means(args.traffic_summary[1], "WRITE_SIZE")
+    kind = args.kernel or "spread_tangent"
+    sym = KERNEL_SYMBOL[kind]
+
+    def find(table, key):
+        hits = [k for k in table if key in k]
+        if not hits:
+            raise SystemExit(f"no dispatch of {key} in the counter file")
+        return hits[0]
+
+    copy_f = find(fetch, "copyBuffer")
+    copy_w = find(write, "copyBuffer")
+    # KiB read / written per copy dispatch vs the bytes it moves
+    f_scale = COPY_BYTES / (fetch[copy_f][0] * 1024.0)
+    w_scale = COPY_BYTES / (write[copy_w][0] * 1024.0)
+    kf = find(fetch, sym)
+    kw = find(write, sym)
+    fb = fetch[kf][0] * 1024.0 * f_scale
+    wb = write[kw][0] * 1024.0 * w_scale
+    n, _, mesh, _, _ = WORKLOADS[args.workload]
+    m = mesh[0] * mesh[1] * mesh[2]
+    out = _traffic_path(kind, args.workload)
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    with open(out, "w") as fh:
+        fh.write(f"# HBM traffic of {sym} ({kind}), workload {args.workload}\n")
+        fh.write("# commands:\n")
+        fh.write("#   rocprofv3 --pmc FETCH_SIZE -d <D1> -o run -- python bench.py --steps 3 "
+                 f"--warmup 2 --workload {args.workload} --cpu-baseline 0 --copy-calibration 1\n")
+        fh.write("#   rocprofv3 --pmc WRITE_SIZE -d <D2> -o run -- python bench.py --steps 3 "
+                 f"--warmup 2 --workload {args.workload} --cpu-baseline 0 --copy-calibration 1\n")
+        fh.write("#   python bench.py --traffic-summary <D1>/run_counter_collection.csv "
+                 f"<D2>/run_counter_collection.csv --kernel {kind} --workload {args.workload}\n")
+        fh.write(f"sources: {source_digest()}\n")
+        fh.write(f"kernel: {kf}\n")
+        fh.write(f"dispatches: {fetch[kf][1]} (FETCH_SIZE), {write[kw][1]} (WRITE_SIZE)\n")
+        fh.write(f"fetch_kib_per_dispatch: {fetch[kf][0]:.1f}\n")
+        fh.write(f"write_kib_per_dispatch: {write[kw][0]:.1f}\n")
+        fh.write(f"copy_kernel: {copy_f}\n")
+        fh.write(f"copy_fetch_kib: {fetch[copy_f][0]:.1f} for {COPY_BYTES} bytes read "
+                 f"(scale {f_scale:.4f})\n")
+        fh.write(f"copy_write_kib: {write[copy_w][0]:.1f} for {COPY_BYTES} bytes written "
+                 f"(scale {w_scale:.4f})\n")
+        fh.write(f"fetch_bytes_per_launch: {fb:.0f}\n")
+        fh.write(f"write_bytes_per_launch: {wb:.0f}\n")
+        fh.write(f"traffic_bytes_per_launch: {fb + wb:.0f}\n")
+        fh.write(f"alg_bytes_per_launch: {alg_bytes(kind, n, m)}\n")
+    print(open(out).read())
+    return 0
+
+
 def cpu_baseline(frame, mesh, p, alpha, v, steps):
     """The FP64 oracle (forward + HVP) timed on the host cores, on `steps` full steps."""
-    import numpy as np
-
     from oracle import pme as opme
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = 1
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
+    except Exception:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
     t0 = time.perf_counter()
     for _ in range(steps):
         opme.forward(frame.pos, frame.q, frame.mu, frame.box, mesh, p, alpha)
@@ -126,7 +331,8 @@ def cpu_baseline(frame, mesh, p, alpha, v, steps):
     return {"value": frame.n * steps / dt / 1e6, "unit": "Matom-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"{steps} full forward+HVP steps of the same {frame.n}-ion workload "
-                      f"({dt:.1f} s)"}
+                      f"({dt:.1f} s; the DFT matrix products use {threads} BLAS threads, the "
+                      f"spread and gather loops one)"}
 
 
 if __name__ == "__main__":

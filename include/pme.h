@@ -150,6 +150,38 @@ const char* pme_last_hip_error(void);
 const float* pme_plan_phi(pme_plan_t plan);
 const float* pme_plan_rho(pme_plan_t plan);
 
+/* ---- launch timing (measurement support) ------------------------------ */
+/* Kernel kinds that pme_plan_timer can bracket.  Each kind is one launch (or, in
+ * the pencil FFT layout, the two launches of one transform half) per call. */
+#define PME_K_NONE           -1
+#define PME_K_BIN             0   /* forward binning: stencil anchors, records     */
+#define PME_K_BIN_TANGENT     1   /* binning of the tangent density (backward)     */
+#define PME_K_SPREAD          2   /* spread of q and mu onto the mesh (Eq.
+                                     charge_dipole_assign)                          */
+#define PME_K_SPREAD_TANGENT  3   /* spread of the tangent density (backward)      */
+#define PME_K_FFT_R2C         4   /* forward real-to-complex passes before the x
+                                     pass (Eq. fft)                                 */
+#define PME_K_FFT_X           5   /* x pass: forward x FFT, influence multiply
+                                     (Eqs. influence, potential_k), energy, inverse */
+#define PME_K_FFT_C2R         6   /* inverse complex-to-real passes (Eq. ifft)      */
+#define PME_K_GATHER          7   /* gradient gather + energy (Eqs. energy_recip,
+                                     forces)                                        */
+#define PME_K_GATHER_HVP      8   /* Hessian-vector product gather (backward)       */
+#define PME_K_COUNT           9
+
+/* Time every later launch of kernel kind `kind` (PME_K_*) by this plan: the
+ * launch records its kernel's own begin and end timestamps into a HIP event
+ * pair (hipExtLaunchKernel), so the interval excludes queueing and dispatch.
+ * PME_K_NONE stops timing.  Switching kinds discards what was recorded.  Up to
+ * 65536 launches are kept between reads; later ones are not timed.  Returns
+ * PME_OK, PME_EINVAL (bad kind or plan) or PME_EHIP (event creation failed). */
+int pme_plan_timer(pme_plan_t plan, int kind);
+
+/* Wait for the recorded events, then return the number of timed launches in
+ * *launches and their summed duration in milliseconds in *total_ms, and clear
+ * the record (the kind stays armed).  Host pointers; either may be NULL. */
+int pme_plan_timer_read(pme_plan_t plan, int64_t* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,7 +31,11 @@ PME_MESH_CEIL = 2
 # every symbol include/pme.h declares
 EXPORTS = ("pme_mesh_dims", "pme_plan_create", "pme_plan_destroy", "pme_plan_workspace_bytes",
            "pme_forward", "pme_backward", "pme_status", "pme_strerror", "pme_last_hip_error",
-           "pme_plan_phi", "pme_plan_rho")
+           "pme_plan_phi", "pme_plan_rho", "pme_plan_timer", "pme_plan_timer_read")
+
+# launch-timer kinds (PME_K_* of include/pme.h)
+KERNEL_KINDS = ("bin", "bin_tangent", "spread", "spread_tangent", "fft_r2c", "fft_x",
+                "fft_c2r", "gather", "gather_hvp")
 
 
 class PMEDesc(ctypes.Structure):
@@ -85,6 +89,11 @@ def load():
     lib.pme_plan_phi.restype = vp
     lib.pme_plan_rho.argtypes = [vp]
     lib.pme_plan_rho.restype = vp
+    lib.pme_plan_timer.argtypes = [vp, ctypes.c_int]
+    lib.pme_plan_timer.restype = ctypes.c_int
+    lib.pme_plan_timer_read.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_double)]
+    lib.pme_plan_timer_read.restype = ctypes.c_int
     _lib = lib
     return lib
 

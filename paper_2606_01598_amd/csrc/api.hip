@@ -19,7 +19,31 @@ struct pme_plan_s {
   int max_atoms;
   bool phi_valid;
   int set;        // counter set of the next binning (alternates)
+  pme::KTimer timer;
 };
+
+namespace pme {
+
+constexpr size_t kTimerMaxEvents = 2 * 65536;
+
+const LaunchEvents* KTimer::next(int k) {
+  if (k != kind) return nullptr;
+  if (used + 2 > ev.size()) {
+    if (ev.size() >= kTimerMaxEvents) return nullptr;
+    for (int i = 0; i < 512; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) break;
+      ev.push_back(e);
+    }
+    if (used + 2 > ev.size()) return nullptr;
+  }
+  cur.start = ev[used];
+  cur.stop = ev[used + 1];
+  used += 2;
+  return &cur;
+}
+
+}  // namespace pme
 
 namespace {
 
@@ -85,6 +109,7 @@ hipError_t dev_alloc(T** p, size_t count, int64_t& bytes) {
 }
 
 void free_plan(pme_plan_s* pl) {
+  for (hipEvent_t e : pl->timer.ev) (void)hipEventDestroy(e);
   DevPlan& d = pl->d;
   void* ptrs[] = {d.count[0], d.count[1], d.ovf_count[0], d.ovf_count[1], d.cmax[0],
                   d.cmax[1], d.rec, d.ovf_rec, d.twiddle[0], d.twiddle[1], d.twiddle[2],
@@ -309,18 +334,20 @@ int pme_forward(pme_plan_t plan, void* stream, int32_t n, const float* pos, cons
   if (n > plan->max_atoms) return PME_ECAPACITY;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const DevPlan& d = plan->d;
+  pme::KTimer& tm = plan->timer;
   hipError_t e;
   plan->phi_valid = false;
   const int set = plan->set;
   plan->set ^= 1;
   if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
-                           energy != nullptr)) != hipSuccess)
+                           energy != nullptr, tm.next(PME_K_BIN))) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_spread(d, s, set, false)) != hipSuccess) return hip_fail(e);
-  if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr)) != hipSuccess)
+  if ((e = pme::launch_spread(d, s, set, false, tm.next(PME_K_SPREAD))) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm)) != hipSuccess)
     return hip_fail(e);
   if ((e = pme::launch_gather(d, s, set, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu,
-                              pme::bin_blocks(n))) != hipSuccess)
+                              pme::bin_blocks(n), tm.next(PME_K_GATHER))) != hipSuccess)
     return hip_fail(e);
   plan->phi_valid = true;
   return PME_OK;
@@ -333,27 +360,63 @@ int pme_backward(pme_plan_t plan, void* stream, int32_t n, const float* pos, con
   if (n > plan->max_atoms) return PME_ECAPACITY;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const DevPlan& d = plan->d;
+  pme::KTimer& tm = plan->timer;
   hipError_t e;
   if (!((plan->desc.flags & PME_F_KEEP_PHI) && plan->phi_valid)) {
     const int set = plan->set;
     plan->set ^= 1;
     if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
-                             false)) != hipSuccess)
+                             false, tm.next(PME_K_BIN))) != hipSuccess)
       return hip_fail(e);
-    if ((e = pme::launch_spread(d, s, set, false)) != hipSuccess) return hip_fail(e);
-    if ((e = pme::launch_convolve(d, s, box, d.phi, false)) != hipSuccess) return hip_fail(e);
+    if ((e = pme::launch_spread(d, s, set, false, tm.next(PME_K_SPREAD))) != hipSuccess)
+      return hip_fail(e);
+    if ((e = pme::launch_convolve(d, s, box, d.phi, false, &tm)) != hipSuccess) return hip_fail(e);
     plan->phi_valid = true;
   }
   const int set = plan->set;
   plan->set ^= 1;
-  if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, v_pos, v_q, v_mu, true, false)) !=
-      hipSuccess)
+  if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, v_pos, v_q, v_mu, true, false,
+                           tm.next(PME_K_BIN_TANGENT))) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_spread(d, s, set, true)) != hipSuccess) return hip_fail(e);
-  if ((e = pme::launch_convolve(d, s, box, d.rho, false)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_spread(d, s, set, true, tm.next(PME_K_SPREAD_TANGENT))) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_convolve(d, s, box, d.rho, false, &tm)) != hipSuccess) return hip_fail(e);
   if ((e = pme::launch_gather_hvp(d, s, set, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q,
-                                  g_mu)) != hipSuccess)
+                                  g_mu, tm.next(PME_K_GATHER_HVP))) != hipSuccess)
     return hip_fail(e);
+  return PME_OK;
+}
+
+int pme_plan_timer(pme_plan_t plan, int kind) {
+  if (!plan || kind < PME_K_NONE || kind >= PME_K_COUNT) return PME_EINVAL;
+  pme::KTimer& t = plan->timer;
+  t.kind = kind;
+  t.used = 0;
+  if (kind != PME_K_NONE && t.ev.empty()) {
+    for (int i = 0; i < 512; ++i) {
+      hipEvent_t ev;
+      const hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return hip_fail(e);
+      t.ev.push_back(ev);
+    }
+  }
+  return PME_OK;
+}
+
+int pme_plan_timer_read(pme_plan_t plan, int64_t* launches, double* total_ms) {
+  if (!plan) return PME_EINVAL;
+  pme::KTimer& t = plan->timer;
+  double sum = 0.0;
+  for (size_t i = 0; i + 1 < t.used; i += 2) {
+    hipError_t e = hipEventSynchronize(t.ev[i + 1]);
+    if (e != hipSuccess) return hip_fail(e);
+    float ms = 0.0f;
+    if ((e = hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1])) != hipSuccess) return hip_fail(e);
+    sum += ms;
+  }
+  if (launches) *launches = int64_t(t.used / 2);
+  if (total_ms) *total_ms = sum;
+  t.used = 0;
   return PME_OK;
 }
 

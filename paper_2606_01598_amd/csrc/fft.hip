@@ -19,6 +19,7 @@
 // Nyquist bins of a non-orthogonal cell use the mean of g over the bin and its
 // Hermitian partner, which makes the half-spectrum product equal the real part of
 // the full complex product (the real-to-complex semantics).
+#include "../../include/pme.h"
 #include "kernels.h"
 #include "pme_common.h"
 
@@ -526,7 +527,7 @@ FastDiv host_fastdiv(int d) {
 }  // namespace
 
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
-                           bool energy) {
+                           bool energy, KTimer* tm) {
   hipError_t err;
   XArgs x;
   x.ax = d.ax[0]; x.tw = d.twiddle[0];
@@ -536,17 +537,25 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   x.alpha = float(d.alpha);
   x.epart = energy ? d.epart : nullptr;
   const size_t xsh = sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1));
+  // timed kinds: a kind spanning two launches records its start with the first
+  // and its stop with the second
+  const LaunchEvents* er = tm ? tm->next(PME_K_FFT_R2C) : nullptr;
+  const LaunchEvents* ex = tm ? tm->next(PME_K_FFT_X) : nullptr;
+  const LaunchEvents* ei = tm ? tm->next(PME_K_FFT_C2R) : nullptr;
+  LaunchEvents er0, er1, ei0, ei1;
+  if (er) { er0.start = er->start; er1.stop = er->stop; }
+  if (ei) { ei0.start = ei->start; ei1.stop = ei->stop; }
 
   if (d.slab) {
     SlabArgs sa;
     sa.ay = d.ax[1]; sa.az = d.ax[2]; sa.twy = d.twiddle[1]; sa.twz = d.twiddle[2];
     sa.H = d.H; sa.nzd = host_fastdiv(d.N[2]); sa.hd = host_fastdiv(d.H);
     sa.src = d.rho; sa.spec = d.spec; sa.dst = out;
-    hipLaunchKernelGGL(k_slab_fwd, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
+    launch_k(er, k_slab_fwd, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_fftx_fused, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+    launch_k(ex, k_fftx_fused, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_slab_inv, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
+    launch_k(ei, k_slab_inv, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
     return hipGetLastError();
   }
 
@@ -557,26 +566,25 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   z.nd = host_fastdiv(d.N[2]);
   const int zb = fftz_blocks(d);
   const size_t zsh_f = sizeof(float2) * (d.N[2] + d.rows_per_block * d.N[2]);
-  hipLaunchKernelGGL(k_fftz_r2c, dim3(zb), dim3(kFFTThreads), zsh_f, s, z);
-  if ((err = hipGetLastError()) != hipSuccess) return err;
-
   YArgs y;
   y.ax = d.ax[1]; y.tw = d.twiddle[1]; y.Ny = d.N[1]; y.H = d.H; y.kt = d.ktile; y.spec = d.spec;
   y.ktd = host_fastdiv(d.ktile);
   const size_t ysh = sizeof(float2) * (d.N[1] + 2 * d.ktile * (d.N[1] + 1));
+
+  launch_k(er ? &er0 : nullptr, k_fftz_r2c, dim3(zb), dim3(kFFTThreads), zsh_f, s, z);
+  if ((err = hipGetLastError()) != hipSuccess) return err;
   y.sign = -1.0f;
-  hipLaunchKernelGGL(k_ffty, dim3(ffty_blocks(d)), dim3(kFFTThreads), ysh, s, y);
+  launch_k(er ? &er1 : nullptr, k_ffty, dim3(ffty_blocks(d)), dim3(kFFTThreads), ysh, s, y);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
-  hipLaunchKernelGGL(k_fftx_fused, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+  launch_k(ex, k_fftx_fused, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
   y.sign = +1.0f;
-  hipLaunchKernelGGL(k_ffty, dim3(ffty_blocks(d)), dim3(kFFTThreads), ysh, s, y);
+  launch_k(ei ? &ei0 : nullptr, k_ffty, dim3(ffty_blocks(d)), dim3(kFFTThreads), ysh, s, y);
   if ((err = hipGetLastError()) != hipSuccess) return err;
-
   const size_t zsh_i = sizeof(float2) * (d.N[2] + d.rows_per_block * d.H + d.rows_per_block * d.N[2]);
-  hipLaunchKernelGGL(k_fftz_c2r, dim3(zb), dim3(kFFTThreads), zsh_i, s, z);
+  launch_k(ei ? &ei1 : nullptr, k_fftz_c2r, dim3(zb), dim3(kFFTThreads), zsh_i, s, z);
   return hipGetLastError();
 }
 

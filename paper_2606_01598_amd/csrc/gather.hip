@@ -513,11 +513,12 @@ __global__ void __launch_bounds__(256) k_gather_hvp(GArgs a) {
 }
 
 template <bool HVP>
-hipError_t gather_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const GArgs& a) {
-#define PME_G(P)                                                                  \
-  case P:                                                                         \
-    if (HVP) hipLaunchKernelGGL(k_gather_hvp<P>, g, dim3(256), sh, s, a);         \
-    else hipLaunchKernelGGL(k_gather<P>, g, dim3(256), sh, s, a);                  \
+hipError_t gather_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const GArgs& a,
+                           const LaunchEvents* ev) {
+#define PME_G(P)                                                    \
+  case P:                                                           \
+    if (HVP) launch_k(ev, k_gather_hvp<P>, g, dim3(256), sh, s, a); \
+    else launch_k(ev, k_gather<P>, g, dim3(256), sh, s, a);         \
     break;
   switch (p) {
     PME_G(1) PME_G(2) PME_G(3) PME_G(4) PME_G(5) PME_G(6) PME_G(7)
@@ -549,23 +550,26 @@ size_t region_bytes(const DevPlan& d, int fields) {
 
 hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                          const float* q, const float* mu, const double* box, double* energy,
-                         float* dE_dpos, float* dE_dq, float* dE_dmu, int n_spart) {
+                         float* dE_dpos, float* dE_dq, float* dE_dmu, int n_spart,
+                         const LaunchEvents* ev) {
   GArgs a = base_args(d, set, n, pos, q, mu, box);
   a.o_pos = dE_dpos; a.o_q = dE_dq; a.o_mu = dE_dmu;
   a.energy = energy; a.epart = d.epart; a.n_epart = fftx_blocks(d);
   a.spart = d.spart; a.n_spart = n_spart;
-  return gather_dispatch<false>(d.p, dim3(d.nt[0] * d.nt[1] * d.nt[2]), region_bytes(d, 1), s, a);
+  return gather_dispatch<false>(d.p, dim3(d.nt[0] * d.nt[1] * d.nt[2]), region_bytes(d, 1), s, a,
+                                ev);
 }
 
 hipError_t launch_gather_hvp(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                              const float* q, const float* mu, const double* box,
                              const float* v_pos, const float* v_q, const float* v_mu,
-                             float* g_pos, float* g_q, float* g_mu) {
+                             float* g_pos, float* g_q, float* g_mu, const LaunchEvents* ev) {
   GArgs a = base_args(d, set, n, pos, q, mu, box);
   a.psi = d.rho;
   a.v_pos = v_pos; a.v_q = v_q; a.v_mu = v_mu;
   a.o_pos = g_pos; a.o_q = g_q; a.o_mu = g_mu;
-  return gather_dispatch<true>(d.p, dim3(d.nt[0] * d.nt[1] * d.nt[2]), region_bytes(d, 2), s, a);
+  return gather_dispatch<true>(d.p, dim3(d.nt[0] * d.nt[1] * d.nt[2]), region_bytes(d, 2), s, a,
+                               ev);
 }
 
 }  // namespace pme

@@ -1,8 +1,11 @@
 // Host-side launchers of the PME kernels and the plan data they read.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <vector>
 
 namespace pme {
 
@@ -79,6 +82,31 @@ struct DevPlan {
   int* status;             // bit 0: non-finite input seen
 };
 
+// Events into which a launch records its kernel's own begin and end timestamps
+// (hipExtLaunchKernel); null members are not recorded.
+struct LaunchEvents {
+  hipEvent_t start = nullptr;
+  hipEvent_t stop = nullptr;
+};
+
+template <class F, class... A>
+inline void launch_k(const LaunchEvents* ev, F kernel, dim3 g, dim3 b, size_t sh, hipStream_t s,
+                     A... args) {
+  hipExtLaunchKernelGGL(kernel, g, b, uint32_t(sh), s, ev ? ev->start : nullptr,
+                        ev ? ev->stop : nullptr, 0u, args...);
+}
+
+// Launch timer (host side): hands out event pairs for the launches of one kernel
+// kind.
+struct KTimer {
+  int kind = -1;
+  std::vector<hipEvent_t> ev;   // start/stop pairs
+  size_t used = 0;              // events handed out since the last read
+  LaunchEvents cur;
+  // Events for the next launch of kind k, or nullptr when k is not being timed.
+  const LaunchEvents* next(int k);
+};
+
 inline int fftx_blocks(const DevPlan& d) { return d.N[1] * ((d.H + d.ktile - 1) / d.ktile); }
 inline int ffty_blocks(const DevPlan& d) { return d.N[0] * ((d.H + d.ktile - 1) / d.ktile); }
 inline int fftz_blocks(const DevPlan& d) {
@@ -91,22 +119,25 @@ inline int bin_blocks(int n) { return n > 0 ? (n + 255) / 256 : 1; }
 // dipole; tangent: the 10 monomial coefficients of the tangent density).
 hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                       const float* q, const float* mu, const double* box, const float* v_pos,
-                      const float* v_q, const float* v_mu, bool tangent, bool self_sums);
+                      const float* v_q, const float* v_mu, bool tangent, bool self_sums,
+                      const LaunchEvents* ev);
 // Owner-computes spread of the binned records (counter set `set`) into d.rho.
-hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent);
+hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
+                         const LaunchEvents* ev);
 // rho -> spec -> (x g) -> out, the mesh operator K; energy partials when wanted.
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
-                           bool energy);
+                           bool energy, KTimer* tm);
 // Allow slab workgroups `bytes` of dynamic LDS (above the 64 KiB default).
 hipError_t enable_slab_lds(size_t bytes);
 // Gradient gather (+ energy finalisation) over the atoms binned in counter set `set`.
 hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                          const float* q, const float* mu, const double* box, double* energy,
-                         float* dE_dpos, float* dE_dq, float* dE_dmu, int n_spart);
+                         float* dE_dpos, float* dE_dq, float* dE_dmu, int n_spart,
+                         const LaunchEvents* ev);
 // Hessian-vector product gather from phi (d.phi) and psi (d.rho).
 hipError_t launch_gather_hvp(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                              const float* q, const float* mu, const double* box,
                              const float* v_pos, const float* v_q, const float* v_mu,
-                             float* g_pos, float* g_q, float* g_mu);
+                             float* g_pos, float* g_q, float* g_mu, const LaunchEvents* ev);
 
 }  // namespace pme

@@ -417,30 +417,31 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
 }
 
 template <bool TANGENT>
-hipError_t bin_dispatch(int p, dim3 g, hipStream_t s, const BinArgs& a) {
+hipError_t bin_dispatch(int p, dim3 g, hipStream_t s, const BinArgs& a, const LaunchEvents* ev) {
   switch (p) {
-    case 1: hipLaunchKernelGGL((k_bin<1, TANGENT>), g, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_bin<2, TANGENT>), g, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_bin<3, TANGENT>), g, dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_bin<4, TANGENT>), g, dim3(256), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((k_bin<5, TANGENT>), g, dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_bin<6, TANGENT>), g, dim3(256), 0, s, a); break;
-    case 7: hipLaunchKernelGGL((k_bin<7, TANGENT>), g, dim3(256), 0, s, a); break;
+    case 1: launch_k(ev, k_bin<1, TANGENT>, g, dim3(256), 0, s, a); break;
+    case 2: launch_k(ev, k_bin<2, TANGENT>, g, dim3(256), 0, s, a); break;
+    case 3: launch_k(ev, k_bin<3, TANGENT>, g, dim3(256), 0, s, a); break;
+    case 4: launch_k(ev, k_bin<4, TANGENT>, g, dim3(256), 0, s, a); break;
+    case 5: launch_k(ev, k_bin<5, TANGENT>, g, dim3(256), 0, s, a); break;
+    case 6: launch_k(ev, k_bin<6, TANGENT>, g, dim3(256), 0, s, a); break;
+    case 7: launch_k(ev, k_bin<7, TANGENT>, g, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
 template <int DEG>
-hipError_t spread_dispatch(int p, dim3 g, hipStream_t s, const SpreadArgs& a) {
+hipError_t spread_dispatch(int p, dim3 g, hipStream_t s, const SpreadArgs& a,
+                           const LaunchEvents* ev) {
   switch (p) {
-    case 1: hipLaunchKernelGGL((k_spread<1, DEG>), g, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_spread<2, DEG>), g, dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_spread<3, DEG>), g, dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_spread<4, DEG>), g, dim3(256), 0, s, a); break;
-    case 5: hipLaunchKernelGGL((k_spread<5, DEG>), g, dim3(256), 0, s, a); break;
-    case 6: hipLaunchKernelGGL((k_spread<6, DEG>), g, dim3(256), 0, s, a); break;
-    case 7: hipLaunchKernelGGL((k_spread<7, DEG>), g, dim3(256), 0, s, a); break;
+    case 1: launch_k(ev, k_spread<1, DEG>, g, dim3(256), 0, s, a); break;
+    case 2: launch_k(ev, k_spread<2, DEG>, g, dim3(256), 0, s, a); break;
+    case 3: launch_k(ev, k_spread<3, DEG>, g, dim3(256), 0, s, a); break;
+    case 4: launch_k(ev, k_spread<4, DEG>, g, dim3(256), 0, s, a); break;
+    case 5: launch_k(ev, k_spread<5, DEG>, g, dim3(256), 0, s, a); break;
+    case 6: launch_k(ev, k_spread<6, DEG>, g, dim3(256), 0, s, a); break;
+    case 7: launch_k(ev, k_spread<7, DEG>, g, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -450,7 +451,8 @@ hipError_t spread_dispatch(int p, dim3 g, hipStream_t s, const SpreadArgs& a) {
 
 hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                       const float* q, const float* mu, const double* box, const float* v_pos,
-                      const float* v_q, const float* v_mu, bool tangent, bool self_sums) {
+                      const float* v_q, const float* v_mu, bool tangent, bool self_sums,
+                      const LaunchEvents* ev) {
   BinArgs a;
   a.n = n; a.pos = pos; a.q = q; a.mu = mu; a.box = box;
   a.v_pos = v_pos; a.v_q = v_q; a.v_mu = v_mu;
@@ -464,10 +466,11 @@ hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const flo
   a.spart = self_sums ? d.spart : nullptr;
   a.status = d.status;
   const dim3 g(bin_blocks(n));
-  return tangent ? bin_dispatch<true>(d.p, g, s, a) : bin_dispatch<false>(d.p, g, s, a);
+  return tangent ? bin_dispatch<true>(d.p, g, s, a, ev) : bin_dispatch<false>(d.p, g, s, a, ev);
 }
 
-hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent) {
+hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
+                         const LaunchEvents* ev) {
   SpreadArgs a;
   for (int k = 0; k < 3; ++k) {
     a.N[k] = d.N[k]; a.B[k] = d.B[k]; a.nb[k] = d.nb[k]; a.T[k] = d.T[k]; a.nt[k] = d.nt[k];
@@ -476,7 +479,7 @@ hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent)
   a.count = d.count[set]; a.ovf_count = d.ovf_count[set]; a.cmax = d.cmax[set];
   a.rec = d.rec; a.ovf_rec = d.ovf_rec; a.rho = d.rho;
   const dim3 g(d.nt[0] * d.nt[1] * d.nt[2]);
-  return tangent ? spread_dispatch<2>(d.p, g, s, a) : spread_dispatch<1>(d.p, g, s, a);
+  return tangent ? spread_dispatch<2>(d.p, g, s, a, ev) : spread_dispatch<1>(d.p, g, s, a, ev);
 }
 
 }  // namespace pme

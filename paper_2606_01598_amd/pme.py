@@ -155,6 +155,20 @@ class Plan:
         """pme_status: synchronise and raise on device-detected errors."""
         _lib.check(self._lib.pme_status(self.handle, _stream()))
 
+    def timer(self, kind) -> None:
+        """pme_plan_timer: bracket every later launch of one kernel kind (a name of
+        _lib.KERNEL_KINDS, or None to stop) with HIP events on the launch stream."""
+        k = -1 if kind is None else _lib.KERNEL_KINDS.index(kind)
+        _lib.check(self._lib.pme_plan_timer(self.handle, k))
+
+    def timer_read(self):
+        """pme_plan_timer_read: (launches, total milliseconds) since the last read."""
+        import ctypes as ct
+        n = ct.c_int64(0)
+        ms = ct.c_double(0.0)
+        _lib.check(self._lib.pme_plan_timer_read(self.handle, ct.byref(n), ct.byref(ms)))
+        return int(n.value), float(ms.value)
+
     def phi(self) -> torch.Tensor:
         """Copy of the potential mesh of the last forward (N_x, N_y, N_z)."""
         return self._mesh_copy(self._lib.pme_plan_phi(self.handle))

@@ -266,3 +266,35 @@ def test_config3_32k_full_parity():
     configuration, against the oracle on every atom."""
     f = synth.molten_box(32000, 3)
     _check_forward(f, (100, 100, 100), 6, 0.3, label="32k")
+
+
+def test_launch_timer_counts_and_outputs_unchanged():
+    """pme_plan_timer brackets exactly the launches of the chosen kind and leaves
+    the results untouched."""
+    from paper_2606_01598_amd import _lib
+    f = synth.molten_box(1000, 1)
+    plan = _plan((32, 32, 32), 6, 0.3, f.n)
+    pos, q, mu, box = to_dev(f)
+    v = [torch.tensor(x, dtype=torch.float32, device=dev()) for x in
+         synth.random_cotangents(f.n, 5, scale_r=0.1)]
+    ref = plan.forward(pos, q, mu, box)
+    ref_b = plan.backward(pos, q, mu, box, *v)
+    per_step = {"bin": 1, "bin_tangent": 1, "spread": 1, "spread_tangent": 1, "fft_r2c": 2,
+                "fft_x": 2, "fft_c2r": 2, "gather": 1, "gather_hvp": 1}
+    for kind in _lib.KERNEL_KINDS:
+        plan.timer(kind)
+        for _ in range(3):
+            out = plan.forward(pos, q, mu, box)
+            outb = plan.backward(pos, q, mu, box, *v)
+        launches, ms = plan.timer_read()
+        assert launches == 3 * per_step[kind], (kind, launches)
+        assert 0.0 < ms < 1e3, (kind, ms)
+        for k in ("dE_dpos", "dE_dq", "dE_dmu"):
+            assert torch.equal(out[k], ref[k])
+        for k in ("g_pos", "g_q", "g_mu"):
+            assert torch.equal(outb[k], ref_b[k])
+    plan.timer(None)
+    plan.forward(pos, q, mu, box)
+    assert plan.timer_read() == (0, 0.0)
+    assert plan._lib.pme_plan_timer(plan.handle, _lib.PME_EINVAL + 100) == _lib.PME_EINVAL
+    plan.status()
