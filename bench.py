@@ -99,7 +99,7 @@ def _args(argv=None):
     ap.add_argument("--workload", default="32k", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-baseline", type=int, default=1,
                     help="0 skips the oracle timing on the host")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--breakdown-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="1 also runs a device copy of 256 MiB (byte-counter calibration)")
