@@ -112,7 +112,7 @@ void free_plan(pme_plan_s* pl) {
   for (hipEvent_t e : pl->timer.ev) (void)hipEventDestroy(e);
   DevPlan& d = pl->d;
   void* ptrs[] = {d.count[0], d.count[1], d.ovf_count[0], d.ovf_count[1], d.cmax[0],
-                  d.cmax[1], d.rec, d.ovf_rec, d.twiddle[0], d.twiddle[1], d.twiddle[2],
+                  d.cmax[1], d.rec, d.twiddle[0], d.twiddle[1], d.twiddle[2],
                   d.deconv[0], d.deconv[1], d.deconv[2], d.rho, d.spec, d.phi, d.epart,
                   d.spart, d.status};
   for (void* p : ptrs)
@@ -229,6 +229,26 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   }
   for (int a = 0; a < 3; ++a) d.nt[a] = (d.N[a] + d.T[a] - 1) / d.T[a];
   {
+    // spread staging: records per round such that five workgroups share a CU's
+    // 160 KiB of LDS (all tiles of a 100^3 mesh resident at once; 1 KiB per
+    // workgroup is left for static LDS and allocation granularity), at least 64
+    long range = 1;
+    for (int a = 0; a < 3; ++a) {
+      long k = (d.T[a] + p - 1 + d.B[a] - 1) / d.B[a] + 1;
+      range *= (k < d.nb[a] ? k : d.nb[a]);
+    }
+    d.nbr_max = int(range);
+    const int tw = d.T[0] * d.T[1] * (d.T[2] + 1);
+    for (int deg = 1; deg <= 2; ++deg) {
+      const long fixed = long(pme::spread_lds_bytes(tw, d.nbr_max, 0, p, deg));
+      const long per = 4L * pme::spread_entry_words(p, deg) + 2L * p;
+      long ch = (32768 - 1024 - fixed) / per;
+      if (ch > 256) ch = 256;
+      if (ch < 64) ch = 64;
+      d.spread_ch[deg - 1] = int(ch);
+    }
+  }
+  {
     const double per_bin = double(desc->max_atoms) * d.B[0] * d.B[1] * d.B[2] / double(M);
     long cap = long(ceil(2.0 * per_bin)) + 8;
     if (cap > 64) cap = 64;
@@ -266,8 +286,10 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
     ok(dev_alloc(&d.ovf_count[k], 1, by));
     ok(dev_alloc(&d.cmax[k], 1, by));
   }
-  ok(dev_alloc(&d.rec, size_t(nbins) * d.cap * 16, by));
-  ok(dev_alloc(&d.ovf_rec, size_t(desc->max_atoms) * 16, by));
+  // one allocation for the bins and the overflow list, so that kernels select a
+  // record by index from a single base pointer
+  d.ovf_base = (long long)nbins * d.cap;
+  ok(dev_alloc(&d.rec, (size_t(d.ovf_base) + size_t(desc->max_atoms)) * 16, by));
   for (int a = 0; a < 3; ++a) {
     ok(dev_alloc(&d.twiddle[a], size_t(d.N[a]), by));
     ok(dev_alloc(&d.deconv[a], size_t(d.N[a]), by));

@@ -58,7 +58,7 @@ struct GArgs {
   const int* count;
   const int* ovf_count;
   const float* rec;
-  const float* ovf_rec;
+  long long ovf_base;      // record index of the overflow list
   int T[3];
   int nt[3];
 };
@@ -226,9 +226,8 @@ __device__ __forceinline__ const float4* item_record(const GArgs& a, int item, i
   }
   const int bin = s_bin[lo_i];
   const int slot = item - s_off[lo_i];
-  const float4* r = reinterpret_cast<const float4*>(
-      (bin >= 0) ? a.rec + (size_t(bin) * a.cap + slot) * kRecWords
-                 : a.ovf_rec + size_t(slot) * kRecWords);
+  const size_t ri = (bin >= 0) ? size_t(bin) * a.cap + slot : size_t(a.ovf_base) + slot;
+  const float4* r = reinterpret_cast<const float4*>(a.rec + ri * kRecWords);
   owned = true;
   if (bin < 0) {
     const int pk = __float_as_int(r[0].w);
@@ -538,7 +537,7 @@ GArgs base_args(const DevPlan& d, int set, int n, const float* pos, const float*
   a.phi = d.phi;
   a.alpha = d.alpha; a.prefactor = d.prefactor;
   a.cap = d.cap; a.count = d.count[set]; a.ovf_count = d.ovf_count[set];
-  a.rec = d.rec; a.ovf_rec = d.ovf_rec;
+  a.rec = d.rec; a.ovf_base = d.ovf_base;
   return a;
 }
 

@@ -12,6 +12,22 @@ namespace pme {
 constexpr int kMaxStages = 16;
 constexpr int kMaxBinRange = 512;    // bins a spread tile may scan (LDS count array)
 constexpr int kTileLds = 1536;       // max padded spread-tile points: T_x T_y (T_z + 1)
+
+// LDS words of one staged spread entry: weights of three axes (derivative orders up
+// to deg), the assignment coefficients, the tile-local stencil coordinates and the
+// three fractional offsets; odd, so that consecutive entries start in different
+// LDS banks.
+constexpr int spread_entry_words(int p, int deg) {
+  return (3 * (deg + 1) * p + (deg == 1 ? 4 : 10) + 9) | 1;
+}
+// Slots of the item -> bin map of a spread workgroup (larger scanned ranges fall
+// back to a binary search).
+constexpr int kSpreadMap = 1024;
+// Dynamic LDS of a spread workgroup staging `ch` entries per round.
+inline size_t spread_lds_bytes(int tile_words, int nbr_max, int ch, int p, int deg) {
+  return size_t(8) * tile_words + size_t(8) * (nbr_max + 2) + size_t(2) * kSpreadMap +
+         size_t(4) * ch * spread_entry_words(p, deg) + size_t(2) * ch * p;
+}
 constexpr int kRecWords = 16;        // words per atom record
 
 // n / d for 0 <= n < 2^17 and 1 <= d <= 4096 by a multiply-high:
@@ -54,13 +70,16 @@ struct DevPlan {
   int B[3];
   int nb[3];
   int cap;                 // records per bin
+  int nbr_max;             // largest bin range a spread tile scans
+  int spread_ch[2];        // records staged per round by the forward / tangent spread
   // two counter sets used alternately by successive binnings; a binning clears the
   // other set, so no kernel has to clear the set it reads
   int* count[2];           // [nbins] atoms per bin
   int* ovf_count[2];       // [1] atoms in the overflow list
   unsigned* cmax[2];       // [1] max over atoms of sum |assignment coefficients| (float bits)
-  float* rec;              // [nbins * cap * 16] records (16 words each)
-  float* ovf_rec;          // [max_atoms * 16]
+  float* rec;              // [(nbins * cap + max_atoms) * 16] records (16 words each):
+                           // the bins, then the overflow list
+  long long ovf_base;      // record index of the overflow list (nbins * cap)
   // mesh tiles shared by the spread and the gathers (T[a] a multiple of B[a])
   int T[3];
   int nt[3];

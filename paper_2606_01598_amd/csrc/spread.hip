@@ -49,7 +49,7 @@ struct BinArgs {
   unsigned* cmax_other;
   int nbins;
   float* rec;
-  float* ovf_rec;
+  long long ovf_base;      // record index of the overflow list
   double* spart;
   int* status;
 };
@@ -120,14 +120,11 @@ __global__ void __launch_bounds__(256) k_bin(BinArgs a) {
       else atomicOr(a.status, 1);
       const int bin = ((base[0] / a.B[0]) * a.nb[1] + base[1] / a.B[1]) * a.nb[2] + base[2] / a.B[2];
       const int slot = atomicAdd(&a.count[bin], 1);
-      float* dst;
-      if (slot < a.cap) {
-        dst = a.rec + (size_t(bin) * a.cap + slot) * kRecWords;
-      } else {
-        const int o = atomicAdd(a.ovf_count, 1);
-        dst = a.ovf_rec + size_t(o) * kRecWords;
-      }
-      float4* d4 = reinterpret_cast<float4*>(dst);
+      // every atom takes one slot of its bin or of the overflow list (which holds
+      // max_atoms records)
+      const size_t ri = (slot < a.cap) ? size_t(bin) * a.cap + slot
+                                       : size_t(a.ovf_base) + atomicAdd(a.ovf_count, 1);
+      float4* d4 = reinterpret_cast<float4*>(a.rec + ri * kRecWords);
       d4[0] = make_float4(f[0], f[1], f[2],
                           __int_as_float(base[0] | (base[1] << 10) | (base[2] << 20)));
       d4[1] = make_float4(co[0], co[1], co[2], co[3]);
@@ -157,11 +154,14 @@ struct SpreadArgs {
   int B[3];
   int nb[3];
   int cap;
+  int ch;                  // records staged per round (<= 256)
+  int nbr_max;             // largest scanned bin range of a tile
+  int tile_words;          // largest padded tile T_x T_y (T_z + 1)
   const int* count;
   const int* ovf_count;
   const unsigned* cmax;
   const float* rec;
-  const float* ovf_rec;
+  long long ovf_base;      // record index of the overflow list
   int T[3];
   int nt[3];
   float* rho;
@@ -203,19 +203,37 @@ __device__ __forceinline__ int loc_of(int w0, int w1, int j) {
   return int(int8_t((w >> (8 * (j & 3))) & 0xff));
 }
 
+// Round a float of magnitude below 2^51 to the nearest integer (ties to even) as a
+// two's-complement 64-bit word.  Adding 1.5 * 2^52 in double precision leaves the
+// rounded value in the low mantissa bits; the constant's low word is zero, so only
+// the high word needs the bias removed (3 instructions instead of the long
+// float -> int64 conversion sequence).
+__device__ __forceinline__ unsigned long long to_fixed(float v) {
+  const double t = double(v) + 6755399441055744.0;   // 1.5 * 2^52
+  const unsigned long long b = (unsigned long long)__double_as_longlong(t);
+  const uint32_t lo = uint32_t(b), hi = uint32_t(b >> 32) - 0x43380000u;
+  return (unsigned long long)lo | ((unsigned long long)hi << 32);
+}
+
 template <int P, int DEG>
-__global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+k_spread(SpreadArgs a) {
   constexpr int NC = (DEG == 1) ? 4 : 10;
   constexpr int D = DEG;                      // highest weight derivative needed
-  constexpr int CH = 128;                     // atoms staged per round
   constexpr int NW = 3 * (D + 1) * P;         // weights w[axis][d][j]
-  constexpr int ES = (NW + NC + 6) | 1;       // odd entry stride (LDS banks)
+  constexpr int ES = spread_entry_words(P, DEG);
   constexpr int lo = (P - 1) / 2;
-  __shared__ unsigned long long s_tile[kTileLds];
-  __shared__ int s_off[kMaxBinRange + 2];
-  __shared__ int s_bin[kMaxBinRange + 1];
-  __shared__ float s_ent[CH * ES];
-  __shared__ int s_n;
+  const int CH = a.ch;                        // records staged per round
+  // dynamic LDS, sized by the host (spread_lds_bytes): the fixed-point tile, the
+  // scanned bin range, the staged entries and the task list
+  extern __shared__ unsigned long long s_dyn[];
+  unsigned long long* s_tile = s_dyn;
+  int* s_off = reinterpret_cast<int*>(s_tile + a.tile_words);
+  int* s_bin = s_off + a.nbr_max + 2;
+  uint16_t* s_map = reinterpret_cast<uint16_t*>(s_bin + a.nbr_max + 2);
+  float* s_ent = reinterpret_cast<float*>(s_map + kSpreadMap);
+  uint16_t* s_task = reinterpret_cast<uint16_t*>(s_ent + CH * ES);
+  __shared__ int s_n, s_ntask;
 
   const int tid = threadIdx.x;
   int t0[3], T[3];
@@ -244,7 +262,7 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
     kmin[ax] = k0;
     if (nk[ax] >= a.nb[ax]) { nk[ax] = a.nb[ax]; kmin[ax] = 0; }
   }
-  const int nbr = nk[0] * nk[1] * nk[2];      // <= kMaxBinRange (host guarantees)
+  const int nbr = nk[0] * nk[1] * nk[2];      // <= a.nbr_max (host guarantees)
   for (int e = tid; e < nbr; e += 256) {
     const int kz = e % nk[2], ky = (e / nk[2]) % nk[1], kx = e / (nk[1] * nk[2]);
     const int bx = wrapn(kmin[0] + kx, a.nb[0]);
@@ -264,7 +282,7 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
     const float cm = __uint_as_float(*a.cmax);
     if (cm > 0.0f && isfinite(cm)) scale = ldexpf(1.0f, 40 - (ilogbf(8.0f * cm) + 1));
   }
-  const int TZP = T[2] + 1;                   // padded z stride of the LDS tile
+  const int TZP = T[2] + 1;                   // padded z stride; column T_z is scratch
   const int tpad = T[0] * T[1] * TZP;
   for (int e = tid; e < tpad; e += 256) s_tile[e] = 0ull;
   __syncthreads();
@@ -287,80 +305,128 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
   }
   __syncthreads();
   const int total = s_off[nbr + 1];
+  const bool mapped = total <= kSpreadMap;
+  if (mapped)
+    for (int e = tid; e <= nbr; e += 256)
+      for (int k = s_off[e]; k < s_off[e + 1]; ++k) s_map[k] = uint16_t(e);
+  __syncthreads();
 
-  for (int r0 = 0; r0 < total; r0 += CH) {
-    if (tid == 0) s_n = 0;
-    __syncthreads();
-    // 1. load the round's records, keep those whose stencil reaches the tile, stage
-    //    their weights, tile-local coordinates and coefficients
-    const int item = r0 + tid;
-    bool hit = false;
-    float4 h = make_float4(0.f, 0.f, 0.f, 0.f), c0v = h, c1v = h, c2v = h;
-    if (tid < CH && item < total) {
-      int lo_i = 0, hi_i = nbr;                 // largest bin with s_off <= item
+  // record of scanned slot `item`: the bin is the last one whose offset is <= item
+  auto fetch = [&](int item, float4& h, float4& c0v, float4& c1v, float4& c2v) {
+    int lo_i = 0;
+    if (mapped) {
+      lo_i = s_map[item];
+    } else {
+      int hi_i = nbr;
       while (lo_i < hi_i) {
         const int mid = (lo_i + hi_i + 1) >> 1;
         if (s_off[mid] <= item) lo_i = mid; else hi_i = mid - 1;
       }
-      const int bin = s_bin[lo_i];
-      const int slot = item - s_off[lo_i];
-      const float4* r = reinterpret_cast<const float4*>(
-          (bin >= 0) ? a.rec + (size_t(bin) * a.cap + slot) * kRecWords
-                     : a.ovf_rec + size_t(slot) * kRecWords);
-      h = r[0];
-      c0v = r[1];
-      if (NC == 10) {
-        c1v = r[2];
-        c2v = r[3];
-      }
+    }
+    const int bin = s_bin[lo_i];
+    const int slot = item - s_off[lo_i];
+    const size_t ri = (bin >= 0) ? size_t(bin) * a.cap + slot : size_t(a.ovf_base) + slot;
+    const float4* r = reinterpret_cast<const float4*>(a.rec + ri * kRecWords);
+    h = r[0];
+    c0v = r[1];
+    if (NC == 10) {
+      c1v = r[2];
+      c2v = r[3];
+    }
+  };
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  float4 h = z4, c0v = z4, c1v = z4, c2v = z4;
+  if (tid < CH && tid < total) fetch(tid, h, c0v, c1v, c2v);
+
+  for (int r0 = 0; r0 < total; r0 += CH) {
+    if (tid == 0) { s_n = 0; s_ntask = 0; }
+    // the next round's record is loaded now and used after this round's
+    // accumulation (barriers do not wait for global loads)
+    float4 nh = z4, nc0 = z4, nc1 = z4, nc2 = z4;
+    if (tid < CH && r0 + CH + tid < total) fetch(r0 + CH + tid, nh, nc0, nc1, nc2);
+    __syncthreads();
+    // 1. keep the records whose stencil reaches the tile; stage their weights,
+    //    tile-local coordinates and coefficients, and one task per stencil x-plane
+    //    that lies in the tile
+    bool hit = false;
+    int lw[3][2];
+    if (tid < CH && r0 + tid < total) {
       const int pk = __float_as_int(h.w);
-      hit = axis_hits<P>(pk & 1023, t0[0], T[0], a.N[0]) &&
-            axis_hits<P>((pk >> 10) & 1023, t0[1], T[1], a.N[1]) &&
-            axis_hits<P>((pk >> 20) & 1023, t0[2], T[2], a.N[2]);
+      const int b[3] = {pk & 1023, (pk >> 10) & 1023, (pk >> 20) & 1023};
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) axis_locs<P>(b[ax], t0[ax], T[ax], a.N[ax], lw[ax][0], lw[ax][1]);
+      // a byte is 0xff where the stencil point lies outside the tile
+      auto any_in = [](int w0, int w1) {
+        const uint32_t u0 = uint32_t(w0), u1 = uint32_t(w1) | (P <= 4 ? 0xffffffffu : 0u);
+        const uint32_t m0 = (P >= 4) ? 0xffffffffu : ((1u << (8 * P)) - 1u);
+        const uint32_t m1 = (P > 4) ? ((P == 8) ? 0xffffffffu : ((1u << (8 * (P - 4))) - 1u)) : 0u;
+        return ((u0 & m0) != (0xffffffffu & m0)) || ((u1 & m1) != (0xffffffffu & m1));
+      };
+      hit = any_in(lw[0][0], lw[0][1]) && any_in(lw[1][0], lw[1][1]) && any_in(lw[2][0], lw[2][1]);
     }
     const int k = wave_compact(hit, &s_n);
     if (hit) {
-      const int pk = __float_as_int(h.w);
-      const int b[3] = {pk & 1023, (pk >> 10) & 1023, (pk >> 20) & 1023};
-      const float fr[3] = {h.x, h.y, h.z};
       float* ent = s_ent + k * ES;
 #pragma unroll
       for (int ax = 0; ax < 3; ++ax) {
-        float w[D + 1][P];
-        spline_weights<P, D>(fr[ax], w);
-#pragma unroll
-        for (int d = 0; d <= D; ++d)
-#pragma unroll
-          for (int j = 0; j < P; ++j) ent[(ax * (D + 1) + d) * P + j] = w[d][j];
-        int l0, l1;
-        axis_locs<P>(b[ax], t0[ax], T[ax], a.N[ax], l0, l1);
-        ent[NW + NC + 2 * ax] = __int_as_float(l0);
-        ent[NW + NC + 2 * ax + 1] = __int_as_float(l1);
+        ent[NW + NC + 2 * ax] = __int_as_float(lw[ax][0]);
+        ent[NW + NC + 2 * ax + 1] = __int_as_float(lw[ax][1]);
       }
+      ent[NW + NC + 6] = h.x; ent[NW + NC + 7] = h.y; ent[NW + NC + 8] = h.z;
       ent[NW + 0] = c0v.x; ent[NW + 1] = c0v.y; ent[NW + 2] = c0v.z; ent[NW + 3] = c0v.w;
       if (NC == 10) {
         ent[NW + 4] = c1v.x; ent[NW + 5] = c1v.y; ent[NW + 6] = c1v.z; ent[NW + 7] = c1v.w;
         ent[NW + 8] = c2v.x; ent[NW + 9] = c2v.y;
       }
+      int nx = 0;
+#pragma unroll
+      for (int j = 0; j < P; ++j) nx += (loc_of(lw[0][0], lw[0][1], j) >= 0) ? 1 : 0;
+      int t = atomicAdd(&s_ntask, nx);
+#pragma unroll
+      for (int j = 0; j < P; ++j)
+        if (loc_of(lw[0][0], lw[0][1], j) >= 0) s_task[t++] = uint16_t((k << 3) | j);
     }
     __syncthreads();
-    // 2. accumulate: one task per (atom, x-plane of its stencil)
-    const int ntask = s_n * P;
+    // weights: one thread per (entry, axis); the x weights carry the fixed-point unit
+    {
+      const int nent = s_n;
+      for (int t = tid; t < 3 * nent; t += 256) {
+        const int e = t / 3, ax = t - 3 * e;
+        float* ent = s_ent + e * ES;
+        float w[D + 1][P];
+        spline_weights<P, D>(ent[NW + NC + 6 + ax], w);
+        const float sc = (ax == 0) ? scale : 1.0f;
+#pragma unroll
+        for (int d = 0; d <= D; ++d)
+#pragma unroll
+          for (int j = 0; j < P; ++j) ent[(ax * (D + 1) + d) * P + j] = w[d][j] * sc;
+      }
+    }
+    __syncthreads();
+    // 2. accumulate: one task per (atom, in-tile x-plane of its stencil); stencil
+    //    points outside the tile along z go to the scratch column T_z of their row
+    const int ntask = s_ntask;
     for (int t = tid; t < ntask; t += 256) {
-      const int e = t / P, ix = t - e * P;
+      const int task = s_task[t];
+      const int e = task >> 3, ix = task & 7;
       const float* ent = s_ent + e * ES;
       const int lx = loc_of(__float_as_int(ent[NW + NC]), __float_as_int(ent[NW + NC + 1]), ix);
-      if (lx < 0) continue;
       const int ly0 = __float_as_int(ent[NW + NC + 2]), ly1 = __float_as_int(ent[NW + NC + 3]);
       const int lz0 = __float_as_int(ent[NW + NC + 4]), lz1 = __float_as_int(ent[NW + NC + 5]);
       float wz[D + 1][P];
+      int zi[P];
 #pragma unroll
       for (int d = 0; d <= D; ++d)
 #pragma unroll
         for (int j = 0; j < P; ++j) wz[d][j] = ent[(2 * (D + 1) + d) * P + j];
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int l = loc_of(lz0, lz1, j);
+        zi[j] = (l >= 0) ? l : T[2];
+      }
       float x[D + 1];
 #pragma unroll
-      for (int d = 0; d <= D; ++d) x[d] = ent[d * P + ix];
+      for (int d = 0; d <= D; ++d) x[d] = ent[d * P + ix];   // pre-scaled by the fixed-point unit
       float co[NC];
 #pragma unroll
       for (int kk = 0; kk < NC; ++kk) co[kk] = ent[NW + kk];
@@ -394,15 +460,14 @@ __global__ void __launch_bounds__(256) k_spread(SpreadArgs a) {
         unsigned long long* row = s_tile + (rowx + ly) * TZP;
 #pragma unroll
         for (int iz = 0; iz < P; ++iz) {
-          const int lz = loc_of(lz0, lz1, iz);
-          if (lz < 0) continue;
           float v = c0 * wz[0][iz] + c1 * wz[1][iz];
           if (DEG == 2) v += c2 * wz[2][iz];
-          atomicAdd(row + lz, (unsigned long long)__float2ll_rn(v * scale));
+          atomicAdd(row + zi[iz], to_fixed(v));
         }
       }
     }
     __syncthreads();
+    h = nh; c0v = nc0; c1v = nc1; c2v = nc2;
   }
 
   // 3. write the tile back (plain stores; every point is owned by this tile)
@@ -432,16 +497,16 @@ hipError_t bin_dispatch(int p, dim3 g, hipStream_t s, const BinArgs& a, const La
 }
 
 template <int DEG>
-hipError_t spread_dispatch(int p, dim3 g, hipStream_t s, const SpreadArgs& a,
+hipError_t spread_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const SpreadArgs& a,
                            const LaunchEvents* ev) {
   switch (p) {
-    case 1: launch_k(ev, k_spread<1, DEG>, g, dim3(256), 0, s, a); break;
-    case 2: launch_k(ev, k_spread<2, DEG>, g, dim3(256), 0, s, a); break;
-    case 3: launch_k(ev, k_spread<3, DEG>, g, dim3(256), 0, s, a); break;
-    case 4: launch_k(ev, k_spread<4, DEG>, g, dim3(256), 0, s, a); break;
-    case 5: launch_k(ev, k_spread<5, DEG>, g, dim3(256), 0, s, a); break;
-    case 6: launch_k(ev, k_spread<6, DEG>, g, dim3(256), 0, s, a); break;
-    case 7: launch_k(ev, k_spread<7, DEG>, g, dim3(256), 0, s, a); break;
+    case 1: launch_k(ev, k_spread<1, DEG>, g, dim3(256), sh, s, a); break;
+    case 2: launch_k(ev, k_spread<2, DEG>, g, dim3(256), sh, s, a); break;
+    case 3: launch_k(ev, k_spread<3, DEG>, g, dim3(256), sh, s, a); break;
+    case 4: launch_k(ev, k_spread<4, DEG>, g, dim3(256), sh, s, a); break;
+    case 5: launch_k(ev, k_spread<5, DEG>, g, dim3(256), sh, s, a); break;
+    case 6: launch_k(ev, k_spread<6, DEG>, g, dim3(256), sh, s, a); break;
+    case 7: launch_k(ev, k_spread<7, DEG>, g, dim3(256), sh, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -462,7 +527,7 @@ hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const flo
   a.count_other = d.count[1 - set]; a.ovf_other = d.ovf_count[1 - set];
   a.cmax_other = d.cmax[1 - set];
   a.nbins = d.nb[0] * d.nb[1] * d.nb[2];
-  a.rec = d.rec; a.ovf_rec = d.ovf_rec;
+  a.rec = d.rec; a.ovf_base = d.ovf_base;
   a.spart = self_sums ? d.spart : nullptr;
   a.status = d.status;
   const dim3 g(bin_blocks(n));
@@ -477,9 +542,14 @@ hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
   }
   a.cap = d.cap;
   a.count = d.count[set]; a.ovf_count = d.ovf_count[set]; a.cmax = d.cmax[set];
-  a.rec = d.rec; a.ovf_rec = d.ovf_rec; a.rho = d.rho;
+  a.rec = d.rec; a.ovf_base = d.ovf_base; a.rho = d.rho;
+  a.ch = d.spread_ch[tangent ? 1 : 0];
+  a.nbr_max = d.nbr_max;
+  a.tile_words = d.T[0] * d.T[1] * (d.T[2] + 1);
+  const size_t sh = spread_lds_bytes(a.tile_words, a.nbr_max, a.ch, d.p, tangent ? 2 : 1);
   const dim3 g(d.nt[0] * d.nt[1] * d.nt[2]);
-  return tangent ? spread_dispatch<2>(d.p, g, s, a, ev) : spread_dispatch<1>(d.p, g, s, a, ev);
+  return tangent ? spread_dispatch<2>(d.p, g, sh, s, a, ev)
+                 : spread_dispatch<1>(d.p, g, sh, s, a, ev);
 }
 
 }  // namespace pme
