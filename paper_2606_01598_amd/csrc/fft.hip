@@ -285,7 +285,8 @@ __global__ void __launch_bounds__(kSlabThreads) k_slab_fwd(SlabArgs a) {
   ty.load(a.twy, Ny);
   const float* src = a.src + size_t(x) * Ny * Nz;
   float* Af = reinterpret_cast<float*>(A);
-  staged_copy<8, float>(
+  // one batch of loads per thread for planes up to 20 * 1024 points
+  staged_copy<20, float>(
       Ny * Nz, [&](int e) { return src[e]; },
       [&](int e, float v) {
         const int y = int(fdiv(uint32_t(e), a.nzd)), m = e - y * Nz;
@@ -329,7 +330,7 @@ __global__ void __launch_bounds__(kSlabThreads) k_slab_inv(SlabArgs a) {
   ty.load(a.twy, Ny);
   const int ps = Ny + 1;
   const float2* src = a.spec + size_t(x) * Ny * H;
-  staged_copy<8, float2>(
+  staged_copy<12, float2>(
       Ny * H, [&](int e) { return src[e]; },
       [&](int e, float2 v) {
         const int y = int(fdiv(uint32_t(e), a.hd)), k = e - y * H;

@@ -57,7 +57,7 @@ struct AxisPlan {          // 1D mixed-radix FFT of length N
 };
 
 constexpr int kFFTThreads = 256;    // pencil-pass workgroup
-constexpr int kSlabThreads = 512;   // slab-pass workgroup (one x-plane)
+constexpr int kSlabThreads = 1024;  // slab-pass workgroup (one x-plane)
 constexpr int kSlabLdsMax = 160 * 1024 - 2048;
 
 struct DevPlan {
