@@ -31,7 +31,9 @@ PME_MESH_CEIL = 2
 # every symbol include/pme.h declares
 EXPORTS = ("pme_mesh_dims", "pme_plan_create", "pme_plan_destroy", "pme_plan_workspace_bytes",
            "pme_forward", "pme_backward", "pme_status", "pme_strerror", "pme_last_hip_error",
-           "pme_plan_phi", "pme_plan_rho", "pme_plan_timer", "pme_plan_timer_read")
+           "pme_plan_phi", "pme_plan_rho", "pme_plan_timer", "pme_plan_timer_read",
+           "pol_plan_create", "pol_plan_destroy", "pol_real", "pol_real_mixed", "pol_model",
+           "pol_scf")
 
 # launch-timer kinds (PME_K_* of include/pme.h)
 KERNEL_KINDS = ("bin", "bin_tangent", "spread", "spread_tangent", "fft_r2c", "fft_x",
@@ -46,6 +48,19 @@ class PMEDesc(ctypes.Structure):
                 ("alpha", ctypes.c_double),
                 ("influence_power", ctypes.c_double),
                 ("prefactor", ctypes.c_double)]
+
+
+class PolDesc(ctypes.Structure):
+    _fields_ = [("max_atoms", ctypes.c_int32),
+                ("flags", ctypes.c_int32),
+                ("box", ctypes.c_double * 9),
+                ("alpha", ctypes.c_double),
+                ("cutoff", ctypes.c_double),
+                ("thole_a", ctypes.c_double),
+                ("prefactor", ctypes.c_double)]
+
+
+POL_F_WARM_START = 1
 
 
 class PMEError(RuntimeError):
@@ -94,6 +109,19 @@ def load():
     lib.pme_plan_timer_read.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_double)]
     lib.pme_plan_timer_read.restype = ctypes.c_int
+    lib.pol_plan_create.argtypes = [ctypes.POINTER(PolDesc), ctypes.POINTER(vp)]
+    lib.pol_plan_create.restype = ctypes.c_int
+    lib.pol_plan_destroy.argtypes = [vp]
+    lib.pol_plan_destroy.restype = None
+    lib.pol_real.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.pol_real.restype = ctypes.c_int
+    lib.pol_real_mixed.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp]
+    lib.pol_real_mixed.restype = ctypes.c_int
+    lib.pol_model.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pol_model.restype = ctypes.c_int
+    lib.pol_scf.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, vp,
+                            ctypes.POINTER(i32), ctypes.POINTER(f64)]
+    lib.pol_scf.restype = ctypes.c_int
     _lib = lib
     return lib
 

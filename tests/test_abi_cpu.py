@@ -23,8 +23,11 @@ def _lib_or_skip():
 
 def test_header_declarations_are_exported():
     lib = _lib_or_skip()
-    header = open(os.path.join(ROOT, "include", "pme.h")).read()
-    declared = set(re.findall(r"\b(pme_[a-z_]+)\s*\(", header))
+    declared = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            declared |= set(re.findall(r"\b((?:pme|pol|dip)_[a-z_0-9]+)\s*\(", text))
     assert declared == set(_lib.EXPORTS)
     for name in declared:
         assert hasattr(lib, name), name
