@@ -33,7 +33,10 @@ EXPORTS = ("pme_mesh_dims", "pme_plan_create", "pme_plan_destroy", "pme_plan_wor
            "pme_forward", "pme_backward", "pme_status", "pme_strerror", "pme_last_hip_error",
            "pme_plan_phi", "pme_plan_rho", "pme_plan_timer", "pme_plan_timer_read",
            "pol_plan_create", "pol_plan_destroy", "pol_real", "pol_real_mixed", "pol_model",
-           "pol_scf")
+           "pol_scf", "dip_plan_create", "dip_plan_destroy", "dip_features", "dip_forward",
+           "dip_backward", "dip_loss", "dip_adam")
+
+DIP_NFEAT, DIP_NCH, DIP_HIDDEN, DIP_NPARAM = 34, 16, 64, 7440
 
 # launch-timer kinds (PME_K_* of include/pme.h)
 KERNEL_KINDS = ("bin", "bin_tangent", "spread", "spread_tangent", "fft_r2c", "fft_x",
@@ -61,6 +64,13 @@ class PolDesc(ctypes.Structure):
 
 
 POL_F_WARM_START = 1
+
+
+class DipDesc(ctypes.Structure):
+    _fields_ = [("max_atoms", ctypes.c_int32),
+                ("flags", ctypes.c_int32),
+                ("box", ctypes.c_double * 9),
+                ("cutoff", ctypes.c_double)]
 
 
 class PMEError(RuntimeError):
@@ -122,6 +132,20 @@ def load():
     lib.pol_scf.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, vp,
                             ctypes.POINTER(i32), ctypes.POINTER(f64)]
     lib.pol_scf.restype = ctypes.c_int
+    lib.dip_plan_create.argtypes = [ctypes.POINTER(DipDesc), ctypes.POINTER(vp)]
+    lib.dip_plan_create.restype = ctypes.c_int
+    lib.dip_plan_destroy.argtypes = [vp]
+    lib.dip_plan_destroy.restype = None
+    lib.dip_features.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    lib.dip_features.restype = ctypes.c_int
+    lib.dip_forward.argtypes = [vp, vp, i32, vp, vp, vp, vp]
+    lib.dip_forward.restype = ctypes.c_int
+    lib.dip_backward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.dip_backward.restype = ctypes.c_int
+    lib.dip_loss.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, f64, f64, f64, vp, vp, vp]
+    lib.dip_loss.restype = ctypes.c_int
+    lib.dip_adam.argtypes = [vp, i32, i32, f64, f64, f64, f64, vp, vp, vp, vp]
+    lib.dip_adam.restype = ctypes.c_int
     _lib = lib
     return lib
 

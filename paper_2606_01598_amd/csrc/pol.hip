@@ -16,77 +16,13 @@
 #include <new>
 
 #include "../../include/pol.h"
+#include "cells.h"
 #include "kernels.h"
 
 namespace {
 
 constexpr int kLanes = 16;          // lanes per atom in the pair kernels
 constexpr int kPairThreads = 256;
-constexpr int kMaxCells = 1 << 20;
-
-struct CellGrid {
-  float C[9];                       // rows are lattice vectors
-  float Ci[9];                      // inverse: s = r Ci
-  int nc[3];
-  int ncell;
-};
-
-__device__ __forceinline__ void frac(const CellGrid& g, float x, float y, float z, float& s0,
-                                     float& s1, float& s2) {
-  s0 = x * g.Ci[0] + y * g.Ci[3] + z * g.Ci[6];
-  s1 = x * g.Ci[1] + y * g.Ci[4] + z * g.Ci[7];
-  s2 = x * g.Ci[2] + y * g.Ci[5] + z * g.Ci[8];
-}
-
-__global__ void k_cell_clear(int* count, int ncell) {
-  for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < ncell; c += gridDim.x * blockDim.x)
-    count[c] = 0;
-}
-
-__global__ void k_cell_count(int n, const float* pos, CellGrid g, int* count, int* cellof,
-                             int* slot) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float s[3];
-  frac(g, pos[3 * i], pos[3 * i + 1], pos[3 * i + 2], s[0], s[1], s[2]);
-  int c[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    float t = s[a] - floorf(s[a]);
-    int k = int(t * float(g.nc[a]));
-    c[a] = (k < 0) ? 0 : ((k >= g.nc[a]) ? g.nc[a] - 1 : k);   // NaN positions land in cell 0
-  }
-  const int cell = (c[0] * g.nc[1] + c[1]) * g.nc[2] + c[2];
-  cellof[i] = cell;
-  slot[i] = atomicAdd(&count[cell], 1);
-}
-
-// exclusive scan of the cell counts (one workgroup of 1024)
-__global__ void __launch_bounds__(1024) k_cell_scan(const int* count, int* start, int ncell) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
-  const int seg = (ncell + 1023) / 1024;
-  const int s0 = min(t * seg, ncell), s1 = min(s0 + seg, ncell);
-  int acc = 0;
-  for (int c = s0; c < s1; ++c) acc += count[c];
-  part[t] = acc;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    const int v = (t >= o) ? part[t - o] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int run = part[t] - acc;
-  for (int c = s0; c < s1; ++c) { start[c] = run; run += count[c]; }
-  if (t == 1023) start[ncell] = part[1023];
-}
-
-__global__ void k_cell_fill(int n, const int* cellof, const int* slot, const int* start,
-                            int* sorted) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) sorted[start[cellof[i]] + slot[i]] = i;
-}
 
 enum PairMode { kEnergyGrad = 0, kMuGrad = 1, kMixed = 2 };
 
@@ -133,16 +69,10 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   const float3 mi = ld3(a.mu, ii);
   const float ai = a.pol[ii];
   const float3 vi = (MODE == kMixed) ? ld3(a.vpos, ii) : make_float3(0.f, 0.f, 0.f);
-  float s[3];
-  frac(a.g, pi.x, pi.y, pi.z, s[0], s[1], s[2]);
   int c[3], no[3];
+  cell_of(a.g, pi.x, pi.y, pi.z, c);
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const float t = s[d] - floorf(s[d]);
-    int k = int(t * float(a.g.nc[d]));
-    c[d] = (k < 0) ? 0 : ((k >= a.g.nc[d]) ? a.g.nc[d] - 1 : k);
-    no[d] = a.g.nc[d] < 3 ? a.g.nc[d] : 3;
-  }
+  for (int d = 0; d < 3; ++d) no[d] = a.g.nc[d] < 3 ? a.g.nc[d] : 3;
   const float sqpi = 1.7724538509055159f;
   const float t2 = 2.0f * a.alpha * a.alpha;
   float e = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
@@ -150,23 +80,16 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
     for (int ox = 0; ox < no[0]; ++ox)
       for (int oy = 0; oy < no[1]; ++oy)
         for (int oz = 0; oz < no[2]; ++oz) {
-          // neighbour cells: c-1..c+1 (wrapped), or every cell of a short axis once
-          const int cx = (a.g.nc[0] >= 3) ? (c[0] + ox - 1 + a.g.nc[0]) % a.g.nc[0] : ox;
-          const int cy = (a.g.nc[1] >= 3) ? (c[1] + oy - 1 + a.g.nc[1]) % a.g.nc[1] : oy;
-          const int cz = (a.g.nc[2] >= 3) ? (c[2] + oz - 1 + a.g.nc[2]) % a.g.nc[2] : oz;
+          const int cx = neighbour_cell(c[0], ox, a.g.nc[0]);
+          const int cy = neighbour_cell(c[1], oy, a.g.nc[1]);
+          const int cz = neighbour_cell(c[2], oz, a.g.nc[2]);
           const int cell = (cx * a.g.nc[1] + cy) * a.g.nc[2] + cz;
           const int b0 = a.start[cell], b1 = a.start[cell + 1];
           for (int k = b0 + lane; k < b1; k += kLanes) {
             const int j = a.sorted[k];
             if (j == i) continue;
             const float3 pj = ld3(a.pos, j);
-            // minimum image through fractional coordinates
-            float f0, f1, f2;
-            frac(a.g, pi.x - pj.x, pi.y - pj.y, pi.z - pj.z, f0, f1, f2);
-            f0 -= rintf(f0); f1 -= rintf(f1); f2 -= rintf(f2);
-            const float3 R = make_float3(f0 * a.g.C[0] + f1 * a.g.C[3] + f2 * a.g.C[6],
-                                         f0 * a.g.C[1] + f1 * a.g.C[4] + f2 * a.g.C[7],
-                                         f0 * a.g.C[2] + f1 * a.g.C[5] + f2 * a.g.C[8]);
+            const float3 R = min_image(a.g, pi.x - pj.x, pi.y - pj.y, pi.z - pj.z);
             const float r2 = dot3(R, R);
             if (r2 >= a.rc2 || r2 <= 0.0f) continue;
             const float r = sqrtf(r2), ir = 1.0f / r, ir2 = ir * ir;
@@ -368,12 +291,7 @@ __global__ void k_copy_scal(double* scal) {
 
 struct pol_plan_s {
   pol_desc_t desc;
-  CellGrid g;
-  int* count = nullptr;
-  int* start = nullptr;
-  int* cellof = nullptr;
-  int* slot = nullptr;
-  int* sorted = nullptr;
+  CellList cells;
   double* epart = nullptr;
   double* scal = nullptr;
   float* vec = nullptr;      // 8 work vectors of 3 max_atoms floats
@@ -389,35 +307,21 @@ int pol_hip_fail(hipError_t e) {
 }
 
 void pol_free(pol_plan_s* p) {
-  void* ptrs[] = {p->count, p->start, p->cellof, p->slot, p->sorted, p->epart, p->scal, p->vec};
+  free_cells(p->cells);
+  void* ptrs[] = {p->epart, p->scal, p->vec};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
   delete p;
 }
 
-inline int blocks_for(int m, int t) { return m > 0 ? (m + t - 1) / t : 1; }
-
-// Cell list of the current positions (4 launches).
-hipError_t build_cells(pol_plan_s* pl, hipStream_t s, int n, const float* pos) {
-  const CellGrid& g = pl->g;
-  hipLaunchKernelGGL(k_cell_clear, dim3(blocks_for(g.ncell, 256)), dim3(256), 0, s, pl->count,
-                     g.ncell);
-  if (n > 0)
-    hipLaunchKernelGGL(k_cell_count, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, pos, g,
-                       pl->count, pl->cellof, pl->slot);
-  hipLaunchKernelGGL(k_cell_scan, dim3(1), dim3(1024), 0, s, pl->count, pl->start, g.ncell);
-  if (n > 0)
-    hipLaunchKernelGGL(k_cell_fill, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, pl->cellof,
-                       pl->slot, pl->start, pl->sorted);
-  return hipGetLastError();
-}
+inline int blocks_for(int m, int t) { return cell_blocks(m, t); }
 
 PairArgs pair_args(const pol_plan_s* pl, int n, const float* pos, const float* q, const float* mu,
                    const float* pol) {
   PairArgs a;
   a.n = n; a.pos = pos; a.q = q; a.mu = mu; a.pol = pol; a.vpos = nullptr;
-  a.g = pl->g;
-  a.start = pl->start; a.sorted = pl->sorted;
+  a.g = pl->cells.g;
+  a.start = pl->cells.start; a.sorted = pl->cells.sorted;
   a.alpha = float(pl->desc.alpha);
   a.rc2 = float(pl->desc.cutoff * pl->desc.cutoff);
   a.A = float(pl->desc.thole_a);
@@ -431,7 +335,7 @@ int pair_blocks(int n) { return blocks_for(n, kPairThreads / kLanes); }
 // dE_real/dmu only (dipole field of mu and q)
 hipError_t real_mu_grad(pol_plan_s* pl, hipStream_t s, int n, const float* pos, const float* q,
                         const float* mu, const float* pol, float* out) {
-  hipError_t e = build_cells(pl, s, n, pos);
+  hipError_t e = build_cells(pl->cells, s, n, pos);
   if (e != hipSuccess) return e;
   PairArgs a = pair_args(pl, n, pos, q, mu, pol);
   a.o_mu = out;
@@ -454,44 +358,17 @@ int pol_plan_create(const pol_desc_t* desc, pol_plan_t* out) {
   if (!(desc->alpha > 0.0) || !isfinite(desc->alpha) || !(desc->thole_a >= 0.0) ||
       !isfinite(desc->thole_a) || !isfinite(desc->prefactor) || desc->prefactor == 0.0)
     return PME_EALPHA;
-  const double* C = desc->box;
-  const double det = C[0] * (C[4] * C[8] - C[5] * C[7]) - C[1] * (C[3] * C[8] - C[5] * C[6]) +
-                     C[2] * (C[3] * C[7] - C[4] * C[6]);
-  if (!isfinite(det) || fabs(det) < 1e-12) return PME_EINVAL;
-  double Ci[9];
-  Ci[0] = (C[4] * C[8] - C[5] * C[7]) / det; Ci[1] = (C[2] * C[7] - C[1] * C[8]) / det;
-  Ci[2] = (C[1] * C[5] - C[2] * C[4]) / det; Ci[3] = (C[5] * C[6] - C[3] * C[8]) / det;
-  Ci[4] = (C[0] * C[8] - C[2] * C[6]) / det; Ci[5] = (C[2] * C[3] - C[0] * C[5]) / det;
-  Ci[6] = (C[3] * C[7] - C[4] * C[6]) / det; Ci[7] = (C[1] * C[6] - C[0] * C[7]) / det;
-  Ci[8] = (C[0] * C[4] - C[1] * C[3]) / det;
-  // perpendicular widths w_a = 1 / |column a of C^-1|
-  double w[3];
-  for (int a = 0; a < 3; ++a)
-    w[a] = 1.0 / sqrt(Ci[a] * Ci[a] + Ci[3 + a] * Ci[3 + a] + Ci[6 + a] * Ci[6 + a]);
-  const double rc = desc->cutoff;
-  if (!(rc > 0.0) || !isfinite(rc) || rc >= 0.5 * fmin(w[0], fmin(w[1], w[2])))
-    return PME_EINVAL;
   pol_plan_s* pl = new (std::nothrow) pol_plan_s();
   if (!pl) return PME_ENOMEM;
   pl->desc = *desc;
-  long ncell = 1;
-  for (int a = 0; a < 3; ++a) {
-    int k = int(floor(w[a] / rc));
-    if (k < 1) k = 1;
-    if (k > 128) k = 128;
-    pl->g.nc[a] = k;
-    ncell *= k;
+  int rc0 = setup_cells(pl->cells, desc->box, desc->cutoff, desc->max_atoms);
+  if (rc0 != PME_OK) {
+    pol_free(pl);
+    return rc0;
   }
-  pl->g.ncell = int(ncell);
-  for (int k = 0; k < 9; ++k) { pl->g.C[k] = float(C[k]); pl->g.Ci[k] = float(Ci[k]); }
   const size_t m = size_t(desc->max_atoms);
   hipError_t e = hipSuccess;
   auto ok = [&](hipError_t r) { if (r != hipSuccess && e == hipSuccess) e = r; };
-  ok(hipMalloc(&pl->count, sizeof(int) * ncell));
-  ok(hipMalloc(&pl->start, sizeof(int) * (ncell + 1)));
-  ok(hipMalloc(&pl->cellof, sizeof(int) * m));
-  ok(hipMalloc(&pl->slot, sizeof(int) * m));
-  ok(hipMalloc(&pl->sorted, sizeof(int) * m));
   ok(hipMalloc(&pl->epart, sizeof(double) * pair_blocks(int(m))));
   ok(hipMalloc(&pl->scal, sizeof(double) * 8));
   ok(hipMalloc(&pl->vec, sizeof(float) * 8 * 3 * m));
@@ -513,7 +390,7 @@ int pol_real(pol_plan_t plan, void* stream, int32_t n, const float* pos, const f
              const float* mu, const float* pol, double* energy, float* dE_dpos, float* dE_dmu) {
   if (!check_common(plan, n, pos, pol)) return PME_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = build_cells(plan, s, n, pos);
+  hipError_t e = build_cells(plan->cells, s, n, pos);
   if (e != hipSuccess) return pol_hip_fail(e);
   PairArgs a = pair_args(plan, n, pos, q, mu, pol);
   a.o_pos = dE_dpos;
@@ -537,7 +414,7 @@ int pol_real_mixed(pol_plan_t plan, void* stream, int32_t n, const float* pos, c
                    const float* mu, const float* pol, const float* v_pos, float* g_mu) {
   if (!check_common(plan, n, pos, pol) || !g_mu || (n > 0 && !v_pos)) return PME_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = build_cells(plan, s, n, pos);
+  hipError_t e = build_cells(plan->cells, s, n, pos);
   if (e != hipSuccess) return pol_hip_fail(e);
   PairArgs a = pair_args(plan, n, pos, q, mu, pol);
   a.vpos = v_pos;

@@ -193,3 +193,15 @@ def triclinic_cell(seed: int = 7, n: int = 8):
     q -= q.mean()
     mu = rng.normal(0, 0.2, (n, 3))
     return Frame(pos=pos, q=q, mu=mu, box=box)
+
+
+def mlp_init(seed: int, layers=((64, 34), (64, 64), (16, 64)), last_scale: float = 0.1):
+    """Seeded initial parameters of a SiLU MLP, flat in the order W1 b1 W2 b2 W3 b3:
+    Glorot-uniform weights (the last layer scaled by `last_scale`), zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for k, (fo, fi) in enumerate(layers):
+        lim = math.sqrt(6.0 / (fi + fo)) * (last_scale if k == len(layers) - 1 else 1.0)
+        parts.append(rng.uniform(-lim, lim, (fo, fi)).reshape(-1))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts)
