@@ -273,13 +273,12 @@ __device__ __forceinline__ void slab_layout(const SlabArgs& a, float2* sm, float
 }
 
 // forward slab: rho[x] -> z R2C -> y FFT -> spec[x]
-__global__ void __launch_bounds__(kSlabThreads) k_slab_fwd(SlabArgs a) {
+__device__ __forceinline__ void slab_fwd_body(const SlabArgs& a, const int x) {
   extern __shared__ float2 sm[];
   const int Ny = a.ay.N, Nz = a.az.N, H = a.H;
   const int npairs = (Ny + 1) / 2;
   float2 *twz, *twy, *A, *B;
   slab_layout(a, sm, twz, twy, A, B);
-  const int x = blockIdx.x;
   Twiddles<kSlabThreads> tz, ty;
   tz.load(a.twz, Nz);
   ty.load(a.twy, Ny);
@@ -318,13 +317,12 @@ __global__ void __launch_bounds__(kSlabThreads) k_slab_fwd(SlabArgs a) {
 }
 
 // inverse slab: spec[x] -> y inverse FFT -> z C2R -> out[x]
-__global__ void __launch_bounds__(kSlabThreads) k_slab_inv(SlabArgs a) {
+__device__ __forceinline__ void slab_inv_body(const SlabArgs& a, const int x) {
   extern __shared__ float2 sm[];
   const int Ny = a.ay.N, Nz = a.az.N, H = a.H;
   const int npairs = (Ny + 1) / 2;
   float2 *twz, *twy, *A, *B;
   slab_layout(a, sm, twz, twy, A, B);
-  const int x = blockIdx.x;
   Twiddles<kSlabThreads> tz, ty;
   tz.load(a.twz, Nz);
   ty.load(a.twy, Ny);
@@ -429,7 +427,7 @@ struct XArgs {
 __device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) / 2) ? k - N : k; }
 
 // x pass fused with the influence function
-__global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
+__device__ __forceinline__ void fftx_body(const XArgs& a, const int blk) {
   extern __shared__ float2 sm[];
   __shared__ double red[8];
   const int Nx = a.N[0], Ny = a.N[1], Nz = a.N[2], H = a.H, kt = a.kt;
@@ -438,7 +436,7 @@ __global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
   float2* X = tw + Nx;
   float2* Y = X + kt * ps;
   const int ntk = (H + kt - 1) / kt;
-  const int y = blockIdx.x / ntk, kz0 = (blockIdx.x - y * ntk) * kt;
+  const int y = blk / ntk, kz0 = (blk - y * ntk) * kt;
   Twiddles<kFFTThreads> twr;
   twr.load(a.tw, Nx);
   const size_t xstride = size_t(Ny) * H;
@@ -514,7 +512,7 @@ __global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
   }
   if (a.epart) {
     const double s = block_sum(e_acc, red);
-    if (threadIdx.x == 0) a.epart[blockIdx.x] = s;
+    if (threadIdx.x == 0) a.epart[blk] = s;
   }
 }
 
@@ -523,6 +521,18 @@ FastDiv host_fastdiv(int d) {
   f.d = uint32_t(d);
   f.m = d <= 1 ? 0u : uint32_t(((uint64_t(1) << 32) + uint64_t(d) - 1) / uint64_t(d));
   return f;
+}
+
+__global__ void __launch_bounds__(kSlabThreads) k_slab_fwd(SlabArgs a) {
+  slab_fwd_body(a, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kSlabThreads) k_slab_inv(SlabArgs a) {
+  slab_inv_body(a, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
+  fftx_body(a, blockIdx.x);
 }
 
 }  // namespace

@@ -124,11 +124,12 @@ __device__ __forceinline__ FastDiv make_fastdiv(int d) {
 // halo, and the occupied-slot counts of the tile's own bins (s_off[0..nown)) and of
 // the overflow list (s_off[nown]); all loads are issued before the first wait.
 template <int P, bool TWO>
-__device__ __forceinline__ void stage_tile(const GArgs& a, float* sm, int (&t0)[3], int (&T)[3],
-                                           int (&E)[3], int* s_off, int* s_bin, int& nown) {
+__device__ __forceinline__ void stage_tile(const GArgs& a, int tile, float* sm, int (&t0)[3],
+                                           int (&T)[3], int (&E)[3], int* s_off, int* s_bin,
+                                           int& nown) {
   constexpr int lo = (P - 1) / 2;
   {
-    int t = blockIdx.x;
+    int t = tile;
     const int tz = t % a.nt[2];
     t /= a.nt[2];
     const int ty = t % a.nt[1];
@@ -239,15 +240,15 @@ __device__ __forceinline__ const float4* item_record(const GArgs& a, int item, i
 }
 
 template <int P>
-__global__ void __launch_bounds__(256) k_gather(GArgs a) {
+__device__ __forceinline__ void gather_body(const GArgs& a, const int tile) {
   extern __shared__ float sm[];
   __shared__ int s_off[kMaxOwnBins + 2];
   __shared__ int s_bin[kMaxOwnBins + 1];
   constexpr int APW = 64 / P;
   const Cell c = cell_from_box(a.box);
-  if (blockIdx.x == 0 && a.energy) finalize_energy(a, c);
+  if (tile == 0 && a.energy) finalize_energy(a, c);
   int t0[3], T[3], E[3], nown;
-  stage_tile<P, false>(a, sm, t0, T, E, s_off, s_bin, nown);
+  stage_tile<P, false>(a, tile, sm, t0, T, E, s_off, s_bin, nown);
   const int total = s_off[nown + 1];
   float J[3][3];
   jacobian(c, a.N, J);
@@ -334,14 +335,14 @@ __global__ void __launch_bounds__(256) k_gather(GArgs a) {
 }
 
 template <int P>
-__global__ void __launch_bounds__(256) k_gather_hvp(GArgs a) {
+__device__ __forceinline__ void gather_hvp_body(const GArgs& a, const int tile) {
   extern __shared__ float sm[];
   __shared__ int s_off[kMaxOwnBins + 2];
   __shared__ int s_bin[kMaxOwnBins + 1];
   constexpr int APW = 64 / P;
   const Cell c = cell_from_box(a.box);
   int t0[3], T[3], E[3], nown;
-  stage_tile<P, true>(a, sm, t0, T, E, s_off, s_bin, nown);
+  stage_tile<P, true>(a, tile, sm, t0, T, E, s_off, s_bin, nown);
   const int EV = E[0] * E[1] * E[2];
   const int total = s_off[nown + 1];
   float J[3][3];
@@ -509,6 +510,16 @@ __global__ void __launch_bounds__(256) k_gather_hvp(GArgs a) {
       }
     }
   }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_gather(GArgs a) {
+  gather_body<P>(a, blockIdx.x);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_gather_hvp(GArgs a) {
+  gather_hvp_body<P>(a, blockIdx.x);
 }
 
 template <bool HVP>

@@ -52,6 +52,7 @@ struct BinArgs {
   long long ovf_base;      // record index of the overflow list
   double* spart;
   int* status;
+  int nblk;            // workgroups of this binning (bin_blocks(n))
 };
 
 __device__ __forceinline__ float3 ld3(const float* p, int i) {
@@ -66,18 +67,18 @@ __device__ __forceinline__ float3 jmul(const float (&J)[3][3], float3 v) {
 }
 
 template <int P, bool TANGENT>
-__global__ void __launch_bounds__(256) k_bin(BinArgs a) {
+__device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
   __shared__ double red[8];
   __shared__ unsigned s_cmax;
   if (threadIdx.x == 0) s_cmax = 0u;
   // clear the other counter set for the next binning
-  for (int e = blockIdx.x * 256 + threadIdx.x; e < a.nbins; e += gridDim.x * 256) a.count_other[e] = 0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  for (int e = blk * 256 + threadIdx.x; e < a.nbins; e += a.nblk * 256) a.count_other[e] = 0;
+  if (blk == 0 && threadIdx.x == 0) {
     *a.ovf_other = 0;
     *a.cmax_other = 0u;
   }
   __syncthreads();
-  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int i = blk * 256 + threadIdx.x;
   const Cell c = cell_from_box(a.box);
   double sq = 0.0, smu = 0.0;
   if (i < a.n) {
@@ -143,9 +144,26 @@ __global__ void __launch_bounds__(256) k_bin(BinArgs a) {
     const double s1 = block_sum(sq, red);
     const double s2 = block_sum(smu, red);
     if (threadIdx.x == 0) {
-      a.spart[2 * blockIdx.x] = s1;
-      a.spart[2 * blockIdx.x + 1] = s2;
+      a.spart[2 * blk] = s1;
+      a.spart[2 * blk + 1] = s2;
     }
+  }
+}
+
+template <int P, bool TANGENT>
+__global__ void __launch_bounds__(256) k_bin(BinArgs a) {
+  bin_body<P, TANGENT>(a, blockIdx.x);
+}
+
+// Batched binning: work item (box, workgroup of the box), per-box arguments in
+// device memory; workgroups loop over the items.
+template <int P, bool TANGENT>
+__global__ void __launch_bounds__(256) k_bin_batch(const BinArgs* args, const int2* items,
+                                                   int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    bin_body<P, TANGENT>(args[w.x], w.y);
+    __syncthreads();
   }
 }
 
@@ -216,8 +234,7 @@ __device__ __forceinline__ unsigned long long to_fixed(float v) {
 }
 
 template <int P, int DEG>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
-k_spread(SpreadArgs a) {
+__device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_id) {
   constexpr int NC = (DEG == 1) ? 4 : 10;
   constexpr int D = DEG;                      // highest weight derivative needed
   constexpr int NW = 3 * (D + 1) * P;         // weights w[axis][d][j]
@@ -238,7 +255,7 @@ k_spread(SpreadArgs a) {
   const int tid = threadIdx.x;
   int t0[3], T[3];
   {
-    int t = blockIdx.x;
+    int t = tile_id;
     const int tz = t % a.nt[2];
     t /= a.nt[2];
     const int ty = t % a.nt[1];
@@ -481,6 +498,23 @@ k_spread(SpreadArgs a) {
   }
 }
 
+template <int P, int DEG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+k_spread(SpreadArgs a) {
+  spread_body<P, DEG>(a, blockIdx.x);
+}
+
+// Batched spread: work item (box, tile of the box).
+template <int P, int DEG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
+k_spread_batch(const SpreadArgs* args, const int2* items, int nitems) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const int2 w = items[it];
+    spread_body<P, DEG>(args[w.x], w.y);
+    __syncthreads();
+  }
+}
+
 template <bool TANGENT>
 hipError_t bin_dispatch(int p, dim3 g, hipStream_t s, const BinArgs& a, const LaunchEvents* ev) {
   switch (p) {
@@ -530,6 +564,7 @@ hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const flo
   a.rec = d.rec; a.ovf_base = d.ovf_base;
   a.spart = self_sums ? d.spart : nullptr;
   a.status = d.status;
+  a.nblk = bin_blocks(n);
   const dim3 g(bin_blocks(n));
   return tangent ? bin_dispatch<true>(d.p, g, s, a, ev) : bin_dispatch<false>(d.p, g, s, a, ev);
 }
