@@ -83,6 +83,9 @@ typedef struct {
     double  influence_power;  /* gamma of Eq. influence, >= 0 (1 = default,
                                  0 = no assignment deconvolution)                 */
     double  prefactor;        /* energy unit factor (1, or 14.3996454784 for eV)  */
+    int32_t tile[3];          /* spread/gather tile target per axis in mesh points
+                                 (0 = default 8, 8, 16); rounded to the atom-bin
+                                 size and shrunk to fit LDS (set by autotuning)   */
 } pme_desc_t;
 
 /* Eq. mesh_target, N_a = ceil(2 |a_a| / spacing + 1), mapped by `strategy`
@@ -149,6 +152,57 @@ const char* pme_last_hip_error(void);
  * For inspection and tests; valid until the plan is destroyed. */
 const float* pme_plan_phi(pme_plan_t plan);
 const float* pme_plan_rho(pme_plan_t plan);
+
+/* ---- batches of boxes ---------------------------------------------------
+ * Many independent cells of uneven atom count and mesh (e.g. a training batch)
+ * evaluated together: every kernel kind runs once for all boxes, over a list of
+ * (box, work item) pairs, instead of once per box.  Per-atom arrays are packed:
+ * the atoms of box b occupy [off_b, off_b + n_b), off = exclusive prefix sum of
+ * n_atoms; cells are packed as [nbox][9] doubles and energies as [nbox][3].
+ * Results equal those of one plan per box, bit for bit (same kernels, same
+ * tiles).  A batch needs one order p for all boxes and meshes whose y-z planes
+ * fit in LDS (at most about 130 x 130). */
+typedef struct pme_batch_s* pme_batch_t;
+
+/* descs[b] describes box b (its flags are ignored: the backward always reuses
+ * the potential of the preceding pme_batch_forward); n_atoms[b] >= 0 is its atom
+ * count.  PME_EORDER if the orders differ, PME_EMESH if a mesh does not fit. */
+int pme_batch_create(const pme_desc_t* descs, int32_t nbox, const int32_t* n_atoms,
+                     pme_batch_t* out);
+void pme_batch_destroy(pme_batch_t batch);
+
+/* pme_forward of every box (packed arrays as above; NULL outputs skipped). */
+int pme_batch_forward(pme_batch_t batch, void* stream, const float* pos, const float* q,
+                      const float* mu, const double* box, double* energy, float* dE_dpos,
+                      float* dE_dq, float* dE_dmu);
+
+/* pme_backward of every box with the potentials of the last pme_batch_forward
+ * (same pos, q, mu, box). */
+int pme_batch_backward(pme_batch_t batch, void* stream, const float* pos, const float* q,
+                       const float* mu, const double* box, const float* v_pos, const float* v_q,
+                       const float* v_mu, float* g_pos, float* g_q, float* g_mu);
+
+/* The buffers of one captured training step (all packed, device). */
+typedef struct {
+    const float* pos; const float* q; const float* mu; const double* box;
+    double* energy; float* dE_dpos; float* dE_dq; float* dE_dmu;      /* forward        */
+    const float* v_pos; const float* v_q; const float* v_mu;          /* generic H v    */
+    float* g_pos; float* g_q; float* g_mu;
+    const float* vf_pos;                                              /* force-loss H v */
+    float* gf_pos; float* gf_q; float* gf_mu;                         /* (v_q = v_mu = 0) */
+} pme_batch_step_t;
+
+/* Capture forward + Hessian-vector product + force-loss double backward of the
+ * whole batch into one HIP graph owned by the batch (replacing any previous
+ * one); the buffer addresses are fixed at capture, their contents are read at
+ * every replay.  Capture runs on a stream of the batch's own. */
+int pme_batch_capture(pme_batch_t batch, const pme_batch_step_t* step);
+
+/* Launch the captured graph on `stream`. */
+int pme_batch_replay(pme_batch_t batch, void* stream);
+
+/* pme_status over every box of the batch. */
+int pme_batch_status(pme_batch_t batch, void* stream);
 
 /* ---- launch timing (measurement support) ------------------------------ */
 /* Kernel kinds that pme_plan_timer can bracket.  Each kind is one launch (or, in

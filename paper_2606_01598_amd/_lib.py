@@ -34,7 +34,9 @@ EXPORTS = ("pme_mesh_dims", "pme_plan_create", "pme_plan_destroy", "pme_plan_wor
            "pme_plan_phi", "pme_plan_rho", "pme_plan_timer", "pme_plan_timer_read",
            "pol_plan_create", "pol_plan_destroy", "pol_real", "pol_real_mixed", "pol_model",
            "pol_scf", "dip_plan_create", "dip_plan_destroy", "dip_features", "dip_forward",
-           "dip_backward", "dip_loss", "dip_adam")
+           "dip_backward", "dip_loss", "dip_adam", "pme_batch_create", "pme_batch_destroy",
+           "pme_batch_forward", "pme_batch_backward", "pme_batch_capture", "pme_batch_replay",
+           "pme_batch_status")
 
 DIP_NFEAT, DIP_NCH, DIP_HIDDEN, DIP_NPARAM = 34, 16, 64, 7440
 
@@ -50,7 +52,14 @@ class PMEDesc(ctypes.Structure):
                 ("flags", ctypes.c_int32),
                 ("alpha", ctypes.c_double),
                 ("influence_power", ctypes.c_double),
-                ("prefactor", ctypes.c_double)]
+                ("prefactor", ctypes.c_double),
+                ("tile", ctypes.c_int32 * 3)]
+
+
+class BatchStep(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_void_p) for name in (
+        "pos", "q", "mu", "box", "energy", "dE_dpos", "dE_dq", "dE_dmu", "v_pos", "v_q", "v_mu",
+        "g_pos", "g_q", "g_mu", "vf_pos", "gf_pos", "gf_q", "gf_mu")]
 
 
 class PolDesc(ctypes.Structure):
@@ -132,6 +141,21 @@ def load():
     lib.pol_scf.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, vp,
                             ctypes.POINTER(i32), ctypes.POINTER(f64)]
     lib.pol_scf.restype = ctypes.c_int
+    lib.pme_batch_create.argtypes = [ctypes.POINTER(PMEDesc), i32, ctypes.POINTER(i32),
+                                     ctypes.POINTER(vp)]
+    lib.pme_batch_create.restype = ctypes.c_int
+    lib.pme_batch_destroy.argtypes = [vp]
+    lib.pme_batch_destroy.restype = None
+    lib.pme_batch_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pme_batch_forward.restype = ctypes.c_int
+    lib.pme_batch_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pme_batch_backward.restype = ctypes.c_int
+    lib.pme_batch_capture.argtypes = [vp, ctypes.POINTER(BatchStep)]
+    lib.pme_batch_capture.restype = ctypes.c_int
+    lib.pme_batch_replay.argtypes = [vp, vp]
+    lib.pme_batch_replay.restype = ctypes.c_int
+    lib.pme_batch_status.argtypes = [vp, vp]
+    lib.pme_batch_status.restype = ctypes.c_int
     lib.dip_plan_create.argtypes = [ctypes.POINTER(DipDesc), ctypes.POINTER(vp)]
     lib.dip_plan_create.restype = ctypes.c_int
     lib.dip_plan_destroy.argtypes = [vp]

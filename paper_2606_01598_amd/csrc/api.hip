@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "../../include/pme.h"
 #include "kernels.h"
@@ -178,6 +179,8 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
       !isfinite(desc->influence_power) || !isfinite(desc->prefactor))
     return PME_EALPHA;
   if (desc->max_atoms < 1 || (desc->flags & ~PME_F_KEEP_PHI)) return PME_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (desc->tile[a] < 0 || desc->tile[a] > 1024) return PME_EINVAL;
 
   pme_plan_s* pl = new (std::nothrow) pme_plan_s();
   if (!pl) return PME_ENOMEM;
@@ -196,9 +199,12 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   d.prefactor = desc->prefactor;
   const long M = long(d.N[0]) * d.N[1] * d.N[2];
 
-  // bins of B cells and mesh tiles of T = k B cells (targets 8 x 8 x 16)
+  // bins of B cells and mesh tiles of T = k B cells (targets 8 x 8 x 16 unless the
+  // descriptor sets them)
   long nbins = 1;
-  const int target[3] = {8, 8, 16};
+  int target[3] = {8, 8, 16};
+  for (int a = 0; a < 3; ++a)
+    if (desc->tile[a] > 0) target[a] = desc->tile[a];
   for (int a = 0; a < 3; ++a) {
     d.B[a] = pick_bin(d.N[a]);
     d.nb[a] = d.N[a] / d.B[a];
@@ -455,6 +461,205 @@ int pme_status(pme_plan_t plan, void* stream) {
     return PME_ENONFINITE;
   }
   return PME_OK;
+}
+
+}  // extern "C"
+
+// ---- batches ------------------------------------------------------------
+
+struct pme_batch_s {
+  int nbox = 0;
+  std::vector<pme_plan_s*> plans;
+  std::vector<int> n, off;
+  pme::SpreadBatch sp;
+  pme::FFTBatch ff;
+  pme::GatherBatch ga;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int next_set = 1;     // counter set of the next backward (alternates after a forward)
+};
+
+namespace {
+
+void free_batch(pme_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  pme::spread_batch_free(b->sp);
+  pme::fft_batch_free(b->ff);
+  pme::gather_batch_free(b->ga);
+  for (pme_plan_s* p : b->plans)
+    if (p) free_plan(p);
+  delete b;
+}
+
+// forward of every box: counters of set 0 cleared, binning (set 0), spread,
+// convolution with energy, gather; backward: set 1
+int batch_forward(pme_batch_s* b, hipStream_t s, const pme::BatchIO& io) {
+  hipError_t e;
+  if ((e = pme::launch_clear_batch(b->sp, s)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_bin_batch(b->sp, s, 0, false, io, io.energy != nullptr)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_spread_batch(b->sp, s, 0, false)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_convolve_batch(b->ff, s, io.box, true, io.energy != nullptr)) !=
+      hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_gather_batch(b->ga, s, 0, false, io)) != hipSuccess) return hip_fail(e);
+  return PME_OK;
+}
+
+// Hessian-vector product of every box; `set` alternates 1, 0, 1, ... over the
+// backward calls that follow one forward
+int batch_backward(pme_batch_s* b, hipStream_t s, int set, const pme::BatchIO& io) {
+  hipError_t e;
+  if ((e = pme::launch_bin_batch(b->sp, s, set, true, io, false)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_spread_batch(b->sp, s, set, true)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_convolve_batch(b->ff, s, io.box, false, false)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_gather_batch(b->ga, s, set, true, io)) != hipSuccess) return hip_fail(e);
+  return PME_OK;
+}
+
+pme::BatchIO fwd_io(const float* pos, const float* q, const float* mu, const double* box,
+                    double* energy, float* gp, float* gq, float* gm) {
+  pme::BatchIO io;
+  io.pos = pos; io.q = q; io.mu = mu; io.box = box; io.energy = energy;
+  io.o_pos = gp; io.o_q = gq; io.o_mu = gm;
+  return io;
+}
+
+pme::BatchIO bwd_io(const float* pos, const float* q, const float* mu, const double* box,
+                    const float* vp, const float* vq, const float* vm, float* gp, float* gq,
+                    float* gm) {
+  pme::BatchIO io = fwd_io(pos, q, mu, box, nullptr, gp, gq, gm);
+  io.v_pos = vp; io.v_q = vq; io.v_mu = vm;
+  return io;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pme_batch_create(const pme_desc_t* descs, int32_t nbox, const int32_t* n_atoms,
+                     pme_batch_t* out) {
+  if (!descs || !n_atoms || !out || nbox < 1) return PME_EINVAL;
+  *out = nullptr;
+  for (int b = 0; b < nbox; ++b) {
+    if (n_atoms[b] < 0) return PME_EINVAL;
+    if (descs[b].order != descs[0].order) return PME_EORDER;
+  }
+  pme_batch_s* bt = new (std::nothrow) pme_batch_s();
+  if (!bt) return PME_ENOMEM;
+  bt->nbox = nbox;
+  bt->plans.assign(nbox, nullptr);
+  bt->n.resize(nbox);
+  bt->off.resize(nbox);
+  long long acc = 0;
+  std::vector<DevPlan> dp(nbox);
+  for (int b = 0; b < nbox; ++b) {
+    pme_desc_t d = descs[b];
+    d.flags = PME_F_KEEP_PHI;
+    d.max_atoms = n_atoms[b] > 0 ? n_atoms[b] : 1;
+    const int rc = pme_plan_create(&d, &bt->plans[b]);
+    if (rc != PME_OK) {
+      free_batch(bt);
+      return rc;
+    }
+    if (!bt->plans[b]->d.slab) {
+      free_batch(bt);
+      return PME_EMESH;
+    }
+    bt->n[b] = n_atoms[b];
+    bt->off[b] = int(acc);
+    acc += n_atoms[b];
+    if (acc > 0x7fffffffLL) {
+      free_batch(bt);
+      return PME_EINVAL;
+    }
+    dp[b] = bt->plans[b]->d;
+  }
+  hipError_t e = pme::spread_batch_build(dp.data(), bt->n.data(), bt->off.data(), nbox, bt->sp);
+  if (e == hipSuccess) e = pme::fft_batch_build(dp.data(), nbox, bt->ff);
+  if (e == hipSuccess)
+    e = pme::gather_batch_build(dp.data(), bt->n.data(), bt->off.data(), nbox, bt->ga);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_batch(bt);
+    return e == hipErrorOutOfMemory ? PME_ENOMEM : hip_fail(e);
+  }
+  *out = bt;
+  return PME_OK;
+}
+
+void pme_batch_destroy(pme_batch_t batch) {
+  if (!batch) return;
+  (void)hipDeviceSynchronize();
+  free_batch(batch);
+}
+
+int pme_batch_forward(pme_batch_t batch, void* stream, const float* pos, const float* q,
+                      const float* mu, const double* box, double* energy, float* dE_dpos,
+                      float* dE_dq, float* dE_dmu) {
+  if (!batch || !box || !pos) return PME_EINVAL;
+  batch->next_set = 1;
+  return batch_forward(batch, static_cast<hipStream_t>(stream),
+                       fwd_io(pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu));
+}
+
+int pme_batch_backward(pme_batch_t batch, void* stream, const float* pos, const float* q,
+                       const float* mu, const double* box, const float* v_pos, const float* v_q,
+                       const float* v_mu, float* g_pos, float* g_q, float* g_mu) {
+  if (!batch || !box || !pos) return PME_EINVAL;
+  const int set = batch->next_set;
+  batch->next_set ^= 1;
+  return batch_backward(batch, static_cast<hipStream_t>(stream), set,
+                        bwd_io(pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q, g_mu));
+}
+
+int pme_batch_capture(pme_batch_t batch, const pme_batch_step_t* st) {
+  if (!batch || !st || !st->pos || !st->box) return PME_EINVAL;
+  if (batch->exec) { (void)hipGraphExecDestroy(batch->exec); batch->exec = nullptr; }
+  if (batch->graph) { (void)hipGraphDestroy(batch->graph); batch->graph = nullptr; }
+  hipStream_t s = batch->cap;
+  hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return hip_fail(e);
+  int rc = batch_forward(batch, s, fwd_io(st->pos, st->q, st->mu, st->box, st->energy,
+                                          st->dE_dpos, st->dE_dq, st->dE_dmu));
+  if (rc == PME_OK)
+    rc = batch_backward(batch, s, 1, bwd_io(st->pos, st->q, st->mu, st->box, st->v_pos, st->v_q,
+                                            st->v_mu, st->g_pos, st->g_q, st->g_mu));
+  if (rc == PME_OK)
+    rc = batch_backward(batch, s, 0, bwd_io(st->pos, st->q, st->mu, st->box, st->vf_pos, nullptr,
+                                            nullptr, st->gf_pos, st->gf_q, st->gf_mu));
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(s, &g);
+  if (rc != PME_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  batch->graph = g;
+  e = hipGraphInstantiate(&batch->exec, g, nullptr, nullptr, 0);
+  return e == hipSuccess ? PME_OK : hip_fail(e);
+}
+
+int pme_batch_replay(pme_batch_t batch, void* stream) {
+  if (!batch || !batch->exec) return PME_EINVAL;
+  const hipError_t e = hipGraphLaunch(batch->exec, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? PME_OK : hip_fail(e);
+}
+
+int pme_batch_status(pme_batch_t batch, void* stream) {
+  if (!batch) return PME_EINVAL;
+  int worst = PME_OK;
+  for (pme_plan_s* p : batch->plans) {
+    const int rc = pme_status(p, stream);
+    if (rc != PME_OK && worst == PME_OK) worst = rc;
+  }
+  return worst;
 }
 
 }  // extern "C"

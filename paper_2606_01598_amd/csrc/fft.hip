@@ -19,6 +19,8 @@
 // Nyquist bins of a non-orthogonal cell use the mean of g over the bin and its
 // Hermitian partner, which makes the half-spectrum product equal the real part of
 // the full complex product (the real-to-complex semantics).
+#include <vector>
+
 #include "../../include/pme.h"
 #include "kernels.h"
 #include "pme_common.h"
@@ -427,7 +429,8 @@ struct XArgs {
 __device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) / 2) ? k - N : k; }
 
 // x pass fused with the influence function
-__device__ __forceinline__ void fftx_body(const XArgs& a, const int blk) {
+__device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const double* box,
+                                          double* epart) {
   extern __shared__ float2 sm[];
   __shared__ double red[8];
   const int Nx = a.N[0], Ny = a.N[1], Nz = a.N[2], H = a.H, kt = a.kt;
@@ -457,7 +460,7 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk) {
   float2* Z = lds_fft(X, Y, kt, ps, a.ax, tw, -1.0f);
   float2* W = (Z == X) ? Y : X;
   // reciprocal metric M_ab = b_a . b_b, b_a = 2 pi C^-1[:, a]
-  const Cell c = cell_from_box(a.box);
+  const Cell c = cell_from_box(box);
   float M[3][3];
 #pragma unroll
   for (int p = 0; p < 3; ++p)
@@ -510,9 +513,9 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk) {
     const int kz = kz0 + l;
     if (kz < H) base[xx * xstride + kz] = R[l * ps + xx];
   }
-  if (a.epart) {
+  if (epart) {
     const double s = block_sum(e_acc, red);
-    if (threadIdx.x == 0) a.epart[blk] = s;
+    if (threadIdx.x == 0) epart[blk] = s;
   }
 }
 
@@ -532,14 +535,44 @@ __global__ void __launch_bounds__(kSlabThreads) k_slab_inv(SlabArgs a) {
 }
 
 __global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
-  fftx_body(a, blockIdx.x);
+  fftx_body(a, blockIdx.x, a.box, a.epart);
+}
+
+// Batched passes: work item (box, x-plane) or (box, x-pass workgroup); per-box
+// argument templates in device memory; workgroups loop over the items.
+__global__ void __launch_bounds__(kSlabThreads) k_slab_fwd_batch(const SlabArgs* args,
+                                                                 const int2* items, int n) {
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int2 w = items[it];
+    slab_fwd_body(args[w.x], w.y);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kSlabThreads) k_slab_inv_batch(const SlabArgs* args,
+                                                                 const int2* items, int n) {
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int2 w = items[it];
+    slab_inv_body(args[w.x], w.y);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kFFTThreads) k_fftx_batch(const XArgs* args, const int2* items,
+                                                            int n, const double* box, int energy) {
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int2 w = items[it];
+    const XArgs& a = args[w.x];
+    fftx_body(a, w.y, box + 9 * w.x, energy ? a.epart : nullptr);
+    __syncthreads();
+  }
 }
 
 }  // namespace
 
-hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
-                           bool energy, KTimer* tm) {
-  hipError_t err;
+namespace {
+
+XArgs make_x_args(const DevPlan& d, const double* box, bool energy) {
   XArgs x;
   x.ax = d.ax[0]; x.tw = d.twiddle[0];
   for (int k = 0; k < 3; ++k) x.N[k] = d.N[k];
@@ -547,7 +580,82 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   x.dcx = d.deconv[0]; x.dcy = d.deconv[1]; x.dcz = d.deconv[2];
   x.alpha = float(d.alpha);
   x.epart = energy ? d.epart : nullptr;
-  const size_t xsh = sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1));
+  return x;
+}
+
+size_t x_lds(const DevPlan& d) { return sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1)); }
+
+SlabArgs make_slab_args(const DevPlan& d, float* out) {
+  SlabArgs sa;
+  sa.ay = d.ax[1]; sa.az = d.ax[2]; sa.twy = d.twiddle[1]; sa.twz = d.twiddle[2];
+  sa.H = d.H; sa.nzd = host_fastdiv(d.N[2]); sa.hd = host_fastdiv(d.H);
+  sa.src = d.rho; sa.spec = d.spec; sa.dst = out;
+  return sa;
+}
+
+inline dim3 fft_batch_grid(int items, int cap) {
+  return dim3(items < cap ? (items > 0 ? items : 1) : cap);
+}
+
+}  // namespace
+
+hipError_t fft_batch_build(const DevPlan* plans, int nbox, FFTBatch& t) {
+  t = FFTBatch();
+  std::vector<SlabArgs> s0(nbox), s1(nbox);
+  std::vector<XArgs> xa(nbox);
+  std::vector<int2> si, xi;
+  for (int b = 0; b < nbox; ++b) {
+    const DevPlan& d = plans[b];
+    if (!d.slab) return hipErrorInvalidValue;
+    s0[b] = make_slab_args(d, d.phi);
+    s1[b] = make_slab_args(d, d.rho);
+    xa[b] = make_x_args(d, nullptr, true);
+    for (int x = 0; x < d.N[0]; ++x) si.push_back(make_int2(b, x));
+    for (int k = 0; k < fftx_blocks(d); ++k) xi.push_back(make_int2(b, k));
+    if (d.slab_lds > t.slab_lds) t.slab_lds = d.slab_lds;
+    if (x_lds(d) > t.x_lds) t.x_lds = x_lds(d);
+  }
+  hipError_t e = hipSuccess;
+  auto ok = [&](hipError_t r) { if (r != hipSuccess && e == hipSuccess) e = r; };
+  ok(upload(&t.slab[0], s0.data(), sizeof(SlabArgs) * nbox));
+  ok(upload(&t.slab[1], s1.data(), sizeof(SlabArgs) * nbox));
+  ok(upload(&t.x, xa.data(), sizeof(XArgs) * nbox));
+  ok(upload(reinterpret_cast<void**>(&t.slab_items), si.data(), sizeof(int2) * si.size()));
+  ok(upload(reinterpret_cast<void**>(&t.x_items), xi.data(), sizeof(int2) * xi.size()));
+  t.n_slab_items = int(si.size());
+  t.n_x_items = int(xi.size());
+  if (e == hipSuccess) e = enable_slab_lds(t.slab_lds);
+  return e;
+}
+
+void fft_batch_free(FFTBatch& t) {
+  void* ptrs[] = {t.slab[0], t.slab[1], t.x, t.slab_items, t.x_items};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  t = FFTBatch();
+}
+
+hipError_t launch_convolve_batch(const FFTBatch& t, hipStream_t s, const double* box, bool to_phi,
+                                 bool energy) {
+  const SlabArgs* sa = static_cast<const SlabArgs*>(t.slab[to_phi ? 0 : 1]);
+  hipLaunchKernelGGL(k_slab_fwd_batch, fft_batch_grid(t.n_slab_items, 512), dim3(kSlabThreads),
+                     t.slab_lds, s, sa, t.slab_items, t.n_slab_items);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fftx_batch, fft_batch_grid(t.n_x_items, 2048), dim3(kFFTThreads), t.x_lds,
+                     s, static_cast<const XArgs*>(t.x), t.x_items, t.n_x_items, box,
+                     energy ? 1 : 0);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_slab_inv_batch, fft_batch_grid(t.n_slab_items, 512), dim3(kSlabThreads),
+                     t.slab_lds, s, sa, t.slab_items, t.n_slab_items);
+  return hipGetLastError();
+}
+
+hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
+                           bool energy, KTimer* tm) {
+  hipError_t err;
+  const XArgs x = make_x_args(d, box, energy);
+  const size_t xsh = x_lds(d);
   // timed kinds: a kind spanning two launches records its start with the first
   // and its stop with the second
   const LaunchEvents* er = tm ? tm->next(PME_K_FFT_R2C) : nullptr;
@@ -558,10 +666,7 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   if (ei) { ei0.start = ei->start; ei1.stop = ei->stop; }
 
   if (d.slab) {
-    SlabArgs sa;
-    sa.ay = d.ax[1]; sa.az = d.ax[2]; sa.twy = d.twiddle[1]; sa.twz = d.twiddle[2];
-    sa.H = d.H; sa.nzd = host_fastdiv(d.N[2]); sa.hd = host_fastdiv(d.H);
-    sa.src = d.rho; sa.spec = d.spec; sa.dst = out;
+    const SlabArgs sa = make_slab_args(d, out);
     launch_k(er, k_slab_fwd, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     launch_k(ex, k_fftx_fused, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
@@ -600,11 +705,19 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
 }
 
 hipError_t enable_slab_lds(size_t bytes) {
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_slab_fwd),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(k_slab_inv),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  // The limit is per kernel, not per plan: raise it to the largest slab any plan
+  // may use, so that a later plan with smaller planes does not lower it.
+  if (bytes > size_t(kSlabLdsMax)) return hipErrorInvalidValue;
+  const void* fns[] = {reinterpret_cast<const void*>(k_slab_fwd),
+                       reinterpret_cast<const void*>(k_slab_inv),
+                       reinterpret_cast<const void*>(k_slab_fwd_batch),
+                       reinterpret_cast<const void*>(k_slab_inv_batch)};
+  for (const void* f : fns) {
+    const hipError_t e =
+        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kSlabLdsMax);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace pme

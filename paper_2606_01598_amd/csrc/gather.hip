@@ -24,6 +24,8 @@
 //     r_bar  = (1/V) J^T [q P1 + P2 d + v_q S1 + S2 w + S3(d, v, .)]
 // where P_k are the order-k derivative sums of psi, S_k those of phi,
 // d = J mu, v = J v_r, w = J (v_mu + q v_r).
+#include <vector>
+
 #include "kernels.h"
 #include "pme_common.h"
 
@@ -61,6 +63,7 @@ struct GArgs {
   long long ovf_base;      // record index of the overflow list
   int T[3];
   int nt[3];
+  int off;                 // batches: offset of the box's atoms in the packed arrays
 };
 
 constexpr int kMaxOwnBins = 256;
@@ -522,6 +525,32 @@ __global__ void __launch_bounds__(256) k_gather_hvp(GArgs a) {
   gather_hvp_body<P>(a, blockIdx.x);
 }
 
+// Batched gathers: work item (box, tile), per-box argument templates completed
+// with the call's packed arrays; workgroups loop over the items.
+template <int P, bool HVP>
+__global__ void __launch_bounds__(256) k_gather_batch(const GArgs* args, const int2* items, int n,
+                                                      BatchIO io) {
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int2 w = items[it];
+    GArgs a = args[w.x];
+    const size_t o = size_t(a.off);
+    a.pos = io.pos + 3 * o;
+    a.q = io.q ? io.q + o : nullptr;
+    a.mu = io.mu ? io.mu + 3 * o : nullptr;
+    a.box = io.box + 9 * w.x;
+    a.v_pos = io.v_pos ? io.v_pos + 3 * o : nullptr;
+    a.v_q = io.v_q ? io.v_q + o : nullptr;
+    a.v_mu = io.v_mu ? io.v_mu + 3 * o : nullptr;
+    a.o_pos = io.o_pos ? io.o_pos + 3 * o : nullptr;
+    a.o_q = io.o_q ? io.o_q + o : nullptr;
+    a.o_mu = io.o_mu ? io.o_mu + 3 * o : nullptr;
+    a.energy = io.energy ? io.energy + 3 * w.x : nullptr;
+    if (HVP) gather_hvp_body<P>(a, w.y);
+    else gather_body<P>(a, w.y);
+    __syncthreads();
+  }
+}
+
 template <bool HVP>
 hipError_t gather_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const GArgs& a,
                            const LaunchEvents* ev) {
@@ -541,6 +570,7 @@ hipError_t gather_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const GArgs&
 GArgs base_args(const DevPlan& d, int set, int n, const float* pos, const float* q,
                 const float* mu, const double* box) {
   GArgs a{};
+  a.off = 0;
   a.n = n; a.pos = pos; a.q = q; a.mu = mu; a.box = box;
   for (int k = 0; k < 3; ++k) {
     a.N[k] = d.N[k]; a.B[k] = d.B[k]; a.nb[k] = d.nb[k]; a.T[k] = d.T[k]; a.nt[k] = d.nt[k];
@@ -556,7 +586,70 @@ size_t region_bytes(const DevPlan& d, int fields) {
   return sizeof(float) * size_t(fields) * (d.T[0] + d.p - 1) * (d.T[1] + d.p - 1) * (d.T[2] + d.p - 1);
 }
 
+template <bool HVP>
+hipError_t gather_batch_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const GArgs* args,
+                                 const int2* it, int n, const BatchIO& io) {
+  switch (p) {
+    case 1: hipLaunchKernelGGL((k_gather_batch<1, HVP>), g, dim3(256), sh, s, args, it, n, io); break;
+    case 2: hipLaunchKernelGGL((k_gather_batch<2, HVP>), g, dim3(256), sh, s, args, it, n, io); break;
+    case 3: hipLaunchKernelGGL((k_gather_batch<3, HVP>), g, dim3(256), sh, s, args, it, n, io); break;
+    case 4: hipLaunchKernelGGL((k_gather_batch<4, HVP>), g, dim3(256), sh, s, args, it, n, io); break;
+    case 5: hipLaunchKernelGGL((k_gather_batch<5, HVP>), g, dim3(256), sh, s, args, it, n, io); break;
+    case 6: hipLaunchKernelGGL((k_gather_batch<6, HVP>), g, dim3(256), sh, s, args, it, n, io); break;
+    case 7: hipLaunchKernelGGL((k_gather_batch<7, HVP>), g, dim3(256), sh, s, args, it, n, io); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t gather_batch_build(const DevPlan* plans, const int* n, const int* off, int nbox,
+                              GatherBatch& t) {
+  t = GatherBatch();
+  t.p = nbox > 0 ? plans[0].p : 0;
+  std::vector<GArgs> ga(nbox);
+  std::vector<int2> items;
+  for (int b = 0; b < nbox; ++b) {
+    const DevPlan& d = plans[b];
+    const int nt = d.nt[0] * d.nt[1] * d.nt[2];
+    for (int k = 0; k < nt; ++k) items.push_back(make_int2(b, k));
+    for (int h = 0; h < 2; ++h)
+      if (region_bytes(d, h + 1) > t.lds[h]) t.lds[h] = region_bytes(d, h + 1);
+  }
+  hipError_t e = hipSuccess;
+  for (int set = 0; set < 2 && e == hipSuccess; ++set) {
+    for (int b = 0; b < nbox; ++b) {
+      const DevPlan& d = plans[b];
+      GArgs a = base_args(d, set, n[b], nullptr, nullptr, nullptr, nullptr);
+      a.off = off[b];
+      a.psi = d.rho;
+      a.epart = d.epart; a.n_epart = fftx_blocks(d);
+      a.spart = d.spart; a.n_spart = bin_blocks(n[b]);
+      ga[b] = a;
+    }
+    e = upload(&t.g[set], ga.data(), sizeof(GArgs) * nbox);
+  }
+  if (e == hipSuccess)
+    e = upload(reinterpret_cast<void**>(&t.items), items.data(), sizeof(int2) * items.size());
+  t.n_items = int(items.size());
+  return e;
+}
+
+void gather_batch_free(GatherBatch& t) {
+  void* ptrs[] = {t.g[0], t.g[1], t.items};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  t = GatherBatch();
+}
+
+hipError_t launch_gather_batch(const GatherBatch& t, hipStream_t s, int set, bool hvp,
+                               const BatchIO& io) {
+  const GArgs* args = static_cast<const GArgs*>(t.g[set]);
+  const dim3 g(t.n_items < 2048 ? (t.n_items > 0 ? t.n_items : 1) : 2048);
+  return hvp ? gather_batch_dispatch<true>(t.p, g, t.lds[1], s, args, t.items, t.n_items, io)
+             : gather_batch_dispatch<false>(t.p, g, t.lds[0], s, args, t.items, t.n_items, io);
+}
 
 hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                          const float* q, const float* mu, const double* box, double* energy,

@@ -126,6 +126,77 @@ struct KTimer {
   const LaunchEvents* next(int k);
 };
 
+// ---- batches of boxes (one launch per kernel kind for all boxes) ----
+
+// Per-call arrays of a batch: the atoms of box b occupy [off_b, off_b + n_b) of the
+// packed per-atom arrays, cells are [nbox][9] and energies [nbox][3].
+struct BatchIO {
+  const float* pos = nullptr;
+  const float* q = nullptr;
+  const float* mu = nullptr;
+  const double* box = nullptr;
+  const float* v_pos = nullptr;
+  const float* v_q = nullptr;
+  const float* v_mu = nullptr;
+  double* energy = nullptr;
+  float* o_pos = nullptr;
+  float* o_q = nullptr;
+  float* o_mu = nullptr;
+};
+
+// Device tables of a batch: per-box argument templates (indexed by box) and the
+// (box, work item) lists of each batched kernel.
+struct SpreadBatch {
+  int p = 0;
+  void* bin[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};      // [tangent][set]
+  void* spread[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [tangent][set]
+  void* clear = nullptr;                                            // set-0 counters per box
+  int2* bin_items = nullptr;
+  int n_bin_items = 0;
+  int2* tile_items = nullptr;
+  int n_tile_items = 0;
+  int nbox = 0;
+  size_t lds[2] = {0, 0};                                           // spread LDS [tangent]
+};
+struct FFTBatch {
+  void* slab[2] = {nullptr, nullptr};   // potential into phi / into rho
+  void* x = nullptr;
+  int2* slab_items = nullptr;
+  int n_slab_items = 0;
+  int2* x_items = nullptr;
+  int n_x_items = 0;
+  size_t slab_lds = 0, x_lds = 0;
+};
+struct GatherBatch {
+  int p = 0;
+  void* g[2] = {nullptr, nullptr};      // [set]
+  int2* items = nullptr;
+  int n_items = 0;
+  size_t lds[2] = {0, 0};               // [hvp]
+};
+
+// Build the tables of boxes `plans[0..nbox)` with n[b] atoms at offsets off[b]
+// (all plans of one order, slab FFT layout).
+hipError_t spread_batch_build(const DevPlan* plans, const int* n, const int* off, int nbox,
+                              SpreadBatch& t);
+void spread_batch_free(SpreadBatch& t);
+hipError_t fft_batch_build(const DevPlan* plans, int nbox, FFTBatch& t);
+void fft_batch_free(FFTBatch& t);
+hipError_t gather_batch_build(const DevPlan* plans, const int* n, const int* off, int nbox,
+                              GatherBatch& t);
+void gather_batch_free(GatherBatch& t);
+// Clear counter set 0 of every box (the first binning of a batch step uses it).
+hipError_t launch_clear_batch(const SpreadBatch& t, hipStream_t s);
+hipError_t launch_bin_batch(const SpreadBatch& t, hipStream_t s, int set, bool tangent,
+                            const BatchIO& io, bool self_sums);
+hipError_t launch_spread_batch(const SpreadBatch& t, hipStream_t s, int set, bool tangent);
+hipError_t launch_convolve_batch(const FFTBatch& t, hipStream_t s, const double* box, bool to_phi,
+                                 bool energy);
+hipError_t launch_gather_batch(const GatherBatch& t, hipStream_t s, int set, bool hvp,
+                               const BatchIO& io);
+// Upload `count` bytes of host data to a new device array.
+hipError_t upload(void** dst, const void* src, size_t bytes);
+
 inline int fftx_blocks(const DevPlan& d) { return d.N[1] * ((d.H + d.ktile - 1) / d.ktile); }
 inline int ffty_blocks(const DevPlan& d) { return d.N[0] * ((d.H + d.ktile - 1) / d.ktile); }
 inline int fftz_blocks(const DevPlan& d) {
@@ -146,7 +217,8 @@ hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
 // rho -> spec -> (x g) -> out, the mesh operator K; energy partials when wanted.
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
                            bool energy, KTimer* tm);
-// Allow slab workgroups `bytes` of dynamic LDS (above the 64 KiB default).
+// Allow slab workgroups up to kSlabLdsMax of dynamic LDS (above the 64 KiB
+// default); `bytes`, the need of the calling plan, must not exceed it.
 hipError_t enable_slab_lds(size_t bytes);
 // Gradient gather (+ energy finalisation) over the atoms binned in counter set `set`.
 hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,

@@ -22,6 +22,8 @@
 //
 // Record layout (16 words): f_x f_y f_z anchor | c0 c1 c2 c3 | forward: mu_x mu_y mu_z -,
 // tangent: c4 c5 c6 c7 | tangent: c8 c9 - atom, forward: - - - atom.
+#include <vector>
+
 #include "kernels.h"
 #include "pme_common.h"
 
@@ -53,6 +55,7 @@ struct BinArgs {
   double* spart;
   int* status;
   int nblk;            // workgroups of this binning (bin_blocks(n))
+  int off;             // batches: offset of the box's atoms in the packed arrays
 };
 
 __device__ __forceinline__ float3 ld3(const float* p, int i) {
@@ -155,15 +158,45 @@ __global__ void __launch_bounds__(256) k_bin(BinArgs a) {
   bin_body<P, TANGENT>(a, blockIdx.x);
 }
 
-// Batched binning: work item (box, workgroup of the box), per-box arguments in
-// device memory; workgroups loop over the items.
+// Batched binning: work item (box, workgroup of the box), per-box argument
+// templates in device memory completed with the call's packed arrays; workgroups
+// loop over the items.
 template <int P, bool TANGENT>
 __global__ void __launch_bounds__(256) k_bin_batch(const BinArgs* args, const int2* items,
-                                                   int nitems) {
+                                                   int nitems, BatchIO io, int self_sums) {
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 w = items[it];
-    bin_body<P, TANGENT>(args[w.x], w.y);
+    BinArgs a = args[w.x];
+    const int o = a.off;
+    a.pos = io.pos + 3 * size_t(o);
+    a.q = io.q ? io.q + o : nullptr;
+    a.mu = io.mu ? io.mu + 3 * size_t(o) : nullptr;
+    a.box = io.box + 9 * w.x;
+    a.v_pos = io.v_pos ? io.v_pos + 3 * size_t(o) : nullptr;
+    a.v_q = io.v_q ? io.v_q + o : nullptr;
+    a.v_mu = io.v_mu ? io.v_mu + 3 * size_t(o) : nullptr;
+    if (!self_sums) a.spart = nullptr;
+    bin_body<P, TANGENT>(a, w.y);
     __syncthreads();
+  }
+}
+
+struct ClearItem {
+  int* count;
+  int nbins;
+  int* ovf_count;
+  unsigned* cmax;
+};
+
+// one workgroup per box: zero counter set 0
+__global__ void __launch_bounds__(256) k_clear_batch(const ClearItem* items, int nbox) {
+  for (int b = blockIdx.x; b < nbox; b += gridDim.x) {
+    const ClearItem c = items[b];
+    for (int e = threadIdx.x; e < c.nbins; e += 256) c.count[e] = 0;
+    if (threadIdx.x == 0) {
+      *c.ovf_count = 0;
+      *c.cmax = 0u;
+    }
   }
 }
 
@@ -548,10 +581,11 @@ hipError_t spread_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const Spread
 
 }  // namespace
 
-hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
-                      const float* q, const float* mu, const double* box, const float* v_pos,
-                      const float* v_q, const float* v_mu, bool tangent, bool self_sums,
-                      const LaunchEvents* ev) {
+namespace {
+
+BinArgs make_bin_args(const DevPlan& d, int set, int n, const float* pos, const float* q,
+                      const float* mu, const double* box, const float* v_pos, const float* v_q,
+                      const float* v_mu, bool self_sums) {
   BinArgs a;
   a.n = n; a.pos = pos; a.q = q; a.mu = mu; a.box = box;
   a.v_pos = v_pos; a.v_q = v_q; a.v_mu = v_mu;
@@ -565,12 +599,11 @@ hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const flo
   a.spart = self_sums ? d.spart : nullptr;
   a.status = d.status;
   a.nblk = bin_blocks(n);
-  const dim3 g(bin_blocks(n));
-  return tangent ? bin_dispatch<true>(d.p, g, s, a, ev) : bin_dispatch<false>(d.p, g, s, a, ev);
+  a.off = 0;
+  return a;
 }
 
-hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
-                         const LaunchEvents* ev) {
+SpreadArgs make_spread_args(const DevPlan& d, int set, bool tangent) {
   SpreadArgs a;
   for (int k = 0; k < 3; ++k) {
     a.N[k] = d.N[k]; a.B[k] = d.B[k]; a.nb[k] = d.nb[k]; a.T[k] = d.T[k]; a.nt[k] = d.nt[k];
@@ -581,10 +614,153 @@ hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
   a.ch = d.spread_ch[tangent ? 1 : 0];
   a.nbr_max = d.nbr_max;
   a.tile_words = d.T[0] * d.T[1] * (d.T[2] + 1);
-  const size_t sh = spread_lds_bytes(a.tile_words, a.nbr_max, a.ch, d.p, tangent ? 2 : 1);
+  return a;
+}
+
+size_t spread_lds(const DevPlan& d, bool tangent) {
+  const SpreadArgs a = make_spread_args(d, 0, tangent);
+  return spread_lds_bytes(a.tile_words, a.nbr_max, a.ch, d.p, tangent ? 2 : 1);
+}
+
+template <bool TANGENT>
+hipError_t bin_batch_dispatch(int p, dim3 g, hipStream_t s, const BinArgs* args, const int2* it,
+                              int n, const BatchIO& io, int ss) {
+  switch (p) {
+    case 1: hipLaunchKernelGGL((k_bin_batch<1, TANGENT>), g, dim3(256), 0, s, args, it, n, io, ss); break;
+    case 2: hipLaunchKernelGGL((k_bin_batch<2, TANGENT>), g, dim3(256), 0, s, args, it, n, io, ss); break;
+    case 3: hipLaunchKernelGGL((k_bin_batch<3, TANGENT>), g, dim3(256), 0, s, args, it, n, io, ss); break;
+    case 4: hipLaunchKernelGGL((k_bin_batch<4, TANGENT>), g, dim3(256), 0, s, args, it, n, io, ss); break;
+    case 5: hipLaunchKernelGGL((k_bin_batch<5, TANGENT>), g, dim3(256), 0, s, args, it, n, io, ss); break;
+    case 6: hipLaunchKernelGGL((k_bin_batch<6, TANGENT>), g, dim3(256), 0, s, args, it, n, io, ss); break;
+    case 7: hipLaunchKernelGGL((k_bin_batch<7, TANGENT>), g, dim3(256), 0, s, args, it, n, io, ss); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int DEG>
+hipError_t spread_batch_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const SpreadArgs* args,
+                                 const int2* it, int n) {
+  switch (p) {
+    case 1: hipLaunchKernelGGL((k_spread_batch<1, DEG>), g, dim3(256), sh, s, args, it, n); break;
+    case 2: hipLaunchKernelGGL((k_spread_batch<2, DEG>), g, dim3(256), sh, s, args, it, n); break;
+    case 3: hipLaunchKernelGGL((k_spread_batch<3, DEG>), g, dim3(256), sh, s, args, it, n); break;
+    case 4: hipLaunchKernelGGL((k_spread_batch<4, DEG>), g, dim3(256), sh, s, args, it, n); break;
+    case 5: hipLaunchKernelGGL((k_spread_batch<5, DEG>), g, dim3(256), sh, s, args, it, n); break;
+    case 6: hipLaunchKernelGGL((k_spread_batch<6, DEG>), g, dim3(256), sh, s, args, it, n); break;
+    case 7: hipLaunchKernelGGL((k_spread_batch<7, DEG>), g, dim3(256), sh, s, args, it, n); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// grid of a batched launch: every work item, up to a few workgroups per CU
+inline dim3 batch_grid(int items, int cap) { return dim3(items < cap ? (items > 0 ? items : 1) : cap); }
+
+}  // namespace
+
+hipError_t upload(void** dst, const void* src, size_t bytes) {
+  *dst = nullptr;
+  hipError_t e = hipMalloc(dst, bytes ? bytes : 1);
+  if (e != hipSuccess) return e;
+  return bytes ? hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+}
+
+hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
+                      const float* q, const float* mu, const double* box, const float* v_pos,
+                      const float* v_q, const float* v_mu, bool tangent, bool self_sums,
+                      const LaunchEvents* ev) {
+  const BinArgs a = make_bin_args(d, set, n, pos, q, mu, box, v_pos, v_q, v_mu, self_sums);
+  const dim3 g(bin_blocks(n));
+  return tangent ? bin_dispatch<true>(d.p, g, s, a, ev) : bin_dispatch<false>(d.p, g, s, a, ev);
+}
+
+hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
+                         const LaunchEvents* ev) {
+  const SpreadArgs a = make_spread_args(d, set, tangent);
+  const size_t sh = spread_lds(d, tangent);
   const dim3 g(d.nt[0] * d.nt[1] * d.nt[2]);
   return tangent ? spread_dispatch<2>(d.p, g, sh, s, a, ev)
                  : spread_dispatch<1>(d.p, g, sh, s, a, ev);
+}
+
+hipError_t spread_batch_build(const DevPlan* plans, const int* n, const int* off, int nbox,
+                              SpreadBatch& t) {
+  t = SpreadBatch();
+  t.nbox = nbox;
+  t.p = nbox > 0 ? plans[0].p : 0;
+  std::vector<BinArgs> ba(nbox);
+  std::vector<SpreadArgs> sa(nbox);
+  std::vector<ClearItem> ci(nbox);
+  std::vector<int2> bitems, titems;
+  for (int b = 0; b < nbox; ++b) {
+    const DevPlan& d = plans[b];
+    for (int k = 0; k < bin_blocks(n[b]); ++k) bitems.push_back(make_int2(b, k));
+    const int nt = d.nt[0] * d.nt[1] * d.nt[2];
+    for (int k = 0; k < nt; ++k) titems.push_back(make_int2(b, k));
+    for (int tg = 0; tg < 2; ++tg) {
+      const size_t l = spread_lds(d, tg == 1);
+      if (l > t.lds[tg]) t.lds[tg] = l;
+    }
+    ci[b].count = d.count[0];
+    ci[b].nbins = d.nb[0] * d.nb[1] * d.nb[2];
+    ci[b].ovf_count = d.ovf_count[0];
+    ci[b].cmax = d.cmax[0];
+  }
+  hipError_t e = hipSuccess;
+  auto ok = [&](hipError_t r) { if (r != hipSuccess && e == hipSuccess) e = r; };
+  for (int tg = 0; tg < 2; ++tg)
+    for (int set = 0; set < 2; ++set) {
+      for (int b = 0; b < nbox; ++b) {
+        ba[b] = make_bin_args(plans[b], set, n[b], nullptr, nullptr, nullptr, nullptr, nullptr,
+                              nullptr, nullptr, tg == 0);
+        ba[b].off = off[b];
+        sa[b] = make_spread_args(plans[b], set, tg == 1);
+      }
+      ok(upload(&t.bin[tg][set], ba.data(), sizeof(BinArgs) * nbox));
+      ok(upload(&t.spread[tg][set], sa.data(), sizeof(SpreadArgs) * nbox));
+    }
+  ok(upload(&t.clear, ci.data(), sizeof(ClearItem) * nbox));
+  ok(upload(reinterpret_cast<void**>(&t.bin_items), bitems.data(), sizeof(int2) * bitems.size()));
+  ok(upload(reinterpret_cast<void**>(&t.tile_items), titems.data(), sizeof(int2) * titems.size()));
+  t.n_bin_items = int(bitems.size());
+  t.n_tile_items = int(titems.size());
+  return e;
+}
+
+void spread_batch_free(SpreadBatch& t) {
+  for (int tg = 0; tg < 2; ++tg)
+    for (int set = 0; set < 2; ++set) {
+      if (t.bin[tg][set]) (void)hipFree(t.bin[tg][set]);
+      if (t.spread[tg][set]) (void)hipFree(t.spread[tg][set]);
+    }
+  if (t.clear) (void)hipFree(t.clear);
+  if (t.bin_items) (void)hipFree(t.bin_items);
+  if (t.tile_items) (void)hipFree(t.tile_items);
+  t = SpreadBatch();
+}
+
+hipError_t launch_clear_batch(const SpreadBatch& t, hipStream_t s) {
+  hipLaunchKernelGGL(k_clear_batch, batch_grid(t.nbox, 1024), dim3(256), 0, s,
+                     static_cast<const ClearItem*>(t.clear), t.nbox);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_batch(const SpreadBatch& t, hipStream_t s, int set, bool tangent,
+                            const BatchIO& io, bool self_sums) {
+  const BinArgs* args = static_cast<const BinArgs*>(t.bin[tangent ? 1 : 0][set]);
+  const dim3 g = batch_grid(t.n_bin_items, 2048);
+  return tangent ? bin_batch_dispatch<true>(t.p, g, s, args, t.bin_items, t.n_bin_items, io, 0)
+                 : bin_batch_dispatch<false>(t.p, g, s, args, t.bin_items, t.n_bin_items, io,
+                                             self_sums ? 1 : 0);
+}
+
+hipError_t launch_spread_batch(const SpreadBatch& t, hipStream_t s, int set, bool tangent) {
+  const SpreadArgs* args = static_cast<const SpreadArgs*>(t.spread[tangent ? 1 : 0][set]);
+  const dim3 g = batch_grid(t.n_tile_items, 1280);
+  const size_t sh = t.lds[tangent ? 1 : 0];
+  return tangent ? spread_batch_dispatch<2>(t.p, g, sh, s, args, t.tile_items, t.n_tile_items)
+                 : spread_batch_dispatch<1>(t.p, g, sh, s, args, t.tile_items, t.n_tile_items);
 }
 
 }  // namespace pme

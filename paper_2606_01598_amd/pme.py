@@ -63,7 +63,7 @@ class Plan:
     """A PME plan: mesh, order, alpha and the device workspaces (pme_plan_create)."""
 
     def __init__(self, mesh, order: int, alpha: float, max_atoms: int, influence_power: float = 1.0,
-                 prefactor: float = 1.0, keep_phi: bool = True, device=None):
+                 prefactor: float = 1.0, keep_phi: bool = True, device=None, tile=None):
         self._lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         d = _lib.PMEDesc()
@@ -75,6 +75,8 @@ class Plan:
         d.alpha = float(alpha)
         d.influence_power = float(influence_power)
         d.prefactor = float(prefactor)
+        for k in range(3):
+            d.tile[k] = 0 if tile is None else int(tile[k])
         self.desc = d
         self.mesh = tuple(int(m) for m in mesh)
         self.order = int(order)

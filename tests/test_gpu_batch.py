@@ -1,0 +1,144 @@
+"""Batched boxes (pme_batch_*): equality with one plan per box, parity with the
+oracle, HIP-graph replays against the eager batch, and the tile autotuner.
+
+The batch runs the same kernels and tiles as per-box plans, so the results are
+required to agree to 1e-6 relative (they are expected to be bit-identical).
+Graph replays are checked one by one against the eager results, with eager work
+and synchronisations between the replays.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from gpu_util import E_REL_TOL, RMS_REL_TOL, dev, host, oracle_forward, oracle_hvp, rel, rms_rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _pack(frames, seed=0):
+    d = dev()
+    cat = lambda xs: torch.tensor(np.concatenate(xs), dtype=torch.float32, device=d)
+    pos = cat([f.pos for f in frames])
+    q = cat([f.q for f in frames])
+    mu = cat([f.mu for f in frames])
+    box = torch.tensor(np.stack([f.box for f in frames]), dtype=torch.float64, device=d)
+    n = sum(f.n for f in frames)
+    v = synth.random_cotangents(n, 100 + seed, scale_r=0.1)
+    vr, vq, vm = (torch.tensor(x, dtype=torch.float32, device=d) for x in v)
+    vf = torch.tensor(synth.random_cotangents(n, 200 + seed, scale_r=0.1)[0], dtype=torch.float32,
+                      device=d)
+    return pos, q, mu, box, vr, vq, vm, vf
+
+
+def _boxes(k=6, seed=6):
+    frames, meshes = synth.batch_boxes(k, seed, nmin=64, nmax=900, mesh_hi=32)
+    return frames, meshes
+
+
+def _close(a, b):
+    a, b = host(a), host(b)
+    scale = max(np.abs(b).max(), 1e-30)
+    return float(np.abs(a - b).max() / scale)
+
+
+def test_batch_equals_single_plans():
+    from paper_2606_01598_amd.batch import Batch
+    from paper_2606_01598_amd.pme import Plan
+    frames, meshes = _boxes()
+    pos, q, mu, box, vr, vq, vm, _ = _pack(frames)
+    bt = Batch(meshes, [f.n for f in frames], 6, 0.3)
+    fo = bt.forward(pos, q, mu, box)
+    bo = bt.backward(pos, q, mu, box, vr, vq, vm)
+    bt.status()
+    worst, bitwise = 0.0, True
+    for b, (f, m) in enumerate(zip(frames, meshes)):
+        s0, s1 = int(bt.offsets[b]), int(bt.offsets[b + 1])
+        pl = Plan(m, 6, 0.3, max_atoms=f.n)
+        o = pl.forward(pos[s0:s1].contiguous(), q[s0:s1].contiguous(), mu[s0:s1].contiguous(),
+                       box[b].contiguous())
+        ob = pl.backward(pos[s0:s1].contiguous(), q[s0:s1].contiguous(), mu[s0:s1].contiguous(),
+                         box[b].contiguous(), vr[s0:s1].contiguous(), vq[s0:s1].contiguous(),
+                         vm[s0:s1].contiguous())
+        pairs = [(fo["energy"][b], o["energy"])]
+        pairs += [(fo[k][s0:s1], o[k]) for k in ("dE_dpos", "dE_dq", "dE_dmu")]
+        pairs += [(bo[k][s0:s1], ob[k]) for k in ("g_pos", "g_q", "g_mu")]
+        for x, y in pairs:
+            worst = max(worst, _close(x, y))
+            bitwise &= bool(torch.equal(x, y))
+    print("batch vs single: max rel", f"{worst:.2e}", "bitwise", bitwise, flush=True)
+    assert worst <= 1e-6
+
+
+def test_batch_parity_with_oracle():
+    from paper_2606_01598_amd.batch import Batch
+    frames, meshes = _boxes(k=3, seed=9)
+    pos, q, mu, box, vr, vq, vm, _ = _pack(frames, seed=1)
+    bt = Batch(meshes, [f.n for f in frames], 6, 0.3)
+    fo = bt.forward(pos, q, mu, box)
+    bo = bt.backward(pos, q, mu, box, vr, vq, vm)
+    for b, (f, m) in enumerate(zip(frames, meshes)):
+        s0, s1 = int(bt.offsets[b]), int(bt.offsets[b + 1])
+        ref = oracle_forward(f, m, 6, 0.3)
+        e = host(fo["energy"][b])
+        assert rel(e.sum(), ref.energy) <= E_REL_TOL
+        assert rms_rel(host(fo["dE_dpos"][s0:s1]), ref.dE_dpos) <= RMS_REL_TOL
+        v = (host(vr[s0:s1]), host(vq[s0:s1]), host(vm[s0:s1]))
+        gp, gq, gm = oracle_hvp(f, m, 6, 0.3, v)
+        assert rms_rel(host(bo["g_pos"][s0:s1]), gp) <= RMS_REL_TOL
+        assert rms_rel(host(bo["g_mu"][s0:s1]), gm) <= RMS_REL_TOL
+
+
+def test_graph_replays_match_eager():
+    from paper_2606_01598_amd.batch import Batch
+    frames, meshes = _boxes(k=5, seed=7)
+    pos, q, mu, box, vr, vq, vm, vf = _pack(frames, seed=2)
+    bt = Batch(meshes, [f.n for f in frames], 6, 0.3)
+    N, B = bt.total, bt.nbox
+    emp = lambda *s: torch.full(s, float("nan"), dtype=torch.float32, device=dev())
+    step = {"pos": pos, "q": q, "mu": mu, "box": box,
+            "energy": torch.full((B, 3), float("nan"), dtype=torch.float64, device=dev()),
+            "dE_dpos": emp(N, 3), "dE_dq": emp(N), "dE_dmu": emp(N, 3),
+            "v_pos": vr, "v_q": vq, "v_mu": vm, "g_pos": emp(N, 3), "g_q": emp(N), "g_mu": emp(N, 3),
+            "vf_pos": vf, "gf_pos": emp(N, 3), "gf_q": emp(N), "gf_mu": emp(N, 3)}
+    # eager reference of the same three calls
+    fo = bt.forward(pos, q, mu, box)
+    bo = bt.backward(pos, q, mu, box, vr, vq, vm)
+    ff = bt.backward(pos, q, mu, box, vf, None, None)
+    ref = {"energy": fo["energy"], "dE_dpos": fo["dE_dpos"], "dE_dq": fo["dE_dq"],
+           "dE_dmu": fo["dE_dmu"], "g_pos": bo["g_pos"], "g_q": bo["g_q"], "g_mu": bo["g_mu"],
+           "gf_pos": ff["g_pos"], "gf_q": ff["g_q"], "gf_mu": ff["g_mu"]}
+    ref = {k: t.clone() for k, t in ref.items()}
+    bt.capture(step)
+    for r in range(3):
+        for k in ref:
+            step[k].fill_(float("nan"))
+        torch.cuda.synchronize()
+        bt.replay()
+        torch.cuda.synchronize()
+        worst = max(_close(step[k], ref[k]) for k in ref)
+        print("replay", r, "max rel", f"{worst:.2e}", flush=True)
+        assert worst <= 1e-6
+        # eager work between replays
+        bt.forward(pos, q, mu, box)
+        torch.cuda.synchronize()
+    bt.status()
+
+
+def test_autotuner_picks_and_caches(tmp_path):
+    from paper_2606_01598_amd import autotune
+    frames, meshes = _boxes(k=2, seed=11)
+    boxes = []
+    for f, m in zip(frames, meshes):
+        t = lambda a: torch.tensor(a, dtype=torch.float32, device=dev())
+        v = synth.random_cotangents(f.n, 5, scale_r=0.1)
+        boxes.append({"mesh": m, "pos": t(f.pos), "q": t(f.q), "mu": t(f.mu),
+                      "box": torch.tensor(f.box, dtype=torch.float64, device=dev()),
+                      "v": [t(x) for x in v]})
+    path = str(tmp_path / "tiles.json")
+    cands = ((8, 8, 16), (8, 16, 16))
+    tiles, timed = autotune.tune(boxes, 6, 0.3, cache_path=path, steps=2, candidates=cands)
+    assert timed >= 1 and all(t in cands for t in tiles)
+    tiles2, timed2 = autotune.tune(boxes, 6, 0.3, cache_path=path, steps=2, candidates=cands)
+    assert timed2 == 0 and tiles2 == tiles
+    print("autotuned tiles", tiles, flush=True)
