@@ -106,6 +106,10 @@ def _args(argv=None):
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter summary of the dominant kernel and exit")
     ap.add_argument("--kernel", default=None, help="kernel kind for --traffic-summary")
+    ap.add_argument("--batched", type=int, default=1,
+                    help="1 adds the batched-graph leg (64 boxes, one HIP graph per step)")
+    ap.add_argument("--learned", type=int, default=1,
+                    help="1 adds the learned-dipole leg (SCF teacher vs trained network)")
     return ap.parse_args(argv)
 
 
@@ -213,10 +217,183 @@ def main(argv=None):
         "kernels_us": kernels_us,
         "step_model_bytes": 224 * n + 36 * m,
     }
+    if args.batched:
+        line["batched"] = batched_leg()
+    if args.learned:
+        line["learned_dipole"] = learned_leg()
     if args.cpu_baseline and args.workload == "32k":
         line["cpu_baseline"] = cpu_baseline(frame, mesh, p, alpha, v, args.cpu_steps)
     print(json.dumps(line), flush=True)
     return 0
+
+
+def _median_ms(fn, reps):
+    import torch
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+    times.sort()
+    return times[len(times) // 2]
+
+
+def batched_leg(n_boxes=64, seed=6, reps=20):
+    """64 molten-salt boxes, atom counts log-uniform in [64, 4096], meshes of about
+    1 A (16..64 per side), p = 6, alpha = 0.30: one training step (forward,
+    Hessian-vector product, force-loss double backward) as one replay of a HIP
+    graph over the batch, against 64 sequential un-graphed single-box plans doing
+    the same three calls.  Tiles come from the autotuner."""
+    import tempfile
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2606_01598_amd import autotune
+    from paper_2606_01598_amd.batch import Batch
+    from paper_2606_01598_amd.pme import Plan
+
+    dev = torch.device("cuda", 0)
+    frames, meshes = synth.batch_boxes(n_boxes, seed)
+    t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+    boxes = []
+    for b, f in enumerate(frames):
+        vr, vq, vm = synth.random_cotangents(f.n, 300 + b, scale_r=0.1)
+        vf = synth.random_cotangents(f.n, 600 + b, scale_r=0.1)[0]
+        boxes.append({"mesh": meshes[b], "pos": t(f.pos), "q": t(f.q), "mu": t(f.mu),
+                      "box": torch.tensor(f.box, dtype=torch.float64, device=dev),
+                      "v": [t(vr), t(vq), t(vm)], "vf": t(vf)})
+    cache = os.path.join(tempfile.gettempdir(), "pme_bench_tiles.json")
+    t0 = time.perf_counter()
+    tiles, timed = autotune.tune(boxes, 6, 0.30, cache_path=cache, steps=2,
+                                 candidates=((8, 8, 16), (8, 16, 16), (16, 16, 16)))
+    tune_s = time.perf_counter() - t0
+    plans = [Plan(b["mesh"], 6, 0.30, max_atoms=b["pos"].shape[0], tile=tiles[k])
+             for k, b in enumerate(boxes)]
+    outs = []
+
+    def sequential():
+        outs.clear()
+        for pl, b in zip(plans, boxes):
+            o = pl.forward(b["pos"], b["q"], b["mu"], b["box"])
+            g = pl.backward(b["pos"], b["q"], b["mu"], b["box"], *b["v"])
+            gf = pl.backward(b["pos"], b["q"], b["mu"], b["box"], b["vf"], None, None)
+            outs.append((o, g, gf))
+
+    for _ in range(2):
+        sequential()
+    seq_ms = _median_ms(sequential, 5)
+    cat = lambda k: torch.cat([b[k] for b in boxes]).contiguous()
+    pos, q, mu = cat("pos"), cat("q"), cat("mu")
+    box = torch.stack([b["box"] for b in boxes]).contiguous()
+    vr = torch.cat([b["v"][0] for b in boxes]); vq = torch.cat([b["v"][1] for b in boxes])
+    vm = torch.cat([b["v"][2] for b in boxes]); vf = cat("vf")
+    bt = Batch(meshes, [f.n for f in frames], 6, 0.30, tiles=tiles)
+    N, B = bt.total, bt.nbox
+    emp = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=dev)
+    step = {"pos": pos, "q": q, "mu": mu, "box": box,
+            "energy": torch.empty(B, 3, dtype=torch.float64, device=dev),
+            "dE_dpos": emp(N, 3), "dE_dq": emp(N), "dE_dmu": emp(N, 3), "v_pos": vr, "v_q": vq,
+            "v_mu": vm, "g_pos": emp(N, 3), "g_q": emp(N), "g_mu": emp(N, 3), "vf_pos": vf,
+            "gf_pos": emp(N, 3), "gf_q": emp(N), "gf_mu": emp(N, 3)}
+    bt.capture(step)
+    for _ in range(3):
+        bt.replay()
+    graph_ms = _median_ms(bt.replay, reps)
+    bt.status()
+    # largest relative difference between the sequential and the graph results
+    worst = 0.0
+    for k, (o, g, gf) in enumerate(outs):
+        s0, s1 = int(bt.offsets[k]), int(bt.offsets[k + 1])
+        pairs = [(step["energy"][k], o["energy"]), (step["dE_dpos"][s0:s1], o["dE_dpos"]),
+                 (step["g_pos"][s0:s1], g["g_pos"]), (step["gf_pos"][s0:s1], gf["g_pos"]),
+                 (step["g_mu"][s0:s1], g["g_mu"])]
+        for x, y in pairs:
+            den = float(y.abs().max().clamp_min(1e-30))
+            worst = max(worst, float((x - y).abs().max()) / den)
+    return {"workload": f"{B} molten-salt boxes, {N} ions in all (64..4096 per box, log-uniform), "
+                        "meshes 16..64 at ~1 A, p=6, alpha=0.3; forward + H v + force-loss H v",
+            "graph_ms": round(graph_ms, 4), "sequential_ms": round(seq_ms, 4),
+            "speedup": round(seq_ms / graph_ms, 3),
+            "graph_Matom_steps_per_s": round(N / graph_ms / 1e3, 3),
+            "max_rel_diff": worst, "autotune_keys_timed": timed, "autotune_s": round(tune_s, 2)}
+
+
+def learned_leg(n_train=32, n_val=4, epochs=80):
+    """4096-ion boxes of the Thole-damped polarizable model (polarizabilities
+    0.15 / 3.5 A^3, L = 50.4 A, mesh 50^3, p = 6, alpha = 0.30, r_c = 10 A): the
+    self-consistent dipoles by PCG to 1e-6 e*A (the teacher) against the trained
+    dipole network (features + network + one model evaluation).  Reports times per
+    box and force RMSE against the teacher on held-out boxes, and the same error
+    with the dipoles left at zero."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2606_01598_amd.dip import DipPlan, Trainer
+    from paper_2606_01598_amd.pme import Plan
+    from paper_2606_01598_amd.pol import PolPlan
+
+    dev = torch.device("cuda", 0)
+    n = 4096
+    L = synth.molten_side(n)
+    box_np = np.eye(3) * L
+    box = torch.tensor(box_np, dtype=torch.float64, device=dev)
+    mesh, p, alpha, rc = (50, 50, 50), 6, 0.30, 10.0
+    pme = Plan(mesh, p, alpha, max_atoms=n, keep_phi=True)
+    polp = PolPlan(box_np, alpha, rc, max_atoms=n)
+    dip = DipPlan(box_np, n, cutoff=5.0)
+    t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+    data, scf_ms, iters = [], [], []
+    for k in range(n_train + n_val):
+        f = synth.molten_box(n, (1000 + k) if k < n_train else (2000 + k - n_train))
+        pos, q, a = t(f.pos), t(f.q), t(np.where(f.q > 0, 0.15, 3.5))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mu, it, res = polp.scf(pme, pos, q, a, box, tol=1e-6, max_iter=300)
+        o = polp.model(pme, pos, q, mu, a, box, dU_dmu=False)
+        torch.cuda.synchronize()
+        scf_ms.append((time.perf_counter() - t0) * 1e3)
+        iters.append(it)
+        feat, vec = dip.features(pos, q)
+        data.append({"pos": pos, "q": q, "pol": a, "feat": feat, "vec": vec, "U": o["energy"],
+                     "dUdr": o["dU_dpos"], "mu": mu})
+    train, val = data[:n_train], data[n_train:]
+    tr = Trainer(dip, polp, pme, box, synth.mlp_init(7), lr=3e-3, lE=1.0, lF=1.0)
+    t0 = time.perf_counter()
+    for _ in range(epochs):
+        for b in train:
+            tr.step(b)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+
+    def rmse(mu, b):
+        s = polp.model(pme, b["pos"], b["q"], mu, b["pol"], box, energy=False, dU_dmu=False)
+        return float(torch.sqrt(torch.mean((s["dU_dpos"] - b["dUdr"]) ** 2)))
+
+    zero = torch.zeros(n, 3, dtype=torch.float32, device=dev)
+    e_nn = float(np.mean([rmse(tr.predict(b["feat"], b["vec"]), b) for b in val]))
+    e_zero = float(np.mean([rmse(zero, b) for b in val]))
+    b = val[0]
+
+    def infer():
+        feat, vec = dip.features(b["pos"], b["q"])
+        mu = dip.forward(tr.theta, feat, vec)
+        polp.model(pme, b["pos"], b["q"], mu, b["pol"], box, dU_dmu=False)
+
+    for _ in range(3):
+        infer()
+    nn_ms = _median_ms(infer, 20)
+    scf_med = float(np.median(scf_ms[n_train:]))
+    return {"workload": f"{n}-ion Thole boxes, L={L:.1f} A, mesh 50^3, p=6, alpha=0.3, r_c=10 A; "
+                        f"{n_train} training / {n_val} held-out boxes, {epochs} epochs",
+            "scf_ms": round(scf_med, 3), "scf_iterations": int(np.median(iters)),
+            "nn_ms": round(nn_ms, 4), "speedup": round(scf_med / nn_ms, 2),
+            "force_rmse_nn": e_nn, "force_rmse_zero_dipoles": e_zero,
+            "force_unit": "e^2/A^2", "train_s": round(train_s, 2)}
 
 
 def _traffic_path(kind: str, workload: str) -> str:
