@@ -110,6 +110,9 @@ def _args(argv=None):
                     help="1 adds the batched-graph leg (64 boxes, one HIP graph per step)")
     ap.add_argument("--learned", type=int, default=1,
                     help="1 adds the learned-dipole leg (SCF teacher vs trained network)")
+    ap.add_argument("--crossover", type=int, default=0,
+                    help="1: time explicit Ewald and PME (oracles on the host, PME on the GPU) "
+                         "for 128..8192 ions and print one JSON line per size, then exit")
     return ap.parse_args(argv)
 
 
@@ -121,6 +124,8 @@ def main(argv=None):
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         return 2
+    if args.crossover:
+        return crossover()
     import torch
 
     import synth
@@ -488,6 +493,46 @@ def traffic_summary(args) -> int:
         fh.write(f"traffic_bytes_per_launch: {fb + wb:.0f}\n")
         fh.write(f"alg_bytes_per_launch: {alg_bytes(kind, n, m)}\n")
     print(open(out).read())
+    return 0
+
+
+def crossover(sizes=(128, 512, 1024, 2048, 4096), alpha=0.30):
+    """Explicit Ewald against PME for replicated-density molten-salt boxes: the
+    FP64 Ewald oracle at a matched accuracy (erfc(alpha r_c) = 1e-6, k_c =
+    2 alpha sqrt(ln 1e6)), the FP64 PME oracle and the GPU PME (forward only, mesh
+    ~1 A, p = 6), energy and gradients.  One JSON line per size."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import ewald as oew
+    from oracle import pme as opme
+    from paper_2606_01598_amd.pme import Plan
+
+    dev = torch.device("cuda", 0)
+    for n in sizes:
+        f = synth.molten_box(n, 40 + n)
+        L = f.box[0, 0]
+        m = synth.nearest_smooth(L)
+        mesh = (m, m, m)
+        t0 = time.perf_counter()
+        ew = oew.ewald(f.pos, f.q, f.mu, f.box, alpha, eps=1e-6)
+        t_ew = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        pm = opme.forward(f.pos, f.q, f.mu, f.box, mesh, 6, alpha)
+        t_pm = time.perf_counter() - t0
+        t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=dev)
+        plan = Plan(mesh, 6, alpha, max_atoms=n)
+        pos, q, mu = t(f.pos), t(f.q), t(f.mu)
+        box = torch.tensor(f.box, dtype=torch.float64, device=dev)
+        for _ in range(5):
+            plan.forward(pos, q, mu, box)
+        gpu_ms = _median_ms(lambda: plan.forward(pos, q, mu, box), 20)
+        err = abs(pm.energy - ew.long_range) / abs(ew.long_range)
+        print(json.dumps({"atoms": n, "L": round(L, 3), "mesh": m, "ewald_cpu_s": round(t_ew, 4),
+                          "pme_cpu_s": round(t_pm, 4), "pme_gpu_ms": round(gpu_ms, 4),
+                          "ewald_over_pme_cpu": round(t_ew / t_pm, 3),
+                          "pme_vs_ewald_rel_energy_diff": err}), flush=True)
     return 0
 
 
