@@ -16,7 +16,7 @@ import torch
 
 from .pme import Plan
 
-CANDIDATES = ((8, 8, 16), (8, 16, 16), (16, 16, 16), (8, 8, 8), (4, 8, 16), (16, 16, 8))
+CANDIDATES = ((8, 8, 16), (8, 16, 16), (12, 12, 16), (16, 16, 16), (8, 8, 8), (16, 16, 8))
 TIMED = ("bin", "bin_tangent", "spread", "spread_tangent", "gather", "gather_hvp")
 
 

@@ -225,7 +225,9 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
       region *= d.T[a] + p - 1;
     }
     const long tpad = long(d.T[0]) * d.T[1] * (d.T[2] + 1);
-    if (range <= pme::kMaxBinRange && own <= 256 && tpad <= pme::kTileLds && region * 4 <= 65536)
+    if (range <= pme::kMaxBinRange && own <= 256 && tpad <= pme::kTileLds &&
+        region * 4 <= pme::kBigLds &&
+        long(pme::spread_lds_bytes(int(tpad), int(range), 64, p, 2)) <= pme::kBigLds)
       break;
     int big = 0;
     for (int a = 1; a < 3; ++a)
@@ -335,6 +337,8 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   ok(hipMemset(d.status, 0, sizeof(int)));
   ok(hipMemset(d.phi, 0, sizeof(float) * M));
   if (d.slab) ok(pme::enable_slab_lds(d.slab_lds));
+  ok(pme::enable_spread_lds());
+  ok(pme::enable_gather_lds());
   ok(hipDeviceSynchronize());
   if (e != hipSuccess) {
     free_plan(pl);

@@ -604,6 +604,22 @@ hipError_t gather_batch_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const 
 
 }  // namespace
 
+hipError_t enable_gather_lds() {
+  const void* fns[] = {
+#define PME_G(P)                                                                             \
+  reinterpret_cast<const void*>(k_gather<P>), reinterpret_cast<const void*>(k_gather_hvp<P>), \
+      reinterpret_cast<const void*>(k_gather_batch<P, false>),                               \
+      reinterpret_cast<const void*>(k_gather_batch<P, true>),
+      PME_G(1) PME_G(2) PME_G(3) PME_G(4) PME_G(5) PME_G(6) PME_G(7)
+#undef PME_G
+  };
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kBigLds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t gather_batch_build(const DevPlan* plans, const int* n, const int* off, int nbox,
                               GatherBatch& t) {
   t = GatherBatch();

@@ -10,8 +10,9 @@
 namespace pme {
 
 constexpr int kMaxStages = 16;
-constexpr int kMaxBinRange = 512;    // bins a spread tile may scan (LDS count array)
-constexpr int kTileLds = 1536;       // max padded spread-tile points: T_x T_y (T_z + 1)
+constexpr int kMaxBinRange = 2048;   // bins a spread tile may scan (LDS count array)
+constexpr int kTileLds = 8192;       // max padded spread-tile points: T_x T_y (T_z + 1)
+constexpr int kBigLds = 150 * 1024;  // dynamic LDS limit of the spread and gather kernels
 
 // LDS words of one staged spread entry: weights of three axes (derivative orders up
 // to deg), the assignment coefficients, the tile-local stencil coordinates and the
@@ -217,6 +218,9 @@ hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
 // rho -> spec -> (x g) -> out, the mesh operator K; energy partials when wanted.
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
                            bool energy, KTimer* tm);
+// Allow the spread and gather kernels up to kBigLds of dynamic LDS.
+hipError_t enable_spread_lds();
+hipError_t enable_gather_lds();
 // Allow slab workgroups up to kSlabLdsMax of dynamic LDS (above the 64 KiB
 // default); `bytes`, the need of the calling plan, must not exceed it.
 hipError_t enable_slab_lds(size_t bytes);

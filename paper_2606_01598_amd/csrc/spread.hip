@@ -659,6 +659,22 @@ inline dim3 batch_grid(int items, int cap) { return dim3(items < cap ? (items > 
 
 }  // namespace
 
+hipError_t enable_spread_lds() {
+  const void* fns[] = {
+#define PME_S(P)                                                               \
+  reinterpret_cast<const void*>(k_spread<P, 1>), reinterpret_cast<const void*>(k_spread<P, 2>), \
+      reinterpret_cast<const void*>(k_spread_batch<P, 1>),                     \
+      reinterpret_cast<const void*>(k_spread_batch<P, 2>),
+      PME_S(1) PME_S(2) PME_S(3) PME_S(4) PME_S(5) PME_S(6) PME_S(7)
+#undef PME_S
+  };
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kBigLds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t upload(void** dst, const void* src, size_t bytes) {
   *dst = nullptr;
   hipError_t e = hipMalloc(dst, bytes ? bytes : 1);
