@@ -226,7 +226,7 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
     }
     const long tpad = long(d.T[0]) * d.T[1] * (d.T[2] + 1);
     if (range <= pme::kMaxBinRange && own <= 256 && tpad <= pme::kTileLds &&
-        region * 4 <= pme::kBigLds &&
+        region * 4 <= pme::kGatherLds &&
         long(pme::spread_lds_bytes(int(tpad), int(range), 64, p, 2)) <= pme::kBigLds)
       break;
     int big = 0;
@@ -374,7 +374,7 @@ int pme_forward(pme_plan_t plan, void* stream, int32_t n, const float* pos, cons
   if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
                            energy != nullptr, tm.next(PME_K_BIN))) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_spread(d, s, set, false, tm.next(PME_K_SPREAD))) != hipSuccess)
+  if ((e = pme::launch_spread(d, s, set, false, box, tm.next(PME_K_SPREAD))) != hipSuccess)
     return hip_fail(e);
   if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm)) != hipSuccess)
     return hip_fail(e);
@@ -400,7 +400,7 @@ int pme_backward(pme_plan_t plan, void* stream, int32_t n, const float* pos, con
     if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
                              false, tm.next(PME_K_BIN))) != hipSuccess)
       return hip_fail(e);
-    if ((e = pme::launch_spread(d, s, set, false, tm.next(PME_K_SPREAD))) != hipSuccess)
+    if ((e = pme::launch_spread(d, s, set, false, box, tm.next(PME_K_SPREAD))) != hipSuccess)
       return hip_fail(e);
     if ((e = pme::launch_convolve(d, s, box, d.phi, false, &tm)) != hipSuccess) return hip_fail(e);
     plan->phi_valid = true;
@@ -410,7 +410,7 @@ int pme_backward(pme_plan_t plan, void* stream, int32_t n, const float* pos, con
   if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, v_pos, v_q, v_mu, true, false,
                            tm.next(PME_K_BIN_TANGENT))) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_spread(d, s, set, true, tm.next(PME_K_SPREAD_TANGENT))) != hipSuccess)
+  if ((e = pme::launch_spread(d, s, set, true, box, tm.next(PME_K_SPREAD_TANGENT))) != hipSuccess)
     return hip_fail(e);
   if ((e = pme::launch_convolve(d, s, box, d.rho, false, &tm)) != hipSuccess) return hip_fail(e);
   if ((e = pme::launch_gather_hvp(d, s, set, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q,
@@ -505,7 +505,7 @@ int batch_forward(pme_batch_s* b, hipStream_t s, const pme::BatchIO& io) {
   if ((e = pme::launch_clear_batch(b->sp, s)) != hipSuccess) return hip_fail(e);
   if ((e = pme::launch_bin_batch(b->sp, s, 0, false, io, io.energy != nullptr)) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_spread_batch(b->sp, s, 0, false)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_spread_batch(b->sp, s, 0, false, io.box)) != hipSuccess) return hip_fail(e);
   if ((e = pme::launch_convolve_batch(b->ff, s, io.box, true, io.energy != nullptr)) !=
       hipSuccess)
     return hip_fail(e);
@@ -519,7 +519,7 @@ int batch_backward(pme_batch_s* b, hipStream_t s, int set, const pme::BatchIO& i
   hipError_t e;
   if ((e = pme::launch_bin_batch(b->sp, s, set, true, io, false)) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_spread_batch(b->sp, s, set, true)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_spread_batch(b->sp, s, set, true, io.box)) != hipSuccess) return hip_fail(e);
   if ((e = pme::launch_convolve_batch(b->ff, s, io.box, false, false)) != hipSuccess)
     return hip_fail(e);
   if ((e = pme::launch_gather_batch(b->ga, s, set, true, io)) != hipSuccess) return hip_fail(e);

@@ -66,7 +66,6 @@ struct GArgs {
   int off;                 // batches: offset of the box's atoms in the packed arrays
 };
 
-constexpr int kMaxOwnBins = 256;
 
 __device__ void finalize_energy(const GArgs& a, const Cell& c) {
   __shared__ double red[8];
@@ -123,14 +122,86 @@ __device__ __forceinline__ FastDiv make_fastdiv(int d) {
   return f;
 }
 
-// Tile setup shared by both gathers: LDS staging of the field(s) over the tile plus
-// halo, and the occupied-slot counts of the tile's own bins (s_off[0..nown)) and of
-// the overflow list (s_off[nown]); all loads are issued before the first wait.
-template <int P, bool TWO>
-__device__ __forceinline__ void stage_tile(const GArgs& a, int tile, float* sm, int (&t0)[3],
-                                           int (&T)[3], int (&E)[3], int* s_off, int* s_bin,
-                                           int& nown) {
+// One tile of either gather.
+//  1. One round trip: every thread loads the record of one slot of the tile's own
+//     bins speculatively (slot e is slot e mod cap of own bin e / cap; it is used only
+//     if it is occupied), the own-bin counts, the overflow count and the field
+//     region(s) over the tile plus the stencil halo.
+//  2. Rounds of up to 256 slots: occupied slots are compacted into an LDS queue
+//     (the next round's records are loaded meanwhile) and the queue is processed
+//     with p lanes per atom.
+//  3. Overflow records whose anchor lies in the tile, the same way.
+// Queue entries: the anchor header and, forward: q, mu, atom; Hessian-vector
+// product: q, mu, v_q, v_r, v_mu, atom (the tangent record carries them).
+// Weights of stencil point j (lane-dependent) for derivative orders 0..D, from an LDS
+// copy of the coefficients of N_P (an indexed constant table would be hoisted into
+// registers for the whole kernel).
+template <int P, int D>
+__device__ __forceinline__ void weight_at_lds(const float* tab, int j, float f, float (&w)[D + 1]) {
+  const int pc = P - 1 - j;
+#pragma unroll
+  for (int d = 0; d <= D; ++d) {
+    if (d > P - 1) {
+      w[d] = 0.0f;
+      continue;
+    }
+    const float* c = &tab[(d * P + pc) * P];
+    float acc = c[P - 1];
+#pragma unroll
+    for (int k = P - 2; k >= d; --k) acc = fmaf(acc, f, c[k]);
+    w[d] = acc;
+  }
+}
+
+// What the queue needs of a record: the anchor header and, forward: q, mu, atom;
+// Hessian-vector product: (q, mu), (v_q, v_r), (v_mu, atom).
+template <bool HVP>
+struct RecRegs {
+  float4 h, r1, r2, r3;
+};
+template <>
+struct RecRegs<false> {
+  float4 h, qm;
+  int atom;
+};
+
+template <bool HVP>
+__device__ __forceinline__ RecRegs<HVP> load_rec(const float* rec, size_t ri) {
+  const float4* r = reinterpret_cast<const float4*>(rec + ri * kRecWords);
+  RecRegs<HVP> o;
+  if constexpr (HVP) {
+    o.h = r[0];
+    o.r1 = r[1];
+    o.r2 = r[2];
+    o.r3 = r[3];
+  } else {
+    const float* f = rec + ri * kRecWords;
+    o.h = r[0];
+    o.qm = make_float4(f[4], f[8], f[9], f[10]);
+    o.atom = __float_as_int(f[15]);
+  }
+  return o;
+}
+
+template <int P, bool HVP>
+__device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
+  extern __shared__ float sm[];
+  __shared__ float4 s_h[256];
+  __shared__ float4 s_qm[256];              // q, mu
+  __shared__ float4 s_v1[HVP ? 256 : 1];    // v_q, v_r
+  __shared__ float4 s_v2[HVP ? 256 : 1];    // v_mu
+  __shared__ int s_atom[256];
+  __shared__ int s_n;
+  __shared__ float s_coef[4 * P * P];       // pieces of N_P and their derivatives
   constexpr int lo = (P - 1) / 2;
+  constexpr int APW = 64 / P;
+  const int tid = threadIdx.x;
+  if (tid == 0) s_n = 0;
+  for (int k = tid; k < 4 * P * P; k += blockDim.x) s_coef[k] = c_spline.coef[spline_offset(P) + k];
+  __syncthreads();
+  const Cell c = cell_from_box(a.box);
+  if (!HVP && tile == 0 && a.energy) finalize_energy(a, c);
+  int t0[3], T[3], E[3];
   {
     int t = tile;
     const int tz = t % a.nt[2];
@@ -151,368 +222,348 @@ __device__ __forceinline__ void stage_tile(const GArgs& a, int tile, float* sm, 
     nbo[ax] = T[ax] / a.B[ax];
     kb0[ax] = t0[ax] / a.B[ax];
   }
-  nown = nbo[0] * nbo[1] * nbo[2];
-  for (int e = threadIdx.x; e < nown; e += blockDim.x) {
-    const int kz = e % nbo[2], ky = (e / nbo[2]) % nbo[1], kx = e / (nbo[1] * nbo[2]);
-    const int bin = ((kb0[0] + kx) * a.nb[1] + kb0[1] + ky) * a.nb[2] + kb0[2] + kz;
-    s_bin[e] = bin;
-    s_off[e] = min(a.count[bin], a.cap);
-  }
-  if (threadIdx.x == 0) {
-    s_bin[nown] = -1;
-    s_off[nown] = *a.ovf_count;
-  }
+  const int nown = nbo[0] * nbo[1] * nbo[2];
+  const int cap = a.cap;
+  const int nslot = nown * cap;
+  auto own_bin = [&](int j) {
+    const int kz = j % nbo[2], ky = (j / nbo[2]) % nbo[1], kx = j / (nbo[1] * nbo[2]);
+    return ((kb0[0] + kx) * a.nb[1] + kb0[1] + ky) * a.nb[2] + kb0[2] + kz;
+  };
+  auto slot_rec = [&](int e) {
+    const int j = e / cap;
+    return load_rec<HVP>(a.rec, size_t(own_bin(j)) * cap + (e - j * cap));
+  };
+  // 1. records of the first 256 slots, their bins' counts and the field region in
+  // flight together (nslot >= cap > 0: a tile holds whole bins; slots past the end
+  // load the last one again and are not used)
+  int ec = min(tid, nslot - 1);
+  RecRegs<HVP> cur = slot_rec(ec);
+  int cnt = a.count[own_bin(ec / cap)];
+  const int novf = *a.ovf_count;
   const int EV = E[0] * E[1] * E[2];
-  const FastDiv d2 = make_fastdiv(E[2]), d1 = make_fastdiv(E[1]);
-  const bool small = (a.N[0] < P) || (a.N[1] < P) || (a.N[2] < P);
-  constexpr int U = 16;   // loads kept in flight per thread
-  for (int e0 = threadIdx.x; e0 < EV; e0 += U * blockDim.x) {
-    float vphi[U], vpsi[U];
+  {
+    const FastDiv d2 = make_fastdiv(E[2]), d1 = make_fastdiv(E[1]);
+    const bool small = (a.N[0] < P) || (a.N[1] < P) || (a.N[2] < P);
+    constexpr int U = 16;   // loads kept in flight per thread
+    for (int e0 = tid; e0 < EV; e0 += U * blockDim.x) {
+      float vphi[U], vpsi[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * blockDim.x;
-      const int ec = min(e, EV - 1);
-      const int r = int(fdiv(uint32_t(ec), d2)), ez = ec - r * E[2];
-      const int ex = int(fdiv(uint32_t(r), d1)), ey = r - ex * E[1];
-      int mx = t0[0] - lo + ex, my = t0[1] - lo + ey, mz = t0[2] - lo + ez;
-      if (small) {
-        mx = wrapn(mx, a.N[0]); my = wrapn(my, a.N[1]); mz = wrapn(mz, a.N[2]);
-      } else {
-        mx = (mx < 0) ? mx + a.N[0] : ((mx >= a.N[0]) ? mx - a.N[0] : mx);
-        my = (my < 0) ? my + a.N[1] : ((my >= a.N[1]) ? my - a.N[1] : my);
-        mz = (mz < 0) ? mz + a.N[2] : ((mz >= a.N[2]) ? mz - a.N[2] : mz);
-      }
-      const size_t g = (size_t(mx) * a.N[1] + my) * a.N[2] + mz;
-      vphi[u] = a.phi[g];
-      if (TWO) vpsi[u] = a.psi[g];
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * blockDim.x;
-      if (e < EV) {
-        sm[e] = vphi[u];
-        if (TWO) sm[EV + e] = vpsi[u];
-      }
-    }
-  }
-  __syncthreads();
-  // exclusive scan of s_off[0..nown] (wavefront 0)
-  if (threadIdx.x < 64) {
-    const int tid = threadIdx.x;
-    const int len = nown + 1;
-    const int seg = (len + 63) / 64;
-    const int s0 = min(tid * seg, len), s1 = min(s0 + seg, len);
-    int acc = 0;
-    for (int e = s0; e < s1; ++e) acc += s_off[e];
-    int incl = acc;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int v = __shfl_up(incl, o, 64);
-      if (tid >= o) incl += v;
-    }
-    int run = incl - acc;
-    for (int e = s0; e < s1; ++e) { const int v = s_off[e]; s_off[e] = run; run += v; }
-    if (tid == 63) s_off[len] = incl;
-  }
-  __syncthreads();
-}
-
-// Record of item `item` of the tile's slot space and whether the tile owns the atom
-// (own-bin records always; overflow records when their anchor lies in the tile).
-__device__ __forceinline__ const float4* item_record(const GArgs& a, int item, int nown,
-                                                     const int* s_off, const int* s_bin,
-                                                     const int (&t0)[3], const int (&T)[3],
-                                                     bool& owned) {
-  int lo_i = 0, hi_i = nown;
-  while (lo_i < hi_i) {
-    const int mid = (lo_i + hi_i + 1) >> 1;
-    if (s_off[mid] <= item) lo_i = mid; else hi_i = mid - 1;
-  }
-  const int bin = s_bin[lo_i];
-  const int slot = item - s_off[lo_i];
-  const size_t ri = (bin >= 0) ? size_t(bin) * a.cap + slot : size_t(a.ovf_base) + slot;
-  const float4* r = reinterpret_cast<const float4*>(a.rec + ri * kRecWords);
-  owned = true;
-  if (bin < 0) {
-    const int pk = __float_as_int(r[0].w);
-    const int b0 = pk & 1023, b1 = (pk >> 10) & 1023, b2 = (pk >> 20) & 1023;
-    owned = b0 >= t0[0] && b0 < t0[0] + T[0] && b1 >= t0[1] && b1 < t0[1] + T[1] &&
-            b2 >= t0[2] && b2 < t0[2] + T[2];
-  }
-  return r;
-}
-
-template <int P>
-__device__ __forceinline__ void gather_body(const GArgs& a, const int tile) {
-  extern __shared__ float sm[];
-  __shared__ int s_off[kMaxOwnBins + 2];
-  __shared__ int s_bin[kMaxOwnBins + 1];
-  constexpr int APW = 64 / P;
-  const Cell c = cell_from_box(a.box);
-  if (tile == 0 && a.energy) finalize_energy(a, c);
-  int t0[3], T[3], E[3], nown;
-  stage_tile<P, false>(a, tile, sm, t0, T, E, s_off, s_bin, nown);
-  const int total = s_off[nown + 1];
-  float J[3][3];
-  jacobian(c, a.N, J);
-  const float iv = float(1.0 / c.vol);
-  const float pf = float(a.prefactor);
-  const float cq = float(2.0 * a.alpha / sqrt(M_PI));
-  const float cm = float(4.0 * a.alpha * a.alpha * a.alpha / (3.0 * sqrt(M_PI)));
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int gslot = lane / P, ix = lane - gslot * P;
-  for (int b0 = 0; b0 < total; b0 += 4 * APW) {
-    const int item = b0 + wave * APW + gslot;
-    bool active = (gslot < APW) && (item < total);
-    float S000 = 0, S100 = 0, S010 = 0, S001 = 0, S200 = 0, S020 = 0, S002 = 0, S110 = 0,
-          S101 = 0, S011 = 0;
-    int atom = 0;
-    float q = 0.f;
-    float3 mu = make_float3(0.f, 0.f, 0.f);
-    if (active) {
-      bool owned;
-      const float4* r = item_record(a, item, nown, s_off, s_bin, t0, T, owned);
-      active = owned;
-      const float4 h = r[0], rq = r[1], rm = r[2], ri = r[3];
-      atom = __float_as_int(ri.w);
-      q = rq.x;
-      mu = make_float3(rm.x, rm.y, rm.z);
-      if (active) {
-        const int pk = __float_as_int(h.w);
-        const int lx = (pk & 1023) - t0[0] + ix;
-        const int yb = ((pk >> 10) & 1023) - t0[1], zb = ((pk >> 20) & 1023) - t0[2];
-        float wy[3][P], wz[3][P], wx[3];
-        spline_weights<P, 2>(h.y, wy);
-        spline_weights<P, 2>(h.z, wz);
-        spline_weight_at<P, 2>(ix, h.x, wx);
-        const float* plane = sm + (lx * E[1] + yb) * E[2] + zb;
-        float Y00 = 0, Y01 = 0, Y02 = 0, Y10 = 0, Y11 = 0, Y20 = 0;
-#pragma unroll
-        for (int iy = 0; iy < P; ++iy) {
-          const float* row = plane + iy * E[2];
-          float z0 = 0, z1 = 0, z2 = 0;
-#pragma unroll
-          for (int iz = 0; iz < P; ++iz) {
-            const float v = row[iz];
-            z0 = fmaf(v, wz[0][iz], z0);
-            z1 = fmaf(v, wz[1][iz], z1);
-            z2 = fmaf(v, wz[2][iz], z2);
-          }
-          Y00 = fmaf(wy[0][iy], z0, Y00);
-          Y01 = fmaf(wy[0][iy], z1, Y01);
-          Y02 = fmaf(wy[0][iy], z2, Y02);
-          Y10 = fmaf(wy[1][iy], z0, Y10);
-          Y11 = fmaf(wy[1][iy], z1, Y11);
-          Y20 = fmaf(wy[2][iy], z0, Y20);
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * blockDim.x;
+        const int ec = min(e, EV - 1);
+        const int r = int(fdiv(uint32_t(ec), d2)), ez = ec - r * E[2];
+        const int ex = int(fdiv(uint32_t(r), d1)), ey = r - ex * E[1];
+        int mx = t0[0] - lo + ex, my = t0[1] - lo + ey, mz = t0[2] - lo + ez;
+        if (small) {
+          mx = wrapn(mx, a.N[0]); my = wrapn(my, a.N[1]); mz = wrapn(mz, a.N[2]);
+        } else {
+          mx = (mx < 0) ? mx + a.N[0] : ((mx >= a.N[0]) ? mx - a.N[0] : mx);
+          my = (my < 0) ? my + a.N[1] : ((my >= a.N[1]) ? my - a.N[1] : my);
+          mz = (mz < 0) ? mz + a.N[2] : ((mz >= a.N[2]) ? mz - a.N[2] : mz);
         }
-        S000 = wx[0] * Y00; S001 = wx[0] * Y01; S002 = wx[0] * Y02;
-        S010 = wx[0] * Y10; S011 = wx[0] * Y11; S020 = wx[0] * Y20;
-        S100 = wx[1] * Y00; S101 = wx[1] * Y01; S110 = wx[1] * Y10;
-        S200 = wx[2] * Y00;
+        const size_t g = (size_t(mx) * a.N[1] + my) * a.N[2] + mz;
+        vphi[u] = a.phi[g];
+        if (HVP) vpsi[u] = a.psi[g];
       }
-    }
-    S000 = group_sum<P>(S000, ix); S100 = group_sum<P>(S100, ix);
-    S010 = group_sum<P>(S010, ix); S001 = group_sum<P>(S001, ix);
-    S200 = group_sum<P>(S200, ix); S020 = group_sum<P>(S020, ix);
-    S002 = group_sum<P>(S002, ix); S110 = group_sum<P>(S110, ix);
-    S101 = group_sum<P>(S101, ix); S011 = group_sum<P>(S011, ix);
-    if (active && ix == 0) {
-      const int i = atom;
-      const float3 d = jmul(J, mu);
-      const float3 G = make_float3(S100, S010, S001);
-      const float3 Hd = make_float3(S200 * d.x + S110 * d.y + S101 * d.z,
-                                    S110 * d.x + S020 * d.y + S011 * d.z,
-                                    S101 * d.x + S011 * d.y + S002 * d.z);
-      if (a.o_q) a.o_q[i] = pf * (S000 * iv - cq * q);
-      if (a.o_mu) {
-        const float3 g = jtmul(J, G);
-        st3(a.o_mu, i, make_float3(pf * (g.x * iv - cm * mu.x), pf * (g.y * iv - cm * mu.y),
-                                   pf * (g.z * iv - cm * mu.z)));
-      }
-      if (a.o_pos) {
-        const float3 g = jtmul(J, make_float3(q * G.x + Hd.x, q * G.y + Hd.y, q * G.z + Hd.z));
-        st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * blockDim.x;
+        if (e < EV) {
+          sm[e] = vphi[u];
+          if (HVP) sm[EV + e] = vpsi[u];
+        }
       }
     }
   }
-}
-
-template <int P>
-__device__ __forceinline__ void gather_hvp_body(const GArgs& a, const int tile) {
-  extern __shared__ float sm[];
-  __shared__ int s_off[kMaxOwnBins + 2];
-  __shared__ int s_bin[kMaxOwnBins + 1];
-  constexpr int APW = 64 / P;
-  const Cell c = cell_from_box(a.box);
-  int t0[3], T[3], E[3], nown;
-  stage_tile<P, true>(a, tile, sm, t0, T, E, s_off, s_bin, nown);
-  const int EV = E[0] * E[1] * E[2];
-  const int total = s_off[nown + 1];
+  // cell and prefactor constants are uniform: kept in scalar registers
   float J[3][3];
   jacobian(c, a.N, J);
-  const float iv = float(1.0 / c.vol);
-  const float pf = float(a.prefactor);
-  const float cq = float(2.0 * a.alpha / sqrt(M_PI));
-  const float cm = float(4.0 * a.alpha * a.alpha * a.alpha / (3.0 * sqrt(M_PI)));
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) J[i][j] = uniform(J[i][j]);
+  const float iv = uniform(float(1.0 / c.vol));
+  const float pf = uniform(float(a.prefactor));
+  const float cq = uniform(float(2.0 * a.alpha / sqrt(M_PI)));
+  const float cm = uniform(float(4.0 * a.alpha * a.alpha * a.alpha / (3.0 * sqrt(M_PI))));
+  const int lane = tid & 63, wave = tid >> 6;
   const int gslot = lane / P, ix = lane - gslot * P;
-  {   // atoms in groups of 4 wavefronts x APW
-    for (int b0 = 0; b0 < total; b0 += 4 * APW) {
-      const int item = b0 + wave * APW + gslot;
-      bool active = (gslot < APW) && (item < total);
-      // phi sums S_abc (1 <= a+b+c <= 3) and psi sums Q_abc (a+b+c <= 2)
-      float S[4][4][4];
-      float Q[3][3][3];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-#pragma unroll
-          for (int z = 0; z < 4; ++z) S[x][y][z] = 0.0f;
-#pragma unroll
-      for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int y = 0; y < 3; ++y)
-#pragma unroll
-          for (int z = 0; z < 3; ++z) Q[x][y][z] = 0.0f;
-      int atom = 0;
-      float q = 0.f, vq = 0.f;
-      float3 mu = make_float3(0.f, 0.f, 0.f), vr = mu, vm = mu;
-      float4 h = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (active) {
-        bool owned;
-        const float4* r = item_record(a, item, nown, s_off, s_bin, t0, T, owned);
-        active = owned;
-        h = r[0];
-        atom = __float_as_int(r[3].w);
-        // per-atom inputs fetched before the stencil work so their latency overlaps it
-        q = a.q ? a.q[atom] : 0.0f;
-        mu = ld3(a.mu, atom);
-        vq = a.v_q ? a.v_q[atom] : 0.0f;
-        vr = ld3(a.v_pos, atom);
-        vm = ld3(a.v_mu, atom);
+
+  auto enqueue = [&](bool valid, const RecRegs<HVP>& r) {
+    const int k = wave_compact(valid, &s_n);
+    if (valid) {
+      s_h[k] = r.h;
+      if constexpr (HVP) {
+        s_qm[k] = r.r1;
+        s_v1[k] = r.r2;
+        s_v2[k] = r.r3;
+        s_atom[k] = __float_as_int(r.r3.w);
+      } else {
+        s_qm[k] = r.qm;
+        s_atom[k] = r.atom;
       }
-      if (active) {
-        const int pk = __float_as_int(h.w);
-        const int lx = (pk & 1023) - t0[0] + ix;
-        const int yb = ((pk >> 10) & 1023) - t0[1], zb = ((pk >> 20) & 1023) - t0[2];
-        float wy[4][P], wz[4][P], wx[4];
-        spline_weights<P, 3>(h.y, wy);
-        spline_weights<P, 3>(h.z, wz);
-        spline_weight_at<P, 3>(ix, h.x, wx);
-        const float* pphi = sm + (lx * E[1] + yb) * E[2] + zb;
-        const float* ppsi = pphi + EV;
-        float Ys[4][4], Yq[3][3];
+    }
+  };
+  auto process = [&](int nq) {
+    for (int b0 = 0; b0 < nq; b0 += 4 * APW) {
+      const int slot = b0 + wave * APW + gslot;
+      const bool active = (gslot < APW) && (slot < nq);
+      if (!HVP) {
+        float S000 = 0, S100 = 0, S010 = 0, S001 = 0, S200 = 0, S020 = 0, S002 = 0, S110 = 0,
+              S101 = 0, S011 = 0;
+        if (active) {
+          const float4 h = s_h[slot];
+          const int pk = __float_as_int(h.w);
+          const int lx = (pk & 1023) - t0[0] + ix;
+          const int yb = ((pk >> 10) & 1023) - t0[1], zb = ((pk >> 20) & 1023) - t0[2];
+          // y weights are made per row (fewer live registers), z weights once
+          float wz[3][P], wx[3];
+          spline_weights<P, 2>(h.z, wz);
+          weight_at_lds<P, 2>(s_coef, ix, h.x, wx);
+          const float* plane = sm + (lx * E[1] + yb) * E[2] + zb;
+          float Y00 = 0, Y01 = 0, Y02 = 0, Y10 = 0, Y11 = 0, Y20 = 0;
 #pragma unroll
-        for (int y = 0; y < 4; ++y)
+          for (int iy = 0; iy < P; ++iy) {
+            const float* row = plane + iy * E[2];
+            float z0 = 0, z1 = 0, z2 = 0;
 #pragma unroll
-          for (int z = 0; z < 4; ++z) Ys[y][z] = 0.0f;
+            for (int iz = 0; iz < P; ++iz) {
+              const float v = row[iz];
+              z0 = fmaf(v, wz[0][iz], z0);
+              z1 = fmaf(v, wz[1][iz], z1);
+              z2 = fmaf(v, wz[2][iz], z2);
+            }
+            float wy[3];
+            spline_weight_at<P, 2>(iy, h.y, wy);
+            Y00 = fmaf(wy[0], z0, Y00);
+            Y01 = fmaf(wy[0], z1, Y01);
+            Y02 = fmaf(wy[0], z2, Y02);
+            Y10 = fmaf(wy[1], z0, Y10);
+            Y11 = fmaf(wy[1], z1, Y11);
+            Y20 = fmaf(wy[2], z0, Y20);
+          }
+          S000 = wx[0] * Y00; S001 = wx[0] * Y01; S002 = wx[0] * Y02;
+          S010 = wx[0] * Y10; S011 = wx[0] * Y11; S020 = wx[0] * Y20;
+          S100 = wx[1] * Y00; S101 = wx[1] * Y01; S110 = wx[1] * Y10;
+          S200 = wx[2] * Y00;
+        }
+        S000 = group_sum<P>(S000, ix); S100 = group_sum<P>(S100, ix);
+        S010 = group_sum<P>(S010, ix); S001 = group_sum<P>(S001, ix);
+        S200 = group_sum<P>(S200, ix); S020 = group_sum<P>(S020, ix);
+        S002 = group_sum<P>(S002, ix); S110 = group_sum<P>(S110, ix);
+        S101 = group_sum<P>(S101, ix); S011 = group_sum<P>(S011, ix);
+        if (active && ix == 0) {
+          const int i = s_atom[slot];
+          const float4 qmv = s_qm[slot];
+          const float q = qmv.x;
+          const float3 mu = make_float3(qmv.y, qmv.z, qmv.w);
+          const float3 d = jmul(J, mu);
+          const float3 G = make_float3(S100, S010, S001);
+          const float3 Hd = make_float3(S200 * d.x + S110 * d.y + S101 * d.z,
+                                        S110 * d.x + S020 * d.y + S011 * d.z,
+                                        S101 * d.x + S011 * d.y + S002 * d.z);
+          if (a.o_q) a.o_q[i] = pf * (S000 * iv - cq * q);
+          if (a.o_mu) {
+            const float3 g = jtmul(J, G);
+            st3(a.o_mu, i, make_float3(pf * (g.x * iv - cm * mu.x), pf * (g.y * iv - cm * mu.y),
+                                       pf * (g.z * iv - cm * mu.z)));
+          }
+          if (a.o_pos) {
+            const float3 g = jtmul(J, make_float3(q * G.x + Hd.x, q * G.y + Hd.y, q * G.z + Hd.z));
+            st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+          }
+        }
+      } else {
+        // phi sums S_abc (1 <= a+b+c <= 3) and psi sums Q_abc (a+b+c <= 2)
+        float S[4][4][4];
+        float Q[3][3][3];
 #pragma unroll
-        for (int y = 0; y < 3; ++y)
+        for (int x = 0; x < 4; ++x)
 #pragma unroll
-          for (int z = 0; z < 3; ++z) Yq[y][z] = 0.0f;
+          for (int y = 0; y < 4; ++y)
 #pragma unroll
-        for (int iy = 0; iy < P; ++iy) {
-          float zs[4] = {0, 0, 0, 0}, zq[3] = {0, 0, 0};
+            for (int z = 0; z < 4; ++z) S[x][y][z] = 0.0f;
 #pragma unroll
-          for (int iz = 0; iz < P; ++iz) {
-            const float v = pphi[iy * E[2] + iz], u = ppsi[iy * E[2] + iz];
+        for (int x = 0; x < 3; ++x)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) zs[k] = fmaf(v, wz[k][iz], zs[k]);
+          for (int y = 0; y < 3; ++y)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) zq[k] = fmaf(u, wz[k][iz], zq[k]);
+            for (int z = 0; z < 3; ++z) Q[x][y][z] = 0.0f;
+        if (active) {
+          const float4 h = s_h[slot];
+          const int pk = __float_as_int(h.w);
+          const int lx = (pk & 1023) - t0[0] + ix;
+          const int yb = ((pk >> 10) & 1023) - t0[1], zb = ((pk >> 20) & 1023) - t0[2];
+          float wy[4][P], wz[4][P], wx[4];
+          spline_weights<P, 3>(h.y, wy);
+          spline_weights<P, 3>(h.z, wz);
+          weight_at_lds<P, 3>(s_coef, ix, h.x, wx);
+          const float* pphi = sm + (lx * E[1] + yb) * E[2] + zb;
+          const float* ppsi = pphi + EV;
+          float Ys[4][4], Yq[3][3];
+#pragma unroll
+          for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int z = 0; z < 4; ++z) Ys[y][z] = 0.0f;
+#pragma unroll
+          for (int y = 0; y < 3; ++y)
+#pragma unroll
+            for (int z = 0; z < 3; ++z) Yq[y][z] = 0.0f;
+#pragma unroll
+          for (int iy = 0; iy < P; ++iy) {
+            float zs[4] = {0, 0, 0, 0}, zq[3] = {0, 0, 0};
+#pragma unroll
+            for (int iz = 0; iz < P; ++iz) {
+              const float v = pphi[iy * E[2] + iz], u = ppsi[iy * E[2] + iz];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) zs[k] = fmaf(v, wz[k][iz], zs[k]);
+#pragma unroll
+              for (int k = 0; k < 3; ++k) zq[k] = fmaf(u, wz[k][iz], zq[k]);
+            }
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+              for (int k = 0; k + b < 4; ++k) Ys[b][k] = fmaf(wy[b][iy], zs[k], Ys[b][k]);
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+              for (int k = 0; k + b < 3; ++k) Yq[b][k] = fmaf(wy[b][iy], zq[k], Yq[b][k]);
           }
 #pragma unroll
-          for (int b = 0; b < 4; ++b)
+          for (int x = 0; x < 4; ++x)
 #pragma unroll
-            for (int k = 0; k + b < 4; ++k) Ys[b][k] = fmaf(wy[b][iy], zs[k], Ys[b][k]);
+            for (int b = 0; b + x < 4; ++b)
 #pragma unroll
-          for (int b = 0; b < 3; ++b)
+              for (int k = 0; k + b + x < 4; ++k) S[x][b][k] = wx[x] * Ys[b][k];
 #pragma unroll
-            for (int k = 0; k + b < 3; ++k) Yq[b][k] = fmaf(wy[b][iy], zq[k], Yq[b][k]);
+          for (int x = 0; x < 3; ++x)
+#pragma unroll
+            for (int b = 0; b + x < 3; ++b)
+#pragma unroll
+              for (int k = 0; k + b + x < 3; ++k) Q[x][b][k] = wx[x] * Yq[b][k];
         }
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
           for (int b = 0; b + x < 4; ++b)
 #pragma unroll
-            for (int k = 0; k + b + x < 4; ++k) S[x][b][k] = wx[x] * Ys[b][k];
+            for (int k = 0; k + b + x < 4; ++k)
+              if (x + b + k >= 1) S[x][b][k] = group_sum<P>(S[x][b][k], ix);
 #pragma unroll
         for (int x = 0; x < 3; ++x)
 #pragma unroll
           for (int b = 0; b + x < 3; ++b)
 #pragma unroll
-            for (int k = 0; k + b + x < 3; ++k) Q[x][b][k] = wx[x] * Yq[b][k];
-      }
+            for (int k = 0; k + b + x < 3; ++k) Q[x][b][k] = group_sum<P>(Q[x][b][k], ix);
+        if (active && ix == 0) {
+          const int i = s_atom[slot];
+          const float4 qm = s_qm[slot], e1 = s_v1[slot], e2 = s_v2[slot];
+          const float q = qm.x, vq = e1.x;
+          const float3 mu = make_float3(qm.y, qm.z, qm.w);
+          const float3 vr = make_float3(e1.y, e1.z, e1.w);
+          const float3 vm = make_float3(e2.x, e2.y, e2.z);
+          const float3 d3 = jmul(J, mu);
+          const float3 v3 = jmul(J, vr);
+          const float3 w3 = jmul(J, make_float3(vm.x + q * vr.x, vm.y + q * vr.y, vm.z + q * vr.z));
+          const float d[3] = {d3.x, d3.y, d3.z}, v[3] = {v3.x, v3.y, v3.z};
+          const float w[3] = {w3.x, w3.y, w3.z};
+          float S1[3], P1[3], S2[3][3], P2[3][3];
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+          for (int x = 0; x < 3; ++x) {
+            const int ex[3] = {x == 0, x == 1, x == 2};
+            S1[x] = S[ex[0]][ex[1]][ex[2]];
+            P1[x] = Q[ex[0]][ex[1]][ex[2]];
 #pragma unroll
-        for (int b = 0; b + x < 4; ++b)
-#pragma unroll
-          for (int k = 0; k + b + x < 4; ++k)
-            if (x + b + k >= 1) S[x][b][k] = group_sum<P>(S[x][b][k], ix);
-#pragma unroll
-      for (int x = 0; x < 3; ++x)
-#pragma unroll
-        for (int b = 0; b + x < 3; ++b)
-#pragma unroll
-          for (int k = 0; k + b + x < 3; ++k) Q[x][b][k] = group_sum<P>(Q[x][b][k], ix);
-      if (active && ix == 0) {
-        const int i = atom;
-        const float3 d3 = jmul(J, mu);
-        const float3 v3 = jmul(J, vr);
-        const float3 w3 = jmul(J, make_float3(vm.x + q * vr.x, vm.y + q * vr.y, vm.z + q * vr.z));
-        const float d[3] = {d3.x, d3.y, d3.z}, v[3] = {v3.x, v3.y, v3.z}, w[3] = {w3.x, w3.y, w3.z};
-        float S1[3], P1[3], S2[3][3], P2[3][3];
-#pragma unroll
-        for (int x = 0; x < 3; ++x) {
-          const int ex[3] = {x == 0, x == 1, x == 2};
-          S1[x] = S[ex[0]][ex[1]][ex[2]];
-          P1[x] = Q[ex[0]][ex[1]][ex[2]];
-#pragma unroll
-          for (int y = 0; y < 3; ++y) {
-            const int e0 = ex[0] + (y == 0), e1 = ex[1] + (y == 1), e2 = ex[2] + (y == 2);
-            S2[x][y] = S[e0][e1][e2];
-            P2[x][y] = Q[e0][e1][e2];
-          }
-        }
-        float T3[3] = {0, 0, 0};   // S3(d, v, .)
-#pragma unroll
-        for (int x = 0; x < 3; ++x)
-#pragma unroll
-          for (int y = 0; y < 3; ++y)
-#pragma unroll
-            for (int z = 0; z < 3; ++z) {
-              const int e0 = (x == 0) + (y == 0) + (z == 0);
-              const int e1 = (x == 1) + (y == 1) + (z == 1);
-              const int e2 = (x == 2) + (y == 2) + (z == 2);
-              T3[z] = fmaf(d[x] * v[y], S[e0][e1][e2], T3[z]);
+            for (int y = 0; y < 3; ++y) {
+              const int e0 = ex[0] + (y == 0), e1i = ex[1] + (y == 1), e2i = ex[2] + (y == 2);
+              S2[x][y] = S[e0][e1i][e2i];
+              P2[x][y] = Q[e0][e1i][e2i];
             }
-        const float P0 = Q[0][0][0];
-        if (a.o_q) {
-          const float sq = P0 + S1[0] * v[0] + S1[1] * v[1] + S1[2] * v[2];
-          a.o_q[i] = pf * (sq * iv - cq * vq);
-        }
-        if (a.o_mu) {
-          float u[3];
-#pragma unroll
-          for (int x = 0; x < 3; ++x) u[x] = P1[x] + S2[x][0] * v[0] + S2[x][1] * v[1] + S2[x][2] * v[2];
-          const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
-          st3(a.o_mu, i, make_float3(pf * (g.x * iv - cm * vm.x), pf * (g.y * iv - cm * vm.y),
-                                     pf * (g.z * iv - cm * vm.z)));
-        }
-        if (a.o_pos) {
-          float u[3];
+          }
+          float T3[3] = {0, 0, 0};   // S3(d, v, .)
 #pragma unroll
           for (int x = 0; x < 3; ++x)
-            u[x] = q * P1[x] + P2[x][0] * d[0] + P2[x][1] * d[1] + P2[x][2] * d[2] + vq * S1[x] +
-                   S2[x][0] * w[0] + S2[x][1] * w[1] + S2[x][2] * w[2] + T3[x];
-          const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
-          st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+#pragma unroll
+            for (int y = 0; y < 3; ++y)
+#pragma unroll
+              for (int z = 0; z < 3; ++z) {
+                const int e0 = (x == 0) + (y == 0) + (z == 0);
+                const int e1i = (x == 1) + (y == 1) + (z == 1);
+                const int e2i = (x == 2) + (y == 2) + (z == 2);
+                T3[z] = fmaf(d[x] * v[y], S[e0][e1i][e2i], T3[z]);
+              }
+          const float P0 = Q[0][0][0];
+          if (a.o_q) {
+            const float sq = P0 + S1[0] * v[0] + S1[1] * v[1] + S1[2] * v[2];
+            a.o_q[i] = pf * (sq * iv - cq * vq);
+          }
+          if (a.o_mu) {
+            float u[3];
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+              u[x] = P1[x] + S2[x][0] * v[0] + S2[x][1] * v[1] + S2[x][2] * v[2];
+            const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
+            st3(a.o_mu, i, make_float3(pf * (g.x * iv - cm * vm.x), pf * (g.y * iv - cm * vm.y),
+                                       pf * (g.z * iv - cm * vm.z)));
+          }
+          if (a.o_pos) {
+            float u[3];
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+              u[x] = q * P1[x] + P2[x][0] * d[0] + P2[x][1] * d[1] + P2[x][2] * d[2] +
+                     vq * S1[x] + S2[x][0] * w[0] + S2[x][1] * w[1] + S2[x][2] * w[2] + T3[x];
+            const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
+            st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+          }
         }
       }
     }
+  };
+
+  // 2. rounds of 256 own-bin slots, then of 256 overflow records (those anchored in
+  // the tile are owned); one round is compacted into the queue while the previous
+  // one has been processed, so that no record registers live across the stencil work
+  enqueue(tid < nslot && ec % cap < cnt, cur);
+  __syncthreads();
+  const int nrs = (nslot + 255) >> 8;
+  const int nr = nrs + ((novf + 255) >> 8);
+  for (int r = 0;;) {
+    process(s_n);
+    if (++r >= nr) break;
+    __syncthreads();   // the queue has been read
+    if (tid == 0) s_n = 0;
+    bool valid = false;
+    RecRegs<HVP> rec;
+    if (r < nrs) {
+      const int e = r * 256 + tid;
+      ec = min(e, nslot - 1);
+      rec = slot_rec(ec);
+      cnt = a.count[own_bin(ec / cap)];
+      valid = e < nslot && ec % cap < cnt;
+    } else {
+      const int o = (r - nrs) * 256 + tid;
+      if (o < novf) {
+        rec = load_rec<HVP>(a.rec, size_t(a.ovf_base) + o);
+        const int pk = __float_as_int(rec.h.w);
+        const int b0 = pk & 1023, b1 = (pk >> 10) & 1023, b2 = (pk >> 20) & 1023;
+        valid = b0 >= t0[0] && b0 < t0[0] + T[0] && b1 >= t0[1] && b1 < t0[1] + T[1] &&
+                b2 >= t0[2] && b2 < t0[2] + T[2];
+      }
+    }
+    __syncthreads();   // s_n is cleared
+    enqueue(valid, rec);
+    __syncthreads();
   }
+}
+
+template <int P>
+__device__ __forceinline__ void gather_body(const GArgs& a, const int tile) {
+  gather_tile<P, false>(a, tile);
+}
+
+template <int P>
+__device__ __forceinline__ void gather_hvp_body(const GArgs& a, const int tile) {
+  gather_tile<P, true>(a, tile);
 }
 
 template <int P>
@@ -614,7 +665,7 @@ hipError_t enable_gather_lds() {
 #undef PME_G
   };
   for (const void* f : fns) {
-    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kBigLds);
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kGatherLds);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

@@ -12,7 +12,9 @@ namespace pme {
 constexpr int kMaxStages = 16;
 constexpr int kMaxBinRange = 2048;   // bins a spread tile may scan (LDS count array)
 constexpr int kTileLds = 8192;       // max padded spread-tile points: T_x T_y (T_z + 1)
-constexpr int kBigLds = 150 * 1024;  // dynamic LDS limit of the spread and gather kernels
+constexpr int kBigLds = 150 * 1024;  // dynamic LDS limit of the spread kernels
+constexpr int kGatherStaticLds = 20 * 1024;            // bound on the gathers' static LDS
+constexpr int kGatherLds = 160 * 1024 - kGatherStaticLds;  // their dynamic LDS limit
 
 // LDS words of one staged spread entry: weights of three axes (derivative orders up
 // to deg), the assignment coefficients, the tile-local stencil coordinates and the
@@ -190,7 +192,8 @@ void gather_batch_free(GatherBatch& t);
 hipError_t launch_clear_batch(const SpreadBatch& t, hipStream_t s);
 hipError_t launch_bin_batch(const SpreadBatch& t, hipStream_t s, int set, bool tangent,
                             const BatchIO& io, bool self_sums);
-hipError_t launch_spread_batch(const SpreadBatch& t, hipStream_t s, int set, bool tangent);
+hipError_t launch_spread_batch(const SpreadBatch& t, hipStream_t s, int set, bool tangent,
+                               const double* box);
 hipError_t launch_convolve_batch(const FFTBatch& t, hipStream_t s, const double* box, bool to_phi,
                                  bool energy);
 hipError_t launch_gather_batch(const GatherBatch& t, hipStream_t s, int set, bool hvp,
@@ -214,11 +217,11 @@ hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const flo
                       const LaunchEvents* ev);
 // Owner-computes spread of the binned records (counter set `set`) into d.rho.
 hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
-                         const LaunchEvents* ev);
+                         const double* box, const LaunchEvents* ev);
 // rho -> spec -> (x g) -> out, the mesh operator K; energy partials when wanted.
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
                            bool energy, KTimer* tm);
-// Allow the spread and gather kernels up to kBigLds of dynamic LDS.
+// Raise the dynamic LDS limit of the spread (kBigLds) and gather (kGatherLds) kernels.
 hipError_t enable_spread_lds();
 hipError_t enable_gather_lds();
 // Allow slab workgroups up to kSlabLdsMax of dynamic LDS (above the 64 KiB

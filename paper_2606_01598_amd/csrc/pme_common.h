@@ -117,6 +117,11 @@ __device__ __forceinline__ void spline_weight_at(int j, float f, float (&w)[D + 
   }
 }
 
+// A value the caller knows to be the same in every lane, moved to a scalar register.
+__device__ __forceinline__ float uniform(float v) {
+  return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // ---------------------------------------------------------------------------
 // cell geometry
 // ---------------------------------------------------------------------------

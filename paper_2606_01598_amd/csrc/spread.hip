@@ -69,6 +69,23 @@ __device__ __forceinline__ float3 jmul(const float (&J)[3][3], float3 v) {
                      J[2][0] * v.x + J[2][1] * v.y + J[2][2] * v.z);
 }
 
+// Coefficients of the tangent density of the Hessian-vector product:
+// rho_dot = v_q W + w.grad_x W + d^T (grad_x grad_x W) v with d = J mu,
+// v = J v_r, w = J (v_mu + q v_r); monomials 000, 100, 010, 001, 200, 020, 002,
+// 110, 101, 011.
+__device__ __forceinline__ void tangent_coeffs(const float (&J)[3][3], float q, float3 mu, float vq,
+                                               float3 vr, float3 vm, float (&co)[10]) {
+  const float3 d = jmul(J, mu);
+  const float3 w = jmul(J, make_float3(vm.x + q * vr.x, vm.y + q * vr.y, vm.z + q * vr.z));
+  const float3 v = jmul(J, vr);
+  co[0] = vq;
+  co[1] = w.x; co[2] = w.y; co[3] = w.z;
+  co[4] = d.x * v.x; co[5] = d.y * v.y; co[6] = d.z * v.z;
+  co[7] = d.x * v.y + d.y * v.x;
+  co[8] = d.x * v.z + d.z * v.x;
+  co[9] = d.y * v.z + d.z * v.y;
+}
+
 template <int P, bool TANGENT>
 __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
   __shared__ double red[8];
@@ -102,19 +119,7 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
       if (!TANGENT) {
         co[0] = q; co[1] = d.x; co[2] = d.y; co[3] = d.z;
       } else {
-        // rho_dot = v_q W + w.grad_x W + d^T (grad_x grad_x W) v,
-        // w = J (v_mu + q v_r), v = J v_r, d = J mu
-        const float vq = a.v_q ? a.v_q[i] : 0.0f;
-        const float3 vr = ld3(a.v_pos, i);
-        const float3 vm = ld3(a.v_mu, i);
-        const float3 w = jmul(J, make_float3(vm.x + q * vr.x, vm.y + q * vr.y, vm.z + q * vr.z));
-        const float3 v = jmul(J, vr);
-        co[0] = vq;
-        co[1] = w.x; co[2] = w.y; co[3] = w.z;
-        co[4] = d.x * v.x; co[5] = d.y * v.y; co[6] = d.z * v.z;     // 200 020 002
-        co[7] = d.x * v.y + d.y * v.x;                               // 110
-        co[8] = d.x * v.z + d.z * v.x;                               // 101
-        co[9] = d.y * v.z + d.z * v.y;                               // 011
+        tangent_coeffs(J, q, mu, a.v_q ? a.v_q[i] : 0.0f, ld3(a.v_pos, i), ld3(a.v_mu, i), co);
       }
       constexpr int nc = TANGENT ? 10 : 4;
       float amax = 0.0f;
@@ -131,11 +136,17 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
       float4* d4 = reinterpret_cast<float4*>(a.rec + ri * kRecWords);
       d4[0] = make_float4(f[0], f[1], f[2],
                           __int_as_float(base[0] | (base[1] << 10) | (base[2] << 20)));
-      d4[1] = make_float4(co[0], co[1], co[2], co[3]);
       if (TANGENT) {
-        d4[2] = make_float4(co[4], co[5], co[6], co[7]);
-        d4[3] = make_float4(co[8], co[9], 0.f, __int_as_float(i));
+        // the raw inputs: the spread rebuilds the coefficients, and the gather of the
+        // Hessian-vector product needs no per-atom loads of its own
+        const float vq = a.v_q ? a.v_q[i] : 0.0f;
+        const float3 vr = ld3(a.v_pos, i);
+        const float3 vm = ld3(a.v_mu, i);
+        d4[1] = make_float4(q, mu.x, mu.y, mu.z);
+        d4[2] = make_float4(vq, vr.x, vr.y, vr.z);
+        d4[3] = make_float4(vm.x, vm.y, vm.z, __int_as_float(i));
       } else {
+        d4[1] = make_float4(co[0], co[1], co[2], co[3]);
         d4[2] = make_float4(mu.x, mu.y, mu.z, 0.f);
         d4[3] = make_float4(0.f, 0.f, 0.f, __int_as_float(i));
       }
@@ -267,7 +278,8 @@ __device__ __forceinline__ unsigned long long to_fixed(float v) {
 }
 
 template <int P, int DEG>
-__device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_id) {
+__device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_id,
+                                            const double* box) {
   constexpr int NC = (DEG == 1) ? 4 : 10;
   constexpr int D = DEG;                      // highest weight derivative needed
   constexpr int NW = 3 * (D + 1) * P;         // weights w[axis][d][j]
@@ -286,6 +298,15 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
   __shared__ int s_n, s_ntask;
 
   const int tid = threadIdx.x;
+  // tangent records: the Jacobian rebuilds their coefficients at staging; it is
+  // kept in LDS, where it takes no registers across the accumulation
+  __shared__ float s_J[DEG == 2 ? 9 : 1];
+  if (DEG == 2 && tid == 0) {
+    float J[3][3];
+    jacobian(cell_from_box(box), a.N, J);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s_J[i] = J[i / 3][i % 3];
+  }
   int t0[3], T[3];
   {
     int t = tile_id;
@@ -381,7 +402,8 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
     c0v = r[1];
     if (NC == 10) {
       c1v = r[2];
-      c2v = r[3];
+      const float* f = a.rec + ri * kRecWords;   // v_mu; the atom index is not needed here
+      c2v = make_float4(f[12], f[13], f[14], 0.0f);
     }
   };
   const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -423,10 +445,18 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
         ent[NW + NC + 2 * ax + 1] = __int_as_float(lw[ax][1]);
       }
       ent[NW + NC + 6] = h.x; ent[NW + NC + 7] = h.y; ent[NW + NC + 8] = h.z;
-      ent[NW + 0] = c0v.x; ent[NW + 1] = c0v.y; ent[NW + 2] = c0v.z; ent[NW + 3] = c0v.w;
       if (NC == 10) {
-        ent[NW + 4] = c1v.x; ent[NW + 5] = c1v.y; ent[NW + 6] = c1v.z; ent[NW + 7] = c1v.w;
-        ent[NW + 8] = c2v.x; ent[NW + 9] = c2v.y;
+        // tangent records carry q, mu, v_q, v_r, v_mu
+        float co[10];
+        float Jt[3][3];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Jt[i / 3][i % 3] = s_J[i];
+        tangent_coeffs(Jt, c0v.x, make_float3(c0v.y, c0v.z, c0v.w), c1v.x,
+                       make_float3(c1v.y, c1v.z, c1v.w), make_float3(c2v.x, c2v.y, c2v.z), co);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) ent[NW + k] = co[k];
+      } else {
+        ent[NW + 0] = c0v.x; ent[NW + 1] = c0v.y; ent[NW + 2] = c0v.z; ent[NW + 3] = c0v.w;
       }
       int nx = 0;
 #pragma unroll
@@ -533,17 +563,17 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
 
 template <int P, int DEG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
-k_spread(SpreadArgs a) {
-  spread_body<P, DEG>(a, blockIdx.x);
+k_spread(SpreadArgs a, const double* box) {
+  spread_body<P, DEG>(a, blockIdx.x, box);
 }
 
 // Batched spread: work item (box, tile of the box).
 template <int P, int DEG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
-k_spread_batch(const SpreadArgs* args, const int2* items, int nitems) {
+k_spread_batch(const SpreadArgs* args, const int2* items, int nitems, const double* box) {
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const int2 w = items[it];
-    spread_body<P, DEG>(args[w.x], w.y);
+    spread_body<P, DEG>(args[w.x], w.y, box + 9 * w.x);
     __syncthreads();
   }
 }
@@ -565,15 +595,15 @@ hipError_t bin_dispatch(int p, dim3 g, hipStream_t s, const BinArgs& a, const La
 
 template <int DEG>
 hipError_t spread_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const SpreadArgs& a,
-                           const LaunchEvents* ev) {
+                           const double* box, const LaunchEvents* ev) {
   switch (p) {
-    case 1: launch_k(ev, k_spread<1, DEG>, g, dim3(256), sh, s, a); break;
-    case 2: launch_k(ev, k_spread<2, DEG>, g, dim3(256), sh, s, a); break;
-    case 3: launch_k(ev, k_spread<3, DEG>, g, dim3(256), sh, s, a); break;
-    case 4: launch_k(ev, k_spread<4, DEG>, g, dim3(256), sh, s, a); break;
-    case 5: launch_k(ev, k_spread<5, DEG>, g, dim3(256), sh, s, a); break;
-    case 6: launch_k(ev, k_spread<6, DEG>, g, dim3(256), sh, s, a); break;
-    case 7: launch_k(ev, k_spread<7, DEG>, g, dim3(256), sh, s, a); break;
+    case 1: launch_k(ev, k_spread<1, DEG>, g, dim3(256), sh, s, a, box); break;
+    case 2: launch_k(ev, k_spread<2, DEG>, g, dim3(256), sh, s, a, box); break;
+    case 3: launch_k(ev, k_spread<3, DEG>, g, dim3(256), sh, s, a, box); break;
+    case 4: launch_k(ev, k_spread<4, DEG>, g, dim3(256), sh, s, a, box); break;
+    case 5: launch_k(ev, k_spread<5, DEG>, g, dim3(256), sh, s, a, box); break;
+    case 6: launch_k(ev, k_spread<6, DEG>, g, dim3(256), sh, s, a, box); break;
+    case 7: launch_k(ev, k_spread<7, DEG>, g, dim3(256), sh, s, a, box); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -640,15 +670,15 @@ hipError_t bin_batch_dispatch(int p, dim3 g, hipStream_t s, const BinArgs* args,
 
 template <int DEG>
 hipError_t spread_batch_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const SpreadArgs* args,
-                                 const int2* it, int n) {
+                                 const int2* it, int n, const double* box) {
   switch (p) {
-    case 1: hipLaunchKernelGGL((k_spread_batch<1, DEG>), g, dim3(256), sh, s, args, it, n); break;
-    case 2: hipLaunchKernelGGL((k_spread_batch<2, DEG>), g, dim3(256), sh, s, args, it, n); break;
-    case 3: hipLaunchKernelGGL((k_spread_batch<3, DEG>), g, dim3(256), sh, s, args, it, n); break;
-    case 4: hipLaunchKernelGGL((k_spread_batch<4, DEG>), g, dim3(256), sh, s, args, it, n); break;
-    case 5: hipLaunchKernelGGL((k_spread_batch<5, DEG>), g, dim3(256), sh, s, args, it, n); break;
-    case 6: hipLaunchKernelGGL((k_spread_batch<6, DEG>), g, dim3(256), sh, s, args, it, n); break;
-    case 7: hipLaunchKernelGGL((k_spread_batch<7, DEG>), g, dim3(256), sh, s, args, it, n); break;
+    case 1: hipLaunchKernelGGL((k_spread_batch<1, DEG>), g, dim3(256), sh, s, args, it, n, box); break;
+    case 2: hipLaunchKernelGGL((k_spread_batch<2, DEG>), g, dim3(256), sh, s, args, it, n, box); break;
+    case 3: hipLaunchKernelGGL((k_spread_batch<3, DEG>), g, dim3(256), sh, s, args, it, n, box); break;
+    case 4: hipLaunchKernelGGL((k_spread_batch<4, DEG>), g, dim3(256), sh, s, args, it, n, box); break;
+    case 5: hipLaunchKernelGGL((k_spread_batch<5, DEG>), g, dim3(256), sh, s, args, it, n, box); break;
+    case 6: hipLaunchKernelGGL((k_spread_batch<6, DEG>), g, dim3(256), sh, s, args, it, n, box); break;
+    case 7: hipLaunchKernelGGL((k_spread_batch<7, DEG>), g, dim3(256), sh, s, args, it, n, box); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -692,12 +722,12 @@ hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const flo
 }
 
 hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
-                         const LaunchEvents* ev) {
+                         const double* box, const LaunchEvents* ev) {
   const SpreadArgs a = make_spread_args(d, set, tangent);
   const size_t sh = spread_lds(d, tangent);
   const dim3 g(d.nt[0] * d.nt[1] * d.nt[2]);
-  return tangent ? spread_dispatch<2>(d.p, g, sh, s, a, ev)
-                 : spread_dispatch<1>(d.p, g, sh, s, a, ev);
+  return tangent ? spread_dispatch<2>(d.p, g, sh, s, a, box, ev)
+                 : spread_dispatch<1>(d.p, g, sh, s, a, box, ev);
 }
 
 hipError_t spread_batch_build(const DevPlan* plans, const int* n, const int* off, int nbox,
@@ -771,12 +801,14 @@ hipError_t launch_bin_batch(const SpreadBatch& t, hipStream_t s, int set, bool t
                                              self_sums ? 1 : 0);
 }
 
-hipError_t launch_spread_batch(const SpreadBatch& t, hipStream_t s, int set, bool tangent) {
+hipError_t launch_spread_batch(const SpreadBatch& t, hipStream_t s, int set, bool tangent,
+                               const double* box) {
   const SpreadArgs* args = static_cast<const SpreadArgs*>(t.spread[tangent ? 1 : 0][set]);
   const dim3 g = batch_grid(t.n_tile_items, 1280);
   const size_t sh = t.lds[tangent ? 1 : 0];
-  return tangent ? spread_batch_dispatch<2>(t.p, g, sh, s, args, t.tile_items, t.n_tile_items)
-                 : spread_batch_dispatch<1>(t.p, g, sh, s, args, t.tile_items, t.n_tile_items);
+  return tangent ? spread_batch_dispatch<2>(t.p, g, sh, s, args, t.tile_items, t.n_tile_items, box)
+                 : spread_batch_dispatch<1>(t.p, g, sh, s, args, t.tile_items, t.n_tile_items,
+                                            box);
 }
 
 }  // namespace pme
