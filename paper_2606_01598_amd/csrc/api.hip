@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "../../include/pme.h"
+#include "fft_radix.h"
 #include "kernels.h"
 
 using pme::DevPlan;
@@ -60,38 +61,6 @@ bool five_smooth(long m) {
   for (long f : {2L, 3L, 5L})
     while (m % f == 0) m /= f;
   return m == 1;
-}
-
-pme::FastDiv fast_div(int d) {
-  pme::FastDiv f;
-  f.d = uint32_t(d);
-  f.m = d <= 1 ? 0u : uint32_t(((uint64_t(1) << 32) + uint64_t(d) - 1) / uint64_t(d));
-  return f;
-}
-
-// radix schedule for a 1D length: 4s first, then 2, 3s, 5s; per-stage constants
-bool radix_plan(int N, pme::AxisPlan& ax) {
-  ax.N = N;
-  ax.nst = 0;
-  int n = N, Ns = 1;
-  auto push = [&](int r) {
-    if (ax.nst >= pme::kMaxStages) return false;
-    pme::FFTStage& st = ax.st[ax.nst++];
-    st.R = r;
-    st.Ns = Ns;
-    st.NR = N / r;
-    st.step = N / (Ns * r);
-    st.ns = fast_div(Ns);
-    st.nr = fast_div(N / r);
-    Ns *= r;
-    n /= r;
-    return true;
-  };
-  while (n % 4 == 0) if (!push(4)) return false;
-  while (n % 2 == 0) if (!push(2)) return false;
-  while (n % 3 == 0) if (!push(3)) return false;
-  while (n % 5 == 0) if (!push(5)) return false;
-  return n == 1;
 }
 
 int pick_bin(int N) {
@@ -264,7 +233,7 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   }
   // FFT layout
   for (int a = 0; a < 3; ++a)
-    if (!radix_plan(d.N[a], d.ax[a])) { free_plan(pl); return PME_EMESH; }
+    if (!pme::radix_plan(d.N[a], d.ax[a])) { free_plan(pl); return PME_EMESH; }
   {
     // slab mode when a y-z plane of the half spectrum (two LDS buffers) fits
     const long npairs = (d.N[1] + 1) / 2;
@@ -279,7 +248,9 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
     d.rows_per_block = 2 * pairs;
     const int nmax = d.N[0] > d.N[1] ? d.N[0] : d.N[1];
     int kt = nmax <= 64 ? 16 : (nmax <= 160 ? 8 : 4);
-    const int lds_cap = (7000 - nmax) / (2 * (nmax + 1));
+    // LDS of a line workgroup within 56 KB: twiddles, two line buffers and (x pass)
+    // the kt N_x table of g: 8 N + kt (16 (N + 1) + 4 N) bytes
+    const int lds_cap = (7000 - nmax) / (2 * (nmax + 1) + (nmax + 1) / 2 + 1);
     if (kt > lds_cap) kt = lds_cap;
     if (kt < 1) kt = 1;
     if (kt > d.H) kt = d.H;

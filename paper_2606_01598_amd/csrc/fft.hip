@@ -12,8 +12,8 @@
 //   slab inv  y inverse FFT then z C2R (two Hermitian rows unpacked into one
 //             complex pencil), in LDS
 // Otherwise five pencil passes: z R2C, y fwd, x fused, y inv, z C2R.
-// Each 1D transform is a mixed-radix (2, 3, 4, 5) Stockham autosort over LDS
-// ping-pong buffers; twiddles come from a per-axis table staged into LDS.
+// Each 1D transform is a mixed-radix (2, 3, 4, 5, 6, 8, 10) Stockham autosort over
+// LDS ping-pong buffers; twiddles come from a per-axis table staged into LDS.
 //
 // Readings: signed frequency indices in fftfreq order (Nyquist at -N/2); the
 // Nyquist bins of a non-orthogonal cell use the mean of g over the bin and its
@@ -22,80 +22,19 @@
 #include <vector>
 
 #include "../../include/pme.h"
+#include "fft_radix.h"
 #include "kernels.h"
 #include "pme_common.h"
 
 namespace pme {
 namespace {
 
-__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
-  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
-__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
-// multiply by i*s (s = +-1)
-__device__ __forceinline__ float2 imul(float2 a, float s) { return make_float2(-s * a.y, s * a.x); }
-
-// One radix-R Stockham butterfly of a pencil: inputs in[j + r N/R], outputs
-// out[(j/Ns) Ns R + k + r Ns], k = j mod Ns, twiddle w^(r k), w = e^{s 2 pi i/(Ns R)}
-// (table index r k N/(Ns R) < N).
-template <int R>
-__device__ __forceinline__ void butterfly(const float2* __restrict__ in, float2* __restrict__ out,
-                                          int j, int k, int jq, const FFTStage& st,
-                                          const float2* __restrict__ tw, float s) {
-  float2 v[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = in[j + r * st.NR];
-  const int tstep = k * st.step;
-#pragma unroll
-  for (int r = 1; r < R; ++r) {
-    float2 w = tw[r * tstep];
-    w.y *= -s;        // table holds e^{-2 pi i t/N}; s = -1 forward, +1 inverse
-    v[r] = cmul(v[r], w);
-  }
-  float2 y[R];
-  if (R == 2) {
-    y[0] = cadd(v[0], v[1]);
-    y[1] = csub(v[0], v[1]);
-  } else if (R == 3) {
-    const float c = -0.5f, sn = 0.86602540378443864676f;
-    const float2 t1 = cadd(v[1], v[2]);
-    const float2 t2 = make_float2(v[0].x + c * t1.x, v[0].y + c * t1.y);
-    const float2 t3 = imul(csub(v[1], v[2]), s * sn);
-    y[0] = cadd(v[0], t1);
-    y[1] = cadd(t2, t3);
-    y[2] = csub(t2, t3);
-  } else if (R == 4) {
-    const float2 a = cadd(v[0], v[2]), b = csub(v[0], v[2]);
-    const float2 c = cadd(v[1], v[3]), d = imul(csub(v[1], v[3]), s);
-    y[0] = cadd(a, c);
-    y[1] = cadd(b, d);
-    y[2] = csub(a, c);
-    y[3] = csub(b, d);
-  } else if (R == 5) {
-    const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
-    const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
-    const float2 t1 = cadd(v[1], v[4]), t2 = cadd(v[2], v[3]);
-    const float2 t3 = csub(v[1], v[4]), t4 = csub(v[2], v[3]);
-    const float2 a1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
-    const float2 a2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
-    const float2 b1 = imul(make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y), s);
-    const float2 b2 = imul(make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y), s);
-    y[0] = cadd(v[0], cadd(t1, t2));
-    y[1] = cadd(a1, b1);
-    y[4] = csub(a1, b1);
-    y[2] = cadd(a2, b2);
-    y[3] = csub(a2, b2);
-  }
-  const int base = jq * st.Ns * R + k;
-#pragma unroll
-  for (int r = 0; r < R; ++r) out[base + r * st.Ns] = y[r];
-}
-
-// Transform npen pencils (stride ps) held in x; returns the buffer holding the result.
+// Transform npen pencils (stride ps) held in x by stages [s0, s1) of the plan (all
+// by default); returns the buffer holding the result.
 __device__ float2* lds_fft(float2* x, float2* y, int npen, int ps, const AxisPlan& ax,
-                           const float2* tw, float s) {
-  for (int sti = 0; sti < ax.nst; ++sti) {
+                           const float2* tw, float s, int s0 = 0, int s1 = -1) {
+  if (s1 < 0) s1 = ax.nst;
+  for (int sti = s0; sti < s1; ++sti) {
     const FFTStage& st = ax.st[sti];
     const int total = npen * st.NR;
     for (int t = threadIdx.x; t < total; t += blockDim.x) {
@@ -106,10 +45,11 @@ __device__ float2* lds_fft(float2* x, float2* y, int npen, int ps, const AxisPla
       const float2* in = x + pen * ps;
       float2* out = y + pen * ps;
       switch (st.R) {
-        case 2: butterfly<2>(in, out, j, k, jq, st, tw, s); break;
-        case 3: butterfly<3>(in, out, j, k, jq, st, tw, s); break;
-        case 4: butterfly<4>(in, out, j, k, jq, st, tw, s); break;
-        default: butterfly<5>(in, out, j, k, jq, st, tw, s); break;
+#define PME_R(R) \
+  case R: stockham_butterfly<R>(in, out, j, k, jq, st.Ns, st.NR, st.step, tw, s); break;
+        PME_R(2) PME_R(3) PME_R(4) PME_R(5) PME_R(6) PME_R(8) PME_R(10)
+#undef PME_R
+        default: break;
       }
     }
     __syncthreads();
@@ -413,6 +353,7 @@ __global__ void __launch_bounds__(kFFTThreads) k_ffty(YArgs a) {
 
 struct XArgs {
   AxisPlan ax;
+  AxisPlan axi;    // the same radices in reverse order (inverse transform)
   const float2* tw;
   int N[3];
   int H, kt;
@@ -428,7 +369,14 @@ struct XArgs {
 
 __device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) / 2) ? k - N : k; }
 
-// x pass fused with the influence function
+// x pass fused with the influence function: forward FFT along x of kt half-spectrum
+// lines (fixed y, consecutive kz), x g(k) (with the energy partial), inverse FFT.
+//   g(k) = (4 pi / k^2) exp(-k^2 / (4 alpha^2)) dcx(kx) dcy(ky) dcz(kz),
+//   k^2 = f^T M f, M = 4 pi^2 C^-1 C^-T (reciprocal metric), f = signed frequencies;
+// g is 0 at k = 0; a Nyquist bin takes the mean of g over the bin and its Hermitian
+// partner.  g is tabulated for the workgroup's points while the line loads are in
+// flight; the product itself sits between the last forward and the first inverse
+// stage, in registers (x_middle).
 __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const double* box,
                                           double* epart) {
   extern __shared__ float2 sm[];
@@ -438,93 +386,116 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
   float2* tw = sm;
   float2* X = tw + Nx;
   float2* Y = X + kt * ps;
+  float* s_g = reinterpret_cast<float*>(Y + kt * ps);   // g[l Nx + kx]
   const int ntk = (H + kt - 1) / kt;
   const int y = blk / ntk, kz0 = (blk - y * ntk) * kt;
   Twiddles<kFFTThreads> twr;
   twr.load(a.tw, Nx);
   const size_t xstride = size_t(Ny) * H;
   float2* base = a.spec + size_t(y) * H;
-  staged_copy<16, float2>(
-      Nx * kt,
-      [&](int e) {
-        const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
-        const int kz = kz0 + l;
-        return (kz < H) ? base[xx * xstride + kz] : make_float2(0.f, 0.f);
-      },
-      [&](int e, float2 v) {
-        const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
-        X[l * ps + xx] = v;
-      });
+  constexpr int U = 16;   // Nx kt <= U blockDim (the plan bounds kt (Nx + 1) by 3500)
+  float2 lv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * kFFTThreads;
+    if (e < Nx * kt) {
+      const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
+      const int kz = kz0 + l;
+      lv[u] = (kz < H) ? base[xx * xstride + kz] : make_float2(0.f, 0.f);
+    }
+  }
+  // g of this thread's points, computed while the loads are in flight
+  {
+    const Cell c = cell_from_box(box);
+    float M[3][3];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        double m = 0.0;
+#pragma unroll
+        for (int g = 0; g < 3; ++g) m += c.inv[3 * g + p] * c.inv[3 * g + q];
+        M[p][q] = float(4.0 * M_PI * M_PI * m);
+      }
+    const float inv4a2 = 1.0f / (4.0f * a.alpha * a.alpha);
+    const int fyi = signed_freq(y, Ny);
+    const float fy = float(fyi);
+    const bool nyq_y = ((Ny & 1) == 0) && (2 * fyi == -Ny);
+    const float dcy = a.dcy[y];
+    auto gk = [&](float px, float py, float pz) {
+      const float k2 = M[0][0] * px * px + M[1][1] * py * py + M[2][2] * pz * pz +
+                       2.0f * (M[0][1] * px * py + M[0][2] * px * pz + M[1][2] * py * pz);
+      return 4.0f * float(M_PI) / k2 * expf(-k2 * inv4a2);
+    };
+    for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
+      const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
+      const int kz = kz0 + l;
+      float g = 0.0f;
+      if (kz < H && (xx | y | kz) != 0) {
+        const float fx = float(signed_freq(xx, Nx)), fz = float(signed_freq(kz, Nz));
+        g = gk(fx, fy, fz);
+        const bool nx = ((Nx & 1) == 0) && (2 * xx == Nx);
+        const bool nz = ((Nz & 1) == 0) && (2 * kz == Nz);
+        if (nx || nyq_y || nz)   // Hermitian partner: the non-Nyquist components change sign
+          g = 0.5f * (g + gk(nx ? fx : -fx, nyq_y ? fy : -fy, nz ? fz : -fz));
+        g *= a.dcx[xx] * dcy * a.dcz[kz];
+      }
+      s_g[l * Nx + xx] = g;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int e = threadIdx.x + u * kFFTThreads;
+    if (e < Nx * kt) {
+      const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
+      X[l * ps + xx] = lv[u];
+    }
+  }
   twr.store(tw, Nx);
   __syncthreads();
-  float2* Z = lds_fft(X, Y, kt, ps, a.ax, tw, -1.0f);
+  const int last = a.ax.nst - 1;
+  float2* Z = lds_fft(X, Y, kt, ps, a.ax, tw, -1.0f, 0, last);
   float2* W = (Z == X) ? Y : X;
-  // reciprocal metric M_ab = b_a . b_b, b_a = 2 pi C^-1[:, a]
-  const Cell c = cell_from_box(box);
-  float M[3][3];
-#pragma unroll
-  for (int p = 0; p < 3; ++p)
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      double s = 0.0;
-#pragma unroll
-      for (int g = 0; g < 3; ++g) s += c.inv[3 * g + p] * c.inv[3 * g + q];
-      M[p][q] = float(4.0 * M_PI * M_PI * s);
-    }
-  const float inv4a2 = 1.0f / (4.0f * a.alpha * a.alpha);
-  const int fy = signed_freq(y, Ny);
-  const bool nyq_y = ((Ny & 1) == 0) && (fy == -Ny / 2);
-  double e_acc = 0.0;
-  for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
-    const int l = e / Nx, i = e - l * Nx;
-    const int kz = kz0 + l;
-    float2 v = Z[l * ps + i];
-    if (kz < H) {
-      const int fx = signed_freq(i, Nx);
-      const int fz = signed_freq(kz, Nz);
-      const float ffx = float(fx), ffy = float(fy), ffz = float(fz);
-      const float k2 = M[0][0] * ffx * ffx + M[1][1] * ffy * ffy + M[2][2] * ffz * ffz +
-                       2.0f * (M[0][1] * ffx * ffy + M[0][2] * ffx * ffz + M[1][2] * ffy * ffz);
-      float g = 0.0f;
-      if (fx != 0 || fy != 0 || fz != 0) {
-        g = 4.0f * float(M_PI) / k2 * expf(-k2 * inv4a2);
-        const bool nx = ((Nx & 1) == 0) && (fx == -Nx / 2);
-        const bool nz = ((Nz & 1) == 0) && (fz == -Nz / 2);
-        if (nx || nyq_y || nz) {
-          // Hermitian partner: non-Nyquist components change sign
-          const float px = nx ? ffx : -ffx, py = nyq_y ? ffy : -ffy, pz = nz ? ffz : -ffz;
-          const float k2p = M[0][0] * px * px + M[1][1] * py * py + M[2][2] * pz * pz +
-                            2.0f * (M[0][1] * px * py + M[0][2] * px * pz + M[1][2] * py * pz);
-          if (k2p != k2) g = 0.5f * (g + 4.0f * float(M_PI) / k2p * expf(-k2p * inv4a2));
-        }
-        g *= a.dcx[i] * a.dcy[y] * a.dcz[kz];
+  float e_acc = 0.0f;
+  {
+    const FFTStage& st = a.ax.st[last];
+    const int NR = st.NR;
+    for (int t = threadIdx.x; t < kt * NR; t += blockDim.x) {
+      const int pen = int(fdiv(uint32_t(t), st.nr));
+      const int j = t - pen * NR;
+      const float2* in = Z + pen * ps;
+      float2* out = W + pen * ps;
+      const float* gl = s_g + pen * Nx;
+      const int kz = kz0 + pen;
+      const float wgt = (kz == 0 || (((Nz & 1) == 0) && 2 * kz == Nz)) ? 1.0f : 2.0f;
+      // g, and the energy partial wgt g |v|^2 of the value it scales
+      auto gm = [&](int i, float2 v) -> float {
+        const float gg = gl[i];
+        if (epart) e_acc = fmaf(wgt * gg, v.x * v.x + v.y * v.y, e_acc);
+        return gg;
+      };
+      switch (st.R) {
+#define PME_XM(R) \
+  case R: x_middle<R>(in, out, j, NR, tw, gm); break;
+        PME_XM(2) PME_XM(3) PME_XM(4) PME_XM(5) PME_XM(6) PME_XM(8) PME_XM(10)
+#undef PME_XM
+        default: break;
       }
-      const float wgt = (kz == 0 || (((Nz & 1) == 0) && kz == Nz / 2)) ? 1.0f : 2.0f;
-      e_acc += double(wgt * g) * (double(v.x) * v.x + double(v.y) * v.y);
-      v.x *= g;
-      v.y *= g;
     }
-    Z[l * ps + i] = v;
   }
   __syncthreads();
-  const float2* R = lds_fft(Z, W, kt, ps, a.ax, tw, +1.0f);
+  const float2* R = lds_fft(W, Z, kt, ps, a.axi, tw, +1.0f, 1, -1);
   for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
     const int xx = e / kt, l = e - xx * kt;
     const int kz = kz0 + l;
     if (kz < H) base[xx * xstride + kz] = R[l * ps + xx];
   }
   if (epart) {
-    const double s = block_sum(e_acc, red);
+    const double s = block_sum(double(e_acc), red);
     if (threadIdx.x == 0) epart[blk] = s;
   }
 }
 
-FastDiv host_fastdiv(int d) {
-  FastDiv f;
-  f.d = uint32_t(d);
-  f.m = d <= 1 ? 0u : uint32_t(((uint64_t(1) << 32) + uint64_t(d) - 1) / uint64_t(d));
-  return f;
-}
 
 __global__ void __launch_bounds__(kSlabThreads) k_slab_fwd(SlabArgs a) {
   slab_fwd_body(a, blockIdx.x);
@@ -575,20 +546,23 @@ namespace {
 XArgs make_x_args(const DevPlan& d, const double* box, bool energy) {
   XArgs x;
   x.ax = d.ax[0]; x.tw = d.twiddle[0];
+  reverse_plan(d.ax[0], x.axi);
   for (int k = 0; k < 3; ++k) x.N[k] = d.N[k];
-  x.H = d.H; x.kt = d.ktile; x.ktd = host_fastdiv(d.ktile); x.spec = d.spec; x.box = box;
+  x.H = d.H; x.kt = d.ktile; x.ktd = make_fast_div(d.ktile); x.spec = d.spec; x.box = box;
   x.dcx = d.deconv[0]; x.dcy = d.deconv[1]; x.dcz = d.deconv[2];
   x.alpha = float(d.alpha);
   x.epart = energy ? d.epart : nullptr;
   return x;
 }
 
-size_t x_lds(const DevPlan& d) { return sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1)); }
+size_t x_lds(const DevPlan& d) {
+  return sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1)) + sizeof(float) * d.N[0] * d.ktile;
+}
 
 SlabArgs make_slab_args(const DevPlan& d, float* out) {
   SlabArgs sa;
   sa.ay = d.ax[1]; sa.az = d.ax[2]; sa.twy = d.twiddle[1]; sa.twz = d.twiddle[2];
-  sa.H = d.H; sa.nzd = host_fastdiv(d.N[2]); sa.hd = host_fastdiv(d.H);
+  sa.H = d.H; sa.nzd = make_fast_div(d.N[2]); sa.hd = make_fast_div(d.H);
   sa.src = d.rho; sa.spec = d.spec; sa.dst = out;
   return sa;
 }
@@ -679,12 +653,12 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   ZArgs z;
   z.ax = d.ax[2]; z.tw = d.twiddle[2]; z.rows = rows; z.H = d.H; z.rp = d.rows_per_block;
   z.src = d.rho; z.spec = d.spec; z.dst = out;
-  z.nd = host_fastdiv(d.N[2]);
+  z.nd = make_fast_div(d.N[2]);
   const int zb = fftz_blocks(d);
   const size_t zsh_f = sizeof(float2) * (d.N[2] + d.rows_per_block * d.N[2]);
   YArgs y;
   y.ax = d.ax[1]; y.tw = d.twiddle[1]; y.Ny = d.N[1]; y.H = d.H; y.kt = d.ktile; y.spec = d.spec;
-  y.ktd = host_fastdiv(d.ktile);
+  y.ktd = make_fast_div(d.ktile);
   const size_t ysh = sizeof(float2) * (d.N[1] + 2 * d.ktile * (d.N[1] + 1));
 
   launch_k(er ? &er0 : nullptr, k_fftz_r2c, dim3(zb), dim3(kFFTThreads), zsh_f, s, z);
