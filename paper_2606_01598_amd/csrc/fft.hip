@@ -214,7 +214,11 @@ __device__ __forceinline__ void slab_layout(const SlabArgs& a, float2* sm, float
   B = A + buf;
 }
 
-// forward slab: rho[x] -> z R2C -> y FFT -> spec[x]
+// forward slab: rho[x] -> z R2C -> y FFT -> spec[x].  Two real rows y = 2c, 2c+1 form
+// one complex pencil; the first z stage reads them from global memory (when one
+// round of the workgroup covers it) and the first y stage unpacks the two real
+// transforms as it reads:
+//   X_2c[k] = (Z[k] + conj Z[N-k]) / 2,  X_2c+1[k] = (Z[k] - conj Z[N-k]) / 2i.
 __device__ __forceinline__ void slab_fwd_body(const SlabArgs& a, const int x) {
   extern __shared__ float2 sm[];
   const int Ny = a.ay.N, Nz = a.az.N, H = a.H;
@@ -225,32 +229,65 @@ __device__ __forceinline__ void slab_fwd_body(const SlabArgs& a, const int x) {
   tz.load(a.twz, Nz);
   ty.load(a.twy, Ny);
   const float* src = a.src + size_t(x) * Ny * Nz;
-  float* Af = reinterpret_cast<float*>(A);
-  // one batch of loads per thread for planes up to 20 * 1024 points
-  staged_copy<20, float>(
-      Ny * Nz, [&](int e) { return src[e]; },
-      [&](int e, float v) {
-        const int y = int(fdiv(uint32_t(e), a.nzd)), m = e - y * Nz;
-        Af[2 * ((y >> 1) * Nz + m) + (y & 1)] = v;
+  const FFTStage& z0 = a.az.st[0];
+  float2* Z;
+  if (npairs * z0.NR <= int(blockDim.x)) {
+    const int t = threadIdx.x;
+    if (t < npairs * z0.NR) {
+      const int c = int(fdiv(uint32_t(t), z0.nr)), j = t - c * z0.NR;
+      const float* r0 = src + size_t(2 * c) * Nz;
+      const float* r1 = r0 + Nz;
+      const bool odd_last = (2 * c + 1 >= Ny);   // odd row count: zero imaginary row
+      float2* out = A + c * Nz;
+      with_radix(z0.R, [&](auto rc) {
+        constexpr int R = decltype(rc)::value;
+        stockham_butterfly_io<R, false>(
+            [&](int i) { return make_float2(r0[i], odd_last ? 0.0f : r1[i]); },
+            [&](int i, float2 v) { out[i] = v; }, j, 0, j, 1, z0.NR, z0.step, twz, -1.0f);
       });
-  if (Ny & 1)   // odd row count: the last pencil's imaginary row is zero
-    for (int m = threadIdx.x; m < Nz; m += blockDim.x) Af[2 * ((Ny >> 1) * Nz + m) + 1] = 0.0f;
-  tz.store(twz, Nz);
-  ty.store(twy, Ny);
-  __syncthreads();
-  float2* Z = lds_fft(A, B, npairs, Nz, a.az, twz, -1.0f);
+    }
+    tz.store(twz, Nz);
+    ty.store(twy, Ny);
+    __syncthreads();
+    Z = lds_fft(A, B, npairs, Nz, a.az, twz, -1.0f, 1, -1);
+  } else {
+    float* Af = reinterpret_cast<float*>(A);
+    staged_copy<12, float>(
+        Ny * Nz, [&](int e) { return src[e]; },
+        [&](int e, float v) {
+          const int y = int(fdiv(uint32_t(e), a.nzd)), m = e - y * Nz;
+          Af[2 * ((y >> 1) * Nz + m) + (y & 1)] = v;
+        });
+    if (Ny & 1)
+      for (int m = threadIdx.x; m < Nz; m += blockDim.x) Af[2 * ((Ny >> 1) * Nz + m) + 1] = 0.0f;
+    tz.store(twz, Nz);
+    ty.store(twy, Ny);
+    __syncthreads();
+    Z = lds_fft(A, B, npairs, Nz, a.az, twz, -1.0f);
+  }
   float2* O = (Z == A) ? B : A;
   const int ps = Ny + 1;
-  for (int e = threadIdx.x; e < Ny * H; e += blockDim.x) {
-    const int y = int(fdiv(uint32_t(e), a.hd)), k = e - y * H;
-    const int c = y >> 1;
-    const float2 zk = Z[c * Nz + k];
-    const float2 zn = Z[c * Nz + (k ? Nz - k : 0)];
-    O[k * ps + y] = ((y & 1) == 0) ? make_float2(0.5f * (zk.x + zn.x), 0.5f * (zk.y - zn.y))
-                                   : make_float2(0.5f * (zk.y + zn.y), -0.5f * (zk.x - zn.x));
+  {
+    const FFTStage& y0 = a.ay.st[0];
+    for (int t = threadIdx.x; t < H * y0.NR; t += blockDim.x) {
+      const int k = int(fdiv(uint32_t(t), y0.nr)), j = t - k * y0.NR;
+      const int kn = k ? Nz - k : 0;
+      float2* out = O + k * ps;
+      with_radix(y0.R, [&](auto rc) {
+        constexpr int R = decltype(rc)::value;
+        stockham_butterfly_io<R, false>(
+            [&](int y) {
+              const int c = y >> 1;
+              const float2 zk = Z[c * Nz + k], zn = Z[c * Nz + kn];
+              return ((y & 1) == 0) ? make_float2(0.5f * (zk.x + zn.x), 0.5f * (zk.y - zn.y))
+                                    : make_float2(0.5f * (zk.y + zn.y), -0.5f * (zk.x - zn.x));
+            },
+            [&](int i, float2 v) { out[i] = v; }, j, 0, j, 1, y0.NR, y0.step, twy, -1.0f);
+      });
+    }
   }
   __syncthreads();
-  const float2* R = lds_fft(O, Z, H, ps, a.ay, twy, -1.0f);
+  const float2* R = lds_fft(O, Z, H, ps, a.ay, twy, -1.0f, 1, -1);
   float2* dst = a.spec + size_t(x) * Ny * H;
   for (int e = threadIdx.x; e < Ny * H; e += blockDim.x) {
     const int y = int(fdiv(uint32_t(e), a.hd)), k = e - y * H;
@@ -258,7 +295,10 @@ __device__ __forceinline__ void slab_fwd_body(const SlabArgs& a, const int x) {
   }
 }
 
-// inverse slab: spec[x] -> y inverse FFT -> z C2R -> out[x]
+// inverse slab: spec[x] -> y inverse FFT -> z C2R -> out[x].  The first y stage reads
+// from global memory (when one round covers it); the first z stage packs two
+// Hermitian rows into one complex pencil as it reads:
+//   P[m] = X_2c[m] + i X_2c+1[m], X[m] = conj X[N-m] for m >= H.
 __device__ __forceinline__ void slab_inv_body(const SlabArgs& a, const int x) {
   extern __shared__ float2 sm[];
   const int Ny = a.ay.N, Nz = a.az.N, H = a.H;
@@ -270,36 +310,72 @@ __device__ __forceinline__ void slab_inv_body(const SlabArgs& a, const int x) {
   ty.load(a.twy, Ny);
   const int ps = Ny + 1;
   const float2* src = a.spec + size_t(x) * Ny * H;
-  staged_copy<12, float2>(
-      Ny * H, [&](int e) { return src[e]; },
-      [&](int e, float2 v) {
-        const int y = int(fdiv(uint32_t(e), a.hd)), k = e - y * H;
-        A[k * ps + y] = v;
+  const FFTStage& y0 = a.ay.st[0];
+  float2* R;
+  if (H * y0.NR <= int(blockDim.x)) {
+    const int t = threadIdx.x;
+    if (t < H * y0.NR) {
+      // k fastest: consecutive lanes read consecutive kz of one spectrum row
+      const int j = int(fdiv(uint32_t(t), a.hd)), k = t - j * H;
+      float2* out = A + k * ps;
+      with_radix(y0.R, [&](auto rc) {
+        constexpr int Rr = decltype(rc)::value;
+        stockham_butterfly_io<Rr, false>([&](int y) { return src[size_t(y) * H + k]; },
+                                         [&](int i, float2 v) { out[i] = v; }, j, 0, j, 1, y0.NR,
+                                         y0.step, twy, 1.0f);
       });
-  tz.store(twz, Nz);
-  ty.store(twy, Ny);
-  __syncthreads();
-  float2* R = lds_fft(A, B, H, ps, a.ay, twy, +1.0f);
+    }
+    tz.store(twz, Nz);
+    ty.store(twy, Ny);
+    __syncthreads();
+    R = lds_fft(A, B, H, ps, a.ay, twy, +1.0f, 1, -1);
+  } else {
+    staged_copy<12, float2>(
+        Ny * H, [&](int e) { return src[e]; },
+        [&](int e, float2 v) {
+          const int y = int(fdiv(uint32_t(e), a.hd)), k = e - y * H;
+          A[k * ps + y] = v;
+        });
+    tz.store(twz, Nz);
+    ty.store(twy, Ny);
+    __syncthreads();
+    R = lds_fft(A, B, H, ps, a.ay, twy, +1.0f);
+  }
   float2* O = (R == A) ? B : A;
   const bool even = (Nz & 1) == 0;
-  for (int e = threadIdx.x; e < npairs * Nz; e += blockDim.x) {
-    const int c = int(fdiv(uint32_t(e), a.nzd)), m = e - c * Nz;
-    const int ya = 2 * c, yb = ya + 1;
-    float2 Av, Bv;
-    if (m < H) {
-      Av = R[m * ps + ya];
-      Bv = (yb < Ny) ? R[m * ps + yb] : make_float2(0.f, 0.f);
-    } else {
-      Av = R[(Nz - m) * ps + ya];
-      Bv = (yb < Ny) ? R[(Nz - m) * ps + yb] : make_float2(0.f, 0.f);
-      Av.y = -Av.y;
-      Bv.y = -Bv.y;
+  {
+    const FFTStage& z0 = a.az.st[0];
+    for (int t = threadIdx.x; t < npairs * z0.NR; t += blockDim.x) {
+      const int c = int(fdiv(uint32_t(t), z0.nr)), j = t - c * z0.NR;
+      const int ya = 2 * c, yb = ya + 1;
+      const bool hasb = yb < Ny;
+      float2* out = O + c * Nz;
+      with_radix(z0.R, [&](auto rc) {
+        constexpr int Rr = decltype(rc)::value;
+        stockham_butterfly_io<Rr, false>(
+            [&](int m) {
+              float2 Av, Bv;
+              if (m < H) {
+                Av = R[m * ps + ya];
+                Bv = hasb ? R[m * ps + yb] : make_float2(0.f, 0.f);
+              } else {
+                Av = R[(Nz - m) * ps + ya];
+                Bv = hasb ? R[(Nz - m) * ps + yb] : make_float2(0.f, 0.f);
+                Av.y = -Av.y;
+                Bv.y = -Bv.y;
+              }
+              if (m == 0 || (even && m == Nz / 2)) {
+                Av.y = 0.0f;
+                Bv.y = 0.0f;
+              }
+              return make_float2(Av.x - Bv.y, Av.y + Bv.x);
+            },
+            [&](int i, float2 v) { out[i] = v; }, j, 0, j, 1, z0.NR, z0.step, twz, 1.0f);
+      });
     }
-    if (m == 0 || (even && m == Nz / 2)) { Av.y = 0.0f; Bv.y = 0.0f; }
-    O[e] = make_float2(Av.x - Bv.y, Av.y + Bv.x);
   }
   __syncthreads();
-  const float2* Z = lds_fft(O, R, npairs, Nz, a.az, twz, +1.0f);
+  const float2* Z = lds_fft(O, R, npairs, Nz, a.az, twz, +1.0f, 1, -1);
   float* dst = a.dst + size_t(x) * Ny * Nz;
   for (int e = threadIdx.x; e < Ny * Nz; e += blockDim.x) {
     const int y = int(fdiv(uint32_t(e), a.nzd)), m = e - y * Nz;

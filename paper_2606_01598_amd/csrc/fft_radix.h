@@ -177,27 +177,56 @@ struct Dft<10> : DftSplit<2, 5> {};
 // Radices a stage may use, in the order the planner prefers at equal stage count.
 constexpr int kRadices[] = {10, 8, 6, 5, 4, 3, 2};
 
-// One radix-R Stockham butterfly (see the header comment); the twiddle table holds
-// e^{-2 pi i t / N}, t < N; s = -1 forward, +1 inverse.
+// One radix-R Stockham butterfly (see the header comment) reading its inputs through
+// ld(index in the pencil) and writing through st(index, value); the twiddle table
+// holds e^{-2 pi i t / N}, t < N; s = -1 forward, +1 inverse.  TW = false for a first
+// stage (Ns = 1, k = 0: no twiddles, the table need not be loaded yet).
+template <int R, bool TW, class LD, class ST>
+__host__ __device__ __forceinline__ void stockham_butterfly_io(LD&& ld, ST&& st, int j, int k,
+                                                               int jq, int Ns, int NR, int step,
+                                                               const float2* __restrict__ tw,
+                                                               float s) {
+  float2 v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = ld(j + r * NR);
+  if constexpr (TW) {
+    const int tstep = k * step;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      float2 w = tw[r * tstep];
+      w.y *= -s;
+      v[r] = c_mul(v[r], w);
+    }
+  }
+  Dft<R>::run(v, s);
+  const int base = jq * Ns * R + k;
+#pragma unroll
+  for (int r = 0; r < R; ++r) st(base + r * Ns, v[r]);
+}
+
+// The same from and to pencils in memory.
 template <int R>
 __host__ __device__ __forceinline__ void stockham_butterfly(const float2* __restrict__ in,
                                                             float2* __restrict__ out, int j, int k,
                                                             int jq, int Ns, int NR, int step,
                                                             const float2* __restrict__ tw, float s) {
-  float2 v[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) v[r] = in[j + r * NR];
-  const int tstep = k * step;
-#pragma unroll
-  for (int r = 1; r < R; ++r) {
-    float2 w = tw[r * tstep];
-    w.y *= -s;
-    v[r] = c_mul(v[r], w);
+  stockham_butterfly_io<R, true>([&](int i) { return in[i]; },
+                                 [&](int i, float2 v) { out[i] = v; }, j, k, jq, Ns, NR, step, tw, s);
+}
+
+// f(integral_constant<int, R>) for the runtime radix R of a stage.
+template <class F>
+__host__ __device__ __forceinline__ void with_radix(int R, F&& f) {
+  switch (R) {
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 3: f(std::integral_constant<int, 3>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 5: f(std::integral_constant<int, 5>{}); break;
+    case 6: f(std::integral_constant<int, 6>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 10: f(std::integral_constant<int, 10>{}); break;
+    default: break;
   }
-  Dft<R>::run(v, s);
-  const int base = jq * Ns * R + k;
-#pragma unroll
-  for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
 }
 
 // Last forward stage, x g(k) and first inverse stage of one butterfly, in registers.
