@@ -287,11 +287,30 @@ __device__ __forceinline__ void slab_fwd_body(const SlabArgs& a, const int x) {
     }
   }
   __syncthreads();
-  const float2* R = lds_fft(O, Z, H, ps, a.ay, twy, -1.0f, 1, -1);
   float2* dst = a.spec + size_t(x) * Ny * H;
-  for (int e = threadIdx.x; e < Ny * H; e += blockDim.x) {
-    const int y = int(fdiv(uint32_t(e), a.hd)), k = e - y * H;
-    dst[e] = R[k * ps + y];
+  const int ny = a.ay.nst;
+  if (ny >= 2 && H * a.ay.st[ny - 1].NR <= int(blockDim.x)) {
+    // last y stage writes the spectrum rows itself (kz fastest across lanes)
+    const float2* Rin = lds_fft(O, Z, H, ps, a.ay, twy, -1.0f, 1, ny - 1);
+    const FFTStage& yl = a.ay.st[ny - 1];
+    const int t = threadIdx.x;
+    if (t < H * yl.NR) {
+      const int j = int(fdiv(uint32_t(t), a.hd)), k = t - j * H;
+      const int jq = int(fdiv(uint32_t(j), yl.ns)), kk = j - jq * yl.Ns;
+      const float2* in = Rin + k * ps;
+      with_radix(yl.R, [&](auto rc) {
+        constexpr int Rr = decltype(rc)::value;
+        stockham_butterfly_io<Rr, true>([&](int i) { return in[i]; },
+                                        [&](int y, float2 v) { dst[size_t(y) * H + k] = v; }, j, kk,
+                                        jq, yl.Ns, yl.NR, yl.step, twy, -1.0f);
+      });
+    }
+  } else {
+    const float2* R = lds_fft(O, Z, H, ps, a.ay, twy, -1.0f, 1, -1);
+    for (int e = threadIdx.x; e < Ny * H; e += blockDim.x) {
+      const int y = int(fdiv(uint32_t(e), a.hd)), k = e - y * H;
+      dst[e] = R[k * ps + y];
+    }
   }
 }
 
@@ -375,12 +394,38 @@ __device__ __forceinline__ void slab_inv_body(const SlabArgs& a, const int x) {
     }
   }
   __syncthreads();
-  const float2* Z = lds_fft(O, R, npairs, Nz, a.az, twz, +1.0f, 1, -1);
   float* dst = a.dst + size_t(x) * Ny * Nz;
-  for (int e = threadIdx.x; e < Ny * Nz; e += blockDim.x) {
-    const int y = int(fdiv(uint32_t(e), a.nzd)), m = e - y * Nz;
-    const float2 v = Z[(y >> 1) * Nz + m];
-    dst[e] = (y & 1) ? v.y : v.x;
+  const int nz = a.az.nst;
+  if (nz >= 2 && npairs * a.az.st[nz - 1].NR <= int(blockDim.x)) {
+    // last z stage writes the two real rows of its pencil itself
+    const float2* Zin = lds_fft(O, R, npairs, Nz, a.az, twz, +1.0f, 1, nz - 1);
+    const FFTStage& zl = a.az.st[nz - 1];
+    const int t = threadIdx.x;
+    if (t < npairs * zl.NR) {
+      const int c = int(fdiv(uint32_t(t), zl.nr)), j = t - c * zl.NR;
+      const int jq = int(fdiv(uint32_t(j), zl.ns)), kk = j - jq * zl.Ns;
+      const float2* in = Zin + c * Nz;
+      float* ra = dst + size_t(2 * c) * Nz;
+      float* rb = ra + Nz;
+      const bool hasb = 2 * c + 1 < Ny;
+      with_radix(zl.R, [&](auto rc) {
+        constexpr int Rr = decltype(rc)::value;
+        stockham_butterfly_io<Rr, true>(
+            [&](int i) { return in[i]; },
+            [&](int m, float2 v) {
+              ra[m] = v.x;
+              if (hasb) rb[m] = v.y;
+            },
+            j, kk, jq, zl.Ns, zl.NR, zl.step, twz, 1.0f);
+      });
+    }
+  } else {
+    const float2* Z = lds_fft(O, R, npairs, Nz, a.az, twz, +1.0f, 1, -1);
+    for (int e = threadIdx.x; e < Ny * Nz; e += blockDim.x) {
+      const int y = int(fdiv(uint32_t(e), a.nzd)), m = e - y * Nz;
+      const float2 v = Z[(y >> 1) * Nz + m];
+      dst[e] = (y & 1) ? v.y : v.x;
+    }
   }
 }
 
@@ -469,19 +514,8 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
   twr.load(a.tw, Nx);
   const size_t xstride = size_t(Ny) * H;
   float2* base = a.spec + size_t(y) * H;
-  constexpr int U = 16;   // Nx kt <= U blockDim (the plan bounds kt (Nx + 1) by 3500)
-  float2 lv[U];
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int e = threadIdx.x + u * kFFTThreads;
-    if (e < Nx * kt) {
-      const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
-      const int kz = kz0 + l;
-      lv[u] = (kz < H) ? base[xx * xstride + kz] : make_float2(0.f, 0.f);
-    }
-  }
-  // g of this thread's points, computed while the loads are in flight
-  {
+  // g of the workgroup's points into LDS (issued while the line loads are in flight)
+  auto gtable = [&]() {
     const Cell c = cell_from_box(box);
     float M[3][3];
 #pragma unroll
@@ -518,19 +552,63 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
       }
       s_g[l * Nx + xx] = g;
     }
-  }
-#pragma unroll
-  for (int u = 0; u < U; ++u) {
-    const int e = threadIdx.x + u * kFFTThreads;
-    if (e < Nx * kt) {
-      const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
-      X[l * ps + xx] = lv[u];
-    }
-  }
-  twr.store(tw, Nx);
-  __syncthreads();
+  };
   const int last = a.ax.nst - 1;
-  float2* Z = lds_fft(X, Y, kt, ps, a.ax, tw, -1.0f, 0, last);
+  // first forward stage reading the lines from global memory and last inverse stage
+  // writing them back, when one round of the workgroup covers each (lanes: kz fastest)
+  const bool fuse_io = last >= 1 && kt * a.ax.st[0].NR <= int(blockDim.x) &&
+                       kt * a.axi.st[last].NR <= int(blockDim.x);
+  float2* Z;
+  if (fuse_io) {
+    const FFTStage& x0 = a.ax.st[0];
+    const int t = threadIdx.x;
+    const bool act = t < kt * x0.NR;
+    const int j = int(fdiv(uint32_t(t), a.ktd)), l = t - j * kt;
+    const int kz = kz0 + l;
+    with_radix(x0.R, [&](auto rc) {
+      constexpr int Rr = decltype(rc)::value;
+      float2 v[Rr];
+      if (act) {
+#pragma unroll
+        for (int r = 0; r < Rr; ++r)
+          v[r] = (kz < H) ? base[size_t(j + r * x0.NR) * xstride + kz] : make_float2(0.f, 0.f);
+      }
+      gtable();
+      if (act) {
+        Dft<Rr>::run(v, -1.0f);
+        float2* out = X + l * ps;
+#pragma unroll
+        for (int r = 0; r < Rr; ++r) out[j * Rr + r] = v[r];
+      }
+    });
+    twr.store(tw, Nx);
+    __syncthreads();
+    Z = lds_fft(X, Y, kt, ps, a.ax, tw, -1.0f, 1, last);
+  } else {
+    constexpr int U = 16;   // Nx kt <= U blockDim (the plan bounds kt (Nx + 1) by 3500)
+    float2 lv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = threadIdx.x + u * kFFTThreads;
+      if (e < Nx * kt) {
+        const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
+        const int kz = kz0 + l;
+        lv[u] = (kz < H) ? base[xx * xstride + kz] : make_float2(0.f, 0.f);
+      }
+    }
+    gtable();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = threadIdx.x + u * kFFTThreads;
+      if (e < Nx * kt) {
+        const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
+        X[l * ps + xx] = lv[u];
+      }
+    }
+    twr.store(tw, Nx);
+    __syncthreads();
+    Z = lds_fft(X, Y, kt, ps, a.ax, tw, -1.0f, 0, last);
+  }
   float2* W = (Z == X) ? Y : X;
   float e_acc = 0.0f;
   {
@@ -550,21 +628,36 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
         if (epart) e_acc = fmaf(wgt * gg, v.x * v.x + v.y * v.y, e_acc);
         return gg;
       };
-      switch (st.R) {
-#define PME_XM(R) \
-  case R: x_middle<R>(in, out, j, NR, tw, gm); break;
-        PME_XM(2) PME_XM(3) PME_XM(4) PME_XM(5) PME_XM(6) PME_XM(8) PME_XM(10)
-#undef PME_XM
-        default: break;
-      }
+      with_radix(st.R, [&](auto rc) { x_middle<decltype(rc)::value>(in, out, j, NR, tw, gm); });
     }
   }
   __syncthreads();
-  const float2* R = lds_fft(W, Z, kt, ps, a.axi, tw, +1.0f, 1, -1);
-  for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
-    const int xx = e / kt, l = e - xx * kt;
-    const int kz = kz0 + l;
-    if (kz < H) base[xx * xstride + kz] = R[l * ps + xx];
+  if (fuse_io) {
+    const float2* Rin = lds_fft(W, Z, kt, ps, a.axi, tw, +1.0f, 1, last);
+    const FFTStage& xl = a.axi.st[last];
+    const int t = threadIdx.x;
+    if (t < kt * xl.NR) {
+      const int j = int(fdiv(uint32_t(t), a.ktd)), l = t - j * kt;
+      const int kz = kz0 + l;
+      const int jq = int(fdiv(uint32_t(j), xl.ns)), kk = j - jq * xl.Ns;
+      const float2* in = Rin + l * ps;
+      with_radix(xl.R, [&](auto rc) {
+        constexpr int Rr = decltype(rc)::value;
+        stockham_butterfly_io<Rr, true>(
+            [&](int i) { return in[i]; },
+            [&](int i, float2 v) {
+              if (kz < H) base[size_t(i) * xstride + kz] = v;
+            },
+            j, kk, jq, xl.Ns, xl.NR, xl.step, tw, 1.0f);
+      });
+    }
+  } else {
+    const float2* R = lds_fft(W, Z, kt, ps, a.axi, tw, +1.0f, 1, -1);
+    for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
+      const int xx = e / kt, l = e - xx * kt;
+      const int kz = kz0 + l;
+      if (kz < H) base[xx * xstride + kz] = R[l * ps + xx];
+    }
   }
   if (epart) {
     const double s = block_sum(double(e_acc), red);
