@@ -101,6 +101,9 @@ def _args(argv=None):
                     help="0 skips the oracle timing on the host")
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--breakdown-steps", type=int, default=10)
+    ap.add_argument("--sequential", type=int, default=0,
+                    help="1: pme_forward then pme_backward on one stream instead of pme_step "
+                         "with the cotangent chain on a second stream")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="1 also runs a device copy of 256 MiB (byte-counter calibration)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -142,16 +145,20 @@ def main(argv=None):
     box = torch.tensor(frame.box, dtype=torch.float64, device=dev)
     v = synth.random_cotangents(n, 11, scale_r=0.1)
     vr, vq, vm = (torch.tensor(x, dtype=torch.float32, device=dev) for x in v)
-    plan = Plan(mesh, p, alpha, max_atoms=n, keep_phi=True)
+    plan = Plan(mesh, p, alpha, max_atoms=n, keep_phi=True, concurrent=not args.sequential)
     fo = {"energy": torch.empty(3, dtype=torch.float64, device=dev),
           "dE_dpos": torch.empty(n, 3, device=dev), "dE_dq": torch.empty(n, device=dev),
           "dE_dmu": torch.empty(n, 3, device=dev)}
     bo = {"g_pos": torch.empty(n, 3, device=dev), "g_q": torch.empty(n, device=dev),
           "g_mu": torch.empty(n, 3, device=dev)}
+    so = {**fo, **bo}
 
     def step():
-        plan.forward(pos, q, mu, box, out=fo)
-        plan.backward(pos, q, mu, box, vr, vq, vm, out=bo)
+        if args.sequential:
+            plan.forward(pos, q, mu, box, out=fo)
+            plan.backward(pos, q, mu, box, vr, vq, vm, out=bo)
+        else:
+            plan.step(pos, q, mu, box, vr, vq, vm, out=so)
 
     for _ in range(args.warmup):
         step()
@@ -213,7 +220,9 @@ def main(argv=None):
         "config": {"workload": f"molten-salt box, {n} ions (+-1 e, mu ~ N(0, 0.1^2) e*A), "
                                f"cubic L={frame.box[0, 0]:.3f} A, mesh {mesh[0]}x{mesh[1]}x{mesh[2]}, "
                                f"p={p}, alpha={alpha}, forward + Hessian-vector product",
-                   "atoms": n, "mesh": list(mesh), "order": p, "alpha": alpha},
+                   "atoms": n, "mesh": list(mesh), "order": p, "alpha": alpha,
+                   "call": "pme_forward; pme_backward" if args.sequential else
+                           "pme_step (cotangent chain on a second stream)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                      "traffic": traffic, "kernel": KERNEL_SYMBOL[dominant], "kind": dominant,

@@ -66,6 +66,11 @@ extern "C" {
  * pme_backward with the same (pos, q, mu, box) then reuses it instead of
  * recomputing it.  The caller asserts the inputs are unchanged. */
 #define PME_F_KEEP_PHI  1
+/* Allocate a second set of atom records, counters, density and spectrum (about
+ * doubling the plan's workspace) and a second stream, so that pme_step runs the
+ * forward chain and the cotangent's chain (its density, transform and potential)
+ * concurrently. */
+#define PME_F_CONCURRENT 2
 
 /* ---- mesh strategies for pme_mesh_dims (Sec. 2.3.1) ------------------- */
 #define PME_MESH_POW2    0   /* N = 2^ceil(log2 N_target)                       */
@@ -135,6 +140,21 @@ int pme_backward(pme_plan_t plan, void* stream, int32_t n,
                  const float* pos, const float* q, const float* mu, const double* box,
                  const float* v_pos, const float* v_q, const float* v_mu,
                  float* g_pos, float* g_q, float* g_mu);
+
+/* pme_forward followed by pme_backward of the same (pos, q, mu, box) in one call
+ * (arguments and outputs as there; the backward reuses the forward's phi).  The
+ * forward gradient and H v of one evaluation, as a training step with a force
+ * loss needs them (Sec. 2.4).  With PME_F_CONCURRENT the cotangent's binning,
+ * spread and mesh transform run on the plan's second stream, forked from and
+ * joined back into `stream` before the Hessian-vector gather, so that they
+ * overlap the forward chain; all work is ordered before later work on `stream`.
+ * Without the flag the two run in sequence on `stream`.  Calls on one plan must
+ * not overlap (they share its workspaces). */
+int pme_step(pme_plan_t plan, void* stream, int32_t n,
+             const float* pos, const float* q, const float* mu, const double* box,
+             double* energy, float* dE_dpos, float* dE_dq, float* dE_dmu,
+             const float* v_pos, const float* v_q, const float* v_mu,
+             float* g_pos, float* g_q, float* g_mu);
 
 /* Synchronise `stream`, then return PME_ENONFINITE if any kernel of this plan
  * saw a non-finite position or box since the last pme_status call, or

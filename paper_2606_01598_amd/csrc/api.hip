@@ -22,6 +22,15 @@ struct pme_plan_s {
   bool phi_valid;
   int set;        // counter set of the next binning (alternates)
   pme::KTimer timer;
+  // PME_F_CONCURRENT: the cotangent chain's view of the plan (own records,
+  // counters, density and spectrum; the rest shared with d), its stream and the
+  // fork/join events
+  bool concurrent = false;
+  DevPlan dt;
+  int tset = 0;
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr;
+  hipEvent_t join = nullptr;
 };
 
 namespace pme {
@@ -80,6 +89,16 @@ hipError_t dev_alloc(T** p, size_t count, int64_t& bytes) {
 
 void free_plan(pme_plan_s* pl) {
   for (hipEvent_t e : pl->timer.ev) (void)hipEventDestroy(e);
+  if (pl->concurrent) {
+    DevPlan& t = pl->dt;
+    void* own[] = {t.count[0], t.count[1], t.ovf_count[0], t.ovf_count[1], t.cmax[0], t.cmax[1],
+                   t.rec, t.rho, t.spec};
+    for (void* p : own)
+      if (p) (void)hipFree(p);
+  }
+  if (pl->fork) (void)hipEventDestroy(pl->fork);
+  if (pl->join) (void)hipEventDestroy(pl->join);
+  if (pl->aux) (void)hipStreamDestroy(pl->aux);
   DevPlan& d = pl->d;
   void* ptrs[] = {d.count[0], d.count[1], d.ovf_count[0], d.ovf_count[1], d.cmax[0],
                   d.cmax[1], d.rec, d.twiddle[0], d.twiddle[1], d.twiddle[2],
@@ -147,7 +166,7 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   if (!(desc->alpha > 0.0) || !isfinite(desc->alpha) || !(desc->influence_power >= 0.0) ||
       !isfinite(desc->influence_power) || !isfinite(desc->prefactor))
     return PME_EALPHA;
-  if (desc->max_atoms < 1 || (desc->flags & ~PME_F_KEEP_PHI)) return PME_EINVAL;
+  if (desc->max_atoms < 1 || (desc->flags & ~(PME_F_KEEP_PHI | PME_F_CONCURRENT))) return PME_EINVAL;
   for (int a = 0; a < 3; ++a)
     if (desc->tile[a] < 0 || desc->tile[a] > 1024) return PME_EINVAL;
 
@@ -307,6 +326,33 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   }
   ok(hipMemset(d.status, 0, sizeof(int)));
   ok(hipMemset(d.phi, 0, sizeof(float) * M));
+  if (e == hipSuccess && (desc->flags & PME_F_CONCURRENT)) {
+    pl->concurrent = true;
+    DevPlan& t = pl->dt;
+    t = d;
+    t.count[0] = t.count[1] = nullptr;
+    t.ovf_count[0] = t.ovf_count[1] = nullptr;
+    t.cmax[0] = t.cmax[1] = nullptr;
+    t.rec = nullptr;
+    t.rho = nullptr;
+    t.spec = nullptr;
+    for (int k = 0; k < 2; ++k) {
+      ok(dev_alloc(&t.count[k], size_t(nbins), by));
+      ok(dev_alloc(&t.ovf_count[k], 1, by));
+      ok(dev_alloc(&t.cmax[k], 1, by));
+    }
+    ok(dev_alloc(&t.rec, (size_t(t.ovf_base) + size_t(desc->max_atoms)) * 16, by));
+    ok(dev_alloc(&t.rho, size_t(M), by));
+    ok(dev_alloc(&t.spec, size_t(d.N[0]) * d.N[1] * d.H, by));
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+      ok(hipMemset(t.count[k], 0, sizeof(int) * nbins));
+      ok(hipMemset(t.ovf_count[k], 0, sizeof(int)));
+      ok(hipMemset(t.cmax[k], 0, sizeof(unsigned)));
+    }
+    ok(hipStreamCreateWithFlags(&pl->aux, hipStreamNonBlocking));
+    ok(hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming));
+    ok(hipEventCreateWithFlags(&pl->join, hipEventDisableTiming));
+  }
   if (d.slab) ok(pme::enable_slab_lds(d.slab_lds));
   ok(pme::enable_spread_lds());
   ok(pme::enable_gather_lds());
@@ -387,6 +433,63 @@ int pme_backward(pme_plan_t plan, void* stream, int32_t n, const float* pos, con
   if ((e = pme::launch_gather_hvp(d, s, set, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q,
                                   g_mu, tm.next(PME_K_GATHER_HVP))) != hipSuccess)
     return hip_fail(e);
+  return PME_OK;
+}
+
+int pme_step(pme_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
+             const float* mu, const double* box, double* energy, float* dE_dpos, float* dE_dq,
+             float* dE_dmu, const float* v_pos, const float* v_q, const float* v_mu, float* g_pos,
+             float* g_q, float* g_mu) {
+  if (!plan || n < 0 || !box || (n > 0 && !pos)) return PME_EINVAL;
+  if (n > plan->max_atoms) return PME_ECAPACITY;
+  if (!plan->concurrent) {
+    const int32_t flags = plan->desc.flags;
+    plan->desc.flags |= PME_F_KEEP_PHI;   // the backward reuses this forward's phi
+    int r = pme_forward(plan, stream, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu);
+    if (r == PME_OK)
+      r = pme_backward(plan, stream, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q, g_mu);
+    plan->desc.flags = flags;
+    return r;
+  }
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipStream_t s2 = plan->aux;
+  const DevPlan& d = plan->d;
+  const DevPlan& dt = plan->dt;
+  pme::KTimer& tm = plan->timer;
+  hipError_t e;
+  plan->phi_valid = false;
+  const int set = plan->set;
+  plan->set ^= 1;
+  const int tset = plan->tset;
+  plan->tset ^= 1;
+  // cotangent chain on the second stream: binning, tangent density, its potential
+  // (into dt.rho); it reads only inputs and the shared tables
+  if ((e = hipEventRecord(plan->fork, s)) != hipSuccess) return hip_fail(e);
+  if ((e = hipStreamWaitEvent(s2, plan->fork, 0)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_bin(dt, s2, tset, n, pos, q, mu, box, v_pos, v_q, v_mu, true, false,
+                           tm.next(PME_K_BIN_TANGENT))) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_spread(dt, s2, tset, true, box, tm.next(PME_K_SPREAD_TANGENT))) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_convolve(dt, s2, box, dt.rho, false, &tm)) != hipSuccess) return hip_fail(e);
+  if ((e = hipEventRecord(plan->join, s2)) != hipSuccess) return hip_fail(e);
+  // forward chain on the caller's stream
+  if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
+                           energy != nullptr, tm.next(PME_K_BIN))) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_spread(d, s, set, false, box, tm.next(PME_K_SPREAD))) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_gather(d, s, set, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu,
+                              pme::bin_blocks(n), tm.next(PME_K_GATHER))) != hipSuccess)
+    return hip_fail(e);
+  // join: the Hessian-vector gather reads phi (forward) and the tangent potential
+  if ((e = hipStreamWaitEvent(s, plan->join, 0)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_gather_hvp(dt, s, tset, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q,
+                                  g_mu, tm.next(PME_K_GATHER_HVP))) != hipSuccess)
+    return hip_fail(e);
+  plan->phi_valid = true;
   return PME_OK;
 }
 

@@ -9,6 +9,7 @@ stream.
 * ``Plan``                                     -- pme_plan_create / destroy
 * ``Plan.forward(...)``                        -- pme_forward
 * ``Plan.backward(...)``                       -- pme_backward (Hessian-vector product)
+* ``Plan.step(...)``                           -- pme_step (forward and H v in one call)
 * ``pme_energy(pos, q, mu, box, plan)``        -- E^lr as a differentiable torch op
   (first and second order: forces inside a loss, trained with create_graph)
 """
@@ -63,7 +64,8 @@ class Plan:
     """A PME plan: mesh, order, alpha and the device workspaces (pme_plan_create)."""
 
     def __init__(self, mesh, order: int, alpha: float, max_atoms: int, influence_power: float = 1.0,
-                 prefactor: float = 1.0, keep_phi: bool = True, device=None, tile=None):
+                 prefactor: float = 1.0, keep_phi: bool = True, device=None, tile=None,
+                 concurrent: bool = False):
         self._lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         d = _lib.PMEDesc()
@@ -71,7 +73,7 @@ class Plan:
             d.mesh[k] = int(mesh[k])
         d.order = int(order)
         d.max_atoms = int(max_atoms)
-        d.flags = _lib.PME_F_KEEP_PHI if keep_phi else 0
+        d.flags = (_lib.PME_F_KEEP_PHI if keep_phi else 0) | (_lib.PME_F_CONCURRENT if concurrent else 0)
         d.alpha = float(alpha)
         d.influence_power = float(influence_power)
         d.prefactor = float(prefactor)
@@ -150,6 +152,29 @@ class Plan:
         rc = self._lib.pme_backward(self.handle, _stream(), n, _ptr(pos), _ptr(q), _ptr(mu), _ptr(box),
                                     _ptr(v_pos), _ptr(v_q), _ptr(v_mu), _ptr(out.get("g_pos")),
                                     _ptr(out.get("g_q")), _ptr(out.get("g_mu")))
+        _lib.check(rc)
+        return out
+
+    def step(self, pos, q, mu, box, v_pos=None, v_q=None, v_mu=None, out=None):
+        """pme_step: forward outputs (energy, dE_dpos, dE_dq, dE_dmu) and the
+        Hessian-vector product (g_pos, g_q, g_mu) of one evaluation, in one dict."""
+        n = self._check_common(pos, q, mu, box)
+        _atoms("v_pos", v_pos, n, 3, self.device)
+        _atoms("v_q", v_q, n, 0, self.device)
+        _atoms("v_mu", v_mu, n, 3, self.device)
+        out = {} if out is None else dict(out)
+        dev = self.device
+        shapes = {"energy": ((3,), torch.float64), "dE_dpos": ((n, 3), torch.float32),
+                  "dE_dq": ((n,), torch.float32), "dE_dmu": ((n, 3), torch.float32),
+                  "g_pos": ((n, 3), torch.float32), "g_q": ((n,), torch.float32),
+                  "g_mu": ((n, 3), torch.float32)}
+        for k, (shape, dt) in shapes.items():
+            if k not in out:
+                out[k] = torch.empty(shape, dtype=dt, device=dev)
+        rc = self._lib.pme_step(self.handle, _stream(), n, _ptr(pos), _ptr(q), _ptr(mu), _ptr(box),
+                                _ptr(out["energy"]), _ptr(out["dE_dpos"]), _ptr(out["dE_dq"]),
+                                _ptr(out["dE_dmu"]), _ptr(v_pos), _ptr(v_q), _ptr(v_mu),
+                                _ptr(out["g_pos"]), _ptr(out["g_q"]), _ptr(out["g_mu"]))
         _lib.check(rc)
         return out
 

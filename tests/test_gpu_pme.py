@@ -298,3 +298,41 @@ def test_launch_timer_counts_and_outputs_unchanged():
     assert plan.timer_read() == (0, 0.0)
     assert plan._lib.pme_plan_timer(plan.handle, _lib.PME_EINVAL + 100) == _lib.PME_EINVAL
     plan.status()
+
+
+@pytest.mark.parametrize("concurrent", [False, True])
+def test_step_equals_forward_then_backward(concurrent):
+    """pme_step (forward and H v in one call; with PME_F_CONCURRENT the cotangent
+    chain runs on the plan's second stream) gives the outputs of pme_forward
+    followed by pme_backward, over several calls in a row (both counter sets of
+    each chain), interleaved with plain forward/backward calls, and matches the
+    oracle."""
+    f = synth.molten_box(3000, 12)   # L = 45.4 A
+    mesh, p, a = (48, 45, 50), 6, 0.32
+    pos, q, mu, box = to_dev(f)
+    v = synth.random_cotangents(f.n, 13, scale_r=0.1)
+    vr, vq, vm = (torch.tensor(x, dtype=torch.float32, device=dev()) for x in v)
+    ref_plan = _plan(mesh, p, a, f.n)
+    fo = ref_plan.forward(pos, q, mu, box)
+    bo = ref_plan.backward(pos, q, mu, box, vr, vq, vm)
+    plan = _plan(mesh, p, a, f.n, concurrent=concurrent)
+    keys = ("energy", "dE_dpos", "dE_dq", "dE_dmu", "g_pos", "g_q", "g_mu")
+    want = {**fo, **bo}
+    for call in range(3):
+        out = plan.step(pos, q, mu, box, vr, vq, vm)
+        plan.status()
+        worst = max(float((out[k] - want[k]).abs().max() / want[k].abs().max()) for k in keys)
+        print("step", concurrent, call, f"{worst:.2e}", flush=True)
+        assert worst <= 1e-6
+        # a plain forward/backward between steps keeps both paths consistent
+        fo2 = plan.forward(pos, q, mu, box)
+        bo2 = plan.backward(pos, q, mu, box, vr, vq, vm)
+        assert float((bo2["g_pos"] - bo["g_pos"]).abs().max() / bo["g_pos"].abs().max()) <= 1e-6
+        assert float((fo2["dE_dpos"] - fo["dE_dpos"]).abs().max() / fo["dE_dpos"].abs().max()) <= 1e-6
+    ref = oracle_forward(f, mesh, p, a)
+    assert rel(host(out["energy"]).sum(), ref.energy) <= E_REL_TOL
+    assert rms_rel(host(out["dE_dpos"]), ref.dE_dpos) <= RMS_REL_TOL
+    gp, gq, gm = oracle_hvp(f, mesh, p, a, (host(vr), host(vq), host(vm)))
+    assert rms_rel(host(out["g_pos"]), gp) <= RMS_REL_TOL
+    assert rms_rel(host(out["g_q"]), gq) <= RMS_REL_TOL
+    assert rms_rel(host(out["g_mu"]), gm) <= RMS_REL_TOL
