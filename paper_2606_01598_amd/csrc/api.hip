@@ -472,7 +472,6 @@ int pme_step(pme_plan_t plan, void* stream, int32_t n, const float* pos, const f
   if ((e = pme::launch_spread(dt, s2, tset, true, box, tm.next(PME_K_SPREAD_TANGENT))) != hipSuccess)
     return hip_fail(e);
   if ((e = pme::launch_convolve(dt, s2, box, dt.rho, false, &tm)) != hipSuccess) return hip_fail(e);
-  if ((e = hipEventRecord(plan->join, s2)) != hipSuccess) return hip_fail(e);
   // forward chain on the caller's stream
   if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
                            energy != nullptr, tm.next(PME_K_BIN))) != hipSuccess)
@@ -481,14 +480,19 @@ int pme_step(pme_plan_t plan, void* stream, int32_t n, const float* pos, const f
     return hip_fail(e);
   if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm)) != hipSuccess)
     return hip_fail(e);
+  // the Hessian-vector gather (second stream) reads phi of the forward and the
+  // tangent potential; it runs beside the forward gather
+  if ((e = hipEventRecord(plan->fork, s)) != hipSuccess) return hip_fail(e);
+  if ((e = hipStreamWaitEvent(s2, plan->fork, 0)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_gather_hvp(dt, s2, tset, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q,
+                                  g_mu, tm.next(PME_K_GATHER_HVP))) != hipSuccess)
+    return hip_fail(e);
+  if ((e = hipEventRecord(plan->join, s2)) != hipSuccess) return hip_fail(e);
   if ((e = pme::launch_gather(d, s, set, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu,
                               pme::bin_blocks(n), tm.next(PME_K_GATHER))) != hipSuccess)
     return hip_fail(e);
-  // join: the Hessian-vector gather reads phi (forward) and the tangent potential
+  // join: everything on the second stream is ordered before later work on `stream`
   if ((e = hipStreamWaitEvent(s, plan->join, 0)) != hipSuccess) return hip_fail(e);
-  if ((e = pme::launch_gather_hvp(dt, s, tset, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q,
-                                  g_mu, tm.next(PME_K_GATHER_HVP))) != hipSuccess)
-    return hip_fail(e);
   plan->phi_valid = true;
   return PME_OK;
 }

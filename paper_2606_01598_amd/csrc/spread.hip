@@ -295,7 +295,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
   uint16_t* s_map = reinterpret_cast<uint16_t*>(s_bin + a.nbr_max + 2);
   float* s_ent = reinterpret_cast<float*>(s_map + kSpreadMap);
   uint16_t* s_task = reinterpret_cast<uint16_t*>(s_ent + CH * ES);
-  __shared__ int s_n, s_ntask;
+  __shared__ int s_nr[2], s_ntask;
 
   const int tid = threadIdx.x;
   // tangent records: the Jacobian rebuilds their coefficients at staging; it is
@@ -346,6 +346,8 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
   if (tid == 0) {
     s_bin[nbr] = -1;                          // pseudo-bin: the overflow list
     s_off[nbr] = *a.ovf_count;
+    s_nr[0] = 0;
+    s_ntask = 0;
   }
   // each contribution is bounded by 8 sum_k |c_k| <= 8 cmax: scale it to <= 2^40
   float scale = 1.0f;
@@ -408,21 +410,25 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
   };
   const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
   float4 h = z4, c0v = z4, c1v = z4, c2v = z4;
-  if (tid < CH && tid < total) fetch(tid, h, c0v, c1v, c2v);
+  if (tid < total) fetch(tid, h, c0v, c1v, c2v);
 
-  for (int r0 = 0; r0 < total; r0 += CH) {
-    if (tid == 0) { s_n = 0; s_ntask = 0; }
+  // rounds of 256 scanned records (one per thread); the hits of a round (about a
+  // third of them) are staged and accumulated in sub-rounds of at most CH entries
+  // (the hit counter of round r is s_nr[r & 1]; the other one is cleared once every
+  // thread has passed the round's first barrier, i.e. has read it in round r - 1)
+  for (int r0 = 0, rr = 0; r0 < total; r0 += 256, ++rr) {
     // the next round's record is loaded now and used after this round's
     // accumulation (barriers do not wait for global loads)
     float4 nh = z4, nc0 = z4, nc1 = z4, nc2 = z4;
-    if (tid < CH && r0 + CH + tid < total) fetch(r0 + CH + tid, nh, nc0, nc1, nc2);
+    if (r0 + 256 + tid < total) fetch(r0 + 256 + tid, nh, nc0, nc1, nc2);
     __syncthreads();
+    if (tid == 0) s_nr[(rr + 1) & 1] = 0;
     // 1. keep the records whose stencil reaches the tile; stage their weights,
     //    tile-local coordinates and coefficients, and one task per stencil x-plane
     //    that lies in the tile
     bool hit = false;
-    int lw[3][2];
-    if (tid < CH && r0 + tid < total) {
+    if (r0 + tid < total) {
+      int lw[3][2];
       const int pk = __float_as_int(h.w);
       const int b[3] = {pk & 1023, (pk >> 10) & 1023, (pk >> 20) & 1023};
 #pragma unroll
@@ -436,117 +442,133 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
       };
       hit = any_in(lw[0][0], lw[0][1]) && any_in(lw[1][0], lw[1][1]) && any_in(lw[2][0], lw[2][1]);
     }
-    const int k = wave_compact(hit, &s_n);
-    if (hit) {
-      float* ent = s_ent + k * ES;
-#pragma unroll
-      for (int ax = 0; ax < 3; ++ax) {
-        ent[NW + NC + 2 * ax] = __int_as_float(lw[ax][0]);
-        ent[NW + NC + 2 * ax + 1] = __int_as_float(lw[ax][1]);
-      }
-      ent[NW + NC + 6] = h.x; ent[NW + NC + 7] = h.y; ent[NW + NC + 8] = h.z;
-      if (NC == 10) {
-        // tangent records carry q, mu, v_q, v_r, v_mu
-        float co[10];
-        float Jt[3][3];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) Jt[i / 3][i % 3] = s_J[i];
-        tangent_coeffs(Jt, c0v.x, make_float3(c0v.y, c0v.z, c0v.w), c1v.x,
-                       make_float3(c1v.y, c1v.z, c1v.w), make_float3(c2v.x, c2v.y, c2v.z), co);
-#pragma unroll
-        for (int k = 0; k < 10; ++k) ent[NW + k] = co[k];
-      } else {
-        ent[NW + 0] = c0v.x; ent[NW + 1] = c0v.y; ent[NW + 2] = c0v.z; ent[NW + 3] = c0v.w;
-      }
-      int nx = 0;
-#pragma unroll
-      for (int j = 0; j < P; ++j) nx += (loc_of(lw[0][0], lw[0][1], j) >= 0) ? 1 : 0;
-      int t = atomicAdd(&s_ntask, nx);
-#pragma unroll
-      for (int j = 0; j < P; ++j)
-        if (loc_of(lw[0][0], lw[0][1], j) >= 0) s_task[t++] = uint16_t((k << 3) | j);
-    }
+    const int k = wave_compact(hit, &s_nr[rr & 1]);
     __syncthreads();
-    // weights: one thread per (entry, axis); the x weights carry the fixed-point unit
-    {
-      const int nent = s_n;
-      for (int t = tid; t < 3 * nent; t += 256) {
-        const int e = t / 3, ax = t - 3 * e;
-        float* ent = s_ent + e * ES;
-        float w[D + 1][P];
-        spline_weights<P, D>(ent[NW + NC + 6 + ax], w);
-        const float sc = (ax == 0) ? scale : 1.0f;
+    const int nhit = s_nr[rr & 1];
+    for (int base = 0; base < nhit; base += CH) {
+      if (hit && k >= base && k < base + CH) {
+        const int ke = k - base;
+        float* ent = s_ent + ke * ES;
+        int lw[3][2];   // made again from the anchor: not held in registers across sub-rounds
+        {
+          int pk = __float_as_int(h.w);
+          asm volatile("" : "+v"(pk));   // opaque here, so that this is not hoisted out of the loop
+          const int b[3] = {pk & 1023, (pk >> 10) & 1023, (pk >> 20) & 1023};
+#pragma unroll
+          for (int ax = 0; ax < 3; ++ax)
+            axis_locs<P>(b[ax], t0[ax], T[ax], a.N[ax], lw[ax][0], lw[ax][1]);
+        }
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+          ent[NW + NC + 2 * ax] = __int_as_float(lw[ax][0]);
+          ent[NW + NC + 2 * ax + 1] = __int_as_float(lw[ax][1]);
+        }
+        ent[NW + NC + 6] = h.x; ent[NW + NC + 7] = h.y; ent[NW + NC + 8] = h.z;
+        if (NC == 10) {
+          // tangent records carry q, mu, v_q, v_r, v_mu
+          float co[10];
+          float Jt[3][3];
+#pragma unroll
+          for (int i = 0; i < 9; ++i) Jt[i / 3][i % 3] = s_J[i];
+          tangent_coeffs(Jt, c0v.x, make_float3(c0v.y, c0v.z, c0v.w), c1v.x,
+                         make_float3(c1v.y, c1v.z, c1v.w), make_float3(c2v.x, c2v.y, c2v.z), co);
+#pragma unroll
+          for (int k = 0; k < 10; ++k) ent[NW + k] = co[k];
+        } else {
+          ent[NW + 0] = c0v.x; ent[NW + 1] = c0v.y; ent[NW + 2] = c0v.z; ent[NW + 3] = c0v.w;
+        }
+        int nx = 0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) nx += (loc_of(lw[0][0], lw[0][1], j) >= 0) ? 1 : 0;
+        int t = atomicAdd(&s_ntask, nx);
+#pragma unroll
+        for (int j = 0; j < P; ++j)
+          if (loc_of(lw[0][0], lw[0][1], j) >= 0) s_task[t++] = uint16_t((ke << 3) | j);
+      }
+
+      __syncthreads();
+      const int ntask = s_ntask;
+      // weights: one thread per (entry, axis); the x weights carry the fixed-point unit
+      {
+        const int nent = min(CH, nhit - base);
+        for (int t = tid; t < 3 * nent; t += 256) {
+          const int e = t / 3, ax = t - 3 * e;
+          float* ent = s_ent + e * ES;
+          float w[D + 1][P];
+          spline_weights<P, D>(ent[NW + NC + 6 + ax], w);
+          const float sc = (ax == 0) ? scale : 1.0f;
+#pragma unroll
+          for (int d = 0; d <= D; ++d)
+#pragma unroll
+            for (int j = 0; j < P; ++j) ent[(ax * (D + 1) + d) * P + j] = w[d][j] * sc;
+        }
+      }
+      __syncthreads();
+      if (tid == 0) s_ntask = 0;   // every thread has read it before the barrier above
+      // 2. accumulate: one task per (atom, in-tile x-plane of its stencil); stencil
+      //    points outside the tile along z go to the scratch column T_z of their row
+      for (int t = tid; t < ntask; t += 256) {
+        const int task = s_task[t];
+        const int e = task >> 3, ix = task & 7;
+        const float* ent = s_ent + e * ES;
+        const int lx = loc_of(__float_as_int(ent[NW + NC]), __float_as_int(ent[NW + NC + 1]), ix);
+        const int ly0 = __float_as_int(ent[NW + NC + 2]), ly1 = __float_as_int(ent[NW + NC + 3]);
+        const int lz0 = __float_as_int(ent[NW + NC + 4]), lz1 = __float_as_int(ent[NW + NC + 5]);
+        float wz[D + 1][P];
+        int zi[P];
 #pragma unroll
         for (int d = 0; d <= D; ++d)
 #pragma unroll
-          for (int j = 0; j < P; ++j) ent[(ax * (D + 1) + d) * P + j] = w[d][j] * sc;
-      }
-    }
-    __syncthreads();
-    // 2. accumulate: one task per (atom, in-tile x-plane of its stencil); stencil
-    //    points outside the tile along z go to the scratch column T_z of their row
-    const int ntask = s_ntask;
-    for (int t = tid; t < ntask; t += 256) {
-      const int task = s_task[t];
-      const int e = task >> 3, ix = task & 7;
-      const float* ent = s_ent + e * ES;
-      const int lx = loc_of(__float_as_int(ent[NW + NC]), __float_as_int(ent[NW + NC + 1]), ix);
-      const int ly0 = __float_as_int(ent[NW + NC + 2]), ly1 = __float_as_int(ent[NW + NC + 3]);
-      const int lz0 = __float_as_int(ent[NW + NC + 4]), lz1 = __float_as_int(ent[NW + NC + 5]);
-      float wz[D + 1][P];
-      int zi[P];
+          for (int j = 0; j < P; ++j) wz[d][j] = ent[(2 * (D + 1) + d) * P + j];
 #pragma unroll
-      for (int d = 0; d <= D; ++d)
-#pragma unroll
-        for (int j = 0; j < P; ++j) wz[d][j] = ent[(2 * (D + 1) + d) * P + j];
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        const int l = loc_of(lz0, lz1, j);
-        zi[j] = (l >= 0) ? l : T[2];
-      }
-      float x[D + 1];
-#pragma unroll
-      for (int d = 0; d <= D; ++d) x[d] = ent[d * P + ix];   // pre-scaled by the fixed-point unit
-      float co[NC];
-#pragma unroll
-      for (int kk = 0; kk < NC; ++kk) co[kk] = ent[NW + kk];
-      // this x-plane's coefficients of the (y, z) derivative monomials
-      float ax0, az1, az2 = 0.f, ay1, ay2 = 0.f, ayz = 0.f;
-      if (DEG == 1) {
-        ax0 = co[0] * x[0] + co[1] * x[1];   // W_y W_z
-        ay1 = co[2] * x[0];                  // W_y' W_z
-        az1 = co[3] * x[0];                  // W_y W_z'
-      } else {
-        ax0 = co[0] * x[0] + co[1] * x[1] + co[4] * x[2];
-        ay1 = co[2] * x[0] + co[7] * x[1];
-        az1 = co[3] * x[0] + co[8] * x[1];
-        ay2 = co[5] * x[0];
-        az2 = co[6] * x[0];
-        ayz = co[9] * x[0];
-      }
-      const int rowx = lx * T[1];
-#pragma unroll
-      for (int iy = 0; iy < P; ++iy) {
-        const int ly = loc_of(ly0, ly1, iy);
-        if (ly < 0) continue;
-        const float y0 = ent[(D + 1) * P + iy], y1 = ent[(D + 1) * P + P + iy];
-        float c0 = ax0 * y0 + ay1 * y1, c1 = az1 * y0, c2 = 0.f;
-        if (DEG == 2) {
-          const float y2 = ent[(D + 1) * P + 2 * P + iy];
-          c0 += ay2 * y2;
-          c1 += ayz * y1;
-          c2 = az2 * y0;
+        for (int j = 0; j < P; ++j) {
+          const int l = loc_of(lz0, lz1, j);
+          zi[j] = (l >= 0) ? l : T[2];
         }
-        unsigned long long* row = s_tile + (rowx + ly) * TZP;
+        float x[D + 1];
 #pragma unroll
-        for (int iz = 0; iz < P; ++iz) {
-          float v = c0 * wz[0][iz] + c1 * wz[1][iz];
-          if (DEG == 2) v += c2 * wz[2][iz];
-          atomicAdd(row + zi[iz], to_fixed(v));
+        for (int d = 0; d <= D; ++d) x[d] = ent[d * P + ix];   // pre-scaled by the fixed-point unit
+        float co[NC];
+#pragma unroll
+        for (int kk = 0; kk < NC; ++kk) co[kk] = ent[NW + kk];
+        // this x-plane's coefficients of the (y, z) derivative monomials
+        float ax0, az1, az2 = 0.f, ay1, ay2 = 0.f, ayz = 0.f;
+        if (DEG == 1) {
+          ax0 = co[0] * x[0] + co[1] * x[1];   // W_y W_z
+          ay1 = co[2] * x[0];                  // W_y' W_z
+          az1 = co[3] * x[0];                  // W_y W_z'
+        } else {
+          ax0 = co[0] * x[0] + co[1] * x[1] + co[4] * x[2];
+          ay1 = co[2] * x[0] + co[7] * x[1];
+          az1 = co[3] * x[0] + co[8] * x[1];
+          ay2 = co[5] * x[0];
+          az2 = co[6] * x[0];
+          ayz = co[9] * x[0];
+        }
+        const int rowx = lx * T[1];
+#pragma unroll
+        for (int iy = 0; iy < P; ++iy) {
+          const int ly = loc_of(ly0, ly1, iy);
+          if (ly < 0) continue;
+          const float y0 = ent[(D + 1) * P + iy], y1 = ent[(D + 1) * P + P + iy];
+          float c0 = ax0 * y0 + ay1 * y1, c1 = az1 * y0, c2 = 0.f;
+          if (DEG == 2) {
+            const float y2 = ent[(D + 1) * P + 2 * P + iy];
+            c0 += ay2 * y2;
+            c1 += ayz * y1;
+            c2 = az2 * y0;
+          }
+          unsigned long long* row = s_tile + (rowx + ly) * TZP;
+#pragma unroll
+          for (int iz = 0; iz < P; ++iz) {
+            float v = c0 * wz[0][iz] + c1 * wz[1][iz];
+            if (DEG == 2) v += c2 * wz[2][iz];
+            atomicAdd(row + zi[iz], to_fixed(v));
+          }
         }
       }
+      __syncthreads();
     }
-    __syncthreads();
     h = nh; c0v = nc0; c1v = nc1; c2v = nc2;
   }
 
