@@ -145,9 +145,10 @@ int pme_backward(pme_plan_t plan, void* stream, int32_t n,
  * (arguments and outputs as there; the backward reuses the forward's phi).  The
  * forward gradient and H v of one evaluation, as a training step with a force
  * loss needs them (Sec. 2.4).  With PME_F_CONCURRENT the cotangent's binning,
- * spread and mesh transform run on the plan's second stream, forked from and
- * joined back into `stream` before the Hessian-vector gather, so that they
- * overlap the forward chain; all work is ordered before later work on `stream`.
+ * spread and mesh transform run on the plan's second stream, forked from
+ * `stream`, beside the forward chain; the Hessian-vector gather follows there once
+ * the forward potential exists, beside the forward gather, and the second stream
+ * is joined back into `stream`, so all work is ordered before later work on it.
  * Without the flag the two run in sequence on `stream`.  Calls on one plan must
  * not overlap (they share its workspaces). */
 int pme_step(pme_plan_t plan, void* stream, int32_t n,
