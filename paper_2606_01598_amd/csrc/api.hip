@@ -480,19 +480,14 @@ int pme_step(pme_plan_t plan, void* stream, int32_t n, const float* pos, const f
     return hip_fail(e);
   if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm)) != hipSuccess)
     return hip_fail(e);
-  // the Hessian-vector gather (second stream) reads phi of the forward and the
-  // tangent potential; it runs beside the forward gather
-  if ((e = hipEventRecord(plan->fork, s)) != hipSuccess) return hip_fail(e);
-  if ((e = hipStreamWaitEvent(s2, plan->fork, 0)) != hipSuccess) return hip_fail(e);
-  if ((e = pme::launch_gather_hvp(dt, s2, tset, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q,
-                                  g_mu, tm.next(PME_K_GATHER_HVP))) != hipSuccess)
-    return hip_fail(e);
+  // join, then one gather over the cotangent chain's records (which carry q and mu)
+  // forms H v and the forward outputs from phi and the tangent potential
   if ((e = hipEventRecord(plan->join, s2)) != hipSuccess) return hip_fail(e);
-  if ((e = pme::launch_gather(d, s, set, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu,
-                              pme::bin_blocks(n), tm.next(PME_K_GATHER))) != hipSuccess)
-    return hip_fail(e);
-  // join: everything on the second stream is ordered before later work on `stream`
   if ((e = hipStreamWaitEvent(s, plan->join, 0)) != hipSuccess) return hip_fail(e);
+  const pme::GatherForward fwd{energy, dE_dpos, dE_dq, dE_dmu, pme::bin_blocks(n)};
+  if ((e = pme::launch_gather_hvp(dt, s, tset, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q,
+                                  g_mu, tm.next(PME_K_GATHER_HVP), &fwd)) != hipSuccess)
+    return hip_fail(e);
   plan->phi_valid = true;
   return PME_OK;
 }

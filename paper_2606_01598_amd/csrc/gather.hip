@@ -47,6 +47,11 @@ struct GArgs {
   float* o_pos;
   float* o_q;
   float* o_mu;
+  // Hessian-vector gather only: the forward outputs of the same atoms as well (the
+  // stencil sums of phi it forms include those of the gradient); null to skip
+  float* f_pos;
+  float* f_q;
+  float* f_mu;
   double* energy;
   const double* epart;
   int n_epart;
@@ -200,7 +205,7 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   for (int k = tid; k < 4 * P * P; k += blockDim.x) s_coef[k] = c_spline.coef[spline_offset(P) + k];
   __syncthreads();
   const Cell c = cell_from_box(a.box);
-  if (!HVP && tile == 0 && a.energy) finalize_energy(a, c);
+  if (tile == 0 && a.energy) finalize_energy(a, c);
   int t0[3], T[3], E[3];
   {
     int t = tile;
@@ -442,13 +447,14 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
 #pragma unroll
               for (int k = 0; k + b + x < 3; ++k) Q[x][b][k] = wx[x] * Yq[b][k];
         }
+        const bool dual = a.f_q || a.f_mu || a.f_pos;
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
           for (int b = 0; b + x < 4; ++b)
 #pragma unroll
             for (int k = 0; k + b + x < 4; ++k)
-              if (x + b + k >= 1) S[x][b][k] = group_sum<P>(S[x][b][k], ix);
+              if (x + b + k >= 1 || dual) S[x][b][k] = group_sum<P>(S[x][b][k], ix);
 #pragma unroll
         for (int x = 0; x < 3; ++x)
 #pragma unroll
@@ -514,6 +520,23 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
                      vq * S1[x] + S2[x][0] * w[0] + S2[x][1] * w[1] + S2[x][2] * w[2] + T3[x];
             const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
             st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+          }
+          if (dual) {
+            // gradient of E^lr: S000, the first and second derivative sums of phi
+            if (a.f_q) a.f_q[i] = pf * (S[0][0][0] * iv - cq * q);
+            if (a.f_mu) {
+              const float3 g = jtmul(J, make_float3(S1[0], S1[1], S1[2]));
+              st3(a.f_mu, i, make_float3(pf * (g.x * iv - cm * mu.x), pf * (g.y * iv - cm * mu.y),
+                                         pf * (g.z * iv - cm * mu.z)));
+            }
+            if (a.f_pos) {
+              float u[3];
+#pragma unroll
+              for (int x = 0; x < 3; ++x)
+                u[x] = q * S1[x] + S2[x][0] * d[0] + S2[x][1] * d[1] + S2[x][2] * d[2];
+              const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
+              st3(a.f_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+            }
           }
         }
       }
@@ -733,11 +756,17 @@ hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const 
 hipError_t launch_gather_hvp(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                              const float* q, const float* mu, const double* box,
                              const float* v_pos, const float* v_q, const float* v_mu,
-                             float* g_pos, float* g_q, float* g_mu, const LaunchEvents* ev) {
+                             float* g_pos, float* g_q, float* g_mu, const LaunchEvents* ev,
+                             const GatherForward* fwd) {
   GArgs a = base_args(d, set, n, pos, q, mu, box);
   a.psi = d.rho;
   a.v_pos = v_pos; a.v_q = v_q; a.v_mu = v_mu;
   a.o_pos = g_pos; a.o_q = g_q; a.o_mu = g_mu;
+  if (fwd) {
+    a.f_pos = fwd->dE_dpos; a.f_q = fwd->dE_dq; a.f_mu = fwd->dE_dmu;
+    a.energy = fwd->energy; a.epart = d.epart; a.n_epart = fftx_blocks(d);
+    a.spart = d.spart; a.n_spart = fwd->n_spart;
+  }
   return gather_dispatch<true>(d.p, dim3(d.nt[0] * d.nt[1] * d.nt[2]), region_bytes(d, 2), s, a,
                                ev);
 }

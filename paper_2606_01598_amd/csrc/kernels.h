@@ -233,9 +233,18 @@ hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const 
                          float* dE_dpos, float* dE_dq, float* dE_dmu, int n_spart,
                          const LaunchEvents* ev);
 // Hessian-vector product gather from phi (d.phi) and psi (d.rho).
+// Forward outputs a Hessian-vector gather may form as well (same atoms, same phi).
+struct GatherForward {
+  double* energy;
+  float* dE_dpos;
+  float* dE_dq;
+  float* dE_dmu;
+  int n_spart;   // self-term partial sums written by the forward binning
+};
 hipError_t launch_gather_hvp(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                              const float* q, const float* mu, const double* box,
                              const float* v_pos, const float* v_q, const float* v_mu,
-                             float* g_pos, float* g_q, float* g_mu, const LaunchEvents* ev);
+                             float* g_pos, float* g_q, float* g_mu, const LaunchEvents* ev,
+                             const GatherForward* fwd = nullptr);
 
 }  // namespace pme
