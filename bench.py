@@ -61,10 +61,9 @@ KERNEL_SYMBOL = {
 }
 
 
-def alg_bytes(kind: str, n: int, m: int) -> int:
+def alg_bytes(kind: str, n: int, m: int, step: bool = True) -> int:
     """Algorithmic HBM bytes of one launch: the method's arrays (FP32) that the
-    step must read or write, split over the kernels that touch them.  Summed over a
-    forward + backward step this is 224 B per atom + 36 B per mesh point:
+    step must read or write, split over the kernels that touch them.
       bin            pos, q, mu in                               28 n
       bin_tangent    pos, q, mu, v_pos, v_q, v_mu in             56 n
       spread(_tan.)  rho (or the tangent density) out            4 M
@@ -73,11 +72,18 @@ def alg_bytes(kind: str, n: int, m: int) -> int:
       fft_c2r        potential out                               4 M
       gather         pos, q, mu in; 3 gradients out; phi in      56 n + 4 M
       gather_hvp     6 inputs in; 3 outputs; phi and psi in      84 n + 8 M
+                     (pme_step: also the 3 gradients out        112 n + 8 M)
+    A pme_forward + pme_backward step sums to 224 B per atom + 36 B per mesh point;
+    a pme_step (one gather for both) to 196 B per atom + 32 B per mesh point.
     """
     table = {"bin": 28 * n, "bin_tangent": 56 * n, "spread": 4 * m, "spread_tangent": 4 * m,
              "fft_r2c": 4 * m, "fft_x": 0, "fft_c2r": 4 * m, "gather": 56 * n + 4 * m,
-             "gather_hvp": 84 * n + 8 * m}
+             "gather_hvp": (112 if step else 84) * n + 8 * m}
     return table[kind]
+
+
+def step_bytes(n: int, m: int, step: bool = True) -> int:
+    return 196 * n + 32 * m if step else 224 * n + 36 * m
 
 
 def source_digest() -> str:
@@ -109,6 +115,9 @@ def _args(argv=None):
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter summary of the dominant kernel and exit")
     ap.add_argument("--kernel", default=None, help="kernel kind for --traffic-summary")
+    ap.add_argument("--kernel-stats", default=None, metavar="STATS_CSV",
+                    help="write profiles/<workload> kernel-statistics summary from a "
+                         "rocprofv3 --stats kernel_stats.csv")
     ap.add_argument("--batched", type=int, default=1,
                     help="1 adds the batched-graph leg (64 boxes, one HIP graph per step)")
     ap.add_argument("--learned", type=int, default=1,
@@ -123,6 +132,8 @@ def main(argv=None):
     args = _args(argv)
     if args.traffic_summary:
         return traffic_summary(args)
+    if args.kernel_stats:
+        return kernel_stats_summary(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -176,7 +187,7 @@ def main(argv=None):
             kernels_us[kind] = round(1e3 * ms / launches, 3)
             per_step_us[kind] = 1e3 * ms / args.breakdown_steps
     plan.timer(None)
-    dominant = max((k for k in per_step_us if alg_bytes(k, n, m) > 0),
+    dominant = max((k for k in per_step_us if alg_bytes(k, n, m, not args.sequential) > 0),
                    key=lambda k: per_step_us[k])
 
     # timed region; the dominant kernel's launches are bracketed by HIP events
@@ -201,7 +212,7 @@ def main(argv=None):
         torch.cuda.synchronize()
 
     dur_s = dom_ms / launches / 1e3
-    ab = alg_bytes(dominant, n, m)
+    ab = alg_bytes(dominant, n, m, not args.sequential)
     achieved = ab / dur_s / 1e9
     traffic = read_traffic(dominant, args.workload)
     line = {
@@ -229,7 +240,7 @@ def main(argv=None):
                      "alg_bytes_per_launch": ab, "avg_launch_us": round(dur_s * 1e6, 3),
                      "launches": launches},
         "kernels_us": kernels_us,
-        "step_model_bytes": 224 * n + 36 * m,
+        "step_model_bytes": step_bytes(n, m, not args.sequential),
     }
     if args.batched:
         line["batched"] = batched_leg()
@@ -501,6 +512,43 @@ def traffic_summary(args) -> int:
         fh.write(f"write_bytes_per_launch: {wb:.0f}\n")
         fh.write(f"traffic_bytes_per_launch: {fb + wb:.0f}\n")
         fh.write(f"alg_bytes_per_launch: {alg_bytes(kind, n, m)}\n")
+    print(open(out).read())
+    return 0
+
+
+def kernel_stats_summary(args) -> int:
+    """profiles/pme_step_<workload>_kernel_stats.txt from rocprofv3's kernel_stats.csv."""
+    rows = []
+    with open(args.kernel_stats) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Name"].replace("void ", "").replace("pme::(anonymous namespace)::", "")
+            name = name.split("(")[0] if "(" in name else name
+            rows.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3,
+                         float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
+    rows.sort(key=lambda x: -x[5])
+    out = os.path.join(ROOT, "profiles", f"pme_step_{args.workload}_kernel_stats.txt")
+    n, _, mesh, p, _ = WORKLOADS[args.workload]
+    call = "pme_forward; pme_backward" if args.sequential else "pme_step (concurrent chains)"
+    seq = " --sequential 1" if args.sequential else ""
+    lines = [
+        f"# rocprofv3 kernel statistics: PME forward + Hessian-vector product ({call}),",
+        f"# {n}-ion molten-salt box, mesh {mesh[0]}^3, p = {p}, one MI355X",
+        "# commands (from the repository root):",
+        "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- \\",
+        f"#       python -u bench.py --steps 20 --warmup 5 --cpu-baseline 0 --batched 0 "
+        f"--learned 0 --workload {args.workload}{seq}",
+        f"#   python bench.py --kernel-stats <dir>/run_kernel_stats.csv --workload "
+        f"{args.workload}{seq}",
+        "# (20 timed + 5 warm-up + 10 per kernel kind breakdown steps; copyBuffer and",
+        "#  fillBuffer are input uploads)",
+        f"# source digest of paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
+        "",
+        f"{'kernel':58s} {'calls':>7s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} {'pct':>6s}",
+    ]
+    for name, calls, avg, mn, mx, pct in rows:
+        lines.append(f"{name[:58]:58s} {calls:7d} {avg:8.2f} {mn:8.2f} {mx:8.2f} {pct:6.2f}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
     print(open(out).read())
     return 0
 
