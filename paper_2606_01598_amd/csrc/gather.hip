@@ -399,8 +399,8 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
           const int pk = __float_as_int(h.w);
           const int lx = (pk & 1023) - t0[0] + ix;
           const int yb = ((pk >> 10) & 1023) - t0[1], zb = ((pk >> 20) & 1023) - t0[2];
-          float wy[4][P], wz[4][P], wx[4];
-          spline_weights<P, 3>(h.y, wy);
+          // y weights are made per row (fewer live registers), z weights once
+          float wz[4][P], wx[4];
           spline_weights<P, 3>(h.z, wz);
           weight_at_lds<P, 3>(s_coef, ix, h.x, wx);
           const float* pphi = sm + (lx * E[1] + yb) * E[2] + zb;
@@ -425,14 +425,16 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
 #pragma unroll
               for (int k = 0; k < 3; ++k) zq[k] = fmaf(u, wz[k][iz], zq[k]);
             }
+            float wy[4];
+            spline_weight_at<P, 3>(iy, h.y, wy);
 #pragma unroll
             for (int b = 0; b < 4; ++b)
 #pragma unroll
-              for (int k = 0; k + b < 4; ++k) Ys[b][k] = fmaf(wy[b][iy], zs[k], Ys[b][k]);
+              for (int k = 0; k + b < 4; ++k) Ys[b][k] = fmaf(wy[b], zs[k], Ys[b][k]);
 #pragma unroll
             for (int b = 0; b < 3; ++b)
 #pragma unroll
-              for (int k = 0; k + b < 3; ++k) Yq[b][k] = fmaf(wy[b][iy], zq[k], Yq[b][k]);
+              for (int k = 0; k + b < 3; ++k) Yq[b][k] = fmaf(wy[b], zq[k], Yq[b][k]);
           }
 #pragma unroll
           for (int x = 0; x < 4; ++x)

@@ -336,3 +336,33 @@ def test_step_equals_forward_then_backward(concurrent):
     assert rms_rel(host(out["g_pos"]), gp) <= RMS_REL_TOL
     assert rms_rel(host(out["g_q"]), gq) <= RMS_REL_TOL
     assert rms_rel(host(out["g_mu"]), gm) <= RMS_REL_TOL
+
+
+def test_step_edge_cases_concurrent():
+    """pme_step with PME_F_CONCURRENT: no atoms; a pencil-layout mesh with odd
+    sizes; cotangents on positions only (the force-loss case, v_q = v_mu = NULL),
+    each against pme_forward + pme_backward of a plain plan."""
+    # no atoms: zero energy, nothing written
+    plan = _plan((16, 16, 16), 6, 0.3, 4, concurrent=True)
+    box = torch.eye(3, dtype=torch.float64, device=dev()) * 12.0
+    z = torch.zeros(0, 3, dtype=torch.float32, device=dev())
+    out = plan.step(z, torch.zeros(0, device=dev()), z.clone(), box, z.clone(),
+                    torch.zeros(0, device=dev()), z.clone())
+    plan.status()
+    assert np.all(host(out["energy"]) == 0.0)
+    # pencil layout, odd sizes, position-only cotangents
+    box_np = np.diag([12.0, 80.0, 75.0])
+    f = _random_frame(400, box_np, 21)
+    mesh, p, a = (12, 160, 150), 5, 0.45
+    pos, q, mu, box_t = to_dev(f)
+    vr = torch.tensor(synth.random_cotangents(f.n, 4, scale_r=0.1)[0], dtype=torch.float32,
+                      device=dev())
+    ref_plan = _plan(mesh, p, a, f.n)
+    want = {**ref_plan.forward(pos, q, mu, box_t), **ref_plan.backward(pos, q, mu, box_t, vr)}
+    plan = _plan(mesh, p, a, f.n, concurrent=True)
+    for call in range(2):
+        out = plan.step(pos, q, mu, box_t, vr)
+        plan.status()
+        worst = max(float((out[k] - want[k]).abs().max() / want[k].abs().max()) for k in want)
+        print("step pencil", call, f"{worst:.2e}", flush=True)
+        assert worst <= 1e-6
