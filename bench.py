@@ -118,6 +118,13 @@ def _args(argv=None):
     ap.add_argument("--kernel-stats", default=None, metavar="STATS_CSV",
                     help="write profiles/<workload> kernel-statistics summary from a "
                          "rocprofv3 --stats kernel_stats.csv")
+    ap.add_argument("--bench-line", default=None, metavar="LOG",
+                    help="with --kernel-stats: a log holding the JSON line of the same bench "
+                         "command run without the profiler; its kernels_us are listed beside "
+                         "the profiler's averages")
+    ap.add_argument("--sweep-summary", nargs="+", default=None, metavar="LOG",
+                    help="write profiles/pme_sweep_molten_sizes.txt from the JSON lines of "
+                         "bench runs at several workloads and exit")
     ap.add_argument("--batched", type=int, default=1,
                     help="1 adds the batched-graph leg (64 boxes, one HIP graph per step)")
     ap.add_argument("--learned", type=int, default=1,
@@ -134,6 +141,8 @@ def main(argv=None):
         return traffic_summary(args)
     if args.kernel_stats:
         return kernel_stats_summary(args)
+    if args.sweep_summary:
+        return sweep_summary(args.sweep_summary)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -464,6 +473,12 @@ def _counter_means(path: str, counter: str):
     return {k: (sums[k] / cnt[k], cnt[k]) for k in sums}
 
 
+# bench.py flags of the counter passes: a few steps (a profiler with counters slows
+# every launch), no side legs, one breakdown step per kind, the copy calibration
+PMC_FLAGS = ("--steps 3 --warmup 2 --cpu-baseline 0 --batched 0 --learned 0 "
+             "--copy-calibration 1 --breakdown-steps 1")
+
+
 def traffic_summary(args) -> int:
     fetch = _counter_means(args.traffic_summary[0], "FETCH_SIZE")
     write = _counter_means(args.traffic_summary[1], "WRITE_SIZE")
@@ -491,11 +506,10 @@ def traffic_summary(args) -> int:
     os.makedirs(os.path.dirname(out), exist_ok=True)
     with open(out, "w") as fh:
         fh.write(f"# HBM traffic of {sym} ({kind}), workload {args.workload}\n")
-        fh.write("# commands:\n")
-        fh.write("#   rocprofv3 --pmc FETCH_SIZE -d <D1> -o run -- python bench.py --steps 3 "
-                 f"--warmup 2 --workload {args.workload} --cpu-baseline 0 --copy-calibration 1\n")
-        fh.write("#   rocprofv3 --pmc WRITE_SIZE -d <D2> -o run -- python bench.py --steps 3 "
-                 f"--warmup 2 --workload {args.workload} --cpu-baseline 0 --copy-calibration 1\n")
+        fh.write("# commands (from the repository root):\n")
+        for ctr, d in (("FETCH_SIZE", "<D1>"), ("WRITE_SIZE", "<D2>")):
+            fh.write(f"#   rocprofv3 --pmc {ctr} --output-format csv -d {d} -o run -- "
+                     f"python -u bench.py {PMC_FLAGS} --workload {args.workload}\n")
         fh.write("#   python bench.py --traffic-summary <D1>/run_counter_collection.csv "
                  f"<D2>/run_counter_collection.csv --kernel {kind} --workload {args.workload}\n")
         fh.write(f"sources: {source_digest()}\n")
@@ -517,7 +531,9 @@ def traffic_summary(args) -> int:
 
 
 def kernel_stats_summary(args) -> int:
-    """profiles/pme_step_<workload>_kernel_stats.txt from rocprofv3's kernel_stats.csv."""
+    """profiles/pme_step_<workload>[_sequential]_kernel_stats.txt from rocprofv3's
+    kernel_stats.csv, with bench.py's own launch timer beside it when --bench-line
+    names the log of the same command run without the profiler."""
     rows = []
     with open(args.kernel_stats) as fh:
         for r in csv.DictReader(fh):
@@ -526,7 +542,18 @@ def kernel_stats_summary(args) -> int:
             rows.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3,
                          float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
     rows.sort(key=lambda x: -x[5])
-    out = os.path.join(ROOT, "profiles", f"pme_step_{args.workload}_kernel_stats.txt")
+    bench_us, bench_val = {}, None
+    if args.bench_line:
+        with open(args.bench_line) as fh:
+            for ln in fh:
+                if ln.startswith("{") and '"kernels_us"' in ln:
+                    d = json.loads(ln)
+                    bench_us = {KERNEL_SYMBOL[k]: v for k, v in d["kernels_us"].items()}
+                    bench_val = (d["value"], d["unit"], d["roofline"]["kernel"],
+                                 d["roofline"]["avg_launch_us"])
+                    break
+    suffix = "_sequential" if args.sequential else ""
+    out = os.path.join(ROOT, "profiles", f"pme_step_{args.workload}{suffix}_kernel_stats.txt")
     n, _, mesh, p, _ = WORKLOADS[args.workload]
     call = "pme_forward; pme_backward" if args.sequential else "pme_step (concurrent chains)"
     seq = " --sequential 1" if args.sequential else ""
@@ -537,16 +564,82 @@ def kernel_stats_summary(args) -> int:
         "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- \\",
         f"#       python -u bench.py --steps 20 --warmup 5 --cpu-baseline 0 --batched 0 "
         f"--learned 0 --workload {args.workload}{seq}",
-        f"#   python bench.py --kernel-stats <dir>/run_kernel_stats.csv --workload "
-        f"{args.workload}{seq}",
+        f"#   python -u bench.py --workload {args.workload}{seq} > <log>   (no profiler)",
+        f"#   python bench.py --kernel-stats <dir>/run_kernel_stats.csv --bench-line <log> "
+        f"--workload {args.workload}{seq}",
         "# (20 timed + 5 warm-up + 10 per kernel kind breakdown steps; copyBuffer and",
         "#  fillBuffer are input uploads)",
         f"# source digest of paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
-        "",
-        f"{'kernel':58s} {'calls':>7s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} {'pct':>6s}",
     ]
+    if bench_val:
+        lines.append(f"# bench_us: bench.py's launch timer without the profiler (kernels_us); "
+                     f"that run: {bench_val[0]:.1f} {bench_val[1]}, roofline kernel "
+                     f"{bench_val[2]} at {bench_val[3]:.2f} us per launch")
+    if not args.sequential:
+        lines += [
+            "# Under the profiler every launch is issued some 10-15 us later than without it,",
+            "# so the cotangent chain (second stream) and the forward chain run mostly one",
+            "# after the other and each kernel has the GPU to itself.  Without the profiler",
+            "# the two chains overlap and the kernels that share CUs take longer (bench_us);",
+            "# the sequential-call summary has no overlap to lose and agrees with its timer.",
+        ]
+    lines += ["", f"{'kernel':40s} {'calls':>7s} {'avg_us':>8s} {'min_us':>8s} {'max_us':>8s} "
+              f"{'pct':>6s} {'bench_us':>9s}"]
     for name, calls, avg, mn, mx, pct in rows:
-        lines.append(f"{name[:58]:58s} {calls:7d} {avg:8.2f} {mn:8.2f} {mx:8.2f} {pct:6.2f}")
+        b = bench_us.get(name)
+        bs = f"{b:9.2f}" if b is not None else f"{'':9s}"
+        lines.append(f"{name[:40]:40s} {calls:7d} {avg:8.2f} {mn:8.2f} {mx:8.2f} {pct:6.2f} {bs}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(open(out).read())
+    return 0
+
+
+def sweep_summary(logs) -> int:
+    """profiles/pme_sweep_molten_sizes.txt from bench JSON lines at several sizes."""
+    res = []
+    for path in logs:
+        with open(path) as fh:
+            for ln in fh:
+                if ln.startswith("{") and '"kernels_us"' in ln:
+                    res.append(json.loads(ln))
+                    break
+    res.sort(key=lambda d: d["config"]["atoms"])
+    kinds = [k for k in KERNEL_SYMBOL if any(k in d["kernels_us"] for d in res)]
+    lines = [
+        "# PME forward + Hessian-vector product across sizes (molten-salt boxes at the",
+        "# density of molten NaCl, mesh ~1 A, p = 6, alpha = 0.30), one MI355X, pme_step",
+        "# with the cotangent chain on a second stream",
+        "# commands (repository root):",
+        "#   python -u bench.py --workload 8k   --batched 0 --learned 0 --cpu-baseline 0 "
+        "--steps 100 --warmup 10",
+        "#   python -u bench.py --workload 32k  (the default bench run)",
+        "#   python -u bench.py --workload 128k --batched 0 --learned 0 --cpu-baseline 0 "
+        "--steps 100 --warmup 10",
+        "#   python -u bench.py --workload 1m   --batched 0 --learned 0 --cpu-baseline 0 "
+        "--steps 10 --warmup 3 --breakdown-steps 2",
+        "#   python bench.py --sweep-summary <log 8k> <log 32k> <log 128k> <log 1m>",
+        f"# model bytes per step: {step_bytes(1, 0)} B per atom + {step_bytes(0, 1)} B per "
+        f"mesh point; HBM peak {HBM_PEAK_GBS:.0f} GB/s",
+        f"# source digest of paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
+        "",
+        f"{'atoms':>8s} {'mesh':>5s} {'ms/step':>9s} {'Matom-steps/s':>14s} {'model GB/s':>11s} "
+        f"{'% HBM':>6s}  dominant kernel (us/launch, % HBM of its algorithmic bytes)",
+    ]
+    for d in res:
+        c, r = d["config"], d["roofline"]
+        n, mesh = c["atoms"], c["mesh"]
+        m = mesh[0] * mesh[1] * mesh[2]
+        gbs = step_bytes(n, m) / (d["ms_per_step"] * 1e-3) / 1e9
+        lines.append(f"{n:8d} {mesh[0]:5d} {d['ms_per_step']:9.4f} {d['value']:14.2f} "
+                     f"{gbs:11.1f} {100 * gbs / HBM_PEAK_GBS:6.2f}  {r['kernel']} "
+                     f"{r['avg_launch_us']:.1f} us, {100 * r['frac']:.2f}%")
+    lines += ["", "per-kernel average launch durations (us, the bench's breakdown pass):",
+              f"{'atoms':>8s} " + " ".join(f"{k:>14s}" for k in kinds)]
+    for d in res:
+        lines.append(f"{d['config']['atoms']:8d} " +
+                     " ".join(f"{d['kernels_us'].get(k, float('nan')):14.2f}" for k in kinds))
+    out = os.path.join(ROOT, "profiles", "pme_sweep_molten_sizes.txt")
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print(open(out).read())
