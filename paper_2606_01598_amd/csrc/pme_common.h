@@ -194,12 +194,14 @@ __device__ __forceinline__ int wrapn(int m, int N) {
 __device__ __forceinline__ int wave_compact(bool pred, int* counter) {
   const unsigned long long m = __ballot(pred);
   if (m == 0ull) return -1;
-  const int lane = threadIdx.x & 63;
   const int leader = __ffsll((long long)m) - 1;
+  // set lanes below this one (mbcnt: no per-lane mask register)
+  const int below = int(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)));
   int base = 0;
-  if (lane == leader) base = atomicAdd(counter, __popcll(m));
-  base = __shfl(base, leader, 64);
-  return pred ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+  if (int(threadIdx.x & 63) == leader) base = atomicAdd(counter, __popcll(m));
+  base = __builtin_amdgcn_readlane(base, leader);
+  return pred ? base + below : -1;
 }
 
 // block-wide sum of a double (blockDim.x a multiple of 64, at most 1024)

@@ -226,6 +226,7 @@ struct SpreadArgs {
   long long ovf_base;      // record index of the overflow list
   int T[3];
   int nt[3];
+  int rel;                 // 1: N[a] >= T[a] + p - 1 on every axis (tile-relative offsets)
   float* rho;
 };
 
@@ -254,6 +255,32 @@ __device__ __forceinline__ void axis_locs(int b, int t0, int T, int N, int& w0, 
     const int m = (N >= P) ? wrap1(b - lo + j, N) : wrapn(b - lo + j, N);
     const int l = m - t0;
     const uint32_t byte = (l >= 0 && l < T) ? uint32_t(l) : 0xffu;
+    if (j < 4) p0 |= byte << (8 * j); else p1 |= byte << (8 * (j - 4));
+  }
+  w0 = int(p0);
+  w1 = int(p1);
+}
+
+// Tile-relative position of an atom's first stencil point along one axis, wrapped
+// into [-(P-1), N-(P-1)): stencil point j lies in the tile [t0, t0+T) iff
+// 0 <= d + j < T.  Exact when N >= T + P - 1 (no other periodic image of the
+// stencil reaches the tile); the stencil reaches the tile iff d < T.
+template <int P>
+__device__ __forceinline__ int axis_rel(int b, int t0, int N) {
+  int d = b - (P - 1) / 2 - t0;
+  d += (d < -(P - 1)) ? N : 0;
+  d -= (d >= N - (P - 1)) ? N : 0;
+  return d;
+}
+
+// axis_locs from the tile-relative position d (same packed bytes)
+template <int P>
+__device__ __forceinline__ void rel_locs(int d, int T, int& w0, int& w1) {
+  uint32_t p0 = 0, p1 = 0;
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int l = d + j;
+    const uint32_t byte = (uint32_t(l) < uint32_t(T)) ? uint32_t(l) : 0xffu;
     if (j < 4) p0 |= byte << (8 * j); else p1 |= byte << (8 * (j - 4));
   }
   w0 = int(p0);
@@ -427,7 +454,12 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
     //    tile-local coordinates and coefficients, and one task per stencil x-plane
     //    that lies in the tile
     bool hit = false;
-    if (r0 + tid < total) {
+    if (r0 + tid < total && a.rel) {
+      const int pk = __float_as_int(h.w);
+      hit = axis_rel<P>(pk & 1023, t0[0], a.N[0]) < T[0] &&
+            axis_rel<P>((pk >> 10) & 1023, t0[1], a.N[1]) < T[1] &&
+            axis_rel<P>((pk >> 20) & 1023, t0[2], a.N[2]) < T[2];
+    } else if (r0 + tid < total) {
       int lw[3][2];
       const int pk = __float_as_int(h.w);
       const int b[3] = {pk & 1023, (pk >> 10) & 1023, (pk >> 20) & 1023};
@@ -454,9 +486,15 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
           int pk = __float_as_int(h.w);
           asm volatile("" : "+v"(pk));   // opaque here, so that this is not hoisted out of the loop
           const int b[3] = {pk & 1023, (pk >> 10) & 1023, (pk >> 20) & 1023};
+          if (a.rel) {
 #pragma unroll
-          for (int ax = 0; ax < 3; ++ax)
-            axis_locs<P>(b[ax], t0[ax], T[ax], a.N[ax], lw[ax][0], lw[ax][1]);
+            for (int ax = 0; ax < 3; ++ax)
+              rel_locs<P>(axis_rel<P>(b[ax], t0[ax], a.N[ax]), T[ax], lw[ax][0], lw[ax][1]);
+          } else {
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax)
+              axis_locs<P>(b[ax], t0[ax], T[ax], a.N[ax], lw[ax][0], lw[ax][1]);
+          }
         }
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
@@ -575,11 +613,21 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
   // 3. write the tile back (plain stores; every point is owned by this tile)
   const float inv_scale = 1.0f / scale;
   const int tvol = T[0] * T[1] * T[2];
+  // tile extents are uniform: the multiply-high divisors are made once
+  const uint32_t tz = uint32_t(__builtin_amdgcn_readfirstlane(T[2]));
+  const uint32_t ty = uint32_t(__builtin_amdgcn_readfirstlane(T[1]));
+  const FastDiv dz{tz, tz <= 1 ? 0u : uint32_t(__builtin_amdgcn_readfirstlane(int(0xffffffffu / tz + 1u)))};
+  const FastDiv dy{ty, ty <= 1 ? 0u : uint32_t(__builtin_amdgcn_readfirstlane(int(0xffffffffu / ty + 1u)))};
+#pragma unroll 1
   for (int e = tid; e < tvol; e += 256) {
-    const int lz = e % T[2], r = e / T[2];
-    const int ly = r % T[1], lx = r / T[1];
+    const int r = int(fdiv(uint32_t(e), dz)), lz = e - r * T[2];
+    const int lx = int(fdiv(uint32_t(r), dy)), ly = r - lx * T[1];
+    // the 64-bit sum as hi * 2^32 + lo in double precision (exact below 2^53),
+    // then rounded once to float
+    const long long v = (long long)s_tile[r * TZP + lz];
+    const double vd = fma(double(int(v >> 32)), 4294967296.0, double(uint32_t(v)));
     a.rho[(size_t(t0[0] + lx) * a.N[1] + (t0[1] + ly)) * a.N[2] + t0[2] + lz] =
-        __ll2float_rn((long long)s_tile[r * TZP + lz]) * inv_scale;
+        float(vd) * inv_scale;
   }
 }
 
@@ -666,6 +714,9 @@ SpreadArgs make_spread_args(const DevPlan& d, int set, bool tangent) {
   a.ch = d.spread_ch[tangent ? 1 : 0];
   a.nbr_max = d.nbr_max;
   a.tile_words = d.T[0] * d.T[1] * (d.T[2] + 1);
+  a.rel = 1;
+  for (int k = 0; k < 3; ++k)
+    if (d.N[k] < d.T[k] + d.p - 1) a.rel = 0;
   return a;
 }
 
