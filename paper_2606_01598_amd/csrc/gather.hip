@@ -188,14 +188,14 @@ __device__ __forceinline__ RecRegs<HVP> load_rec(const float* rec, size_t ri) {
   return o;
 }
 
-template <int P, bool HVP>
+template <int P, bool HVP, bool DUAL = false>
 __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   extern __shared__ float sm[];
   __shared__ float4 s_h[256];
   __shared__ float4 s_qm[256];              // q, mu
   __shared__ float4 s_v1[HVP ? 256 : 1];    // v_q, v_r
   __shared__ float4 s_v2[HVP ? 256 : 1];    // v_mu
-  __shared__ int s_atom[256];
+  __shared__ int s_atom[HVP ? 1 : 256];      // forward (the HVP queue has it in s_v2.w)
   __shared__ int s_n;
   __shared__ float s_coef[4 * P * P];       // pieces of N_P and their derivatives
   constexpr int lo = (P - 1) / 2;
@@ -302,7 +302,6 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
         s_qm[k] = r.r1;
         s_v1[k] = r.r2;
         s_v2[k] = r.r3;
-        s_atom[k] = __float_as_int(r.r3.w);
       } else {
         s_qm[k] = r.qm;
         s_atom[k] = r.atom;
@@ -313,9 +312,12 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
     for (int b0 = 0; b0 < nq; b0 += 4 * APW) {
       const int slot = b0 + wave * APW + gslot;
       const bool active = (gslot < APW) && (slot < nq);
+      // a wavefront with no atom in this pass skips it (its lanes would only sum zeros)
+      if (__ballot(active) == 0ull) continue;
       if (!HVP) {
-        float S000 = 0, S100 = 0, S010 = 0, S001 = 0, S200 = 0, S020 = 0, S002 = 0, S110 = 0,
-              S101 = 0, S011 = 0;
+        // per-lane partial outputs (linear in the phi sums), summed over the atom's
+        // lanes: dE/dq, the pre-J dipole gradient G, the pre-J position gradient
+        float oq = 0, og[3] = {0, 0, 0}, op[3] = {0, 0, 0};
         if (active) {
           const float4 h = s_h[slot];
           const int pk = __float_as_int(h.w);
@@ -347,132 +349,117 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
             Y11 = fmaf(wy[1], z1, Y11);
             Y20 = fmaf(wy[2], z0, Y20);
           }
-          S000 = wx[0] * Y00; S001 = wx[0] * Y01; S002 = wx[0] * Y02;
-          S010 = wx[0] * Y10; S011 = wx[0] * Y11; S020 = wx[0] * Y20;
-          S100 = wx[1] * Y00; S101 = wx[1] * Y01; S110 = wx[1] * Y10;
-          S200 = wx[2] * Y00;
+          const float S000 = wx[0] * Y00, S001 = wx[0] * Y01, S002 = wx[0] * Y02;
+          const float S010 = wx[0] * Y10, S011 = wx[0] * Y11, S020 = wx[0] * Y20;
+          const float S100 = wx[1] * Y00, S101 = wx[1] * Y01, S110 = wx[1] * Y10;
+          const float S200 = wx[2] * Y00;
+          const float4 qmv = s_qm[slot];
+          const float q = qmv.x;
+          const float3 d = jmul(J, make_float3(qmv.y, qmv.z, qmv.w));
+          oq = S000;
+          og[0] = S100; og[1] = S010; og[2] = S001;
+          op[0] = q * S100 + S200 * d.x + S110 * d.y + S101 * d.z;
+          op[1] = q * S010 + S110 * d.x + S020 * d.y + S011 * d.z;
+          op[2] = q * S001 + S101 * d.x + S011 * d.y + S002 * d.z;
         }
-        S000 = group_sum<P>(S000, ix); S100 = group_sum<P>(S100, ix);
-        S010 = group_sum<P>(S010, ix); S001 = group_sum<P>(S001, ix);
-        S200 = group_sum<P>(S200, ix); S020 = group_sum<P>(S020, ix);
-        S002 = group_sum<P>(S002, ix); S110 = group_sum<P>(S110, ix);
-        S101 = group_sum<P>(S101, ix); S011 = group_sum<P>(S011, ix);
+        oq = group_sum<P>(oq, ix);
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+          og[x] = group_sum<P>(og[x], ix);
+          op[x] = group_sum<P>(op[x], ix);
+        }
         if (active && ix == 0) {
           const int i = s_atom[slot];
           const float4 qmv = s_qm[slot];
           const float q = qmv.x;
           const float3 mu = make_float3(qmv.y, qmv.z, qmv.w);
-          const float3 d = jmul(J, mu);
-          const float3 G = make_float3(S100, S010, S001);
-          const float3 Hd = make_float3(S200 * d.x + S110 * d.y + S101 * d.z,
-                                        S110 * d.x + S020 * d.y + S011 * d.z,
-                                        S101 * d.x + S011 * d.y + S002 * d.z);
-          if (a.o_q) a.o_q[i] = pf * (S000 * iv - cq * q);
+          if (a.o_q) a.o_q[i] = pf * (oq * iv - cq * q);
           if (a.o_mu) {
-            const float3 g = jtmul(J, G);
+            const float3 g = jtmul(J, make_float3(og[0], og[1], og[2]));
             st3(a.o_mu, i, make_float3(pf * (g.x * iv - cm * mu.x), pf * (g.y * iv - cm * mu.y),
                                        pf * (g.z * iv - cm * mu.z)));
           }
           if (a.o_pos) {
-            const float3 g = jtmul(J, make_float3(q * G.x + Hd.x, q * G.y + Hd.y, q * G.z + Hd.z));
+            const float3 g = jtmul(J, make_float3(op[0], op[1], op[2]));
             st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
           }
         }
       } else {
-        // phi sums S_abc (1 <= a+b+c <= 3) and psi sums Q_abc (a+b+c <= 2)
+        // DUAL: the forward outputs too (a compile-time switch: the two epilogues
+        // merged under a run-time flag need far more registers)
+        constexpr bool dual = DUAL;
+        // per-lane partial outputs, linear in the phi sums S_abc (a+b+c <= 3) and
+        // the psi sums Q_abc (a+b+c <= 2) of the lane's x-plane, summed over the
+        // atom's lanes: the pre-J Hessian-vector products (q, mu, r) and, with the
+        // forward outputs, dE/dq and the pre-J dipole and position gradients
+        float oq = 0, om[3] = {0, 0, 0}, op[3] = {0, 0, 0};
+        float fq = 0, fm[3] = {0, 0, 0}, fp[3] = {0, 0, 0};
         float S[4][4][4];
         float Q[3][3][3];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int z = 0; z < 4; ++z) S[x][y][z] = 0.0f;
-#pragma unroll
-        for (int x = 0; x < 3; ++x)
-#pragma unroll
-          for (int y = 0; y < 3; ++y)
-#pragma unroll
-            for (int z = 0; z < 3; ++z) Q[x][y][z] = 0.0f;
         if (active) {
-          const float4 h = s_h[slot];
-          const int pk = __float_as_int(h.w);
-          const int lx = (pk & 1023) - t0[0] + ix;
-          const int yb = ((pk >> 10) & 1023) - t0[1], zb = ((pk >> 20) & 1023) - t0[2];
-          // y weights are made per row (fewer live registers), z weights once
-          float wz[4][P], wx[4];
-          spline_weights<P, 3>(h.z, wz);
-          weight_at_lds<P, 3>(s_coef, ix, h.x, wx);
-          const float* pphi = sm + (lx * E[1] + yb) * E[2] + zb;
-          const float* ppsi = pphi + EV;
-          float Ys[4][4], Yq[3][3];
+          {
+            const float4 h = s_h[slot];
+            const int pk = __float_as_int(h.w);
+            const int lx = (pk & 1023) - t0[0] + ix;
+            const int yb = ((pk >> 10) & 1023) - t0[1], zb = ((pk >> 20) & 1023) - t0[2];
+            // y weights are made per row (fewer live registers), z weights once
+            float wz[4][P], wx[4];
+            spline_weights<P, 3>(h.z, wz);
+            weight_at_lds<P, 3>(s_coef, ix, h.x, wx);
+            const float* pphi = sm + (lx * E[1] + yb) * E[2] + zb;
+            const float* ppsi = pphi + EV;
+            float Ys[4][4], Yq[3][3];
 #pragma unroll
-          for (int y = 0; y < 4; ++y)
+            for (int y = 0; y < 4; ++y)
 #pragma unroll
-            for (int z = 0; z < 4; ++z) Ys[y][z] = 0.0f;
+              for (int z = 0; z < 4; ++z) Ys[y][z] = 0.0f;
 #pragma unroll
-          for (int y = 0; y < 3; ++y)
+            for (int y = 0; y < 3; ++y)
 #pragma unroll
-            for (int z = 0; z < 3; ++z) Yq[y][z] = 0.0f;
+              for (int z = 0; z < 3; ++z) Yq[y][z] = 0.0f;
 #pragma unroll
-          for (int iy = 0; iy < P; ++iy) {
-            float zs[4] = {0, 0, 0, 0}, zq[3] = {0, 0, 0};
+            for (int iy = 0; iy < P; ++iy) {
+              float zs[4] = {0, 0, 0, 0}, zq[3] = {0, 0, 0};
 #pragma unroll
-            for (int iz = 0; iz < P; ++iz) {
-              const float v = pphi[iy * E[2] + iz], u = ppsi[iy * E[2] + iz];
+              for (int iz = 0; iz < P; ++iz) {
+                const float v = pphi[iy * E[2] + iz], u = ppsi[iy * E[2] + iz];
 #pragma unroll
-              for (int k = 0; k < 4; ++k) zs[k] = fmaf(v, wz[k][iz], zs[k]);
+                for (int k = 0; k < 4; ++k) zs[k] = fmaf(v, wz[k][iz], zs[k]);
 #pragma unroll
-              for (int k = 0; k < 3; ++k) zq[k] = fmaf(u, wz[k][iz], zq[k]);
+                for (int k = 0; k < 3; ++k) zq[k] = fmaf(u, wz[k][iz], zq[k]);
+              }
+              float wy[4];
+              spline_weight_at<P, 3>(iy, h.y, wy);
+#pragma unroll
+              for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int k = 0; k + b < 4; ++k) Ys[b][k] = fmaf(wy[b], zs[k], Ys[b][k]);
+#pragma unroll
+              for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int k = 0; k + b < 3; ++k) Yq[b][k] = fmaf(wy[b], zq[k], Yq[b][k]);
             }
-            float wy[4];
-            spline_weight_at<P, 3>(iy, h.y, wy);
 #pragma unroll
-            for (int b = 0; b < 4; ++b)
+            for (int x = 0; x < 4; ++x)
 #pragma unroll
-              for (int k = 0; k + b < 4; ++k) Ys[b][k] = fmaf(wy[b], zs[k], Ys[b][k]);
+              for (int b = 0; b + x < 4; ++b)
 #pragma unroll
-            for (int b = 0; b < 3; ++b)
+                for (int k = 0; k + b + x < 4; ++k) S[x][b][k] = wx[x] * Ys[b][k];
 #pragma unroll
-              for (int k = 0; k + b < 3; ++k) Yq[b][k] = fmaf(wy[b], zq[k], Yq[b][k]);
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+              for (int b = 0; b + x < 3; ++b)
+#pragma unroll
+                for (int k = 0; k + b + x < 3; ++k) Q[x][b][k] = wx[x] * Yq[b][k];
           }
-#pragma unroll
-          for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int b = 0; b + x < 4; ++b)
-#pragma unroll
-              for (int k = 0; k + b + x < 4; ++k) S[x][b][k] = wx[x] * Ys[b][k];
-#pragma unroll
-          for (int x = 0; x < 3; ++x)
-#pragma unroll
-            for (int b = 0; b + x < 3; ++b)
-#pragma unroll
-              for (int k = 0; k + b + x < 3; ++k) Q[x][b][k] = wx[x] * Yq[b][k];
         }
-        const bool dual = a.f_q || a.f_mu || a.f_pos;
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int b = 0; b + x < 4; ++b)
-#pragma unroll
-            for (int k = 0; k + b + x < 4; ++k)
-              if (x + b + k >= 1 || dual) S[x][b][k] = group_sum<P>(S[x][b][k], ix);
-#pragma unroll
-        for (int x = 0; x < 3; ++x)
-#pragma unroll
-          for (int b = 0; b + x < 3; ++b)
-#pragma unroll
-            for (int k = 0; k + b + x < 3; ++k) Q[x][b][k] = group_sum<P>(Q[x][b][k], ix);
-        if (active && ix == 0) {
-          const int i = s_atom[slot];
+        if (active) {
           const float4 qm = s_qm[slot], e1 = s_v1[slot], e2 = s_v2[slot];
           const float q = qm.x, vq = e1.x;
-          const float3 mu = make_float3(qm.y, qm.z, qm.w);
           const float3 vr = make_float3(e1.y, e1.z, e1.w);
-          const float3 vm = make_float3(e2.x, e2.y, e2.z);
-          const float3 d3 = jmul(J, mu);
+          const float3 d3 = jmul(J, make_float3(qm.y, qm.z, qm.w));
           const float3 v3 = jmul(J, vr);
-          const float3 w3 = jmul(J, make_float3(vm.x + q * vr.x, vm.y + q * vr.y, vm.z + q * vr.z));
+          const float3 w3 = jmul(J, make_float3(e2.x + q * vr.x, e2.y + q * vr.y, e2.z + q * vr.z));
           const float d[3] = {d3.x, d3.y, d3.z}, v[3] = {v3.x, v3.y, v3.z};
           const float w[3] = {w3.x, w3.y, w3.z};
           float S1[3], P1[3], S2[3][3], P2[3][3];
@@ -500,43 +487,62 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
                 const int e2i = (x == 2) + (y == 2) + (z == 2);
                 T3[z] = fmaf(d[x] * v[y], S[e0][e1i][e2i], T3[z]);
               }
-          const float P0 = Q[0][0][0];
-          if (a.o_q) {
-            const float sq = P0 + S1[0] * v[0] + S1[1] * v[1] + S1[2] * v[2];
-            a.o_q[i] = pf * (sq * iv - cq * vq);
-          }
-          if (a.o_mu) {
-            float u[3];
+          oq = Q[0][0][0] + S1[0] * v[0] + S1[1] * v[1] + S1[2] * v[2];
 #pragma unroll
-            for (int x = 0; x < 3; ++x)
-              u[x] = P1[x] + S2[x][0] * v[0] + S2[x][1] * v[1] + S2[x][2] * v[2];
-            const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
+          for (int x = 0; x < 3; ++x) {
+            om[x] = P1[x] + S2[x][0] * v[0] + S2[x][1] * v[1] + S2[x][2] * v[2];
+            op[x] = q * P1[x] + P2[x][0] * d[0] + P2[x][1] * d[1] + P2[x][2] * d[2] +
+                    vq * S1[x] + S2[x][0] * w[0] + S2[x][1] * w[1] + S2[x][2] * w[2] + T3[x];
+          }
+          if (dual) {
+            fq = S[0][0][0];
+#pragma unroll
+            for (int x = 0; x < 3; ++x) {
+              fm[x] = S1[x];
+              fp[x] = q * S1[x] + S2[x][0] * d[0] + S2[x][1] * d[1] + S2[x][2] * d[2];
+            }
+          }
+        }
+        oq = group_sum<P>(oq, ix);
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+          om[x] = group_sum<P>(om[x], ix);
+          op[x] = group_sum<P>(op[x], ix);
+        }
+        if (dual) {
+          fq = group_sum<P>(fq, ix);
+#pragma unroll
+          for (int x = 0; x < 3; ++x) {
+            fm[x] = group_sum<P>(fm[x], ix);
+            fp[x] = group_sum<P>(fp[x], ix);
+          }
+        }
+        if (active && ix == 0) {
+          const float4 qm = s_qm[slot], e1 = s_v1[slot], e2 = s_v2[slot];
+          const int i = __float_as_int(e2.w);
+          const float q = qm.x, vq = e1.x;
+          const float3 mu = make_float3(qm.y, qm.z, qm.w);
+          const float3 vm = make_float3(e2.x, e2.y, e2.z);
+          if (a.o_q) a.o_q[i] = pf * (oq * iv - cq * vq);
+          if (a.o_mu) {
+            const float3 g = jtmul(J, make_float3(om[0], om[1], om[2]));
             st3(a.o_mu, i, make_float3(pf * (g.x * iv - cm * vm.x), pf * (g.y * iv - cm * vm.y),
                                        pf * (g.z * iv - cm * vm.z)));
           }
           if (a.o_pos) {
-            float u[3];
-#pragma unroll
-            for (int x = 0; x < 3; ++x)
-              u[x] = q * P1[x] + P2[x][0] * d[0] + P2[x][1] * d[1] + P2[x][2] * d[2] +
-                     vq * S1[x] + S2[x][0] * w[0] + S2[x][1] * w[1] + S2[x][2] * w[2] + T3[x];
-            const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
+            const float3 g = jtmul(J, make_float3(op[0], op[1], op[2]));
             st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
           }
           if (dual) {
-            // gradient of E^lr: S000, the first and second derivative sums of phi
-            if (a.f_q) a.f_q[i] = pf * (S[0][0][0] * iv - cq * q);
+            // gradient of E^lr from the same phi sums
+            if (a.f_q) a.f_q[i] = pf * (fq * iv - cq * q);
             if (a.f_mu) {
-              const float3 g = jtmul(J, make_float3(S1[0], S1[1], S1[2]));
+              const float3 g = jtmul(J, make_float3(fm[0], fm[1], fm[2]));
               st3(a.f_mu, i, make_float3(pf * (g.x * iv - cm * mu.x), pf * (g.y * iv - cm * mu.y),
                                          pf * (g.z * iv - cm * mu.z)));
             }
             if (a.f_pos) {
-              float u[3];
-#pragma unroll
-              for (int x = 0; x < 3; ++x)
-                u[x] = q * S1[x] + S2[x][0] * d[0] + S2[x][1] * d[1] + S2[x][2] * d[2];
-              const float3 g = jtmul(J, make_float3(u[0], u[1], u[2]));
+              const float3 g = jtmul(J, make_float3(fp[0], fp[1], fp[2]));
               st3(a.f_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
             }
           }
@@ -586,9 +592,9 @@ __device__ __forceinline__ void gather_body(const GArgs& a, const int tile) {
   gather_tile<P, false>(a, tile);
 }
 
-template <int P>
+template <int P, bool DUAL = false>
 __device__ __forceinline__ void gather_hvp_body(const GArgs& a, const int tile) {
-  gather_tile<P, true>(a, tile);
+  gather_tile<P, true, DUAL>(a, tile);
 }
 
 template <int P>
@@ -596,9 +602,9 @@ __global__ void __launch_bounds__(256) k_gather(GArgs a) {
   gather_body<P>(a, blockIdx.x);
 }
 
-template <int P>
+template <int P, bool DUAL>
 __global__ void __launch_bounds__(256) k_gather_hvp(GArgs a) {
-  gather_hvp_body<P>(a, blockIdx.x);
+  gather_hvp_body<P, DUAL>(a, blockIdx.x);
 }
 
 // Batched gathers: work item (box, tile), per-box argument templates completed
@@ -629,11 +635,12 @@ __global__ void __launch_bounds__(256) k_gather_batch(const GArgs* args, const i
 
 template <bool HVP>
 hipError_t gather_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const GArgs& a,
-                           const LaunchEvents* ev) {
-#define PME_G(P)                                                    \
-  case P:                                                           \
-    if (HVP) launch_k(ev, k_gather_hvp<P>, g, dim3(256), sh, s, a); \
-    else launch_k(ev, k_gather<P>, g, dim3(256), sh, s, a);         \
+                           const LaunchEvents* ev, bool dual = false) {
+#define PME_G(P)                                                              \
+  case P:                                                                     \
+    if (HVP && dual) launch_k(ev, k_gather_hvp<P, true>, g, dim3(256), sh, s, a); \
+    else if (HVP) launch_k(ev, k_gather_hvp<P, false>, g, dim3(256), sh, s, a);   \
+    else launch_k(ev, k_gather<P>, g, dim3(256), sh, s, a);                   \
     break;
   switch (p) {
     PME_G(1) PME_G(2) PME_G(3) PME_G(4) PME_G(5) PME_G(6) PME_G(7)
@@ -683,7 +690,9 @@ hipError_t gather_batch_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const 
 hipError_t enable_gather_lds() {
   const void* fns[] = {
 #define PME_G(P)                                                                             \
-  reinterpret_cast<const void*>(k_gather<P>), reinterpret_cast<const void*>(k_gather_hvp<P>), \
+  reinterpret_cast<const void*>(k_gather<P>),                                                \
+      reinterpret_cast<const void*>(k_gather_hvp<P, false>),                                \
+      reinterpret_cast<const void*>(k_gather_hvp<P, true>),                                 \
       reinterpret_cast<const void*>(k_gather_batch<P, false>),                               \
       reinterpret_cast<const void*>(k_gather_batch<P, true>),
       PME_G(1) PME_G(2) PME_G(3) PME_G(4) PME_G(5) PME_G(6) PME_G(7)
@@ -769,8 +778,9 @@ hipError_t launch_gather_hvp(const DevPlan& d, hipStream_t s, int set, int n, co
     a.energy = fwd->energy; a.epart = d.epart; a.n_epart = fftx_blocks(d);
     a.spart = d.spart; a.n_spart = fwd->n_spart;
   }
+  const bool dual = a.f_pos || a.f_q || a.f_mu;
   return gather_dispatch<true>(d.p, dim3(d.nt[0] * d.nt[1] * d.nt[2]), region_bytes(d, 2), s, a,
-                               ev);
+                               ev, dual);
 }
 
 }  // namespace pme
