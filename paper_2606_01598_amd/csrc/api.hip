@@ -213,8 +213,10 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
       region *= d.T[a] + p - 1;
     }
     const long tpad = long(d.T[0]) * d.T[1] * (d.T[2] + 1);
+    // two field regions and their row and z tables
+    const long rows = long(d.T[0] + p - 1) * (d.T[1] + p - 1) + (d.T[2] + p - 1);
     if (range <= pme::kMaxBinRange && own <= 256 && tpad <= pme::kTileLds &&
-        region * 4 <= pme::kGatherLds &&
+        region * 4 + rows * 4 <= pme::kGatherLds &&
         long(pme::spread_lds_bytes(int(tpad), int(range), 64, p, 2)) <= pme::kBigLds)
       break;
     int big = 0;

@@ -202,8 +202,10 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   constexpr int APW = 64 / P;
   const int tid = threadIdx.x;
   if (tid == 0) s_n = 0;
-  for (int k = tid; k < 4 * P * P; k += blockDim.x) s_coef[k] = c_spline.coef[spline_offset(P) + k];
-  __syncthreads();
+  // the spline table is loaded now and stored in LDS after the field region, so that
+  // no barrier waits for it
+  static_assert(4 * P * P <= 256, "one coefficient per thread");
+  const float coef = tid < 4 * P * P ? c_spline.coef[spline_offset(P) + tid] : 0.0f;
   const Cell c = cell_from_box(a.box);
   if (tile == 0 && a.energy) finalize_energy(a, c);
   int t0[3], T[3], E[3];
@@ -246,9 +248,26 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   int cnt = a.count[own_bin(ec / cap)];
   const int novf = *a.ovf_count;
   const int EV = E[0] * E[1] * E[2];
+  // global offsets of the region's rows (ex, ey) and wrapped z coordinates, made
+  // once, after the field region in LDS: a region element then costs two LDS reads
+  const int nrow = E[0] * E[1];
+  int* s_row = reinterpret_cast<int*>(sm + (HVP ? 2 : 1) * EV);
+  int* s_zo = s_row + nrow;
   {
-    const FastDiv d2 = make_fastdiv(E[2]), d1 = make_fastdiv(E[1]);
     const bool small = (a.N[0] < P) || (a.N[1] < P) || (a.N[2] < P);
+    auto wrap = [&](int m, int N) {
+      return small ? wrapn(m, N) : ((m < 0) ? m + N : ((m >= N) ? m - N : m));
+    };
+    const FastDiv d1 = make_fastdiv(E[1]);
+    for (int r = tid; r < nrow; r += blockDim.x) {
+      const int ex = int(fdiv(uint32_t(r), d1)), ey = r - ex * E[1];
+      s_row[r] = (wrap(t0[0] - lo + ex, a.N[0]) * a.N[1] + wrap(t0[1] - lo + ey, a.N[1])) * a.N[2];
+    }
+    for (int z = tid; z < E[2]; z += blockDim.x) s_zo[z] = wrap(t0[2] - lo + z, a.N[2]);
+  }
+  __syncthreads();
+  {
+    const FastDiv d2 = make_fastdiv(E[2]);
     constexpr int U = 16;   // loads kept in flight per thread
     for (int e0 = tid; e0 < EV; e0 += U * blockDim.x) {
       float vphi[U], vpsi[U];
@@ -256,17 +275,8 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
       for (int u = 0; u < U; ++u) {
         const int e = e0 + u * blockDim.x;
         const int ec = min(e, EV - 1);
-        const int r = int(fdiv(uint32_t(ec), d2)), ez = ec - r * E[2];
-        const int ex = int(fdiv(uint32_t(r), d1)), ey = r - ex * E[1];
-        int mx = t0[0] - lo + ex, my = t0[1] - lo + ey, mz = t0[2] - lo + ez;
-        if (small) {
-          mx = wrapn(mx, a.N[0]); my = wrapn(my, a.N[1]); mz = wrapn(mz, a.N[2]);
-        } else {
-          mx = (mx < 0) ? mx + a.N[0] : ((mx >= a.N[0]) ? mx - a.N[0] : mx);
-          my = (my < 0) ? my + a.N[1] : ((my >= a.N[1]) ? my - a.N[1] : my);
-          mz = (mz < 0) ? mz + a.N[2] : ((mz >= a.N[2]) ? mz - a.N[2] : mz);
-        }
-        const size_t g = (size_t(mx) * a.N[1] + my) * a.N[2] + mz;
+        const int r = int(fdiv(uint32_t(ec), d2));
+        const uint32_t g = uint32_t(s_row[r] + s_zo[ec - r * E[2]]);
         vphi[u] = a.phi[g];
         if (HVP) vpsi[u] = a.psi[g];
       }
@@ -280,6 +290,7 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
       }
     }
   }
+  if (tid < 4 * P * P) s_coef[tid] = coef;
   // cell and prefactor constants are uniform: kept in scalar registers
   float J[3][3];
   jacobian(c, a.N, J);
@@ -665,8 +676,11 @@ GArgs base_args(const DevPlan& d, int set, int n, const float* pos, const float*
   return a;
 }
 
+// the field region(s) over a tile plus its stencil halo, then the row offsets and
+// wrapped z coordinates of the region
 size_t region_bytes(const DevPlan& d, int fields) {
-  return sizeof(float) * size_t(fields) * (d.T[0] + d.p - 1) * (d.T[1] + d.p - 1) * (d.T[2] + d.p - 1);
+  const size_t e0 = d.T[0] + d.p - 1, e1 = d.T[1] + d.p - 1, e2 = d.T[2] + d.p - 1;
+  return sizeof(float) * size_t(fields) * e0 * e1 * e2 + sizeof(int) * (e0 * e1 + e2);
 }
 
 template <bool HVP>
