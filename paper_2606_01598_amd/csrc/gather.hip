@@ -191,11 +191,13 @@ __device__ __forceinline__ RecRegs<HVP> load_rec(const float* rec, size_t ri) {
 template <int P, bool HVP, bool DUAL = false>
 __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   extern __shared__ float sm[];
-  __shared__ float4 s_h[256];
-  __shared__ float4 s_qm[256];              // q, mu
-  __shared__ float4 s_v1[HVP ? 256 : 1];    // v_q, v_r
-  __shared__ float4 s_v2[HVP ? 256 : 1];    // v_mu
-  __shared__ int s_atom[HVP ? 1 : 256];      // forward (the HVP queue has it in s_v2.w)
+  // the queue holds kGatherQueue atoms; a round's compacted records beyond that are
+  // processed in further chunks, reloaded from the records
+  __shared__ float4 s_h[kGatherQueue];
+  __shared__ float4 s_qm[kGatherQueue];              // q, mu
+  __shared__ float4 s_v1[HVP ? kGatherQueue : 1];    // v_q, v_r
+  __shared__ float4 s_v2[HVP ? kGatherQueue : 1];    // v_mu, atom
+  __shared__ int s_atom[HVP ? 1 : kGatherQueue];     // forward
   __shared__ int s_n;
   __shared__ float s_coef[4 * P * P];       // pieces of N_P and their derivatives
   constexpr int lo = (P - 1) / 2;
@@ -305,19 +307,22 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   const int lane = tid & 63, wave = tid >> 6;
   const int gslot = lane / P, ix = lane - gslot * P;
 
+  auto put = [&](int k, const RecRegs<HVP>& r) {
+    s_h[k] = r.h;
+    if constexpr (HVP) {
+      s_qm[k] = r.r1;
+      s_v1[k] = r.r2;
+      s_v2[k] = r.r3;
+    } else {
+      s_qm[k] = r.qm;
+      s_atom[k] = r.atom;
+    }
+  };
+  // compacted index of a valid record (-1 otherwise); the first kGatherQueue are queued
   auto enqueue = [&](bool valid, const RecRegs<HVP>& r) {
     const int k = wave_compact(valid, &s_n);
-    if (valid) {
-      s_h[k] = r.h;
-      if constexpr (HVP) {
-        s_qm[k] = r.r1;
-        s_v1[k] = r.r2;
-        s_v2[k] = r.r3;
-      } else {
-        s_qm[k] = r.qm;
-        s_atom[k] = r.atom;
-      }
-    }
+    if (valid && k < kGatherQueue) put(k, r);
+    return k;
   };
   auto process = [&](int nq) {
     for (int b0 = 0; b0 < nq; b0 += 4 * APW) {
@@ -565,12 +570,25 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   // 2. rounds of 256 own-bin slots, then of 256 overflow records (those anchored in
   // the tile are owned); one round is compacted into the queue while the previous
   // one has been processed, so that no record registers live across the stencil work
-  enqueue(tid < nslot && ec % cap < cnt, cur);
+  // the queue of a round in chunks of kGatherQueue: chunks after the first reload
+  // their records (record index ri) from global memory
+  auto drain = [&](int k, uint32_t ri) {
+    const int nv = s_n;
+    process(min(nv, kGatherQueue));
+    for (int c0 = kGatherQueue; c0 < nv; c0 += kGatherQueue) {
+      __syncthreads();   // the queue has been read
+      if (k >= c0 && k < c0 + kGatherQueue) put(k - c0, load_rec<HVP>(a.rec, ri));
+      __syncthreads();
+      process(min(kGatherQueue, nv - c0));
+    }
+  };
+  int kq = enqueue(tid < nslot && ec % cap < cnt, cur);
+  uint32_t rq = uint32_t(own_bin(ec / cap) * cap + (ec - (ec / cap) * cap));
   __syncthreads();
   const int nrs = (nslot + 255) >> 8;
   const int nr = nrs + ((novf + 255) >> 8);
   for (int r = 0;;) {
-    process(s_n);
+    drain(kq, rq);
     if (++r >= nr) break;
     __syncthreads();   // the queue has been read
     if (tid == 0) s_n = 0;
@@ -582,10 +600,12 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
       rec = slot_rec(ec);
       cnt = a.count[own_bin(ec / cap)];
       valid = e < nslot && ec % cap < cnt;
+      rq = uint32_t(own_bin(ec / cap) * cap + (ec - (ec / cap) * cap));
     } else {
       const int o = (r - nrs) * 256 + tid;
       if (o < novf) {
-        rec = load_rec<HVP>(a.rec, size_t(a.ovf_base) + o);
+        rq = uint32_t(a.ovf_base + o);
+        rec = load_rec<HVP>(a.rec, rq);
         const int pk = __float_as_int(rec.h.w);
         const int b0 = pk & 1023, b1 = (pk >> 10) & 1023, b2 = (pk >> 20) & 1023;
         valid = b0 >= t0[0] && b0 < t0[0] + T[0] && b1 >= t0[1] && b1 < t0[1] + T[1] &&
@@ -593,7 +613,7 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
       }
     }
     __syncthreads();   // s_n is cleared
-    enqueue(valid, rec);
+    kq = enqueue(valid, rec);
     __syncthreads();
   }
 }
@@ -609,12 +629,14 @@ __device__ __forceinline__ void gather_hvp_body(const GArgs& a, const int tile) 
 }
 
 template <int P>
-__global__ void __launch_bounds__(256) k_gather(GArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 6 ? 4 : 5)))
+k_gather(GArgs a) {
   gather_body<P>(a, blockIdx.x);
 }
 
 template <int P, bool DUAL>
-__global__ void __launch_bounds__(256) k_gather_hvp(GArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 3 : 4)))
+k_gather_hvp(GArgs a) {
   gather_hvp_body<P, DUAL>(a, blockIdx.x);
 }
 

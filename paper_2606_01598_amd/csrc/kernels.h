@@ -13,6 +13,7 @@ constexpr int kMaxStages = 16;
 constexpr int kMaxBinRange = 2048;   // bins a spread tile may scan (LDS count array)
 constexpr int kTileLds = 8192;       // max padded spread-tile points: T_x T_y (T_z + 1)
 constexpr int kBigLds = 150 * 1024;  // dynamic LDS limit of the spread kernels
+constexpr int kGatherQueue = 128;                      // atoms a gather queues at once
 constexpr int kGatherStaticLds = 20 * 1024;            // bound on the gathers' static LDS
 constexpr int kGatherLds = 160 * 1024 - kGatherStaticLds;  // their dynamic LDS limit
 

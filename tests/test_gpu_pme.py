@@ -261,6 +261,46 @@ def test_overflowing_bins_still_exact():
     _check_forward(f, (16, 16, 16), 6, 0.3, label="crowded")
 
 
+@pytest.mark.parametrize("lo,hi,max_atoms", [((0.2, 0.2, 0.2), (3.8, 3.8, 15.8), 10000),
+                                              ((4.0, 4.0, 4.0), (5.5, 5.5, 5.5), 300)])
+def test_crowded_tile_hvp_and_step(lo, hi, max_atoms):
+    """More atoms in one tile than a gather queues at once (128): 300 atoms in one
+    column of 4 bins (64 slots each) of a 16^3 mesh, which fill the tile's first
+    round of 256 own slots, and 300 atoms in a 1.5 A cube of a plan with 18 slots
+    per bin, most of them in the overflow list; the forward outputs, H v and the
+    concurrent pme_step against the oracle."""
+    rng = np.random.default_rng(17)
+    n = 300
+    pos = rng.uniform(lo, hi, (n, 3))
+    q = rng.normal(0, 1, n)
+    q -= q.mean()
+    f = synth.Frame(pos=pos, q=q, mu=rng.normal(0, 0.1, (n, 3)), box=np.eye(3) * 16.0)
+    mesh, p, a = (16, 16, 16), 6, 0.3
+    v = synth.random_cotangents(n, 23, scale_r=0.1)
+    vt = [torch.tensor(x, dtype=torch.float32, device=dev()) for x in v]
+    pos_t, q_t, mu_t, box = to_dev(f)
+    plan = _plan(mesh, p, a, max_atoms)
+    fo = plan.forward(pos_t, q_t, mu_t, box)
+    bo = plan.backward(pos_t, q_t, mu_t, box, *vt)
+    plan.status()
+    ref = oracle_forward(f, mesh, p, a)
+    gp, gq, gm = oracle_hvp(f, mesh, p, a, v)
+    errs = {"E_lr": rel(host(fo["energy"]).sum(), ref.energy),
+            "dE_dpos": rms_rel(host(fo["dE_dpos"]), ref.dE_dpos),
+            "g_pos": rms_rel(host(bo["g_pos"]), gp), "g_q": rms_rel(host(bo["g_q"]), gq),
+            "g_mu": rms_rel(host(bo["g_mu"]), gm)}
+    print("crowded", max_atoms, {k: f"{e:.2e}" for k, e in errs.items()}, flush=True)
+    assert errs["E_lr"] <= E_REL_TOL
+    assert max(e for k, e in errs.items() if k != "E_lr") <= RMS_REL_TOL
+    cplan = _plan(mesh, p, a, max_atoms, concurrent=True)
+    out = cplan.step(pos_t, q_t, mu_t, box, *vt)
+    cplan.status()
+    want = {**fo, **bo}
+    worst = max(float((out[k] - want[k]).abs().max() / want[k].abs().max()) for k in want)
+    print("crowded step", max_atoms, f"{worst:.2e}", flush=True)
+    assert worst <= 1e-6
+
+
 def test_config3_32k_full_parity():
     """The 32k-ion, 100^3, p = 6 workload timed by the benchmark, in the same launch
     configuration, against the oracle on every atom."""
