@@ -57,8 +57,16 @@ KERNEL_SYMBOL = {
     "bin": "k_bin<6, false>", "bin_tangent": "k_bin<6, true>",
     "spread": "k_spread<6, 1>", "spread_tangent": "k_spread<6, 2>",
     "fft_r2c": "k_slab_fwd", "fft_x": "k_fftx_fused", "fft_c2r": "k_slab_inv",
-    "gather": "k_gather<6>", "gather_hvp": "k_gather_hvp<6>",
+    "gather": "k_gather<6>", "gather_hvp": "k_gather_hvp<6, false>",
 }
+
+
+def kernel_symbol(kind: str, step: bool = False) -> str:
+    """Profiler name of a timer kind's kernel; under pme_step the Hessian-vector
+    gather is the variant that also forms the forward outputs."""
+    if kind == "gather_hvp" and step:
+        return "k_gather_hvp<6, true>"
+    return KERNEL_SYMBOL[kind]
 
 
 def alg_bytes(kind: str, n: int, m: int, step: bool = True) -> int:
@@ -245,7 +253,8 @@ def main(argv=None):
                            "pme_step (cotangent chain on a second stream)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": traffic, "kernel": KERNEL_SYMBOL[dominant], "kind": dominant,
+                     "traffic": traffic, "kernel": kernel_symbol(dominant, not args.sequential),
+                     "kind": dominant,
                      "alg_bytes_per_launch": ab, "avg_launch_us": round(dur_s * 1e6, 3),
                      "launches": launches},
         "kernels_us": kernels_us,
@@ -483,7 +492,7 @@ def traffic_summary(args) -> int:
     fetch = _counter_means(args.traffic_summary[0], "FETCH_SIZE")
     write = _counter_means(args.traffic_summary[1], "WRITE_SIZE")
     kind = args.kernel or "spread_tangent"
-    sym = KERNEL_SYMBOL[kind]
+    sym = kernel_symbol(kind, not args.sequential)
 
     def find(table, key):
         hits = [k for k in table if key in k]
@@ -548,7 +557,8 @@ def kernel_stats_summary(args) -> int:
             for ln in fh:
                 if ln.startswith("{") and '"kernels_us"' in ln:
                     d = json.loads(ln)
-                    bench_us = {KERNEL_SYMBOL[k]: v for k, v in d["kernels_us"].items()}
+                    step = "pme_step" in d["config"].get("call", "")
+                    bench_us = {kernel_symbol(k, step): v for k, v in d["kernels_us"].items()}
                     bench_val = (d["value"], d["unit"], d["roofline"]["kernel"],
                                  d["roofline"]["avg_launch_us"])
                     break
