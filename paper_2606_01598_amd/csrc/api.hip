@@ -270,8 +270,9 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
     const int nmax = d.N[0] > d.N[1] ? d.N[0] : d.N[1];
     int kt = nmax <= 64 ? 16 : (nmax <= 160 ? 24 : 4);
     // LDS of a line workgroup within 56 KB: twiddles, two line buffers and (x pass)
-    // the kt N_x table of g: 8 N + kt (16 (N + 1) + 4 N) bytes
-    const int lds_cap = (7000 - nmax) / (2 * (nmax + 1) + (nmax + 1) / 2 + 1);
+    // the kt N_x table of g and the deconvolution factors:
+    // 8 N + kt (16 (N + 1) + 4 N) + 4 (N + kt) bytes
+    const int lds_cap = (7000 - nmax - (nmax + 1) / 2) / (2 * (nmax + 1) + (nmax + 1) / 2 + 2);
     if (kt > lds_cap) kt = lds_cap;
     if (kt < 1) kt = 1;
     if (kt > d.H) kt = d.H;

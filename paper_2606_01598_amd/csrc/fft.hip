@@ -508,8 +508,30 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
   float2* X = tw + Nx;
   float2* Y = X + kt * ps;
   float* s_g = reinterpret_cast<float*>(Y + kt * ps);   // g[l Nx + kx]
+  float* s_dc = s_g + Nx * kt;                          // deconvolution: [Nx] x, [kt] z
   const int ntk = (H + kt - 1) / kt;
   const int y = blk / ntk, kz0 = (blk - y * ntk) * kt;
+  // the x and z deconvolution factors of the workgroup's points, loaded before the
+  // lines (waiting for them does not wait for the lines) and put in LDS before the
+  // g table is made
+  constexpr int DCU = 5;   // Nx + kt <= DCU blockDim (Nx <= 1024, kt <= 24)
+  float dcv[DCU];
+#pragma unroll
+  for (int k = 0; k < DCU; ++k) {
+    // unconditional loads from clamped addresses (straight-line code lets the later
+    // wait count only these loads); entries past Nx + kt are not stored
+    const int i = int(threadIdx.x) + k * int(blockDim.x);
+    const float* src = (i < Nx) ? a.dcx + i : a.dcz + min(kz0 + max(i - Nx, 0), H - 1);
+    dcv[k] = *src;
+  }
+  auto store_dc = [&]() {
+#pragma unroll
+    for (int k = 0; k < DCU; ++k) {
+      const int i = int(threadIdx.x) + k * int(blockDim.x);
+      if (i < Nx + kt) s_dc[i] = dcv[k];
+    }
+    __syncthreads();
+  };
   Twiddles<kFFTThreads> twr;
   twr.load(a.tw, Nx);
   const size_t xstride = size_t(Ny) * H;
@@ -548,7 +570,7 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
         const bool nz = ((Nz & 1) == 0) && (2 * kz == Nz);
         if (nx || nyq_y || nz)   // Hermitian partner: the non-Nyquist components change sign
           g = 0.5f * (g + gk(nx ? fx : -fx, nyq_y ? fy : -fy, nz ? fz : -fz));
-        g *= a.dcx[xx] * dcy * a.dcz[kz];
+        g *= s_dc[xx] * dcy * s_dc[Nx + l];
       }
       s_g[l * Nx + xx] = g;
     }
@@ -568,13 +590,20 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
     with_radix(x0.R, [&](auto rc) {
       constexpr int Rr = decltype(rc)::value;
       float2 v[Rr];
-      if (act) {
+      {
+        // unconditional loads from clamped addresses: the waits before the g table
+        // then count only the deconvolution loads issued before these
+        const int jc = act ? j : 0, kc = (kz < H) ? kz : H - 1;
 #pragma unroll
-        for (int r = 0; r < Rr; ++r)
-          v[r] = (kz < H) ? base[size_t(j + r * x0.NR) * xstride + kz] : make_float2(0.f, 0.f);
+        for (int r = 0; r < Rr; ++r) v[r] = base[size_t(jc + r * x0.NR) * xstride + kc];
       }
+      store_dc();
       gtable();
       if (act) {
+        if (kz >= H) {
+#pragma unroll
+          for (int r = 0; r < Rr; ++r) v[r] = make_float2(0.f, 0.f);
+        }
         Dft<Rr>::run(v, -1.0f);
         float2* out = X + l * ps;
 #pragma unroll
@@ -596,6 +625,7 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
         lv[u] = (kz < H) ? base[xx * xstride + kz] : make_float2(0.f, 0.f);
       }
     }
+    store_dc();
     gtable();
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -725,7 +755,8 @@ XArgs make_x_args(const DevPlan& d, const double* box, bool energy) {
 }
 
 size_t x_lds(const DevPlan& d) {
-  return sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1)) + sizeof(float) * d.N[0] * d.ktile;
+  return sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1)) + sizeof(float) * d.N[0] * d.ktile +
+         sizeof(float) * (d.N[0] + d.ktile);
 }
 
 SlabArgs make_slab_args(const DevPlan& d, float* out) {
