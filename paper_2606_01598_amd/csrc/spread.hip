@@ -292,16 +292,14 @@ __device__ __forceinline__ int loc_of(int w0, int w1, int j) {
   return int(int8_t((w >> (8 * (j & 3))) & 0xff));
 }
 
-// Round a float of magnitude below 2^51 to the nearest integer (ties to even) as a
-// two's-complement 64-bit word.  Adding 1.5 * 2^52 in double precision leaves the
-// rounded value in the low mantissa bits; the constant's low word is zero, so only
-// the high word needs the bias removed (3 instructions instead of the long
-// float -> int64 conversion sequence).
+// A contribution of magnitude below 2^31 as a 64-bit fixed-point word: rounded to
+// the nearest 32-bit integer, ties up (floor(v + 1/2), one conversion instruction)
+// and sign-extended.  The rounding moves a contribution by at most half a unit,
+// 2^-31 of the largest possible one, with no bias but at exact ties.
 __device__ __forceinline__ unsigned long long to_fixed(float v) {
-  const double t = double(v) + 6755399441055744.0;   // 1.5 * 2^52
-  const unsigned long long b = (unsigned long long)__double_as_longlong(t);
-  const uint32_t lo = uint32_t(b), hi = uint32_t(b >> 32) - 0x43380000u;
-  return (unsigned long long)lo | ((unsigned long long)hi << 32);
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+  return (unsigned long long)(long long)r;
 }
 
 template <int P, int DEG>
@@ -376,11 +374,11 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
     s_nr[0] = 0;
     s_ntask = 0;
   }
-  // each contribution is bounded by 8 sum_k |c_k| <= 8 cmax: scale it to <= 2^40
+  // each contribution is bounded by 8 sum_k |c_k| <= 8 cmax: scale it below 2^31
   float scale = 1.0f;
   {
     const float cm = __uint_as_float(*a.cmax);
-    if (cm > 0.0f && isfinite(cm)) scale = ldexpf(1.0f, 40 - (ilogbf(8.0f * cm) + 1));
+    if (cm > 0.0f && isfinite(cm)) scale = ldexpf(1.0f, 31 - (ilogbf(8.0f * cm) + 1));
   }
   const int TZP = T[2] + 1;                   // padded z stride; column T_z is scratch
   const int tpad = T[0] * T[1] * TZP;
