@@ -59,6 +59,9 @@ struct GArgs {
   int n_spart;
   double alpha;
   double prefactor;
+  // float constants of the outputs, made on the host: the prefactor, the self-term
+  // factors 2 alpha / sqrt(pi) and 4 alpha^3 / (3 sqrt(pi))
+  float pf, cq, cm;
   int B[3];
   int nb[3];
   int cap;
@@ -120,10 +123,11 @@ __device__ __forceinline__ float group_sum(float v, int ix) {
   return v;
 }
 
+// ceil(2^32 / d) as 0xffffffff / d + 1 (a 32-bit division; d = 1 passes through)
 __device__ __forceinline__ FastDiv make_fastdiv(int d) {
   FastDiv f;
   f.d = uint32_t(d);
-  f.m = d <= 1 ? 0u : uint32_t(((1ull << 32) + uint64_t(d) - 1) / uint64_t(d));
+  f.m = d <= 1 ? 0u : 0xffffffffu / uint32_t(d) + 1u;
   return f;
 }
 
@@ -301,9 +305,7 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) J[i][j] = uniform(J[i][j]);
   const float iv = uniform(float(1.0 / c.vol));
-  const float pf = uniform(float(a.prefactor));
-  const float cq = uniform(float(2.0 * a.alpha / sqrt(M_PI)));
-  const float cm = uniform(float(4.0 * a.alpha * a.alpha * a.alpha / (3.0 * sqrt(M_PI))));
+  const float pf = a.pf, cq = a.cq, cm = a.cm;
   const int lane = tid & 63, wave = tid >> 6;
   const int gslot = lane / P, ix = lane - gslot * P;
 
@@ -693,6 +695,9 @@ GArgs base_args(const DevPlan& d, int set, int n, const float* pos, const float*
   }
   a.phi = d.phi;
   a.alpha = d.alpha; a.prefactor = d.prefactor;
+  a.pf = float(d.prefactor);
+  a.cq = float(2.0 * d.alpha / sqrt(M_PI));
+  a.cm = float(4.0 * d.alpha * d.alpha * d.alpha / (3.0 * sqrt(M_PI)));
   a.cap = d.cap; a.count = d.count[set]; a.ovf_count = d.ovf_count[set];
   a.rec = d.rec; a.ovf_base = d.ovf_base;
   return a;
