@@ -14,6 +14,8 @@ Follows Secs. 2.3.1-2.3.5 of the paper step by step:
 9. analytic gradients of E^lr with respect to r, q and mu, and
    the Hessian-vector product of E^lr (what autograd of the
    pipeline yields, Sec. 2.3.5 and Eq. forces)
+10. the gradient of E^lr with respect to the cell at fixed Cartesian
+   inputs (the stress/virial loss of Sec. 2.4)
 
 Readings of the text (where it is silent or ambiguous):
 
@@ -334,6 +336,54 @@ def energy(pos, q, mu, box, mesh, p, alpha, gamma=1.0, prefactor=1.0) -> float:
     e -= alpha / math.sqrt(math.pi) * float(np.sum(q * q))
     e -= 2.0 * alpha ** 3 / (3.0 * math.sqrt(math.pi)) * float(np.sum(mu * mu))
     return prefactor * e
+
+
+def cell_gradient(pos, q, mu, box, mesh, p, alpha, gamma=1.0, prefactor=1.0) -> np.ndarray:
+    """d E^lr / d C at fixed Cartesian positions, charges and dipoles (3x3, laid out
+    like the box: G[a, b] = dE / dC[a, b]); what autograd of the pipeline gives for
+    the cell (Sec. 2.4, the virial/stress loss).
+
+    The self terms do not depend on C.  E_recip = (1/2V) sum_f g(f) |rho~(f)|^2
+    depends on C through
+      (i)   the volume:                     -E_recip C^-T
+      (ii)  k = 2 pi C^-1 f in G(k) (the deconvolution depends on f alone), with
+            dG/d(k^2) = -G (1/k^2 + 1/(4 alpha^2)) and d(k^2)/dC = -2 (C^-T k) k^T:
+                                            (1/V) sum_f |rho~|^2 g (1/k^2 + 1/(4 alpha^2)) (C^-T k) k^T
+      (iii) the density, whose mesh coordinates x_i = N (r_i C^-1) and x-space
+            dipoles N (mu_i C^-1) move with C; with G_i = sum phi grad_x W and
+            H_i = sum phi grad_x grad_x W over atom i's stencil and the unwrapped
+            fractional coordinates s_i = r_i C^-1:
+                                            -(1/V) [sum_i s_i (x) N (q_i G_i + H_i J mu_i)
+                                                    + (mu_i C^-1) (x) N G_i] C^-T
+    """
+    pos, q, mu = _inputs(pos, q, mu)
+    mesh = tuple(int(m) for m in mesh)
+    _, Cinv, V, recip = cell(box)
+    J = jacobian(box, mesh)
+    g = influence(box, mesh, p, alpha, gamma)
+    rho = density(pos, q, mu, box, mesh, p)
+    rk = dft3(rho, -1)
+    phi = dft3(g * rk, +1).real
+    e_recip = float(np.sum(rho * phi)) / (2.0 * V)
+    # (ii)
+    fx, fy, fz = (signed_index(N).astype(np.float64) for N in mesh)
+    kvec = (fx[:, None, None, None] * recip[0] + fy[None, :, None, None] * recip[1]
+            + fz[None, None, :, None] * recip[2])
+    k2 = np.einsum('xyzc,xyzc->xyz', kvec, kvec)
+    with np.errstate(divide='ignore', invalid='ignore'):
+        fac = g * (1.0 / k2 + 1.0 / (4.0 * alpha * alpha))
+    fac[0, 0, 0] = 0.0
+    T = np.einsum('xyz,xyzc,xyzd->cd', np.abs(rk) ** 2 * fac, kvec, kvec)
+    term2 = Cinv.T @ T / V
+    # (iii)
+    S = _stencil_sums(pos, box, mesh, p, phi, _orders(1) + _orders(2))
+    G, H = _grad_vec(S), _hess_mat(S)
+    gx = q[:, None] * G + np.einsum('nab,nb->na', H, mu @ J.T)
+    Nv = np.asarray(mesh, dtype=np.float64)
+    s = pos @ Cinv
+    term3 = -((s.T @ (gx * Nv)) + ((mu @ Cinv).T @ (G * Nv))) @ Cinv.T / V
+    term1 = -e_recip * Cinv.T
+    return prefactor * (term1 + term2 + term3)
 
 
 def hvp(pos, q, mu, box, mesh, p, alpha, v_pos=None, v_q=None, v_mu=None, gamma=1.0,
