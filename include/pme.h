@@ -127,6 +127,27 @@ int pme_forward(pme_plan_t plan, void* stream, int32_t n,
                 const float* pos, const float* q, const float* mu, const double* box,
                 double* energy, float* dE_dpos, float* dE_dq, float* dE_dmu);
 
+/* pme_forward (same arguments and outputs) that also returns the gradient of E^lr
+ * with respect to the cell at fixed Cartesian positions, charges and dipoles, what
+ * the virial/stress loss of Sec. 2.4 differentiates.  The self terms do not depend
+ * on the cell; E_recip does through the volume, the k-vectors of the Green's
+ * function and the density (mesh coordinates N (r_i C^-1) and x-space dipoles
+ * N (mu_i C^-1)):
+ *   dE/dC = -E_recip C^-T + (1/V) C^-T T - (1/V) (P + Q) C^-T
+ *   T = sum_k |rho~|^2 g (1/k^2 + 1/(4 alpha^2)) k k^T          (the x pass)
+ *   P + Q = sum_i s_i (x) N (q_i G_i + H_i J mu_i) + (mu_i C^-1) (x) N G_i
+ *           with s_i = r_i C^-1 from the caller's (unwrapped) position  (the gather)
+ * (times the prefactor; G_i, H_i the stencil sums of phi with grad W and
+ * grad grad W).  The result depends on which periodic image a position is given
+ * in: moving atom i by n C changes it by -n (x) dE/dr_i.
+ *   dE_dbox   device double[9], row-major like box: dE_dbox[3a+b] = dE/dbox[a][b]
+ *   energy    may be NULL (E_recip is then formed in the plan's workspace)
+ * Uses the plan's workspace; calls on one plan must not overlap. */
+int pme_forward_cell(pme_plan_t plan, void* stream, int32_t n,
+                     const float* pos, const float* q, const float* mu, const double* box,
+                     double* energy, float* dE_dpos, float* dE_dq, float* dE_dmu,
+                     double* dE_dbox);
+
 /* Hessian-vector product of E^lr in (r, q, mu): with the gradient
  * (dE/dr, dE/dq, dE/dmu) of pme_forward and cotangents (v_pos, v_q, v_mu)
  * on it, returns H v, which equals the vector-Jacobian product of the
@@ -146,9 +167,10 @@ int pme_backward(pme_plan_t plan, void* stream, int32_t n,
  * forward gradient and H v of one evaluation, as a training step with a force
  * loss needs them (Sec. 2.4).  With PME_F_CONCURRENT the cotangent's binning,
  * spread and mesh transform run on the plan's second stream, forked from
- * `stream`, beside the forward chain; the Hessian-vector gather follows there once
- * the forward potential exists, beside the forward gather, and the second stream
- * is joined back into `stream`, so all work is ordered before later work on it.
+ * `stream`, beside the forward chain on `stream`; the second stream is joined back
+ * into `stream`, where one gather over the cotangent's records forms H v and the
+ * forward outputs from both potentials, so all work is ordered before later work
+ * on `stream`.
  * Without the flag the two run in sequence on `stream`.  Calls on one plan must
  * not overlap (they share its workspaces). */
 int pme_step(pme_plan_t plan, void* stream, int32_t n,

@@ -103,7 +103,7 @@ void free_plan(pme_plan_s* pl) {
   void* ptrs[] = {d.count[0], d.count[1], d.ovf_count[0], d.ovf_count[1], d.cmax[0],
                   d.cmax[1], d.rec, d.twiddle[0], d.twiddle[1], d.twiddle[2],
                   d.deconv[0], d.deconv[1], d.deconv[2], d.rho, d.spec, d.phi, d.epart,
-                  d.spart, d.status};
+                  d.spart, d.vpart, d.escr, d.status};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete pl;
@@ -303,6 +303,8 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   ok(dev_alloc(&d.phi, size_t(M), by));
   ok(dev_alloc(&d.epart, size_t(pme::fftx_blocks(d)), by));
   ok(dev_alloc(&d.spart, size_t(2 * pme::bin_blocks(desc->max_atoms)), by));
+  ok(dev_alloc(&d.vpart, size_t(6 * pme::fftx_blocks(d) + 9 * d.nt[0] * d.nt[1] * d.nt[2]), by));
+  ok(dev_alloc(&d.escr, 3, by));
   ok(dev_alloc(&d.status, 1, by));
   if (e != hipSuccess) {
     free_plan(pl);
@@ -382,15 +384,23 @@ int64_t pme_plan_workspace_bytes(pme_plan_t plan) { return plan ? plan->bytes : 
 const float* pme_plan_phi(pme_plan_t plan) { return plan ? plan->d.phi : nullptr; }
 const float* pme_plan_rho(pme_plan_t plan) { return plan ? plan->d.rho : nullptr; }
 
-int pme_forward(pme_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
-                const float* mu, const double* box, double* energy, float* dE_dpos,
-                float* dE_dq, float* dE_dmu) {
+}  // extern "C"
+
+namespace {
+
+// pme_forward, and with dE_dbox the cell gradient: the x pass and the gather also
+// form their partials of it and one workgroup assembles dE/dC after the gather
+int forward_impl(pme_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
+                 const float* mu, const double* box, double* energy, float* dE_dpos,
+                 float* dE_dq, float* dE_dmu, double* dE_dbox) {
   if (!plan || n < 0 || !box || (n > 0 && !pos)) return PME_EINVAL;
   if (n > plan->max_atoms) return PME_ECAPACITY;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const DevPlan& d = plan->d;
   pme::KTimer& tm = plan->timer;
   hipError_t e;
+  if (dE_dbox && !energy) energy = d.escr;
+  double* vpart = dE_dbox ? d.vpart : nullptr;
   plan->phi_valid = false;
   const int set = plan->set;
   plan->set ^= 1;
@@ -399,13 +409,33 @@ int pme_forward(pme_plan_t plan, void* stream, int32_t n, const float* pos, cons
     return hip_fail(e);
   if ((e = pme::launch_spread(d, s, set, false, box, tm.next(PME_K_SPREAD))) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm)) != hipSuccess)
+  if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm, vpart)) != hipSuccess)
     return hip_fail(e);
   if ((e = pme::launch_gather(d, s, set, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu,
-                              pme::bin_blocks(n), tm.next(PME_K_GATHER))) != hipSuccess)
+                              pme::bin_blocks(n), tm.next(PME_K_GATHER),
+                              vpart ? vpart + 6 * pme::fftx_blocks(d) : nullptr)) != hipSuccess)
+    return hip_fail(e);
+  if (dE_dbox && (e = pme::launch_cell_grad(d, s, box, energy, dE_dbox)) != hipSuccess)
     return hip_fail(e);
   plan->phi_valid = true;
   return PME_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pme_forward(pme_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
+                const float* mu, const double* box, double* energy, float* dE_dpos,
+                float* dE_dq, float* dE_dmu) {
+  return forward_impl(plan, stream, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu, nullptr);
+}
+
+int pme_forward_cell(pme_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
+                     const float* mu, const double* box, double* energy, float* dE_dpos,
+                     float* dE_dq, float* dE_dmu, double* dE_dbox) {
+  if (!dE_dbox) return PME_EINVAL;
+  return forward_impl(plan, stream, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu, dE_dbox);
 }
 
 int pme_backward(pme_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,

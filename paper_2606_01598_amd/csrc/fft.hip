@@ -486,6 +486,9 @@ struct XArgs {
   const float* dcz;
   float alpha;
   double* epart;   // may be null
+  // cell gradient (the VIR variant): per workgroup the six sums over its points of
+  // w |rho~|^2 g (1/k^2 + 1/(4 alpha^2)) k_c k_d (cc, dd, ..: xx yy zz xy xz yz)
+  double* vpart;
 };
 
 __device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) / 2) ? k - N : k; }
@@ -498,6 +501,7 @@ __device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) 
 // partner.  g is tabulated for the workgroup's points while the line loads are in
 // flight; the product itself sits between the last forward and the first inverse
 // stage, in registers (x_middle).
+template <bool VIR = false>
 __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const double* box,
                                           double* epart) {
   extern __shared__ float2 sm[];
@@ -641,6 +645,47 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
   }
   float2* W = (Z == X) ? Y : X;
   float e_acc = 0.0f;
+  // cell gradient: w |v|^2 G(k) D(f) (1/k^2 + 1/(4 alpha^2)) k k^T with k = 2 pi C^-1 f,
+  // the mean over a Nyquist bin and its Hermitian partner as for g (where a signed
+  // frequency is -N/2 the partner keeps it and flips the others)
+  float vacc[6] = {0, 0, 0, 0, 0, 0};
+  float ci[9];
+  if constexpr (VIR) {
+    const Cell c = cell_from_box(box);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) ci[k] = float(2.0 * M_PI * c.inv[k]);   // 2 pi (C^-1)[b][a]
+  }
+  const float inv4a2v = 1.0f / (4.0f * a.alpha * a.alpha);
+  const int fyv = signed_freq(y, Ny);
+  const bool nyq_yv = ((Ny & 1) == 0) && (2 * fyv == -Ny);
+  auto vir_point = [&](int xx, int kz, int pen, float wv2) {
+    const int fxi = signed_freq(xx, Nx), fzi = signed_freq(kz, Nz);
+    if (kz >= H || (fxi | fyv | fzi) == 0) return;
+    const bool nx = ((Nx & 1) == 0) && (2 * fxi == -Nx);
+    const bool nz = ((Nz & 1) == 0) && (2 * kz == Nz);
+    const float dc = s_dc[xx] * a.dcy[y] * s_dc[Nx + pen];
+    auto add = [&](float fx, float fy, float fz, float scale) {
+      const float k0 = ci[0] * fx + ci[1] * fy + ci[2] * fz;
+      const float k1 = ci[3] * fx + ci[4] * fy + ci[5] * fz;
+      const float k2c = ci[6] * fx + ci[7] * fy + ci[8] * fz;
+      const float k2 = k0 * k0 + k1 * k1 + k2c * k2c;
+      const float f = scale * 4.0f * float(M_PI) / k2 * expf(-k2 * inv4a2v) * dc *
+                      (1.0f / k2 + inv4a2v);
+      vacc[0] = fmaf(f, k0 * k0, vacc[0]);
+      vacc[1] = fmaf(f, k1 * k1, vacc[1]);
+      vacc[2] = fmaf(f, k2c * k2c, vacc[2]);
+      vacc[3] = fmaf(f, k0 * k1, vacc[3]);
+      vacc[4] = fmaf(f, k0 * k2c, vacc[4]);
+      vacc[5] = fmaf(f, k1 * k2c, vacc[5]);
+    };
+    const float fx = float(fxi), fy = float(fyv), fz = float(fzi);
+    if (nx || nyq_yv || nz) {
+      add(fx, fy, fz, 0.5f * wv2);
+      add(nx ? fx : -fx, nyq_yv ? fy : -fy, nz ? fz : -fz, 0.5f * wv2);
+    } else {
+      add(fx, fy, fz, wv2);
+    }
+  };
   {
     const FFTStage& st = a.ax.st[last];
     const int NR = st.NR;
@@ -656,6 +701,7 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
       auto gm = [&](int i, float2 v) -> float {
         const float gg = gl[i];
         if (epart) e_acc = fmaf(wgt * gg, v.x * v.x + v.y * v.y, e_acc);
+        if constexpr (VIR) vir_point(i, kz, pen, wgt * (v.x * v.x + v.y * v.y));
         return gg;
       };
       with_radix(st.R, [&](auto rc) { x_middle<decltype(rc)::value>(in, out, j, NR, tw, gm); });
@@ -693,6 +739,13 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
     const double s = block_sum(double(e_acc), red);
     if (threadIdx.x == 0) epart[blk] = s;
   }
+  if constexpr (VIR) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      const double s = block_sum(double(vacc[k]), red);
+      if (threadIdx.x == 0) a.vpart[6 * blk + k] = s;
+    }
+  }
 }
 
 
@@ -704,8 +757,9 @@ __global__ void __launch_bounds__(kSlabThreads) k_slab_inv(SlabArgs a) {
   slab_inv_body(a, blockIdx.x);
 }
 
+template <bool VIR>
 __global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
-  fftx_body(a, blockIdx.x, a.box, a.epart);
+  fftx_body<VIR>(a, blockIdx.x, a.box, a.epart);
 }
 
 // Batched passes: work item (box, x-plane) or (box, x-pass workgroup); per-box
@@ -751,6 +805,7 @@ XArgs make_x_args(const DevPlan& d, const double* box, bool energy) {
   x.dcx = d.deconv[0]; x.dcy = d.deconv[1]; x.dcz = d.deconv[2];
   x.alpha = float(d.alpha);
   x.epart = energy ? d.epart : nullptr;
+  x.vpart = nullptr;
   return x;
 }
 
@@ -826,9 +881,10 @@ hipError_t launch_convolve_batch(const FFTBatch& t, hipStream_t s, const double*
 }
 
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
-                           bool energy, KTimer* tm) {
+                           bool energy, KTimer* tm, double* vpart) {
   hipError_t err;
-  const XArgs x = make_x_args(d, box, energy);
+  XArgs x = make_x_args(d, box, energy);
+  x.vpart = vpart;
   const size_t xsh = x_lds(d);
   // timed kinds: a kind spanning two launches records its start with the first
   // and its stop with the second
@@ -843,7 +899,8 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
     const SlabArgs sa = make_slab_args(d, out);
     launch_k(er, k_slab_fwd, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    launch_k(ex, k_fftx_fused, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+    if (vpart) launch_k(ex, k_fftx_fused<true>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+    else launch_k(ex, k_fftx_fused<false>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     launch_k(ei, k_slab_inv, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
     return hipGetLastError();
@@ -867,7 +924,8 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   launch_k(er ? &er1 : nullptr, k_ffty, dim3(ffty_blocks(d)), dim3(kFFTThreads), ysh, s, y);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
-  launch_k(ex, k_fftx_fused, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+  if (vpart) launch_k(ex, k_fftx_fused<true>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+  else launch_k(ex, k_fftx_fused<false>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
   y.sign = +1.0f;

@@ -62,6 +62,9 @@ struct GArgs {
   // float constants of the outputs, made on the host: the prefactor, the self-term
   // factors 2 alpha / sqrt(pi) and 4 alpha^3 / (3 sqrt(pi))
   float pf, cq, cm;
+  // cell gradient (forward gather, VIR variant): 9 partials per tile,
+  // sum_i s_i (x) N (q_i G_i + H_i J mu_i) + (mu_i C^-1) (x) N G_i, s_i = r_i C^-1
+  double* vpart;
   int B[3];
   int nb[3];
   int cap;
@@ -192,7 +195,7 @@ __device__ __forceinline__ RecRegs<HVP> load_rec(const float* rec, size_t ri) {
   return o;
 }
 
-template <int P, bool HVP, bool DUAL = false>
+template <int P, bool HVP, bool DUAL = false, bool VIR = false>
 __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   extern __shared__ float sm[];
   // the queue holds kGatherQueue atoms; a round's compacted records beyond that are
@@ -306,6 +309,15 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
     for (int j = 0; j < 3; ++j) J[i][j] = uniform(J[i][j]);
   const float iv = uniform(float(1.0 / c.vol));
   const float pf = a.pf, cq = a.cq, cm = a.cm;
+  // VIR: C^-1 in float and the per-thread sums of the atoms this thread finishes
+  float ci[9], vg[9];
+  if constexpr (VIR) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      ci[k] = float(c.inv[k]);
+      vg[k] = 0.0f;
+    }
+  }
   const int lane = tid & 63, wave = tid >> 6;
   const int gslot = lane / P, ix = lane - gslot * P;
 
@@ -400,6 +412,21 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
           if (a.o_pos) {
             const float3 g = jtmul(J, make_float3(op[0], op[1], op[2]));
             st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+          }
+          if constexpr (VIR) {
+            // unwrapped fractional position (the caller's position) and x-space dipole
+            const float3 r = ld3(a.pos, i);
+            float sf[3], mc[3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+              sf[b] = r.x * ci[b] + r.y * ci[3 + b] + r.z * ci[6 + b];
+              mc[b] = mu.x * ci[b] + mu.y * ci[3 + b] + mu.z * ci[6 + b];
+            }
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+              for (int x = 0; x < 3; ++x)
+                vg[3 * b + x] += float(a.N[x]) * (sf[b] * op[x] + mc[b] * og[x]);
           }
         }
       } else {
@@ -618,11 +645,19 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
     kq = enqueue(valid, rec);
     __syncthreads();
   }
+  if constexpr (VIR) {
+    __shared__ double vred[8];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const double sum = block_sum(double(vg[k]), vred);
+      if (tid == 0) a.vpart[9 * tile + k] = sum;
+    }
+  }
 }
 
-template <int P>
+template <int P, bool VIR = false>
 __device__ __forceinline__ void gather_body(const GArgs& a, const int tile) {
-  gather_tile<P, false>(a, tile);
+  gather_tile<P, false, false, VIR>(a, tile);
 }
 
 template <int P, bool DUAL = false>
@@ -630,10 +665,41 @@ __device__ __forceinline__ void gather_hvp_body(const GArgs& a, const int tile) 
   gather_tile<P, true, DUAL>(a, tile);
 }
 
-template <int P>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 6 ? 4 : 5)))
+template <int P, bool VIR>
+__global__ void __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(P >= 7 && VIR ? 3 : (P >= 6 ? 4 : 5))))
 k_gather(GArgs a) {
-  gather_body<P>(a, blockIdx.x);
+  gather_body<P, VIR>(a, blockIdx.x);
+}
+
+// Cell gradient from E_recip and the partials (one workgroup):
+//   dE/dC = -E_recip C^-T + (pf/V) C^-T T - (pf/V) (P + Q) C^-T
+// with T the k-space sums of the x pass and P + Q the per-atom sums of the gather.
+__global__ void __launch_bounds__(256) k_cell_grad(const double* box, const double* energy,
+                                                   const double* xpart, int nx,
+                                                   const double* gpart, int ng, double pf,
+                                                   double* out) {
+  __shared__ double red[8];
+  double t[6] = {0, 0, 0, 0, 0, 0}, m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = threadIdx.x; k < nx; k += blockDim.x)
+    for (int c = 0; c < 6; ++c) t[c] += xpart[6 * k + c];
+  for (int k = threadIdx.x; k < ng; k += blockDim.x)
+    for (int c = 0; c < 9; ++c) m[c] += gpart[9 * k + c];
+  for (int c = 0; c < 6; ++c) t[c] = block_sum(t[c], red);
+  for (int c = 0; c < 9; ++c) m[c] = block_sum(m[c], red);
+  if (threadIdx.x == 0) {
+    const Cell cl = cell_from_box(box);
+    const double e = energy[0], s = cl.ok ? pf / cl.vol : 0.0;
+    const double T[3][3] = {{t[0], t[3], t[4]}, {t[3], t[1], t[5]}, {t[4], t[5], t[2]}};
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        // (C^-T)[a][b] = (C^-1)[b][a] = inv[3 b + a]
+        double g = -e * cl.inv[3 * b + a];
+        for (int c = 0; c < 3; ++c)
+          g += s * (cl.inv[3 * c + a] * T[c][b] - m[3 * a + c] * cl.inv[3 * b + c]);
+        out[3 * a + b] = g;
+      }
+  }
 }
 
 template <int P, bool DUAL>
@@ -671,11 +737,12 @@ __global__ void __launch_bounds__(256) k_gather_batch(const GArgs* args, const i
 template <bool HVP>
 hipError_t gather_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const GArgs& a,
                            const LaunchEvents* ev, bool dual = false) {
-#define PME_G(P)                                                              \
-  case P:                                                                     \
-    if (HVP && dual) launch_k(ev, k_gather_hvp<P, true>, g, dim3(256), sh, s, a); \
-    else if (HVP) launch_k(ev, k_gather_hvp<P, false>, g, dim3(256), sh, s, a);   \
-    else launch_k(ev, k_gather<P>, g, dim3(256), sh, s, a);                   \
+#define PME_G(P)                                                                  \
+  case P:                                                                         \
+    if (HVP && dual) launch_k(ev, k_gather_hvp<P, true>, g, dim3(256), sh, s, a);     \
+    else if (HVP) launch_k(ev, k_gather_hvp<P, false>, g, dim3(256), sh, s, a);       \
+    else if (a.vpart) launch_k(ev, k_gather<P, true>, g, dim3(256), sh, s, a);        \
+    else launch_k(ev, k_gather<P, false>, g, dim3(256), sh, s, a);                    \
     break;
   switch (p) {
     PME_G(1) PME_G(2) PME_G(3) PME_G(4) PME_G(5) PME_G(6) PME_G(7)
@@ -731,7 +798,8 @@ hipError_t gather_batch_dispatch(int p, dim3 g, size_t sh, hipStream_t s, const 
 hipError_t enable_gather_lds() {
   const void* fns[] = {
 #define PME_G(P)                                                                             \
-  reinterpret_cast<const void*>(k_gather<P>),                                                \
+  reinterpret_cast<const void*>(k_gather<P, false>),                                         \
+      reinterpret_cast<const void*>(k_gather<P, true>),                                     \
       reinterpret_cast<const void*>(k_gather_hvp<P, false>),                                \
       reinterpret_cast<const void*>(k_gather_hvp<P, true>),                                 \
       reinterpret_cast<const void*>(k_gather_batch<P, false>),                               \
@@ -796,13 +864,22 @@ hipError_t launch_gather_batch(const GatherBatch& t, hipStream_t s, int set, boo
 hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                          const float* q, const float* mu, const double* box, double* energy,
                          float* dE_dpos, float* dE_dq, float* dE_dmu, int n_spart,
-                         const LaunchEvents* ev) {
+                         const LaunchEvents* ev, double* vpart) {
   GArgs a = base_args(d, set, n, pos, q, mu, box);
   a.o_pos = dE_dpos; a.o_q = dE_dq; a.o_mu = dE_dmu;
   a.energy = energy; a.epart = d.epart; a.n_epart = fftx_blocks(d);
   a.spart = d.spart; a.n_spart = n_spart;
+  a.vpart = vpart;
   return gather_dispatch<false>(d.p, dim3(d.nt[0] * d.nt[1] * d.nt[2]), region_bytes(d, 1), s, a,
                                 ev);
+}
+
+hipError_t launch_cell_grad(const DevPlan& d, hipStream_t s, const double* box,
+                            const double* energy, double* dE_dbox) {
+  const int nx = fftx_blocks(d);
+  hipLaunchKernelGGL(k_cell_grad, dim3(1), dim3(256), 0, s, box, energy, d.vpart, nx,
+                     d.vpart + 6 * nx, d.nt[0] * d.nt[1] * d.nt[2], d.prefactor, dE_dbox);
+  return hipGetLastError();
 }
 
 hipError_t launch_gather_hvp(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,

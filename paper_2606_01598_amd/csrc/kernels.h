@@ -102,6 +102,8 @@ struct DevPlan {
   // reductions
   double* epart;           // [x-pass blocks]
   double* spart;           // [2 * bin blocks]
+  double* vpart;           // cell gradient: [6 per x-pass block] then [9 per tile]
+  double* escr;            // [3] energy of a cell-gradient call that asks for none
   int* status;             // bit 0: non-finite input seen
 };
 
@@ -219,9 +221,10 @@ hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const flo
 // Owner-computes spread of the binned records (counter set `set`) into d.rho.
 hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
                          const double* box, const LaunchEvents* ev);
-// rho -> spec -> (x g) -> out, the mesh operator K; energy partials when wanted.
+// rho -> spec -> (x g) -> out, the mesh operator K; energy partials when wanted, and
+// with vpart the six k-space partials of the cell gradient per x-pass workgroup.
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
-                           bool energy, KTimer* tm);
+                           bool energy, KTimer* tm, double* vpart = nullptr);
 // Raise the dynamic LDS limit of the spread (kBigLds) and gather (kGatherLds) kernels.
 hipError_t enable_spread_lds();
 hipError_t enable_gather_lds();
@@ -232,7 +235,11 @@ hipError_t enable_slab_lds(size_t bytes);
 hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                          const float* q, const float* mu, const double* box, double* energy,
                          float* dE_dpos, float* dE_dq, float* dE_dmu, int n_spart,
-                         const LaunchEvents* ev);
+                         const LaunchEvents* ev, double* vpart = nullptr);
+// Cell gradient dE^lr/dC (row-major like the box) from E_recip (energy[0]) and the
+// partials of the x pass (vpart, 6 per block) and of the gather (9 per tile after them).
+hipError_t launch_cell_grad(const DevPlan& d, hipStream_t s, const double* box,
+                            const double* energy, double* dE_dbox);
 // Hessian-vector product gather from phi (d.phi) and psi (d.rho).
 // Forward outputs a Hessian-vector gather may form as well (same atoms, same phi).
 struct GatherForward {

@@ -7,7 +7,8 @@ stream.
 
 * ``mesh_dims(box, spacing, strategy)``        -- Eq. mesh_target + strategies
 * ``Plan``                                     -- pme_plan_create / destroy
-* ``Plan.forward(...)``                        -- pme_forward
+* ``Plan.forward(...)``                        -- pme_forward (``cell=True``: pme_forward_cell,
+  also dE/dbox at fixed Cartesian inputs)
 * ``Plan.backward(...)``                       -- pme_backward (Hessian-vector product)
 * ``Plan.step(...)``                           -- pme_step (forward and H v in one call)
 * ``pme_energy(pos, q, mu, box, plan)``        -- E^lr as a differentiable torch op
@@ -114,12 +115,16 @@ class Plan:
         return n
 
     def forward(self, pos, q, mu, box, energy=True, dE_dpos=True, dE_dq=True, dE_dmu=True,
-                out=None):
+                out=None, cell=False):
         """pme_forward.  Returns dict(energy (3,) f64, dE_dpos, dE_dq, dE_dmu) of the
-        requested outputs; ``out`` may supply preallocated tensors with those keys."""
+        requested outputs; ``out`` may supply preallocated tensors with those keys.
+        With ``cell=True`` (pme_forward_cell) also dE_dbox (3, 3) f64, the gradient of
+        E^lr with respect to the cell at fixed Cartesian positions."""
         n = self._check_common(pos, q, mu, box)
         out = {} if out is None else dict(out)
         dev = self.device
+        if cell and "dE_dbox" not in out:
+            out["dE_dbox"] = torch.empty(3, 3, dtype=torch.float64, device=dev)
         if energy and "energy" not in out:
             out["energy"] = torch.empty(3, dtype=torch.float64, device=dev)
         if dE_dpos and "dE_dpos" not in out:
@@ -128,9 +133,13 @@ class Plan:
             out["dE_dq"] = torch.empty(n, dtype=torch.float32, device=dev)
         if dE_dmu and "dE_dmu" not in out:
             out["dE_dmu"] = torch.empty(n, 3, dtype=torch.float32, device=dev)
-        rc = self._lib.pme_forward(self.handle, _stream(), n, _ptr(pos), _ptr(q), _ptr(mu), _ptr(box),
-                                   _ptr(out.get("energy")), _ptr(out.get("dE_dpos")),
-                                   _ptr(out.get("dE_dq")), _ptr(out.get("dE_dmu")))
+        args = (self.handle, _stream(), n, _ptr(pos), _ptr(q), _ptr(mu), _ptr(box),
+                _ptr(out.get("energy")), _ptr(out.get("dE_dpos")), _ptr(out.get("dE_dq")),
+                _ptr(out.get("dE_dmu")))
+        if cell:
+            rc = self._lib.pme_forward_cell(*args, _ptr(out["dE_dbox"]))
+        else:
+            rc = self._lib.pme_forward(*args)
         _lib.check(rc)
         return out
 
@@ -246,21 +255,26 @@ class _PMEGrad(torch.autograd.Function):
 class _PMEEnergy(torch.autograd.Function):
     @staticmethod
     def forward(ctx, pos, q, mu, box, plan):
-        r = plan.forward(pos.detach(), q.detach(), mu.detach(), box)
+        cell = box.requires_grad
+        r = plan.forward(pos.detach(), q.detach(), mu.detach(), box.detach(), cell=cell)
         ctx.plan = plan
-        ctx.save_for_backward(pos, q, mu, box, r["dE_dpos"], r["dE_dq"], r["dE_dmu"])
+        gb = r["dE_dbox"] if cell else torch.zeros(0, dtype=torch.float64, device=box.device)
+        ctx.save_for_backward(pos, q, mu, box, r["dE_dpos"], r["dE_dq"], r["dE_dmu"], gb)
         return r["energy"].sum()
 
     @staticmethod
     def backward(ctx, gE):
-        pos, q, mu, box, gp, gq, gm = ctx.saved_tensors
+        pos, q, mu, box, gp, gq, gm, gb = ctx.saved_tensors
         if torch.is_grad_enabled():
-            gp, gq, gm = _PMEGrad.apply(pos, q, mu, box, ctx.plan, gp, gq, gm)
+            gp, gq, gm = _PMEGrad.apply(pos, q, mu, box.detach(), ctx.plan, gp, gq, gm)
         s = gE.to(torch.float32)
-        return gp * s, gq * s, gm * s, None, None
+        # the cell gradient is first order: a constant for a second differentiation
+        g_box = gb * gE.to(torch.float64) if gb.numel() else None
+        return gp * s, gq * s, gm * s, g_box, None
 
 
 def pme_energy(pos: torch.Tensor, q: torch.Tensor, mu: torch.Tensor, box: torch.Tensor,
                plan: Plan) -> torch.Tensor:
-    """E^lr (float64 scalar) with gradients to pos, q and mu; differentiable twice."""
+    """E^lr (float64 scalar) with gradients to pos, q and mu, differentiable twice, and
+    to box (first order, pme_forward_cell) when box requires grad."""
     return _PMEEnergy.apply(pos, q, mu, box, plan)
