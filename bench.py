@@ -133,6 +133,8 @@ def _args(argv=None):
     ap.add_argument("--sweep-summary", nargs="+", default=None, metavar="LOG",
                     help="write profiles/pme_sweep_molten_sizes.txt from the JSON lines of "
                          "bench runs at several workloads and exit")
+    ap.add_argument("--cell", type=int, default=1,
+                    help="1 adds the cell-gradient leg (pme_forward_cell against pme_forward)")
     ap.add_argument("--batched", type=int, default=1,
                     help="1 adds the batched-graph leg (64 boxes, one HIP graph per step)")
     ap.add_argument("--learned", type=int, default=1,
@@ -260,6 +262,8 @@ def main(argv=None):
         "kernels_us": kernels_us,
         "step_model_bytes": step_bytes(n, m, not args.sequential),
     }
+    if args.cell:
+        line["cell_gradient"] = cell_leg(pos, q, mu, box, mesh, p, alpha, n)
     if args.batched:
         line["batched"] = batched_leg()
     if args.learned:
@@ -281,6 +285,42 @@ def _median_ms(fn, reps):
         times.append((time.perf_counter() - t0) * 1e3)
     times.sort()
     return times[len(times) // 2]
+
+
+def cell_leg(pos, q, mu, box, mesh, p, alpha, n, reps=50):
+    """The cell gradient dE^lr/dC (pme_forward_cell) on the benchmark workload: the
+    forward call with and without it, median of ``reps`` timed calls each (inputs
+    resident in HBM), and the launch-timer durations of the kernel variants that
+    form its partials."""
+    import torch
+
+    from paper_2606_01598_amd.pme import Plan
+    plan = Plan(mesh, p, alpha, max_atoms=n)
+    dev = pos.device
+    fo = {"energy": torch.empty(3, dtype=torch.float64, device=dev),
+          "dE_dpos": torch.empty(n, 3, device=dev), "dE_dq": torch.empty(n, device=dev),
+          "dE_dmu": torch.empty(n, 3, device=dev),
+          "dE_dbox": torch.empty(3, 3, dtype=torch.float64, device=dev)}
+    plain = {k: v for k, v in fo.items() if k != "dE_dbox"}
+    for _ in range(10):
+        plan.forward(pos, q, mu, box, out=plain)
+        plan.forward(pos, q, mu, box, out=fo, cell=True)
+    plan.status()
+    t_plain = _median_ms(lambda: plan.forward(pos, q, mu, box, out=plain), reps)
+    t_cell = _median_ms(lambda: plan.forward(pos, q, mu, box, out=fo, cell=True), reps)
+    kern = {}
+    for kind in ("fft_x", "gather"):
+        for cell in (False, True):
+            plan.timer(kind)
+            for _ in range(10):
+                plan.forward(pos, q, mu, box, out=fo if cell else plain, cell=cell)
+            k, ms = plan.timer_read()
+            kern[f"{kind}{'_cell' if cell else ''}"] = round(1e3 * ms / max(k, 1), 3)
+    plan.timer(None)
+    plan.status()
+    return {"workload": "the benchmark box, pme_forward vs pme_forward_cell",
+            "forward_ms": round(t_plain, 4), "forward_cell_ms": round(t_cell, 4),
+            "overhead_ms": round(t_cell - t_plain, 4), "kernels_us": kern}
 
 
 def batched_leg(n_boxes=64, seed=6, reps=20):

@@ -658,19 +658,22 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
   const float inv4a2v = 1.0f / (4.0f * a.alpha * a.alpha);
   const int fyv = signed_freq(y, Ny);
   const bool nyq_yv = ((Ny & 1) == 0) && (2 * fyv == -Ny);
-  auto vir_point = [&](int xx, int kz, int pen, float wv2) {
+  auto vir_point = [&](int xx, int kz, int pen, float wv2, float gg) {
     const int fxi = signed_freq(xx, Nx), fzi = signed_freq(kz, Nz);
     if (kz >= H || (fxi | fyv | fzi) == 0) return;
     const bool nx = ((Nx & 1) == 0) && (2 * fxi == -Nx);
     const bool nz = ((Nz & 1) == 0) && (2 * kz == Nz);
-    const float dc = s_dc[xx] * a.dcy[y] * s_dc[Nx + pen];
+    const bool nyq = nx || nyq_yv || nz;
+    // off the Nyquist bins the tabulated g is this point's own; on them each of the
+    // bin and its partner needs its own G(k)
+    const float dc = nyq ? s_dc[xx] * a.dcy[y] * s_dc[Nx + pen] : 0.0f;
     auto add = [&](float fx, float fy, float fz, float scale) {
       const float k0 = ci[0] * fx + ci[1] * fy + ci[2] * fz;
       const float k1 = ci[3] * fx + ci[4] * fy + ci[5] * fz;
       const float k2c = ci[6] * fx + ci[7] * fy + ci[8] * fz;
       const float k2 = k0 * k0 + k1 * k1 + k2c * k2c;
-      const float f = scale * 4.0f * float(M_PI) / k2 * expf(-k2 * inv4a2v) * dc *
-                      (1.0f / k2 + inv4a2v);
+      const float gk = nyq ? 4.0f * float(M_PI) / k2 * expf(-k2 * inv4a2v) * dc : gg;
+      const float f = scale * gk * (1.0f / k2 + inv4a2v);
       vacc[0] = fmaf(f, k0 * k0, vacc[0]);
       vacc[1] = fmaf(f, k1 * k1, vacc[1]);
       vacc[2] = fmaf(f, k2c * k2c, vacc[2]);
@@ -679,7 +682,7 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
       vacc[5] = fmaf(f, k1 * k2c, vacc[5]);
     };
     const float fx = float(fxi), fy = float(fyv), fz = float(fzi);
-    if (nx || nyq_yv || nz) {
+    if (nyq) {
       add(fx, fy, fz, 0.5f * wv2);
       add(nx ? fx : -fx, nyq_yv ? fy : -fy, nz ? fz : -fz, 0.5f * wv2);
     } else {
@@ -701,7 +704,7 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
       auto gm = [&](int i, float2 v) -> float {
         const float gg = gl[i];
         if (epart) e_acc = fmaf(wgt * gg, v.x * v.x + v.y * v.y, e_acc);
-        if constexpr (VIR) vir_point(i, kz, pen, wgt * (v.x * v.x + v.y * v.y));
+        if constexpr (VIR) vir_point(i, kz, pen, wgt * (v.x * v.x + v.y * v.y), gg);
         return gg;
       };
       with_radix(st.R, [&](auto rc) { x_middle<decltype(rc)::value>(in, out, j, NR, tw, gm); });
@@ -740,11 +743,14 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
     if (threadIdx.x == 0) epart[blk] = s;
   }
   if constexpr (VIR) {
+    __shared__ double vred[16 * 6];
+    double v[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      const double s = block_sum(double(vacc[k]), red);
-      if (threadIdx.x == 0) a.vpart[6 * blk + k] = s;
-    }
+    for (int k = 0; k < 6; ++k) v[k] = vacc[k];
+    block_sums<6>(v, vred);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) a.vpart[6 * blk + k] = v[k];
   }
 }
 

@@ -174,7 +174,7 @@ struct RecRegs {
 template <>
 struct RecRegs<false> {
   float4 h, qm;
-  int atom;
+  float4 sa;   // unwrapped fractional position, atom index (bits)
 };
 
 template <bool HVP>
@@ -190,7 +190,7 @@ __device__ __forceinline__ RecRegs<HVP> load_rec(const float* rec, size_t ri) {
     const float* f = rec + ri * kRecWords;
     o.h = r[0];
     o.qm = make_float4(f[4], f[8], f[9], f[10]);
-    o.atom = __float_as_int(f[15]);
+    o.sa = r[3];
   }
   return o;
 }
@@ -205,6 +205,7 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   __shared__ float4 s_v1[HVP ? kGatherQueue : 1];    // v_q, v_r
   __shared__ float4 s_v2[HVP ? kGatherQueue : 1];    // v_mu, atom
   __shared__ int s_atom[HVP ? 1 : kGatherQueue];     // forward
+  __shared__ float4 s_sa[VIR ? kGatherQueue : 1];    // VIR: unwrapped fractional position
   __shared__ int s_n;
   __shared__ float s_coef[4 * P * P];       // pieces of N_P and their derivatives
   constexpr int lo = (P - 1) / 2;
@@ -329,7 +330,8 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
       s_v2[k] = r.r3;
     } else {
       s_qm[k] = r.qm;
-      s_atom[k] = r.atom;
+      s_atom[k] = __float_as_int(r.sa.w);
+      if constexpr (VIR) s_sa[k] = r.sa;
     }
   };
   // compacted index of a valid record (-1 otherwise); the first kGatherQueue are queued
@@ -414,14 +416,13 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
             st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
           }
           if constexpr (VIR) {
-            // unwrapped fractional position (the caller's position) and x-space dipole
-            const float3 r = ld3(a.pos, i);
-            float sf[3], mc[3];
+            // unwrapped fractional position (from the caller's position, by the
+            // binning) and the dipole times C^-1
+            const float4 sa = s_sa[slot];
+            const float sf[3] = {sa.x, sa.y, sa.z};
+            float mc[3];
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-              sf[b] = r.x * ci[b] + r.y * ci[3 + b] + r.z * ci[6 + b];
-              mc[b] = mu.x * ci[b] + mu.y * ci[3 + b] + mu.z * ci[6 + b];
-            }
+            for (int b = 0; b < 3; ++b) mc[b] = mu.x * ci[b] + mu.y * ci[3 + b] + mu.z * ci[6 + b];
 #pragma unroll
             for (int b = 0; b < 3; ++b)
 #pragma unroll
@@ -646,12 +647,14 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
     __syncthreads();
   }
   if constexpr (VIR) {
-    __shared__ double vred[8];
+    __shared__ double vred[16 * 9];
+    double v[9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) {
-      const double sum = block_sum(double(vg[k]), vred);
-      if (tid == 0) a.vpart[9 * tile + k] = sum;
-    }
+    for (int k = 0; k < 9; ++k) v[k] = vg[k];
+    block_sums<9>(v, vred);
+    if (tid == 0)
+#pragma unroll
+      for (int k = 0; k < 9; ++k) a.vpart[9 * tile + k] = v[k];
   }
 }
 
@@ -679,14 +682,14 @@ __global__ void __launch_bounds__(256) k_cell_grad(const double* box, const doub
                                                    const double* xpart, int nx,
                                                    const double* gpart, int ng, double pf,
                                                    double* out) {
-  __shared__ double red[8];
+  __shared__ double red[16 * 9];
   double t[6] = {0, 0, 0, 0, 0, 0}, m[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   for (int k = threadIdx.x; k < nx; k += blockDim.x)
     for (int c = 0; c < 6; ++c) t[c] += xpart[6 * k + c];
   for (int k = threadIdx.x; k < ng; k += blockDim.x)
     for (int c = 0; c < 9; ++c) m[c] += gpart[9 * k + c];
-  for (int c = 0; c < 6; ++c) t[c] = block_sum(t[c], red);
-  for (int c = 0; c < 9; ++c) m[c] = block_sum(m[c], red);
+  block_sums<6>(t, red);
+  block_sums<9>(m, red);
   if (threadIdx.x == 0) {
     const Cell cl = cell_from_box(box);
     const double e = energy[0], s = cl.ok ? pf / cl.vol : 0.0;

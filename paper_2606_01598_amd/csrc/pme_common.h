@@ -218,4 +218,27 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return s;   // valid in thread 0
 }
 
+// block-wide sums of K doubles with one pair of barriers (blockDim.x a multiple of
+// 64, at most 1024; scratch holds 16 K doubles); the sums land in v of thread 0
+template <int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_down(v[k], o, 64);
+    if (lane == 0) scratch[wid * K + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      double s = 0.0;
+      for (int w = 0; w < int(blockDim.x >> 6); ++w) s += scratch[w * K + k];
+      v[k] = s;
+    }
+  }
+  __syncthreads();
+}
+
 }  // namespace pme

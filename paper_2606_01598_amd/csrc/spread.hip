@@ -20,8 +20,8 @@
 //    instead of being flushed with global atomics, so the mesh needs no clearing
 //    and no global read-modify-write.
 //
-// Record layout (16 words): f_x f_y f_z anchor | c0 c1 c2 c3 | forward: mu_x mu_y mu_z -,
-// tangent: c4 c5 c6 c7 | tangent: c8 c9 - atom, forward: - - - atom.
+// Record layout (16 words): f_x f_y f_z anchor | forward: q d_x d_y d_z, tangent: q mu |
+// forward: mu -, tangent: v_q v_r | forward: s (= r C^-1, unwrapped) atom, tangent: v_mu atom.
 #include <vector>
 
 #include "kernels.h"
@@ -146,9 +146,16 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
         d4[2] = make_float4(vq, vr.x, vr.y, vr.z);
         d4[3] = make_float4(vm.x, vm.y, vm.z, __int_as_float(i));
       } else {
+        // and the unwrapped fractional position r C^-1 (its image matters to the
+        // cell gradient, which the forward gather forms when asked)
+        const double r0 = a.pos[3 * i], r1 = a.pos[3 * i + 1], r2 = a.pos[3 * i + 2];
+        float sf[3];
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          sf[b] = float(r0 * c.inv[b] + r1 * c.inv[3 + b] + r2 * c.inv[6 + b]);
         d4[1] = make_float4(co[0], co[1], co[2], co[3]);
         d4[2] = make_float4(mu.x, mu.y, mu.z, 0.f);
-        d4[3] = make_float4(0.f, 0.f, 0.f, __int_as_float(i));
+        d4[3] = make_float4(sf[0], sf[1], sf[2], __int_as_float(i));
       }
     }
   }
