@@ -206,8 +206,46 @@ def signed_index(N: int) -> np.ndarray:
     return k - N * (k >= (N + 1) // 2)
 
 
+def influence_optimal(box, mesh, p, alpha, m_max=1):
+    """The energy-optimal influence function of the assignment of order p, with
+    aliasing sums (an alternative to the sinc^(-2 gamma p) deconvolution, Sec. 2.3.4
+    mentions it only by name):
+        g(f) = sum_m U^2(f + m N) G(k(f + m N)) / (sum_m U^2(f + m N))^2,
+        U(f) = prod_a sinc(f_a / N_a)^p,  m in [-m_max, m_max]^3,  g(0) = 0.
+    Restricted to m = 0 it is G / U^2, the gamma = 1 deconvolution."""
+    _, _, _, recip = cell(box)
+    N = [int(n) for n in mesh]
+    f = [signed_index(n).astype(np.float64) for n in N]
+    # separable denominator: sum_m U^2 = prod_a sum_{m_a} sinc^(2p)((f_a + m_a N_a)/N_a)
+    S = [sum(np.sinc((f[a] + m * N[a]) / N[a]) ** (2 * p) for m in range(-m_max, m_max + 1))
+         for a in range(3)]
+    den = (S[0][:, None, None] * S[1][None, :, None] * S[2][None, None, :]) ** 2
+    num = np.zeros(tuple(N))
+    for mx in range(-m_max, m_max + 1):
+        for my in range(-m_max, m_max + 1):
+            for mz in range(-m_max, m_max + 1):
+                fx, fy, fz = f[0] + mx * N[0], f[1] + my * N[1], f[2] + mz * N[2]
+                u2 = (np.sinc(fx / N[0])[:, None, None] * np.sinc(fy / N[1])[None, :, None]
+                      * np.sinc(fz / N[2])[None, None, :]) ** (2 * p)
+                kvec = (fx[:, None, None, None] * recip[0] + fy[None, :, None, None] * recip[1]
+                        + fz[None, None, :, None] * recip[2])
+                k2 = np.einsum('xyzc,xyzc->xyz', kvec, kvec)
+                with np.errstate(divide='ignore', invalid='ignore'):
+                    G = 4.0 * math.pi / k2 * np.exp(-k2 / (4.0 * alpha * alpha))
+                G[k2 == 0.0] = 0.0
+                num += u2 * G
+    g = num / den
+    g[0, 0, 0] = 0.0
+    return g
+
+
 def influence(box, mesh, p, alpha, gamma=1.0):
-    """g(n) = G(k) * C(n) on the full grid, with k = sum_a f_a b_a and g(0) = 0."""
+    """g(n) = G(k) * C(n) on the full grid, with k = sum_a f_a b_a and g(0) = 0.
+    gamma = "optimal" selects the energy-optimal influence function instead."""
+    if isinstance(gamma, str):
+        if gamma != "optimal":
+            raise ValueError(gamma)
+        return influence_optimal(box, mesh, p, alpha)
     _, _, _, recip = cell(box)
     fx, fy, fz = (signed_index(N).astype(np.float64) for N in mesh)
     kvec = (fx[:, None, None, None] * recip[0] + fy[None, :, None, None] * recip[1]
@@ -356,6 +394,8 @@ def cell_gradient(pos, q, mu, box, mesh, p, alpha, gamma=1.0, prefactor=1.0) -> 
                                             -(1/V) [sum_i s_i (x) N (q_i G_i + H_i J mu_i)
                                                     + (mu_i C^-1) (x) N G_i] C^-T
     """
+    if isinstance(gamma, str):
+        raise NotImplementedError("the cell gradient is defined for the deconvolution influence")
     pos, q, mu = _inputs(pos, q, mu)
     mesh = tuple(int(m) for m in mesh)
     _, Cinv, V, recip = cell(box)
