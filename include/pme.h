@@ -71,6 +71,12 @@ extern "C" {
  * forward chain and the cotangent's chain (its density, transform and potential)
  * concurrently. */
 #define PME_F_CONCURRENT 2
+/* Use the energy-optimal influence function with aliasing sums instead of the
+ * sinc^(-2 gamma p) deconvolution of Eq. influence (influence_power is then
+ * unused):  g(f) = sum_m U^2(f + m N) G(k(f + m N)) / (sum_m U^2(f + m N))^2,
+ * U(f) = prod_a sinc(f_a / N_a)^p, m in {-1, 0, 1}^3.  Not with pme_forward_cell
+ * or batches (PME_EINVAL). */
+#define PME_F_OPT_INFLUENCE 4
 
 /* ---- mesh strategies for pme_mesh_dims (Sec. 2.3.1) ------------------- */
 #define PME_MESH_POW2    0   /* N = 2^ceil(log2 N_target)                       */

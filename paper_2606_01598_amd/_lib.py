@@ -24,6 +24,7 @@ PME_ENONFINITE = -8
 
 PME_F_KEEP_PHI = 1
 PME_F_CONCURRENT = 2
+PME_F_OPT_INFLUENCE = 4
 
 PME_MESH_POW2 = 0
 PME_MESH_SMOOTH = 1

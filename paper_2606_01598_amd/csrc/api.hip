@@ -103,7 +103,7 @@ void free_plan(pme_plan_s* pl) {
   void* ptrs[] = {d.count[0], d.count[1], d.ovf_count[0], d.ovf_count[1], d.cmax[0],
                   d.cmax[1], d.rec, d.twiddle[0], d.twiddle[1], d.twiddle[2],
                   d.deconv[0], d.deconv[1], d.deconv[2], d.rho, d.spec, d.phi, d.epart,
-                  d.spart, d.vpart, d.escr, d.status};
+                  d.spart, d.vpart, d.escr, d.status, d.alias[0], d.alias[1], d.alias[2]};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete pl;
@@ -166,7 +166,9 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   if (!(desc->alpha > 0.0) || !isfinite(desc->alpha) || !(desc->influence_power >= 0.0) ||
       !isfinite(desc->influence_power) || !isfinite(desc->prefactor))
     return PME_EALPHA;
-  if (desc->max_atoms < 1 || (desc->flags & ~(PME_F_KEEP_PHI | PME_F_CONCURRENT))) return PME_EINVAL;
+  if (desc->max_atoms < 1 ||
+      (desc->flags & ~(PME_F_KEEP_PHI | PME_F_CONCURRENT | PME_F_OPT_INFLUENCE)))
+    return PME_EINVAL;
   for (int a = 0; a < 3; ++a)
     if (desc->tile[a] < 0 || desc->tile[a] > 1024) return PME_EINVAL;
 
@@ -185,6 +187,7 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   d.p = p;
   d.alpha = desc->alpha;
   d.prefactor = desc->prefactor;
+  d.opt = (desc->flags & PME_F_OPT_INFLUENCE) != 0;
   const long M = long(d.N[0]) * d.N[1] * d.N[2];
 
   // bins of B cells and mesh tiles of T = k B cells (targets 8 x 8 x 16 unless the
@@ -272,7 +275,10 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
     // LDS of a line workgroup within 56 KB: twiddles, two line buffers and (x pass)
     // the kt N_x table of g and the deconvolution factors:
     // 8 N + kt (16 (N + 1) + 4 N) + 4 (N + kt) bytes
-    const int lds_cap = (7000 - nmax - (nmax + 1) / 2) / (2 * (nmax + 1) + (nmax + 1) / 2 + 2);
+    // (optimal influence: 12 (N + kt) more bytes of aliasing weights)
+    const int extra = d.opt ? 3 * (nmax + 1) / 2 : 0;
+    const int lds_cap = (7000 - nmax - (nmax + 1) / 2 - extra) /
+                        (2 * (nmax + 1) + (nmax + 1) / 2 + 2 + (d.opt ? 2 : 0));
     if (kt > lds_cap) kt = lds_cap;
     if (kt < 1) kt = 1;
     if (kt > d.H) kt = d.H;
@@ -297,6 +303,7 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   for (int a = 0; a < 3; ++a) {
     ok(dev_alloc(&d.twiddle[a], size_t(d.N[a]), by));
     ok(dev_alloc(&d.deconv[a], size_t(d.N[a]), by));
+    if (d.opt) ok(dev_alloc(&d.alias[a], size_t(3 * d.N[a]), by));
   }
   ok(dev_alloc(&d.rho, size_t(M), by));
   ok(dev_alloc(&d.spec, size_t(d.N[0]) * d.N[1] * d.H, by));
@@ -321,6 +328,23 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
       const int f = (t >= (N + 1) / 2) ? t - N : t;
       const double b = pow(fabs(sinc(double(f) / N)), double(p));
       dc[t] = float(pow(b, -2.0 * desc->influence_power));
+    }
+    if (d.opt) {
+      // aliasing weights sinc^{2p}((f + m N)/N), m = -1, 0, 1, and the separable
+      // denominator of the optimal influence function
+      float* al = new float[3 * N];
+      for (int t = 0; t < N; ++t) {
+        const int f = (t >= (N + 1) / 2) ? t - N : t;
+        double sum = 0.0;
+        for (int m = -1; m <= 1; ++m) {
+          const double u = pow(sinc(double(f + m * N) / N), 2.0 * p);
+          al[(m + 1) * N + t] = float(u);
+          sum += u;
+        }
+        dc[t] = float(1.0 / (sum * sum));
+      }
+      ok(hipMemcpy(d.alias[a], al, sizeof(float) * 3 * N, hipMemcpyHostToDevice));
+      delete[] al;
     }
     ok(hipMemcpy(d.twiddle[a], tw, sizeof(float2) * N, hipMemcpyHostToDevice));
     ok(hipMemcpy(d.deconv[a], dc, sizeof(float) * N, hipMemcpyHostToDevice));
@@ -434,7 +458,7 @@ int pme_forward(pme_plan_t plan, void* stream, int32_t n, const float* pos, cons
 int pme_forward_cell(pme_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
                      const float* mu, const double* box, double* energy, float* dE_dpos,
                      float* dE_dq, float* dE_dmu, double* dE_dbox) {
-  if (!dE_dbox) return PME_EINVAL;
+  if (!dE_dbox || (plan && plan->d.opt)) return PME_EINVAL;
   return forward_impl(plan, stream, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu, dE_dbox);
 }
 
@@ -662,6 +686,7 @@ int pme_batch_create(const pme_desc_t* descs, int32_t nbox, const int32_t* n_ato
   for (int b = 0; b < nbox; ++b) {
     if (n_atoms[b] < 0) return PME_EINVAL;
     if (descs[b].order != descs[0].order) return PME_EORDER;
+    if (descs[b].flags & PME_F_OPT_INFLUENCE) return PME_EINVAL;
   }
   pme_batch_s* bt = new (std::nothrow) pme_batch_s();
   if (!bt) return PME_ENOMEM;

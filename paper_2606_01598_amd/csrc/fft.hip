@@ -489,6 +489,10 @@ struct XArgs {
   // cell gradient (the VIR variant): per workgroup the six sums over its points of
   // w |rho~|^2 g (1/k^2 + 1/(4 alpha^2)) k_c k_d (cc, dd, ..: xx yy zz xy xz yz)
   double* vpart;
+  // optimal influence (the OPT variant): aliasing weights [3][N_a] per axis
+  const float* alx;
+  const float* aly;
+  const float* alz;
 };
 
 __device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) / 2) ? k - N : k; }
@@ -501,7 +505,9 @@ __device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) 
 // partner.  g is tabulated for the workgroup's points while the line loads are in
 // flight; the product itself sits between the last forward and the first inverse
 // stage, in registers (x_middle).
-template <bool VIR = false>
+// MODE 0: the influence function of Eq. influence; 1: the same, also forming the
+// cell-gradient partials; 2: the optimal influence function (aliasing sums).
+template <int MODE = 0>
 __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const double* box,
                                           double* epart) {
   extern __shared__ float2 sm[];
@@ -512,7 +518,10 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
   float2* X = tw + Nx;
   float2* Y = X + kt * ps;
   float* s_g = reinterpret_cast<float*>(Y + kt * ps);   // g[l Nx + kx]
+  constexpr bool VIR = MODE == 1, OPT = MODE == 2;
   float* s_dc = s_g + Nx * kt;                          // deconvolution: [Nx] x, [kt] z
+  float* s_alx = s_dc + Nx + kt;                        // OPT: [3][Nx] x aliasing weights,
+  float* s_alz = s_alx + 3 * Nx;                        //      [3][kt] z aliasing weights
   const int ntk = (H + kt - 1) / kt;
   const int y = blk / ntk, kz0 = (blk - y * ntk) * kt;
   // the x and z deconvolution factors of the workgroup's points, loaded before the
@@ -528,11 +537,31 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
     const float* src = (i < Nx) ? a.dcx + i : a.dcz + min(kz0 + max(i - Nx, 0), H - 1);
     dcv[k] = *src;
   }
+  constexpr int ALU = OPT ? 13 : 1;   // 3 (Nx + kt) <= ALU blockDim
+  float alv[ALU];
+  if constexpr (OPT) {
+#pragma unroll
+    for (int k = 0; k < ALU; ++k) {
+      const int i = int(threadIdx.x) + k * int(blockDim.x);
+      const int j = max(i - 3 * Nx, 0);
+      const int m = int(fdiv(uint32_t(j), a.ktd)), l = j - m * kt;
+      const float* src = (i < 3 * Nx) ? a.alx + i
+                                      : a.alz + min(m, 2) * Nz + min(kz0 + l, H - 1);
+      alv[k] = *src;
+    }
+  }
   auto store_dc = [&]() {
 #pragma unroll
     for (int k = 0; k < DCU; ++k) {
       const int i = int(threadIdx.x) + k * int(blockDim.x);
       if (i < Nx + kt) s_dc[i] = dcv[k];
+    }
+    if constexpr (OPT) {
+#pragma unroll
+      for (int k = 0; k < ALU; ++k) {
+        const int i = int(threadIdx.x) + k * int(blockDim.x);
+        if (i < 3 * (Nx + kt)) s_alx[i] = alv[k];
+      }
     }
     __syncthreads();
   };
@@ -563,17 +592,47 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
                        2.0f * (M[0][1] * px * py + M[0][2] * px * pz + M[1][2] * py * pz);
       return 4.0f * float(M_PI) / k2 * expf(-k2 * inv4a2);
     };
+    float aly3[3] = {0.0f, 0.0f, 0.0f};
+    if constexpr (OPT) {
+#pragma unroll
+      for (int m = 0; m < 3; ++m) aly3[m] = a.aly[m * Ny + y];
+    }
     for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
       const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
       const int kz = kz0 + l;
       float g = 0.0f;
       if (kz < H && (xx | y | kz) != 0) {
         const float fx = float(signed_freq(xx, Nx)), fz = float(signed_freq(kz, Nz));
-        g = gk(fx, fy, fz);
         const bool nx = ((Nx & 1) == 0) && (2 * xx == Nx);
         const bool nz = ((Nz & 1) == 0) && (2 * kz == Nz);
-        if (nx || nyq_y || nz)   // Hermitian partner: the non-Nyquist components change sign
-          g = 0.5f * (g + gk(nx ? fx : -fx, nyq_y ? fy : -fy, nz ? fz : -fz));
+        if constexpr (OPT) {
+          // sum over the aliases f + m N of U^2 G; a partner frequency s f (s = -1 on
+          // the flipped axes) takes the weight of alias -m of f, as sinc is even
+          auto gopt = [&](int sx, int sy, int sz) {
+            float num = 0.0f;
+#pragma unroll
+            for (int mx = -1; mx <= 1; ++mx) {
+              const float ux = s_alx[(sx * mx + 1) * Nx + xx];
+#pragma unroll
+              for (int my = -1; my <= 1; ++my) {
+                const float uxy = ux * aly3[sy * my + 1];
+#pragma unroll
+                for (int mz = -1; mz <= 1; ++mz) {
+                  const float u2 = uxy * s_alz[(sz * mz + 1) * kt + l];
+                  num = fmaf(u2, gk(float(sx) * fx + float(mx * Nx), float(sy) * fy + float(my * Ny),
+                                    float(sz) * fz + float(mz * Nz)), num);
+                }
+              }
+            }
+            return num;
+          };
+          g = gopt(1, 1, 1);
+          if (nx || nyq_y || nz) g = 0.5f * (g + gopt(nx ? 1 : -1, nyq_y ? 1 : -1, nz ? 1 : -1));
+        } else {
+          g = gk(fx, fy, fz);
+          if (nx || nyq_y || nz)   // Hermitian partner: the non-Nyquist components change sign
+            g = 0.5f * (g + gk(nx ? fx : -fx, nyq_y ? fy : -fy, nz ? fz : -fz));
+        }
         g *= s_dc[xx] * dcy * s_dc[Nx + l];
       }
       s_g[l * Nx + xx] = g;
@@ -763,9 +822,9 @@ __global__ void __launch_bounds__(kSlabThreads) k_slab_inv(SlabArgs a) {
   slab_inv_body(a, blockIdx.x);
 }
 
-template <bool VIR>
+template <int MODE>
 __global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
-  fftx_body<VIR>(a, blockIdx.x, a.box, a.epart);
+  fftx_body<MODE>(a, blockIdx.x, a.box, a.epart);
 }
 
 // Batched passes: work item (box, x-plane) or (box, x-pass workgroup); per-box
@@ -812,12 +871,13 @@ XArgs make_x_args(const DevPlan& d, const double* box, bool energy) {
   x.alpha = float(d.alpha);
   x.epart = energy ? d.epart : nullptr;
   x.vpart = nullptr;
+  x.alx = d.alias[0]; x.aly = d.alias[1]; x.alz = d.alias[2];
   return x;
 }
 
 size_t x_lds(const DevPlan& d) {
   return sizeof(float2) * (d.N[0] + 2 * d.ktile * (d.N[0] + 1)) + sizeof(float) * d.N[0] * d.ktile +
-         sizeof(float) * (d.N[0] + d.ktile);
+         sizeof(float) * (d.N[0] + d.ktile) * (d.opt ? 4 : 1);
 }
 
 SlabArgs make_slab_args(const DevPlan& d, float* out) {
@@ -905,8 +965,9 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
     const SlabArgs sa = make_slab_args(d, out);
     launch_k(er, k_slab_fwd, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    if (vpart) launch_k(ex, k_fftx_fused<true>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
-    else launch_k(ex, k_fftx_fused<false>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+    if (vpart) launch_k(ex, k_fftx_fused<1>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+    else if (d.opt) launch_k(ex, k_fftx_fused<2>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+    else launch_k(ex, k_fftx_fused<0>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     launch_k(ei, k_slab_inv, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
     return hipGetLastError();
@@ -930,8 +991,9 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   launch_k(er ? &er1 : nullptr, k_ffty, dim3(ffty_blocks(d)), dim3(kFFTThreads), ysh, s, y);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
-  if (vpart) launch_k(ex, k_fftx_fused<true>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
-  else launch_k(ex, k_fftx_fused<false>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+  if (vpart) launch_k(ex, k_fftx_fused<1>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+  else if (d.opt) launch_k(ex, k_fftx_fused<2>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+  else launch_k(ex, k_fftx_fused<0>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
   y.sign = +1.0f;

@@ -90,7 +90,10 @@ struct DevPlan {
   // FFT
   AxisPlan ax[3];
   float2* twiddle[3];      // e^{-2 pi i t / N_a}, t < N_a
-  float* deconv[3];        // |sinc(f/N_a)|^{-2 gamma p}, signed f
+  float* deconv[3];        // |sinc(f/N_a)|^{-2 gamma p}, signed f; with the optimal
+                           // influence 1 / (sum_m sinc^{2p}((f + m N_a)/N_a))^2
+  bool opt;                // optimal influence function (aliasing sums)
+  float* alias[3];         // optimal influence: [3][N_a] sinc^{2p}((f + m N_a)/N_a), m = -1, 0, 1
   bool slab;               // y-z planes transformed in LDS (z and y passes fused)
   size_t slab_lds;         // dynamic LDS bytes of a slab workgroup
   int rows_per_block;      // z-pass rows per block (even)

@@ -66,7 +66,7 @@ class Plan:
 
     def __init__(self, mesh, order: int, alpha: float, max_atoms: int, influence_power: float = 1.0,
                  prefactor: float = 1.0, keep_phi: bool = True, device=None, tile=None,
-                 concurrent: bool = False):
+                 concurrent: bool = False, optimal_influence: bool = False):
         self._lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         d = _lib.PMEDesc()
@@ -74,7 +74,8 @@ class Plan:
             d.mesh[k] = int(mesh[k])
         d.order = int(order)
         d.max_atoms = int(max_atoms)
-        d.flags = (_lib.PME_F_KEEP_PHI if keep_phi else 0) | (_lib.PME_F_CONCURRENT if concurrent else 0)
+        d.flags = ((_lib.PME_F_KEEP_PHI if keep_phi else 0) | (_lib.PME_F_CONCURRENT if concurrent else 0)
+                   | (_lib.PME_F_OPT_INFLUENCE if optimal_influence else 0))
         d.alpha = float(alpha)
         d.influence_power = float(influence_power)
         d.prefactor = float(prefactor)
