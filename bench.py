@@ -135,6 +135,11 @@ def _args(argv=None):
                          "bench runs at several workloads and exit")
     ap.add_argument("--cell", type=int, default=1,
                     help="1 adds the cell-gradient leg (pme_forward_cell against pme_forward)")
+    ap.add_argument("--influence", type=int, default=1,
+                    help="1 adds the optimal-influence leg (pme_step with each influence function)")
+    ap.add_argument("--influence-compare", type=int, default=0,
+                    help="1: write the accuracy-per-mesh-point comparison of the influence "
+                         "functions against Ewald and exit")
     ap.add_argument("--batched", type=int, default=1,
                     help="1 adds the batched-graph leg (64 boxes, one HIP graph per step)")
     ap.add_argument("--learned", type=int, default=1,
@@ -159,6 +164,8 @@ def main(argv=None):
         return 2
     if args.crossover:
         return crossover()
+    if args.influence_compare:
+        return influence_compare()
     import torch
 
     import synth
@@ -264,6 +271,8 @@ def main(argv=None):
     }
     if args.cell:
         line["cell_gradient"] = cell_leg(pos, q, mu, box, mesh, p, alpha, n)
+    if args.influence:
+        line["optimal_influence"] = influence_leg(pos, q, mu, box, mesh, p, alpha, n, vr, vq, vm)
     if args.batched:
         line["batched"] = batched_leg()
     if args.learned:
@@ -321,6 +330,83 @@ def cell_leg(pos, q, mu, box, mesh, p, alpha, n, reps=50):
     return {"workload": "the benchmark box, pme_forward vs pme_forward_cell",
             "forward_ms": round(t_plain, 4), "forward_cell_ms": round(t_cell, 4),
             "overhead_ms": round(t_cell - t_plain, 4), "kernels_us": kern}
+
+
+def influence_leg(pos, q, mu, box, mesh, p, alpha, n, vr, vq, vm, reps=50):
+    """pme_step (concurrent chains) on the benchmark workload with the optimal
+    influence function against the deconvolution: median step time of each and the
+    x-pass launch duration (where the two differ)."""
+    import torch
+
+    from paper_2606_01598_amd.pme import Plan
+    res = {"workload": "the benchmark box, pme_step with each influence function"}
+    for opt in (False, True):
+        plan = Plan(mesh, p, alpha, max_atoms=n, concurrent=True, optimal_influence=opt)
+        for _ in range(10):
+            plan.step(pos, q, mu, box, vr, vq, vm)
+        plan.status()
+        t = _median_ms(lambda: plan.step(pos, q, mu, box, vr, vq, vm), reps)
+        plan.timer("fft_x")
+        for _ in range(10):
+            plan.step(pos, q, mu, box, vr, vq, vm)
+        k, ms = plan.timer_read()
+        plan.timer(None)
+        plan.status()
+        key = "optimal" if opt else "deconvolution"
+        res[f"{key}_step_ms"] = round(t, 4)
+        res[f"{key}_fft_x_us"] = round(1e3 * ms / max(k, 1), 3)
+    return res
+
+
+def influence_compare(out_path=None):
+    """Accuracy per mesh point of the two influence functions: RMS force error of the
+    GPU PME (forward) against the FP64 explicit Ewald long-range forces on the host,
+    for molten-salt boxes of 512 ions (three configurations) over meshes from 3 A to
+    1 A, p = 4 and 6, alpha = 0.45 / A.  Writes profiles/influence_accuracy_molten512.txt."""
+    import numpy as np
+    import torch
+
+    import synth
+    from oracle import ewald as oew
+    from paper_2606_01598_amd.pme import Plan
+
+    dev = torch.device("cuda", 0)
+    rows = []
+    a = 0.45
+    frames = [synth.molten_box(512, 30 + s) for s in range(3)]
+    refs = [oew.ewald_long_range(f.pos, f.q, f.mu, f.box, a)[1] for f in frames]
+    L = frames[0].box[0, 0]
+    for p in (4, 6):
+        for m in (8, 10, 12, 16, 20, 24):
+            errs = {}
+            for opt in (False, True):
+                e = []
+                for f, gref in zip(frames, refs):
+                    plan = Plan((m, m, m), p, a, max_atoms=f.n, optimal_influence=opt)
+                    t = lambda x: torch.tensor(x, dtype=torch.float32, device=dev)
+                    out = plan.forward(t(f.pos), t(f.q), t(f.mu),
+                                       torch.tensor(f.box, dtype=torch.float64, device=dev))
+                    g = out["dE_dpos"].double().cpu().numpy()
+                    e.append(float(np.sqrt(np.mean((g - gref) ** 2) / np.mean(gref ** 2))))
+                errs[opt] = float(np.mean(e))
+            rows.append((p, m, L / m, errs[False], errs[True]))
+    lines = [
+        "# Accuracy per mesh point of the influence functions: mean over 3 molten-salt",
+        "# boxes of 512 ions (L = %.2f A) of ||F_PME - F_Ewald||_rms / ||F_Ewald||_rms," % L,
+        "# F_PME from the GPU (forward), F_Ewald the FP64 explicit Ewald long-range force",
+        "# (oracle, host); alpha = 0.45 / A",
+        "# command: python -u bench.py --influence-compare 1",
+        f"# source digest of paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
+        "",
+        f"{'p':>3s} {'mesh':>5s} {'h (A)':>7s} {'deconvolution':>14s} {'optimal':>10s} {'ratio':>7s}",
+    ]
+    for p, m, h, e0, e1 in rows:
+        lines.append(f"{p:3d} {m:5d} {h:7.3f} {e0:14.3e} {e1:10.3e} {e1 / e0:7.3f}")
+    out = out_path or os.path.join(ROOT, "profiles", "influence_accuracy_molten512.txt")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(open(out).read())
+    return 0
 
 
 def batched_leg(n_boxes=64, seed=6, reps=20):
