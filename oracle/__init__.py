@@ -17,4 +17,6 @@ pme       the particle-mesh method on a given mesh (Secs. 2.3.1-2.3.5):
           Hessian-vector product
 ewald     explicit Ewald summation for charges and point dipoles (the
           conventional baseline the paper validates against, Sec. 2.3 and 3)
+quad      the quadrupole channel the paper names as its next extension
+          (Sec. 4): density, self terms, PME and Ewald energies and gradients
 """

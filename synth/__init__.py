@@ -183,6 +183,16 @@ def random_cotangents(n: int, seed: int, scale_r: float = 1.0, scale_q: float = 
             rng.normal(0, scale_mu, (n, 3)))
 
 
+def random_quadrupoles(n: int, seed: int, scale: float = 0.3, traceless: bool = False):
+    """Seeded symmetric second moments Theta, stored as (n, 6) in the order xx, yy,
+    zz, xy, xz, yz: Gaussian entries of standard deviation `scale` (e Angstrom^2)."""
+    rng = np.random.default_rng(seed)
+    th = rng.normal(0.0, scale, (n, 6))
+    if traceless:
+        th[:, :3] -= th[:, :3].mean(axis=1, keepdims=True)
+    return th
+
+
 def triclinic_cell(seed: int = 7, n: int = 8):
     """A small triclinic cell with random charges/dipoles (neutral)."""
     rng = np.random.default_rng(seed)
