@@ -154,6 +154,33 @@ int pme_forward_cell(pme_plan_t plan, void* stream, int32_t n,
                      double* energy, float* dE_dpos, float* dE_dq, float* dE_dmu,
                      double* dE_dbox);
 
+/* Charges, dipoles and quadrupoles: pme_forward with a third channel, the
+ * symmetric Cartesian second moment Theta_i of each atom (the quadrupolar PME
+ * channel that Sec. 4 names as the next extension of the method; readings:
+ * the density of atom i is q_i delta - mu_i . grad delta + (1/2) Theta_i : grad
+ * grad delta, the limit of a point-charge cluster with sum q r r^T = Theta_i, so
+ * the mesh density gains (1/2) (J Theta_i J^T) : grad_x grad_x W; the self terms
+ * extend Eqs. self_q and self_mu by the screened self-interaction of the
+ * quadrupole: + 2a^3/(3 sqrt(pi)) q tr Theta - a^5/(5 sqrt(pi)) (tr^2 Theta +
+ * 2 Theta:Theta)).  Theta need not be traceless.
+ *   theta     device float[n][6]: xx, yy, zz, xy, xz, yz (e Angstrom^2), or NULL (= 0)
+ *   energy    device double[4] or NULL: E_recip, E_self_q, E_self_mu, E_self_theta
+ *             (the last holds the q-Theta cross term); E^lr is their sum
+ *   dE_dtheta device float[n][6] or NULL: gradient with respect to the six stored
+ *             entries (an off-diagonal entry stands for both Theta_ab and Theta_ba)
+ *   other arguments and outputs as pme_forward.
+ * Needs order p >= 4 (PME_EINVAL otherwise): the density takes second
+ * derivatives of the weights, which are discontinuous for p <= 3, and the force
+ * third ones.  No
+ * Hessian-vector product, cell gradient or batch form for this channel; its
+ * potential is not kept for pme_backward.  Launches are timed under the
+ * PME_K_BIN, PME_K_SPREAD and PME_K_GATHER kinds.  Uses the plan's workspace;
+ * calls on one plan must not overlap. */
+int pme_forward_quad(pme_plan_t plan, void* stream, int32_t n,
+                     const float* pos, const float* q, const float* mu, const float* theta,
+                     const double* box, double* energy, float* dE_dpos, float* dE_dq,
+                     float* dE_dmu, float* dE_dtheta);
+
 /* Hessian-vector product of E^lr in (r, q, mu): with the gradient
  * (dE/dr, dE/dq, dE/dmu) of pme_forward and cotangents (v_pos, v_q, v_mu)
  * on it, returns H v, which equals the vector-Jacobian product of the

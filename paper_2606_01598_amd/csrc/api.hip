@@ -309,7 +309,7 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
   ok(dev_alloc(&d.spec, size_t(d.N[0]) * d.N[1] * d.H, by));
   ok(dev_alloc(&d.phi, size_t(M), by));
   ok(dev_alloc(&d.epart, size_t(pme::fftx_blocks(d)), by));
-  ok(dev_alloc(&d.spart, size_t(2 * pme::bin_blocks(desc->max_atoms)), by));
+  ok(dev_alloc(&d.spart, size_t(4 * pme::bin_blocks(desc->max_atoms)), by));
   ok(dev_alloc(&d.vpart, size_t(6 * pme::fftx_blocks(d) + 9 * d.nt[0] * d.nt[1] * d.nt[2]), by));
   ok(dev_alloc(&d.escr, 3, by));
   ok(dev_alloc(&d.status, 1, by));
@@ -460,6 +460,32 @@ int pme_forward_cell(pme_plan_t plan, void* stream, int32_t n, const float* pos,
                      float* dE_dq, float* dE_dmu, double* dE_dbox) {
   if (!dE_dbox || (plan && plan->d.opt)) return PME_EINVAL;
   return forward_impl(plan, stream, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu, dE_dbox);
+}
+
+int pme_forward_quad(pme_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
+                     const float* mu, const float* theta, const double* box, double* energy,
+                     float* dE_dpos, float* dE_dq, float* dE_dmu, float* dE_dtheta) {
+  if (!plan || n < 0 || !box || (n > 0 && !pos) || plan->d.p < 4) return PME_EINVAL;
+  if (n > plan->max_atoms) return PME_ECAPACITY;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const DevPlan& d = plan->d;
+  pme::KTimer& tm = plan->timer;
+  hipError_t e;
+  // phi of this call is not the one a following pme_backward may reuse
+  plan->phi_valid = false;
+  const int set = plan->set;
+  plan->set ^= 1;
+  if ((e = pme::launch_bin_quad(d, s, set, n, pos, q, mu, theta, box, energy != nullptr,
+                                tm.next(PME_K_BIN))) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_spread_quad(d, s, set, box, tm.next(PME_K_SPREAD))) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_gather_quad(d, s, set, n, pos, q, mu, theta, box, energy, dE_dpos, dE_dq,
+                                   dE_dmu, dE_dtheta, tm.next(PME_K_GATHER))) != hipSuccess)
+    return hip_fail(e);
+  return PME_OK;
 }
 
 int pme_backward(pme_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,

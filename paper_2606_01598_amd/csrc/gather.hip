@@ -24,6 +24,13 @@
 //     r_bar  = (1/V) J^T [q P1 + P2 d + v_q S1 + S2 w + S3(d, v, .)]
 // where P_k are the order-k derivative sums of psi, S_k those of phi,
 // d = J mu, v = J v_r, w = J (v_mu + q v_r).
+//
+// The quadrupole forward (second moments Theta, Q = J Theta J^T) adds
+//     dE/dq_i     += 2a^3/(3 sqrt(pi)) tr Theta_i
+//     dE/dTheta_i  = (1/2V) J^T S_2 J + d/dTheta [2a^3/(3 sqrt(pi)) q tr Theta
+//                    - a^5/(5 sqrt(pi)) (tr^2 Theta + 2 Theta:Theta)]
+//     dE/dr_i     += (1/V) J^T (1/2) S_3 : Q
+// (Theta gradients of the six stored entries xx yy zz xy xz yz).
 #include <vector>
 
 #include "kernels.h"
@@ -59,6 +66,12 @@ struct GArgs {
   int n_spart;
   double alpha;
   double prefactor;
+  // quadrupole forward: second moments, their gradient, the block sums of the
+  // Theta self terms (2 per binning block) and a^5 / (5 sqrt(pi))
+  const float* theta;
+  float* o_theta;
+  const double* spart_th;
+  float cth;
   // float constants of the outputs, made on the host: the prefactor, the self-term
   // factors 2 alpha / sqrt(pi) and 4 alpha^3 / (3 sqrt(pi))
   float pf, cq, cm;
@@ -94,6 +107,19 @@ __device__ void finalize_energy(const GArgs& a, const Cell& c) {
     a.energy[0] = a.prefactor * e / (2.0 * c.vol);
     a.energy[1] = -a.prefactor * a.alpha / sp * s1;
     a.energy[2] = -a.prefactor * 2.0 * a.alpha * a.alpha * a.alpha / (3.0 * sp) * s2;
+  }
+  if (a.spart_th) {
+    double s3 = 0.0, s4 = 0.0;
+    for (int k = threadIdx.x; k < a.n_spart; k += blockDim.x) {
+      s3 += a.spart_th[2 * k];
+      s4 += a.spart_th[2 * k + 1];
+    }
+    s3 = block_sum(s3, red);
+    s4 = block_sum(s4, red);
+    if (threadIdx.x == 0) {
+      const double sp = sqrt(M_PI), a3 = a.alpha * a.alpha * a.alpha;
+      a.energy[3] = a.prefactor * (2.0 * a3 / (3.0 * sp) * s3 - a3 * a.alpha * a.alpha / (5.0 * sp) * s4);
+    }
   }
 }
 
@@ -195,16 +221,18 @@ __device__ __forceinline__ RecRegs<HVP> load_rec(const float* rec, size_t ri) {
   return o;
 }
 
-template <int P, bool HVP, bool DUAL = false, bool VIR = false>
+template <int P, bool HVP, bool DUAL = false, bool VIR = false, bool QUAD = false>
 __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   extern __shared__ float sm[];
+  // records of four float4 (Hessian-vector product, quadrupole forward)
+  constexpr bool R4 = HVP || QUAD;
   // the queue holds kGatherQueue atoms; a round's compacted records beyond that are
   // processed in further chunks, reloaded from the records
   __shared__ float4 s_h[kGatherQueue];
-  __shared__ float4 s_qm[kGatherQueue];              // q, mu
-  __shared__ float4 s_v1[HVP ? kGatherQueue : 1];    // v_q, v_r
-  __shared__ float4 s_v2[HVP ? kGatherQueue : 1];    // v_mu, atom
-  __shared__ int s_atom[HVP ? 1 : kGatherQueue];     // forward
+  __shared__ float4 s_qm[kGatherQueue];              // q, mu (quadrupole: q, J mu)
+  __shared__ float4 s_v1[R4 ? kGatherQueue : 1];     // v_q, v_r (quadrupole: c_200 .. c_110)
+  __shared__ float4 s_v2[R4 ? kGatherQueue : 1];     // v_mu, atom (quadrupole: c_101 c_011 - atom)
+  __shared__ int s_atom[R4 ? 1 : kGatherQueue];      // forward
   __shared__ float4 s_sa[VIR ? kGatherQueue : 1];    // VIR: unwrapped fractional position
   __shared__ int s_n;
   __shared__ float s_coef[4 * P * P];       // pieces of N_P and their derivatives
@@ -248,13 +276,13 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   };
   auto slot_rec = [&](int e) {
     const int j = e / cap;
-    return load_rec<HVP>(a.rec, size_t(own_bin(j)) * cap + (e - j * cap));
+    return load_rec<R4>(a.rec, size_t(own_bin(j)) * cap + (e - j * cap));
   };
   // 1. records of the first 256 slots, their bins' counts and the field region in
   // flight together (nslot >= cap > 0: a tile holds whole bins; slots past the end
   // load the last one again and are not used)
   int ec = min(tid, nslot - 1);
-  RecRegs<HVP> cur = slot_rec(ec);
+  RecRegs<R4> cur = slot_rec(ec);
   int cnt = a.count[own_bin(ec / cap)];
   const int novf = *a.ovf_count;
   const int EV = E[0] * E[1] * E[2];
@@ -322,9 +350,9 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
   const int lane = tid & 63, wave = tid >> 6;
   const int gslot = lane / P, ix = lane - gslot * P;
 
-  auto put = [&](int k, const RecRegs<HVP>& r) {
+  auto put = [&](int k, const RecRegs<R4>& r) {
     s_h[k] = r.h;
-    if constexpr (HVP) {
+    if constexpr (R4) {
       s_qm[k] = r.r1;
       s_v1[k] = r.r2;
       s_v2[k] = r.r3;
@@ -335,7 +363,7 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
     }
   };
   // compacted index of a valid record (-1 otherwise); the first kGatherQueue are queued
-  auto enqueue = [&](bool valid, const RecRegs<HVP>& r) {
+  auto enqueue = [&](bool valid, const RecRegs<R4>& r) {
     const int k = wave_compact(valid, &s_n);
     if (valid && k < kGatherQueue) put(k, r);
     return k;
@@ -346,7 +374,114 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
       const bool active = (gslot < APW) && (slot < nq);
       // a wavefront with no atom in this pass skips it (its lanes would only sum zeros)
       if (__ballot(active) == 0ull) continue;
-      if (!HVP) {
+      if constexpr (QUAD) {
+        // per-lane partial sums of the lane's x-plane, summed over the atom's lanes:
+        // S_0, S_1, S_2 (200 020 002 110 101 011) and the pre-J position gradient
+        float oq = 0, og[3] = {0, 0, 0}, oh[6] = {0, 0, 0, 0, 0, 0}, op[3] = {0, 0, 0};
+        if (active) {
+          const float4 h = s_h[slot];
+          const int pk = __float_as_int(h.w);
+          const int lx = (pk & 1023) - t0[0] + ix;
+          const int yb = ((pk >> 10) & 1023) - t0[1], zb = ((pk >> 20) & 1023) - t0[2];
+          float wz[4][P], wx[4];
+          spline_weights<P, 3>(h.z, wz);
+          weight_at_lds<P, 3>(s_coef, ix, h.x, wx);
+          const float* plane = sm + (lx * E[1] + yb) * E[2] + zb;
+          float Ys[4][4];
+#pragma unroll
+          for (int y = 0; y < 4; ++y)
+#pragma unroll
+            for (int z = 0; z < 4; ++z) Ys[y][z] = 0.0f;
+#pragma unroll
+          for (int iy = 0; iy < P; ++iy) {
+            float zs[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int iz = 0; iz < P; ++iz) {
+              const float v = plane[iy * E[2] + iz];
+#pragma unroll
+              for (int k = 0; k < 4; ++k) zs[k] = fmaf(v, wz[k][iz], zs[k]);
+            }
+            float wy[4];
+            spline_weight_at<P, 3>(iy, h.y, wy);
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+              for (int k = 0; k + b < 4; ++k) Ys[b][k] = fmaf(wy[b], zs[k], Ys[b][k]);
+          }
+          // S(x, y, z) = sum W^(x) W^(y) W^(z) phi over the lane's plane, x + y + z <= 3
+          auto S = [&](int x, int y, int z) { return wx[x] * Ys[y][z]; };
+          const float4 c0 = s_qm[slot], c1 = s_v1[slot], c2 = s_v2[slot];
+          const float q = c0.x;
+          const float d[3] = {c0.y, c0.z, c0.w};
+          // second-order monomials and their coefficients (1/2) Q_aa, Q_ab
+          constexpr int mono[6][3] = {{2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+          const float cm2[6] = {c1.x, c1.y, c1.z, c1.w, c2.x, c2.y};
+          oq = S(0, 0, 0);
+#pragma unroll
+          for (int m = 0; m < 6; ++m) oh[m] = S(mono[m][0], mono[m][1], mono[m][2]);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const int e[3] = {c == 0, c == 1, c == 2};
+            og[c] = S(e[0], e[1], e[2]);
+            float v = q * og[c];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) v = fmaf(S(e[0] + (b == 0), e[1] + (b == 1), e[2] + (b == 2)), d[b], v);
+#pragma unroll
+            for (int m = 0; m < 6; ++m)
+              v = fmaf(S(mono[m][0] + e[0], mono[m][1] + e[1], mono[m][2] + e[2]), cm2[m], v);
+            op[c] = v;
+          }
+        }
+        oq = group_sum<P>(oq, ix);
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+          og[x] = group_sum<P>(og[x], ix);
+          op[x] = group_sum<P>(op[x], ix);
+        }
+#pragma unroll
+        for (int m = 0; m < 6; ++m) oh[m] = group_sum<P>(oh[m], ix);
+        if (active && ix == 0) {
+          const int i = __float_as_int(s_v2[slot].w);
+          const float q = s_qm[slot].x;
+          const float3 mu = ld3(a.mu, i);
+          float th[6] = {0, 0, 0, 0, 0, 0};
+          if (a.theta)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) th[k] = a.theta[6 * i + k];
+          const float tr = th[0] + th[1] + th[2];
+          const float c1 = 0.5f * cm, c2 = a.cth;
+          if (a.o_q) a.o_q[i] = pf * (oq * iv - cq * q + c1 * tr);
+          if (a.o_mu) {
+            const float3 g = jtmul(J, make_float3(og[0], og[1], og[2]));
+            st3(a.o_mu, i, make_float3(pf * (g.x * iv - cm * mu.x), pf * (g.y * iv - cm * mu.y),
+                                       pf * (g.z * iv - cm * mu.z)));
+          }
+          if (a.o_pos) {
+            const float3 g = jtmul(J, make_float3(op[0], op[1], op[2]));
+            st3(a.o_pos, i, make_float3(pf * iv * g.x, pf * iv * g.y, pf * iv * g.z));
+          }
+          if (a.o_theta) {
+            // G = (1/2V) J^T H J with H the symmetric matrix of the second-order sums
+            const float H[3][3] = {{oh[0], oh[3], oh[4]}, {oh[3], oh[1], oh[5]}, {oh[4], oh[5], oh[2]}};
+            float HJ[3][3];
+#pragma unroll
+            for (int x = 0; x < 3; ++x)
+#pragma unroll
+              for (int b = 0; b < 3; ++b) HJ[x][b] = H[x][0] * J[0][b] + H[x][1] * J[1][b] + H[x][2] * J[2][b];
+            auto G = [&](int u, int b) {
+              return 0.5f * iv * (J[0][u] * HJ[0][b] + J[1][u] * HJ[1][b] + J[2][u] * HJ[2][b]);
+            };
+            const float sd = c1 * q - 2.0f * c2 * tr;
+            float* o = a.o_theta + 6 * i;
+            o[0] = pf * (G(0, 0) + sd - 4.0f * c2 * th[0]);
+            o[1] = pf * (G(1, 1) + sd - 4.0f * c2 * th[1]);
+            o[2] = pf * (G(2, 2) + sd - 4.0f * c2 * th[2]);
+            o[3] = pf * (2.0f * G(0, 1) - 8.0f * c2 * th[3]);
+            o[4] = pf * (2.0f * G(0, 2) - 8.0f * c2 * th[4]);
+            o[5] = pf * (2.0f * G(1, 2) - 8.0f * c2 * th[5]);
+          }
+        }
+      } else if (!HVP) {
         // per-lane partial outputs (linear in the phi sums), summed over the atom's
         // lanes: dE/dq, the pre-J dipole gradient G, the pre-J position gradient
         float oq = 0, og[3] = {0, 0, 0}, op[3] = {0, 0, 0};
@@ -607,7 +742,7 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
     process(min(nv, kGatherQueue));
     for (int c0 = kGatherQueue; c0 < nv; c0 += kGatherQueue) {
       __syncthreads();   // the queue has been read
-      if (k >= c0 && k < c0 + kGatherQueue) put(k - c0, load_rec<HVP>(a.rec, ri));
+      if (k >= c0 && k < c0 + kGatherQueue) put(k - c0, load_rec<R4>(a.rec, ri));
       __syncthreads();
       process(min(kGatherQueue, nv - c0));
     }
@@ -623,7 +758,7 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
     __syncthreads();   // the queue has been read
     if (tid == 0) s_n = 0;
     bool valid = false;
-    RecRegs<HVP> rec;
+    RecRegs<R4> rec;
     if (r < nrs) {
       const int e = r * 256 + tid;
       ec = min(e, nslot - 1);
@@ -635,7 +770,7 @@ __device__ __forceinline__ void gather_tile(const GArgs& a, const int tile) {
       const int o = (r - nrs) * 256 + tid;
       if (o < novf) {
         rq = uint32_t(a.ovf_base + o);
-        rec = load_rec<HVP>(a.rec, rq);
+        rec = load_rec<R4>(a.rec, rq);
         const int pk = __float_as_int(rec.h.w);
         const int b0 = pk & 1023, b1 = (pk >> 10) & 1023, b2 = (pk >> 20) & 1023;
         valid = b0 >= t0[0] && b0 < t0[0] + T[0] && b1 >= t0[1] && b1 < t0[1] + T[1] &&
@@ -709,6 +844,12 @@ template <int P, bool DUAL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 3 : 4)))
 k_gather_hvp(GArgs a) {
   gather_hvp_body<P, DUAL>(a, blockIdx.x);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 3 : 4)))
+k_gather_quad(GArgs a) {
+  gather_tile<P, false, false, false, true>(a, blockIdx.x);
 }
 
 // Batched gathers: work item (box, tile), per-box argument templates completed
@@ -805,6 +946,7 @@ hipError_t enable_gather_lds() {
       reinterpret_cast<const void*>(k_gather<P, true>),                                     \
       reinterpret_cast<const void*>(k_gather_hvp<P, false>),                                \
       reinterpret_cast<const void*>(k_gather_hvp<P, true>),                                 \
+      reinterpret_cast<const void*>(k_gather_quad<P>),                                      \
       reinterpret_cast<const void*>(k_gather_batch<P, false>),                               \
       reinterpret_cast<const void*>(k_gather_batch<P, true>),
       PME_G(1) PME_G(2) PME_G(3) PME_G(4) PME_G(5) PME_G(6) PME_G(7)
@@ -875,6 +1017,32 @@ hipError_t launch_gather(const DevPlan& d, hipStream_t s, int set, int n, const 
   a.vpart = vpart;
   return gather_dispatch<false>(d.p, dim3(d.nt[0] * d.nt[1] * d.nt[2]), region_bytes(d, 1), s, a,
                                 ev);
+}
+
+hipError_t launch_gather_quad(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
+                              const float* q, const float* mu, const float* theta,
+                              const double* box, double* energy, float* dE_dpos, float* dE_dq,
+                              float* dE_dmu, float* dE_dtheta, const LaunchEvents* ev) {
+  GArgs a = base_args(d, set, n, pos, q, mu, box);
+  a.theta = theta;
+  a.o_pos = dE_dpos; a.o_q = dE_dq; a.o_mu = dE_dmu; a.o_theta = dE_dtheta;
+  a.energy = energy; a.epart = d.epart; a.n_epart = fftx_blocks(d);
+  a.spart = d.spart; a.n_spart = bin_blocks(n);
+  a.spart_th = energy ? d.spart + 2 * bin_blocks(n) : nullptr;
+  a.cth = float(pow(d.alpha, 5) / (5.0 * sqrt(M_PI)));
+  const dim3 g(d.nt[0] * d.nt[1] * d.nt[2]);
+  const size_t sh = region_bytes(d, 1);
+  switch (d.p) {
+    case 1: launch_k(ev, k_gather_quad<1>, g, dim3(256), sh, s, a); break;
+    case 2: launch_k(ev, k_gather_quad<2>, g, dim3(256), sh, s, a); break;
+    case 3: launch_k(ev, k_gather_quad<3>, g, dim3(256), sh, s, a); break;
+    case 4: launch_k(ev, k_gather_quad<4>, g, dim3(256), sh, s, a); break;
+    case 5: launch_k(ev, k_gather_quad<5>, g, dim3(256), sh, s, a); break;
+    case 6: launch_k(ev, k_gather_quad<6>, g, dim3(256), sh, s, a); break;
+    case 7: launch_k(ev, k_gather_quad<7>, g, dim3(256), sh, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_cell_grad(const DevPlan& d, hipStream_t s, const double* box,

@@ -104,7 +104,8 @@ struct DevPlan {
   float* phi;              // [M]
   // reductions
   double* epart;           // [x-pass blocks]
-  double* spart;           // [2 * bin blocks]
+  double* spart;           // [4 * bin blocks]: q^2, |mu|^2 per block (then, quadrupole
+                           // forward: q tr Theta, tr^2 Theta + 2 Theta:Theta)
   double* vpart;           // cell gradient: [6 per x-pass block] then [9 per tile]
   double* escr;            // [3] energy of a cell-gradient call that asks for none
   int* status;             // bit 0: non-finite input seen
@@ -224,6 +225,20 @@ hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const flo
 // Owner-computes spread of the binned records (counter set `set`) into d.rho.
 hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
                          const double* box, const LaunchEvents* ev);
+// Quadrupole forward: binning with the ten coefficients of q, J mu and
+// (1/2) J Theta J^T in the records (self sums of Theta after the 2 n_blocks of q, mu),
+// and their spread into d.rho.
+hipError_t launch_bin_quad(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
+                           const float* q, const float* mu, const float* theta, const double* box,
+                           bool self_sums, const LaunchEvents* ev);
+hipError_t launch_spread_quad(const DevPlan& d, hipStream_t s, int set, const double* box,
+                              const LaunchEvents* ev);
+// Quadrupole forward gather: E^lr (energy[0..3]: recip, self q, self mu, self Theta)
+// and its gradients in r, q, mu and the six stored Theta entries.
+hipError_t launch_gather_quad(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
+                              const float* q, const float* mu, const float* theta,
+                              const double* box, double* energy, float* dE_dpos, float* dE_dq,
+                              float* dE_dmu, float* dE_dtheta, const LaunchEvents* ev);
 // rho -> spec -> (x g) -> out, the mesh operator K; energy partials when wanted, and
 // with vpart the six k-space partials of the cell gradient per x-pass workgroup.
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,

@@ -6,7 +6,8 @@
 //    anchor b and offset f (Sec. 2.3.2), and the monomial coefficients of what it
 //    assigns, c_abc, such that the value it adds at stencil point (i, j, k) is
 //        sum_abc c_abc W_x^(a)[i] W_y^(b)[j] W_z^(c)[k]
-//    (forward: c_000 = q, c_100..c_001 = N_a (mu . C^-1[:,a]); tangent: degree <= 2).
+//    (forward: c_000 = q, c_100..c_001 = N_a (mu . C^-1[:,a]); tangent and the
+//    quadrupole forward: degree <= 2).
 //    It files a 16-word record into a fixed-capacity bin of B_x x B_y x B_z anchors
 //    (overflow goes to a list), reduces the largest coefficient sum (the fixed-point
 //    scale of the spread) and, for the forward, block partial sums of q^2 and |mu|^2
@@ -22,6 +23,8 @@
 //
 // Record layout (16 words): f_x f_y f_z anchor | forward: q d_x d_y d_z, tangent: q mu |
 // forward: mu -, tangent: v_q v_r | forward: s (= r C^-1, unwrapped) atom, tangent: v_mu atom.
+// Quadrupole forward: f anchor | q d | c_200 c_020 c_002 c_110 | c_101 c_011 - atom, the
+// second-order coefficients those of (1/2) Q : grad_x grad_x W with Q = J Theta J^T.
 #include <vector>
 
 #include "kernels.h"
@@ -39,6 +42,7 @@ struct BinArgs {
   const float* v_pos;
   const float* v_q;
   const float* v_mu;
+  const float* theta;  // quadrupole forward: second moments (xx yy zz xy xz yz)
   int N[3];
   int B[3];
   int nb[3];
@@ -53,6 +57,7 @@ struct BinArgs {
   float* rec;
   long long ovf_base;      // record index of the overflow list
   double* spart;
+  double* spart_th;    // quadrupole forward: block sums of q tr(Theta), tr^2 + 2 Theta:Theta
   int* status;
   int nblk;            // workgroups of this binning (bin_blocks(n))
   int off;             // batches: offset of the box's atoms in the packed arrays
@@ -86,7 +91,22 @@ __device__ __forceinline__ void tangent_coeffs(const float (&J)[3][3], float q, 
   co[9] = d.y * v.z + d.z * v.y;
 }
 
-template <int P, bool TANGENT>
+// Second-order coefficients of the quadrupole density (1/2) Q : grad_x grad_x W,
+// Q = J Theta J^T: monomials 200, 020, 002 take Q_aa / 2, 110, 101, 011 take Q_ab.
+__device__ __forceinline__ void quad_coeffs(const float (&J)[3][3], const float (&th)[6],
+                                            float* co) {
+  const float T[3][3] = {{th[0], th[3], th[4]}, {th[3], th[1], th[5]}, {th[4], th[5], th[2]}};
+  float JT[3][3];   // J Theta
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) JT[a][b] = J[a][0] * T[0][b] + J[a][1] * T[1][b] + J[a][2] * T[2][b];
+  auto Q = [&](int a, int b) { return JT[a][0] * J[b][0] + JT[a][1] * J[b][1] + JT[a][2] * J[b][2]; };
+  co[0] = 0.5f * Q(0, 0); co[1] = 0.5f * Q(1, 1); co[2] = 0.5f * Q(2, 2);
+  co[3] = Q(0, 1); co[4] = Q(0, 2); co[5] = Q(1, 2);
+}
+
+template <int P, bool TANGENT, bool QUAD = false>
 __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
   __shared__ double red[8];
   __shared__ unsigned s_cmax;
@@ -100,7 +120,7 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
   __syncthreads();
   const int i = blk * 256 + threadIdx.x;
   const Cell c = cell_from_box(a.box);
-  double sq = 0.0, smu = 0.0;
+  double sq = 0.0, smu = 0.0, sqt = 0.0, stt = 0.0;
   if (i < a.n) {
     int base[3];
     float f[3];
@@ -109,6 +129,15 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
     const float3 mu = ld3(a.mu, i);
     sq = double(q) * q;
     smu = double(mu.x) * mu.x + double(mu.y) * mu.y + double(mu.z) * mu.z;
+    float th[6] = {0, 0, 0, 0, 0, 0};
+    if (QUAD && a.theta) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) th[k] = a.theta[6 * i + k];
+      const double tr = double(th[0]) + th[1] + th[2];
+      sqt = double(q) * tr;
+      stt = tr * tr + 2.0 * (double(th[0]) * th[0] + double(th[1]) * th[1] + double(th[2]) * th[2]) +
+            4.0 * (double(th[3]) * th[3] + double(th[4]) * th[4] + double(th[5]) * th[5]);
+    }
     if (!ok) {
       atomicOr(a.status, 1);
     } else {
@@ -118,10 +147,11 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
       float co[10];
       if (!TANGENT) {
         co[0] = q; co[1] = d.x; co[2] = d.y; co[3] = d.z;
+        if (QUAD) quad_coeffs(J, th, co + 4);
       } else {
         tangent_coeffs(J, q, mu, a.v_q ? a.v_q[i] : 0.0f, ld3(a.v_pos, i), ld3(a.v_mu, i), co);
       }
-      constexpr int nc = TANGENT ? 10 : 4;
+      constexpr int nc = (TANGENT || QUAD) ? 10 : 4;
       float amax = 0.0f;
 #pragma unroll
       for (int k = 0; k < nc; ++k) amax += fabsf(co[k]);
@@ -145,6 +175,10 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
         d4[1] = make_float4(q, mu.x, mu.y, mu.z);
         d4[2] = make_float4(vq, vr.x, vr.y, vr.z);
         d4[3] = make_float4(vm.x, vm.y, vm.z, __int_as_float(i));
+      } else if (QUAD) {
+        d4[1] = make_float4(co[0], co[1], co[2], co[3]);
+        d4[2] = make_float4(co[4], co[5], co[6], co[7]);
+        d4[3] = make_float4(co[8], co[9], 0.0f, __int_as_float(i));
       } else {
         // and the unwrapped fractional position r C^-1 (its image matters to the
         // cell gradient, which the forward gather forms when asked)
@@ -168,12 +202,20 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
       a.spart[2 * blk] = s1;
       a.spart[2 * blk + 1] = s2;
     }
+    if (QUAD && a.spart_th) {
+      const double s3 = block_sum(sqt, red);
+      const double s4 = block_sum(stt, red);
+      if (threadIdx.x == 0) {
+        a.spart_th[2 * blk] = s3;
+        a.spart_th[2 * blk + 1] = s4;
+      }
+    }
   }
 }
 
-template <int P, bool TANGENT>
+template <int P, bool TANGENT, bool QUAD = false>
 __global__ void __launch_bounds__(256) k_bin(BinArgs a) {
-  bin_body<P, TANGENT>(a, blockIdx.x);
+  bin_body<P, TANGENT, QUAD>(a, blockIdx.x);
 }
 
 // Batched binning: work item (box, workgroup of the box), per-box argument
@@ -312,10 +354,12 @@ __device__ __forceinline__ unsigned long long to_fixed(float v) {
 template <int P, int DEG>
 __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_id,
                                             const double* box) {
+  // DEG 1: forward (q, mu); 2: tangent density; 3: quadrupole forward (the
+  // coefficients of degree <= 2 come with the record)
   constexpr int NC = (DEG == 1) ? 4 : 10;
-  constexpr int D = DEG;                      // highest weight derivative needed
+  constexpr int D = (DEG == 1) ? 1 : 2;       // highest weight derivative needed
   constexpr int NW = 3 * (D + 1) * P;         // weights w[axis][d][j]
-  constexpr int ES = spread_entry_words(P, DEG);
+  constexpr int ES = spread_entry_words(P, D);
   constexpr int lo = (P - 1) / 2;
   const int CH = a.ch;                        // records staged per round
   // dynamic LDS, sized by the host (spread_lds_bytes): the fixed-point tile, the
@@ -507,7 +551,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
           ent[NW + NC + 2 * ax + 1] = __int_as_float(lw[ax][1]);
         }
         ent[NW + NC + 6] = h.x; ent[NW + NC + 7] = h.y; ent[NW + NC + 8] = h.z;
-        if (NC == 10) {
+        if (DEG == 2) {
           // tangent records carry q, mu, v_q, v_r, v_mu
           float co[10];
           float Jt[3][3];
@@ -517,6 +561,11 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
                          make_float3(c1v.y, c1v.z, c1v.w), make_float3(c2v.x, c2v.y, c2v.z), co);
 #pragma unroll
           for (int k = 0; k < 10; ++k) ent[NW + k] = co[k];
+        } else if (DEG == 3) {
+          // quadrupole records carry the ten coefficients
+          ent[NW + 0] = c0v.x; ent[NW + 1] = c0v.y; ent[NW + 2] = c0v.z; ent[NW + 3] = c0v.w;
+          ent[NW + 4] = c1v.x; ent[NW + 5] = c1v.y; ent[NW + 6] = c1v.z; ent[NW + 7] = c1v.w;
+          ent[NW + 8] = c2v.x; ent[NW + 9] = c2v.y;
         } else {
           ent[NW + 0] = c0v.x; ent[NW + 1] = c0v.y; ent[NW + 2] = c0v.z; ent[NW + 3] = c0v.w;
         }
@@ -595,7 +644,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
           if (ly < 0) continue;
           const float y0 = ent[(D + 1) * P + iy], y1 = ent[(D + 1) * P + P + iy];
           float c0 = ax0 * y0 + ay1 * y1, c1 = az1 * y0, c2 = 0.f;
-          if (DEG == 2) {
+          if (D == 2) {
             const float y2 = ent[(D + 1) * P + 2 * P + iy];
             c0 += ay2 * y2;
             c1 += ayz * y1;
@@ -605,7 +654,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
 #pragma unroll
           for (int iz = 0; iz < P; ++iz) {
             float v = c0 * wz[0][iz] + c1 * wz[1][iz];
-            if (DEG == 2) v += c2 * wz[2][iz];
+            if (D == 2) v += c2 * wz[2][iz];
             atomicAdd(row + zi[iz], to_fixed(v));
           }
         }
@@ -653,16 +702,16 @@ k_spread_batch(const SpreadArgs* args, const int2* items, int nitems, const doub
   }
 }
 
-template <bool TANGENT>
+template <bool TANGENT, bool QUAD = false>
 hipError_t bin_dispatch(int p, dim3 g, hipStream_t s, const BinArgs& a, const LaunchEvents* ev) {
   switch (p) {
-    case 1: launch_k(ev, k_bin<1, TANGENT>, g, dim3(256), 0, s, a); break;
-    case 2: launch_k(ev, k_bin<2, TANGENT>, g, dim3(256), 0, s, a); break;
-    case 3: launch_k(ev, k_bin<3, TANGENT>, g, dim3(256), 0, s, a); break;
-    case 4: launch_k(ev, k_bin<4, TANGENT>, g, dim3(256), 0, s, a); break;
-    case 5: launch_k(ev, k_bin<5, TANGENT>, g, dim3(256), 0, s, a); break;
-    case 6: launch_k(ev, k_bin<6, TANGENT>, g, dim3(256), 0, s, a); break;
-    case 7: launch_k(ev, k_bin<7, TANGENT>, g, dim3(256), 0, s, a); break;
+    case 1: launch_k(ev, k_bin<1, TANGENT, QUAD>, g, dim3(256), 0, s, a); break;
+    case 2: launch_k(ev, k_bin<2, TANGENT, QUAD>, g, dim3(256), 0, s, a); break;
+    case 3: launch_k(ev, k_bin<3, TANGENT, QUAD>, g, dim3(256), 0, s, a); break;
+    case 4: launch_k(ev, k_bin<4, TANGENT, QUAD>, g, dim3(256), 0, s, a); break;
+    case 5: launch_k(ev, k_bin<5, TANGENT, QUAD>, g, dim3(256), 0, s, a); break;
+    case 6: launch_k(ev, k_bin<6, TANGENT, QUAD>, g, dim3(256), 0, s, a); break;
+    case 7: launch_k(ev, k_bin<7, TANGENT, QUAD>, g, dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -694,6 +743,8 @@ BinArgs make_bin_args(const DevPlan& d, int set, int n, const float* pos, const 
   BinArgs a;
   a.n = n; a.pos = pos; a.q = q; a.mu = mu; a.box = box;
   a.v_pos = v_pos; a.v_q = v_q; a.v_mu = v_mu;
+  a.theta = nullptr;
+  a.spart_th = nullptr;
   for (int k = 0; k < 3; ++k) { a.N[k] = d.N[k]; a.B[k] = d.B[k]; a.nb[k] = d.nb[k]; }
   a.cap = d.cap;
   a.count = d.count[set]; a.ovf_count = d.ovf_count[set]; a.cmax = d.cmax[set];
@@ -771,6 +822,7 @@ hipError_t enable_spread_lds() {
   const void* fns[] = {
 #define PME_S(P)                                                               \
   reinterpret_cast<const void*>(k_spread<P, 1>), reinterpret_cast<const void*>(k_spread<P, 2>), \
+      reinterpret_cast<const void*>(k_spread<P, 3>),                           \
       reinterpret_cast<const void*>(k_spread_batch<P, 1>),                     \
       reinterpret_cast<const void*>(k_spread_batch<P, 2>),
       PME_S(1) PME_S(2) PME_S(3) PME_S(4) PME_S(5) PME_S(6) PME_S(7)
@@ -797,6 +849,23 @@ hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const flo
   const BinArgs a = make_bin_args(d, set, n, pos, q, mu, box, v_pos, v_q, v_mu, self_sums);
   const dim3 g(bin_blocks(n));
   return tangent ? bin_dispatch<true>(d.p, g, s, a, ev) : bin_dispatch<false>(d.p, g, s, a, ev);
+}
+
+hipError_t launch_bin_quad(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
+                           const float* q, const float* mu, const float* theta, const double* box,
+                           bool self_sums, const LaunchEvents* ev) {
+  BinArgs a = make_bin_args(d, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, self_sums);
+  a.theta = theta;
+  a.spart_th = self_sums ? d.spart + 2 * bin_blocks(n) : nullptr;
+  return bin_dispatch<false, true>(d.p, dim3(bin_blocks(n)), s, a, ev);
+}
+
+hipError_t launch_spread_quad(const DevPlan& d, hipStream_t s, int set, const double* box,
+                              const LaunchEvents* ev) {
+  // the entries of the tangent spread (coefficients of degree <= 2)
+  const SpreadArgs a = make_spread_args(d, set, true);
+  const size_t sh = spread_lds(d, true);
+  return spread_dispatch<3>(d.p, dim3(d.nt[0] * d.nt[1] * d.nt[2]), sh, s, a, box, ev);
 }
 
 hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,

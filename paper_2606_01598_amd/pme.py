@@ -116,14 +116,24 @@ class Plan:
         return n
 
     def forward(self, pos, q, mu, box, energy=True, dE_dpos=True, dE_dq=True, dE_dmu=True,
-                out=None, cell=False):
+                out=None, cell=False, theta=None):
         """pme_forward.  Returns dict(energy (3,) f64, dE_dpos, dE_dq, dE_dmu) of the
         requested outputs; ``out`` may supply preallocated tensors with those keys.
         With ``cell=True`` (pme_forward_cell) also dE_dbox (3, 3) f64, the gradient of
-        E^lr with respect to the cell at fixed Cartesian positions."""
+        E^lr with respect to the cell at fixed Cartesian positions.  With ``theta``
+        (n, 6) float32 second moments (xx yy zz xy xz yz; pme_forward_quad) the energy
+        has a fourth entry, the Theta self term, and dE_dtheta (n, 6) is added."""
         n = self._check_common(pos, q, mu, box)
         out = {} if out is None else dict(out)
         dev = self.device
+        if theta is not None:
+            if cell:
+                raise ValueError("no cell gradient with quadrupoles")
+            _atoms("theta", theta, n, 6, dev)
+            if energy and "energy" not in out:
+                out["energy"] = torch.empty(4, dtype=torch.float64, device=dev)
+            if "dE_dtheta" not in out:
+                out["dE_dtheta"] = torch.empty(n, 6, dtype=torch.float32, device=dev)
         if cell and "dE_dbox" not in out:
             out["dE_dbox"] = torch.empty(3, 3, dtype=torch.float64, device=dev)
         if energy and "energy" not in out:
@@ -137,7 +147,12 @@ class Plan:
         args = (self.handle, _stream(), n, _ptr(pos), _ptr(q), _ptr(mu), _ptr(box),
                 _ptr(out.get("energy")), _ptr(out.get("dE_dpos")), _ptr(out.get("dE_dq")),
                 _ptr(out.get("dE_dmu")))
-        if cell:
+        if theta is not None:
+            rc = self._lib.pme_forward_quad(self.handle, _stream(), n, _ptr(pos), _ptr(q), _ptr(mu),
+                                            _ptr(theta), _ptr(box), _ptr(out.get("energy")),
+                                            _ptr(out.get("dE_dpos")), _ptr(out.get("dE_dq")),
+                                            _ptr(out.get("dE_dmu")), _ptr(out.get("dE_dtheta")))
+        elif cell:
             rc = self._lib.pme_forward_cell(*args, _ptr(out["dE_dbox"]))
         else:
             rc = self._lib.pme_forward(*args)
