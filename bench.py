@@ -137,6 +137,8 @@ def _args(argv=None):
                     help="1 adds the cell-gradient leg (pme_forward_cell against pme_forward)")
     ap.add_argument("--influence", type=int, default=1,
                     help="1 adds the optimal-influence leg (pme_step with each influence function)")
+    ap.add_argument("--quad", type=int, default=1,
+                    help="1 adds the quadrupole leg (pme_forward_quad against pme_forward)")
     ap.add_argument("--influence-compare", type=int, default=0,
                     help="1: write the accuracy-per-mesh-point comparison of the influence "
                          "functions against Ewald and exit")
@@ -273,6 +275,8 @@ def main(argv=None):
         line["cell_gradient"] = cell_leg(pos, q, mu, box, mesh, p, alpha, n)
     if args.influence:
         line["optimal_influence"] = influence_leg(pos, q, mu, box, mesh, p, alpha, n, vr, vq, vm)
+    if args.quad:
+        line["quadrupole"] = quad_leg(pos, q, mu, box, mesh, p, alpha, n)
     if args.batched:
         line["batched"] = batched_leg()
     if args.learned:
@@ -330,6 +334,48 @@ def cell_leg(pos, q, mu, box, mesh, p, alpha, n, reps=50):
     return {"workload": "the benchmark box, pme_forward vs pme_forward_cell",
             "forward_ms": round(t_plain, 4), "forward_cell_ms": round(t_cell, 4),
             "overhead_ms": round(t_cell - t_plain, 4), "kernels_us": kern}
+
+
+def quad_leg(pos, q, mu, box, mesh, p, alpha, n, reps=50):
+    """The quadrupole channel (pme_forward_quad) on the benchmark workload with seeded
+    second moments: the forward call with and without it, median of ``reps`` timed
+    calls each (inputs resident in HBM), and the launch-timer durations of the
+    binning, spread and gather variants it uses."""
+    import torch
+
+    import synth
+    from paper_2606_01598_amd.pme import Plan
+    plan = Plan(mesh, p, alpha, max_atoms=n)
+    dev = pos.device
+    th = torch.tensor(synth.random_quadrupoles(n, 27), dtype=torch.float32, device=dev)
+    fo = {"energy": torch.empty(4, dtype=torch.float64, device=dev),
+          "dE_dpos": torch.empty(n, 3, device=dev), "dE_dq": torch.empty(n, device=dev),
+          "dE_dmu": torch.empty(n, 3, device=dev), "dE_dtheta": torch.empty(n, 6, device=dev)}
+    plain = {k: v for k, v in fo.items() if k not in ("dE_dtheta", "energy")}
+    plain["energy"] = torch.empty(3, dtype=torch.float64, device=dev)
+    for _ in range(10):
+        plan.forward(pos, q, mu, box, out=plain)
+        plan.forward(pos, q, mu, box, out=fo, theta=th)
+    plan.status()
+    t_plain = _median_ms(lambda: plan.forward(pos, q, mu, box, out=plain), reps)
+    t_quad = _median_ms(lambda: plan.forward(pos, q, mu, box, out=fo, theta=th), reps)
+    kern = {}
+    for kind in ("bin", "spread", "gather"):
+        for quad in (False, True):
+            plan.timer(kind)
+            for _ in range(10):
+                if quad:
+                    plan.forward(pos, q, mu, box, out=fo, theta=th)
+                else:
+                    plan.forward(pos, q, mu, box, out=plain)
+            k, ms = plan.timer_read()
+            kern[f"{kind}{'_quad' if quad else ''}"] = round(1e3 * ms / max(k, 1), 3)
+    plan.timer(None)
+    plan.status()
+    return {"workload": "the benchmark box with seeded second moments Theta, pme_forward vs "
+                        "pme_forward_quad",
+            "forward_ms": round(t_plain, 4), "forward_quad_ms": round(t_quad, 4),
+            "quad_atom_steps_per_s": round(n / (t_quad * 1e-3), 1), "kernels_us": kern}
 
 
 def influence_leg(pos, q, mu, box, mesh, p, alpha, n, vr, vq, vm, reps=50):
