@@ -118,6 +118,9 @@ def _args(argv=None):
     ap.add_argument("--sequential", type=int, default=0,
                     help="1: pme_forward then pme_backward on one stream instead of pme_step "
                          "with the cotangent chain on a second stream")
+    ap.add_argument("--graph", type=int, default=1,
+                    help="1: the timed steps are captured into one HIP graph (pme_step_capture) "
+                         "and replayed once, after one untimed replay; 0: eager calls")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="1 also runs a device copy of 256 MiB (byte-counter calibration)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -218,7 +221,8 @@ def main(argv=None):
     dominant = max((k for k in per_step_us if alg_bytes(k, n, m, not args.sequential) > 0),
                    key=lambda k: per_step_us[k])
 
-    # timed region; the dominant kernel's launches are bracketed by HIP events
+    # eager timed region: K steps, the dominant kernel's launches bracketed by HIP events
+    args.steps += args.steps % 2          # the graph needs an even count (set parity)
     plan.timer(dominant)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -227,6 +231,18 @@ def main(argv=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     launches, dom_ms = plan.timer_read()
+    plan.timer(None)
+    eager_ms = (t1 - t0) * 1e3 / args.steps
+    if args.graph:
+        # the same K steps captured into one HIP graph (launches in a graph cannot be
+        # timed by events here): one untimed replay, then the timed one
+        plan.step_capture(args.steps, pos, q, mu, box, vr, vq, vm, out=so)
+        plan.step_replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.step_replay()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     plan.timer(None)
     plan.status()
     ms = (t1 - t0) * 1e3 / args.steps
@@ -261,7 +277,12 @@ def main(argv=None):
                                f"p={p}, alpha={alpha}, forward + Hessian-vector product",
                    "atoms": n, "mesh": list(mesh), "order": p, "alpha": alpha,
                    "call": "pme_forward; pme_backward" if args.sequential else
-                           "pme_step (cotangent chain on a second stream)"},
+                           "pme_step (cotangent chain on a second stream)",
+                   "launch": ("the timed steps captured into one HIP graph (pme_step_capture), "
+                              "replayed once" if args.graph else "eager calls")},
+        "eager": {"ms_per_step": round(eager_ms, 6), "value": round(n / eager_ms / 1e3, 3),
+                  "note": "the same K steps as eager calls, timed just before; the roofline "
+                          "launch durations are timed over this pass"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
                      "traffic": traffic, "kernel": kernel_symbol(dominant, not args.sequential),

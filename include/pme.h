@@ -212,6 +212,32 @@ int pme_step(pme_plan_t plan, void* stream, int32_t n,
              const float* v_pos, const float* v_q, const float* v_mu,
              float* g_pos, float* g_q, float* g_mu);
 
+/* Capture `steps` consecutive pme_step calls with these arguments into a HIP
+ * graph held by the plan (replacing any earlier one), without running them;
+ * pme_step_replay launches it.  Replaying costs one launch instead of about ten
+ * per step (the per-step launch overhead and the gaps between dependent kernels
+ * shrink), and gives the same results bit for bit as the eager calls.
+ * The pointers are baked into the graph: the caller keeps those buffers alive
+ * and updates their contents in place between replays.  Each binning alternates
+ * between two counter sets, so the captured steps must leave the plan's set
+ * parity unchanged (with PME_F_CONCURRENT an even `steps`; PME_EINVAL
+ * otherwise), and a replay requires the calls made on the plan since the
+ * capture (or the last replay) to have done the same (PME_EINVAL otherwise; one
+ * more eager call restores it).  Launches captured into the graph are not
+ * timed by pme_plan_timer.
+ * Returns PME_OK, PME_EINVAL, PME_ECAPACITY, or PME_EHIP (capture or
+ * instantiation failed). */
+int pme_step_capture(pme_plan_t plan, int32_t steps, int32_t n,
+                     const float* pos, const float* q, const float* mu, const double* box,
+                     double* energy, float* dE_dpos, float* dE_dq, float* dE_dmu,
+                     const float* v_pos, const float* v_q, const float* v_mu,
+                     float* g_pos, float* g_q, float* g_mu);
+
+/* Launch the captured step graph on `stream` (ordered like any other work on
+ * it).  PME_EINVAL without a graph or when the counter-set parity differs from
+ * the capture's. */
+int pme_step_replay(pme_plan_t plan, void* stream);
+
 /* Synchronise `stream`, then return PME_ENONFINITE if any kernel of this plan
  * saw a non-finite position or box since the last pme_status call, or
  * PME_EHIP if the stream reported an error; else PME_OK.  Clears the flag. */

@@ -32,7 +32,7 @@ PME_MESH_CEIL = 2
 
 # every symbol include/pme.h declares
 EXPORTS = ("pme_mesh_dims", "pme_plan_create", "pme_plan_destroy", "pme_plan_workspace_bytes",
-           "pme_forward", "pme_forward_cell", "pme_forward_quad", "pme_backward", "pme_step", "pme_status", "pme_strerror", "pme_last_hip_error",
+           "pme_forward", "pme_forward_cell", "pme_forward_quad", "pme_backward", "pme_step", "pme_step_capture", "pme_step_replay", "pme_status", "pme_strerror", "pme_last_hip_error",
            "pme_plan_phi", "pme_plan_rho", "pme_plan_timer", "pme_plan_timer_read",
            "pol_plan_create", "pol_plan_destroy", "pol_real", "pol_real_mixed", "pol_model",
            "pol_scf", "dip_plan_create", "dip_plan_destroy", "dip_features", "dip_forward",
@@ -121,6 +121,10 @@ def load():
     lib.pme_backward.restype = ctypes.c_int
     lib.pme_step.argtypes = [vp, vp, i32] + [vp] * 14
     lib.pme_step.restype = ctypes.c_int
+    lib.pme_step_capture.argtypes = [vp, i32, i32] + [vp] * 14
+    lib.pme_step_capture.restype = ctypes.c_int
+    lib.pme_step_replay.argtypes = [vp, vp]
+    lib.pme_step_replay.restype = ctypes.c_int
     lib.pme_status.argtypes = [vp, vp]
     lib.pme_status.restype = ctypes.c_int
     lib.pme_strerror.argtypes = [ctypes.c_int]

@@ -31,6 +31,12 @@ struct pme_plan_s {
   hipStream_t aux = nullptr;
   hipEvent_t fork = nullptr;
   hipEvent_t join = nullptr;
+  // pme_step_capture: the capture stream, the graph of the captured steps and the
+  // counter sets (set, tset) the graph starts from
+  hipStream_t cap = nullptr;
+  hipGraph_t sgraph = nullptr;
+  hipGraphExec_t sexec = nullptr;
+  int gset = 0, gtset = 0;
 };
 
 namespace pme {
@@ -38,8 +44,8 @@ namespace pme {
 constexpr size_t kTimerMaxEvents = 2 * 65536;
 
 const LaunchEvents* KTimer::next(int k) {
-  if (k != kind) return nullptr;
-  if (used + 2 > ev.size()) {
+  if (k != kind || capturing) return nullptr;
+  while (used + 2 > ev.size()) {
     if (ev.size() >= kTimerMaxEvents) return nullptr;
     for (int i = 0; i < 512; ++i) {
       hipEvent_t e;
@@ -87,7 +93,16 @@ hipError_t dev_alloc(T** p, size_t count, int64_t& bytes) {
   return hipMalloc(reinterpret_cast<void**>(p), b);
 }
 
+void drop_step_graph(pme_plan_s* pl) {
+  if (pl->sexec) (void)hipGraphExecDestroy(pl->sexec);
+  if (pl->sgraph) (void)hipGraphDestroy(pl->sgraph);
+  pl->sexec = nullptr;
+  pl->sgraph = nullptr;
+}
+
 void free_plan(pme_plan_s* pl) {
+  drop_step_graph(pl);
+  if (pl->cap) (void)hipStreamDestroy(pl->cap);
   for (hipEvent_t e : pl->timer.ev) (void)hipEventDestroy(e);
   if (pl->concurrent) {
     DevPlan& t = pl->dt;
@@ -578,6 +593,62 @@ int pme_step(pme_plan_t plan, void* stream, int32_t n, const float* pos, const f
   return PME_OK;
 }
 
+int pme_step_capture(pme_plan_t plan, int32_t steps, int32_t n, const float* pos, const float* q,
+                     const float* mu, const double* box, double* energy, float* dE_dpos,
+                     float* dE_dq, float* dE_dmu, const float* v_pos, const float* v_q,
+                     const float* v_mu, float* g_pos, float* g_q, float* g_mu) {
+  if (!plan || steps < 1 || n < 0 || !box || (n > 0 && !pos)) return PME_EINVAL;
+  if (n > plan->max_atoms) return PME_ECAPACITY;
+  drop_step_graph(plan);
+  hipError_t e;
+  if (!plan->cap && (e = hipStreamCreateWithFlags(&plan->cap, hipStreamNonBlocking)) != hipSuccess)
+    return hip_fail(e);
+  const int set0 = plan->set, tset0 = plan->tset;
+  const bool phi0 = plan->phi_valid;
+  pme::KTimer& t = plan->timer;
+  t.capturing = true;
+  if ((e = hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+    t.capturing = false;
+    return hip_fail(e);
+  }
+  int rc = PME_OK;
+  for (int k = 0; k < steps && rc == PME_OK; ++k)
+    rc = pme_step(plan, plan->cap, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu, v_pos, v_q,
+                  v_mu, g_pos, g_q, g_mu);
+  hipGraph_t g = nullptr;
+  e = hipStreamEndCapture(plan->cap, &g);
+  t.capturing = false;
+  // nothing ran: the host-side state is that of before the capture
+  const bool parity = plan->set == set0 && plan->tset == tset0;
+  plan->set = set0;
+  plan->tset = tset0;
+  plan->phi_valid = phi0;
+  if (rc != PME_OK || e != hipSuccess || !parity) {
+    if (g) (void)hipGraphDestroy(g);
+    if (rc != PME_OK) return rc;
+    return e != hipSuccess ? hip_fail(e) : PME_EINVAL;
+  }
+  plan->sgraph = g;
+  if ((e = hipGraphInstantiate(&plan->sexec, g, nullptr, nullptr, 0)) != hipSuccess) {
+    drop_step_graph(plan);
+    return hip_fail(e);
+  }
+  plan->gset = set0;
+  plan->gtset = tset0;
+  return PME_OK;
+}
+
+int pme_step_replay(pme_plan_t plan, void* stream) {
+  if (!plan || !plan->sexec) return PME_EINVAL;
+  // the graph bins into the counter sets it was captured with: calls made on the
+  // plan since must have left the same ones next
+  if (plan->set != plan->gset || plan->tset != plan->gtset) return PME_EINVAL;
+  const hipError_t e = hipGraphLaunch(plan->sexec, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e);
+  plan->phi_valid = true;
+  return PME_OK;
+}
+
 int pme_plan_timer(pme_plan_t plan, int kind) {
   if (!plan || kind < PME_K_NONE || kind >= PME_K_COUNT) return PME_EINVAL;
   pme::KTimer& t = plan->timer;
@@ -598,14 +669,16 @@ int pme_plan_timer_read(pme_plan_t plan, int64_t* launches, double* total_ms) {
   if (!plan) return PME_EINVAL;
   pme::KTimer& t = plan->timer;
   double sum = 0.0;
+  int64_t count = 0;
   for (size_t i = 0; i + 1 < t.used; i += 2) {
     hipError_t e = hipEventSynchronize(t.ev[i + 1]);
     if (e != hipSuccess) return hip_fail(e);
     float ms = 0.0f;
     if ((e = hipEventElapsedTime(&ms, t.ev[i], t.ev[i + 1])) != hipSuccess) return hip_fail(e);
     sum += ms;
+    ++count;
   }
-  if (launches) *launches = int64_t(t.used / 2);
+  if (launches) *launches = count;
   if (total_ms) *total_ms = sum;
   t.used = 0;
   return PME_OK;

@@ -118,11 +118,15 @@ struct LaunchEvents {
   hipEvent_t stop = nullptr;
 };
 
+// Without events the plain launch is used (it can be captured into a HIP graph).
 template <class F, class... A>
 inline void launch_k(const LaunchEvents* ev, F kernel, dim3 g, dim3 b, size_t sh, hipStream_t s,
                      A... args) {
-  hipExtLaunchKernelGGL(kernel, g, b, uint32_t(sh), s, ev ? ev->start : nullptr,
-                        ev ? ev->stop : nullptr, 0u, args...);
+  if (ev) {
+    hipExtLaunchKernelGGL(kernel, g, b, uint32_t(sh), s, ev->start, ev->stop, 0u, args...);
+  } else {
+    hipLaunchKernelGGL(kernel, g, b, uint32_t(sh), s, args...);
+  }
 }
 
 // Launch timer (host side): hands out event pairs for the launches of one kernel
@@ -132,6 +136,9 @@ struct KTimer {
   std::vector<hipEvent_t> ev;   // start/stop pairs
   size_t used = 0;              // events handed out since the last read
   LaunchEvents cur;
+  // launches being captured into a HIP graph are not timed (events recorded by
+  // graph nodes cannot be read back here)
+  bool capturing = false;
   // Events for the next launch of kind k, or nullptr when k is not being timed.
   const LaunchEvents* next(int k);
 };

@@ -203,6 +203,35 @@ class Plan:
         _lib.check(rc)
         return out
 
+    def step_capture(self, steps, pos, q, mu, box, v_pos=None, v_q=None, v_mu=None, out=None):
+        """pme_step_capture: capture ``steps`` pme_step calls into the plan's HIP graph
+        (nothing runs).  Returns the output dict the replays write; the plan keeps the
+        input and output tensors alive while the graph exists."""
+        n = self._check_common(pos, q, mu, box)
+        _atoms("v_pos", v_pos, n, 3, self.device)
+        _atoms("v_q", v_q, n, 0, self.device)
+        _atoms("v_mu", v_mu, n, 3, self.device)
+        out = {} if out is None else dict(out)
+        shapes = {"energy": ((3,), torch.float64), "dE_dpos": ((n, 3), torch.float32),
+                  "dE_dq": ((n,), torch.float32), "dE_dmu": ((n, 3), torch.float32),
+                  "g_pos": ((n, 3), torch.float32), "g_q": ((n,), torch.float32),
+                  "g_mu": ((n, 3), torch.float32)}
+        for k, (shape, dt) in shapes.items():
+            if k not in out:
+                out[k] = torch.empty(shape, dtype=dt, device=self.device)
+        rc = self._lib.pme_step_capture(self.handle, int(steps), n, _ptr(pos), _ptr(q), _ptr(mu),
+                                        _ptr(box), _ptr(out["energy"]), _ptr(out["dE_dpos"]),
+                                        _ptr(out["dE_dq"]), _ptr(out["dE_dmu"]), _ptr(v_pos),
+                                        _ptr(v_q), _ptr(v_mu), _ptr(out["g_pos"]), _ptr(out["g_q"]),
+                                        _ptr(out["g_mu"]))
+        _lib.check(rc)
+        self._graph_refs = (pos, q, mu, box, v_pos, v_q, v_mu, out)
+        return out
+
+    def step_replay(self) -> None:
+        """pme_step_replay on the current stream."""
+        _lib.check(self._lib.pme_step_replay(self.handle, _stream()))
+
     def status(self) -> None:
         """pme_status: synchronise and raise on device-detected errors."""
         _lib.check(self._lib.pme_status(self.handle, _stream()))
