@@ -770,8 +770,8 @@ def kernel_stats_summary(args) -> int:
         f"#   python -u bench.py --workload {args.workload}{seq} > <log>   (no profiler)",
         f"#   python bench.py --kernel-stats <dir>/run_kernel_stats.csv --bench-line <log> "
         f"--workload {args.workload}{seq}",
-        "# (20 timed + 5 warm-up + 10 per kernel kind breakdown steps; copyBuffer and",
-        "#  fillBuffer are input uploads)",
+        "# (5 warm-up, 10 per kernel kind breakdown and 20 eager timed steps, then twice",
+        "#  20 steps replayed from one HIP graph; copyBuffer and fillBuffer are input uploads)",
         f"# source digest of paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
     ]
     if bench_val:
