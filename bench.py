@@ -54,10 +54,10 @@ COPY_BYTES = 256 << 20         # calibration copy for the byte counters
 
 # Kernel symbol (as a profiler prints it) of each launch-timer kind, slab FFT layout.
 KERNEL_SYMBOL = {
-    "bin": "k_bin<6, false>", "bin_tangent": "k_bin<6, true>",
+    "bin": "k_bin<6, false, false>", "bin_tangent": "k_bin<6, true, false>",
     "spread": "k_spread<6, 1>", "spread_tangent": "k_spread<6, 2>",
-    "fft_r2c": "k_slab_fwd", "fft_x": "k_fftx_fused", "fft_c2r": "k_slab_inv",
-    "gather": "k_gather<6>", "gather_hvp": "k_gather_hvp<6, false>",
+    "fft_r2c": "k_slab_fwd", "fft_x": "k_fftx_fused<0>", "fft_c2r": "k_slab_inv",
+    "gather": "k_gather<6, false>", "gather_hvp": "k_gather_hvp<6, false>",
 }
 
 
@@ -771,7 +771,10 @@ def kernel_stats_summary(args) -> int:
         f"#   python bench.py --kernel-stats <dir>/run_kernel_stats.csv --bench-line <log> "
         f"--workload {args.workload}{seq}",
         "# (5 warm-up, 10 per kernel kind breakdown and 20 eager timed steps, then twice",
-        "#  20 steps replayed from one HIP graph; copyBuffer and fillBuffer are input uploads)",
+        "#  20 steps replayed from one HIP graph; copyBuffer and fillBuffer are input uploads;",
+        "#  the default legs add their kernel variants: cell gradient k_fftx_fused<1>,",
+        "#  k_gather<p, true>, k_cell_grad; optimal influence k_fftx_fused<2>; quadrupole",
+        "#  k_bin<p, false, true>, k_spread<p, 3>, k_gather_quad<p>)",
         f"# source digest of paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
     ]
     if bench_val:
