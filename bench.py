@@ -815,7 +815,8 @@ def sweep_summary(logs) -> int:
     lines = [
         "# PME forward + Hessian-vector product across sizes (molten-salt boxes at the",
         "# density of molten NaCl, mesh ~1 A, p = 6, alpha = 0.30), one MI355X, pme_step",
-        "# with the cotangent chain on a second stream",
+        "# with the cotangent chain on a second stream, the timed steps replayed from one",
+        "# HIP graph (the bench default; ms/step and Matom-steps/s are of that replay)",
         "# commands (repository root):",
         "#   python -u bench.py --workload 8k   --batched 0 --learned 0 --cpu-baseline 0 "
         "--steps 100 --warmup 10",
