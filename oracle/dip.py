@@ -30,6 +30,8 @@ Here F_s = -dU/dr at mu = mu_NN, the student's Hellmann-Feynman force.
     dL/dmu = (dL/dU_s) dU/dmu + H_{mu r} v,  v = dL/d(dU/dr)
 
 H_{mu r} v is the PME Hessian-vector product (dipole block) plus the real-space mixed block. The gradient then flows through w to the parameters (first order; the features do not depend on them).
+
+Conservative student forces (position_vjp, conservative_forces): F = -dU(r, mu_NN(r))/dr adds to the Hellmann-Feynman force the path through the dipole head, (d mu_NN / dr)^T dU/dmu, which runs back through the network's input gradient and the position derivatives of the features.
 """
 from __future__ import annotations
 
@@ -128,6 +130,80 @@ def mlp_backward(theta, cache, gw):
 def dipoles(theta, x, V):
     w, cache = mlp(theta, x)
     return np.einsum('nc,ncd->nd', w, V), w, cache
+
+
+def radial_derivative(r, rc):
+    """(len(r), NRAD) derivative of the radial basis with respect to r."""
+    r = np.asarray(r, dtype=np.float64)
+    k = np.arange(1, NRAD + 1)
+    x = r / rc
+    env = envelope(x)[:, None]
+    denv = (np.where(x < 1.0, -105.0 * x ** 4 + 210.0 * x ** 5 - 105.0 * x ** 6, 0.0) / rc)[:, None]
+    arg = np.outer(r, k) * math.pi / rc
+    sn, cs = np.sin(arg), np.cos(arg)
+    rr = r[:, None]
+    return math.sqrt(2.0 / rc) * ((k * math.pi / rc) * cs / rr * env - sn / rr ** 2 * env
+                                  + sn / rr * denv)
+
+
+def mlp_input_grad(theta, cache, gw):
+    """dL/dx (n, 34) from dL/dw (n, 16): the network's input gradient."""
+    W1, b1, W2, b2, W3, b3 = unpack(theta)
+    x, z1, h1, z2, h2 = cache
+    gz2 = (gw @ W3) * dsilu(z2)
+    gz1 = (gz2 @ W2) * dsilu(z1)
+    return gz1 @ W1
+
+
+def position_vjp(theta, pos, q, box, rc, u):
+    """g_j = sum_i (d mu_i / d r_j)^T u_i: the total derivative of the dipole head with
+    respect to the positions, contracted with u (n, 3).
+
+    mu_i depends on the positions through its features (the charges and species are
+    fixed): with cotangents cG = dL/dG_i and cV = dL/dV_i (from w_ic u_i and the
+    input gradient of |V_ic|^2), a pair R = r_i - r_j with neighbour j of species s
+    contributes, per radial k,
+        d/dR [cG R_k(r)]              = cG R_k'(r) u_hat
+        d/dR [q_j R_k(r) cV . u_hat]  = q_j [R_k'(r) (cV . u_hat) u_hat
+                                            + R_k(r)/r (cV - (cV . u_hat) u_hat)]
+    to r_i and the negative to r_j."""
+    pos = np.asarray(pos, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    n = pos.shape[0]
+    x, V = features(pos, q, box, rc)
+    _, w, cache = dipoles(theta, x, V)
+    gw = np.einsum('nd,ncd->nc', u, V)
+    gx = mlp_input_grad(theta, cache, gw)
+    cG = gx[:, :NCH].reshape(n, NSPEC, NRAD)
+    cV = (w[:, :, None] * u[:, None, :] + 2.0 * gx[:, NCH:2 * NCH, None] * V).reshape(
+        n, NSPEC, NRAD, 3)
+    ia, ja, R, r = opol._pairs(pos, box, rc)
+    Rk = radial(r, rc)
+    dRk = radial_derivative(r, rc)
+    uh = R / r[:, None]
+    spec = (q[ja] <= 0).astype(int)
+    cg = cG[ia, spec]                                  # (P, 8)
+    cv = cV[ia, spec]                                  # (P, 8, 3)
+    cu = np.einsum('pkd,pd->pk', cv, uh)
+    f = (np.einsum('pk,pk->p', cg, dRk)[:, None] * uh
+         + q[ja][:, None] * (np.einsum('pk,pk->p', cu, dRk)[:, None] * uh
+                             + np.einsum('pk,pkd->pd', Rk / r[:, None],
+                                         cv - cu[:, :, None] * uh[:, None, :])))
+    g = np.zeros((n, 3))
+    np.add.at(g, ia, f)
+    np.add.at(g, ja, -f)
+    return g
+
+
+def conservative_forces(theta, pos, q, pol, box, mesh, p, alpha, rc, rc_feat=5.0):
+    """Student forces as the total derivative F = -dU(r, mu_NN(r))/dr (the conservative
+    alternative to the Hellmann-Feynman force of Eq. loss), the energy and the dipoles;
+    rc is the real-space cutoff of the model, rc_feat that of the features."""
+    x, V = features(pos, q, box, rc_feat)
+    mu, _, _ = dipoles(theta, x, V)
+    U, dUdr, dUdmu = opol.model(pos, q, mu, box, mesh, p, alpha, rc, pol)
+    return -(dUdr + position_vjp(theta, pos, q, box, rc_feat, dUdmu)), U, mu
 
 
 def loss_and_grad(theta, x, V, pos, q, pol, box, mesh, p, alpha, rc, teacher, lE=1.0, lF=1.0,
