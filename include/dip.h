@@ -74,6 +74,20 @@ int dip_backward(dip_plan_t plan, void* stream, int32_t n, const float* params, 
                  const float* vec, const float* g_mu0, const float* g_mu1, const float* g_mu2,
                  float* g_params);
 
+/* Position vector-Jacobian product of the dipole head: g_pos[j] = sum_i (d mu_i /
+ * d r_j)^T u_i (overwritten), for u [n][3] (device).  With u = dU/dmu it is the
+ * term that turns the Hellmann-Feynman force of Eq. loss into the conservative
+ * student force F = -dU(r, mu_NN(r))/dr = -(dU/dr + g_pos) (the total derivative
+ * through the dipole prediction, Eq. forces).  feat and vec are dip_features of
+ * the same (pos, q); the network runs back to its inputs, then the position
+ * derivatives of the features are summed per atom over its pairs (each pair is
+ * visited from both atoms; no atomics).  Uses the plan's cell list (rebuilt
+ * here) and its [max_atoms][64] cotangent workspace; calls on one plan must not
+ * overlap. */
+int dip_position_vjp(dip_plan_t plan, void* stream, int32_t n, const float* params,
+                     const float* pos, const float* q, const float* feat, const float* vec,
+                     const float* u, float* g_pos);
+
 /* Loss of the student (U_s, dUdr_s at dipoles mu, with dU/dmu dUdmu_s) against
  * the teacher (U_t, dUdr_t, mu_t; mu_t may be NULL when lmu = 0).
  *   loss   device double[1]

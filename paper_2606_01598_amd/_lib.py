@@ -36,7 +36,7 @@ EXPORTS = ("pme_mesh_dims", "pme_plan_create", "pme_plan_destroy", "pme_plan_wor
            "pme_plan_phi", "pme_plan_rho", "pme_plan_timer", "pme_plan_timer_read",
            "pol_plan_create", "pol_plan_destroy", "pol_real", "pol_real_mixed", "pol_model",
            "pol_scf", "dip_plan_create", "dip_plan_destroy", "dip_features", "dip_forward",
-           "dip_backward", "dip_loss", "dip_adam", "pme_batch_create", "pme_batch_destroy",
+           "dip_backward", "dip_position_vjp", "dip_loss", "dip_adam", "pme_batch_create", "pme_batch_destroy",
            "pme_batch_forward", "pme_batch_backward", "pme_batch_capture", "pme_batch_replay",
            "pme_batch_status")
 
@@ -178,6 +178,8 @@ def load():
     lib.dip_forward.restype = ctypes.c_int
     lib.dip_backward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.dip_backward.restype = ctypes.c_int
+    lib.dip_position_vjp.argtypes = [vp, vp, i32] + [vp] * 7
+    lib.dip_position_vjp.restype = ctypes.c_int
     lib.dip_loss.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, f64, f64, f64, vp, vp, vp]
     lib.dip_loss.restype = ctypes.c_int
     lib.dip_adam.argtypes = [vp, i32, i32, f64, f64, f64, f64, vp, vp, vp, vp]

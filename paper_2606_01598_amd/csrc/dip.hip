@@ -308,6 +308,187 @@ __global__ void __launch_bounds__(kMlpThreads) k_mlp_backward(int n, const float
   }
 }
 
+// Feature cotangents of the position vector-Jacobian product for dL/dmu = u:
+// fbar[i] = [dL/dG_i (16) | dL/dV_i (16 x 3)], with dL/dw_c = u . V_c run back through
+// the network to its inputs and dL/dV_c = w_c u + 2 (dL/dx_{16+c}) V_c.
+__global__ void __launch_bounds__(kMlpThreads) k_mlp_input_grad(int n, const float* P,
+                                                                const float* feat,
+                                                                const float* vec, const float* u,
+                                                                float* fbar) {
+  __shared__ MlpLds L;
+  __shared__ float gw[kAtoms][NCH + 1];
+  __shared__ float gz2[kAtoms][HP];   // later the input gradient (first 2 NCH inputs)
+  __shared__ float gz1[kAtoms][HP];
+  const int a0 = blockIdx.x * kAtoms;
+  const int na = min(kAtoms, n - a0);
+  mlp_eval(L, P, feat, vec, a0, na);
+  const int t = threadIdx.x;
+  for (int e = t; e < kAtoms * NCH; e += kMlpThreads) {
+    const int a = e / NCH, c = e - a * NCH;
+    float s = 0.0f;
+    if (a < na)
+#pragma unroll
+      for (int d = 0; d < 3; ++d) s += u[size_t(a0 + a) * 3 + d] * L.V[a][3 * c + d];
+    gw[a][c] = s;
+  }
+  __syncthreads();
+  for (int a = 0; a < kAtoms; ++a) {
+    float s = 0.0f;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) s += L.W3[c][t] * gw[a][c];
+    gz2[a][t] = s * dsilu(L.z2[a][t]);
+  }
+  __syncthreads();
+  for (int a = 0; a < kAtoms; ++a) {
+    float s = 0.0f;
+#pragma unroll 8
+    for (int k = 0; k < HID; ++k) s += L.W2T[t][k] * gz2[a][k];   // W2[k][t]
+    gz1[a][t] = s * dsilu(L.z1[a][t]);
+  }
+  __syncthreads();
+  // dL/dx_k = sum_o gz1[o] W1[o][k] for the inputs G and |V|^2 (the species one-hot
+  // does not move)
+  for (int e = t; e < kAtoms * 2 * NCH; e += kMlpThreads) {
+    const int a = e / (2 * NCH), k = e - a * 2 * NCH;
+    float s = 0.0f;
+#pragma unroll 8
+    for (int o = 0; o < HID; ++o) s += gz1[a][o] * L.W1T[k][o];
+    gz2[a][k] = s;
+  }
+  __syncthreads();
+  for (int e = t; e < kAtoms * 4 * NCH; e += kMlpThreads) {
+    const int a = e / (4 * NCH), k = e - a * 4 * NCH;
+    if (a >= na) continue;
+    float v;
+    if (k < NCH) {
+      v = gz2[a][k];
+    } else {
+      const int c = (k - NCH) / 3, d = (k - NCH) - 3 * c;
+      v = L.w[a][c] * u[size_t(a0 + a) * 3 + d] + 2.0f * gz2[a][NCH + c] * L.V[a][3 * c + d];
+    }
+    fbar[size_t(a0 + a) * 4 * NCH + k] = v;
+  }
+}
+
+struct VjpArgs {
+  int n;
+  const float* pos;
+  const float* q;
+  CellGrid g;
+  const int* start;
+  const int* sorted;
+  float rc;
+  const float* fbar;   // [n][64] feature cotangents
+  float* g_pos;        // [n][3] out
+};
+
+// d/dR of the features of the centre atom of a pair (R = r_c - r_o, neighbour o
+// with charge qo) contracted with the cotangents cg[k], cv[k][3] of the neighbour's
+// species: sum_k cg R_k' u + qo [R_k' (cv.u) u + R_k / r (cv - (cv.u) u)].
+__device__ __forceinline__ float3 pair_vjp(const float* cg, const float* cv, float qo, float ux,
+                                           float uy, float uz, const float (&Rk)[NR],
+                                           const float (&dR)[NR], float ir) {
+  float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+#pragma unroll
+  for (int k = 0; k < NR; ++k) {
+    const float vx = cv[3 * k], vy = cv[3 * k + 1], vz = cv[3 * k + 2];
+    const float cu = vx * ux + vy * uy + vz * uz;
+    const float a = cg[k] * dR[k] + qo * (dR[k] - Rk[k] * ir) * cu;
+    const float b = qo * Rk[k] * ir;
+    fx += a * ux + b * vx;
+    fy += a * uy + b * vy;
+    fz += a * uz + b * vz;
+  }
+  return make_float3(fx, fy, fz);
+}
+
+// g_i = sum_j [d/dr_i of the features of i, with i's cotangents] + [d/dr_i of the
+// features of j, with j's cotangents]: the pair (i, j) is visited from i only, so
+// no atomics are needed.  16 lanes per atom as in k_features.
+__global__ void __launch_bounds__(kFeatThreads) k_features_vjp(VjpArgs a) {
+  __shared__ float s_f[kFeatThreads / kLanes][4 * NCH];
+  const int lane = threadIdx.x % kLanes;
+  const int slot = threadIdx.x / kLanes;
+  const int i = blockIdx.x * (kFeatThreads / kLanes) + slot;
+  const bool live = i < a.n;
+  const int ii = live ? i : 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) s_f[slot][lane + kLanes * k] = a.fbar[size_t(ii) * 4 * NCH + lane + kLanes * k];
+  __syncthreads();
+  const float px = a.pos[3 * ii], py = a.pos[3 * ii + 1], pz = a.pos[3 * ii + 2];
+  const float qi = a.q[ii];
+  const int si = qi > 0.0f ? 0 : 1;
+  const float rc2 = a.rc * a.rc, irc = 1.0f / a.rc;
+  const float norm = sqrtf(2.0f * irc);
+  const float kpi = float(M_PI) * irc;
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  if (live) {
+    int c[3], no[3];
+    cell_of(a.g, px, py, pz, c);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) no[d] = a.g.nc[d] < 3 ? a.g.nc[d] : 3;
+    for (int ox = 0; ox < no[0]; ++ox)
+      for (int oy = 0; oy < no[1]; ++oy)
+        for (int oz = 0; oz < no[2]; ++oz) {
+          const int cell = (neighbour_cell(c[0], ox, a.g.nc[0]) * a.g.nc[1] +
+                            neighbour_cell(c[1], oy, a.g.nc[1])) * a.g.nc[2] +
+                           neighbour_cell(c[2], oz, a.g.nc[2]);
+          for (int kk = a.start[cell] + lane; kk < a.start[cell + 1]; kk += kLanes) {
+            const int j = a.sorted[kk];
+            if (j == i) continue;
+            const float3 R = min_image(a.g, px - a.pos[3 * j], py - a.pos[3 * j + 1],
+                                       pz - a.pos[3 * j + 2]);
+            const float r2 = R.x * R.x + R.y * R.y + R.z * R.z;
+            if (r2 >= rc2 || r2 <= 0.0f) continue;
+            const float r = sqrtf(r2), ir = 1.0f / r, x = r * irc;
+            const float x2 = x * x, x4 = x2 * x2, x5 = x4 * x;
+            const float env = 1.0f - 21.0f * x5 + 35.0f * x5 * x - 15.0f * x5 * x2;
+            const float denv = (-105.0f * x4 + 210.0f * x5 - 105.0f * x5 * x) * irc;
+            const float ux = R.x * ir, uy = R.y * ir, uz = R.z * ir;
+            // R_k = norm sin(k pi x) env / r and its r-derivative, sin and cos of
+            // (k+1) pi x by the Chebyshev recurrences
+            float sn, cs;
+            sincosf(float(M_PI) * x, &sn, &cs);
+            float Rk[NR], dR[NR];
+            float s_prev = 0.0f, s_cur = sn, c_prev = 1.0f, c_cur = cs;
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+              Rk[k] = norm * s_cur * env * ir;
+              dR[k] = norm * ((k + 1) * kpi * c_cur * env * ir - s_cur * env * ir * ir +
+                              s_cur * ir * denv);
+              const float s_next = 2.0f * cs * s_cur - s_prev;
+              const float c_next = 2.0f * cs * c_cur - c_prev;
+              s_prev = s_cur;
+              s_cur = s_next;
+              c_prev = c_cur;
+              c_cur = c_next;
+            }
+            const float qj = a.q[j];
+            const int sj = qj > 0.0f ? 0 : 1;
+            // features of i (neighbour j of species sj), R_ij = R
+            const float* fi = s_f[slot];
+            const float3 f1 = pair_vjp(fi + sj * NR, fi + NCH + 3 * sj * NR, qj, ux, uy, uz, Rk,
+                                       dR, ir);
+            // features of j (neighbour i of species si), R_ji = -R
+            const float* fj = a.fbar + size_t(j) * 4 * NCH;
+            const float3 f2 = pair_vjp(fj + si * NR, fj + NCH + 3 * si * NR, qi, -ux, -uy, -uz,
+                                       Rk, dR, ir);
+            gx += f1.x - f2.x;
+            gy += f1.y - f2.y;
+            gz += f1.z - f2.z;
+          }
+        }
+  }
+  gx = lane_sum(gx);
+  gy = lane_sum(gy);
+  gz = lane_sum(gz);
+  if (live && lane == 0) {
+    a.g_pos[3 * i] = gx;
+    a.g_pos[3 * i + 1] = gy;
+    a.g_pos[3 * i + 2] = gz;
+  }
+}
+
 __global__ void k_param_reduce(int nb, const float* part, float* g) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= NP) return;
@@ -375,6 +556,7 @@ struct dip_plan_s {
   dip_desc_t desc;
   CellList cells;
   float* part = nullptr;     // [mlp blocks][NP]
+  float* fbar = nullptr;     // [max_atoms][64] feature cotangents (position VJP)
 };
 
 extern "C" {
@@ -390,9 +572,12 @@ int dip_plan_create(const dip_desc_t* desc, dip_plan_t* out) {
   hipError_t e = hipSuccess;
   if (rc == PME_OK)
     e = hipMalloc(&pl->part, sizeof(float) * size_t(mlp_blocks(desc->max_atoms)) * NP);
+  if (rc == PME_OK && e == hipSuccess)
+    e = hipMalloc(&pl->fbar, sizeof(float) * size_t(desc->max_atoms) * 4 * NCH);
   if (rc != PME_OK || e != hipSuccess) {
     free_cells(pl->cells);
     if (pl->part) (void)hipFree(pl->part);
+    if (pl->fbar) (void)hipFree(pl->fbar);
     delete pl;
     return rc != PME_OK ? rc : (e == hipErrorOutOfMemory ? PME_ENOMEM : dip_fail(e));
   }
@@ -405,6 +590,7 @@ void dip_plan_destroy(dip_plan_t plan) {
   (void)hipDeviceSynchronize();
   free_cells(plan->cells);
   if (plan->part) (void)hipFree(plan->part);
+  if (plan->fbar) (void)hipFree(plan->fbar);
   delete plan;
 }
 
@@ -452,6 +638,28 @@ int dip_backward(dip_plan_t plan, void* stream, int32_t n, const float* params, 
   hipLaunchKernelGGL(k_param_reduce, dim3((NP + 255) / 256), dim3(256), 0, s, nb, plan->part,
                      g_params);
   const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PME_OK : dip_fail(e);
+}
+
+int dip_position_vjp(dip_plan_t plan, void* stream, int32_t n, const float* params,
+                     const float* pos, const float* q, const float* feat, const float* vec,
+                     const float* u, float* g_pos) {
+  if (!plan || n < 0 || n > plan->desc.max_atoms ||
+      (n > 0 && (!params || !pos || !q || !feat || !vec || !u || !g_pos)))
+    return PME_EINVAL;
+  if (n == 0) return PME_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = build_cells(plan->cells, s, n, pos);
+  if (e != hipSuccess) return dip_fail(e);
+  hipLaunchKernelGGL(k_mlp_input_grad, dim3(mlp_blocks(n)), dim3(kMlpThreads), 0, s, n, params,
+                     feat, vec, u, plan->fbar);
+  VjpArgs a;
+  a.n = n; a.pos = pos; a.q = q; a.g = plan->cells.g;
+  a.start = plan->cells.start; a.sorted = plan->cells.sorted;
+  a.rc = float(plan->desc.cutoff); a.fbar = plan->fbar; a.g_pos = g_pos;
+  const int per = kFeatThreads / kLanes;
+  hipLaunchKernelGGL(k_features_vjp, dim3((n + per - 1) / per), dim3(kFeatThreads), 0, s, a);
+  e = hipGetLastError();
   return e == hipSuccess ? PME_OK : dip_fail(e);
 }
 

@@ -9,6 +9,7 @@ module allocates device buffers and passes pointers and the current stream.
 * ``DipPlan.features(pos, q)``    -- dip_features
 * ``DipPlan.forward(theta, ...)`` -- dip_forward
 * ``DipPlan.backward(...)``       -- dip_backward
+* ``DipPlan.position_vjp(...)``   -- dip_position_vjp (conservative student forces)
 * ``DipPlan.loss(...)``           -- dip_loss
 * ``adam(...)``                   -- dip_adam
 * ``Trainer``                     -- one training step per teacher box
@@ -78,6 +79,15 @@ class DipPlan:
         _lib.check(self._lib.dip_backward(self.handle, _stream(), n, _ptr(theta), _ptr(feat),
                                           _ptr(vec), _ptr(g_mu0), _ptr(g_mu1), _ptr(g_mu2),
                                           _ptr(g)))
+        return g
+
+    def position_vjp(self, theta, pos, q, feat, vec, u, out=None):
+        """dip_position_vjp: sum_i (d mu_i / d r_j)^T u_i for every atom j."""
+        n = self._n(pos)
+        _atoms("u", u, n, 3, self.device)
+        g = out if out is not None else torch.empty(n, 3, dtype=torch.float32, device=self.device)
+        _lib.check(self._lib.dip_position_vjp(self.handle, _stream(), n, _ptr(theta), _ptr(pos),
+                                              _ptr(q), _ptr(feat), _ptr(vec), _ptr(u), _ptr(g)))
         return g
 
     def loss(self, U_s, U_t, dUdr_s, dUdr_t, mu, mu_t, dUdmu_s, lE=1.0, lF=1.0, lmu=0.0,
