@@ -620,14 +620,25 @@ def learned_leg(n_train=32, n_val=4, epochs=80):
         mu = dip.forward(tr.theta, feat, vec)
         polp.model(pme, b["pos"], b["q"], mu, b["pol"], box, dU_dmu=False)
 
+    def infer_conservative():
+        # the conservative student force: dU/dr plus the position vector-Jacobian
+        # product of the dipole head with dU/dmu
+        feat, vec = dip.features(b["pos"], b["q"])
+        mu = dip.forward(tr.theta, feat, vec)
+        s = polp.model(pme, b["pos"], b["q"], mu, b["pol"], box)
+        return s["dU_dpos"] + dip.position_vjp(tr.theta, b["pos"], b["q"], feat, vec, s["dU_dmu"])
+
     for _ in range(3):
         infer()
+        infer_conservative()
     nn_ms = _median_ms(infer, 20)
+    cons_ms = _median_ms(infer_conservative, 20)
     scf_med = float(np.median(scf_ms[n_train:]))
     return {"workload": f"{n}-ion Thole boxes, L={L:.1f} A, mesh 50^3, p=6, alpha=0.3, r_c=10 A; "
                         f"{n_train} training / {n_val} held-out boxes, {epochs} epochs",
             "scf_ms": round(scf_med, 3), "scf_iterations": int(np.median(iters)),
             "nn_ms": round(nn_ms, 4), "speedup": round(scf_med / nn_ms, 2),
+            "nn_conservative_ms": round(cons_ms, 4),
             "force_rmse_nn": e_nn, "force_rmse_zero_dipoles": e_zero,
             "force_unit": "e^2/A^2", "train_s": round(train_s, 2)}
 
