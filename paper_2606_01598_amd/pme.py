@@ -318,8 +318,29 @@ class _PMEEnergy(torch.autograd.Function):
         return gp * s, gq * s, gm * s, g_box, None
 
 
+class _PMEEnergyQuad(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, pos, q, mu, theta, box, plan):
+        r = plan.forward(pos.detach(), q.detach(), mu.detach(), box.detach(),
+                         theta=theta.detach())
+        ctx.save_for_backward(r["dE_dpos"], r["dE_dq"], r["dE_dmu"], r["dE_dtheta"])
+        return r["energy"].sum()
+
+    @staticmethod
+    def backward(ctx, gE):
+        gp, gq, gm, gt = ctx.saved_tensors
+        s = gE.to(torch.float32)
+        return gp * s, gq * s, gm * s, gt * s, None, None
+
+
 def pme_energy(pos: torch.Tensor, q: torch.Tensor, mu: torch.Tensor, box: torch.Tensor,
-               plan: Plan) -> torch.Tensor:
+               plan: Plan, theta: torch.Tensor = None) -> torch.Tensor:
     """E^lr (float64 scalar) with gradients to pos, q and mu, differentiable twice, and
-    to box (first order, pme_forward_cell) when box requires grad."""
+    to box (first order, pme_forward_cell) when box requires grad.  With second moments
+    ``theta`` (n, 6; pme_forward_quad) the gradients to pos, q, mu and theta are first
+    order (no Hessian-vector product for the quadrupole channel) and box takes none."""
+    if theta is not None:
+        if box.requires_grad:
+            raise ValueError("no cell gradient with quadrupoles")
+        return _PMEEnergyQuad.apply(pos, q, mu, theta, box, plan)
     return _PMEEnergy.apply(pos, q, mu, box, plan)

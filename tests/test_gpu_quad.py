@@ -129,3 +129,23 @@ def test_quad_32k_workload():
     """The 32k-ion, 100^3, p = 6 workload of the benchmark with second moments."""
     f = synth.molten_box(32000, 3)
     _check(f, synth.random_quadrupoles(f.n, 27), (100, 100, 100), 6, 0.3, "32k")
+
+
+def test_quad_through_autograd():
+    """pme_energy with theta: the gradients autograd returns are those of
+    pme_forward_quad, scaled by the upstream gradient."""
+    from paper_2606_01598_amd.pme import pme_energy
+    f = synth.molten_box(400, 9, L=22.0)
+    mesh, p, a = (24, 24, 24), 6, 0.35
+    plan = _plan(mesh, p, a, f.n)
+    pos, q, mu, box = to_dev(f)
+    th = torch.tensor(synth.random_quadrupoles(f.n, 28), dtype=torch.float32, device=dev())
+    ref = plan.forward(pos, q, mu, box, theta=th)
+    for t in (pos, q, mu, th):
+        t.requires_grad_(True)
+    e = pme_energy(pos, q, mu, box, plan, theta=th)
+    (3.0 * e).backward()
+    assert abs(float(e.detach()) - float(ref["energy"].sum())) <= 1e-12 * abs(float(e.detach()))
+    for t, k in ((pos, "dE_dpos"), (q, "dE_dq"), (mu, "dE_dmu"), (th, "dE_dtheta")):
+        assert torch.allclose(t.grad, 3.0 * ref[k], rtol=1e-6, atol=0.0), k
+
