@@ -87,3 +87,22 @@ def test_timer_and_graph():
     assert k2 == 2 and ms2 > 0.0
     plan.timer(None)
     plan.status()
+
+
+def test_graph_with_optimal_influence_and_sequential_plan():
+    """Replays of a plan with the optimal influence function equal its eager steps."""
+    from paper_2606_01598_amd.pme import Plan
+    f = synth.molten_box(400, 7, L=22.0)
+    pos, q, mu, box = to_dev(f)
+    v = [torch.tensor(x, dtype=torch.float32, device=dev())
+         for x in synth.random_cotangents(f.n, 57, scale_r=0.1)]
+    plan = Plan((24, 24, 24), 5, 0.35, max_atoms=f.n, concurrent=True, optimal_influence=True)
+    ref = {k: t.clone() for k, t in plan.step(pos, q, mu, box, *v).items()}
+    plan.step(pos, q, mu, box, *v)
+    out = plan.step_capture(2, pos, q, mu, box, *v)
+    for _ in range(2):
+        plan.step_replay()
+        plan.status()
+        for k in KEYS:
+            assert torch.equal(out[k], ref[k]), k
+

@@ -24,8 +24,9 @@ def _plan(mesh, p, alpha, n, **kw):
     return Plan(mesh, p, alpha, max_atoms=max(n, 1), **kw)
 
 
-def _check(frame, th, mesh, p, alpha, label, with_q=True, with_mu=True, prefactor=1.0, **kw):
-    plan = _plan(mesh, p, alpha, frame.n, prefactor=prefactor, **kw)
+def _check(frame, th, mesh, p, alpha, label, with_q=True, with_mu=True, prefactor=1.0,
+           max_atoms=None, **kw):
+    plan = _plan(mesh, p, alpha, max_atoms or frame.n, prefactor=prefactor, **kw)
     pos, q, mu, box = to_dev(frame, with_q, with_mu)
     tht = torch.tensor(th, dtype=torch.float32, device=dev())
     out = plan.forward(pos, q, mu, box, theta=tht)
@@ -149,3 +150,18 @@ def test_quad_through_autograd():
     for t, k in ((pos, "dE_dpos"), (q, "dE_dq"), (mu, "dE_dmu"), (th, "dE_dtheta")):
         assert torch.allclose(t.grad, 3.0 * ref[k], rtol=1e-6, atol=0.0), k
 
+
+@pytest.mark.parametrize("lo,hi,max_atoms", [((0.2, 0.2, 0.2), (3.8, 3.8, 15.8), 10000),
+                                             ((4.0, 4.0, 4.0), (5.5, 5.5, 5.5), 300)])
+def test_quad_crowded_tile(lo, hi, max_atoms):
+    """More atoms in one tile than a gather queues at once (a column of 4 bins with
+    64 slots each), and 300 atoms in a 1.5 A cube of a plan with 18 slots per bin,
+    most of them in the overflow list."""
+    rng = np.random.default_rng(18)
+    n = 300
+    q = rng.normal(0, 1, n)
+    q -= q.mean()
+    f = synth.Frame(pos=rng.uniform(lo, hi, (n, 3)), q=q, mu=rng.normal(0, 0.1, (n, 3)),
+                    box=np.eye(3) * 16.0)
+    _check(f, synth.random_quadrupoles(n, 29, scale=0.1), (16, 16, 16), 6, 0.3,
+           f"crowded {max_atoms}", max_atoms=max_atoms)
