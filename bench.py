@@ -94,11 +94,28 @@ def step_bytes(n: int, m: int, step: bool = True) -> int:
     return 196 * n + 32 * m if step else 224 * n + 36 * m
 
 
-def source_digest() -> str:
-    """Digest of the HIP sources: a traffic summary is valid only for the kernels
-    it was measured on."""
+# the sources each timer kind's kernel is compiled from (a traffic summary holds
+# only while they are unchanged)
+KERNEL_SOURCES = {
+    "bin": ("spread.hip",), "bin_tangent": ("spread.hip",), "spread": ("spread.hip",),
+    "spread_tangent": ("spread.hip",), "fft_r2c": ("fft.hip", "fft_radix.h"),
+    "fft_x": ("fft.hip", "fft_radix.h"), "fft_c2r": ("fft.hip", "fft_radix.h"),
+    "gather": ("gather.hip",), "gather_hvp": ("gather.hip",),
+}
+
+
+def source_digest(kind: str = None) -> str:
+    """Digest of the HIP sources (all of them, or those of one kernel kind together
+    with the shared headers): a traffic summary is valid only for the kernel it was
+    measured on."""
+    csrc = os.path.join(ROOT, "paper_2606_01598_amd", "csrc")
+    if kind is None:
+        files = sorted(glob.glob(os.path.join(csrc, "*")))
+    else:
+        files = [os.path.join(csrc, f) for f in
+                 sorted(set(KERNEL_SOURCES[kind]) | {"kernels.h", "pme_common.h"})]
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2606_01598_amd", "csrc", "*"))):
+    for f in files:
         with open(f, "rb") as fh:
             h.update(os.path.basename(f).encode())
             h.update(fh.read())
@@ -659,7 +676,7 @@ def read_traffic(kind: str, workload: str):
             if ":" in ln:
                 k, _, v = ln.partition(":")
                 vals[k.strip()] = v.strip()
-    if vals.get("sources") != source_digest():
+    if vals.get("sources") != source_digest(kind):
         return None
     try:
         return float(vals["traffic_bytes_per_launch"])
@@ -725,7 +742,9 @@ def traffic_summary(args) -> int:
                      f"python -u bench.py {PMC_FLAGS} --workload {args.workload}\n")
         fh.write("#   python bench.py --traffic-summary <D1>/run_counter_collection.csv "
                  f"<D2>/run_counter_collection.csv --kernel {kind} --workload {args.workload}\n")
-        fh.write(f"sources: {source_digest()}\n")
+        fh.write(f"# sources: digest of {', '.join(sorted(set(KERNEL_SOURCES[kind]) | {'kernels.h', 'pme_common.h'}))} "
+                 f"(bench.source_digest('{kind}'))\n")
+        fh.write(f"sources: {source_digest(kind)}\n")
         fh.write(f"kernel: {kf}\n")
         fh.write(f"dispatches: {fetch[kf][1]} (FETCH_SIZE), {write[kw][1]} (WRITE_SIZE)\n")
         fh.write(f"fetch_kib_per_dispatch: {fetch[kf][0]:.1f}\n")
