@@ -118,7 +118,8 @@ void free_plan(pme_plan_s* pl) {
   void* ptrs[] = {d.count[0], d.count[1], d.ovf_count[0], d.ovf_count[1], d.cmax[0],
                   d.cmax[1], d.rec, d.twiddle[0], d.twiddle[1], d.twiddle[2],
                   d.deconv[0], d.deconv[1], d.deconv[2], d.rho, d.spec, d.phi, d.epart,
-                  d.spart, d.vpart, d.escr, d.status, d.alias[0], d.alias[1], d.alias[2]};
+                  d.spart, d.vpart, d.escr, d.status, d.alias[0], d.alias[1], d.alias[2],
+                  d.gcache, d.gbox, d.gvalid};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete pl;
@@ -320,6 +321,11 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
     ok(dev_alloc(&d.deconv[a], size_t(d.N[a]), by));
     if (d.opt) ok(dev_alloc(&d.alias[a], size_t(3 * d.N[a]), by));
   }
+  if (d.opt) {
+    ok(dev_alloc(&d.gcache, size_t(d.N[0]) * d.N[1] * d.H, by));
+    ok(dev_alloc(&d.gbox, 9, by));
+    ok(dev_alloc(&d.gvalid, 1, by));
+  }
   ok(dev_alloc(&d.rho, size_t(M), by));
   ok(dev_alloc(&d.spec, size_t(d.N[0]) * d.N[1] * d.H, by));
   ok(dev_alloc(&d.phi, size_t(M), by));
@@ -372,6 +378,7 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
     ok(hipMemset(d.cmax[k], 0, sizeof(unsigned)));
   }
   ok(hipMemset(d.status, 0, sizeof(int)));
+  if (d.gvalid) ok(hipMemset(d.gvalid, 0, sizeof(int)));
   ok(hipMemset(d.phi, 0, sizeof(float) * M));
   if (e == hipSuccess && (desc->flags & PME_F_CONCURRENT)) {
     pl->concurrent = true;

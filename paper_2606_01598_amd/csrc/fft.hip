@@ -493,6 +493,10 @@ struct XArgs {
   const float* alx;
   const float* aly;
   const float* alz;
+  // and the cache of g for an unchanged box ([N_y][N_x][H]; see DevPlan)
+  float* gcache;
+  const double* gbox;
+  const int* gvalid;
 };
 
 __device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) / 2) ? k - N : k; }
@@ -593,9 +597,14 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
       return 4.0f * float(M_PI) / k2 * expf(-k2 * inv4a2);
     };
     float aly3[3] = {0.0f, 0.0f, 0.0f};
+    // OPT: g from the cache when it holds this box (a uniform decision)
+    bool cached = false;
     if constexpr (OPT) {
 #pragma unroll
       for (int m = 0; m < 3; ++m) aly3[m] = a.aly[m * Ny + y];
+      cached = *a.gvalid != 0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) cached = cached && a.gbox[k] == box[k];
     }
     for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
       const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
@@ -606,6 +615,7 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
         const bool nx = ((Nx & 1) == 0) && (2 * xx == Nx);
         const bool nz = ((Nz & 1) == 0) && (2 * kz == Nz);
         if constexpr (OPT) {
+          float* gc = a.gcache + (size_t(y) * Nx + xx) * H + kz;
           // sum over the aliases f + m N of U^2 G; a partner frequency s f (s = -1 on
           // the flipped axes) takes the weight of alias -m of f, as sinc is even
           auto gopt = [&](int sx, int sy, int sz) {
@@ -626,14 +636,20 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
             }
             return num;
           };
-          g = gopt(1, 1, 1);
-          if (nx || nyq_y || nz) g = 0.5f * (g + gopt(nx ? 1 : -1, nyq_y ? 1 : -1, nz ? 1 : -1));
+          if (cached) {
+            g = *gc;
+          } else {
+            g = gopt(1, 1, 1);
+            if (nx || nyq_y || nz) g = 0.5f * (g + gopt(nx ? 1 : -1, nyq_y ? 1 : -1, nz ? 1 : -1));
+            g *= s_dc[xx] * dcy * s_dc[Nx + l];
+            *gc = g;
+          }
         } else {
           g = gk(fx, fy, fz);
           if (nx || nyq_y || nz)   // Hermitian partner: the non-Nyquist components change sign
             g = 0.5f * (g + gk(nx ? fx : -fx, nyq_y ? fy : -fy, nz ? fz : -fz));
+          g *= s_dc[xx] * dcy * s_dc[Nx + l];
         }
-        g *= s_dc[xx] * dcy * s_dc[Nx + l];
       }
       s_g[l * Nx + xx] = g;
     }
@@ -827,6 +843,15 @@ __global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
   fftx_body<MODE>(a, blockIdx.x, a.box, a.epart);
 }
 
+// After an optimal-influence x pass (every workgroup has written or read the g of
+// its points): the cache now holds g of this box.  A concurrent x pass of the same
+// box that reads the new key reads a complete table, one that reads the old key
+// recomputes the same values.
+__global__ void k_gcache_commit(const double* box, double* gbox, int* gvalid) {
+  if (threadIdx.x < 9) gbox[threadIdx.x] = box[threadIdx.x];
+  if (threadIdx.x == 0) *gvalid = 1;
+}
+
 // Batched passes: work item (box, x-plane) or (box, x-pass workgroup); per-box
 // argument templates in device memory; workgroups loop over the items.
 __global__ void __launch_bounds__(kSlabThreads) k_slab_fwd_batch(const SlabArgs* args,
@@ -872,6 +897,7 @@ XArgs make_x_args(const DevPlan& d, const double* box, bool energy) {
   x.epart = energy ? d.epart : nullptr;
   x.vpart = nullptr;
   x.alx = d.alias[0]; x.aly = d.alias[1]; x.alz = d.alias[2];
+  x.gcache = d.gcache; x.gbox = d.gbox; x.gvalid = d.gvalid;
   return x;
 }
 
@@ -966,7 +992,10 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
     launch_k(er, k_slab_fwd, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     if (vpart) launch_k(ex, k_fftx_fused<1>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
-    else if (d.opt) launch_k(ex, k_fftx_fused<2>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+    else if (d.opt) {
+      launch_k(ex, k_fftx_fused<2>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+      hipLaunchKernelGGL(k_gcache_commit, dim3(1), dim3(64), 0, s, box, d.gbox, d.gvalid);
+    }
     else launch_k(ex, k_fftx_fused<0>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     launch_k(ei, k_slab_inv, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
@@ -992,7 +1021,10 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
   if (vpart) launch_k(ex, k_fftx_fused<1>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
-  else if (d.opt) launch_k(ex, k_fftx_fused<2>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+  else if (d.opt) {
+    launch_k(ex, k_fftx_fused<2>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
+    hipLaunchKernelGGL(k_gcache_commit, dim3(1), dim3(64), 0, s, box, d.gbox, d.gvalid);
+  }
   else launch_k(ex, k_fftx_fused<0>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 

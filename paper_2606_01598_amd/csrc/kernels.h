@@ -94,6 +94,11 @@ struct DevPlan {
                            // influence 1 / (sum_m sinc^{2p}((f + m N_a)/N_a))^2
   bool opt;                // optimal influence function (aliasing sums)
   float* alias[3];         // optimal influence: [3][N_a] sinc^{2p}((f + m N_a)/N_a), m = -1, 0, 1
+  // optimal influence: g of every half-spectrum point [N_y][N_x][H] for the box in
+  // gbox, valid when *gvalid (the x pass reads it when the box is unchanged)
+  float* gcache;
+  double* gbox;            // [9]
+  int* gvalid;             // [1]
   bool slab;               // y-z planes transformed in LDS (z and y passes fused)
   size_t slab_lds;         // dynamic LDS bytes of a slab workgroup
   int rows_per_block;      // z-pass rows per block (even)
