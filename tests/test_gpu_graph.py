@@ -106,3 +106,19 @@ def test_graph_with_optimal_influence_and_sequential_plan():
         for k in KEYS:
             assert torch.equal(out[k], ref[k]), k
 
+
+
+def test_graph_at_the_32k_workload():
+    """The benchmark's configuration (32k ions, 100^3, p = 6, concurrent chains):
+    replays equal the eager steps bit for bit."""
+    plan, (pos, q, mu, box), v = _setup(32000, 3, mesh=(100, 100, 100))
+    ref = {k: t.clone() for k, t in plan.step(pos, q, mu, box, *v).items()}
+    plan.step(pos, q, mu, box, *v)
+    out = plan.step_capture(4, pos, q, mu, box, *v)
+    for _ in range(2):
+        for t in out.values():
+            t.fill_(float("nan"))
+        plan.step_replay()
+        plan.status()
+        for k in KEYS:
+            assert torch.equal(out[k], ref[k]), k
