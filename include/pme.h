@@ -81,7 +81,7 @@ extern "C" {
 /* ---- mesh strategies for pme_mesh_dims (Sec. 2.3.1) ------------------- */
 #define PME_MESH_POW2    0   /* N = 2^ceil(log2 N_target)                       */
 #define PME_MESH_SMOOTH  1   /* smallest N >= N_target with factors {2,3,5}      */
-#define PME_MESH_CEIL    2   /* N = N_target (may be rejected by pme_plan_create) */
+#define PME_MESH_CEIL    2   /* N = N_target (may be rejected by pme_plan) */
 
 typedef struct pme_plan_s* pme_plan_t;
 
@@ -105,17 +105,41 @@ typedef struct {
  * box, unknown strategy, or a dimension above 2^30). */
 int pme_mesh_dims(const double box[9], double spacing, int strategy, int32_t out[3]);
 
-/* Validate `desc` and allocate every workspace of a plan on the current HIP
- * device (meshes, spectrum, atom bins, FFT tables, deconvolution tables).
- * *out receives the plan (NULL on failure). */
-int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out);
+/* The plan of Sec. 2.3.1: mesh dimensions, assignment order p, alpha and the
+ * influence power gamma fixed once; the per-axis deconvolution factors
+ * |sinc(f/N_a)|^(-2 gamma p) of Eqs. Bk and influence (signed frequency f) are
+ * tabulated here, the cell inverse is formed on the device from the caller's box
+ * at every call.  Validates `desc` and allocates every workspace on the current
+ * HIP device (meshes, spectrum, atom bins, FFT tables, deconvolution tables).
+ *   desc   host pointer, read only during the call
+ *   out    host pointer; *out receives the plan (NULL on failure), owned by the
+ *          caller until pme_plan_destroy
+ * Returns PME_OK, PME_EINVAL, PME_EORDER, PME_EMESH, PME_EALPHA, PME_ENOMEM or
+ * PME_EHIP; on failure nothing stays allocated. */
+int pme_plan(const pme_desc_t* desc, pme_plan_t* out);
 
 /* Release a plan and its device memory (synchronises the device first).
  * NULL is ignored. */
 void pme_plan_destroy(pme_plan_t plan);
 
-/* Device bytes held by the plan's workspaces. */
+/* Device bytes held by the plan's workspaces (0 for NULL). */
 int64_t pme_plan_workspace_bytes(pme_plan_t plan);
+
+/* Identifier of the evaluation whose potential phi (Eqs. potential_k, ifft) the
+ * plan keeps for a following pme_backward under PME_F_KEEP_PHI: every call that
+ * writes the kept phi (pme_forward, pme_forward_cell, pme_step, pme_step_replay,
+ * and pme_backward when it recomputes phi) gives it a new identifier, unique per
+ * plan and increasing; 0 when no phi is kept (after pme_forward_quad, or before
+ * the first evaluation).  A caller that evaluates several frames on one plan
+ * (the batch loss of Sec. 2.4, Eq. loss) records the identifier after each
+ * forward and, before the backward of an earlier frame, calls pme_plan_drop_phi
+ * when the identifier has changed, so that phi is recomputed from that frame's
+ * inputs.  Host-side state: no synchronisation.  Returns 0 for NULL. */
+int64_t pme_plan_phi_id(pme_plan_t plan);
+
+/* Forget the kept phi: the next pme_backward recomputes it from its own
+ * (pos, q, mu, box).  Host-side state only.  PME_OK, or PME_EINVAL for NULL. */
+int pme_plan_drop_phi(pme_plan_t plan);
 
 /* Forward evaluation (Secs. 2.3.2-2.3.5).
  *   n                atoms, 0 <= n <= max_atoms
@@ -181,15 +205,21 @@ int pme_forward_quad(pme_plan_t plan, void* stream, int32_t n,
                      const double* box, double* energy, float* dE_dpos, float* dE_dq,
                      float* dE_dmu, float* dE_dtheta);
 
-/* Hessian-vector product of E^lr in (r, q, mu): with the gradient
+/* Hessian-vector product of E^lr in (r, q, mu): the derivative of the gradient
+ * of Eq. forces (and of the q and mu derivatives of Eqs. energy_recip, self_q,
+ * self_mu) that autograd through the pipeline of Sec. 2.3.5 takes when a loss on
+ * the forces is trained (Sec. 2.4, Eq. loss).  With the gradient
  * (dE/dr, dE/dq, dE/dmu) of pme_forward and cotangents (v_pos, v_q, v_mu)
  * on it, returns H v, which equals the vector-Jacobian product of the
  * gradient because H is symmetric.  With v_q = v_mu = 0 and v_pos = -dL/dF it
  * is the double backward of a force loss L(F).
+ *   pos, q, mu, box  as pme_forward (the point the Hessian is taken at)
  *   v_pos, v_q, v_mu device cotangents (shapes as pos, q, mu) or NULL (= 0)
  *   g_pos, g_q, g_mu device outputs (shapes as pos, q, mu) or NULL (skip)
- * With PME_F_KEEP_PHI the potential of the last pme_forward is reused, else it
- * is recomputed from (pos, q, mu, box). */
+ * With PME_F_KEEP_PHI the kept potential (pme_plan_phi_id) is reused: the caller
+ * asserts that it came from these same inputs.  Without the flag, or after
+ * pme_plan_drop_phi, phi is recomputed from (pos, q, mu, box) and kept.
+ * Returns PME_OK, PME_EINVAL, PME_ECAPACITY or PME_EHIP. */
 int pme_backward(pme_plan_t plan, void* stream, int32_t n,
                  const float* pos, const float* q, const float* mu, const double* box,
                  const float* v_pos, const float* v_q, const float* v_mu,
@@ -256,9 +286,11 @@ const float* pme_plan_phi(pme_plan_t plan);
 const float* pme_plan_rho(pme_plan_t plan);
 
 /* ---- batches of boxes ---------------------------------------------------
- * Many independent cells of uneven atom count and mesh (e.g. a training batch)
- * evaluated together: every kernel kind runs once for all boxes, over a list of
- * (box, work item) pairs, instead of once per box.  Per-atom arrays are packed:
+ * The training loss of Sec. 2.4 (Eq. loss) sums energy and force errors over a
+ * batch of structures; each structure is an independent cell with its own PME
+ * evaluation (Secs. 2.3.1-2.3.5).  Many such cells of uneven atom count and mesh
+ * are evaluated together here: every kernel kind runs once for all boxes, over a
+ * list of (box, work item) pairs, instead of once per box.  Per-atom arrays are packed:
  * the atoms of box b occupy [off_b, off_b + n_b), off = exclusive prefix sum of
  * n_atoms; cells are packed as [nbox][9] doubles and energies as [nbox][3].
  * Results equal those of one plan per box, bit for bit (same kernels, same
@@ -266,20 +298,26 @@ const float* pme_plan_rho(pme_plan_t plan);
  * fit in LDS (at most about 130 x 130). */
 typedef struct pme_batch_s* pme_batch_t;
 
-/* descs[b] describes box b (its flags are ignored: the backward always reuses
- * the potential of the preceding pme_batch_forward); n_atoms[b] >= 0 is its atom
- * count.  PME_EORDER if the orders differ, PME_EMESH if a mesh does not fit. */
-int pme_batch_create(const pme_desc_t* descs, int32_t nbox, const int32_t* n_atoms,
+/* The plan of a batch (Sec. 2.3.1 per box, Sec. 2.4 for the batch): descs[b]
+ * describes box b (its flags are ignored: the backward always reuses the
+ * potential of the preceding pme_batch_forward); n_atoms[b] >= 0 is its atom
+ * count.  Host arrays of nbox entries, read during the call; *out receives the
+ * batch (NULL on failure), released by pme_batch_destroy.  PME_EORDER if the
+ * orders differ, PME_EMESH if a mesh does not fit, PME_EINVAL for the optimal
+ * influence function or more than 2^31 - 1 atoms in all, PME_ENOMEM/PME_EHIP. */
+int pme_batch_plan(const pme_desc_t* descs, int32_t nbox, const int32_t* n_atoms,
                      pme_batch_t* out);
 void pme_batch_destroy(pme_batch_t batch);
 
-/* pme_forward of every box (packed arrays as above; NULL outputs skipped). */
+/* pme_forward of every box (Secs. 2.3.2-2.3.5 and Eq. forces per box; packed
+ * device arrays as above; NULL outputs skipped). */
 int pme_batch_forward(pme_batch_t batch, void* stream, const float* pos, const float* q,
                       const float* mu, const double* box, double* energy, float* dE_dpos,
                       float* dE_dq, float* dE_dmu);
 
-/* pme_backward of every box with the potentials of the last pme_batch_forward
- * (same pos, q, mu, box). */
+/* pme_backward of every box (the Hessian-vector product that the force term of
+ * Eq. loss needs) with the potentials of the last pme_batch_forward, which the
+ * caller asserts came from the same pos, q, mu, box. */
 int pme_batch_backward(pme_batch_t batch, void* stream, const float* pos, const float* q,
                        const float* mu, const double* box, const float* v_pos, const float* v_q,
                        const float* v_mu, float* g_pos, float* g_q, float* g_mu);
@@ -294,16 +332,19 @@ typedef struct {
     float* gf_pos; float* gf_q; float* gf_mu;                         /* (v_q = v_mu = 0) */
 } pme_batch_step_t;
 
-/* Capture forward + Hessian-vector product + force-loss double backward of the
- * whole batch into one HIP graph owned by the batch (replacing any previous
- * one); the buffer addresses are fixed at capture, their contents are read at
- * every replay.  Capture runs on a stream of the batch's own. */
-int pme_batch_capture(pme_batch_t batch, const pme_batch_step_t* step);
+/* Capture one training step of Eq. loss over the whole batch -- forward,
+ * Hessian-vector product and force-loss double backward -- into one HIP graph
+ * owned by the batch (replacing any previous one); nothing runs.  The buffer
+ * addresses in `step` (host struct, read during the call) are fixed at capture,
+ * their contents are read at every launch.  Capture runs on a stream of the
+ * batch's own.  PME_OK, PME_EINVAL or PME_EHIP. */
+int pme_batch_graph_capture(pme_batch_t batch, const pme_batch_step_t* step);
 
-/* Launch the captured graph on `stream`. */
-int pme_batch_replay(pme_batch_t batch, void* stream);
+/* Launch the graph of pme_batch_graph_capture on `stream` (ordered like other
+ * work on it).  PME_EINVAL without a captured graph, PME_EHIP on a launch error. */
+int pme_batch_graph_launch(pme_batch_t batch, void* stream);
 
-/* pme_status over every box of the batch. */
+/* pme_status over every box of the batch (synchronises `stream`). */
 int pme_batch_status(pme_batch_t batch, void* stream);
 
 /* ---- launch timing (measurement support) ------------------------------ */

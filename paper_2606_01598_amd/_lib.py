@@ -31,13 +31,14 @@ PME_MESH_SMOOTH = 1
 PME_MESH_CEIL = 2
 
 # every symbol include/pme.h declares
-EXPORTS = ("pme_mesh_dims", "pme_plan_create", "pme_plan_destroy", "pme_plan_workspace_bytes",
+EXPORTS = ("pme_mesh_dims", "pme_plan", "pme_plan_destroy", "pme_plan_workspace_bytes",
+           "pme_plan_phi_id", "pme_plan_drop_phi",
            "pme_forward", "pme_forward_cell", "pme_forward_quad", "pme_backward", "pme_step", "pme_step_capture", "pme_step_replay", "pme_status", "pme_strerror", "pme_last_hip_error",
            "pme_plan_phi", "pme_plan_rho", "pme_plan_timer", "pme_plan_timer_read",
            "pol_plan_create", "pol_plan_destroy", "pol_real", "pol_real_mixed", "pol_model",
            "pol_scf", "dip_plan_create", "dip_plan_destroy", "dip_features", "dip_forward",
-           "dip_backward", "dip_position_vjp", "dip_loss", "dip_adam", "pme_batch_create", "pme_batch_destroy",
-           "pme_batch_forward", "pme_batch_backward", "pme_batch_capture", "pme_batch_replay",
+           "dip_backward", "dip_position_vjp", "dip_loss", "dip_adam", "pme_batch_plan", "pme_batch_destroy",
+           "pme_batch_forward", "pme_batch_backward", "pme_batch_graph_capture", "pme_batch_graph_launch",
            "pme_batch_status")
 
 DIP_NFEAT, DIP_NCH, DIP_HIDDEN, DIP_NPARAM = 34, 16, 64, 7440
@@ -105,12 +106,16 @@ def load():
     vp, i32, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     lib.pme_mesh_dims.argtypes = [ctypes.POINTER(f64), f64, ctypes.c_int, ctypes.POINTER(i32)]
     lib.pme_mesh_dims.restype = ctypes.c_int
-    lib.pme_plan_create.argtypes = [ctypes.POINTER(PMEDesc), ctypes.POINTER(vp)]
-    lib.pme_plan_create.restype = ctypes.c_int
+    lib.pme_plan.argtypes = [ctypes.POINTER(PMEDesc), ctypes.POINTER(vp)]
+    lib.pme_plan.restype = ctypes.c_int
     lib.pme_plan_destroy.argtypes = [vp]
     lib.pme_plan_destroy.restype = None
     lib.pme_plan_workspace_bytes.argtypes = [vp]
     lib.pme_plan_workspace_bytes.restype = ctypes.c_int64
+    lib.pme_plan_phi_id.argtypes = [vp]
+    lib.pme_plan_phi_id.restype = ctypes.c_int64
+    lib.pme_plan_drop_phi.argtypes = [vp]
+    lib.pme_plan_drop_phi.restype = ctypes.c_int
     lib.pme_forward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.pme_forward.restype = ctypes.c_int
     lib.pme_forward_cell.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
@@ -153,19 +158,19 @@ def load():
     lib.pol_scf.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, vp,
                             ctypes.POINTER(i32), ctypes.POINTER(f64)]
     lib.pol_scf.restype = ctypes.c_int
-    lib.pme_batch_create.argtypes = [ctypes.POINTER(PMEDesc), i32, ctypes.POINTER(i32),
-                                     ctypes.POINTER(vp)]
-    lib.pme_batch_create.restype = ctypes.c_int
+    lib.pme_batch_plan.argtypes = [ctypes.POINTER(PMEDesc), i32, ctypes.POINTER(i32),
+                                   ctypes.POINTER(vp)]
+    lib.pme_batch_plan.restype = ctypes.c_int
     lib.pme_batch_destroy.argtypes = [vp]
     lib.pme_batch_destroy.restype = None
     lib.pme_batch_forward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.pme_batch_forward.restype = ctypes.c_int
     lib.pme_batch_backward.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.pme_batch_backward.restype = ctypes.c_int
-    lib.pme_batch_capture.argtypes = [vp, ctypes.POINTER(BatchStep)]
-    lib.pme_batch_capture.restype = ctypes.c_int
-    lib.pme_batch_replay.argtypes = [vp, vp]
-    lib.pme_batch_replay.restype = ctypes.c_int
+    lib.pme_batch_graph_capture.argtypes = [vp, ctypes.POINTER(BatchStep)]
+    lib.pme_batch_graph_capture.restype = ctypes.c_int
+    lib.pme_batch_graph_launch.argtypes = [vp, vp]
+    lib.pme_batch_graph_launch.restype = ctypes.c_int
     lib.pme_batch_status.argtypes = [vp, vp]
     lib.pme_batch_status.restype = ctypes.c_int
     lib.dip_plan_create.argtypes = [ctypes.POINTER(DipDesc), ctypes.POINTER(vp)]

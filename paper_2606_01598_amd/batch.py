@@ -36,7 +36,7 @@ class Batch:
             d.prefactor = float(prefactor)
         n = (ctypes.c_int32 * nbox)(*[int(v) for v in n_atoms])
         h = ctypes.c_void_p()
-        _lib.check(self._lib.pme_batch_create(descs, nbox, n, ctypes.byref(h)))
+        _lib.check(self._lib.pme_batch_plan(descs, nbox, n, ctypes.byref(h)))
         self.handle = h
         self.nbox = nbox
         self.n_atoms = [int(v) for v in n_atoms]
@@ -90,11 +90,11 @@ class Batch:
             t = step.get(name)
             setattr(st, name, None if t is None else t.data_ptr())
         torch.cuda.synchronize()
-        _lib.check(self._lib.pme_batch_capture(self.handle, ctypes.byref(st)))
+        _lib.check(self._lib.pme_batch_graph_capture(self.handle, ctypes.byref(st)))
         self._step = dict(step)
 
     def replay(self):
-        _lib.check(self._lib.pme_batch_replay(self.handle, _stream()))
+        _lib.check(self._lib.pme_batch_graph_launch(self.handle, _stream()))
 
     def status(self):
         _lib.check(self._lib.pme_batch_status(self.handle, _stream()))

@@ -20,6 +20,8 @@ struct pme_plan_s {
   int64_t bytes;
   int max_atoms;
   bool phi_valid;
+  int64_t phi_id = 0;    // evaluation that wrote the kept phi (0: none)
+  int64_t phi_gen = 0;   // last identifier handed out
   int set;        // counter set of the next binning (alternates)
   pme::KTimer timer;
   // PME_F_CONCURRENT: the cotangent chain's view of the plan (own records,
@@ -71,6 +73,12 @@ int hip_fail(hipError_t e) {
   return PME_EHIP;
 }
 
+// phi now holds the potential of a new evaluation (valid) or nothing reusable
+void mark_phi(pme_plan_s* pl, bool valid) {
+  pl->phi_valid = valid;
+  pl->phi_id = valid ? ++pl->phi_gen : 0;
+}
+
 bool five_smooth(long m) {
   if (m < 1) return false;
   for (long f : {2L, 3L, 5L})
@@ -85,6 +93,36 @@ int pick_bin(int N) {
 }
 
 double sinc(double x) { return x == 0.0 ? 1.0 : sin(M_PI * x) / (M_PI * x); }
+
+// e^{-2 pi i t / N} as a float pair: among the pairs within 3 units in the last
+// place of the rounded cosine and sine, the one whose squared modulus is closest to
+// 1 (ties: closest to the exact values).  Rounding each component on its own leaves
+// |w|^2 - 1 of order 1e-8 with a sign that does not average out over the few
+// twiddles a short transform uses, so the transform would scale the norm of its
+// output (and the k-space energy) by a small bias; the phase moves by at most a few
+// units in the last place instead.
+float2 twiddle(int t, int N) {
+  const double ang = -2.0 * M_PI * double(t) / double(N);
+  const double c0 = cos(ang), s0 = sin(ang);
+  float2 best = make_float2(float(c0), float(s0));
+  double score = 1e300;
+  float c = float(c0);
+  for (int i = 0; i < 3; ++i) c = nextafterf(c, -2.0f);
+  for (int i = -3; i <= 3; ++i, c = nextafterf(c, 2.0f)) {
+    float sv = float(s0);
+    for (int k = 0; k < 3; ++k) sv = nextafterf(sv, -2.0f);
+    for (int k = -3; k <= 3; ++k, sv = nextafterf(sv, 2.0f)) {
+      const double m = fabs(double(c) * c + double(sv) * sv - 1.0);
+      const double d = fabs(double(c) - c0) + fabs(double(sv) - s0);
+      const double sc = m + 1e-3 * d;
+      if (sc < score) {
+        score = sc;
+        best = make_float2(c, sv);
+      }
+    }
+  }
+  return best;
+}
 
 template <class T>
 hipError_t dev_alloc(T** p, size_t count, int64_t& bytes) {
@@ -173,7 +211,7 @@ int pme_mesh_dims(const double box[9], double spacing, int strategy, int32_t out
   return PME_OK;
 }
 
-int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
+int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
   if (!desc || !out) return PME_EINVAL;
   *out = nullptr;
   if (desc->order < 1 || desc->order > 7) return PME_EORDER;
@@ -344,8 +382,7 @@ int pme_plan_create(const pme_desc_t* desc, pme_plan_t* out) {
     float2* tw = new float2[N];
     float* dc = new float[N];
     for (int t = 0; t < N; ++t) {
-      const double ang = -2.0 * M_PI * double(t) / double(N);
-      tw[t] = make_float2(float(cos(ang)), float(sin(ang)));
+      tw[t] = twiddle(t, N);
       const int f = (t >= (N + 1) / 2) ? t - N : t;
       const double b = pow(fabs(sinc(double(f) / N)), double(p));
       dc[t] = float(pow(b, -2.0 * desc->influence_power));
@@ -428,6 +465,14 @@ void pme_plan_destroy(pme_plan_t plan) {
 int64_t pme_plan_workspace_bytes(pme_plan_t plan) { return plan ? plan->bytes : 0; }
 
 const float* pme_plan_phi(pme_plan_t plan) { return plan ? plan->d.phi : nullptr; }
+
+int64_t pme_plan_phi_id(pme_plan_t plan) { return plan ? plan->phi_id : 0; }
+
+int pme_plan_drop_phi(pme_plan_t plan) {
+  if (!plan) return PME_EINVAL;
+  mark_phi(plan, false);
+  return PME_OK;
+}
 const float* pme_plan_rho(pme_plan_t plan) { return plan ? plan->d.rho : nullptr; }
 
 }  // extern "C"
@@ -447,7 +492,7 @@ int forward_impl(pme_plan_t plan, void* stream, int32_t n, const float* pos, con
   hipError_t e;
   if (dE_dbox && !energy) energy = d.escr;
   double* vpart = dE_dbox ? d.vpart : nullptr;
-  plan->phi_valid = false;
+  mark_phi(plan, false);
   const int set = plan->set;
   plan->set ^= 1;
   if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
@@ -463,7 +508,7 @@ int forward_impl(pme_plan_t plan, void* stream, int32_t n, const float* pos, con
     return hip_fail(e);
   if (dE_dbox && (e = pme::launch_cell_grad(d, s, box, energy, dE_dbox)) != hipSuccess)
     return hip_fail(e);
-  plan->phi_valid = true;
+  mark_phi(plan, true);
   return PME_OK;
 }
 
@@ -494,7 +539,7 @@ int pme_forward_quad(pme_plan_t plan, void* stream, int32_t n, const float* pos,
   pme::KTimer& tm = plan->timer;
   hipError_t e;
   // phi of this call is not the one a following pme_backward may reuse
-  plan->phi_valid = false;
+  mark_phi(plan, false);
   const int set = plan->set;
   plan->set ^= 1;
   if ((e = pme::launch_bin_quad(d, s, set, n, pos, q, mu, theta, box, energy != nullptr,
@@ -528,7 +573,7 @@ int pme_backward(pme_plan_t plan, void* stream, int32_t n, const float* pos, con
     if ((e = pme::launch_spread(d, s, set, false, box, tm.next(PME_K_SPREAD))) != hipSuccess)
       return hip_fail(e);
     if ((e = pme::launch_convolve(d, s, box, d.phi, false, &tm)) != hipSuccess) return hip_fail(e);
-    plan->phi_valid = true;
+    mark_phi(plan, true);
   }
   const int set = plan->set;
   plan->set ^= 1;
@@ -565,7 +610,7 @@ int pme_step(pme_plan_t plan, void* stream, int32_t n, const float* pos, const f
   const DevPlan& dt = plan->dt;
   pme::KTimer& tm = plan->timer;
   hipError_t e;
-  plan->phi_valid = false;
+  mark_phi(plan, false);
   const int set = plan->set;
   plan->set ^= 1;
   const int tset = plan->tset;
@@ -596,7 +641,7 @@ int pme_step(pme_plan_t plan, void* stream, int32_t n, const float* pos, const f
   if ((e = pme::launch_gather_hvp(dt, s, tset, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q,
                                   g_mu, tm.next(PME_K_GATHER_HVP), &fwd)) != hipSuccess)
     return hip_fail(e);
-  plan->phi_valid = true;
+  mark_phi(plan, true);
   return PME_OK;
 }
 
@@ -612,6 +657,7 @@ int pme_step_capture(pme_plan_t plan, int32_t steps, int32_t n, const float* pos
     return hip_fail(e);
   const int set0 = plan->set, tset0 = plan->tset;
   const bool phi0 = plan->phi_valid;
+  const int64_t id0 = plan->phi_id;
   pme::KTimer& t = plan->timer;
   t.capturing = true;
   if ((e = hipStreamBeginCapture(plan->cap, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
@@ -630,6 +676,7 @@ int pme_step_capture(pme_plan_t plan, int32_t steps, int32_t n, const float* pos
   plan->set = set0;
   plan->tset = tset0;
   plan->phi_valid = phi0;
+  plan->phi_id = id0;
   if (rc != PME_OK || e != hipSuccess || !parity) {
     if (g) (void)hipGraphDestroy(g);
     if (rc != PME_OK) return rc;
@@ -652,7 +699,7 @@ int pme_step_replay(pme_plan_t plan, void* stream) {
   if (plan->set != plan->gset || plan->tset != plan->gtset) return PME_EINVAL;
   const hipError_t e = hipGraphLaunch(plan->sexec, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e);
-  plan->phi_valid = true;
+  mark_phi(plan, true);
   return PME_OK;
 }
 
@@ -785,7 +832,7 @@ pme::BatchIO bwd_io(const float* pos, const float* q, const float* mu, const dou
 
 extern "C" {
 
-int pme_batch_create(const pme_desc_t* descs, int32_t nbox, const int32_t* n_atoms,
+int pme_batch_plan(const pme_desc_t* descs, int32_t nbox, const int32_t* n_atoms,
                      pme_batch_t* out) {
   if (!descs || !n_atoms || !out || nbox < 1) return PME_EINVAL;
   *out = nullptr;
@@ -806,7 +853,7 @@ int pme_batch_create(const pme_desc_t* descs, int32_t nbox, const int32_t* n_ato
     pme_desc_t d = descs[b];
     d.flags = PME_F_KEEP_PHI;
     d.max_atoms = n_atoms[b] > 0 ? n_atoms[b] : 1;
-    const int rc = pme_plan_create(&d, &bt->plans[b]);
+    const int rc = pme_plan(&d, &bt->plans[b]);
     if (rc != PME_OK) {
       free_batch(bt);
       return rc;
@@ -863,7 +910,7 @@ int pme_batch_backward(pme_batch_t batch, void* stream, const float* pos, const 
                         bwd_io(pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q, g_mu));
 }
 
-int pme_batch_capture(pme_batch_t batch, const pme_batch_step_t* st) {
+int pme_batch_graph_capture(pme_batch_t batch, const pme_batch_step_t* st) {
   if (!batch || !st || !st->pos || !st->box) return PME_EINVAL;
   if (batch->exec) { (void)hipGraphExecDestroy(batch->exec); batch->exec = nullptr; }
   if (batch->graph) { (void)hipGraphDestroy(batch->graph); batch->graph = nullptr; }
@@ -890,7 +937,7 @@ int pme_batch_capture(pme_batch_t batch, const pme_batch_step_t* st) {
   return e == hipSuccess ? PME_OK : hip_fail(e);
 }
 
-int pme_batch_replay(pme_batch_t batch, void* stream) {
+int pme_batch_graph_launch(pme_batch_t batch, void* stream) {
   if (!batch || !batch->exec) return PME_EINVAL;
   const hipError_t e = hipGraphLaunch(batch->exec, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? PME_OK : hip_fail(e);

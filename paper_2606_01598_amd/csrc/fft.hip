@@ -484,7 +484,7 @@ struct XArgs {
   const float* dcx;
   const float* dcy;
   const float* dcz;
-  float alpha;
+  double alpha;
   double* epart;   // may be null
   // cell gradient (the VIR variant): per workgroup the six sums over its points of
   // w |rho~|^2 g (1/k^2 + 1/(4 alpha^2)) k_c k_d (cc, dd, ..: xx yy zz xy xz yz)
@@ -576,7 +576,10 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
   // g of the workgroup's points into LDS (issued while the line loads are in flight)
   auto gtable = [&]() {
     const Cell c = cell_from_box(box);
-    float M[3][3];
+    // the reciprocal metric, 1/(4 alpha^2) and k^2 in double precision: rounded
+    // to float they would bias every g(k) alike (about 1e-7 relative, which the
+    // near cancellation of E_recip against the self terms would amplify in E^lr)
+    double M[3][3];
 #pragma unroll
     for (int p = 0; p < 3; ++p)
 #pragma unroll
@@ -584,17 +587,18 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
         double m = 0.0;
 #pragma unroll
         for (int g = 0; g < 3; ++g) m += c.inv[3 * g + p] * c.inv[3 * g + q];
-        M[p][q] = float(4.0 * M_PI * M_PI * m);
+        M[p][q] = 4.0 * M_PI * M_PI * m;
       }
-    const float inv4a2 = 1.0f / (4.0f * a.alpha * a.alpha);
+    const double inv4a2 = 1.0 / (4.0 * a.alpha * a.alpha);
     const int fyi = signed_freq(y, Ny);
     const float fy = float(fyi);
     const bool nyq_y = ((Ny & 1) == 0) && (2 * fyi == -Ny);
     const float dcy = a.dcy[y];
     auto gk = [&](float px, float py, float pz) {
-      const float k2 = M[0][0] * px * px + M[1][1] * py * py + M[2][2] * pz * pz +
-                       2.0f * (M[0][1] * px * py + M[0][2] * px * pz + M[1][2] * py * pz);
-      return 4.0f * float(M_PI) / k2 * expf(-k2 * inv4a2);
+      const double x = px, y = py, z = pz;
+      const double k2 = M[0][0] * x * x + M[1][1] * y * y + M[2][2] * z * z +
+                        2.0 * (M[0][1] * x * y + M[0][2] * x * z + M[1][2] * y * z);
+      return float(4.0 * M_PI / k2 * exp(-k2 * inv4a2));
     };
     float aly3[3] = {0.0f, 0.0f, 0.0f};
     // OPT: g from the cache when it holds this box (a uniform decision)
@@ -893,7 +897,7 @@ XArgs make_x_args(const DevPlan& d, const double* box, bool energy) {
   for (int k = 0; k < 3; ++k) x.N[k] = d.N[k];
   x.H = d.H; x.kt = d.ktile; x.ktd = make_fast_div(d.ktile); x.spec = d.spec; x.box = box;
   x.dcx = d.deconv[0]; x.dcy = d.deconv[1]; x.dcz = d.deconv[2];
-  x.alpha = float(d.alpha);
+  x.alpha = d.alpha;
   x.epart = energy ? d.epart : nullptr;
   x.vpart = nullptr;
   x.alx = d.alias[0]; x.aly = d.alias[1]; x.alz = d.alias[2];

@@ -47,6 +47,23 @@ constexpr double ce_angle(int m, int R) {
   return kTwoPi * double(m) / double(R);
 }
 
+// A constant of the transform split into a float and the float of its remainder,
+// so that x * (hi + lo) is formed with the constant accurate to about 2^-48.  A
+// constant rounded to one float changes every product it forms in the same
+// direction, so the transform would no longer preserve the norm on average
+// (Parseval: sum |X|^2 = N sum |x|^2) but scale it by 1 + O(1e-8) per stage; the
+// k-space energy sum of Eq. energy_recip would inherit that bias.
+struct KConst {
+  float hi, lo;
+};
+constexpr KConst kconst(double v) { return KConst{float(v), float(v - double(float(v)))}; }
+// x * k
+__host__ __device__ __forceinline__ float kmul(float x, KConst k) { return fmaf(x, k.hi, x * k.lo); }
+// x * k + acc
+__host__ __device__ __forceinline__ float kfma(float x, KConst k, float acc) {
+  return fmaf(x, k.hi, fmaf(x, k.lo, acc));
+}
+
 __host__ __device__ __forceinline__ float2 c_add(float2 a, float2 b) {
   return make_float2(a.x + b.x, a.y + b.y);
 }
@@ -63,13 +80,17 @@ __host__ __device__ __forceinline__ float2 c_imul(float2 a, float s) {
 // a e^{s 2 pi i M / R}
 template <int R, int M>
 __host__ __device__ __forceinline__ float2 c_twiddle(float2 a, float s) {
-  constexpr float c = float(ce_cos(ce_angle(M, R)));
-  constexpr float sn = float(ce_sin(ce_angle(M, R)));
+  constexpr KConst c = kconst(ce_cos(ce_angle(M, R)));
+  constexpr KConst sn = kconst(ce_sin(ce_angle(M, R)));
   if constexpr (M % R == 0) {
     return a;
+  } else if constexpr (c.lo == 0.0f && sn.lo == 0.0f) {
+    // exact constants (quarter and half turns, 1/2 ...)
+    const float ss = s * sn.hi;
+    return make_float2(a.x * c.hi - a.y * ss, a.x * ss + a.y * c.hi);
   } else {
-    const float ss = s * sn;
-    return make_float2(a.x * c - a.y * ss, a.x * ss + a.y * c);
+    // s = +-1: s * (a * sn) is exact
+    return make_float2(kfma(a.x, c, -s * kmul(a.y, sn)), kfma(a.y, c, s * kmul(a.x, sn)));
   }
 }
 
@@ -99,10 +120,12 @@ struct Dft<2> {
 template <>
 struct Dft<3> {
   __host__ __device__ static __forceinline__ void run(float2 (&v)[3], float s) {
-    const float c = -0.5f, sn = 0.86602540378443864676f;
+    constexpr float c = -0.5f;
+    constexpr KConst sn = kconst(0.86602540378443864676);
     const float2 t1 = c_add(v[1], v[2]);
     const float2 t2 = make_float2(v[0].x + c * t1.x, v[0].y + c * t1.y);
-    const float2 t3 = c_imul(c_sub(v[1], v[2]), s * sn);
+    const float2 d = c_sub(v[1], v[2]);
+    const float2 t3 = c_imul(make_float2(kmul(d.x, sn), kmul(d.y, sn)), s);
     v[0] = c_add(v[0], t1);
     v[1] = c_add(t2, t3);
     v[2] = c_sub(t2, t3);
@@ -124,14 +147,18 @@ struct Dft<4> {
 template <>
 struct Dft<5> {
   __host__ __device__ static __forceinline__ void run(float2 (&v)[5], float s) {
-    const float c1 = 0.30901699437494742410f, c2 = -0.80901699437494742410f;
-    const float s1 = 0.95105651629515357212f, s2 = 0.58778525229247312917f;
+    constexpr KConst c1 = kconst(0.30901699437494742410), c2 = kconst(-0.80901699437494742410);
+    constexpr KConst s1 = kconst(0.95105651629515357212), s2 = kconst(0.58778525229247312917);
     const float2 t1 = c_add(v[1], v[4]), t2 = c_add(v[2], v[3]);
     const float2 t3 = c_sub(v[1], v[4]), t4 = c_sub(v[2], v[3]);
-    const float2 a1 = make_float2(v[0].x + c1 * t1.x + c2 * t2.x, v[0].y + c1 * t1.y + c2 * t2.y);
-    const float2 a2 = make_float2(v[0].x + c2 * t1.x + c1 * t2.x, v[0].y + c2 * t1.y + c1 * t2.y);
-    const float2 b1 = c_imul(make_float2(s1 * t3.x + s2 * t4.x, s1 * t3.y + s2 * t4.y), s);
-    const float2 b2 = c_imul(make_float2(s2 * t3.x - s1 * t4.x, s2 * t3.y - s1 * t4.y), s);
+    const float2 a1 = make_float2(kfma(t1.x, c1, kfma(t2.x, c2, v[0].x)),
+                                  kfma(t1.y, c1, kfma(t2.y, c2, v[0].y)));
+    const float2 a2 = make_float2(kfma(t1.x, c2, kfma(t2.x, c1, v[0].x)),
+                                  kfma(t1.y, c2, kfma(t2.y, c1, v[0].y)));
+    const float2 b1 = c_imul(make_float2(kfma(t3.x, s1, kmul(t4.x, s2)),
+                                         kfma(t3.y, s1, kmul(t4.y, s2))), s);
+    const float2 b2 = c_imul(make_float2(kfma(t3.x, s2, -kmul(t4.x, s1)),
+                                         kfma(t3.y, s2, -kmul(t4.y, s1))), s);
     v[0] = c_add(v[0], c_add(t1, t2));
     v[1] = c_add(a1, b1);
     v[4] = c_sub(a1, b1);

@@ -37,7 +37,15 @@ constexpr int spline_offset(int p) {
   return off;
 }
 
-constexpr SplineTables make_spline_tables() {
+// (p - 1)!: the tables with `whole` set hold (p - 1)! N_p, whose coefficients are
+// integers (exact in float).
+constexpr int spline_norm(int p) {
+  int f = 1;
+  for (int k = 2; k < p; ++k) f *= k;
+  return f;
+}
+
+constexpr SplineTables make_spline_tables(bool whole = false) {
   SplineTables t{};
   double a[PME_MAX_ORDER][PME_MAX_ORDER] = {};   // pieces of N_p, a[piece][power]
   double b[PME_MAX_ORDER][PME_MAX_ORDER] = {};
@@ -67,13 +75,25 @@ constexpr SplineTables make_spline_tables() {
         for (int k = 0; k < p; ++k) {
           double fall = 1.0;
           for (int m = 0; m < d; ++m) fall *= (k - m);
-          t.coef[off + (d * p + pc) * p + k] = (k >= d) ? float(a[pc][k] * fall) : 0.0f;
+          double v = (k >= d) ? a[pc][k] * fall : 0.0;
+          if (whole) {
+            // an integer up to rounding in the recursion: take the nearest one
+            v *= spline_norm(p);
+            v = double(static_cast<long long>(v + (v >= 0.0 ? 0.5 : -0.5)));
+          }
+          t.coef[off + (d * p + pc) * p + k] = float(v);
         }
   }
   return t;
 }
 
 static __constant__ SplineTables c_spline = make_spline_tables();
+// (p - 1)! times the same: the spread accumulates with these, whose coefficients
+// are exact, and divides the sums by ((p - 1)!)^3 in double precision.  The rounded
+// coefficients of c_spline make the weights of a stencil sum to 1 + O(2e-8) on
+// average (a bias, not noise), which would scale the density and the k-space
+// energy of Eq. energy_recip alike.
+static __constant__ SplineTables c_spline_whole = make_spline_tables(true);
 
 // w[d][j], d = 0..D: d-th derivative (w.r.t. the mesh coordinate) of the weight of
 // stencil point j.
@@ -90,6 +110,28 @@ __device__ __forceinline__ void spline_weights(float f, float (&w)[D + 1][P]) {
         continue;
       }
       const float* c = &c_spline.coef[off + (d * P + pc) * P];
+      float acc = c[P - 1];
+#pragma unroll
+      for (int k = P - 2; k >= d; --k) acc = fmaf(acc, f, c[k]);
+      w[d][j] = acc;
+    }
+  }
+}
+
+// spline_weights times (p - 1)! from the integer tables.
+template <int P, int D>
+__device__ __forceinline__ void spline_weights_whole(float f, float (&w)[D + 1][P]) {
+  constexpr int off = spline_offset(P);
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    const int pc = P - 1 - j;
+#pragma unroll
+    for (int d = 0; d <= D; ++d) {
+      if (d > P - 1) {
+        w[d][j] = 0.0f;
+        continue;
+      }
+      const float* c = &c_spline_whole.coef[off + (d * P + pc) * P];
       float acc = c[P - 1];
 #pragma unroll
       for (int k = P - 2; k >= d; --k) acc = fmaf(acc, f, c[k]);

@@ -425,11 +425,14 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
     s_nr[0] = 0;
     s_ntask = 0;
   }
-  // each contribution is bounded by 8 sum_k |c_k| <= 8 cmax: scale it below 2^31
+  // each contribution is bounded by 8 sum_k |c_k| <= 8 cmax with normalised weights;
+  // the staged weights are the whole-number ones ((P-1)! times larger per axis), so
+  // the bound is 8 cmax ((P-1)!)^3: scale it below 2^31
+  constexpr float kWhole3 = float(spline_norm(P)) * float(spline_norm(P)) * float(spline_norm(P));
   float scale = 1.0f;
   {
     const float cm = __uint_as_float(*a.cmax);
-    if (cm > 0.0f && isfinite(cm)) scale = ldexpf(1.0f, 31 - (ilogbf(8.0f * cm) + 1));
+    if (cm > 0.0f && isfinite(cm)) scale = ldexpf(1.0f, 31 - (ilogbf(8.0f * cm * kWhole3) + 1));
   }
   const int TZP = T[2] + 1;                   // padded z stride; column T_z is scratch
   const int tpad = T[0] * T[1] * TZP;
@@ -587,7 +590,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
           const int e = t / 3, ax = t - 3 * e;
           float* ent = s_ent + e * ES;
           float w[D + 1][P];
-          spline_weights<P, D>(ent[NW + NC + 6 + ax], w);
+          spline_weights_whole<P, D>(ent[NW + NC + 6 + ax], w);
           const float sc = (ax == 0) ? scale : 1.0f;
 #pragma unroll
           for (int d = 0; d <= D; ++d)
@@ -665,7 +668,8 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
   }
 
   // 3. write the tile back (plain stores; every point is owned by this tile)
-  const float inv_scale = 1.0f / scale;
+  // the fixed-point unit and the whole-number weights undone in one double factor
+  const double inv_scale = 1.0 / (double(scale) * double(kWhole3));
   const int tvol = T[0] * T[1] * T[2];
   // tile extents are uniform: the multiply-high divisors are made once
   const uint32_t tz = uint32_t(__builtin_amdgcn_readfirstlane(T[2]));
@@ -681,7 +685,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
     const long long v = (long long)s_tile[r * TZP + lz];
     const double vd = fma(double(int(v >> 32)), 4294967296.0, double(uint32_t(v)));
     a.rho[(size_t(t0[0] + lx) * a.N[1] + (t0[1] + ly)) * a.N[2] + t0[2] + lz] =
-        float(vd) * inv_scale;
+        float(vd * inv_scale);
   }
 }
 

@@ -6,7 +6,7 @@ kernels; this module only checks shapes and passes pointers and the current
 stream.
 
 * ``mesh_dims(box, spacing, strategy)``        -- Eq. mesh_target + strategies
-* ``Plan``                                     -- pme_plan_create / destroy
+* ``Plan``                                     -- pme_plan / destroy
 * ``Plan.forward(...)``                        -- pme_forward (``cell=True``: pme_forward_cell,
   also dE/dbox at fixed Cartesian inputs)
 * ``Plan.backward(...)``                       -- pme_backward (Hessian-vector product)
@@ -62,7 +62,7 @@ def _atoms(name, t, n, cols, device):
 
 
 class Plan:
-    """A PME plan: mesh, order, alpha and the device workspaces (pme_plan_create)."""
+    """A PME plan: mesh, order, alpha and the device workspaces (pme_plan)."""
 
     def __init__(self, mesh, order: int, alpha: float, max_atoms: int, influence_power: float = 1.0,
                  prefactor: float = 1.0, keep_phi: bool = True, device=None, tile=None,
@@ -90,7 +90,7 @@ class Plan:
         self.influence_power = float(influence_power)
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            _lib.check(self._lib.pme_plan_create(ctypes.byref(d), ctypes.byref(handle)))
+            _lib.check(self._lib.pme_plan(ctypes.byref(d), ctypes.byref(handle)))
         self.handle = handle
 
     def __del__(self):
@@ -232,6 +232,14 @@ class Plan:
         """pme_step_replay on the current stream."""
         _lib.check(self._lib.pme_step_replay(self.handle, _stream()))
 
+    def phi_id(self) -> int:
+        """pme_plan_phi_id: identifier of the evaluation whose phi the plan keeps."""
+        return int(self._lib.pme_plan_phi_id(self.handle))
+
+    def drop_phi(self) -> None:
+        """pme_plan_drop_phi: the next backward recomputes phi from its own inputs."""
+        _lib.check(self._lib.pme_plan_drop_phi(self.handle))
+
     def status(self) -> None:
         """pme_status: synchronise and raise on device-detected errors."""
         _lib.check(self._lib.pme_status(self.handle, _stream()))
@@ -279,12 +287,17 @@ class _PMEGrad(torch.autograd.Function):
     """(dE/dpos, dE/dq, dE/dmu) as a differentiable function of (pos, q, mu).
 
     Its backward is the Hessian-vector product of pme_backward, which is what a
-    force loss needs when the forces were taken with create_graph=True.
+    force loss needs when the forces were taken with create_graph=True.  The plan
+    keeps the potential of its last evaluation; ``phi_id`` names the evaluation
+    of these inputs, and when the plan has evaluated other inputs since (several
+    frames of a batch loss through one plan), the kept potential is dropped so
+    that pme_backward recomputes it from these inputs.
     """
 
     @staticmethod
-    def forward(ctx, pos, q, mu, box, plan, g_pos, g_q, g_mu):
+    def forward(ctx, pos, q, mu, box, plan, phi_id, g_pos, g_q, g_mu):
         ctx.plan = plan
+        ctx.phi_id = phi_id
         ctx.save_for_backward(pos, q, mu, box)
         return g_pos, g_q, g_mu
 
@@ -292,9 +305,11 @@ class _PMEGrad(torch.autograd.Function):
     def backward(ctx, v_pos, v_q, v_mu):
         pos, q, mu, box = ctx.saved_tensors
         plan = ctx.plan
+        if plan.phi_id() != ctx.phi_id:
+            plan.drop_phi()
         v = [None if t is None else t.contiguous().float() for t in (v_pos, v_q, v_mu)]
         r = plan.backward(pos.detach(), q.detach(), mu.detach(), box, *v)
-        return r["g_pos"], r["g_q"], r["g_mu"], None, None, None, None, None
+        return r["g_pos"], r["g_q"], r["g_mu"], None, None, None, None, None, None
 
 
 class _PMEEnergy(torch.autograd.Function):
@@ -303,6 +318,7 @@ class _PMEEnergy(torch.autograd.Function):
         cell = box.requires_grad
         r = plan.forward(pos.detach(), q.detach(), mu.detach(), box.detach(), cell=cell)
         ctx.plan = plan
+        ctx.phi_id = plan.phi_id()
         gb = r["dE_dbox"] if cell else torch.zeros(0, dtype=torch.float64, device=box.device)
         ctx.save_for_backward(pos, q, mu, box, r["dE_dpos"], r["dE_dq"], r["dE_dmu"], gb)
         return r["energy"].sum()
@@ -311,7 +327,7 @@ class _PMEEnergy(torch.autograd.Function):
     def backward(ctx, gE):
         pos, q, mu, box, gp, gq, gm, gb = ctx.saved_tensors
         if torch.is_grad_enabled():
-            gp, gq, gm = _PMEGrad.apply(pos, q, mu, box.detach(), ctx.plan, gp, gq, gm)
+            gp, gq, gm = _PMEGrad.apply(pos, q, mu, box.detach(), ctx.plan, ctx.phi_id, gp, gq, gm)
         s = gE.to(torch.float32)
         # the cell gradient is first order: a constant for a second differentiation
         g_box = gb * gE.to(torch.float64) if gb.numel() else None

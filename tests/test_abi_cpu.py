@@ -96,14 +96,14 @@ def test_plan_create_validation(kw, code):
     lib = _lib_or_skip()
     h = ctypes.c_void_p()
     d = _desc(**kw)
-    assert lib.pme_plan_create(ctypes.byref(d), ctypes.byref(h)) == code
+    assert lib.pme_plan(ctypes.byref(d), ctypes.byref(h)) == code
     assert not h.value
 
 
 def test_null_arguments():
     lib = _lib_or_skip()
     h = ctypes.c_void_p()
-    assert lib.pme_plan_create(None, ctypes.byref(h)) == _lib.PME_EINVAL
+    assert lib.pme_plan(None, ctypes.byref(h)) == _lib.PME_EINVAL
     assert lib.pme_forward(None, None, 0, None, None, None, None, None, None, None, None) == _lib.PME_EINVAL
     assert lib.pme_backward(None, None, 0, None, None, None, None, None, None, None, None, None,
                             None) == _lib.PME_EINVAL

@@ -204,6 +204,67 @@ def test_force_loss_double_backward_through_autograd():
     assert e1 <= RMS_REL_TOL and e2 <= RMS_REL_TOL
 
 
+def test_force_loss_two_frames_one_plan():
+    """The batch loss of Sec. 2.4 (Eq. loss) sums over frames: two frames through
+    one plan, forces of E1 + E2 with create_graph, one force loss, backward.  The
+    plan keeps the potential of the second frame only, so the first frame's
+    Hessian-vector product must recompute its own.  Every gradient of every frame
+    is compared with the oracle's H v (v_r = -dL/dF, v_q = v_mu = 0)."""
+    from paper_2606_01598_amd.pme import pme_energy
+    mesh, p, a = (24, 24, 24), 6, 0.35
+    frames = [synth.molten_box(400, 8, L=23.0), synth.molten_box(400, 9, L=23.0)]
+    plan = _plan(mesh, p, a, 400)
+    leaves, forces, targets = [], [], []
+    E = 0.0
+    for k, f in enumerate(frames):
+        pos, q, mu, box = to_dev(f)
+        for t in (pos, q, mu):
+            t.requires_grad_(True)
+        leaves.append((pos, q, mu))
+        E = E + pme_energy(pos, q, mu, box, plan)
+        targets.append(torch.tensor(np.random.default_rng(20 + k).normal(0, 0.05, (f.n, 3)),
+                                    dtype=torch.float32, device=dev()))
+    grads = torch.autograd.grad(E, [lv[0] for lv in leaves], create_graph=True)
+    loss = sum(((-g - t) ** 2).sum() for g, t in zip(grads, targets))
+    loss.backward()
+    for k, f in enumerate(frames):
+        ref = oracle_forward(f, mesh, p, a)
+        # dL/dF = 2 (F - Fref), F = -dE/dr: the cotangent on dE/dr is -dL/dF
+        vr = -2.0 * (-ref.dE_dpos - f32(host(targets[k])))
+        h = opme.hvp(f32(f.pos), f32(f.q), f32(f.mu), f.box, mesh, p, a, v_pos=vr)
+        pos, q, mu = leaves[k]
+        errs = [rms_rel(host(pos.grad), h[0]), rms_rel(host(q.grad), h[1]),
+                rms_rel(host(mu.grad), h[2])]
+        print("frame", k, "force-loss H v", [f"{e:.2e}" for e in errs], flush=True)
+        assert max(errs) <= RMS_REL_TOL, (k, errs)
+
+
+def test_phi_id_follows_evaluations():
+    """pme_plan_phi_id names the evaluation whose potential is kept; dropping it
+    makes the backward recompute (and keep) phi of its own inputs."""
+    f = synth.molten_box(200, 31, L=17.0)
+    g = synth.molten_box(200, 32, L=17.0)
+    mesh, p, a = (16, 16, 16), 6, 0.4
+    plan = _plan(mesh, p, a, f.n)
+    assert plan.phi_id() == 0
+    pf = to_dev(f)
+    pg = to_dev(g)
+    plan.forward(*pf)
+    i1 = plan.phi_id()
+    plan.forward(*pg)
+    i2 = plan.phi_id()
+    assert i1 > 0 and i2 > i1
+    v = synth.random_cotangents(f.n, 3, scale_r=0.1)
+    vt = [torch.tensor(x, dtype=torch.float32, device=dev()) for x in v]
+    plan.drop_phi()
+    assert plan.phi_id() == 0
+    out = plan.backward(*pf, *vt)
+    assert plan.phi_id() > i2
+    ref = oracle_hvp(f, mesh, p, a, v)
+    errs = [rms_rel(host(out[k]), r) for k, r in zip(("g_pos", "g_q", "g_mu"), ref)]
+    assert max(errs) <= RMS_REL_TOL, errs
+
+
 def test_finite_differences_config2():
     """FP32 GPU gradients against central differences of the GPU energy."""
     f = synth.molten_box(1000, 1, L=31.5)
@@ -223,10 +284,18 @@ def test_finite_differences_config2():
     assert rel(fdm, float((out["dE_dmu"] * dm).sum())) < 1e-3
     d = torch.tensor(rng.normal(0, 1, (f.n, 3)), dtype=torch.float32, device=dev())
     d /= d.norm()
-    an = float((out["dE_dpos"] * d).sum())
-    best = min(rel((E(pos + h * d, q, mu) - E(pos - h * d, q, mu)) / (2 * h), an)
-               for h in (1e-1, 3e-2, 1e-2, 3e-3))
-    print("fd r", best, flush=True)
+    # along r: the directional derivative along the step the float32 positions
+    # actually take, against central differences of the FP32 energy.  Those carry
+    # about 1e-8 relative noise (E_recip ~ 1e3 here, the derivative along a unit
+    # global step ~ 0.04), so the sweep also holds a 0.3 A global step (0.005 A per
+    # atom), where the oracle's own truncation error is below 1e-4.
+    errs = []
+    for h in (3e-1, 1e-1, 3e-2, 1e-2, 3e-3):
+        pp, pm = pos + h * d, pos - h * d
+        an = float((out["dE_dpos"] * (pp - pm)).sum()) / 2
+        errs.append(rel((E(pp, q, mu) - E(pm, q, mu)) / 2, an))
+    best = min(errs)
+    print("fd r", [f"{e:.2e}" for e in errs], flush=True)
     assert best < 1e-3
 
 
