@@ -60,6 +60,7 @@ extern "C" {
 #define PME_ENOMEM     -6   /* device allocation failed                           */
 #define PME_EHIP       -7   /* a HIP runtime call failed (see pme_last_hip_error) */
 #define PME_ENONFINITE -8   /* device saw NaN/Inf in positions or box (pme_status) */
+#define PME_ESCRATCH   -9   /* pme_forward_noalloc: workspace above its fixed scratch */
 
 /* ---- plan flags ------------------------------------------------------ */
 /* Keep phi (the potential mesh) of the last pme_forward; a following
@@ -267,6 +268,29 @@ int pme_step_capture(pme_plan_t plan, int32_t steps, int32_t n,
  * it).  PME_EINVAL without a graph or when the counter-set parity differs from
  * the capture's. */
 int pme_step_replay(pme_plan_t plan, void* stream);
+
+/* pme_forward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results as pme_forward on a plan made from `desc` with
+ * max_atoms = n, but with no plan.  Every workspace (atom bins and records,
+ * counters, density, spectrum, potential, per-axis twiddle and deconvolution
+ * tables, energy partials) is carved from one fixed device array of
+ * PME_NOALLOC_SCRATCH_BYTES per GPU, held from the library's first use of that
+ * GPU until the process ends; the call makes no device or host allocation and
+ * does not synchronise.  The tables are rebuilt on the device by every call.
+ *   desc     host, read during the call; desc->max_atoms is ignored (sized for n);
+ *            PME_F_OPT_INFLUENCE is rejected (PME_EINVAL), the other flags have
+ *            no effect
+ *   other arguments and outputs as pme_forward
+ * Returns PME_ESCRATCH when the workspace of (desc, n) exceeds the array (about
+ * 27 MB for 32,000 atoms on 100^3), else as pme_forward.  All calls on one GPU
+ * share the array: calls that overlap on one GPU (two streams, or two host
+ * threads) race and give wrong results; calls ordered on one stream do not.
+ * Non-finite inputs are not reported (there is no plan for pme_status to read). */
+#define PME_NOALLOC_SCRATCH_BYTES (64 << 20)
+int pme_forward_noalloc(const pme_desc_t* desc, void* stream, int32_t n,
+                        const float* pos, const float* q, const float* mu, const double* box,
+                        double* energy, float* dE_dpos, float* dE_dq, float* dE_dmu);
 
 /* Synchronise `stream`, then return PME_ENONFINITE if any kernel of this plan
  * saw a non-finite position or box since the last pme_status call, or

@@ -21,6 +21,8 @@ PME_ECAPACITY = -5
 PME_ENOMEM = -6
 PME_EHIP = -7
 PME_ENONFINITE = -8
+PME_ESCRATCH = -9
+PME_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 PME_F_KEEP_PHI = 1
 PME_F_CONCURRENT = 2
@@ -32,7 +34,7 @@ PME_MESH_CEIL = 2
 
 # every symbol include/pme.h declares
 EXPORTS = ("pme_mesh_dims", "pme_plan", "pme_plan_destroy", "pme_plan_workspace_bytes",
-           "pme_plan_phi_id", "pme_plan_drop_phi",
+           "pme_plan_phi_id", "pme_plan_drop_phi", "pme_forward_noalloc",
            "pme_forward", "pme_forward_cell", "pme_forward_quad", "pme_backward", "pme_step", "pme_step_capture", "pme_step_replay", "pme_status", "pme_strerror", "pme_last_hip_error",
            "pme_plan_phi", "pme_plan_rho", "pme_plan_timer", "pme_plan_timer_read",
            "pol_plan_create", "pol_plan_destroy", "pol_real", "pol_real_mixed", "pol_model",
@@ -117,6 +119,9 @@ def load():
     lib.pme_plan_drop_phi.argtypes = [vp]
     lib.pme_plan_drop_phi.restype = ctypes.c_int
     lib.pme_forward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pme_forward_noalloc.argtypes = [ctypes.POINTER(PMEDesc), vp, i32, vp, vp, vp, vp, vp, vp,
+                                        vp, vp]
+    lib.pme_forward_noalloc.restype = ctypes.c_int
     lib.pme_forward.restype = ctypes.c_int
     lib.pme_forward_cell.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.pme_forward_cell.restype = ctypes.c_int

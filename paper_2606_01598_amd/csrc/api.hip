@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -13,6 +14,53 @@
 #include "kernels.h"
 
 using pme::DevPlan;
+
+// ---- table values shared by the host (plans) and the device (pme_forward_noalloc) ----
+namespace {
+
+__host__ __device__ double sinc(double x) { return x == 0.0 ? 1.0 : sin(M_PI * x) / (M_PI * x); }
+
+// e^{-2 pi i t / N} as a float pair: among the pairs within 3 units in the last
+// place of the rounded cosine and sine, the one whose squared modulus is closest to
+// 1 (ties: closest to the exact values).  Rounding each component on its own leaves
+// |w|^2 - 1 of order 1e-8 with a sign that does not average out over the few
+// twiddles a short transform uses, so the transform would scale the norm of its
+// output (and the k-space energy) by a small bias; the phase moves by at most a few
+// units in the last place instead.
+__host__ __device__ float2 twiddle(int t, int N) {
+  const double ang = -2.0 * M_PI * double(t) / double(N);
+  const double c0 = cos(ang), s0 = sin(ang);
+  float2 best = make_float2(float(c0), float(s0));
+  double score = 1e300;
+  float c = float(c0);
+  for (int i = 0; i < 3; ++i) c = nextafterf(c, -2.0f);
+  for (int i = -3; i <= 3; ++i, c = nextafterf(c, 2.0f)) {
+    float sv = float(s0);
+    for (int k = 0; k < 3; ++k) sv = nextafterf(sv, -2.0f);
+    for (int k = -3; k <= 3; ++k, sv = nextafterf(sv, 2.0f)) {
+      const double m = fabs(double(c) * c + double(sv) * sv - 1.0);
+      const double d = fabs(double(c) - c0) + fabs(double(sv) - s0);
+      const double sc = m + 1e-3 * d;
+      if (sc < score) {
+        score = sc;
+        best = make_float2(c, sv);
+      }
+    }
+  }
+  return best;
+}
+
+// Deconvolution factor |sinc(f/N)|^(-2 gamma p) of Eqs. Bk and influence at index t
+// (signed frequency f = t - N [t >= ceil(N/2)]).
+__host__ __device__ float deconv_factor(int t, int N, int p, double gamma) {
+  const int f = (t >= (N + 1) / 2) ? t - N : t;
+  const double b = pow(fabs(sinc(double(f) / N)), double(p));
+  return float(pow(b, -2.0 * gamma));
+}
+
+}  // namespace
+
+
 
 struct pme_plan_s {
   pme_desc_t desc;
@@ -92,36 +140,138 @@ int pick_bin(int N) {
   return N;
 }
 
-double sinc(double x) { return x == 0.0 ? 1.0 : sin(M_PI * x) / (M_PI * x); }
 
-// e^{-2 pi i t / N} as a float pair: among the pairs within 3 units in the last
-// place of the rounded cosine and sine, the one whose squared modulus is closest to
-// 1 (ties: closest to the exact values).  Rounding each component on its own leaves
-// |w|^2 - 1 of order 1e-8 with a sign that does not average out over the few
-// twiddles a short transform uses, so the transform would scale the norm of its
-// output (and the k-space energy) by a small bias; the phase moves by at most a few
-// units in the last place instead.
-float2 twiddle(int t, int N) {
-  const double ang = -2.0 * M_PI * double(t) / double(N);
-  const double c0 = cos(ang), s0 = sin(ang);
-  float2 best = make_float2(float(c0), float(s0));
-  double score = 1e300;
-  float c = float(c0);
-  for (int i = 0; i < 3; ++i) c = nextafterf(c, -2.0f);
-  for (int i = -3; i <= 3; ++i, c = nextafterf(c, 2.0f)) {
-    float sv = float(s0);
-    for (int k = 0; k < 3; ++k) sv = nextafterf(sv, -2.0f);
-    for (int k = -3; k <= 3; ++k, sv = nextafterf(sv, 2.0f)) {
-      const double m = fabs(double(c) * c + double(sv) * sv - 1.0);
-      const double d = fabs(double(c) - c0) + fabs(double(sv) - s0);
-      const double sc = m + 1e-3 * d;
-      if (sc < score) {
-        score = sc;
-        best = make_float2(c, sv);
-      }
+
+
+
+// Descriptor checks shared by every entry point that takes one.
+int check_desc(const pme_desc_t& desc) {
+  if (desc.order < 1 || desc.order > 7) return PME_EORDER;
+  for (int a = 0; a < 3; ++a)
+    if (desc.mesh[a] < 2 || desc.mesh[a] > 1024 || !five_smooth(desc.mesh[a])) return PME_EMESH;
+  if (!(desc.alpha > 0.0) || !isfinite(desc.alpha) || !(desc.influence_power >= 0.0) ||
+      !isfinite(desc.influence_power) || !isfinite(desc.prefactor))
+    return PME_EALPHA;
+  if (desc.max_atoms < 1 ||
+      (desc.flags & ~(PME_F_KEEP_PHI | PME_F_CONCURRENT | PME_F_OPT_INFLUENCE)))
+    return PME_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (desc.tile[a] < 0 || desc.tile[a] > 1024) return PME_EINVAL;
+  return PME_OK;
+}
+
+// Geometry of a plan (host only, nothing allocated): mesh and order, atom bins and
+// their capacity, spread and gather tiles, spread staging, FFT layout.  `nbins`
+// receives the number of atom bins.  PME_EMESH when no tile or FFT layout fits.
+int plan_geometry(const pme_desc_t& desc, DevPlan& d, long& nbins_out) {
+  const int p = desc.order;
+  for (int a = 0; a < 3; ++a) d.N[a] = desc.mesh[a];
+  d.H = d.N[2] / 2 + 1;
+  d.p = p;
+  d.alpha = desc.alpha;
+  d.prefactor = desc.prefactor;
+  d.opt = (desc.flags & PME_F_OPT_INFLUENCE) != 0;
+  const long M = long(d.N[0]) * d.N[1] * d.N[2];
+
+  // bins of B cells and mesh tiles of T = k B cells (targets 8 x 8 x 16 unless the
+  // descriptor sets them)
+  long nbins = 1;
+  int target[3] = {8, 8, 16};
+  for (int a = 0; a < 3; ++a)
+    if (desc.tile[a] > 0) target[a] = desc.tile[a];
+  for (int a = 0; a < 3; ++a) {
+    d.B[a] = pick_bin(d.N[a]);
+    d.nb[a] = d.N[a] / d.B[a];
+    nbins *= d.nb[a];
+    int k = (target[a] + d.B[a] / 2) / d.B[a];
+    if (k < 1) k = 1;
+    if (k > d.nb[a]) k = d.nb[a];
+    d.T[a] = k * d.B[a];
+  }
+  // shrink tiles until the spread tile, the scanned bin range, the gather's own
+  // bins and its LDS field region fit their bounds
+  for (;;) {
+    long range = 1, own = 1, region = 2;
+    for (int a = 0; a < 3; ++a) {
+      long k = (d.T[a] + p - 1 + d.B[a] - 1) / d.B[a] + 1;
+      range *= (k < d.nb[a] ? k : d.nb[a]);
+      own *= d.T[a] / d.B[a];
+      region *= d.T[a] + p - 1;
+    }
+    const long tpad = long(d.T[0]) * d.T[1] * (d.T[2] + 1);
+    // two field regions and their row and z tables
+    const long rows = long(d.T[0] + p - 1) * (d.T[1] + p - 1) + (d.T[2] + p - 1);
+    if (range <= pme::kMaxBinRange && own <= 256 && tpad <= pme::kTileLds &&
+        region * 4 + rows * 4 <= pme::kGatherLds &&
+        long(pme::spread_lds_bytes(int(tpad), int(range), 64, p, 2)) <= pme::kBigLds)
+      break;
+    int big = 0;
+    for (int a = 1; a < 3; ++a)
+      if (d.T[a] / d.B[a] > d.T[big] / d.B[big]) big = a;
+    if (d.T[big] == d.B[big]) return PME_EMESH;
+    d.T[big] -= d.B[big];
+  }
+  for (int a = 0; a < 3; ++a) d.nt[a] = (d.N[a] + d.T[a] - 1) / d.T[a];
+  {
+    // spread staging: records per round such that five workgroups share a CU's
+    // 160 KiB of LDS (all tiles of a 100^3 mesh resident at once; 1 KiB per
+    // workgroup is left for static LDS and allocation granularity), at least 64
+    long range = 1;
+    for (int a = 0; a < 3; ++a) {
+      long k = (d.T[a] + p - 1 + d.B[a] - 1) / d.B[a] + 1;
+      range *= (k < d.nb[a] ? k : d.nb[a]);
+    }
+    d.nbr_max = int(range);
+    const int tw = d.T[0] * d.T[1] * (d.T[2] + 1);
+    for (int deg = 1; deg <= 2; ++deg) {
+      const long fixed = long(pme::spread_lds_bytes(tw, d.nbr_max, 0, p, deg));
+      const long per = 4L * pme::spread_entry_words(p, deg) + 2L * p;
+      long ch = (32768 - 1024 - fixed) / per;
+      if (ch > 256) ch = 256;
+      if (ch < 64) ch = 64;
+      d.spread_ch[deg - 1] = int(ch);
     }
   }
-  return best;
+  {
+    const double per_bin = double(desc.max_atoms) * d.B[0] * d.B[1] * d.B[2] / double(M);
+    long cap = long(ceil(2.0 * per_bin)) + 8;
+    if (cap > 64) cap = 64;
+    d.cap = int(cap);
+  }
+  // FFT layout
+  for (int a = 0; a < 3; ++a)
+    if (!pme::radix_plan(d.N[a], d.ax[a])) return PME_EMESH;
+  {
+    // slab mode when a y-z plane of the half spectrum (two LDS buffers) fits
+    const long npairs = (d.N[1] + 1) / 2;
+    long buf = npairs * d.N[2];
+    if (long(d.H) * (d.N[1] + 1) > buf) buf = long(d.H) * (d.N[1] + 1);
+    const long slab_bytes = long(sizeof(float2)) * (2 * buf + d.N[1] + d.N[2]);
+    d.slab = slab_bytes <= pme::kSlabLdsMax;
+    d.slab_lds = size_t(slab_bytes);
+    // pencil passes: about 1024 complex points per workgroup
+    int pairs = (1024 + d.N[2] - 1) / d.N[2];
+    if (pairs > 32) pairs = 32;
+    d.rows_per_block = 2 * pairs;
+    const int nmax = d.N[0] > d.N[1] ? d.N[0] : d.N[1];
+    int kt = nmax <= 64 ? 16 : (nmax <= 160 ? 24 : 4);
+    // LDS of a line workgroup within 56 KB: twiddles, two line buffers and (x pass)
+    // the kt N_x table of g and the deconvolution factors:
+    // 8 N + kt (16 (N + 1) + 4 N) + 4 (N + kt) bytes
+    // (optimal influence: 12 (N + kt) more bytes of aliasing weights)
+    const int extra = d.opt ? 3 * (nmax + 1) / 2 : 0;
+    const int lds_cap = (7000 - nmax - (nmax + 1) / 2 - extra) /
+                        (2 * (nmax + 1) + (nmax + 1) / 2 + 2 + (d.opt ? 2 : 0));
+    if (kt > lds_cap) kt = lds_cap;
+    if (kt < 1) kt = 1;
+    if (kt > d.H) kt = d.H;
+    // equal chunks of the H columns (no mostly-empty last chunk)
+    const int nchunk = (d.H + kt - 1) / kt;
+    kt = (d.H + nchunk - 1) / nchunk;
+    d.ktile = kt;
+  }
+  nbins_out = nbins;
+  return PME_OK;
 }
 
 template <class T>
@@ -178,6 +328,9 @@ const char* pme_strerror(int code) {
     case PME_ENOMEM: return "device allocation failed";
     case PME_EHIP: return "HIP runtime error";
     case PME_ENONFINITE: return "non-finite position or box seen on the device";
+    case PME_ESCRATCH:
+      return "workspace of pme_forward_noalloc exceeds its fixed scratch array "
+             "(PME_NOALLOC_SCRATCH_BYTES per GPU)";
     default: return "unknown error";
   }
 }
@@ -214,17 +367,10 @@ int pme_mesh_dims(const double box[9], double spacing, int strategy, int32_t out
 int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
   if (!desc || !out) return PME_EINVAL;
   *out = nullptr;
-  if (desc->order < 1 || desc->order > 7) return PME_EORDER;
-  for (int a = 0; a < 3; ++a)
-    if (desc->mesh[a] < 2 || desc->mesh[a] > 1024 || !five_smooth(desc->mesh[a])) return PME_EMESH;
-  if (!(desc->alpha > 0.0) || !isfinite(desc->alpha) || !(desc->influence_power >= 0.0) ||
-      !isfinite(desc->influence_power) || !isfinite(desc->prefactor))
-    return PME_EALPHA;
-  if (desc->max_atoms < 1 ||
-      (desc->flags & ~(PME_F_KEEP_PHI | PME_F_CONCURRENT | PME_F_OPT_INFLUENCE)))
-    return PME_EINVAL;
-  for (int a = 0; a < 3; ++a)
-    if (desc->tile[a] < 0 || desc->tile[a] > 1024) return PME_EINVAL;
+  {
+    const int vc = check_desc(*desc);
+    if (vc != PME_OK) return vc;
+  }
 
   pme_plan_s* pl = new (std::nothrow) pme_plan_s();
   if (!pl) return PME_ENOMEM;
@@ -235,112 +381,16 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
   pl->phi_valid = false;
   pl->set = 0;
   DevPlan& d = pl->d;
+  long nbins = 0;
   const int p = desc->order;
-  for (int a = 0; a < 3; ++a) d.N[a] = desc->mesh[a];
-  d.H = d.N[2] / 2 + 1;
-  d.p = p;
-  d.alpha = desc->alpha;
-  d.prefactor = desc->prefactor;
-  d.opt = (desc->flags & PME_F_OPT_INFLUENCE) != 0;
+  {
+    const int gc = plan_geometry(*desc, d, nbins);
+    if (gc != PME_OK) {
+      free_plan(pl);
+      return gc;
+    }
+  }
   const long M = long(d.N[0]) * d.N[1] * d.N[2];
-
-  // bins of B cells and mesh tiles of T = k B cells (targets 8 x 8 x 16 unless the
-  // descriptor sets them)
-  long nbins = 1;
-  int target[3] = {8, 8, 16};
-  for (int a = 0; a < 3; ++a)
-    if (desc->tile[a] > 0) target[a] = desc->tile[a];
-  for (int a = 0; a < 3; ++a) {
-    d.B[a] = pick_bin(d.N[a]);
-    d.nb[a] = d.N[a] / d.B[a];
-    nbins *= d.nb[a];
-    int k = (target[a] + d.B[a] / 2) / d.B[a];
-    if (k < 1) k = 1;
-    if (k > d.nb[a]) k = d.nb[a];
-    d.T[a] = k * d.B[a];
-  }
-  // shrink tiles until the spread tile, the scanned bin range, the gather's own
-  // bins and its LDS field region fit their bounds
-  for (;;) {
-    long range = 1, own = 1, region = 2;
-    for (int a = 0; a < 3; ++a) {
-      long k = (d.T[a] + p - 1 + d.B[a] - 1) / d.B[a] + 1;
-      range *= (k < d.nb[a] ? k : d.nb[a]);
-      own *= d.T[a] / d.B[a];
-      region *= d.T[a] + p - 1;
-    }
-    const long tpad = long(d.T[0]) * d.T[1] * (d.T[2] + 1);
-    // two field regions and their row and z tables
-    const long rows = long(d.T[0] + p - 1) * (d.T[1] + p - 1) + (d.T[2] + p - 1);
-    if (range <= pme::kMaxBinRange && own <= 256 && tpad <= pme::kTileLds &&
-        region * 4 + rows * 4 <= pme::kGatherLds &&
-        long(pme::spread_lds_bytes(int(tpad), int(range), 64, p, 2)) <= pme::kBigLds)
-      break;
-    int big = 0;
-    for (int a = 1; a < 3; ++a)
-      if (d.T[a] / d.B[a] > d.T[big] / d.B[big]) big = a;
-    if (d.T[big] == d.B[big]) { free_plan(pl); return PME_EMESH; }
-    d.T[big] -= d.B[big];
-  }
-  for (int a = 0; a < 3; ++a) d.nt[a] = (d.N[a] + d.T[a] - 1) / d.T[a];
-  {
-    // spread staging: records per round such that five workgroups share a CU's
-    // 160 KiB of LDS (all tiles of a 100^3 mesh resident at once; 1 KiB per
-    // workgroup is left for static LDS and allocation granularity), at least 64
-    long range = 1;
-    for (int a = 0; a < 3; ++a) {
-      long k = (d.T[a] + p - 1 + d.B[a] - 1) / d.B[a] + 1;
-      range *= (k < d.nb[a] ? k : d.nb[a]);
-    }
-    d.nbr_max = int(range);
-    const int tw = d.T[0] * d.T[1] * (d.T[2] + 1);
-    for (int deg = 1; deg <= 2; ++deg) {
-      const long fixed = long(pme::spread_lds_bytes(tw, d.nbr_max, 0, p, deg));
-      const long per = 4L * pme::spread_entry_words(p, deg) + 2L * p;
-      long ch = (32768 - 1024 - fixed) / per;
-      if (ch > 256) ch = 256;
-      if (ch < 64) ch = 64;
-      d.spread_ch[deg - 1] = int(ch);
-    }
-  }
-  {
-    const double per_bin = double(desc->max_atoms) * d.B[0] * d.B[1] * d.B[2] / double(M);
-    long cap = long(ceil(2.0 * per_bin)) + 8;
-    if (cap > 64) cap = 64;
-    d.cap = int(cap);
-  }
-  // FFT layout
-  for (int a = 0; a < 3; ++a)
-    if (!pme::radix_plan(d.N[a], d.ax[a])) { free_plan(pl); return PME_EMESH; }
-  {
-    // slab mode when a y-z plane of the half spectrum (two LDS buffers) fits
-    const long npairs = (d.N[1] + 1) / 2;
-    long buf = npairs * d.N[2];
-    if (long(d.H) * (d.N[1] + 1) > buf) buf = long(d.H) * (d.N[1] + 1);
-    const long slab_bytes = long(sizeof(float2)) * (2 * buf + d.N[1] + d.N[2]);
-    d.slab = slab_bytes <= pme::kSlabLdsMax;
-    d.slab_lds = size_t(slab_bytes);
-    // pencil passes: about 1024 complex points per workgroup
-    int pairs = (1024 + d.N[2] - 1) / d.N[2];
-    if (pairs > 32) pairs = 32;
-    d.rows_per_block = 2 * pairs;
-    const int nmax = d.N[0] > d.N[1] ? d.N[0] : d.N[1];
-    int kt = nmax <= 64 ? 16 : (nmax <= 160 ? 24 : 4);
-    // LDS of a line workgroup within 56 KB: twiddles, two line buffers and (x pass)
-    // the kt N_x table of g and the deconvolution factors:
-    // 8 N + kt (16 (N + 1) + 4 N) + 4 (N + kt) bytes
-    // (optimal influence: 12 (N + kt) more bytes of aliasing weights)
-    const int extra = d.opt ? 3 * (nmax + 1) / 2 : 0;
-    const int lds_cap = (7000 - nmax - (nmax + 1) / 2 - extra) /
-                        (2 * (nmax + 1) + (nmax + 1) / 2 + 2 + (d.opt ? 2 : 0));
-    if (kt > lds_cap) kt = lds_cap;
-    if (kt < 1) kt = 1;
-    if (kt > d.H) kt = d.H;
-    // equal chunks of the H columns (no mostly-empty last chunk)
-    const int nchunk = (d.H + kt - 1) / kt;
-    kt = (d.H + nchunk - 1) / nchunk;
-    d.ktile = kt;
-  }
 
   hipError_t e = hipSuccess;
   int64_t& by = pl->bytes;
@@ -383,9 +433,7 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
     float* dc = new float[N];
     for (int t = 0; t < N; ++t) {
       tw[t] = twiddle(t, N);
-      const int f = (t >= (N + 1) / 2) ? t - N : t;
-      const double b = pow(fabs(sinc(double(f) / N)), double(p));
-      dc[t] = float(pow(b, -2.0 * desc->influence_power));
+      dc[t] = deconv_factor(t, N, p, desc->influence_power);
     }
     if (d.opt) {
       // aliasing weights sinc^{2p}((f + m N)/N), m = -1, 0, 1, and the separable
@@ -951,6 +999,169 @@ int pme_batch_status(pme_batch_t batch, void* stream) {
     if (rc != PME_OK && worst == PME_OK) worst = rc;
   }
   return worst;
+}
+
+}  // extern "C"
+
+// ---- pme_forward without allocation --------------------------------------
+//
+// Every workspace of the forward (atom bins and records, counters, density,
+// spectrum, potential, twiddle and deconvolution tables, energy partials) is
+// carved from one fixed device array per GPU.  The array's name is a host-side
+// stand-in: host code uses only the device address that hipGetSymbolAddress
+// returns for the current device, kept per device.
+
+namespace {
+
+constexpr size_t kScratchBytes = size_t(PME_NOALLOC_SCRATCH_BYTES);
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+unsigned char* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device: looked up once per device
+// (with that device current), together with the dynamic LDS limits the kernels
+// need, which pme_plan sets for plans.
+int scratch_address(unsigned char** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e);
+  if (dev < 0 || dev >= kMaxDevices) return PME_EINVAL;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return hip_fail(e);
+    if (!p) return PME_EHIP;
+    if ((e = pme::enable_slab_lds(pme::kSlabLdsMax)) != hipSuccess) return hip_fail(e);
+    if ((e = pme::enable_spread_lds()) != hipSuccess) return hip_fail(e);
+    if ((e = pme::enable_gather_lds()) != hipSuccess) return hip_fail(e);
+    g_scratch[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = g_scratch[dev];
+  return PME_OK;
+}
+
+struct TableArgs {
+  int N[3];
+  int p;
+  double gamma;
+  float2* tw[3];
+  float* dc[3];
+};
+
+// The per-axis twiddle and deconvolution tables, one thread per entry (the same
+// values pme_plan computes on the host).
+__global__ void __launch_bounds__(256) k_tables(TableArgs a) {
+  int i = blockIdx.x * 256 + threadIdx.x;
+  for (int ax = 0; ax < 3; ++ax) {
+    if (i < a.N[ax]) {
+      a.tw[ax][i] = twiddle(i, a.N[ax]);
+      a.dc[ax][i] = deconv_factor(i, a.N[ax], a.p, a.gamma);
+      return;
+    }
+    i -= a.N[ax];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_zero(int* p, int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pme_forward_noalloc(const pme_desc_t* desc, void* stream, int32_t n, const float* pos,
+                        const float* q, const float* mu, const double* box, double* energy,
+                        float* dE_dpos, float* dE_dq, float* dE_dmu) {
+  if (!desc || n < 0 || !box || (n > 0 && !pos)) return PME_EINVAL;
+  pme_desc_t dd = *desc;
+  dd.max_atoms = n > 0 ? n : 1;       // the workspaces are sized for this call
+  {
+    const int vc = check_desc(dd);
+    if (vc != PME_OK) return vc;
+  }
+  if (dd.flags & PME_F_OPT_INFLUENCE) return PME_EINVAL;
+  DevPlan d;
+  memset(&d, 0, sizeof(d));
+  long nbins = 0;
+  {
+    const int gc = plan_geometry(dd, d, nbins);
+    if (gc != PME_OK) return gc;
+  }
+  const long M = long(d.N[0]) * d.N[1] * d.N[2];
+  d.ovf_base = (long long)nbins * d.cap;
+  // layout of the scratch array (256-byte aligned pieces)
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const int nzero = int(2 * nbins + 5);   // both counter sets, overflow counts, cmax, status
+  const size_t o_zero = take(sizeof(int) * size_t(nzero));
+  const size_t o_rec = take(sizeof(float) * 16 * (size_t(d.ovf_base) + size_t(dd.max_atoms)));
+  size_t o_tw[3], o_dc[3];
+  for (int a = 0; a < 3; ++a) {
+    o_tw[a] = take(sizeof(float2) * size_t(d.N[a]));
+    o_dc[a] = take(sizeof(float) * size_t(d.N[a]));
+  }
+  const size_t o_rho = take(sizeof(float) * size_t(M));
+  const size_t o_phi = take(sizeof(float) * size_t(M));
+  const size_t o_spec = take(sizeof(float2) * size_t(d.N[0]) * d.N[1] * d.H);
+  const size_t o_epart = take(sizeof(double) * size_t(pme::fftx_blocks(d)));
+  const size_t o_spart = take(sizeof(double) * 4 * size_t(pme::bin_blocks(dd.max_atoms)));
+  if (off > kScratchBytes) return PME_ESCRATCH;
+
+  unsigned char* base = nullptr;
+  {
+    const int rc = scratch_address(&base);
+    if (rc != PME_OK) return rc;
+  }
+  int* zero = reinterpret_cast<int*>(base + o_zero);
+  d.count[0] = zero;
+  d.count[1] = zero + nbins;
+  d.ovf_count[0] = zero + 2 * nbins;
+  d.ovf_count[1] = zero + 2 * nbins + 1;
+  d.cmax[0] = reinterpret_cast<unsigned*>(zero + 2 * nbins + 2);
+  d.cmax[1] = reinterpret_cast<unsigned*>(zero + 2 * nbins + 3);
+  d.status = zero + 2 * nbins + 4;
+  d.rec = reinterpret_cast<float*>(base + o_rec);
+  TableArgs ta;
+  ta.p = d.p;
+  ta.gamma = dd.influence_power;
+  for (int a = 0; a < 3; ++a) {
+    d.twiddle[a] = reinterpret_cast<float2*>(base + o_tw[a]);
+    d.deconv[a] = reinterpret_cast<float*>(base + o_dc[a]);
+    ta.N[a] = d.N[a];
+    ta.tw[a] = d.twiddle[a];
+    ta.dc[a] = d.deconv[a];
+  }
+  d.rho = reinterpret_cast<float*>(base + o_rho);
+  d.phi = reinterpret_cast<float*>(base + o_phi);
+  d.spec = reinterpret_cast<float2*>(base + o_spec);
+  d.epart = reinterpret_cast<double*>(base + o_epart);
+  d.spart = reinterpret_cast<double*>(base + o_spart);
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e;
+  hipLaunchKernelGGL(k_zero, dim3((nzero + 255) / 256), dim3(256), 0, s, zero, nzero);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
+  hipLaunchKernelGGL(k_tables, dim3((d.N[0] + d.N[1] + d.N[2] + 255) / 256), dim3(256), 0, s, ta);
+  if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e);
+  // the forward of pme_forward with counter set 0
+  if ((e = pme::launch_bin(d, s, 0, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
+                           energy != nullptr, nullptr)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_spread(d, s, 0, false, box, nullptr)) != hipSuccess) return hip_fail(e);
+  if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, nullptr)) != hipSuccess)
+    return hip_fail(e);
+  if ((e = pme::launch_gather(d, s, 0, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu,
+                              pme::bin_blocks(n), nullptr)) != hipSuccess)
+    return hip_fail(e);
+  return PME_OK;
 }
 
 }  // extern "C"

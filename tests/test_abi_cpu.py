@@ -35,7 +35,7 @@ def test_header_declarations_are_exported():
 
 def test_strerror_codes():
     lib = _lib_or_skip()
-    for code in range(-8, 1):
+    for code in range(-9, 1):
         assert lib.pme_strerror(code).decode() != "unknown error"
     assert lib.pme_strerror(-99).decode() == "unknown error"
 
