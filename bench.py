@@ -71,10 +71,11 @@ def kernel_symbol(kind: str, step: bool = False) -> str:
 
 def alg_bytes(kind: str, n: int, m: int, step: bool = True) -> int:
     """Algorithmic HBM bytes of one launch: the method's arrays (FP32) that the
-    step must read or write, split over the kernels that touch them.
-      bin            pos, q, mu in                               28 n
-      bin_tangent    pos, q, mu, v_pos, v_q, v_mu in             56 n
-      spread(_tan.)  rho (or the tangent density) out            4 M
+    step must read or write, split over the kernels that perform the method's
+    steps (the binning is part of the spread step, Eq. charge_dipole_assign):
+      bin            (charged to the spread)                     0
+      spread         pos, q, mu in; rho out                      28 n + 4 M
+      spread_tangent pos, q, mu, v_pos, v_q, v_mu in; rho_dot out  56 n + 4 M
       fft_r2c        density in                                  4 M
       fft_x          (intermediate spectrum only)                0
       fft_c2r        potential out                               4 M
@@ -84,9 +85,9 @@ def alg_bytes(kind: str, n: int, m: int, step: bool = True) -> int:
     A pme_forward + pme_backward step sums to 224 B per atom + 36 B per mesh point;
     a pme_step (one gather for both) to 196 B per atom + 32 B per mesh point.
     """
-    table = {"bin": 28 * n, "bin_tangent": 56 * n, "spread": 4 * m, "spread_tangent": 4 * m,
-             "fft_r2c": 4 * m, "fft_x": 0, "fft_c2r": 4 * m, "gather": 56 * n + 4 * m,
-             "gather_hvp": (112 if step else 84) * n + 8 * m}
+    table = {"bin": 0, "bin_tangent": 0, "spread": 28 * n + 4 * m,
+             "spread_tangent": 56 * n + 4 * m, "fft_r2c": 4 * m, "fft_x": 0, "fft_c2r": 4 * m,
+             "gather": 56 * n + 4 * m, "gather_hvp": (112 if step else 84) * n + 8 * m}
     return table[kind]
 
 
@@ -138,11 +139,16 @@ def _args(argv=None):
     ap.add_argument("--graph", type=int, default=1,
                     help="1: the timed steps are captured into one HIP graph (pme_step_capture) "
                          "and replayed once, after one untimed replay; 0: eager calls")
+    ap.add_argument("--replays", type=int, default=200,
+                    help="single replays of a two-step graph timed one by one (median, p10, p90)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="1 also runs a device copy of 256 MiB (byte-counter calibration)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the counter summary of the dominant kernel and exit")
     ap.add_argument("--kernel", default=None, help="kernel kind for --traffic-summary")
+    ap.add_argument("--counter-summary", nargs="+", default=None, metavar="DIR",
+                    help="write profiles/kernels_<workload>_counters.txt from rocprofv3 counter "
+                         "directories (one per COUNTER_PASSES entry) and exit")
     ap.add_argument("--kernel-stats", default=None, metavar="STATS_CSV",
                     help="write profiles/<workload> kernel-statistics summary from a "
                          "rocprofv3 --stats kernel_stats.csv")
@@ -178,6 +184,8 @@ def main(argv=None):
         return traffic_summary(args)
     if args.kernel_stats:
         return kernel_stats_summary(args)
+    if args.counter_summary:
+        return counter_summary(args)
     if args.sweep_summary:
         return sweep_summary(args.sweep_summary)
     if args.gpus != 1:
@@ -264,6 +272,19 @@ def main(argv=None):
     plan.status()
     ms = (t1 - t0) * 1e3 / args.steps
     value = n * args.steps / (t1 - t0) / 1e6
+    replays = None
+    if args.graph and args.replays > 0:
+        # distribution over single replays of a two-step graph (HIP events around each)
+        plan.step_capture(2, pos, q, mu, box, vr, vq, vm, out=so)
+        for _ in range(5):
+            plan.step_replay()
+        per = [t / 2 for t in device_ms(plan.step_replay, args.replays)]
+        plan.status()
+        replays = {"replays": args.replays, "steps_per_replay": 2,
+                   "ms_per_step_median": round(pct(per, 0.5), 5),
+                   "ms_per_step_p10": round(pct(per, 0.1), 5),
+                   "ms_per_step_p90": round(pct(per, 0.9), 5),
+                   "note": "HIP events around each replay of a captured two-step graph"}
 
     if args.copy_calibration:
         src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
@@ -276,6 +297,11 @@ def main(argv=None):
     ab = alg_bytes(dominant, n, m, not args.sequential)
     achieved = ab / dur_s / 1e9
     traffic = read_traffic(dominant, args.workload)
+    sym = kernel_symbol(dominant, not args.sequential)
+    rp_us = read_kernel_stats(args.workload + ("_sequential" if args.sequential else ""), sym)
+    copy_bw = copy_bandwidth(dev)
+    lds = lds_peak(dev)
+    lds_bytes = read_lds_bytes(args.workload, sym)
     line = {
         "metric": "PME q+mu fwd+bwd Matom-steps/s @32k atoms",
         "value": value,
@@ -302,10 +328,22 @@ def main(argv=None):
                           "launch durations are timed over this pass"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 3), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 6),
-                     "traffic": traffic, "kernel": kernel_symbol(dominant, not args.sequential),
-                     "kind": dominant,
+                     "traffic": traffic, "kernel": sym, "kind": dominant,
                      "alg_bytes_per_launch": ab, "avg_launch_us": round(dur_s * 1e6, 3),
-                     "launches": launches},
+                     "launches": launches,
+                     "rocprof_avg_us": rp_us,
+                     "frac_rocprof": (round(ab / (rp_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 6)
+                                      if rp_us else None),
+                     "frac_of_copy": round(achieved / copy_bw["GBps"], 6),
+                     "copy": copy_bw,
+                     "lds": {"bytes_per_launch": lds_bytes,
+                             "GBps": round(lds_bytes / dur_s / 1e9, 1) if lds_bytes else None,
+                             "peak_read_b128_GBps": lds["read_b128_GBps"],
+                             "peak_atomic_add_u64_GBps": lds["atomic_add_u64_GBps"],
+                             "frac_of_read_peak": (round(lds_bytes / dur_s / 1e9 /
+                                                         lds["read_b128_GBps"], 6)
+                                                   if lds_bytes else None)}},
+        "replays": replays,
         "kernels_us": kernels_us,
         "step_model_bytes": step_bytes(n, m, not args.sequential),
     }
@@ -737,11 +775,14 @@ def traffic_summary(args) -> int:
     with open(out, "w") as fh:
         fh.write(f"# HBM traffic of {sym} ({kind}), workload {args.workload}\n")
         fh.write("# commands (from the repository root):\n")
+        flags = COUNTER_FLAGS if args.sequential else PMC_FLAGS
+        seq = " --sequential 1" if args.sequential else ""
         for ctr, d in (("FETCH_SIZE", "<D1>"), ("WRITE_SIZE", "<D2>")):
             fh.write(f"#   rocprofv3 --pmc {ctr} --output-format csv -d {d} -o run -- "
-                     f"python -u bench.py {PMC_FLAGS} --workload {args.workload}\n")
+                     f"python -u bench.py {flags} --workload {args.workload}\n")
         fh.write("#   python bench.py --traffic-summary <D1>/run_counter_collection.csv "
-                 f"<D2>/run_counter_collection.csv --kernel {kind} --workload {args.workload}\n")
+                 f"<D2>/run_counter_collection.csv --kernel {kind} --workload {args.workload}"
+                 f"{seq}\n")
         fh.write(f"# sources: digest of {', '.join(sorted(set(KERNEL_SOURCES[kind]) | {'kernels.h', 'pme_common.h'}))} "
                  f"(bench.source_digest('{kind}'))\n")
         fh.write(f"sources: {source_digest(kind)}\n")
@@ -762,6 +803,113 @@ def traffic_summary(args) -> int:
     return 0
 
 
+# counter passes of the per-kernel summary (one rocprofv3 run each; every pass stays
+# within the per-block counter limits)
+COUNTER_PASSES = (
+    "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR "
+    "SQ_WAVE_CYCLES SQ_BUSY_CYCLES",
+    "SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_LDS "
+    "SQ_WAIT_INST_ANY SQ_INSTS_LDS_ATOMIC SQ_LDS_IDX_ACTIVE SQ_INSTS_BRANCH",
+    "SQ_INSTS_LDS_LOAD_BANDWIDTH SQ_INSTS_LDS_STORE_BANDWIDTH SQ_INSTS_LDS_ATOMIC_BANDWIDTH "
+    "SQ_INSTS_VALU_FMA_F32 SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_CVT GRBM_GUI_ACTIVE",
+    "FETCH_SIZE",
+    "WRITE_SIZE",
+)
+COUNTER_FLAGS = ("--steps 3 --warmup 2 --cpu-baseline 0 --batched 0 --learned 0 --cell 0 "
+                 "--influence 0 --quad 0 --copy-calibration 1 --breakdown-steps 1 --sequential 1 "
+                 "--graph 0 --replays 0")
+
+
+def _pass_rows(path):
+    """{kernel: {counter: mean per dispatch}} and {kernel: (grid, wg, lds, vgpr)} of a
+    rocprofv3 counter-collection CSV (the calibration copy: its largest grid only)."""
+    vals, meta = {}, {}
+    rows = list(csv.DictReader(open(path)))
+    copy_grid = max([int(r["Grid_Size"]) for r in rows if "copyBuffer" in r["Kernel_Name"]],
+                    default=0)
+    for r in rows:
+        k = r["Kernel_Name"].replace("void ", "").replace("pme::(anonymous namespace)::", "")
+        k = k.replace("(anonymous namespace)::", "").split("(")[0]
+        if "copyBuffer" in k and int(r["Grid_Size"]) != copy_grid:
+            continue
+        vals.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+        meta[k] = (int(r["Grid_Size"]), int(r["Workgroup_Size"]), int(r["LDS_Block_Size"]),
+                   int(r.get("VGPR_Count") or r.get("Arch_VGPR_Count") or 0))
+    return ({k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in vals.items()}, meta)
+
+
+def counter_summary(args) -> int:
+    """profiles/kernels_<workload>_counters.txt: per-kernel instruction mix, LDS
+    traffic and bank conflicts, occupancy and HBM bytes of the two-call step, from the
+    rocprofv3 counter passes in the directories given (one per COUNTER_PASSES entry)."""
+    merged, meta = {}, {}
+    for d in args.counter_summary:
+        v, m = _pass_rows(os.path.join(d, "run_counter_collection.csv"))
+        for k, cs in v.items():
+            merged.setdefault(k, {}).update(cs)
+        meta.update(m)
+    copy = next(k for k in merged if "copyBuffer" in k)
+    f_scale = COPY_BYTES / (merged[copy]["FETCH_SIZE"] * 1024.0)
+    w_scale = COPY_BYTES / (merged[copy]["WRITE_SIZE"] * 1024.0)
+    n, _, mesh, p, _ = WORKLOADS[args.workload]
+    out = os.path.join(ROOT, "profiles", f"kernels_{args.workload}_counters.txt")
+    lines = [
+        f"# rocprofv3 counters of the PME kernels, two-call step (pme_forward; pme_backward, each",
+        f"# kernel alone on the GPU), {n}-ion molten-salt box, mesh {mesh[0]}^3, p = {p}, one MI355X",
+        "# commands (repository root), one run per counter pass:",
+    ]
+    for i, ps in enumerate(COUNTER_PASSES):
+        lines.append(f"#   rocprofv3 --pmc {ps} --output-format csv -d <D{i + 1}> -o run -- "
+                     f"python -u bench.py {COUNTER_FLAGS} --workload {args.workload}")
+    lines += [
+        "#   python bench.py --counter-summary <D1> <D2> <D3> <D4> <D5> --workload " + args.workload,
+        "# per wave: instructions issued per wavefront (SQ_INSTS_* / SQ_WAVES);",
+        "# lds_bytes = 64 * (SQ_INSTS_LDS_{LOAD,STORE,ATOMIC}_BANDWIDTH) per launch;",
+        "# bank_conflict = SQ_LDS_BANK_CONFLICT / (SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT)",
+        "#   (stall cycles per LDS access cycle);",
+        "# occupancy = 400 SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE / 8 XCDs) / 256 CUs / 32 waves (%);",
+        "# hbm = FETCH_SIZE, WRITE_SIZE scaled by a 256 MiB device copy in the same run "
+        f"(x {f_scale:.3f}, x {w_scale:.3f});",
+        "# vgpr, lds_alloc: per workitem registers and LDS bytes per workgroup of the dispatch.",
+        f"# source digest of paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
+        "",
+        f"{'kernel':28s} {'grid':>8s} {'wg':>5s} {'vgpr':>5s} {'lds_alloc':>9s} {'waves':>7s} "
+        f"{'valu/w':>7s} {'salu/w':>7s} {'lds/w':>6s} {'ldsat/w':>7s} {'vmem/w':>7s} "
+        f"{'lds_MB':>7s} {'bank_cf':>7s} {'occ%':>5s} {'hbm_MB':>7s}",
+    ]
+    lds_lines = []
+    order = [KERNEL_SYMBOL[k] for k in ("bin", "bin_tangent", "spread", "spread_tangent",
+                                        "fft_r2c", "fft_x", "fft_c2r", "gather", "gather_hvp")]
+    for k in order:
+        if k not in merged:
+            continue
+        c = merged[k]
+        grid, wg, lds_alloc, vgpr = meta[k]
+        waves = max(c.get("SQ_WAVES", 0.0), 1.0)
+        pw = lambda name: c.get(name, float("nan")) / waves
+        lds_b = 64.0 * sum(c.get(x, 0.0) for x in ("SQ_INSTS_LDS_LOAD_BANDWIDTH",
+                                                   "SQ_INSTS_LDS_STORE_BANDWIDTH",
+                                                   "SQ_INSTS_LDS_ATOMIC_BANDWIDTH"))
+        act = c.get("SQ_LDS_IDX_ACTIVE", 0.0)
+        cf = c.get("SQ_LDS_BANK_CONFLICT", 0.0)
+        bank = cf / (act - cf) if act > cf else float("nan")
+        gui = c.get("GRBM_GUI_ACTIVE", 0.0) / 8.0
+        occ = 400.0 * c.get("SQ_WAVE_CYCLES", 0.0) / gui / 256 / 32 if gui else float("nan")
+        hbm = c.get("FETCH_SIZE", 0.0) * 1024 * f_scale + c.get("WRITE_SIZE", 0.0) * 1024 * w_scale
+        lines.append(f"{k[:28]:28s} {grid:8d} {wg:5d} {vgpr:5d} {lds_alloc:9d} {int(waves):7d} "
+                     f"{pw('SQ_INSTS_VALU'):7.0f} {pw('SQ_INSTS_SALU'):7.0f} "
+                     f"{pw('SQ_INSTS_LDS'):6.0f} {pw('SQ_INSTS_LDS_ATOMIC'):7.1f} "
+                     f"{pw('SQ_INSTS_VMEM_RD') + pw('SQ_INSTS_VMEM_WR'):7.1f} {lds_b / 1e6:7.2f} "
+                     f"{bank:7.3f} {occ:5.1f} {hbm / 1e6:7.2f}")
+        lds_lines.append(f"lds_bytes_per_launch {k} {lds_b:.0f}")
+    lines += ["", "# LDS bytes per launch (read by bench.py for the roofline's LDS figure):"]
+    lines += lds_lines
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print(open(out).read())
+    return 0
+
+
 def kernel_stats_summary(args) -> int:
     """profiles/pme_step_<workload>[_sequential]_kernel_stats.txt from rocprofv3's
     kernel_stats.csv, with bench.py's own launch timer beside it when --bench-line
@@ -770,6 +918,7 @@ def kernel_stats_summary(args) -> int:
     with open(args.kernel_stats) as fh:
         for r in csv.DictReader(fh):
             name = r["Name"].replace("void ", "").replace("pme::(anonymous namespace)::", "")
+            name = name.replace("(anonymous namespace)::", "")
             name = name.split("(")[0] if "(" in name else name
             rows.append((name, int(r["Calls"]), float(r["AverageNs"]) / 1e3,
                          float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3, float(r["Percentage"])))
@@ -923,8 +1072,20 @@ def crossover(sizes=(128, 512, 1024, 2048, 4096), alpha=0.30):
     return 0
 
 
-def cpu_baseline(frame, mesh, p, alpha, v, steps):
-    """The FP64 oracle (forward + HVP) timed on the host cores, on `steps` full steps."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(frame, mesh, p, alpha, v, steps, runs=3):
+    """The FP64 oracle (forward + HVP) timed on the host cores: the median of `runs`
+    runs of `steps` full steps each."""
     from oracle import pme as opme
     threads = 1
     try:
@@ -932,16 +1093,108 @@ def cpu_baseline(frame, mesh, p, alpha, v, steps):
         threads = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
     except Exception:
         threads = int(os.environ.get("OMP_NUM_THREADS", "1"))
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        opme.forward(frame.pos, frame.q, frame.mu, frame.box, mesh, p, alpha)
-        opme.hvp(frame.pos, frame.q, frame.mu, frame.box, mesh, p, alpha, *v)
-    dt = time.perf_counter() - t0
+    times = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            opme.forward(frame.pos, frame.q, frame.mu, frame.box, mesh, p, alpha)
+            opme.hvp(frame.pos, frame.q, frame.mu, frame.box, mesh, p, alpha, *v)
+        times.append(time.perf_counter() - t0)
+    dt = sorted(times)[len(times) // 2]
     return {"value": frame.n * steps / dt / 1e6, "unit": "Matom-steps/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{steps} full forward+HVP steps of the same {frame.n}-ion workload "
-                      f"({dt:.1f} s; the DFT matrix products use {threads} BLAS threads, the "
-                      f"spread and gather loops one)"}
+            "kind": "oracle", "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+            "sample": f"median of {runs} runs of {steps} full forward+HVP steps of the same "
+                      f"{frame.n}-ion workload ({dt:.2f} s per run; the DFT matrix products "
+                      f"use {threads} BLAS threads, the spread and gather loops one)"}
+
+
+def device_ms(fn, reps):
+    """Per-call durations (ms) of fn() on the current stream, from HIP events
+    recorded around each call."""
+    import torch
+    out = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn()
+        b.record()
+        b.synchronize()
+        out.append(a.elapsed_time(b))
+    return out
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    return xs[min(len(xs) - 1, int(round(q * (len(xs) - 1))))]
+
+
+def copy_bandwidth(dev):
+    """Device-to-device copy of 256 MiB (bytes read + written per second): the
+    achievable HBM bandwidth beside the 8 TB/s datasheet peak."""
+    import torch
+    src = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ms = sorted(device_ms(lambda: dst.copy_(src), 10))[5]
+    del src, dst
+    return {"bytes": 2 * COPY_BYTES, "ms": round(ms, 4), "GBps": round(2 * COPY_BYTES / ms / 1e6, 1)}
+
+
+def lds_peak(dev):
+    """LDS bandwidth of the GPU from the library's probe (pme_lds_probe): conflict-
+    free 16-byte reads and 64-bit atomic adds, 8 workgroups per CU."""
+    import ctypes
+
+    import torch
+
+    from paper_2606_01598_amd import _lib
+    lib = _lib.load()
+    nblocks, iters = 256 * 8, 4096
+    out = torch.empty(nblocks, dtype=torch.float32, device=dev)
+    res = {}
+    for kind, name, width in ((_lib.PME_PROBE_LDS_READ, "read_b128", 16),
+                              (_lib.PME_PROBE_LDS_ATOMIC, "atomic_add_u64", 8)):
+        def run():
+            _lib.check(lib.pme_lds_probe(ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                         kind, iters, nblocks, ctypes.c_void_p(out.data_ptr())))
+        run()
+        ms = sorted(device_ms(run, 5))[2]
+        res[name + "_GBps"] = round(nblocks * 256 * iters * width / ms / 1e6, 1)
+    return res
+
+
+def read_kernel_stats(workload: str, symbol: str):
+    """rocprofv3 average duration (us) of `symbol` from the committed kernel-statistics
+    summary of the workload, when it was taken on the current sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"pme_step_{workload}_kernel_stats.txt")
+    if not os.path.exists(path):
+        return None
+    digest, avg = None, None
+    with open(path) as fh:
+        for ln in fh:
+            if "source digest" in ln:
+                digest = ln.rsplit(":", 1)[1].strip()
+            elif ln.startswith(symbol[:40]) and not ln.startswith("#"):
+                avg = float(ln[40:].split()[1])
+    return avg if digest == source_digest() else None
+
+
+def read_lds_bytes(workload: str, symbol: str):
+    """LDS bytes per launch of `symbol` from the committed counter summary of the
+    workload, when it was taken on the current sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"kernels_{workload}_counters.txt")
+    if not os.path.exists(path):
+        return None
+    digest, val = None, None
+    with open(path) as fh:
+        for ln in fh:
+            if "source digest" in ln:
+                digest = ln.rsplit(":", 1)[1].strip()
+            elif ln.startswith("lds_bytes_per_launch " + symbol):
+                val = float(ln.rsplit(None, 1)[1])
+    return val if digest == source_digest() else None
 
 
 if __name__ == "__main__":

@@ -41,7 +41,7 @@ EXPORTS = ("pme_mesh_dims", "pme_plan", "pme_plan_destroy", "pme_plan_workspace_
            "pol_scf", "dip_plan_create", "dip_plan_destroy", "dip_features", "dip_forward",
            "dip_backward", "dip_position_vjp", "dip_loss", "dip_adam", "pme_batch_plan", "pme_batch_destroy",
            "pme_batch_forward", "pme_batch_backward", "pme_batch_graph_capture", "pme_batch_graph_launch",
-           "pme_batch_status")
+           "pme_batch_status", "pme_lds_probe")
 
 DIP_NFEAT, DIP_NCH, DIP_HIDDEN, DIP_NPARAM = 34, 16, 64, 7440
 
@@ -78,6 +78,9 @@ class PolDesc(ctypes.Structure):
 
 
 POL_F_WARM_START = 1
+
+PME_PROBE_LDS_READ = 0
+PME_PROBE_LDS_ATOMIC = 1
 
 
 class DipDesc(ctypes.Structure):
@@ -178,6 +181,8 @@ def load():
     lib.pme_batch_graph_launch.restype = ctypes.c_int
     lib.pme_batch_status.argtypes = [vp, vp]
     lib.pme_batch_status.restype = ctypes.c_int
+    lib.pme_lds_probe.argtypes = [vp, i32, i32, i32, vp]
+    lib.pme_lds_probe.restype = ctypes.c_int
     lib.dip_plan_create.argtypes = [ctypes.POINTER(DipDesc), ctypes.POINTER(vp)]
     lib.dip_plan_create.restype = ctypes.c_int
     lib.dip_plan_destroy.argtypes = [vp]

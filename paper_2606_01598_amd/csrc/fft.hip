@@ -576,9 +576,11 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
   // g of the workgroup's points into LDS (issued while the line loads are in flight)
   auto gtable = [&]() {
     const Cell c = cell_from_box(box);
-    // the reciprocal metric, 1/(4 alpha^2) and k^2 in double precision: rounded
-    // to float they would bias every g(k) alike (about 1e-7 relative, which the
-    // near cancellation of E_recip against the self terms would amplify in E^lr)
+    // the reciprocal metric, 1/(4 alpha^2), k^2 and the exponent argument in double
+    // precision, rounded once each to float: constants rounded to float would bias
+    // every g(k) alike (about 1e-7 relative, which the near cancellation of E_recip
+    // against the self terms would amplify in E^lr); a single rounding of k^2 and of
+    // the argument is unbiased, and the exponential itself is evaluated in float
     double M[3][3];
 #pragma unroll
     for (int p = 0; p < 3; ++p)
@@ -598,7 +600,7 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
       const double x = px, y = py, z = pz;
       const double k2 = M[0][0] * x * x + M[1][1] * y * y + M[2][2] * z * z +
                         2.0 * (M[0][1] * x * y + M[0][2] * x * z + M[1][2] * y * z);
-      return float(4.0 * M_PI / k2 * exp(-k2 * inv4a2));
+      return float(4.0 * M_PI / k2) * expf(-float(k2 * inv4a2));
     };
     float aly3[3] = {0.0f, 0.0f, 0.0f};
     // OPT: g from the cache when it holds this box (a uniform decision)
@@ -844,7 +846,7 @@ __global__ void __launch_bounds__(kSlabThreads) k_slab_inv(SlabArgs a) {
 
 template <int MODE>
 __global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
-  fftx_body<MODE>(a, blockIdx.x, a.box, a.epart);
+  fftx_body<MODE>(a, xcd_item(blockIdx.x, gridDim.x), a.box, a.epart);
 }
 
 // After an optimal-influence x pass (every workgroup has written or read the g of

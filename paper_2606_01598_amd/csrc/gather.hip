@@ -807,7 +807,7 @@ template <int P, bool VIR>
 __global__ void __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(P >= 7 && VIR ? 3 : (P >= 6 ? 4 : 5))))
 k_gather(GArgs a) {
-  gather_body<P, VIR>(a, blockIdx.x);
+  gather_body<P, VIR>(a, xcd_item(blockIdx.x, gridDim.x));
 }
 
 // Cell gradient from E_recip and the partials (one workgroup):
@@ -843,13 +843,13 @@ __global__ void __launch_bounds__(256) k_cell_grad(const double* box, const doub
 template <int P, bool DUAL>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 3 : 4)))
 k_gather_hvp(GArgs a) {
-  gather_hvp_body<P, DUAL>(a, blockIdx.x);
+  gather_hvp_body<P, DUAL>(a, xcd_item(blockIdx.x, gridDim.x));
 }
 
 template <int P>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(P >= 7 ? 3 : 4)))
 k_gather_quad(GArgs a) {
-  gather_tile<P, false, false, false, true>(a, blockIdx.x);
+  gather_tile<P, false, false, false, true>(a, xcd_item(blockIdx.x, gridDim.x));
 }
 
 // Batched gathers: work item (box, tile), per-box argument templates completed

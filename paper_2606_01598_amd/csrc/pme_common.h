@@ -246,6 +246,17 @@ __device__ __forceinline__ int wave_compact(bool pred, int* counter) {
   return pred ? base + below : -1;
 }
 
+// Work item of workgroup b of a G-workgroup launch, chosen so that the workgroups
+// one XCD receives take a contiguous range of items.  The GPU hands workgroups to
+// its 8 XCDs in turn (b mod 8), and each XCD has its own L2: with tiles numbered
+// along the mesh, a contiguous range is a compact block of neighbouring tiles whose
+// halos and records that XCD's L2 then serves.  A bijection of [0, G).
+__device__ __forceinline__ int xcd_item(int b, int G) {
+  constexpr int kXcd = 8;
+  const int x = b % kXcd, per = G / kXcd, rem = G % kXcd;
+  return x * per + min(x, rem) + b / kXcd;
+}
+
 // block-wide sum of a double (blockDim.x a multiple of 64, at most 1024)
 __device__ __forceinline__ double block_sum(double v, double* scratch) {
 #pragma unroll

@@ -692,7 +692,7 @@ __device__ __forceinline__ void spread_body(const SpreadArgs& a, const int tile_
 template <int P, int DEG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5)))
 k_spread(SpreadArgs a, const double* box) {
-  spread_body<P, DEG>(a, blockIdx.x, box);
+  spread_body<P, DEG>(a, xcd_item(blockIdx.x, gridDim.x), box);
 }
 
 // Batched spread: work item (box, tile of the box).

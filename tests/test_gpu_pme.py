@@ -377,12 +377,15 @@ def test_config3_32k_full_parity():
     _check_forward(f, (100, 100, 100), 6, 0.3, label="32k")
 
 
-def test_launch_timer_counts_and_outputs_unchanged():
+@pytest.mark.parametrize("mesh", [(32, 32, 32), (12, 160, 150)])
+def test_launch_timer_counts_and_outputs_unchanged(mesh):
     """pme_plan_timer brackets exactly the launches of the chosen kind and leaves
-    the results untouched."""
+    the results untouched, in the slab layout (32^3: one launch per transform half)
+    and the pencil layout (12 x 160 x 150: two launches per transform half, the z
+    and y passes; the x pass is one)."""
     from paper_2606_01598_amd import _lib
     f = synth.molten_box(1000, 1)
-    plan = _plan((32, 32, 32), 6, 0.3, f.n)
+    plan = _plan(mesh, 6, 0.3, f.n)
     pos, q, mu, box = to_dev(f)
     v = [torch.tensor(x, dtype=torch.float32, device=dev()) for x in
          synth.random_cotangents(f.n, 5, scale_r=0.1)]
@@ -397,7 +400,7 @@ def test_launch_timer_counts_and_outputs_unchanged():
             outb = plan.backward(pos, q, mu, box, *v)
         launches, ms = plan.timer_read()
         assert launches == 3 * per_step[kind], (kind, launches)
-        assert 0.0 < ms < 1e3, (kind, ms)
+        assert (0.0 < ms < 1e3) if launches else ms == 0.0, (kind, ms)
         for k in ("dE_dpos", "dE_dq", "dE_dmu"):
             assert torch.equal(out[k], ref[k])
         for k in ("g_pos", "g_q", "g_mu"):
