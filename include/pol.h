@@ -25,7 +25,7 @@
  *   a_i, in Angstrom^3) is [n].
  * - Outputs are overwritten; a NULL output is skipped; a NULL q or mu means zero.
  * - Calls are asynchronous on `stream`, except pol_scf, which synchronises once
- *   per iteration to test convergence.
+ *   per iteration to test convergence (unless POL_F_FIXED_ITERS).
  * - Every energy and gradient is multiplied by `prefactor`, including the
  *   polarization term, so the dipoles do not depend on it. It must equal the
  *   prefactor of the PME plan used with pol_scf.
@@ -58,6 +58,12 @@ typedef struct {
 
 /* pol_scf: start from the dipoles in `mu` instead of zero. */
 #define POL_F_WARM_START 1
+/* pol_scf: run exactly max_iter iterations and never synchronise the stream (no
+ * host-side convergence test), so that a solve can be captured into a HIP graph;
+ * *iters receives max_iter and *resid -1 (the caller checks the solution, e.g. by
+ * the stationarity dU/dmu = 0 of pol_model).  The PME plan's binnings in such a
+ * solve are 1 + max_iter (2 + max_iter with POL_F_WARM_START). */
+#define POL_F_FIXED_ITERS 2
 
 /* Validate `desc`, build the cell grid and allocate the workspaces.  Returns
  * PME_EINVAL for a bad cell, cutoff, alpha or exponent. */

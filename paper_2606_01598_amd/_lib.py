@@ -78,6 +78,7 @@ class PolDesc(ctypes.Structure):
 
 
 POL_F_WARM_START = 1
+POL_F_FIXED_ITERS = 2
 
 PME_PROBE_LDS_READ = 0
 PME_PROBE_LDS_ATOMIC = 1

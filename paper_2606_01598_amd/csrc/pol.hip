@@ -354,7 +354,8 @@ extern "C" {
 int pol_plan_create(const pol_desc_t* desc, pol_plan_t* out) {
   if (!desc || !out) return PME_EINVAL;
   *out = nullptr;
-  if (desc->max_atoms < 1 || (desc->flags & ~POL_F_WARM_START)) return PME_EINVAL;
+  if (desc->max_atoms < 1 || (desc->flags & ~(POL_F_WARM_START | POL_F_FIXED_ITERS)))
+    return PME_EINVAL;
   if (!(desc->alpha > 0.0) || !isfinite(desc->alpha) || !(desc->thole_a >= 0.0) ||
       !isfinite(desc->thole_a) || !isfinite(desc->prefactor) || desc->prefactor == 0.0)
     return PME_EALPHA;
@@ -470,6 +471,7 @@ int pol_scf(pol_plan_t plan, pme_plan_t pme, void* stream, int32_t n, const floa
   double* scal = plan->scal;
   const float pf = float(plan->desc.prefactor);
   const bool warm = (plan->desc.flags & POL_F_WARM_START) != 0;
+  const bool fixed = (plan->desc.flags & POL_F_FIXED_ITERS) != 0;
   const int vb = blocks_for(m, 256);
   int rc;
   hipError_t e;
@@ -500,13 +502,21 @@ int pol_scf(pol_plan_t plan, pme_plan_t pme, void* stream, int32_t n, const floa
   int it = 0;
   double rms = 0.0;
   for (;;) {
-    double h[2];
-    if ((e = hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-      return pol_hip_fail(e);
-    rms = sqrt(fmax(h[1], 0.0) / double(m));
-    if (!isfinite(rms)) return PME_ENONFINITE;
-    if (rms < tol || it >= max_iter) break;
+    if (fixed) {
+      // no host round trip: exactly max_iter iterations (capturable)
+      if (it >= max_iter) {
+        rms = -1.0;
+        break;
+      }
+    } else {
+      double h[2];
+      if ((e = hipMemcpyAsync(h, scal, sizeof(h), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+          (e = hipStreamSynchronize(s)) != hipSuccess)
+        return pol_hip_fail(e);
+      rms = sqrt(fmax(h[1], 0.0) / double(m));
+      if (!isfinite(rms)) return PME_ENONFINITE;
+      if (rms < tol || it >= max_iter) break;
+    }
     if ((rc = matvec(p, Ap)) != PME_OK) return rc;
     hipLaunchKernelGGL(k_dot2, dim3(1), dim3(1024), 0, s, m, p, Ap, p, p, scal + 2);
     hipLaunchKernelGGL(k_pcg_step, dim3(vb), dim3(256), 0, s, m, pf, pol, scal, p, Ap, mu, r, z);

@@ -118,7 +118,7 @@ class Trainer:
     update."""
 
     def __init__(self, dip: DipPlan, pol_plan, pme_plan, box, theta0, lr=2e-3, lE=1.0, lF=1.0,
-                 lmu=0.0):
+                 lmu=0.0, warmup=0, decay=1.0, decay_steps=1000):
         self.dip, self.pol, self.pme, self.box = dip, pol_plan, pme_plan, box
         dev = dip.device
         self.theta = torch.tensor(np.asarray(theta0), dtype=torch.float32, device=dev)
@@ -127,6 +127,14 @@ class Trainer:
         self.g = torch.empty_like(self.theta)
         self.t = 0
         self.lr, self.lE, self.lF, self.lmu = lr, lE, lF, lmu
+        self.warmup, self.decay, self.decay_steps = int(warmup), float(decay), float(decay_steps)
+
+    def rate(self, t: int) -> float:
+        """Learning rate of step t (1-based): a linear warmup over `warmup` steps, then
+        exponential decay by `decay` every `decay_steps` steps (the optimizer setting
+        of Sec. 2.4: Adam with warmup and exponential decay)."""
+        warm = min(1.0, t / self.warmup) if self.warmup > 0 else 1.0
+        return self.lr * warm * self.decay ** (max(0, t - self.warmup) / self.decay_steps)
 
     def predict(self, feat, vec):
         return self.dip.forward(self.theta, feat, vec)
@@ -141,5 +149,5 @@ class Trainer:
         h_real = self.pol.mixed(b["pos"], b["q"], mu, b["pol"], o["v_pos"])
         self.dip.backward(self.theta, b["feat"], b["vec"], o["g_mu"], h_pme, h_real, out=self.g)
         self.t += 1
-        adam(self.theta, self.g, self.m, self.v, self.t, lr=self.lr)
+        adam(self.theta, self.g, self.m, self.v, self.t, lr=self.rate(self.t))
         return o["loss"]

@@ -31,14 +31,15 @@ class PolPlan:
 
     def __init__(self, box, alpha: float, cutoff: float, max_atoms: int,
                  thole_a: float = THOLE_A, prefactor: float = 1.0, warm_start: bool = False,
-                 device=None):
+                 fixed_iters: bool = False, device=None):
         self._lib = _lib.load()
         self.device = torch.device("cuda", 0) if device is None else torch.device(device)
         b = np.asarray(box.detach().cpu() if isinstance(box, torch.Tensor) else box,
                        dtype=np.float64).reshape(9)
         d = _lib.PolDesc()
         d.max_atoms = int(max_atoms)
-        d.flags = _lib.POL_F_WARM_START if warm_start else 0
+        d.flags = ((_lib.POL_F_WARM_START if warm_start else 0)
+                   | (_lib.POL_F_FIXED_ITERS if fixed_iters else 0))
         for k in range(9):
             d.box[k] = float(b[k])
         d.alpha = float(alpha)

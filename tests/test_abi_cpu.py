@@ -110,3 +110,18 @@ def test_null_arguments():
     assert lib.pme_status(None, None) == _lib.PME_EINVAL
     lib.pme_plan_destroy(None)
     assert lib.pme_plan_workspace_bytes(None) == 0
+
+
+def test_learning_rate_schedule():
+    """Adam's learning rate in the dipole-head trainer: a linear warmup over the
+    first steps, then exponential decay (the optimizer setting of Sec. 2.4)."""
+    from types import SimpleNamespace
+
+    from paper_2606_01598_amd.dip import Trainer
+    tr = SimpleNamespace(lr=1e-3, warmup=10, decay=0.5, decay_steps=100)
+    rate = lambda t: Trainer.rate(tr, t)
+    assert abs(rate(1) - 1e-4) < 1e-15 and abs(rate(5) - 5e-4) < 1e-15
+    assert abs(rate(10) - 1e-3) < 1e-15
+    assert abs(rate(110) - 5e-4) < 1e-15 and abs(rate(210) - 2.5e-4) < 1e-15
+    tr0 = SimpleNamespace(lr=2e-3, warmup=0, decay=1.0, decay_steps=1)
+    assert Trainer.rate(tr0, 1) == 2e-3 and Trainer.rate(tr0, 1000) == 2e-3

@@ -121,3 +121,64 @@ def test_model_energy_and_gradients():
     print("model", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     assert errs["U"] <= E_REL_TOL
     assert errs["dU_dpos"] <= RMS_REL_TOL and errs["dU_dmu"] <= RMS_REL_TOL
+
+
+def test_fixed_iteration_solve_and_graph_replays():
+    """POL_F_FIXED_ITERS: exactly max_iter PCG iterations with no host round trip
+    give the converging solve's dipoles; the fixed solve and the model evaluation
+    captured into a HIP graph replay to the eager results (three replays, eager
+    work and synchronisations between them).  The real-space pair sums follow the
+    cell list, whose order within a cell is that of atomic insertions, so the
+    comparisons allow FP32 rounding amplified by the iterations (1e-4 RMS)."""
+    from paper_2606_01598_amd.pme import Plan
+    from paper_2606_01598_amd.pol import PolPlan
+    f, pol = _frame(300, 21.0, 23)
+    alpha, rc, mesh = 0.35, 8.0, (24, 24, 24)
+    pos, q, a = _t(f.pos), _t(f.q), _t(pol)
+    box = torch.tensor(f.box, dtype=torch.float64, device=dev())
+    pme = Plan(mesh, 6, alpha, max_atoms=f.n)
+    plan = PolPlan(f.box, alpha, rc, max_atoms=f.n)
+    mu_c, it, res = plan.scf(pme, pos, q, a, box, tol=1e-6, max_iter=100)
+    assert res < 1e-6 and it > 0
+    k = it + it % 2                        # even: 2 + k binnings per captured solve + model
+    pme_f = Plan(mesh, 6, alpha, max_atoms=f.n)
+    fixed = PolPlan(f.box, alpha, rc, max_atoms=f.n, fixed_iters=True)
+    mu_same = torch.zeros(f.n, 3, dtype=torch.float32, device=dev())
+    _, it2, res2 = fixed.scf(pme_f, pos, q, a, box, max_iter=it, mu=mu_same)
+    assert it2 == it and res2 == -1.0
+    assert rms_rel(host(mu_same), host(mu_c)) <= RMS_REL_TOL
+    mu_g = torch.zeros(f.n, 3, dtype=torch.float32, device=dev())
+
+    def solve():
+        fixed.scf(pme_f, pos, q, a, box, max_iter=k, mu=mu_g)
+        return fixed.model(pme_f, pos, q, mu_g, a, box)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        ref = {kk: v.clone() for kk, v in solve().items()}
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out = solve()
+    for r in range(3):
+        for v in out.values():
+            v.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for kk in ref:
+            if kk == "energy":
+                assert rel(float(out[kk][0]), float(ref[kk][0])) <= E_REL_TOL, (r, kk)
+            else:
+                # dU/dmu vanishes at the solution: measured on the scale of the forces
+                floor = float(np.sqrt(np.mean(host(ref["dU_dpos"]) ** 2)))
+                assert rms_rel(host(out[kk]), host(ref[kk]), floor=floor) <= RMS_REL_TOL, (r, kk)
+        plan.model(pme, pos, q, mu_c, a, box)   # eager work between replays
+        torch.cuda.synchronize()
+    # the fixed-count dipoles are the converged ones: stationarity of U
+    stat = float(torch.sqrt(torch.mean(out["dU_dmu"] ** 2)))
+    ref_field = float(torch.sqrt(torch.mean(ref["dU_dpos"] ** 2)))
+    print("fixed solve: iterations", it, "graph count", k, "rms dU/dmu", stat, flush=True)
+    assert stat <= 1e-4 * max(ref_field, 1e-6) + 1e-5
