@@ -19,4 +19,10 @@ ewald     explicit Ewald summation for charges and point dipoles (the
           conventional baseline the paper validates against, Sec. 2.3 and 3)
 quad      the quadrupole channel the paper names as its next extension
           (Sec. 4): density, self terms, PME and Ewald energies and gradients
+pol       the Thole-damped polarizable teacher: real-space pair sum, its
+          gradients and Hessian rows, and the self-consistent dipoles
+dip       the learned dipole head on local features (Sec. 2.2) and its
+          training through PME (Sec. 2.4)
+heads     the charge head (Sec. 2.2) and training on conservative forces
+          (Sec. 2.4), second order through the features and both networks
 """

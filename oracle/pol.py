@@ -133,6 +133,57 @@ def real_mixed(pos, q, mu, box, alpha, rc, pol, v_pos, A=THOLE_A):
     return g
 
 
+def real_charge_grad(pos, q, mu, box, alpha, rc, pol, A=THOLE_A):
+    """dE_real/dq (n,): differentiating the pair energy in q_i, the (i, j) and (j, i)
+    visits give the same term, so with the factor 1/2
+        dE/dq_i = sum_j [q_j B0 + (mu_j . R_ij) B1t]."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    q = np.zeros(n) if q is None else np.asarray(q, dtype=np.float64)
+    mu = np.zeros((n, 3)) if mu is None else np.asarray(mu, dtype=np.float64)
+    pol = np.asarray(pol, dtype=np.float64)
+    ia, ja, R, r = _pairs(pos, box, rc)
+    s = (pol[ia] * pol[ja]) ** (1.0 / 6.0)
+    B0, B1, _, _ = thole_b(r, s, alpha, A)
+    g = np.zeros(n)
+    np.add.at(g, ia, q[ja] * B0 + np.einsum('pc,pc->p', mu[ja], R) * B1)
+    return g
+
+
+def real_hvp(pos, q, mu, box, alpha, rc, pol, v_pos=None, v_q=None, v_mu=None, A=THOLE_A):
+    """The q and mu rows of the E_real Hessian in (r, q, mu) applied to the tangent
+    (v_pos, v_q, v_mu): returns (h_q (n,), h_mu (n, 3)).
+
+    E_real is bilinear in (q, mu), so the (q, mu) columns are the first-order
+    gradients evaluated with charges v_q and dipoles v_mu.  The r column is the
+    derivative of dE/dq_i and dE/dmu_i along w = v_i - v_j, with grad B0 = -R B1
+    (undamped) and grad B_l^t = -R B_{l+1}^t:
+        h_q  += -q_j B1 (R.w) + B1t (mu_j.w) - (mu_j.R) B2t (R.w)
+        h_mu += the mu-r block of real_mixed."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    q = np.zeros(n) if q is None else np.asarray(q, dtype=np.float64)
+    mu = np.zeros((n, 3)) if mu is None else np.asarray(mu, dtype=np.float64)
+    v = np.zeros((n, 3)) if v_pos is None else np.asarray(v_pos, dtype=np.float64)
+    vq = np.zeros(n) if v_q is None else np.asarray(v_q, dtype=np.float64)
+    vm = np.zeros((n, 3)) if v_mu is None else np.asarray(v_mu, dtype=np.float64)
+    pol = np.asarray(pol, dtype=np.float64)
+    ia, ja, R, r = _pairs(pos, box, rc)
+    s = (pol[ia] * pol[ja]) ** (1.0 / 6.0)
+    _, B1, B2, _ = thole_b(r, s, alpha, A)
+    B1u = _bl(r, alpha, 1)[1]
+    w = v[ia] - v[ja]
+    rw = np.einsum('pc,pc->p', R, w)
+    mjr = np.einsum('pc,pc->p', mu[ja], R)
+    mjw = np.einsum('pc,pc->p', mu[ja], w)
+    h_q = np.zeros(n)
+    np.add.at(h_q, ia, -q[ja] * B1u * rw + B1 * mjw - mjr * B2 * rw)
+    h_q += real_charge_grad(pos, vq, vm, box, alpha, rc, pol, A)
+    h_mu = real_mixed(pos, q, mu, box, alpha, rc, pol, v, A)
+    h_mu += real_space(pos, vq, vm, box, alpha, rc, pol, A)[2]
+    return h_q, h_mu
+
+
 def real_dipole_matrix(pos, box, alpha, rc, pol, A=THOLE_A):
     """Dense mu-mu Hessian of E_real, (3N, 3N)."""
     n = pos.shape[0]
@@ -184,3 +235,28 @@ def model(pos, q, mu, box, mesh, p, alpha, rc, pol, A=THOLE_A, gamma=1.0):
     er, gr_pos, gr_mu = real_space(pos, q, mu, box, alpha, rc, pol, A)
     u = f.energy + er + float(np.sum(np.sum(mu * mu, axis=1) / (2.0 * pol)))
     return u, f.dE_dpos + gr_pos, f.dE_dmu + gr_mu + mu / pol[:, None]
+
+
+def model_grads(pos, q, mu, box, mesh, p, alpha, rc, pol, A=THOLE_A, gamma=1.0):
+    """U and its gradients in all three inputs: (U, dU/dr, dU/dq, dU/dmu)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    mu = np.asarray(mu, dtype=np.float64)
+    pol = np.asarray(pol, dtype=np.float64)
+    f = opme.forward(pos, q, mu, box, mesh, p, alpha, gamma)
+    er, gr_pos, gr_mu = real_space(pos, q, mu, box, alpha, rc, pol, A)
+    gr_q = real_charge_grad(pos, q, mu, box, alpha, rc, pol, A)
+    u = f.energy + er + float(np.sum(np.sum(mu * mu, axis=1) / (2.0 * pol)))
+    return u, f.dE_dpos + gr_pos, f.dE_dq + gr_q, f.dE_dmu + gr_mu + mu / pol[:, None]
+
+
+def model_hvp(pos, q, mu, box, mesh, p, alpha, rc, pol, v_pos=None, v_q=None, v_mu=None,
+              A=THOLE_A, gamma=1.0):
+    """The q and mu rows of the Hessian of U (E_lr + E_real + polarization) in
+    (r, q, mu) applied to (v_pos, v_q, v_mu): returns (h_q, h_mu)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    pol = np.asarray(pol, dtype=np.float64)
+    vm = np.zeros((n, 3)) if v_mu is None else np.asarray(v_mu, dtype=np.float64)
+    _, l_q, l_mu = opme.hvp(pos, q, mu, box, mesh, p, alpha, v_pos, v_q, v_mu, gamma)
+    r_q, r_mu = real_hvp(pos, q, mu, box, alpha, rc, pol, v_pos, v_q, v_mu, A)
+    return l_q + r_q, l_mu + r_mu + vm / pol[:, None]

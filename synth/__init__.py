@@ -215,3 +215,16 @@ def mlp_init(seed: int, layers=((64, 34), (64, 64), (16, 64)), last_scale: float
         parts.append(rng.uniform(-lim, lim, (fo, fi)).reshape(-1))
         parts.append(np.zeros(fo))
     return np.concatenate(parts)
+
+
+def charge_head_init(seed: int, hidden: int = 64, nfeat: int = 34, last_scale: float = 0.1,
+                     bias_scale: float = 0.0):
+    """Seeded initial parameters of the charge head, flat in the order W1 b1 w2:
+    Glorot-uniform weights (the output layer scaled by `last_scale`) and biases
+    uniform in +-bias_scale."""
+    rng = np.random.default_rng(seed)
+    lim1 = math.sqrt(6.0 / (nfeat + hidden))
+    lim2 = math.sqrt(6.0 / (hidden + 1)) * last_scale
+    return np.concatenate([rng.uniform(-lim1, lim1, hidden * nfeat),
+                           rng.uniform(-bias_scale, bias_scale, hidden),
+                           rng.uniform(-lim2, lim2, hidden)])
