@@ -27,8 +27,30 @@
  * dip_loss returns v and the first and last terms.  H_{mu r} v is the dipole
  * output of pme_backward with position cotangent v, plus pol_real_mixed.
  *
+ * Charge head (Sec. 2.2, Eq. charge_pred): a two-layer perceptron with SiLU on
+ * the same 34 inputs, c_i = w2 . silu(W1q feat_i + b1q), and
+ *     q_i = z_i + c_i - (1/n) sum_k c_k,
+ * the formal charges z (the q of dip_features, which fix the species and the
+ * vector weights) plus a centred correction, so the cell keeps its total charge
+ * (the PME energy assumes a neutral cell).  An output bias would cancel in the
+ * centring and is left out.  Parameters: W1q [64][34], b1q [64], w2q [64]
+ * (DIP_NQPARAM values).
+ *
+ * Conservative forces (Eq. forces) of U(r, q(r), mu(r)) add the head channels
+ * J_q^T dU/dq + J_mu^T dU/dmu to dU/dr (dip_position_vjp).  Training on them
+ * needs the parameter derivative of v . dU/dr, v = dL/d(dU/dr), which is
+ * second order: with t = (v, q_dot, mu_dot) the tangent of (r, q, mu) along v,
+ *     dL/dtheta = [a U_q + H_q. t]^T dq/dtheta + [a U_mu + H_mu. t]^T dmu/dtheta
+ *               + U_q^T d(q_dot)/dtheta + U_mu^T d(mu_dot)/dtheta,
+ * a = dL/dU, U_q = dU/dq, U_mu = dU/dmu, H_q. and H_mu. the q and mu rows of the
+ * model Hessian (pol_model_hvp).  The calls in order: dip_features_jvp (the
+ * feature tangent along v), dip_charges and dip_forward_jvp (q_dot, mu_dot),
+ * pol_model_hvp, dip_backward_jvp (reverse mode through the forward-mode
+ * networks).
+ *
  * Conventions as in pme.h: device FP32 arrays, asynchronous on `stream`,
- * PME_* return codes.
+ * PME_* return codes.  A plan's workspaces are shared by its calls: calls on one
+ * plan must not overlap in time.
  */
 #ifndef DIP_MI355X_H
 #define DIP_MI355X_H
@@ -45,6 +67,7 @@ extern "C" {
 #define DIP_NCH 16
 #define DIP_HIDDEN 64
 #define DIP_NPARAM 7440
+#define DIP_NQPARAM 2304
 
 typedef struct dip_plan_s* dip_plan_t;
 
@@ -74,29 +97,73 @@ int dip_backward(dip_plan_t plan, void* stream, int32_t n, const float* params, 
                  const float* vec, const float* g_mu0, const float* g_mu1, const float* g_mu2,
                  float* g_params);
 
-/* Position vector-Jacobian product of the dipole head: g_pos[j] = sum_i (d mu_i /
- * d r_j)^T u_i (overwritten), for u [n][3] (device).  With u = dU/dmu it is the
- * term that turns the Hellmann-Feynman force of Eq. loss into the conservative
- * student force F = -dU(r, mu_NN(r))/dr = -(dU/dr + g_pos) (the total derivative
- * through the dipole prediction, Eq. forces).  feat and vec are dip_features of
- * the same (pos, q); the network runs back to its inputs, then the position
- * derivatives of the features are summed per atom over its pairs (each pair is
- * visited from both atoms; no atomics).  Uses the plan's cell list (rebuilt
- * here) and its [max_atoms][64] cotangent workspace; calls on one plan must not
- * overlap. */
+/* Position vector-Jacobian product of the heads: g_pos[j] = base[j] + sum_i
+ * [(d mu_i / d r_j)^T u_i + (d q_i / d r_j) c_i] (overwritten), for cotangents u
+ * [n][3] on the dipoles and c [n] on the charges (either may be NULL, not both;
+ * base NULL = zero).  With u = dU/dmu, c = dU/dq and base = dU/dr (pol_model) it
+ * is the conservative student gradient dU(r, q_NN(r), mu_NN(r))/dr = -F of
+ * Eq. forces.  feat and vec are dip_features of the same (pos, q = formal
+ * charges); params (dipole head) is needed with u, qparams (charge head) with c.
+ * The networks run back to their inputs (the charge cotangent centred first),
+ * then the position derivatives of the features are summed per atom over its
+ * pairs (each pair is visited from both atoms; no atomics).  Uses the plan's
+ * cell list (rebuilt here) and its [max_atoms][64] cotangent workspace. */
 int dip_position_vjp(dip_plan_t plan, void* stream, int32_t n, const float* params,
-                     const float* pos, const float* q, const float* feat, const float* vec,
-                     const float* u, float* g_pos);
+                     const float* qparams, const float* pos, const float* q, const float* feat,
+                     const float* vec, const float* u, const float* c, const float* base,
+                     float* g_pos);
 
-/* Loss of the student (U_s, dUdr_s at dipoles mu, with dU/dmu dUdmu_s) against
- * the teacher (U_t, dUdr_t, mu_t; mu_t may be NULL when lmu = 0).
+/* Directional derivative of dip_features along the position tangent v [n][3]:
+ *     G_dot  = sum_j R_k'(r) r_dot
+ *     V_dot  = sum_j q_j [R_k'(r) r_dot u + R_k(r)/r (w - r_dot u)]
+ * (w = v_i - v_j, u = R/r, r_dot = u . w), the |V_c|^2 entries 2 V_c . V_dot_c
+ * and zeros for the species one-hot.  vec is dip_features' output for the same
+ * (pos, q).  Outputs feat_dot [n][34], vec_dot [n][16][3]. */
+int dip_features_jvp(dip_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
+                     const float* vec, const float* v, float* feat_dot, float* vec_dot);
+
+/* Charges of the charge head q [n] from the formal charges z [n] and features,
+ * and (feat_dot non-NULL) the tangent q_dot [n] = centred directional
+ * derivative along feat_dot (NULL feat_dot: q_dot = 0).  Either output may be
+ * NULL, not both. */
+int dip_charges(dip_plan_t plan, void* stream, int32_t n, const float* qparams, const float* z,
+                const float* feat, const float* feat_dot, float* q, float* q_dot);
+
+/* Dipoles mu (as dip_forward) and their tangent mu_dot_i = sum_c (w_dot_ic V_ic +
+ * w_ic V_dot_ic), w_dot the network's directional derivative along feat_dot
+ * (NULL feat_dot, vec_dot = zero tangents).  Either output may be NULL. */
+int dip_forward_jvp(dip_plan_t plan, void* stream, int32_t n, const float* params,
+                    const float* feat, const float* vec, const float* feat_dot,
+                    const float* vec_dot, float* mu, float* mu_dot);
+
+/* Parameter gradients of both heads (overwritten; either may be NULL, not both)
+ * for a loss of the heads' outputs and their tangents along one position
+ * direction, given
+ *   on mu:      g_mu0 + g_mu1   [n][3]    on mu_dot: u [n][3]
+ *   on q:       g_q0 + g_q1     [n]       on q_dot:  c [n]
+ * (NULL = zero) and the feature tangents of dip_features_jvp (NULL = zero: then
+ * u and c have no effect and this is the first-order gradient).  Reverse mode
+ * through the forward-mode networks, so silu'' couples the two passes; charge
+ * cotangents are centred as the charges are.  Deterministic: at most 512
+ * workgroups each sum their tiles, then the partial rows are added in order. */
+int dip_backward_jvp(dip_plan_t plan, void* stream, int32_t n, const float* params,
+                     const float* qparams, const float* feat, const float* vec,
+                     const float* feat_dot, const float* vec_dot, const float* g_mu0,
+                     const float* g_mu1, const float* u, const float* g_q0, const float* g_q1,
+                     const float* c, float* g_params, float* g_qparams);
+
+/* Loss of the student (U_s, dUdr_s at dipoles mu, with dU/dmu dUdmu_s and dU/dq
+ * dUdq_s) against the teacher (U_t, dUdr_t, mu_t; mu_t may be NULL when lmu = 0).
+ * dUdr_s is the Hellmann-Feynman gradient or the conservative one of
+ * dip_position_vjp.
  *   loss   device double[1]
- *   v_pos  device float[n][3]: dL/d(dU/dr), the cotangent for H_{mu r}
- *   g_mu   device float[n][3]: dL/dU dU/dmu + 2 lmu (mu - mu_t)/(3n) */
+ *   v_pos  device float[n][3]: dL/d(dU/dr), the cotangent for the Hessian rows
+ *   g_mu   device float[n][3]: dL/dU dU/dmu + 2 lmu (mu - mu_t)/(3n)
+ *   g_q    device float[n]: dL/dU dU/dq (with dUdq_s; both NULL or neither) */
 int dip_loss(dip_plan_t plan, void* stream, int32_t n, const double* U_s, const double* U_t,
              const float* dUdr_s, const float* dUdr_t, const float* mu, const float* mu_t,
-             const float* dUdmu_s, double lE, double lF, double lmu, double* loss,
-             float* v_pos, float* g_mu);
+             const float* dUdmu_s, const float* dUdq_s, double lE, double lF, double lmu,
+             double* loss, float* v_pos, float* g_mu, float* g_q);
 
 /* One Adam step (t = 1, 2, ...) on `count` parameters:
  * m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,

@@ -26,6 +26,8 @@
  * - Outputs are overwritten; a NULL output is skipped; a NULL q or mu means zero.
  * - Calls are asynchronous on `stream`, except pol_scf, which synchronises once
  *   per iteration to test convergence (unless POL_F_FIXED_ITERS).
+ * - A plan's workspaces are shared by its calls: calls on one plan must not
+ *   overlap in time (one stream, or ordered by events).
  * - Every energy and gradient is multiplied by `prefactor`, including the
  *   polarization term, so the dipoles do not depend on it. It must equal the
  *   prefactor of the PME plan used with pol_scf.
@@ -74,9 +76,11 @@ void pol_plan_destroy(pol_plan_t plan);
  * within r_c under the minimum image).
  *   energy   device double[1] or NULL
  *   dE_dpos  device float[n*3] or NULL
+ *   dE_dq    device float[n] or NULL: sum_j [q_j B0 + (mu_j . R_ij) B1t]
  *   dE_dmu   device float[n*3] or NULL */
 int pol_real(pol_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
-             const float* mu, const float* pol, double* energy, float* dE_dpos, float* dE_dmu);
+             const float* mu, const float* pol, double* energy, float* dE_dpos, float* dE_dq,
+             float* dE_dmu);
 
 /* Mixed second derivative of E_real applied to a position cotangent:
  * g_mu = d/dmu (grad_r E_real . v_pos).  Used for the force-loss gradient of
@@ -84,15 +88,33 @@ int pol_real(pol_plan_t plan, void* stream, int32_t n, const float* pos, const f
 int pol_real_mixed(pol_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
                    const float* mu, const float* pol, const float* v_pos, float* g_mu);
 
-/* U(mu) of the model and its gradients at the given dipoles (pme_forward +
- * pol_real + the polarization term sum |mu|^2 / (2 a)).  The teacher's forces are
- * -dU_dpos at the self-consistent dipoles; a student's at its predicted ones.
+/* U(q, mu) of the model and its gradients at the given charges and dipoles
+ * (pme_forward + pol_real + the polarization term sum |mu|^2 / (2 a)).  The
+ * teacher's forces are -dU_dpos at the self-consistent dipoles; a student's
+ * Hellmann-Feynman forces the same at its predicted ones.
  *   energy   device double[1] or NULL
  *   dU_dpos  device float[n*3] or NULL
+ *   dU_dq    device float[n] or NULL (the electrostatic potential at each atom)
  *   dU_dmu   device float[n*3] or NULL */
 int pol_model(pol_plan_t plan, pme_plan_t pme, void* stream, int32_t n, const float* pos,
               const float* q, const float* mu, const float* pol, const double* box,
-              double* energy, float* dU_dpos, float* dU_dmu);
+              double* energy, float* dU_dpos, float* dU_dq, float* dU_dmu);
+
+/* The q and mu rows of the Hessian of U in (r, q, mu) applied to the tangent
+ * (v_pos, v_q, v_mu) (each NULL = zero):
+ *   g_q  = d/dq  (grad U . t),  device float[n]
+ *   g_mu = d/dmu (grad U . t),  device float[n*3]
+ * PME part: pme_backward with the three cotangents (Sec. 2.3.5).  Real-space
+ * part: E_real is bilinear in (q, mu), so its (q, mu) columns are the pol_real
+ * gradients with charges v_q and dipoles v_mu; its r column differentiates
+ * dE/dq_i and dE/dmu_i along w = v_i - v_j (grad B0 = -R B1 undamped, grad
+ * B_l^t = -R B_{l+1}^t).  The polarization term adds (prefactor / a) v_mu.
+ * These rows are what training a charge and dipole head on forces needs
+ * (Eq. loss with the forces of Eq. forces). */
+int pol_model_hvp(pol_plan_t plan, pme_plan_t pme, void* stream, int32_t n, const float* pos,
+                  const float* q, const float* mu, const float* pol, const double* box,
+                  const float* v_pos, const float* v_q, const float* v_mu, float* g_q,
+                  float* g_mu);
 
 /* Self-consistent induced dipoles by preconditioned conjugate gradients.
  *

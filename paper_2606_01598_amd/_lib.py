@@ -38,12 +38,13 @@ EXPORTS = ("pme_mesh_dims", "pme_plan", "pme_plan_destroy", "pme_plan_workspace_
            "pme_forward", "pme_forward_cell", "pme_forward_quad", "pme_backward", "pme_step", "pme_step_capture", "pme_step_replay", "pme_status", "pme_strerror", "pme_last_hip_error",
            "pme_plan_phi", "pme_plan_rho", "pme_plan_timer", "pme_plan_timer_read",
            "pol_plan_create", "pol_plan_destroy", "pol_real", "pol_real_mixed", "pol_model",
-           "pol_scf", "dip_plan_create", "dip_plan_destroy", "dip_features", "dip_forward",
-           "dip_backward", "dip_position_vjp", "dip_loss", "dip_adam", "pme_batch_plan", "pme_batch_destroy",
+           "pol_model_hvp", "pol_scf", "dip_plan_create", "dip_plan_destroy", "dip_features",
+           "dip_forward", "dip_backward", "dip_position_vjp", "dip_features_jvp", "dip_charges",
+           "dip_forward_jvp", "dip_backward_jvp", "dip_loss", "dip_adam", "pme_batch_plan", "pme_batch_destroy",
            "pme_batch_forward", "pme_batch_backward", "pme_batch_graph_capture", "pme_batch_graph_launch",
            "pme_batch_status", "pme_lds_probe")
 
-DIP_NFEAT, DIP_NCH, DIP_HIDDEN, DIP_NPARAM = 34, 16, 64, 7440
+DIP_NFEAT, DIP_NCH, DIP_HIDDEN, DIP_NPARAM, DIP_NQPARAM = 34, 16, 64, 7440, 2304
 
 # launch-timer kinds (PME_K_* of include/pme.h)
 KERNEL_KINDS = ("bin", "bin_tangent", "spread", "spread_tangent", "fft_r2c", "fft_x",
@@ -158,12 +159,14 @@ def load():
     lib.pol_plan_create.restype = ctypes.c_int
     lib.pol_plan_destroy.argtypes = [vp]
     lib.pol_plan_destroy.restype = None
-    lib.pol_real.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
+    lib.pol_real.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.pol_real.restype = ctypes.c_int
     lib.pol_real_mixed.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp]
     lib.pol_real_mixed.restype = ctypes.c_int
-    lib.pol_model.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.pol_model.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.pol_model.restype = ctypes.c_int
+    lib.pol_model_hvp.argtypes = [vp, vp, vp, i32] + [vp] * 10
+    lib.pol_model_hvp.restype = ctypes.c_int
     lib.pol_scf.argtypes = [vp, vp, vp, i32, vp, vp, vp, vp, f64, i32, vp,
                             ctypes.POINTER(i32), ctypes.POINTER(f64)]
     lib.pol_scf.restype = ctypes.c_int
@@ -194,9 +197,18 @@ def load():
     lib.dip_forward.restype = ctypes.c_int
     lib.dip_backward.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp]
     lib.dip_backward.restype = ctypes.c_int
-    lib.dip_position_vjp.argtypes = [vp, vp, i32] + [vp] * 7
+    lib.dip_position_vjp.argtypes = [vp, vp, i32] + [vp] * 10
     lib.dip_position_vjp.restype = ctypes.c_int
-    lib.dip_loss.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, f64, f64, f64, vp, vp, vp]
+    lib.dip_features_jvp.argtypes = [vp, vp, i32] + [vp] * 6
+    lib.dip_features_jvp.restype = ctypes.c_int
+    lib.dip_charges.argtypes = [vp, vp, i32] + [vp] * 6
+    lib.dip_charges.restype = ctypes.c_int
+    lib.dip_forward_jvp.argtypes = [vp, vp, i32] + [vp] * 7
+    lib.dip_forward_jvp.restype = ctypes.c_int
+    lib.dip_backward_jvp.argtypes = [vp, vp, i32] + [vp] * 14
+    lib.dip_backward_jvp.restype = ctypes.c_int
+    lib.dip_loss.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, f64, f64, f64, vp, vp,
+                             vp, vp]
     lib.dip_loss.restype = ctypes.c_int
     lib.dip_adam.argtypes = [vp, i32, i32, f64, f64, f64, f64, vp, vp, vp, vp]
     lib.dip_adam.restype = ctypes.c_int

@@ -24,7 +24,7 @@ namespace {
 constexpr int kLanes = 16;          // lanes per atom in the pair kernels
 constexpr int kPairThreads = 256;
 
-enum PairMode { kEnergyGrad = 0, kMuGrad = 1, kMixed = 2 };
+enum PairMode { kEnergyGrad = 0, kMuGrad = 1, kMixed = 2, kHvp = 3 };
 
 struct PairArgs {
   int n;
@@ -33,6 +33,8 @@ struct PairArgs {
   const float* mu;
   const float* pol;
   const float* vpos;
+  const float* vq;   // charge and dipole tangents (kHvp)
+  const float* vmu;
   CellGrid g;
   const int* start;
   const int* sorted;
@@ -41,7 +43,8 @@ struct PairArgs {
   float A;
   float pf;
   float* o_pos;      // dE/dr
-  float* o_mu;       // dE/dmu (or the mixed block)
+  float* o_q;        // dE/dq (or the q row of the Hessian product)
+  float* o_mu;       // dE/dmu (or the mixed block, or the mu row)
   double* epart;     // [blocks] energy partials
 };
 
@@ -68,14 +71,15 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
   const float qi = a.q ? a.q[ii] : 0.0f;
   const float3 mi = ld3(a.mu, ii);
   const float ai = a.pol[ii];
-  const float3 vi = (MODE == kMixed) ? ld3(a.vpos, ii) : make_float3(0.f, 0.f, 0.f);
+  const float3 vi =
+      (MODE == kMixed || MODE == kHvp) ? ld3(a.vpos, ii) : make_float3(0.f, 0.f, 0.f);
   int c[3], no[3];
   cell_of(a.g, pi.x, pi.y, pi.z, c);
 #pragma unroll
   for (int d = 0; d < 3; ++d) no[d] = a.g.nc[d] < 3 ? a.g.nc[d] : 3;
   const float sqpi = 1.7724538509055159f;
   const float t2 = 2.0f * a.alpha * a.alpha;
-  float e = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
+  float e = 0.f, gx = 0.f, gy = 0.f, gz = 0.f, mx = 0.f, my = 0.f, mz = 0.f, gq = 0.f;
   if (live) {
     for (int ox = 0; ox < no[0]; ++ox)
       for (int oy = 0; oy < no[1]; ++oy)
@@ -113,6 +117,26 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
             const float qj = a.q ? a.q[j] : 0.0f;
             const float3 mj = ld3(a.mu, j);
             const float mjr = dot3(mj, R);
+            if (MODE == kHvp) {
+              // r column: d/dR of dE/dq_i and dE/dmu_i along w = v_i - v_j
+              // (grad B0 = -R B1 undamped); (q, mu) columns: the bilinear
+              // gradients with charges vq and dipoles vmu
+              const float3 vj = ld3(a.vpos, j);
+              const float3 w = make_float3(vi.x - vj.x, vi.y - vj.y, vi.z - vj.z);
+              const float rw = dot3(R, w), mjw = dot3(mj, w);
+              const float vqj = a.vq ? a.vq[j] : 0.0f;
+              const float3 vmj = ld3(a.vmu, j);
+              const float vmjr = dot3(vmj, R);
+              gq += -qj * B1 * rw + B1t * mjw - mjr * B2t * rw + vqj * B0 + vmjr * B1t;
+              const float cw = -qj * B1t - mjr * B2t;
+              const float cR = qj * rw * B2t - mjw * B2t + rw * mjr * B3t - vqj * B1t -
+                               vmjr * B2t;
+              const float cm = -rw * B2t;
+              mx += cw * w.x + cR * R.x + cm * mj.x + B1t * vmj.x;
+              my += cw * w.y + cR * R.y + cm * mj.y + B1t * vmj.y;
+              mz += cw * w.z + cR * R.z + cm * mj.z + B1t * vmj.z;
+              continue;
+            }
             if (MODE == kMixed) {
               const float3 vj = ld3(a.vpos, j);
               const float3 w = make_float3(vi.x - vj.x, vi.y - vj.y, vi.z - vj.z);
@@ -131,6 +155,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
             my += cRm * R.y + B1t * mj.y;
             mz += cRm * R.z + B1t * mj.z;
             if (MODE == kEnergyGrad) {
+              gq += qj * B0 + mjr * B1t;
               const float mir = dot3(mi, R), mm = dot3(mi, mj);
               const float cross = qi * mjr - qj * mir;
               e += 0.5f * (qi * qj * B0 + cross * B1t + mm * B1t - mir * mjr * B2t);
@@ -143,6 +168,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
         }
   }
   mx = lane_sum(mx); my = lane_sum(my); mz = lane_sum(mz);
+  if (MODE == kEnergyGrad || MODE == kHvp) gq = lane_sum(gq);
   if (MODE == kEnergyGrad) {
     e = lane_sum(e);
     gx = lane_sum(gx); gy = lane_sum(gy); gz = lane_sum(gz);
@@ -153,6 +179,7 @@ __global__ void __launch_bounds__(kPairThreads) k_pair(PairArgs a) {
       a.o_mu[3 * i + 1] = a.pf * my;
       a.o_mu[3 * i + 2] = a.pf * mz;
     }
+    if ((MODE == kEnergyGrad || MODE == kHvp) && a.o_q) a.o_q[i] = a.pf * gq;
     if (MODE == kEnergyGrad && a.o_pos) {
       a.o_pos[3 * i] = a.pf * gx;
       a.o_pos[3 * i + 1] = a.pf * gy;
@@ -262,6 +289,12 @@ __global__ void k_model_grads(int n, float pf, const float* pol, const float* mu
   if (dmu) dmu[k] = gm[k] + hm[k] + (mu ? pf * mu[k] / pol[k / 3] : 0.0f);
 }
 
+// dU_dq = g_q + h_q
+__global__ void k_add(int m, const float* a, const float* b, float* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) out[k] = a[k] + b[k];
+}
+
 // energy = e_lr[0] + e_lr[1] + e_lr[2] + e_real + pf sum |mu|^2 / (2 a) (one workgroup)
 __global__ void __launch_bounds__(256) k_model_energy(int n, double pf, const float* pol,
                                                       const float* mu, const double* e_lr,
@@ -319,14 +352,15 @@ inline int blocks_for(int m, int t) { return cell_blocks(m, t); }
 PairArgs pair_args(const pol_plan_s* pl, int n, const float* pos, const float* q, const float* mu,
                    const float* pol) {
   PairArgs a;
-  a.n = n; a.pos = pos; a.q = q; a.mu = mu; a.pol = pol; a.vpos = nullptr;
+  a.n = n; a.pos = pos; a.q = q; a.mu = mu; a.pol = pol;
+  a.vpos = nullptr; a.vq = nullptr; a.vmu = nullptr;
   a.g = pl->cells.g;
   a.start = pl->cells.start; a.sorted = pl->cells.sorted;
   a.alpha = float(pl->desc.alpha);
   a.rc2 = float(pl->desc.cutoff * pl->desc.cutoff);
   a.A = float(pl->desc.thole_a);
   a.pf = float(pl->desc.prefactor);
-  a.o_pos = nullptr; a.o_mu = nullptr; a.epart = nullptr;
+  a.o_pos = nullptr; a.o_q = nullptr; a.o_mu = nullptr; a.epart = nullptr;
   return a;
 }
 
@@ -388,13 +422,15 @@ void pol_plan_destroy(pol_plan_t plan) {
 }
 
 int pol_real(pol_plan_t plan, void* stream, int32_t n, const float* pos, const float* q,
-             const float* mu, const float* pol, double* energy, float* dE_dpos, float* dE_dmu) {
+             const float* mu, const float* pol, double* energy, float* dE_dpos, float* dE_dq,
+             float* dE_dmu) {
   if (!check_common(plan, n, pos, pol)) return PME_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   hipError_t e = build_cells(plan->cells, s, n, pos);
   if (e != hipSuccess) return pol_hip_fail(e);
   PairArgs a = pair_args(plan, n, pos, q, mu, pol);
   a.o_pos = dE_dpos;
+  a.o_q = dE_dq;
   a.o_mu = dE_dmu;
   a.epart = energy ? plan->epart : nullptr;
   const int nb = pair_blocks(n);
@@ -428,7 +464,7 @@ int pol_real_mixed(pol_plan_t plan, void* stream, int32_t n, const float* pos, c
 
 int pol_model(pol_plan_t plan, pme_plan_t pme, void* stream, int32_t n, const float* pos,
               const float* q, const float* mu, const float* pol, const double* box,
-              double* energy, float* dU_dpos, float* dU_dmu) {
+              double* energy, float* dU_dpos, float* dU_dq, float* dU_dmu) {
   if (!check_common(plan, n, pos, pol) || !pme || !box) return PME_EINVAL;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t stride = size_t(3) * plan->desc.max_atoms;
@@ -436,21 +472,55 @@ int pol_model(pol_plan_t plan, pme_plan_t pme, void* stream, int32_t n, const fl
   float* gm = plan->vec + 5 * stride;
   float* hp = plan->vec + 6 * stride;     // real-space gradients
   float* hm = plan->vec + 7 * stride;
+  float* gq = plan->vec;                  // charge gradients (PME, real space)
+  float* hq = plan->vec + stride;
   double* e_lr = plan->scal;              // [0..2]
   double* e_re = plan->scal + 3;
   int rc = pme_forward(pme, stream, n, pos, q, mu, box, energy ? e_lr : nullptr,
-                       dU_dpos ? gp : nullptr, nullptr, dU_dmu ? gm : nullptr);
+                       dU_dpos ? gp : nullptr, dU_dq ? gq : nullptr, dU_dmu ? gm : nullptr);
   if (rc != PME_OK) return rc;
   if ((rc = pol_real(plan, stream, n, pos, q, mu, pol, energy ? e_re : nullptr,
-                     dU_dpos ? hp : nullptr, dU_dmu ? hm : nullptr)) != PME_OK)
+                     dU_dpos ? hp : nullptr, dU_dq ? hq : nullptr,
+                     dU_dmu ? hm : nullptr)) != PME_OK)
     return rc;
   if (n > 0 && (dU_dpos || dU_dmu))
     hipLaunchKernelGGL(k_model_grads, dim3(blocks_for(3 * n, 256)), dim3(256), 0, s, n,
                        float(plan->desc.prefactor), pol, mu, gp, hp, gm, hm, dU_dpos, dU_dmu);
+  if (n > 0 && dU_dq)
+    hipLaunchKernelGGL(k_add, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, gq, hq, dU_dq);
   if (energy)
     hipLaunchKernelGGL(k_model_energy, dim3(1), dim3(256), 0, s, n, plan->desc.prefactor, pol,
                        mu, e_lr, e_re, energy);
   hipError_t e = hipGetLastError();
+  return e == hipSuccess ? PME_OK : pol_hip_fail(e);
+}
+
+int pol_model_hvp(pol_plan_t plan, pme_plan_t pme, void* stream, int32_t n, const float* pos,
+                  const float* q, const float* mu, const float* pol, const double* box,
+                  const float* v_pos, const float* v_q, const float* v_mu, float* g_q,
+                  float* g_mu) {
+  if (!check_common(plan, n, pos, pol) || !pme || !box || !g_q || !g_mu) return PME_EINVAL;
+  if (n == 0) return PME_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t stride = size_t(3) * plan->desc.max_atoms;
+  float* lq = plan->vec;                  // PME rows
+  float* lm = plan->vec + 4 * stride;
+  float* rq = plan->vec + stride;         // real-space rows
+  float* rm = plan->vec + 5 * stride;
+  int rc = pme_backward(pme, stream, n, pos, q, mu, box, v_pos, v_q, v_mu, nullptr, lq, lm);
+  if (rc != PME_OK) return rc;
+  hipError_t e = build_cells(plan->cells, s, n, pos);
+  if (e != hipSuccess) return pol_hip_fail(e);
+  PairArgs a = pair_args(plan, n, pos, q, mu, pol);
+  a.vpos = v_pos; a.vq = v_q; a.vmu = v_mu;
+  a.o_q = rq;
+  a.o_mu = rm;
+  hipLaunchKernelGGL(k_pair<kHvp>, dim3(pair_blocks(n)), dim3(kPairThreads), 0, s, a);
+  // mu row: the polarization term adds (pf / a) v_mu (k_model_grads with mu = v_mu)
+  hipLaunchKernelGGL(k_model_grads, dim3(blocks_for(3 * n, 256)), dim3(256), 0, s, n,
+                     float(plan->desc.prefactor), pol, v_mu, lm, rm, lm, rm, nullptr, g_mu);
+  hipLaunchKernelGGL(k_add, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, lq, rq, g_q);
+  e = hipGetLastError();
   return e == hipSuccess ? PME_OK : pol_hip_fail(e);
 }
 

@@ -6,9 +6,11 @@ self-consistent solve run in the library's HIP kernels; this module checks
 shapes and passes pointers and the current stream.
 
 * ``PolPlan``              -- pol_plan_create / pol_plan_destroy
-* ``PolPlan.real(...)``    -- pol_real: E_real, dE_real/dr, dE_real/dmu
+* ``PolPlan.real(...)``    -- pol_real: E_real, dE_real/dr, dE_real/dq, dE_real/dmu
 * ``PolPlan.mixed(...)``   -- pol_real_mixed: d/dmu (grad_r E_real . v)
-* ``PolPlan.model(...)``   -- pol_model: U(mu), dU/dr, dU/dmu at given dipoles
+* ``PolPlan.model(...)``   -- pol_model: U(q, mu), dU/dr, dU/dq, dU/dmu
+* ``PolPlan.model_hvp(...)`` -- pol_model_hvp: the q and mu rows of the model
+  Hessian applied to (v_pos, v_q, v_mu)
 * ``PolPlan.scf(...)``     -- pol_scf: induced dipoles by preconditioned CG
 * ``teacher(...)``         -- pol_scf then pol_model: dipoles, energy and forces
 """
@@ -65,7 +67,7 @@ class PolPlan:
         _atoms("pol", pol, n, 0, self.device)
         return n
 
-    def real(self, pos, q, mu, pol, energy=True, dE_dpos=True, dE_dmu=True):
+    def real(self, pos, q, mu, pol, energy=True, dE_dpos=True, dE_dmu=True, dE_dq=False):
         n = self._common(pos, pol)
         if q is not None:
             _atoms("q", q, n, 0, self.device)
@@ -78,9 +80,11 @@ class PolPlan:
             out["dE_dpos"] = torch.empty(n, 3, dtype=torch.float32, device=self.device)
         if dE_dmu:
             out["dE_dmu"] = torch.empty(n, 3, dtype=torch.float32, device=self.device)
+        if dE_dq:
+            out["dE_dq"] = torch.empty(n, dtype=torch.float32, device=self.device)
         _lib.check(self._lib.pol_real(self.handle, _stream(), n, _ptr(pos), _ptr(q), _ptr(mu),
                                       _ptr(pol), _ptr(out.get("energy")), _ptr(out.get("dE_dpos")),
-                                      _ptr(out.get("dE_dmu"))))
+                                      _ptr(out.get("dE_dq")), _ptr(out.get("dE_dmu"))))
         return out
 
     def mixed(self, pos, q, mu, pol, v_pos):
@@ -91,7 +95,8 @@ class PolPlan:
                                             _ptr(mu), _ptr(pol), _ptr(v_pos), _ptr(g)))
         return g
 
-    def model(self, pme_plan, pos, q, mu, pol, box, energy=True, dU_dpos=True, dU_dmu=True):
+    def model(self, pme_plan, pos, q, mu, pol, box, energy=True, dU_dpos=True, dU_dmu=True,
+              dU_dq=False):
         n = self._common(pos, pol)
         _atoms("q", q, n, 0, self.device)
         if mu is not None:
@@ -103,11 +108,32 @@ class PolPlan:
             out["dU_dpos"] = torch.empty(n, 3, dtype=torch.float32, device=self.device)
         if dU_dmu:
             out["dU_dmu"] = torch.empty(n, 3, dtype=torch.float32, device=self.device)
+        if dU_dq:
+            out["dU_dq"] = torch.empty(n, dtype=torch.float32, device=self.device)
         _lib.check(self._lib.pol_model(self.handle, pme_plan.handle, _stream(), n, _ptr(pos),
                                        _ptr(q), _ptr(mu), _ptr(pol), _ptr(box),
                                        _ptr(out.get("energy")), _ptr(out.get("dU_dpos")),
-                                       _ptr(out.get("dU_dmu"))))
+                                       _ptr(out.get("dU_dq")), _ptr(out.get("dU_dmu"))))
         return out
+
+    def model_hvp(self, pme_plan, pos, q, mu, pol, box, v_pos=None, v_q=None, v_mu=None,
+                  out=None):
+        """pol_model_hvp: (g_q [n], g_mu [n, 3]), the q and mu rows of the Hessian of U
+        applied to the tangent (v_pos, v_q, v_mu) (None = zero)."""
+        n = self._common(pos, pol)
+        _atoms("q", q, n, 0, self.device)
+        for name, t, w in (("mu", mu, 3), ("v_pos", v_pos, 3), ("v_q", v_q, 0),
+                           ("v_mu", v_mu, 3)):
+            if t is not None:
+                _atoms(name, t, n, w, self.device)
+        o = out if out is not None else {
+            "g_q": torch.empty(n, dtype=torch.float32, device=self.device),
+            "g_mu": torch.empty(n, 3, dtype=torch.float32, device=self.device)}
+        _lib.check(self._lib.pol_model_hvp(self.handle, pme_plan.handle, _stream(), n, _ptr(pos),
+                                           _ptr(q), _ptr(mu), _ptr(pol), _ptr(box), _ptr(v_pos),
+                                           _ptr(v_q), _ptr(v_mu), _ptr(o["g_q"]),
+                                           _ptr(o["g_mu"])))
+        return o
 
     def scf(self, pme_plan, pos, q, pol, box, tol: float = 1e-6, max_iter: int = 200,
             mu: Optional[torch.Tensor] = None):
