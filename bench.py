@@ -670,15 +670,22 @@ def learned_leg(n_train=256, n_val=32, epochs=12, workers=8):
                      "dUdr": o["dU_dpos"], "mu": mu})
     train, val = data[:n_train], data[n_train:]
     steps = epochs * n_train
-    tr = Trainer(dip, polp, pme, box, synth.mlp_init(7), lr=3e-3, lE=1.0, lF=1.0,
-                 warmup=max(1, steps // 20), decay=0.1, decay_steps=steps)
-    order = np.random.default_rng(5)
-    t0 = time.perf_counter()
-    for _ in range(epochs):
-        for k in order.permutation(n_train):
-            tr.step(train[k])
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
+
+    def fit(charge_head, conservative):
+        trn = Trainer(dip, polp, pme, box, synth.mlp_init(7), lr=3e-3, lE=1.0, lF=1.0,
+                      warmup=max(1, steps // 20), decay=0.1, decay_steps=steps,
+                      qtheta0=synth.charge_head_init(8) if charge_head else None,
+                      conservative=conservative)
+        order = np.random.default_rng(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(epochs):
+            for k in order.permutation(n_train):
+                trn.step(train[k])
+        torch.cuda.synchronize()
+        return trn, time.perf_counter() - t0
+
+    tr, train_s = fit(False, False)
 
     def errors(mu, b):
         s = polp.model(pme, b["pos"], b["q"], mu, b["pol"], box, energy=False, dU_dmu=False)
@@ -691,6 +698,20 @@ def learned_leg(n_train=256, n_val=32, epochs=12, workers=8):
     zero = torch.zeros(n, 3, dtype=torch.float32, device=dev)
     e_nn = np.array([errors(tr.predict(b["feat"], b["vec"]), b) for b in val])
     e_zero = np.array([errors(zero, b) for b in val])
+
+    # the charge head and training on conservative forces: the same schedule, the
+    # forces each model is trained on (conservative -dU(r, q(r), mu(r))/dr or the
+    # Hellmann-Feynman -dU/dr at the predicted charges and dipoles) on held-out boxes
+    heads = {}
+    for name, ch, cons in (("hf_charge", True, False), ("conservative", False, True),
+                           ("conservative_charge", True, True)):
+        trn, secs = fit(ch, cons)
+        ev = [trn.evaluate(b) for b in val]
+        df = np.array([float(torch.sqrt(torch.mean((o["dU_dpos"] - b["dUdr"]) ** 2)))
+                       / float(torch.sqrt(torch.mean(b["dUdr"] ** 2))) for o, b in zip(ev, val)])
+        dq = [float(torch.sqrt(torch.mean((o["q"] - b["q"]) ** 2))) for o, b in zip(ev, val)]
+        heads[name] = {"force_rel": float(df.mean()), "charge_rms_shift": float(np.mean(dq)),
+                       "train_ms_per_step": round(secs * 1e3 / steps, 4)}
     b = val[0]
 
     def infer():
@@ -704,7 +725,8 @@ def learned_leg(n_train=256, n_val=32, epochs=12, workers=8):
         feat, vec = dip.features(b["pos"], b["q"])
         mu = dip.forward(tr.theta, feat, vec)
         s = polp.model(pme, b["pos"], b["q"], mu, b["pol"], box)
-        return s["dU_dpos"] + dip.position_vjp(tr.theta, b["pos"], b["q"], feat, vec, s["dU_dmu"])
+        return dip.position_vjp(tr.theta, b["pos"], b["q"], feat, vec, s["dU_dmu"],
+                                base=s["dU_dpos"])
 
     for _ in range(3):
         infer()
@@ -781,7 +803,14 @@ def learned_leg(n_train=256, n_val=32, epochs=12, workers=8):
             "dipole_rmse_nn": float(e_nn[:, 2].mean()),
             "dipole_rel_nn": float((e_nn[:, 2] / e_nn[:, 3]).mean()),
             "force_unit": "e^2/A^2", "dipole_unit": "e*A",
-            "train_s": round(train_s, 2), "generate_s": round(gen_s, 1)}
+            "train_s": round(train_s, 2), "train_ms_per_step": round(train_s * 1e3 / steps, 4),
+            "heads": heads,
+            "heads_note": "hf_charge: charge head + dipole head on Hellmann-Feynman forces; "
+                          "conservative: dipole head on -dU(r, mu(r))/dr (second order); "
+                          "conservative_charge: both heads on -dU(r, q(r), mu(r))/dr; "
+                          "force_rel is the held-out force RMSE over the teacher's RMS force, "
+                          "charge_rms_shift the RMS of q - formal charge",
+            "generate_s": round(gen_s, 1)}
 
 
 def _traffic_path(kind: str, workload: str) -> str:
