@@ -96,8 +96,10 @@ typedef struct {
                                  0 = no assignment deconvolution)                 */
     double  prefactor;        /* energy unit factor (1, or 14.3996454784 for eV)  */
     int32_t tile[3];          /* spread/gather tile target per axis in mesh points
-                                 (0 = default 8, 8, 16); rounded to the atom-bin
-                                 size and shrunk to fit LDS (set by autotuning)   */
+                                 (all 0 = default: per axis the tile near 8, 8, 16
+                                 that divides N with an atom-bin size dividing it;
+                                 a given target is rounded to the atom-bin size);
+                                 shrunk to fit LDS (set by autotuning)            */
 } pme_desc_t;
 
 /* Eq. mesh_target, N_a = ceil(2 |a_a| / spacing + 1), mapped by `strategy`

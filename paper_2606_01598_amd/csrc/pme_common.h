@@ -202,9 +202,9 @@ __device__ __forceinline__ void jacobian(const Cell& c, const int (&N)[3], float
 // Stencil anchor and offset of one atom along the three axes.  Returns false for a
 // non-finite position.  base[a] in [0, N_a), f[a] in [0, 1).
 template <int P>
-__device__ __forceinline__ bool atom_stencil(const float* __restrict__ pos, int i, const Cell& c,
-                                             const int (&N)[3], int (&base)[3], float (&f)[3]) {
-  const double r0 = pos[3 * i], r1 = pos[3 * i + 1], r2 = pos[3 * i + 2];
+__device__ __forceinline__ bool atom_stencil(float3 r, const Cell& c, const int (&N)[3],
+                                             int (&base)[3], float (&f)[3]) {
+  const double r0 = r.x, r1 = r.y, r2 = r.z;
   bool ok = isfinite(r0) && isfinite(r1) && isfinite(r2) && c.ok;
   constexpr double delta = (P & 1) ? 0.5 : 0.0;
 #pragma unroll

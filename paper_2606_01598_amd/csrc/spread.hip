@@ -109,30 +109,37 @@ __device__ __forceinline__ void quad_coeffs(const float (&J)[3][3], const float 
 template <int P, bool TANGENT, bool QUAD = false>
 __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
   __shared__ double red[8];
-  __shared__ unsigned s_cmax;
-  if (threadIdx.x == 0) s_cmax = 0u;
-  // clear the other counter set for the next binning
-  for (int e = blk * 256 + threadIdx.x; e < a.nbins; e += a.nblk * 256) a.count_other[e] = 0;
-  if (blk == 0 && threadIdx.x == 0) {
-    *a.ovf_other = 0;
-    *a.cmax_other = 0u;
-  }
-  __syncthreads();
+  __shared__ unsigned s_wmax[4];
   const int i = blk * 256 + threadIdx.x;
+  const bool live = i < a.n;
+  // every per-atom input is loaded first, so that their latencies overlap with
+  // each other and with the cell algebra
+  const float3 zero3 = make_float3(0.f, 0.f, 0.f);
+  const float3 r = live ? ld3(a.pos, i) : zero3;
+  const float q = (live && a.q) ? a.q[i] : 0.0f;
+  const float3 mu = live ? ld3(a.mu, i) : zero3;
+  float vq = 0.0f;
+  float3 vr = zero3, vm = zero3;
+  if (TANGENT && live) {
+    vq = a.v_q ? a.v_q[i] : 0.0f;
+    vr = ld3(a.v_pos, i);
+    vm = ld3(a.v_mu, i);
+  }
+  float th[6] = {0, 0, 0, 0, 0, 0};
+  if (QUAD && live && a.theta) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) th[k] = a.theta[6 * i + k];
+  }
   const Cell c = cell_from_box(a.box);
   double sq = 0.0, smu = 0.0, sqt = 0.0, stt = 0.0;
-  if (i < a.n) {
+  float amax = 0.0f;
+  if (live) {
     int base[3];
     float f[3];
-    const bool ok = atom_stencil<P>(a.pos, i, c, a.N, base, f);
-    const float q = a.q ? a.q[i] : 0.0f;
-    const float3 mu = ld3(a.mu, i);
+    const bool ok = atom_stencil<P>(r, c, a.N, base, f);
     sq = double(q) * q;
     smu = double(mu.x) * mu.x + double(mu.y) * mu.y + double(mu.z) * mu.z;
-    float th[6] = {0, 0, 0, 0, 0, 0};
     if (QUAD && a.theta) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) th[k] = a.theta[6 * i + k];
       const double tr = double(th[0]) + th[1] + th[2];
       sqt = double(q) * tr;
       stt = tr * tr + 2.0 * (double(th[0]) * th[0] + double(th[1]) * th[1] + double(th[2]) * th[2]) +
@@ -141,6 +148,9 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
     if (!ok) {
       atomicOr(a.status, 1);
     } else {
+      // the slot is reserved first: the coefficients are formed while it returns
+      const int bin = ((base[0] / a.B[0]) * a.nb[1] + base[1] / a.B[1]) * a.nb[2] + base[2] / a.B[2];
+      const int slot = atomicAdd(&a.count[bin], 1);
       float J[3][3];
       jacobian(c, a.N, J);
       const float3 d = jmul(J, mu);
@@ -149,16 +159,15 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
         co[0] = q; co[1] = d.x; co[2] = d.y; co[3] = d.z;
         if (QUAD) quad_coeffs(J, th, co + 4);
       } else {
-        tangent_coeffs(J, q, mu, a.v_q ? a.v_q[i] : 0.0f, ld3(a.v_pos, i), ld3(a.v_mu, i), co);
+        tangent_coeffs(J, q, mu, vq, vr, vm, co);
       }
       constexpr int nc = (TANGENT || QUAD) ? 10 : 4;
-      float amax = 0.0f;
 #pragma unroll
       for (int k = 0; k < nc; ++k) amax += fabsf(co[k]);
-      if (isfinite(amax)) atomicMax(&s_cmax, __float_as_uint(amax));
-      else atomicOr(a.status, 1);
-      const int bin = ((base[0] / a.B[0]) * a.nb[1] + base[1] / a.B[1]) * a.nb[2] + base[2] / a.B[2];
-      const int slot = atomicAdd(&a.count[bin], 1);
+      if (!isfinite(amax)) {
+        atomicOr(a.status, 1);
+        amax = 0.0f;
+      }
       // every atom takes one slot of its bin or of the overflow list (which holds
       // max_atoms records)
       const size_t ri = (slot < a.cap) ? size_t(bin) * a.cap + slot
@@ -169,9 +178,6 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
       if (TANGENT) {
         // the raw inputs: the spread rebuilds the coefficients, and the gather of the
         // Hessian-vector product needs no per-atom loads of its own
-        const float vq = a.v_q ? a.v_q[i] : 0.0f;
-        const float3 vr = ld3(a.v_pos, i);
-        const float3 vm = ld3(a.v_mu, i);
         d4[1] = make_float4(q, mu.x, mu.y, mu.z);
         d4[2] = make_float4(vq, vr.x, vr.y, vr.z);
         d4[3] = make_float4(vm.x, vm.y, vm.z, __int_as_float(i));
@@ -182,7 +188,7 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
       } else {
         // and the unwrapped fractional position r C^-1 (its image matters to the
         // cell gradient, which the forward gather forms when asked)
-        const double r0 = a.pos[3 * i], r1 = a.pos[3 * i + 1], r2 = a.pos[3 * i + 2];
+        const double r0 = r.x, r1 = r.y, r2 = r.z;
         float sf[3];
 #pragma unroll
         for (int b = 0; b < 3; ++b)
@@ -193,8 +199,23 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
       }
     }
   }
+  // clear the other counter set for the next binning
+  for (int e = blk * 256 + threadIdx.x; e < a.nbins; e += a.nblk * 256) a.count_other[e] = 0;
+  if (blk == 0 && threadIdx.x == 0) {
+    *a.ovf_other = 0;
+    *a.cmax_other = 0u;
+  }
+  // the largest coefficient sum: wavefront maxima, then the workgroup's (the sums
+  // are non-negative, so their float bits order as unsigned integers)
+  unsigned um = __float_as_uint(amax);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) um = max(um, unsigned(__shfl_xor(int(um), o, 64)));
+  if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = um;
   __syncthreads();
-  if (threadIdx.x == 0 && s_cmax) atomicMax(a.cmax, s_cmax);
+  if (threadIdx.x == 0) {
+    const unsigned m = max(max(s_wmax[0], s_wmax[1]), max(s_wmax[2], s_wmax[3]));
+    if (m) atomicMax(a.cmax, m);
+  }
   if (!TANGENT && a.spart) {
     const double s1 = block_sum(sq, red);
     const double s2 = block_sum(smu, red);

@@ -25,8 +25,8 @@ def _plan(mesh, p, alpha, n, **kw):
 
 
 def _check_forward(frame, mesh, p, alpha, gamma=1.0, with_q=True, with_mu=True, label="",
-                   force_floor=0.0):
-    plan = _plan(mesh, p, alpha, frame.n, influence_power=gamma)
+                   force_floor=0.0, tile=None):
+    plan = _plan(mesh, p, alpha, frame.n, influence_power=gamma, tile=tile)
     pos, q, mu, box = to_dev(frame, with_q, with_mu)
     out = plan.forward(pos, q, mu, box)
     plan.status()
@@ -75,8 +75,12 @@ def test_forward_config2_molten_charges_dipoles():
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7])
 def test_forward_all_orders_ragged_mesh(p):
     # non-cubic mesh with odd factors: tiles and FFT radices 2, 3, 4, 5 all ragged
+    # (the tile target is given, so it is rounded to the bins, 8 x 8 x 15, and not
+    # to the dividing tiles of the default, 10 x 10 x 25)
     f = synth.molten_box(300, 10 + p, L=20.0)
-    _check_forward(f, (18, 20, 25), p, 0.35, label=f"p{p}")
+    _check_forward(f, (18, 20, 25), p, 0.35, label=f"p{p}", tile=(8, 8, 16))
+    if p == 6:
+        _check_forward(f, (18, 20, 25), p, 0.35, label=f"p{p} default tiles")
 
 
 @pytest.mark.parametrize("mesh,p", [((4, 4, 4), 6), ((2, 3, 5), 4), ((6, 6, 6), 7), ((45, 27, 16), 5),
