@@ -105,13 +105,18 @@ KERNEL_SOURCES = {
 }
 
 
+# sources of the learned-head, teacher and probe calls: no PME step kernel is built from them
+NON_PME_SOURCES = ("cells.h", "dip.hip", "pol.hip", "probe.hip")
+
+
 def source_digest(kind: str = None) -> str:
-    """Digest of the HIP sources (all of them, or those of one kernel kind together
-    with the shared headers): a traffic summary is valid only for the kernel it was
-    measured on."""
+    """Digest of the HIP sources of the PME path (all of them, or those of one kernel
+    kind together with the shared headers): a summary is valid only for the kernels
+    it was measured on."""
     csrc = os.path.join(ROOT, "paper_2606_01598_amd", "csrc")
     if kind is None:
-        files = sorted(glob.glob(os.path.join(csrc, "*")))
+        files = sorted(f for f in glob.glob(os.path.join(csrc, "*"))
+                       if os.path.basename(f) not in NON_PME_SOURCES)
     else:
         files = [os.path.join(csrc, f) for f in
                  sorted(set(KERNEL_SOURCES[kind]) | {"kernels.h", "pme_common.h"})]
@@ -518,7 +523,7 @@ def influence_compare(out_path=None):
         "# F_PME from the GPU (forward), F_Ewald the FP64 explicit Ewald long-range force",
         "# (oracle, host); alpha = 0.45 / A",
         "# command: python -u bench.py --influence-compare 1",
-        f"# source digest of paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
+        f"# source digest of the PME sources in paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
         "",
         f"{'p':>3s} {'mesh':>5s} {'h (A)':>7s} {'deconvolution':>14s} {'optimal':>10s} {'ratio':>7s}",
     ]
@@ -986,7 +991,7 @@ def counter_summary(args) -> int:
         "# hbm = FETCH_SIZE, WRITE_SIZE scaled by a 256 MiB device copy in the same run "
         f"(x {f_scale:.3f}, x {w_scale:.3f});",
         "# vgpr, lds_alloc: per workitem registers and LDS bytes per workgroup of the dispatch.",
-        f"# source digest of paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
+        f"# source digest of the PME sources in paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
         "",
         f"{'kernel':28s} {'grid':>8s} {'wg':>5s} {'vgpr':>5s} {'lds_alloc':>9s} {'waves':>7s} "
         f"{'valu/w':>7s} {'salu/w':>7s} {'lds/w':>6s} {'ldsat/w':>7s} {'vmem/w':>7s} "
@@ -1069,7 +1074,7 @@ def kernel_stats_summary(args) -> int:
         "#  the default legs add their kernel variants: cell gradient k_fftx_fused<1>,",
         "#  k_gather<p, true>, k_cell_grad; optimal influence k_fftx_fused<2>; quadrupole",
         "#  k_bin<p, false, true>, k_spread<p, 3>, k_gather_quad<p>)",
-        f"# source digest of paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
+        f"# source digest of the PME sources in paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
     ]
     if bench_val:
         lines.append(f"# bench_us: bench.py's launch timer without the profiler (kernels_us); "
@@ -1122,7 +1127,7 @@ def sweep_summary(logs) -> int:
         "#   python bench.py --sweep-summary <log 8k> <log 32k> <log 128k> <log 1m>",
         f"# model bytes per step: {step_bytes(1, 0)} B per atom + {step_bytes(0, 1)} B per "
         f"mesh point; HBM peak {HBM_PEAK_GBS:.0f} GB/s",
-        f"# source digest of paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
+        f"# source digest of the PME sources in paper_2606_01598_amd/csrc (bench.source_digest): {source_digest()}",
         "",
         f"{'atoms':>8s} {'mesh':>5s} {'ms/step':>9s} {'Matom-steps/s':>14s} {'model GB/s':>11s} "
         f"{'% HBM':>6s}  dominant kernel (us/launch, % HBM of its algorithmic bytes)",
