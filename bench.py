@@ -541,7 +541,8 @@ def batched_leg(n_boxes=64, seed=6, reps=20):
     1 A (16..64 per side), p = 6, alpha = 0.30: one training step (forward,
     Hessian-vector product, force-loss double backward) as one replay of a HIP
     graph over the batch, against 64 sequential un-graphed single-box plans doing
-    the same three calls.  Tiles come from the autotuner."""
+    the same three calls.  Tiles and FFT lines per workgroup come from the
+    autotuner."""
     import tempfile
 
     import numpy as np
@@ -564,10 +565,14 @@ def batched_leg(n_boxes=64, seed=6, reps=20):
                       "v": [t(vr), t(vq), t(vm)], "vf": t(vf)})
     cache = os.path.join(tempfile.gettempdir(), "pme_bench_tiles.json")
     t0 = time.perf_counter()
-    tiles, timed = autotune.tune(boxes, 6, 0.30, cache_path=cache, steps=2,
-                                 candidates=((8, 8, 16), (8, 16, 16), (16, 16, 16)))
+    cfgs, timed = autotune.tune(boxes, 6, 0.30, cache_path=cache, steps=2,
+                                candidates=((8, 8, 16), (8, 16, 16), (16, 16, 16)),
+                                lines=(8, 16, 32))
     tune_s = time.perf_counter() - t0
-    plans = [Plan(b["mesh"], 6, 0.30, max_atoms=b["pos"].shape[0], tile=tiles[k])
+    tiles = [c.tile for c in cfgs]
+    lines = [c.fft_lines for c in cfgs]
+    plans = [Plan(b["mesh"], 6, 0.30, max_atoms=b["pos"].shape[0], tile=tiles[k],
+                  fft_lines=lines[k] or None)
              for k, b in enumerate(boxes)]
     outs = []
 
@@ -587,7 +592,7 @@ def batched_leg(n_boxes=64, seed=6, reps=20):
     box = torch.stack([b["box"] for b in boxes]).contiguous()
     vr = torch.cat([b["v"][0] for b in boxes]); vq = torch.cat([b["v"][1] for b in boxes])
     vm = torch.cat([b["v"][2] for b in boxes]); vf = cat("vf")
-    bt = Batch(meshes, [f.n for f in frames], 6, 0.30, tiles=tiles)
+    bt = Batch(meshes, [f.n for f in frames], 6, 0.30, tiles=tiles, fft_lines=lines)
     N, B = bt.total, bt.nbox
     emp = lambda *sh: torch.empty(*sh, dtype=torch.float32, device=dev)
     step = {"pos": pos, "q": q, "mu": mu, "box": box,
@@ -615,7 +620,9 @@ def batched_leg(n_boxes=64, seed=6, reps=20):
             "graph_ms": round(graph_ms, 4), "sequential_ms": round(seq_ms, 4),
             "speedup": round(seq_ms / graph_ms, 3),
             "graph_Matom_steps_per_s": round(N / graph_ms / 1e3, 3),
-            "max_rel_diff": worst, "autotune_keys_timed": timed, "autotune_s": round(tune_s, 2)}
+            "max_rel_diff": worst, "autotune_keys_timed": timed, "autotune_s": round(tune_s, 2),
+            "autotune_choices": sorted({f"{c.tile[0]}x{c.tile[1]}x{c.tile[2]}/lines {c.fft_lines}"
+                                        for c in cfgs})}
 
 
 def _thole_frame(seed: int):

@@ -100,6 +100,11 @@ typedef struct {
                                  that divides N with an atom-bin size dividing it;
                                  a given target is rounded to the atom-bin size);
                                  shrunk to fit LDS (set by autotuning)            */
+    int32_t fft_lines;        /* FFT lines per workgroup of the x pass and of the
+                                 pencil y pass, 0..1024 (0 = default: 16 for axes
+                                 up to 64 points, 24 up to 160, 4 above); clamped
+                                 to the LDS budget and to N_z/2 + 1 columns, then
+                                 evened out over the columns (set by autotuning)  */
 } pme_desc_t;
 
 /* Eq. mesh_target, N_a = ceil(2 |a_a| / spacing + 1), mapped by `strategy`

@@ -59,7 +59,8 @@ class PMEDesc(ctypes.Structure):
                 ("alpha", ctypes.c_double),
                 ("influence_power", ctypes.c_double),
                 ("prefactor", ctypes.c_double),
-                ("tile", ctypes.c_int32 * 3)]
+                ("tile", ctypes.c_int32 * 3),
+                ("fft_lines", ctypes.c_int32)]
 
 
 class BatchStep(ctypes.Structure):

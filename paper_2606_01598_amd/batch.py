@@ -18,7 +18,7 @@ from .pme import _ptr, _stream
 
 class Batch:
     def __init__(self, meshes, n_atoms, order: int, alpha: float, influence_power: float = 1.0,
-                 prefactor: float = 1.0, tiles=None, device=None):
+                 prefactor: float = 1.0, tiles=None, device=None, fft_lines=None):
         self._lib = _lib.load()
         self.device = torch.device("cuda", 0) if device is None else torch.device(device)
         nbox = len(meshes)
@@ -28,6 +28,7 @@ class Batch:
             for k in range(3):
                 d.mesh[k] = int(meshes[b][k])
                 d.tile[k] = 0 if tiles is None else int(tiles[b][k])
+            d.fft_lines = 0 if fft_lines is None else int(fft_lines[b])
             d.order = int(order)
             d.max_atoms = max(1, int(n_atoms[b]))
             d.flags = _lib.PME_F_KEEP_PHI

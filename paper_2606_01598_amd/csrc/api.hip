@@ -181,6 +181,7 @@ int check_desc(const pme_desc_t& desc) {
     return PME_EINVAL;
   for (int a = 0; a < 3; ++a)
     if (desc.tile[a] < 0 || desc.tile[a] > 1024) return PME_EINVAL;
+  if (desc.fft_lines < 0 || desc.fft_lines > 1024) return PME_EINVAL;
   return PME_OK;
 }
 
@@ -284,6 +285,7 @@ int plan_geometry(const pme_desc_t& desc, DevPlan& d, long& nbins_out) {
     d.rows_per_block = 2 * pairs;
     const int nmax = d.N[0] > d.N[1] ? d.N[0] : d.N[1];
     int kt = nmax <= 64 ? 16 : (nmax <= 160 ? 24 : 4);
+    if (desc.fft_lines > 0) kt = desc.fft_lines;
     // LDS of a line workgroup within 56 KB: twiddles, two line buffers and (x pass)
     // the kt N_x table of g and the deconvolution factors:
     // 8 N + kt (16 (N + 1) + 4 N) + 4 (N + kt) bytes

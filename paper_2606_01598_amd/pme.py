@@ -66,7 +66,7 @@ class Plan:
 
     def __init__(self, mesh, order: int, alpha: float, max_atoms: int, influence_power: float = 1.0,
                  prefactor: float = 1.0, keep_phi: bool = True, device=None, tile=None,
-                 concurrent: bool = False, optimal_influence: bool = False):
+                 concurrent: bool = False, optimal_influence: bool = False, fft_lines=None):
         self._lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         d = _lib.PMEDesc()
@@ -81,6 +81,7 @@ class Plan:
         d.prefactor = float(prefactor)
         for k in range(3):
             d.tile[k] = 0 if tile is None else int(tile[k])
+        d.fft_lines = 0 if fft_lines is None else int(fft_lines)
         self.desc = d
         self.mesh = tuple(int(m) for m in mesh)
         self.order = int(order)

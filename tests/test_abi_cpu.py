@@ -76,6 +76,7 @@ def _desc(**kw):
     d.alpha = kw.get("alpha", 0.3)
     d.influence_power = kw.get("gamma", 1.0)
     d.prefactor = kw.get("prefactor", 1.0)
+    d.fft_lines = kw.get("fft_lines", 0)
     return d
 
 
@@ -91,6 +92,8 @@ def _desc(**kw):
     (dict(prefactor=float("inf")), _lib.PME_EALPHA),
     (dict(max_atoms=0), _lib.PME_EINVAL),
     (dict(flags=8), _lib.PME_EINVAL),
+    (dict(fft_lines=-1), _lib.PME_EINVAL),
+    (dict(fft_lines=1025), _lib.PME_EINVAL),
 ])
 def test_plan_create_validation(kw, code):
     lib = _lib_or_skip()

@@ -43,12 +43,12 @@ def _close(a, b):
     return float(np.abs(a - b).max() / scale)
 
 
-def _batch_step(frames, meshes, seed, tiles=None):
+def _batch_step(frames, meshes, seed, tiles=None, lines=None):
     """forward, H v and force-loss H v of the batch and of one plan per box"""
     from paper_2606_01598_amd.batch import Batch
     from paper_2606_01598_amd.pme import Plan
     pos, q, mu, box, vr, vq, vm, vf = _pack(frames, seed)
-    bt = Batch(meshes, [f.n for f in frames], 6, 0.3, tiles=tiles)
+    bt = Batch(meshes, [f.n for f in frames], 6, 0.3, tiles=tiles, fft_lines=lines)
     fo = bt.forward(pos, q, mu, box)
     bo = bt.backward(pos, q, mu, box, vr, vq, vm)
     bf = bt.backward(pos, q, mu, box, vf, None, None)
@@ -57,7 +57,8 @@ def _batch_step(frames, meshes, seed, tiles=None):
     for b, (f, m) in enumerate(zip(frames, meshes)):
         s0, s1 = int(bt.offsets[b]), int(bt.offsets[b + 1])
         c = lambda t: t[s0:s1].contiguous()
-        pl = Plan(m, 6, 0.3, max_atoms=max(1, f.n), tile=None if tiles is None else tiles[b])
+        pl = Plan(m, 6, 0.3, max_atoms=max(1, f.n), tile=None if tiles is None else tiles[b],
+                  fft_lines=None if lines is None else lines[b])
         o = pl.forward(c(pos), c(q), c(mu), box[b].contiguous())
         ob = pl.backward(c(pos), c(q), c(mu), box[b].contiguous(), c(vr), c(vq), c(vm))
         of = pl.backward(c(pos), c(q), c(mu), box[b].contiguous(), c(vf), None, None)
@@ -86,6 +87,30 @@ def test_batch_equals_single_plans_64_boxes():
                       flush=True)
     print("batch vs single plans, 64 boxes: outputs differing", nbits, flush=True)
     assert nbits == 0
+
+
+def test_batch_with_tuned_geometry_equals_single_plans_and_oracle():
+    """Boxes with given tiles and FFT lines per workgroup (the autotuner's two
+    parameters, here fixed): the batch equals one plan per box bit for bit, and
+    every box matches the oracle."""
+    frames, meshes = synth.batch_boxes(6, 12, nmax=1500)
+    tiles = [(8, 8, 16), (8, 16, 16), (16, 16, 8), (8, 8, 8), (12, 12, 16), (16, 16, 16)]
+    lines = [4, 8, 32, 24, 0, 16]
+    bt, (pos, q, mu, box, vr, vq, vm, vf), (fo, bo, bf), single = _batch_step(
+        frames, meshes, seed=5, tiles=tiles, lines=lines)
+    for b, (f, m, (o, ob, of)) in enumerate(zip(frames, meshes, single)):
+        s0, s1 = int(bt.offsets[b]), int(bt.offsets[b + 1])
+        assert torch.equal(fo["energy"][b], o["energy"])
+        for k in ("dE_dpos", "dE_dq", "dE_dmu"):
+            assert torch.equal(fo[k][s0:s1], o[k]), (b, k)
+        for k in ("g_pos", "g_q", "g_mu"):
+            assert torch.equal(bo[k][s0:s1], ob[k]), (b, k)
+        ref = oracle_forward(f, m, 6, 0.3)
+        e = host(fo["energy"][b])
+        assert rel(e.sum(), ref.energy) <= E_REL_TOL, b
+        assert rms_rel(host(fo["dE_dpos"][s0:s1]), ref.dE_dpos) <= RMS_REL_TOL, b
+        h = oracle_hvp(f, m, 6, 0.3, (host(vr[s0:s1]), host(vq[s0:s1]), host(vm[s0:s1])))
+        assert rms_rel(host(bo["g_pos"][s0:s1]), h[0]) <= RMS_REL_TOL, b
 
 
 def test_batch_64_boxes_parity_with_oracle():
@@ -181,9 +206,11 @@ def test_autotuner_picks_and_caches(tmp_path):
                       "box": torch.tensor(f.box, dtype=torch.float64, device=dev()),
                       "v": [t(x) for x in v]})
     path = str(tmp_path / "tiles.json")
-    cands = ((8, 8, 16), (8, 16, 16))
-    tiles, timed = autotune.tune(boxes, 6, 0.3, cache_path=path, steps=2, candidates=cands)
-    assert timed >= 1 and all(t in cands for t in tiles)
-    tiles2, timed2 = autotune.tune(boxes, 6, 0.3, cache_path=path, steps=2, candidates=cands)
-    assert timed2 == 0 and tiles2 == tiles
-    print("autotuned tiles", tiles, flush=True)
+    cands, lines = ((8, 8, 16), (8, 16, 16)), (8, 24)
+    cfgs, timed = autotune.tune(boxes, 6, 0.3, cache_path=path, steps=2, candidates=cands,
+                                lines=lines)
+    assert timed >= 1 and all(c.tile in cands and c.fft_lines in (0,) + lines for c in cfgs)
+    cfgs2, timed2 = autotune.tune(boxes, 6, 0.3, cache_path=path, steps=2, candidates=cands,
+                                  lines=lines)
+    assert timed2 == 0 and cfgs2 == cfgs
+    print("autotuned", cfgs, flush=True)

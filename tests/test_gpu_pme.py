@@ -98,6 +98,36 @@ def _random_frame(n, box, seed):
     return synth.Frame(pos=frac @ box, q=q, mu=rng.normal(0, 0.1, (n, 3)), box=box)
 
 
+@pytest.mark.parametrize("mesh,p,a", [((32, 32, 32), 6, 0.3), ((12, 160, 150), 5, 0.45)])
+def test_fft_lines_per_workgroup(mesh, p, a):
+    """The FFT lines per workgroup of the x pass (and of the pencil y pass) set in
+    the descriptor: every per-atom output equals the default's bit for bit (each
+    line is transformed the same way), the energy only regroups its partial sums."""
+    box = np.diag([float(mesh[0]), float(mesh[1]) / 2.0, float(mesh[2]) / 2.0])
+    f = _random_frame(300, box, 23)
+    pos, q, mu, box_t = to_dev(f)
+    v = synth.random_cotangents(f.n, 8, scale_r=0.1)
+    vr, vq, vm = (torch.tensor(x, dtype=torch.float32, device=dev()) for x in v)
+    outs = []
+    for lines in (None, 1, 5, 40):
+        plan = _plan(mesh, p, a, f.n, fft_lines=lines)
+        o = plan.forward(pos, q, mu, box_t)
+        g = plan.backward(pos, q, mu, box_t, vr, vq, vm)
+        plan.status()
+        outs.append((o, g))
+    ref = oracle_forward(f, mesh, p, a)
+    e0 = host(outs[0][0]["energy"])
+    # E_recip and the forces: this random frame's total energy nearly cancels
+    assert rel(e0[0], ref.e_recip) <= E_REL_TOL
+    assert rms_rel(host(outs[0][0]["dE_dpos"]), ref.dE_dpos) <= RMS_REL_TOL
+    for o, g in outs[1:]:
+        for k in ("dE_dpos", "dE_dq", "dE_dmu"):
+            assert torch.equal(o[k], outs[0][0][k]), k
+        for k in ("g_pos", "g_q", "g_mu"):
+            assert torch.equal(g[k], outs[0][1][k]), k
+        assert rel(host(o["energy"]).sum(), e0.sum()) <= 1e-12
+
+
 def test_pencil_mode_mesh_forward_and_hvp():
     # a y-z half-spectrum plane too large for LDS: five pencil passes instead of slabs
     box = np.diag([12.0, 80.0, 75.0])
