@@ -115,6 +115,25 @@ def test_null_arguments():
     assert lib.pme_plan_workspace_bytes(None) == 0
 
 
+def test_teacher_and_head_calls_reject_a_missing_plan():
+    """The polarizable-model and learned-head calls check their arguments before
+    touching the device: a NULL plan is PME_EINVAL."""
+    lib = _lib_or_skip()
+    E = _lib.PME_EINVAL
+    n = 4
+    assert lib.pol_real(None, None, n, *([None] * 8)) == E
+    assert lib.pol_model(None, None, None, n, *([None] * 9)) == E
+    assert lib.pol_model_hvp(None, None, None, n, *([None] * 10)) == E
+    assert lib.dip_features(None, None, n, *([None] * 4)) == E
+    assert lib.dip_features_jvp(None, None, n, *([None] * 6)) == E
+    assert lib.dip_charges(None, None, n, *([None] * 6)) == E
+    assert lib.dip_forward_jvp(None, None, n, *([None] * 7)) == E
+    assert lib.dip_position_vjp(None, None, n, *([None] * 10)) == E
+    assert lib.dip_backward_jvp(None, None, n, *([None] * 14)) == E
+    assert lib.dip_loss(None, None, n, *([None] * 8), 1.0, 1.0, 0.0, *([None] * 4)) == E
+    assert lib.dip_adam(None, 4, 0, 1e-3, 0.9, 0.999, 1e-8, None, None, None, None) == E
+
+
 def test_learning_rate_schedule():
     """Adam's learning rate in the dipole-head trainer: a linear warmup over the
     first steps, then exponential decay (the optimizer setting of Sec. 2.4)."""
