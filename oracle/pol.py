@@ -63,19 +63,29 @@ def thole_b(r, s, alpha, A=THOLE_A):
 
 
 def _pairs(pos, box, rc):
-    """All (i, j, R = r_i - r_j + n C) with 0 < |R| < rc over periodic images."""
+    """All (i, j, R = r_i - r_j + n C) with 0 < |R| < rc over periodic images, in
+    the order (i, j, image).  The centre atoms are taken in chunks, so memory stays
+    bounded for large n; the chunks keep that order."""
     C = np.asarray(box, dtype=np.float64)
+    pos = np.asarray(pos, dtype=np.float64)
     n = pos.shape[0]
     recip_len = np.linalg.norm(np.linalg.inv(C), axis=0)
     nmax = [int(math.ceil(rc * recip_len[a])) for a in range(3)]
     shifts = np.array([[i, j, k] for i in range(-nmax[0], nmax[0] + 1)
                        for j in range(-nmax[1], nmax[1] + 1)
                        for k in range(-nmax[2], nmax[2] + 1)], dtype=np.float64) @ C
-    R = (pos[:, None, None, :] - pos[None, :, None, :]) + shifts[None, None, :, :]
-    r = np.sqrt(np.einsum('ijsc,ijsc->ijs', R, R))
-    mask = (r < rc) & (r > 1e-12)
-    ia, ja, sa = np.nonzero(mask)
-    return ia, ja, R[ia, ja, sa], r[ia, ja, sa]
+    chunk = max(1, 4_000_000 // max(1, n * len(shifts)))
+    out = [], [], [], []
+    for s0 in range(0, n, chunk):
+        R = (pos[s0:s0 + chunk, None, None, :] - pos[None, :, None, :]) + shifts[None, None, :, :]
+        r = np.sqrt(np.einsum('ijsc,ijsc->ijs', R, R))
+        ia, ja, sa = np.nonzero((r < rc) & (r > 1e-12))
+        for lst, v in zip(out, (ia + s0, ja, R[ia, ja, sa], r[ia, ja, sa])):
+            lst.append(v)
+    if not out[0]:
+        return (np.zeros(0, dtype=np.int64), np.zeros(0, dtype=np.int64), np.zeros((0, 3)),
+                np.zeros(0))
+    return tuple(np.concatenate(v) for v in out)
 
 
 def real_space(pos, q, mu, box, alpha, rc, pol, A=THOLE_A):
