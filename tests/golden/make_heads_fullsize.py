@@ -13,8 +13,11 @@ to float32 as the GPU sees them.  The loss compares the student with a fixed
 target (energy 0, forces 0, dipoles 0; lE = lF = 1, lmu = 0.5), which is enough to
 exercise every term of the gradient.  The file keeps the loss, both parameter
 gradients (the dipole head's at a seeded sample of entries), and the charges,
-dipoles and conservative forces of a seeded sample of atoms.  Only oracle/ and
-synth/ are called (about 3 minutes on 8 cores).
+dipoles and conservative forces of a seeded sample of atoms.  A second case is
+the dipole head alone on Hellmann-Feynman forces (oracle/dip.py loss_and_grad,
+the training step of the learned dipole head): its loss and the same sample of
+its parameter gradient, lines prefixed hf_.  Only oracle/ and synth/ are called
+(about 6 minutes on 8 cores).
 """
 from __future__ import annotations
 
@@ -69,6 +72,10 @@ def main():
     L, g, gq = oh.loss_and_grad(theta, thq, pos, z, pol, f.box, MESH, P, ALPHA, RC, teacher(),
                                 conservative=True, rc_feat=RC_FEAT, **LOSS)
     s = oh.student(theta, thq, pos, z, pol, f.box, MESH, P, ALPHA, RC, RC_FEAT)
+    x, V = odip.features(pos, z, f.box, RC_FEAT)
+    tch = teacher()
+    L_hf, g_hf, _ = odip.loss_and_grad(theta, x, V, pos, z, pol, f.box, MESH, P, ALPHA, RC, tch,
+                                       LOSS["lE"], LOSS["lF"], LOSS["lmu"])
     atoms, params = samples()
     with open(PATH, "w") as fh:
         fh.write(f"# FP64 oracle (oracle/heads.py loss_and_grad, student) on synth.molten_box({N}, "
@@ -82,11 +89,27 @@ def main():
             fh.write(f"g_theta {int(k)} {float(v)!r}\n")
         for k, v in enumerate(gq):
             fh.write(f"g_thq {k} {float(v)!r}\n")
+        fh.write(f"hf_loss {float(L_hf)!r}\n")
+        for k, v in zip(params, g_hf[params]):
+            fh.write(f"hf_g_theta {int(k)} {float(v)!r}\n")
         for i in atoms:
             F, m = s["F"][i], s["mu"][i]
             fh.write(f"atom {int(i)} {float(s['q'][i])!r} {float(m[0])!r} {float(m[1])!r} "
                      f"{float(m[2])!r} {float(F[0])!r} {float(F[1])!r} {float(F[2])!r}\n")
     print("wrote", PATH, f"{time.time() - t0:.0f} s")
+
+
+def read_hf():
+    """(loss, {index: dL/dtheta}) of the Hellmann-Feynman dipole-head case"""
+    L, gt = None, {}
+    with open(PATH) as fh:
+        for ln in fh:
+            w = ln.split()
+            if w and w[0] == "hf_loss":
+                L = float(w[1])
+            elif w and w[0] == "hf_g_theta":
+                gt[int(w[1])] = float(w[2])
+    return L, gt
 
 
 def read():

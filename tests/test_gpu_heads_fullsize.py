@@ -7,6 +7,9 @@ seeded inputs: the loss, the charge head's whole parameter gradient and a seeded
 sample of the dipole head's, and the charges, dipoles and conservative forces of
 a seeded sample of atoms.
 
+A second test does the same for the dipole head alone on Hellmann-Feynman forces
+(the learned dipole head's training step) against oracle/dip.py.
+
 Bar: 1e-4 relative for the loss and relative RMS for each compared array.
 """
 import os
@@ -58,3 +61,33 @@ def test_conservative_training_step_4096_ions():
           f"mu {e_mu:.2e} F {e_F:.2e}", flush=True)
     assert e_L <= 1e-4
     assert max(e_g, e_q, e_charge, e_mu, e_F) <= RMS_REL_TOL
+
+
+def test_hellmann_feynman_training_step_4096_ions():
+    """The dipole head alone on Hellmann-Feynman forces (the training step of the
+    learned dipole head: dip_backward with the PME and real-space mixed Hessian
+    products) against oracle/dip.py at the same size."""
+    from paper_2606_01598_amd.dip import DipPlan, Trainer
+    from paper_2606_01598_amd.pme import Plan
+    from paper_2606_01598_amd.pol import PolPlan
+    f, pos, z, pol, theta, _ = mh.inputs()
+    print(f"case: Hellmann-Feynman training step, {mh.N} ions, dipole head", flush=True)
+    d = dev()
+    t = lambda a: torch.tensor(np.asarray(a), dtype=torch.float32, device=d)
+    box = torch.tensor(f.box, dtype=torch.float64, device=d)
+    pme = Plan(mh.MESH, mh.P, mh.ALPHA, max_atoms=mh.N, keep_phi=True)
+    polp = PolPlan(f.box, mh.ALPHA, mh.RC, max_atoms=mh.N)
+    dip = DipPlan(f.box, mh.N, cutoff=mh.RC_FEAT)
+    tp, tz = t(pos), t(z)
+    feat, vec = dip.features(tp, tz)
+    tr = Trainer(dip, polp, pme, box, theta, lr=0.0, **mh.LOSS)
+    zero = torch.zeros(mh.N, 3, dtype=torch.float32, device=d)
+    b = {"pos": tp, "q": tz, "pol": t(pol), "feat": feat, "vec": vec,
+         "U": torch.zeros(1, dtype=torch.float64, device=d), "dUdr": zero, "mu": zero}
+    loss = float(host(tr.step(b))[0])
+    L, gt = mh.read_hf()
+    idx = np.array(sorted(gt))
+    e_L = rel(loss, L)
+    e_g = rms_rel(host(tr.g)[idx], np.array([gt[k] for k in idx]))
+    print("4096 ions HF", f"loss {e_L:.2e} g_theta {e_g:.2e}", flush=True)
+    assert e_L <= 1e-4 and e_g <= RMS_REL_TOL
