@@ -33,7 +33,9 @@ Induced dipoles minimise U. U is quadratic in mu, so
 
     (diag(1/a) + H_real + H_pme) mu = -grad_mu (E_lr + E_real) at mu = 0,
 
-where H_pme and H_real are the mu-mu Hessians of E_lr and E_real.
+where H_pme and H_real are the mu-mu Hessians of E_lr and E_real. Small systems
+solve it densely (induced_dipoles); large ones by conjugate gradients with the PME
+block applied matrix-free (induced_dipoles_cg), pinned to the dense solve.
 """
 from __future__ import annotations
 
@@ -234,6 +236,66 @@ def induced_dipoles(pos, q, box, mesh, p, alpha, rc, pol, A=THOLE_A, gamma=1.0):
             + real_dipole_matrix(pos, box, alpha, rc, pol, A)
             + pme_dipole_matrix(pos, box, mesh, p, alpha, gamma))
     return np.linalg.solve(Amat, b).reshape(n, 3)
+
+
+def real_dipole_sparse(pos, box, alpha, rc, pol, A=THOLE_A):
+    """The matrix of real_dipole_matrix in sparse (CSR) form, for systems too large
+    for the dense one: the same 3x3 pair blocks, duplicates summed."""
+    import scipy.sparse as sp
+    n = pos.shape[0]
+    ia, ja, R, r = _pairs(np.asarray(pos, dtype=np.float64), box, rc)
+    s = (np.asarray(pol)[ia] * np.asarray(pol)[ja]) ** (1.0 / 6.0)
+    _, B1, B2, _ = thole_b(r, s, alpha, A)
+    blk = B1[:, None, None] * np.eye(3)[None] - B2[:, None, None] * R[:, :, None] * R[:, None, :]
+    k = np.arange(3)
+    rows = (3 * ia)[:, None, None] + k[None, :, None] + 0 * k[None, None, :]
+    cols = (3 * ja)[:, None, None] + 0 * k[None, :, None] + k[None, None, :]
+    return sp.coo_matrix((blk.ravel(), (rows.ravel(), cols.ravel())),
+                         shape=(3 * n, 3 * n)).tocsr()
+
+
+def induced_dipoles_cg(pos, q, box, mesh, p, alpha, rc, pol, A=THOLE_A, gamma=1.0,
+                       tol=1e-12, max_iter=5000):
+    """Self-consistent dipoles of the linear system of induced_dipoles, solved by
+    plain conjugate gradients (Hestenes-Stiefel, no preconditioner) for systems too
+    large for the dense matrix.  The PME block is applied matrix-free as the mu row
+    of the E_lr Hessian-vector product with a dipole tangent (it is independent of
+    q and mu, so it is taken at zero), the real-space block as the sparse matrix of
+    real_dipole_sparse.  Stops once |b - A mu| <= tol |b|.  Returns (mu, iterations)."""
+    pos = np.asarray(pos, dtype=np.float64)
+    n = pos.shape[0]
+    q = np.asarray(q, dtype=np.float64)
+    pol = np.asarray(pol, dtype=np.float64)
+    zq = np.zeros(n)
+    zmu = np.zeros((n, 3))
+    g_pme = opme.forward(pos, q, zmu, box, mesh, p, alpha, gamma).dE_dmu
+    _, _, g_real = real_space(pos, q, zmu, box, alpha, rc, pol, A)
+    b = -(g_pme + g_real).reshape(-1)
+    T = real_dipole_sparse(pos, box, alpha, rc, pol, A)
+    d = np.repeat(1.0 / pol, 3)
+
+    def apply(v):
+        _, _, h = opme.hvp(pos, zq, zmu, box, mesh, p, alpha, None, None, v.reshape(n, 3), gamma)
+        return d * v + T @ v + h.reshape(-1)
+
+    x = np.zeros(3 * n)
+    r = b.copy()
+    s = r.copy()
+    rr = float(r @ r)
+    stop = tol * math.sqrt(float(b @ b))
+    it = 0
+    while math.sqrt(rr) > stop:
+        if it == max_iter:
+            raise RuntimeError(f"CG did not converge in {max_iter} iterations")
+        As = apply(s)
+        a = rr / float(s @ As)
+        x += a * s
+        r -= a * As
+        rr_new = float(r @ r)
+        s = r + (rr_new / rr) * s
+        rr = rr_new
+        it += 1
+    return x.reshape(n, 3), it
 
 
 def model(pos, q, mu, box, mesh, p, alpha, rc, pol, A=THOLE_A, gamma=1.0):

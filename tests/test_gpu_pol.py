@@ -105,6 +105,37 @@ def test_scf_4096_ions_self_consistent():
     assert ratio < 1e-4
 
 
+def test_teacher_4096_ions_matches_oracle():
+    """The teacher (self-consistent dipoles, energy and forces) on the 4096-ion
+    teacher box against the FP64 oracle's CG solve written by
+    tests/golden/make_scf_fullsize.py: the energy, the RMS dipole, and the dipoles
+    and forces of a seeded sample of atoms."""
+    import os
+    import sys
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    import make_scf_fullsize as ms
+    from paper_2606_01598_amd.pme import Plan
+    from paper_2606_01598_amd.pol import PolPlan, teacher
+    f, pos, q, pol = ms.inputs()
+    print(f"case: teacher, {ms.N} ions, mesh {ms.MESH}", flush=True)
+    pme = Plan(ms.MESH, ms.P, ms.ALPHA, max_atoms=ms.N, keep_phi=True)
+    plan = PolPlan(f.box, ms.ALPHA, ms.RC, max_atoms=ms.N)
+    box = torch.tensor(f.box, dtype=torch.float64, device=dev())
+    out = teacher(plan, pme, _t(pos), _t(q), _t(pol), box, tol=1e-7, max_iter=300)
+    E, m_rms, atoms, mu_ref, F_ref = ms.read()
+    mu = host(out["mu"])
+    ii = torch.tensor(atoms, device=dev())
+    errs = {"U": rel(float(host(out["energy"])[0]), E),
+            "mu_rms": rel(float(np.sqrt(np.mean(np.sum(mu * mu, axis=1)))), m_rms),
+            "mu": rms_rel(mu[atoms], mu_ref),
+            "F": rms_rel(-host(out["dU_dpos"][ii]), F_ref)}
+    print("teacher4096", out["iters"], f"{out['resid']:.2e}", {k: f"{v:.2e}" for k, v in errs.items()},
+          flush=True)
+    assert out["resid"] < 1e-7
+    assert errs["U"] <= E_REL_TOL and errs["mu_rms"] <= E_REL_TOL
+    assert errs["mu"] <= RMS_REL_TOL and errs["F"] <= RMS_REL_TOL
+
+
 def test_model_energy_and_gradients():
     """pol_model against the oracle's U(mu), dU/dr and dU/dmu at random dipoles."""
     from paper_2606_01598_amd.pme import Plan

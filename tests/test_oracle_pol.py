@@ -107,3 +107,24 @@ def test_scf_stationary_minimum_and_linear():
         assert opol.model(pos, q, mu + d, box, mesh, p, a, rc, pol)[0] > u0
     mu2 = opol.induced_dipoles(pos, 2 * q, box, mesh, p, a, rc, pol)
     np.testing.assert_allclose(mu2, 2 * mu, rtol=1e-9, atol=1e-12)
+
+
+def test_sparse_real_dipole_matrix_equals_dense():
+    pos, q, mu, box, pol = _system(n=9, seed=11)
+    T = opol.real_dipole_matrix(pos, box, 0.35, 5.5, pol)
+    S = opol.real_dipole_sparse(pos, box, 0.35, 5.5, pol).toarray()
+    np.testing.assert_allclose(S, T, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.slow
+def test_cg_solve_equals_dense_solve():
+    """The matrix-free CG solve (used where the dense matrix does not fit) reaches
+    the dense solve's dipoles, and they zero dU/dmu of the forward calls."""
+    pos, q, _, box, pol = _system(n=10, seed=12)
+    mesh, p, a, rc = (12, 12, 12), 5, 0.35, 5.5
+    ref = opol.induced_dipoles(pos, q, box, mesh, p, a, rc, pol)
+    mu, it = opol.induced_dipoles_cg(pos, q, box, mesh, p, a, rc, pol, tol=1e-13)
+    assert 0 < it <= 3 * len(q) + 5
+    np.testing.assert_allclose(mu, ref, rtol=1e-9, atol=1e-11)
+    _, _, gmu = opol.model(pos, q, mu, box, mesh, p, a, rc, pol)
+    assert np.abs(gmu).max() < 1e-9
