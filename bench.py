@@ -177,6 +177,14 @@ def _args(argv=None):
                     help="1 adds the batched-graph leg (64 boxes, one HIP graph per step)")
     ap.add_argument("--learned", type=int, default=1,
                     help="1 adds the learned-dipole leg (SCF teacher vs trained network)")
+    ap.add_argument("--halo-probe", type=int, default=0,
+                    help="1: time the global-memory combination of the overlapping per-tile "
+                         "regions of a scatter-once spread (pme_halo_probe: 64-bit atomics, or "
+                         "contiguous region blocks and a fold) on the 100^3 and 320^3 meshes, "
+                         "print one JSON line per tile shape, then exit")
+    ap.add_argument("--halo-summary", nargs=2, default=None, metavar=("TRACE_CSV", "LOG"),
+                    help="summarise a rocprofv3 kernel trace of --halo-probe 1 and the JSON "
+                         "lines of an unprofiled run (LOG), then exit")
     ap.add_argument("--crossover", type=int, default=0,
                     help="1: time explicit Ewald and PME (oracles on the host, PME on the GPU) "
                          "for 128..8192 ions and print one JSON line per size, then exit")
@@ -193,10 +201,14 @@ def main(argv=None):
         return counter_summary(args)
     if args.sweep_summary:
         return sweep_summary(args.sweep_summary)
+    if args.halo_summary:
+        return halo_summary(*args.halo_summary)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         return 2
+    if args.halo_probe:
+        return halo_probe()
     if args.crossover:
         return crossover()
     if args.influence_compare:
@@ -1267,6 +1279,110 @@ def copy_bandwidth(dev):
     ms = sorted(device_ms(lambda: dst.copy_(src), 10))[5]
     del src, dst
     return {"bytes": 2 * COPY_BYTES, "ms": round(ms, 4), "GBps": round(2 * COPY_BYTES / ms / 1e6, 1)}
+
+
+def halo_probe() -> int:
+    """Cost of combining the overlapping (T + p - 1)^3 regions of a scatter-once
+    spread in global memory (pme_halo_probe), p = 6: 64-bit atomic adds into the
+    mesh, or contiguous region blocks written and then folded per mesh point.  Both
+    combinations are exact; the line says whether the fold equals the atomic sum."""
+    import ctypes
+
+    import torch
+
+    from paper_2606_01598_amd import _lib
+    lib = _lib.load()
+    dev = torch.device("cuda", 0)
+    p = 6
+    cases = (("32k", 100, (10, 10, 20)), ("32k", 100, (10, 10, 10)),
+             ("1m", 320, (8, 8, 16)), ("1m", 320, (16, 16, 16)))
+    stream = lambda: ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for workload, n, tile in cases:
+        N = (ctypes.c_int32 * 3)(n, n, n)
+        T = (ctypes.c_int32 * 3)(*tile)
+        tiles = (n // tile[0]) * (n // tile[1]) * (n // tile[2])
+        vol = (tile[0] + p - 1) * (tile[1] + p - 1) * (tile[2] + p - 1)
+        regions = torch.empty(tiles * vol, dtype=torch.int64, device=dev)
+        mesh64 = torch.zeros(n ** 3, dtype=torch.int64, device=dev)
+        mesh32 = torch.empty(n ** 3, dtype=torch.float32, device=dev)
+
+        def launch(kind, mesh):
+            _lib.check(lib.pme_halo_probe(stream(), kind, N, T, p, ctypes.c_void_p(regions.data_ptr()),
+                                          ctypes.c_void_p(mesh.data_ptr())))
+
+        def timed(kind, mesh, clear):
+            out = []
+            for _ in range(12):
+                if clear:
+                    mesh.zero_()
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                launch(kind, mesh)
+                b.record()
+                b.synchronize()
+                out.append(a.elapsed_time(b) * 1e3)
+            return sorted(out[2:])[5]
+
+        atomic_us = timed(_lib.PME_PROBE_HALO_ATOMIC, mesh64, True)
+        write_us = timed(_lib.PME_PROBE_HALO_WRITE, mesh64, False)
+        fold_us = timed(_lib.PME_PROBE_HALO_FOLD, mesh32, False)
+        mesh64.zero_()
+        launch(_lib.PME_PROBE_HALO_ATOMIC, mesh64)
+        launch(_lib.PME_PROBE_HALO_WRITE, mesh64)
+        launch(_lib.PME_PROBE_HALO_FOLD, mesh32)
+        torch.cuda.synchronize()
+        exact = (int(mesh64.sum()) == tiles * vol) and bool(torch.equal(mesh32, mesh64.float()))
+        print(json.dumps({"halo_probe": {
+            "workload": workload, "mesh": [n, n, n], "tile": list(tile), "p": p, "tiles": tiles,
+            "region_points": tiles * vol, "region_over_mesh": round(tiles * vol / n ** 3, 3),
+            "atomic_us": round(atomic_us, 1),
+            "atomic_G_per_s": round(tiles * vol / atomic_us / 1e3, 1),
+            "write_us": round(write_us, 1), "fold_us": round(fold_us, 1),
+            "write_plus_fold_us": round(write_us + fold_us, 1), "exact": exact}}), flush=True)
+        del regions, mesh64, mesh32
+        torch.cuda.empty_cache()
+    return 0
+
+
+def halo_summary(trace_csv: str, log: str) -> int:
+    """Per-configuration median kernel durations of the halo probe from a rocprofv3
+    kernel trace (a configuration is told apart by its grid), beside the event
+    timings of an unprofiled run."""
+    import csv
+    cases = []
+    with open(log) as fh:
+        for ln in fh:
+            if ln.startswith("{") and "halo_probe" in ln:
+                cases.append(json.loads(ln)["halo_probe"])
+    # the probe launches, per configuration in order, 12 timed atomic, write and fold
+    # launches each and then one of each for the exactness check: 39 launches
+    seq = []
+    with open(trace_csv) as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"]
+            if "k_halo_" not in name:
+                continue
+            kind = "atomic" if "<true>" in name else ("write" if "<false>" in name else "fold")
+            seq.append((int(r["Start_Timestamp"]), kind,
+                        (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3))
+    seq.sort()
+    print("# rocprofv3 median kernel durations (us) of pme_halo_probe, p = 6; event timings of an")
+    print("# unprofiled run in brackets (one launch between two events, launch overhead included)")
+    print(f"{'mesh':>6} {'tile':>10} {'tiles':>6} {'region/mesh':>11} {'atomic':>16} {'G atomics/s':>11} "
+          f"{'write':>14} {'fold':>14} {'write+fold':>10} exact")
+    for ci, c in enumerate(cases):
+        n = c["mesh"][0]
+        block = seq[39 * ci: 39 * (ci + 1)]
+        med = {}
+        for kind in ("atomic", "write", "fold"):
+            v = sorted(d for _, k, d in block if k == kind)
+            med[kind] = v[len(v) // 2] if v else float("nan")
+        tile = "x".join(str(t) for t in c["tile"])
+        print(f"{n:>5}^3 {tile:>10} {c['tiles']:>6} {c['region_over_mesh']:>11.3f} "
+              f"{med['atomic']:>7.1f} [{c['atomic_us']:>6.1f}] {c['region_points'] / med['atomic'] / 1e3:>11.1f} "
+              f"{med['write']:>6.1f} [{c['write_us']:>5.1f}] {med['fold']:>6.1f} [{c['fold_us']:>5.1f}] "
+              f"{med['write'] + med['fold']:>10.1f} {c['exact']}")
+    return 0
 
 
 def lds_peak(dev):

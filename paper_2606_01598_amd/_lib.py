@@ -42,7 +42,7 @@ EXPORTS = ("pme_mesh_dims", "pme_plan", "pme_plan_destroy", "pme_plan_workspace_
            "dip_forward", "dip_backward", "dip_position_vjp", "dip_features_jvp", "dip_charges",
            "dip_forward_jvp", "dip_backward_jvp", "dip_loss", "dip_adam", "pme_batch_plan", "pme_batch_destroy",
            "pme_batch_forward", "pme_batch_backward", "pme_batch_graph_capture", "pme_batch_graph_launch",
-           "pme_batch_status", "pme_lds_probe")
+           "pme_batch_status", "pme_lds_probe", "pme_halo_probe")
 
 DIP_NFEAT, DIP_NCH, DIP_HIDDEN, DIP_NPARAM, DIP_NQPARAM = 34, 16, 64, 7440, 2304
 
@@ -84,6 +84,9 @@ POL_F_FIXED_ITERS = 2
 
 PME_PROBE_LDS_READ = 0
 PME_PROBE_LDS_ATOMIC = 1
+PME_PROBE_HALO_ATOMIC = 2
+PME_PROBE_HALO_WRITE = 3
+PME_PROBE_HALO_FOLD = 4
 
 
 class DipDesc(ctypes.Structure):
@@ -188,6 +191,8 @@ def load():
     lib.pme_batch_status.restype = ctypes.c_int
     lib.pme_lds_probe.argtypes = [vp, i32, i32, i32, vp]
     lib.pme_lds_probe.restype = ctypes.c_int
+    lib.pme_halo_probe.argtypes = [vp, i32, vp, vp, i32, vp, vp]
+    lib.pme_halo_probe.restype = ctypes.c_int
     lib.dip_plan_create.argtypes = [ctypes.POINTER(DipDesc), ctypes.POINTER(vp)]
     lib.dip_plan_create.restype = ctypes.c_int
     lib.dip_plan_destroy.argtypes = [vp]

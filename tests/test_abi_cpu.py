@@ -147,3 +147,23 @@ def test_learning_rate_schedule():
     assert abs(rate(110) - 5e-4) < 1e-15 and abs(rate(210) - 2.5e-4) < 1e-15
     tr0 = SimpleNamespace(lr=2e-3, warmup=0, decay=1.0, decay_steps=1)
     assert Trainer.rate(tr0, 1) == 2e-3 and Trainer.rate(tr0, 1000) == 2e-3
+
+
+def test_halo_probe_rejects_bad_arguments():
+    """pme_halo_probe validates on the host before any launch (no GPU needed)."""
+    import ctypes
+    lib = _lib_or_skip()
+    N = (ctypes.c_int32 * 3)(100, 100, 100)
+    T = (ctypes.c_int32 * 3)(10, 10, 20)
+    buf = ctypes.c_void_p(16)   # never dereferenced on these paths
+    cases = [
+        (9, N, T, 6, buf, buf),                                   # unknown kind
+        (_lib.PME_PROBE_HALO_WRITE, N, T, 6, None, buf),          # no region buffer
+        (_lib.PME_PROBE_HALO_ATOMIC, N, T, 6, buf, None),         # no mesh
+        (_lib.PME_PROBE_HALO_ATOMIC, N, (ctypes.c_int32 * 3)(10, 10, 30), 6, buf, buf),  # T does not divide N
+        (_lib.PME_PROBE_HALO_ATOMIC, (ctypes.c_int32 * 3)(12, 12, 12), (ctypes.c_int32 * 3)(12, 12, 12),
+         6, buf, buf),                                            # N < T + p - 1
+        (_lib.PME_PROBE_HALO_FOLD, N, T, 0, buf, buf),            # order
+    ]
+    for kind, n, t, p, reg, mesh in cases:
+        assert lib.pme_halo_probe(None, kind, n, t, p, reg, mesh) == _lib.PME_EINVAL
