@@ -78,6 +78,13 @@ extern "C" {
  * U(f) = prod_a sinc(f_a / N_a)^p, m in {-1, 0, 1}^3.  Not with pme_forward_cell
  * or batches (PME_EINVAL). */
 #define PME_F_OPT_INFLUENCE 4
+/* Spread the density by mesh tiles and transform it in a separate pass.  Without
+ * this flag, a plan whose y-z plane, padded by p - 1 rows and columns, fits in LDS
+ * beside a transform buffer (meshes up to about 110 points in y and z, and N >= p
+ * plus the bin size on every axis) spreads by x-planes and transforms each plane
+ * in the same workgroup (Sec. 2.3.2 and Eq. fft).  Both give the same density and
+ * spectrum bit for bit; the flag exists for comparison and measurement. */
+#define PME_F_SEPARATE_SPREAD 8
 
 /* ---- mesh strategies for pme_mesh_dims (Sec. 2.3.1) ------------------- */
 #define PME_MESH_POW2    0   /* N = 2^ceil(log2 N_target)                       */
@@ -312,7 +319,9 @@ const char* pme_last_hip_error(void);
 
 /* Device pointer of the potential mesh phi (float[N_x*N_y*N_z], z fastest)
  * left by the last pme_forward, and of the density rho it was built from.
- * For inspection and tests; valid until the plan is destroyed. */
+ * For inspection and tests; valid until the plan is destroyed.  A plan that
+ * spreads by x-planes fused with the transform (the default where it fits, see
+ * PME_F_SEPARATE_SPREAD) never stores the density: pme_plan_rho returns NULL. */
 const float* pme_plan_phi(pme_plan_t plan);
 const float* pme_plan_rho(pme_plan_t plan);
 

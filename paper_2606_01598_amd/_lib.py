@@ -27,6 +27,7 @@ PME_NOALLOC_SCRATCH_BYTES = 64 << 20
 PME_F_KEEP_PHI = 1
 PME_F_CONCURRENT = 2
 PME_F_OPT_INFLUENCE = 4
+PME_F_SEPARATE_SPREAD = 8
 
 PME_MESH_POW2 = 0
 PME_MESH_SMOOTH = 1

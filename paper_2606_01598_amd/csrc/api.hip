@@ -177,7 +177,8 @@ int check_desc(const pme_desc_t& desc) {
       !isfinite(desc.influence_power) || !isfinite(desc.prefactor))
     return PME_EALPHA;
   if (desc.max_atoms < 1 ||
-      (desc.flags & ~(PME_F_KEEP_PHI | PME_F_CONCURRENT | PME_F_OPT_INFLUENCE)))
+      (desc.flags & ~(PME_F_KEEP_PHI | PME_F_CONCURRENT | PME_F_OPT_INFLUENCE |
+                      PME_F_SEPARATE_SPREAD)))
     return PME_EINVAL;
   for (int a = 0; a < 3; ++a)
     if (desc.tile[a] < 0 || desc.tile[a] > 1024) return PME_EINVAL;
@@ -279,6 +280,30 @@ int plan_geometry(const pme_desc_t& desc, DevPlan& d, long& nbins_out) {
     const long slab_bytes = long(sizeof(float2)) * (2 * buf + d.N[1] + d.N[2]);
     d.slab = slab_bytes <= pme::kSlabLdsMax;
     d.slab_lds = size_t(slab_bytes);
+    // spread fused with the forward slab transform: the padded plane (64-bit words)
+    // after the first transform buffer, which also holds the bin scan, the item map
+    // and the hit list while atoms are added; the second buffer overlaps the plane.
+    // Every axis needs N >= p + B (a plane's anchors then lie in at most
+    // (p - 1) / B + 2 bin layers and a padded row or column has one periodic image).
+    d.fused = false;
+    if (d.slab && !(desc.flags & PME_F_SEPARATE_SPREAD) && p <= 7) {
+      bool ok = true;
+      for (int a = 0; a < 3; ++a)
+        if (d.N[a] < p + d.B[a]) ok = false;
+      long layers = (p - 1) / d.B[0] + 2;
+      if (layers > d.nb[0]) layers = d.nb[0];
+      const long nscan = layers * d.nb[1] * d.nb[2];
+      const long arrays = 8 * (nscan + 2) + 2L * pme::kFusedMap + 4L * pme::kFusedHits;
+      const long abuf = buf > (arrays + 7) / 8 ? buf : (arrays + 7) / 8;
+      const long pl = long(d.N[1] + p - 1) * (d.N[2] + p - 1);
+      const long bytes = 8 * (d.N[1] + d.N[2] + abuf + (pl > buf ? pl : buf));
+      if (ok && nscan < 65535 && bytes <= pme::kSlabLdsMax) {
+        d.fused = true;
+        d.fused_lds = size_t(bytes);
+        d.fused_abuf = int(abuf);
+        d.fused_nscan = int(nscan);
+      }
+    }
     // pencil passes: about 1024 complex points per workgroup
     int pairs = (1024 + d.N[2] - 1) / d.N[2];
     if (pairs > 32) pairs = 32;
@@ -552,11 +577,27 @@ int pme_plan_drop_phi(pme_plan_t plan) {
   mark_phi(plan, false);
   return PME_OK;
 }
-const float* pme_plan_rho(pme_plan_t plan) { return plan ? plan->d.rho : nullptr; }
+const float* pme_plan_rho(pme_plan_t plan) {
+  return (plan && !plan->d.fused) ? plan->d.rho : nullptr;
+}
 
 }  // extern "C"
 
 namespace {
+
+// The density (or tangent density) of binning `set` and its potential into `out`:
+// the fused plane spread and transform when the plan has it, else the tile spread
+// and the slab or pencil transform.
+hipError_t spread_convolve(const DevPlan& d, hipStream_t s, int set, bool tangent,
+                           const double* box, float* out, bool energy, pme::KTimer& tm,
+                           double* vpart = nullptr) {
+  hipError_t e;
+  const int kind = tangent ? PME_K_SPREAD_TANGENT : PME_K_SPREAD;
+  if (d.fused) e = pme::launch_spread_slab(d, s, set, tangent, box, tm.next(kind));
+  else e = pme::launch_spread(d, s, set, tangent, box, tm.next(kind));
+  if (e != hipSuccess) return e;
+  return pme::launch_convolve(d, s, box, out, energy, &tm, vpart, d.fused);
+}
 
 // pme_forward, and with dE_dbox the cell gradient: the x pass and the gather also
 // form their partials of it and one workgroup assembles dE/dC after the gather
@@ -577,9 +618,8 @@ int forward_impl(pme_plan_t plan, void* stream, int32_t n, const float* pos, con
   if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
                            energy != nullptr, tm.next(PME_K_BIN))) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_spread(d, s, set, false, box, tm.next(PME_K_SPREAD))) != hipSuccess)
-    return hip_fail(e);
-  if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm, vpart)) != hipSuccess)
+  if ((e = spread_convolve(d, s, set, false, box, d.phi, energy != nullptr, tm, vpart)) !=
+      hipSuccess)
     return hip_fail(e);
   if ((e = pme::launch_gather(d, s, set, n, pos, q, mu, box, energy, dE_dpos, dE_dq, dE_dmu,
                               pme::bin_blocks(n), tm.next(PME_K_GATHER),
@@ -649,9 +689,8 @@ int pme_backward(pme_plan_t plan, void* stream, int32_t n, const float* pos, con
     if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
                              false, tm.next(PME_K_BIN))) != hipSuccess)
       return hip_fail(e);
-    if ((e = pme::launch_spread(d, s, set, false, box, tm.next(PME_K_SPREAD))) != hipSuccess)
+    if ((e = spread_convolve(d, s, set, false, box, d.phi, false, tm)) != hipSuccess)
       return hip_fail(e);
-    if ((e = pme::launch_convolve(d, s, box, d.phi, false, &tm)) != hipSuccess) return hip_fail(e);
     mark_phi(plan, true);
   }
   const int set = plan->set;
@@ -659,9 +698,8 @@ int pme_backward(pme_plan_t plan, void* stream, int32_t n, const float* pos, con
   if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, v_pos, v_q, v_mu, true, false,
                            tm.next(PME_K_BIN_TANGENT))) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_spread(d, s, set, true, box, tm.next(PME_K_SPREAD_TANGENT))) != hipSuccess)
+  if ((e = spread_convolve(d, s, set, true, box, d.rho, false, tm)) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_convolve(d, s, box, d.rho, false, &tm)) != hipSuccess) return hip_fail(e);
   if ((e = pme::launch_gather_hvp(d, s, set, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos, g_q,
                                   g_mu, tm.next(PME_K_GATHER_HVP))) != hipSuccess)
     return hip_fail(e);
@@ -701,16 +739,13 @@ int pme_step(pme_plan_t plan, void* stream, int32_t n, const float* pos, const f
   if ((e = pme::launch_bin(dt, s2, tset, n, pos, q, mu, box, v_pos, v_q, v_mu, true, false,
                            tm.next(PME_K_BIN_TANGENT))) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_spread(dt, s2, tset, true, box, tm.next(PME_K_SPREAD_TANGENT))) != hipSuccess)
+  if ((e = spread_convolve(dt, s2, tset, true, box, dt.rho, false, tm)) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_convolve(dt, s2, box, dt.rho, false, &tm)) != hipSuccess) return hip_fail(e);
   // forward chain on the caller's stream
   if ((e = pme::launch_bin(d, s, set, n, pos, q, mu, box, nullptr, nullptr, nullptr, false,
                            energy != nullptr, tm.next(PME_K_BIN))) != hipSuccess)
     return hip_fail(e);
-  if ((e = pme::launch_spread(d, s, set, false, box, tm.next(PME_K_SPREAD))) != hipSuccess)
-    return hip_fail(e);
-  if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm)) != hipSuccess)
+  if ((e = spread_convolve(d, s, set, false, box, d.phi, energy != nullptr, tm)) != hipSuccess)
     return hip_fail(e);
   // join, then one gather over the cotangent chain's records (which carry q and mu)
   // forms H v and the forward outputs from phi and the tangent potential

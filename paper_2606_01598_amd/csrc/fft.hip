@@ -219,30 +219,28 @@ __device__ __forceinline__ void slab_layout(const SlabArgs& a, float2* sm, float
 // round of the workgroup covers it) and the first y stage unpacks the two real
 // transforms as it reads:
 //   X_2c[k] = (Z[k] + conj Z[N-k]) / 2,  X_2c+1[k] = (Z[k] - conj Z[N-k]) / 2i.
-__device__ __forceinline__ void slab_fwd_body(const SlabArgs& a, const int x) {
-  extern __shared__ float2 sm[];
+// src(y, z) gives the plane's real value at (y, z); the twiddles are in tz and ty
+// (stored to twz and twy before the first barrier); A and B hold max(npairs N_z,
+// H (N_y + 1)) complex values each.
+template <class Src>
+__device__ __forceinline__ void slab_fwd_run(const SlabArgs& a, const int x, const Src& src,
+                                             const Twiddles<kSlabThreads>& tz,
+                                             const Twiddles<kSlabThreads>& ty, float2* twz,
+                                             float2* twy, float2* A, float2* B) {
   const int Ny = a.ay.N, Nz = a.az.N, H = a.H;
   const int npairs = (Ny + 1) / 2;
-  float2 *twz, *twy, *A, *B;
-  slab_layout(a, sm, twz, twy, A, B);
-  Twiddles<kSlabThreads> tz, ty;
-  tz.load(a.twz, Nz);
-  ty.load(a.twy, Ny);
-  const float* src = a.src + size_t(x) * Ny * Nz;
   const FFTStage& z0 = a.az.st[0];
   float2* Z;
   if (npairs * z0.NR <= int(blockDim.x)) {
     const int t = threadIdx.x;
     if (t < npairs * z0.NR) {
       const int c = int(fdiv(uint32_t(t), z0.nr)), j = t - c * z0.NR;
-      const float* r0 = src + size_t(2 * c) * Nz;
-      const float* r1 = r0 + Nz;
       const bool odd_last = (2 * c + 1 >= Ny);   // odd row count: zero imaginary row
       float2* out = A + c * Nz;
       with_radix(z0.R, [&](auto rc) {
         constexpr int R = decltype(rc)::value;
         stockham_butterfly_io<R, false>(
-            [&](int i) { return make_float2(r0[i], odd_last ? 0.0f : r1[i]); },
+            [&](int i) { return make_float2(src(2 * c, i), odd_last ? 0.0f : src(2 * c + 1, i)); },
             [&](int i, float2 v) { out[i] = v; }, j, 0, j, 1, z0.NR, z0.step, twz, -1.0f);
       });
     }
@@ -253,7 +251,11 @@ __device__ __forceinline__ void slab_fwd_body(const SlabArgs& a, const int x) {
   } else {
     float* Af = reinterpret_cast<float*>(A);
     staged_copy<12, float>(
-        Ny * Nz, [&](int e) { return src[e]; },
+        Ny * Nz,
+        [&](int e) {
+          const int y = int(fdiv(uint32_t(e), a.nzd));
+          return src(y, e - y * Nz);
+        },
         [&](int e, float v) {
           const int y = int(fdiv(uint32_t(e), a.nzd)), m = e - y * Nz;
           Af[2 * ((y >> 1) * Nz + m) + (y & 1)] = v;
@@ -312,6 +314,18 @@ __device__ __forceinline__ void slab_fwd_body(const SlabArgs& a, const int x) {
       dst[e] = R[k * ps + y];
     }
   }
+}
+
+__device__ __forceinline__ void slab_fwd_body(const SlabArgs& a, const int x) {
+  extern __shared__ float2 sm[];
+  float2 *twz, *twy, *A, *B;
+  slab_layout(a, sm, twz, twy, A, B);
+  Twiddles<kSlabThreads> tz, ty;
+  tz.load(a.twz, a.az.N);
+  ty.load(a.twy, a.ay.N);
+  const int Nz = a.az.N;
+  const float* src = a.src + size_t(x) * a.ay.N * Nz;
+  slab_fwd_run(a, x, [&](int y, int z) { return src[size_t(y) * Nz + z]; }, tz, ty, twz, twy, A, B);
 }
 
 // inverse slab: spec[x] -> y inverse FFT -> z C2R -> out[x].  The first y stage reads
@@ -888,6 +902,261 @@ __global__ void __launch_bounds__(kFFTThreads) k_fftx_batch(const XArgs* args, c
   }
 }
 
+// Spread fused with the forward slab transform (Eq. charge_dipole_assign, then the
+// z and y halves of Eq. fft): one workgroup per x-plane X.  It takes from the bins
+// every atom whose stencil covers the plane (anchors b with X in [b - lo, b - lo +
+// p - 1]: the bin layers along x that hold them, and the overflow list), adds the
+// atom's p x p footprint in the plane into an LDS copy of the plane, and transforms
+// the plane in place.  The plane carries p - 1 extra rows and columns, so that a
+// stencil never wraps: padded point (b_y + j, b_z + k) holds stencil point (j, k)
+// of an atom anchored at (b_y, b_z); the extra rows and columns are folded into
+// their periodic images as the transform reads the plane.  Every contribution is
+// the tile spread's own value and is added as the same 64-bit fixed-point word, so
+// the plane's sums, and hence the spectrum, equal those of the tile spread followed
+// by the slab transform bit for bit.
+struct SpreadSlabArgs {
+  SlabArgs sl;             // the plane's transform (sl.src unused)
+  int N[3];
+  int B[3];
+  int nb[3];
+  int cap;
+  const int* count;
+  const int* ovf_count;
+  const unsigned* cmax;
+  const float* rec;
+  long long ovf_base;      // record index of the overflow list
+  int PY, PZ;              // padded plane: N_y + p - 1 rows of N_z + p - 1 words
+  int abuf;                // float2 words before the plane (the transform's first buffer)
+  int nscan_max;           // bins a plane may scan
+  int map_cap;             // slots of the item -> bin map
+  int hits_cap;            // entries of the hit list (>= 2 * blockDim)
+};
+
+template <int P, int DEG>
+__device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const int X,
+                                                 const double* box) {
+  constexpr int NC = (DEG == 1) ? 4 : 10;
+  constexpr int D = (DEG == 1) ? 1 : 2;       // highest weight derivative needed
+  constexpr int lo = (P - 1) / 2;
+  extern __shared__ float2 sm[];
+  const int tid = threadIdx.x;
+  const int nthr = int(blockDim.x);
+  const int Ny = a.N[1], Nz = a.N[2];
+  // LDS: twiddles | first transform buffer, which holds the scan, map and hit list
+  // while atoms are added | the padded plane, later the second transform buffer
+  float2* twz = sm;
+  float2* twy = twz + Nz;
+  float2* A = twy + Ny;
+  unsigned long long* plane = reinterpret_cast<unsigned long long*>(A + a.abuf);
+  float2* B = reinterpret_cast<float2*>(plane);
+  int* s_off = reinterpret_cast<int*>(A);
+  int* s_bin = s_off + a.nscan_max + 2;
+  uint16_t* s_map = reinterpret_cast<uint16_t*>(s_bin + a.nscan_max + 2);
+  int* s_hits = reinterpret_cast<int*>(s_map + a.map_cap);
+  __shared__ float s_J[DEG == 2 ? 9 : 1];
+  __shared__ int s_nh;
+  Twiddles<kSlabThreads> tz, ty;
+  tz.load(a.sl.twz, Nz);
+  ty.load(a.sl.twy, Ny);
+  if (DEG == 2 && tid == 0) {
+    float J[3][3];
+    jacobian(cell_from_box(box), a.N, J);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) s_J[i] = J[i / 3][i % 3];
+  }
+  // the bin layers along x of the anchors X + lo - P + 1 .. X + lo (cyclic): from the
+  // first anchor's layer on, nl of them
+  const int b0 = wrapn(X + lo - P + 1, a.N[0]);
+  const int k0 = b0 / a.B[0], k1 = wrapn(X + lo, a.N[0]) / a.B[0];
+  int nl;
+  if (b0 + P - 1 < a.N[0]) nl = k1 - k0 + 1;
+  else nl = (k1 < k0) ? a.nb[0] - k0 + k1 + 1 : a.nb[0];
+  nl = min(nl, a.nb[0]);
+  const int nyz = a.nb[1] * a.nb[2];
+  const int nscan = nl * nyz;                 // <= a.nscan_max (host guarantees)
+  for (int e = tid; e < nscan; e += nthr) {
+    const int li = e / nyz;
+    const int bin = ((k0 + li) % a.nb[0]) * nyz + (e - li * nyz);
+    s_bin[e] = bin;
+    s_off[e] = min(a.count[bin], a.cap);
+  }
+  if (tid == 0) {
+    s_bin[nscan] = -1;                        // pseudo-bin: the overflow list
+    s_off[nscan] = *a.ovf_count;
+    s_nh = 0;
+  }
+  // the fixed-point unit of the tile spread (the same bound and the same scale)
+  constexpr float kWhole3 = float(spline_norm(P)) * float(spline_norm(P)) * float(spline_norm(P));
+  float scale = 1.0f;
+  {
+    const float cm = __uint_as_float(*a.cmax);
+    if (cm > 0.0f && isfinite(cm)) scale = ldexpf(1.0f, 31 - (ilogbf(8.0f * cm * kWhole3) + 1));
+  }
+  const int pvol = a.PY * a.PZ;
+  for (int e = tid; e < pvol; e += nthr) plane[e] = 0ull;
+  __syncthreads();
+  // exclusive scan of the occupied slot counts (wavefront 0)
+  if (tid < 64) {
+    const int len = nscan + 1;
+    const int seg = (len + 63) / 64;
+    const int s0 = min(tid * seg, len), s1 = min(s0 + seg, len);
+    int acc = 0;
+    for (int e = s0; e < s1; ++e) acc += s_off[e];
+    int incl = acc;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o, 64);
+      if (tid >= o) incl += v;
+    }
+    int run = incl - acc;
+    for (int e = s0; e < s1; ++e) { const int v = s_off[e]; s_off[e] = run; run += v; }
+    if (tid == 63) s_off[len] = incl;
+  }
+  __syncthreads();
+  const int total = s_off[nscan + 1];
+  const bool mapped = total <= a.map_cap;
+  if (mapped)
+    for (int e = tid; e <= nscan; e += nthr)
+      for (int k = s_off[e]; k < s_off[e + 1]; ++k) s_map[k] = uint16_t(e);
+  __syncthreads();
+
+  // record index of scanned slot `item`: the bin is the last one whose offset is <= item
+  auto record_of = [&](int item) {
+    int lb = 0;
+    if (mapped) {
+      lb = s_map[item];
+    } else {
+      int hb = nscan;
+      while (lb < hb) {
+        const int mid = (lb + hb + 1) >> 1;
+        if (s_off[mid] <= item) lb = mid; else hb = mid - 1;
+      }
+    }
+    const int bin = s_bin[lb];
+    const int slot = item - s_off[lb];
+    return (bin >= 0) ? size_t(bin) * a.cap + slot : size_t(a.ovf_base) + slot;
+  };
+  // one atom: its footprint in the plane, with the tile spread's arithmetic
+  auto add_atom = [&](size_t ri) {
+    const float4* r = reinterpret_cast<const float4*>(a.rec + ri * kRecWords);
+    const float4 h = r[0];
+    const float4 c0v = r[1];
+    float co[NC];
+    if constexpr (DEG == 2) {
+      const float4 c1v = r[2];
+      const float* f = a.rec + ri * kRecWords;   // v_mu
+      float Jt[3][3];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Jt[i / 3][i % 3] = s_J[i];
+      tangent_coeffs(Jt, c0v.x, make_float3(c0v.y, c0v.z, c0v.w), c1v.x,
+                     make_float3(c1v.y, c1v.z, c1v.w), make_float3(f[12], f[13], f[14]), co);
+    } else {
+      co[0] = c0v.x; co[1] = c0v.y; co[2] = c0v.z; co[3] = c0v.w;
+    }
+    const int pk = __float_as_int(h.w);
+    const int by = (pk >> 10) & 1023, bz = (pk >> 20) & 1023;
+    int ix = X - (pk & 1023) + lo;
+    ix += (ix < 0) ? a.N[0] : 0;
+    ix -= (ix >= a.N[0]) ? a.N[0] : 0;
+    // this plane's x weights (whole-number, times the fixed-point unit)
+    float x[D + 1];
+    {
+      float wx[D + 1][P];
+      spline_weights_whole<P, D>(h.x, wx);
+#pragma unroll
+      for (int d = 0; d <= D; ++d) {
+        float v = wx[d][0];
+#pragma unroll
+        for (int j = 1; j < P; ++j) v = (ix == j) ? wx[d][j] : v;
+        x[d] = v * scale;
+      }
+    }
+    // this x-plane's coefficients of the (y, z) derivative monomials
+    float ax0, az1, az2 = 0.f, ay1, ay2 = 0.f, ayz = 0.f;
+    if (DEG == 1) {
+      ax0 = co[0] * x[0] + co[1] * x[1];   // W_y W_z
+      ay1 = co[2] * x[0];                  // W_y' W_z
+      az1 = co[3] * x[0];                  // W_y W_z'
+    } else {
+      ax0 = co[0] * x[0] + co[1] * x[1] + co[4] * x[2];
+      ay1 = co[2] * x[0] + co[7] * x[1];
+      az1 = co[3] * x[0] + co[8] * x[1];
+      ay2 = co[5] * x[0];
+      az2 = co[6] * x[0];
+      ayz = co[9] * x[0];
+    }
+    float wy[D + 1][P], wz[D + 1][P];
+    spline_weights_whole<P, D>(h.y, wy);
+    spline_weights_whole<P, D>(h.z, wz);
+    unsigned long long* base = plane + by * a.PZ + bz;
+#pragma unroll
+    for (int iy = 0; iy < P; ++iy) {
+      const float y0 = wy[0][iy], y1 = wy[1][iy];
+      float c0 = ax0 * y0 + ay1 * y1, c1 = az1 * y0, c2 = 0.f;
+      if (D == 2) {
+        const float y2 = wy[2][iy];
+        c0 += ay2 * y2;
+        c1 += ayz * y1;
+        c2 = az2 * y0;
+      }
+      unsigned long long* row = base + iy * a.PZ;
+#pragma unroll
+      for (int iz = 0; iz < P; ++iz) {
+        float v = c0 * wz[0][iz] + c1 * wz[1][iz];
+        if (D == 2) v += c2 * wz[2][iz];
+        atomicAdd(row + iz, to_fixed(v));
+      }
+    }
+  };
+
+  // rounds of one scanned slot per thread: the anchors whose stencil covers the plane
+  // are listed; the list is drained (one atom per thread) when another round might
+  // not fit and after the last round
+  for (int r0 = 0; r0 < total; r0 += nthr) {
+    const int item = r0 + tid;
+    bool hit = false;
+    size_t ri = 0;
+    if (item < total) {
+      ri = record_of(item);
+      const int pk = __float_as_int(a.rec[ri * kRecWords + 3]);
+      int d = X - (pk & 1023) + lo;
+      d += (d < 0) ? a.N[0] : 0;
+      d -= (d >= a.N[0]) ? a.N[0] : 0;
+      hit = d < P;
+    }
+    const int k = wave_compact(hit, &s_nh);
+    if (hit) s_hits[k] = int(ri);
+    __syncthreads();
+    const int nh = s_nh;
+    __syncthreads();   // every thread has read the count before it changes
+    if (nh + nthr > a.hits_cap || r0 + nthr >= total) {
+      for (int e = tid; e < nh; e += nthr) add_atom(size_t(uint32_t(s_hits[e])));
+      if (tid == 0) s_nh = 0;
+      __syncthreads();
+    }
+  }
+  // the plane's value at (y, z): the fixed-point words of its periodic images
+  const double inv_scale = 1.0 / (double(scale) * double(kWhole3));
+  auto value = [&](int y, int z) {
+    const int py = y + lo, pz = z + lo;
+    const int py2 = (py + Ny < a.PY) ? py + Ny : ((py >= Ny) ? py - Ny : -1);
+    const int pz2 = (pz + Nz < a.PZ) ? pz + Nz : ((pz >= Nz) ? pz - Nz : -1);
+    unsigned long long acc = plane[py * a.PZ + pz];
+    if (pz2 >= 0) acc += plane[py * a.PZ + pz2];
+    if (py2 >= 0) {
+      acc += plane[py2 * a.PZ + pz];
+      if (pz2 >= 0) acc += plane[py2 * a.PZ + pz2];
+    }
+    return from_fixed((long long)acc, inv_scale);
+  };
+  slab_fwd_run(a.sl, X, value, tz, ty, twz, twy, A, B);
+}
+
+template <int P, int DEG>
+__global__ void __launch_bounds__(kSlabThreads) k_spread_slab(SpreadSlabArgs a, const double* box) {
+  spread_slab_body<P, DEG>(a, xcd_item(blockIdx.x, gridDim.x), box);
+}
+
 }  // namespace
 
 namespace {
@@ -979,14 +1248,15 @@ hipError_t launch_convolve_batch(const FFTBatch& t, hipStream_t s, const double*
 }
 
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
-                           bool energy, KTimer* tm, double* vpart) {
+                           bool energy, KTimer* tm, double* vpart, bool from_spec) {
   hipError_t err;
+  if (from_spec && !d.slab) return hipErrorInvalidValue;
   XArgs x = make_x_args(d, box, energy);
   x.vpart = vpart;
   const size_t xsh = x_lds(d);
   // timed kinds: a kind spanning two launches records its start with the first
   // and its stop with the second
-  const LaunchEvents* er = tm ? tm->next(PME_K_FFT_R2C) : nullptr;
+  const LaunchEvents* er = (tm && !from_spec) ? tm->next(PME_K_FFT_R2C) : nullptr;
   const LaunchEvents* ex = tm ? tm->next(PME_K_FFT_X) : nullptr;
   const LaunchEvents* ei = tm ? tm->next(PME_K_FFT_C2R) : nullptr;
   LaunchEvents er0, er1, ei0, ei1;
@@ -995,8 +1265,10 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
 
   if (d.slab) {
     const SlabArgs sa = make_slab_args(d, out);
-    launch_k(er, k_slab_fwd, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (!from_spec) {
+      launch_k(er, k_slab_fwd, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
+      if ((err = hipGetLastError()) != hipSuccess) return err;
+    }
     if (vpart) launch_k(ex, k_fftx_fused<1>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
     else if (d.opt) {
       launch_k(ex, k_fftx_fused<2>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
@@ -1042,6 +1314,36 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   return hipGetLastError();
 }
 
+hipError_t launch_spread_slab(const DevPlan& d, hipStream_t s, int set, bool tangent,
+                              const double* box, const LaunchEvents* ev) {
+  if (!d.fused) return hipErrorInvalidValue;
+  SpreadSlabArgs a;
+  a.sl = make_slab_args(d, nullptr);
+  for (int k = 0; k < 3; ++k) { a.N[k] = d.N[k]; a.B[k] = d.B[k]; a.nb[k] = d.nb[k]; }
+  a.cap = d.cap;
+  a.count = d.count[set]; a.ovf_count = d.ovf_count[set]; a.cmax = d.cmax[set];
+  a.rec = d.rec; a.ovf_base = d.ovf_base;
+  a.PY = d.N[1] + d.p - 1;
+  a.PZ = d.N[2] + d.p - 1;
+  a.abuf = d.fused_abuf;
+  a.nscan_max = d.fused_nscan;
+  a.map_cap = kFusedMap;
+  a.hits_cap = kFusedHits;
+  const dim3 g(d.N[0]), b(kSlabThreads);
+  const size_t sh = d.fused_lds;
+#define PME_F(P)                                                            \
+  case P:                                                                   \
+    if (tangent) launch_k(ev, k_spread_slab<P, 2>, g, b, sh, s, a, box);    \
+    else launch_k(ev, k_spread_slab<P, 1>, g, b, sh, s, a, box);            \
+    break;
+  switch (d.p) {
+    PME_F(1) PME_F(2) PME_F(3) PME_F(4) PME_F(5) PME_F(6) PME_F(7)
+    default: return hipErrorInvalidValue;
+  }
+#undef PME_F
+  return hipGetLastError();
+}
+
 hipError_t enable_slab_lds(size_t bytes) {
   // The limit is per kernel, not per plan: raise it to the largest slab any plan
   // may use, so that a later plan with smaller planes does not lower it.
@@ -1049,7 +1351,13 @@ hipError_t enable_slab_lds(size_t bytes) {
   const void* fns[] = {reinterpret_cast<const void*>(k_slab_fwd),
                        reinterpret_cast<const void*>(k_slab_inv),
                        reinterpret_cast<const void*>(k_slab_fwd_batch),
-                       reinterpret_cast<const void*>(k_slab_inv_batch)};
+                       reinterpret_cast<const void*>(k_slab_inv_batch),
+#define PME_F(P)                                                   \
+  reinterpret_cast<const void*>(k_spread_slab<P, 1>),              \
+      reinterpret_cast<const void*>(k_spread_slab<P, 2>),
+                       PME_F(1) PME_F(2) PME_F(3) PME_F(4) PME_F(5) PME_F(6) PME_F(7)
+#undef PME_F
+  };
   for (const void* f : fns) {
     const hipError_t e =
         hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kSlabLdsMax);

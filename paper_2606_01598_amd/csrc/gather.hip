@@ -123,11 +123,6 @@ __device__ void finalize_energy(const GArgs& a, const Cell& c) {
   }
 }
 
-__device__ __forceinline__ float3 jmul(const float (&J)[3][3], float3 v) {
-  return make_float3(J[0][0] * v.x + J[0][1] * v.y + J[0][2] * v.z,
-                     J[1][0] * v.x + J[1][1] * v.y + J[1][2] * v.z,
-                     J[2][0] * v.x + J[2][1] * v.y + J[2][2] * v.z);
-}
 // J^T u
 __device__ __forceinline__ float3 jtmul(const float (&J)[3][3], float3 u) {
   return make_float3(J[0][0] * u.x + J[1][0] * u.y + J[2][0] * u.z,

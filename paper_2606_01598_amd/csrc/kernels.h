@@ -63,6 +63,8 @@ struct AxisPlan {          // 1D mixed-radix FFT of length N
 constexpr int kFFTThreads = 256;    // pencil-pass workgroup
 constexpr int kSlabThreads = 1024;  // slab-pass workgroup (one x-plane)
 constexpr int kSlabLdsMax = 160 * 1024 - 2048;
+constexpr int kFusedMap = 4096;     // item -> bin map slots of a fused spread-slab workgroup
+constexpr int kFusedHits = 2048;    // its hit list (two rounds of one slot per thread)
 
 struct DevPlan {
   int N[3];                // mesh dims
@@ -101,6 +103,12 @@ struct DevPlan {
   int* gvalid;             // [1]
   bool slab;               // y-z planes transformed in LDS (z and y passes fused)
   size_t slab_lds;         // dynamic LDS bytes of a slab workgroup
+  // spread fused with the forward slab transform (one x-plane per workgroup), when
+  // the padded plane fits in LDS beside a transform buffer
+  bool fused;
+  size_t fused_lds;        // its dynamic LDS bytes
+  int fused_abuf;          // float2 words before the plane
+  int fused_nscan;         // bins a plane may scan
   int rows_per_block;      // z-pass rows per block (even)
   int ktile;               // half-spectrum z columns per y/x-pass block (y and x pass)
   // meshes
@@ -253,8 +261,14 @@ hipError_t launch_gather_quad(const DevPlan& d, hipStream_t s, int set, int n, c
                               float* dE_dmu, float* dE_dtheta, const LaunchEvents* ev);
 // rho -> spec -> (x g) -> out, the mesh operator K; energy partials when wanted, and
 // with vpart the six k-space partials of the cell gradient per x-pass workgroup.
+// from_spec: the spectrum is already there (the fused spread wrote it); only the
+// x pass and the inverse slab transform run
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
-                           bool energy, KTimer* tm, double* vpart = nullptr);
+                           bool energy, KTimer* tm, double* vpart = nullptr,
+                           bool from_spec = false);
+// Spread fused with the forward slab transform (d.fused): writes d.spec directly
+hipError_t launch_spread_slab(const DevPlan& d, hipStream_t s, int set, bool tangent,
+                              const double* box, const LaunchEvents* ev);
 // Raise the dynamic LDS limit of the spread (kBigLds) and gather (kGatherLds) kernels.
 hipError_t enable_spread_lds();
 hipError_t enable_gather_lds();

@@ -225,6 +225,47 @@ __device__ __forceinline__ bool atom_stencil(float3 r, const Cell& c, const int 
   return ok;
 }
 
+// d = J v  (x-space components of a Cartesian vector)
+__device__ __forceinline__ float3 jmul(const float (&J)[3][3], float3 v) {
+  return make_float3(J[0][0] * v.x + J[0][1] * v.y + J[0][2] * v.z,
+                     J[1][0] * v.x + J[1][1] * v.y + J[1][2] * v.z,
+                     J[2][0] * v.x + J[2][1] * v.y + J[2][2] * v.z);
+}
+
+// Coefficients of the tangent density of the Hessian-vector product:
+// rho_dot = v_q W + w.grad_x W + d^T (grad_x grad_x W) v with d = J mu,
+// v = J v_r, w = J (v_mu + q v_r); monomials 000, 100, 010, 001, 200, 020, 002,
+// 110, 101, 011.
+__device__ __forceinline__ void tangent_coeffs(const float (&J)[3][3], float q, float3 mu, float vq,
+                                               float3 vr, float3 vm, float (&co)[10]) {
+  const float3 d = jmul(J, mu);
+  const float3 w = jmul(J, make_float3(vm.x + q * vr.x, vm.y + q * vr.y, vm.z + q * vr.z));
+  const float3 v = jmul(J, vr);
+  co[0] = vq;
+  co[1] = w.x; co[2] = w.y; co[3] = w.z;
+  co[4] = d.x * v.x; co[5] = d.y * v.y; co[6] = d.z * v.z;
+  co[7] = d.x * v.y + d.y * v.x;
+  co[8] = d.x * v.z + d.z * v.x;
+  co[9] = d.y * v.z + d.z * v.y;
+}
+
+// A contribution of magnitude below 2^31 as a 64-bit fixed-point word: rounded to
+// the nearest 32-bit integer, ties up (floor(v + 1/2), one conversion instruction)
+// and sign-extended.  The rounding moves a contribution by at most half a unit,
+// 2^-31 of the largest possible one, with no bias but at exact ties.
+__device__ __forceinline__ unsigned long long to_fixed(float v) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+  return (unsigned long long)(long long)r;
+}
+
+// A 64-bit fixed-point sum as a float: hi * 2^32 + lo in double precision (exact
+// below 2^53), scaled by inv_scale and rounded once to float.
+__device__ __forceinline__ float from_fixed(long long v, double inv_scale) {
+  const double vd = fma(double(int(v >> 32)), 4294967296.0, double(uint32_t(v)));
+  return float(vd * inv_scale);
+}
+
 // m mod N in [0, N) for any int m
 __device__ __forceinline__ int wrapn(int m, int N) {
   m %= N;

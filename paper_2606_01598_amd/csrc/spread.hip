@@ -67,30 +67,6 @@ __device__ __forceinline__ float3 ld3(const float* p, int i) {
   return p ? make_float3(p[3 * i], p[3 * i + 1], p[3 * i + 2]) : make_float3(0.f, 0.f, 0.f);
 }
 
-// d = J v  (x-space components of a Cartesian vector)
-__device__ __forceinline__ float3 jmul(const float (&J)[3][3], float3 v) {
-  return make_float3(J[0][0] * v.x + J[0][1] * v.y + J[0][2] * v.z,
-                     J[1][0] * v.x + J[1][1] * v.y + J[1][2] * v.z,
-                     J[2][0] * v.x + J[2][1] * v.y + J[2][2] * v.z);
-}
-
-// Coefficients of the tangent density of the Hessian-vector product:
-// rho_dot = v_q W + w.grad_x W + d^T (grad_x grad_x W) v with d = J mu,
-// v = J v_r, w = J (v_mu + q v_r); monomials 000, 100, 010, 001, 200, 020, 002,
-// 110, 101, 011.
-__device__ __forceinline__ void tangent_coeffs(const float (&J)[3][3], float q, float3 mu, float vq,
-                                               float3 vr, float3 vm, float (&co)[10]) {
-  const float3 d = jmul(J, mu);
-  const float3 w = jmul(J, make_float3(vm.x + q * vr.x, vm.y + q * vr.y, vm.z + q * vr.z));
-  const float3 v = jmul(J, vr);
-  co[0] = vq;
-  co[1] = w.x; co[2] = w.y; co[3] = w.z;
-  co[4] = d.x * v.x; co[5] = d.y * v.y; co[6] = d.z * v.z;
-  co[7] = d.x * v.y + d.y * v.x;
-  co[8] = d.x * v.z + d.z * v.x;
-  co[9] = d.y * v.z + d.z * v.y;
-}
-
 // Second-order coefficients of the quadrupole density (1/2) Q : grad_x grad_x W,
 // Q = J Theta J^T: monomials 200, 020, 002 take Q_aa / 2, 110, 101, 011 take Q_ab.
 __device__ __forceinline__ void quad_coeffs(const float (&J)[3][3], const float (&th)[6],
@@ -360,16 +336,6 @@ __device__ __forceinline__ void rel_locs(int d, int T, int& w0, int& w1) {
 __device__ __forceinline__ int loc_of(int w0, int w1, int j) {
   const int w = (j < 4) ? w0 : w1;
   return int(int8_t((w >> (8 * (j & 3))) & 0xff));
-}
-
-// A contribution of magnitude below 2^31 as a 64-bit fixed-point word: rounded to
-// the nearest 32-bit integer, ties up (floor(v + 1/2), one conversion instruction)
-// and sign-extended.  The rounding moves a contribution by at most half a unit,
-// 2^-31 of the largest possible one, with no bias but at exact ties.
-__device__ __forceinline__ unsigned long long to_fixed(float v) {
-  int r;
-  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
-  return (unsigned long long)(long long)r;
 }
 
 template <int P, int DEG>

@@ -66,7 +66,8 @@ class Plan:
 
     def __init__(self, mesh, order: int, alpha: float, max_atoms: int, influence_power: float = 1.0,
                  prefactor: float = 1.0, keep_phi: bool = True, device=None, tile=None,
-                 concurrent: bool = False, optimal_influence: bool = False, fft_lines=None):
+                 concurrent: bool = False, optimal_influence: bool = False, fft_lines=None,
+                 separate_spread: bool = False):
         self._lib = _lib.load()
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
         d = _lib.PMEDesc()
@@ -75,7 +76,8 @@ class Plan:
         d.order = int(order)
         d.max_atoms = int(max_atoms)
         d.flags = ((_lib.PME_F_KEEP_PHI if keep_phi else 0) | (_lib.PME_F_CONCURRENT if concurrent else 0)
-                   | (_lib.PME_F_OPT_INFLUENCE if optimal_influence else 0))
+                   | (_lib.PME_F_OPT_INFLUENCE if optimal_influence else 0)
+                   | (_lib.PME_F_SEPARATE_SPREAD if separate_spread else 0))
         d.alpha = float(alpha)
         d.influence_power = float(influence_power)
         d.prefactor = float(prefactor)
@@ -264,8 +266,13 @@ class Plan:
         return self._mesh_copy(self._lib.pme_plan_phi(self.handle))
 
     def rho(self) -> torch.Tensor:
-        """Copy of the last density spread (forward density or tangent density)."""
-        return self._mesh_copy(self._lib.pme_plan_rho(self.handle))
+        """Copy of the last density spread (forward density or tangent density).
+        A plan with the fused plane spread keeps no density mesh."""
+        ptr = self._lib.pme_plan_rho(self.handle)
+        if not ptr:
+            raise RuntimeError("this plan spreads by x-planes fused with the transform and keeps "
+                               "no density mesh; create it with separate_spread=True")
+        return self._mesh_copy(ptr)
 
     def _mesh_copy(self, ptr) -> torch.Tensor:
         out = torch.empty(self.mesh, dtype=torch.float32, device=self.device)

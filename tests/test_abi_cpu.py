@@ -91,7 +91,7 @@ def _desc(**kw):
     (dict(gamma=-1.0), _lib.PME_EALPHA),
     (dict(prefactor=float("inf")), _lib.PME_EALPHA),
     (dict(max_atoms=0), _lib.PME_EINVAL),
-    (dict(flags=8), _lib.PME_EINVAL),
+    (dict(flags=16), _lib.PME_EINVAL),
     (dict(fft_lines=-1), _lib.PME_EINVAL),
     (dict(fft_lines=1025), _lib.PME_EINVAL),
 ])

@@ -52,9 +52,15 @@ def _check_forward(frame, mesh, p, alpha, gamma=1.0, with_q=True, with_mu=True, 
 
 def test_density_and_potential_config1():
     f = synth.rocksalt()
-    plan = _plan((16, 16, 16), 4, 0.3, f.n)
+    # the tile spread stores the density; the fused plane spread keeps none
+    plan = _plan((16, 16, 16), 4, 0.3, f.n, separate_spread=True)
     pos, q, mu, box = to_dev(f)
     plan.forward(pos, q, mu, box)
+    fused = _plan((16, 16, 16), 4, 0.3, f.n)
+    fused.forward(pos, q, mu, box)
+    with pytest.raises(RuntimeError):
+        fused.rho()
+    assert torch.equal(fused.phi(), plan.phi())
     ref = oracle_forward(f, (16, 16, 16), 4, 0.3)
     rho, phi = host(plan.rho()), host(plan.phi())
     print("rho", np.abs(rho - ref.rho).max(), "phi", rms_rel(phi, ref.phi), flush=True)
@@ -411,22 +417,25 @@ def test_config3_32k_full_parity():
     _check_forward(f, (100, 100, 100), 6, 0.3, label="32k")
 
 
-@pytest.mark.parametrize("mesh", [(32, 32, 32), (12, 160, 150)])
-def test_launch_timer_counts_and_outputs_unchanged(mesh):
+@pytest.mark.parametrize("mesh,separate,fused", [((32, 32, 32), True, False),
+                                                  ((32, 32, 32), False, True),
+                                                  ((12, 160, 150), False, False)])
+def test_launch_timer_counts_and_outputs_unchanged(mesh, separate, fused):
     """pme_plan_timer brackets exactly the launches of the chosen kind and leaves
-    the results untouched, in the slab layout (32^3: one launch per transform half)
-    and the pencil layout (12 x 160 x 150: two launches per transform half, the z
-    and y passes; the x pass is one)."""
+    the results untouched, in the slab layout (32^3: one launch per transform half;
+    with the fused plane spread, none for the forward half, which the spread
+    performs) and the pencil layout (12 x 160 x 150: two launches per transform
+    half, the z and y passes; the x pass is one)."""
     from paper_2606_01598_amd import _lib
     f = synth.molten_box(1000, 1)
-    plan = _plan(mesh, 6, 0.3, f.n)
+    plan = _plan(mesh, 6, 0.3, f.n, separate_spread=separate)
     pos, q, mu, box = to_dev(f)
     v = [torch.tensor(x, dtype=torch.float32, device=dev()) for x in
          synth.random_cotangents(f.n, 5, scale_r=0.1)]
     ref = plan.forward(pos, q, mu, box)
     ref_b = plan.backward(pos, q, mu, box, *v)
-    per_step = {"bin": 1, "bin_tangent": 1, "spread": 1, "spread_tangent": 1, "fft_r2c": 2,
-                "fft_x": 2, "fft_c2r": 2, "gather": 1, "gather_hvp": 1}
+    per_step = {"bin": 1, "bin_tangent": 1, "spread": 1, "spread_tangent": 1,
+                "fft_r2c": 0 if fused else 2, "fft_x": 2, "fft_c2r": 2, "gather": 1, "gather_hvp": 1}
     for kind in _lib.KERNEL_KINDS:
         plan.timer(kind)
         for _ in range(3):
