@@ -61,15 +61,28 @@ KERNEL_SYMBOL = {
 }
 
 
-def kernel_symbol(kind: str, step: bool = False) -> str:
+# The spread kinds where the spread is fused with the forward slab transform (one
+# x-plane per workgroup; the default on meshes whose padded plane fits in LDS)
+FUSED_SYMBOL = {"spread": "k_spread_slab<6, 1>", "spread_tangent": "k_spread_slab<6, 2>"}
+
+
+def kernel_symbol(kind: str, step: bool = False, fused: bool = False) -> str:
     """Profiler name of a timer kind's kernel; under pme_step the Hessian-vector
-    gather is the variant that also forms the forward outputs."""
+    gather is the variant that also forms the forward outputs; with the fused
+    plane spread the spread kinds name the fused kernel."""
     if kind == "gather_hvp" and step:
         return "k_gather_hvp<6, true>"
+    if fused and kind in FUSED_SYMBOL:
+        return FUSED_SYMBOL[kind]
     return KERNEL_SYMBOL[kind]
 
 
-def alg_bytes(kind: str, n: int, m: int, step: bool = True) -> int:
+def spec_bytes(mesh) -> int:
+    """Bytes of the half spectrum (complex float, N_x N_y (N_z/2 + 1))."""
+    return 8 * mesh[0] * mesh[1] * (mesh[2] // 2 + 1)
+
+
+def alg_bytes(kind: str, n: int, m: int, step: bool = True, spec: int = 0) -> int:
     """Algorithmic HBM bytes of one launch: the method's arrays (FP32) that the
     step must read or write, split over the kernels that perform the method's
     steps (the binning is part of the spread step, Eq. charge_dipole_assign):
@@ -84,10 +97,16 @@ def alg_bytes(kind: str, n: int, m: int, step: bool = True) -> int:
                      (pme_step: also the 3 gradients out        112 n + 8 M)
     A pme_forward + pme_backward step sums to 224 B per atom + 36 B per mesh point;
     a pme_step (one gather for both) to 196 B per atom + 32 B per mesh point.
+    With the spread fused with the forward slab transform (spec = the half
+    spectrum's bytes, 8 N_x N_y (N_z/2 + 1)), the density never leaves the
+    workgroup: the fused kernel reads the atom inputs and writes the spectrum,
+      spread         28 n + spec,   spread_tangent   56 n + spec,
+    and the step model is unchanged up to the spectrum's size against 4 M.
     """
-    table = {"bin": 0, "bin_tangent": 0, "spread": 28 * n + 4 * m,
-             "spread_tangent": 56 * n + 4 * m, "fft_r2c": 4 * m, "fft_x": 0, "fft_c2r": 4 * m,
-             "gather": 56 * n + 4 * m, "gather_hvp": (112 if step else 84) * n + 8 * m}
+    table = {"bin": 0, "bin_tangent": 0, "spread": 28 * n + (spec or 4 * m),
+             "spread_tangent": 56 * n + (spec or 4 * m), "fft_r2c": 4 * m, "fft_x": 0,
+             "fft_c2r": 4 * m, "gather": 56 * n + 4 * m,
+             "gather_hvp": (112 if step else 84) * n + 8 * m}
     return table[kind]
 
 
@@ -98,8 +117,9 @@ def step_bytes(n: int, m: int, step: bool = True) -> int:
 # the sources each timer kind's kernel is compiled from (a traffic summary holds
 # only while they are unchanged)
 KERNEL_SOURCES = {
-    "bin": ("spread.hip",), "bin_tangent": ("spread.hip",), "spread": ("spread.hip",),
-    "spread_tangent": ("spread.hip",), "fft_r2c": ("fft.hip", "fft_radix.h"),
+    "bin": ("spread.hip",), "bin_tangent": ("spread.hip",),
+    "spread": ("spread.hip", "fft.hip", "fft_radix.h"),
+    "spread_tangent": ("spread.hip", "fft.hip", "fft_radix.h"), "fft_r2c": ("fft.hip", "fft_radix.h"),
     "fft_x": ("fft.hip", "fft_radix.h"), "fft_c2r": ("fft.hip", "fft_radix.h"),
     "gather": ("gather.hip",), "gather_hvp": ("gather.hip",),
 }
@@ -177,6 +197,9 @@ def _args(argv=None):
                     help="1 adds the batched-graph leg (64 boxes, one HIP graph per step)")
     ap.add_argument("--learned", type=int, default=1,
                     help="1 adds the learned-dipole leg (SCF teacher vs trained network)")
+    ap.add_argument("--separate-spread", type=int, default=0,
+                    help="1: plans spread by mesh tiles and transform in a separate pass "
+                         "(PME_F_SEPARATE_SPREAD) instead of the fused plane spread")
     ap.add_argument("--halo-probe", type=int, default=0,
                     help="1: time the global-memory combination of the overlapping per-tile "
                          "regions of a scatter-once spread (pme_halo_probe: 64-bit atomics, or "
@@ -229,7 +252,8 @@ def main(argv=None):
     box = torch.tensor(frame.box, dtype=torch.float64, device=dev)
     v = synth.random_cotangents(n, 11, scale_r=0.1)
     vr, vq, vm = (torch.tensor(x, dtype=torch.float32, device=dev) for x in v)
-    plan = Plan(mesh, p, alpha, max_atoms=n, keep_phi=True, concurrent=not args.sequential)
+    plan = Plan(mesh, p, alpha, max_atoms=n, keep_phi=True, concurrent=not args.sequential,
+                separate_spread=bool(args.separate_spread))
     fo = {"energy": torch.empty(3, dtype=torch.float64, device=dev),
           "dE_dpos": torch.empty(n, 3, device=dev), "dE_dq": torch.empty(n, device=dev),
           "dE_dmu": torch.empty(n, 3, device=dev)}
@@ -260,7 +284,10 @@ def main(argv=None):
             kernels_us[kind] = round(1e3 * ms / launches, 3)
             per_step_us[kind] = 1e3 * ms / args.breakdown_steps
     plan.timer(None)
-    dominant = max((k for k in per_step_us if alg_bytes(k, n, m, not args.sequential) > 0),
+    # the fused plane spread performs the forward slab transform: no r2c launches
+    fused = "fft_r2c" not in kernels_us
+    spec = spec_bytes(mesh) if fused else 0
+    dominant = max((k for k in per_step_us if alg_bytes(k, n, m, not args.sequential, spec) > 0),
                    key=lambda k: per_step_us[k])
 
     # eager timed region: K steps, the dominant kernel's launches bracketed by HIP events
@@ -311,10 +338,10 @@ def main(argv=None):
         torch.cuda.synchronize()
 
     dur_s = dom_ms / launches / 1e3
-    ab = alg_bytes(dominant, n, m, not args.sequential)
+    ab = alg_bytes(dominant, n, m, not args.sequential, spec)
     achieved = ab / dur_s / 1e9
     traffic = read_traffic(dominant, args.workload)
-    sym = kernel_symbol(dominant, not args.sequential)
+    sym = kernel_symbol(dominant, not args.sequential, fused)
     rp_us = read_kernel_stats(args.workload + ("_sequential" if args.sequential else ""), sym)
     copy_bw = copy_bandwidth(dev)
     lds = lds_peak(dev)
@@ -362,6 +389,8 @@ def main(argv=None):
                                                    if lds_bytes else None)}},
         "replays": replays,
         "kernels_us": kernels_us,
+        "spread": ("fused with the forward slab transform (one x-plane per workgroup)" if fused
+                   else "mesh tiles, separate slab transform"),
         "step_model_bytes": step_bytes(n, m, not args.sequential),
     }
     if args.cell:
@@ -890,7 +919,8 @@ def traffic_summary(args) -> int:
     fetch = _counter_means(args.traffic_summary[0], "FETCH_SIZE")
     write = _counter_means(args.traffic_summary[1], "WRITE_SIZE")
     kind = args.kernel or "spread_tangent"
-    sym = kernel_symbol(kind, not args.sequential)
+    fused = any(FUSED_SYMBOL.get(kind, "?") in k for k in fetch)
+    sym = kernel_symbol(kind, not args.sequential, fused)
 
     def find(table, key):
         hits = [k for k in table if key in k]
@@ -937,7 +967,7 @@ def traffic_summary(args) -> int:
         fh.write(f"fetch_bytes_per_launch: {fb:.0f}\n")
         fh.write(f"write_bytes_per_launch: {wb:.0f}\n")
         fh.write(f"traffic_bytes_per_launch: {fb + wb:.0f}\n")
-        fh.write(f"alg_bytes_per_launch: {alg_bytes(kind, n, m)}\n")
+        fh.write(f"alg_bytes_per_launch: {alg_bytes(kind, n, m, True, spec_bytes(mesh) if fused else 0)}\n")
     print(open(out).read())
     return 0
 
@@ -1017,8 +1047,9 @@ def counter_summary(args) -> int:
         f"{'lds_MB':>7s} {'bank_cf':>7s} {'occ%':>5s} {'hbm_MB':>7s}",
     ]
     lds_lines = []
-    order = [KERNEL_SYMBOL[k] for k in ("bin", "bin_tangent", "spread", "spread_tangent",
-                                        "fft_r2c", "fft_x", "fft_c2r", "gather", "gather_hvp")]
+    order = [KERNEL_SYMBOL[k] for k in ("bin", "bin_tangent", "spread", "spread_tangent")]
+    order += [FUSED_SYMBOL[k] for k in ("spread", "spread_tangent")]
+    order += [KERNEL_SYMBOL[k] for k in ("fft_r2c", "fft_x", "fft_c2r", "gather", "gather_hvp")]
     for k in order:
         if k not in merged:
             continue
@@ -1069,7 +1100,8 @@ def kernel_stats_summary(args) -> int:
                 if ln.startswith("{") and '"kernels_us"' in ln:
                     d = json.loads(ln)
                     step = "pme_step" in d["config"].get("call", "")
-                    bench_us = {kernel_symbol(k, step): v for k, v in d["kernels_us"].items()}
+                    fz = "fft_r2c" not in d["kernels_us"]
+                    bench_us = {kernel_symbol(k, step, fz): v for k, v in d["kernels_us"].items()}
                     bench_val = (d["value"], d["unit"], d["roofline"]["kernel"],
                                  d["roofline"]["avg_launch_us"])
                     break

@@ -929,7 +929,7 @@ struct SpreadSlabArgs {
   int abuf;                // float2 words before the plane (the transform's first buffer)
   int nscan_max;           // bins a plane may scan
   int map_cap;             // slots of the item -> bin map
-  int hits_cap;            // entries of the hit list (>= 2 * blockDim)
+  int hits_cap;            // entries of the hit list (>= 2 kFusedSlotsPerThread blockDim)
 };
 
 template <int P, int DEG>
@@ -955,7 +955,10 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
   int* s_hits = reinterpret_cast<int*>(s_map + a.map_cap);
   __shared__ float s_J[DEG == 2 ? 9 : 1];
   __shared__ int s_nh;
+  __shared__ float s_cw[4 * P * P];           // whole-number spline pieces (x weights)
+  __shared__ int s_wsum[kSlabThreads / 64];   // per-wavefront sums of the scan
   Twiddles<kSlabThreads> tz, ty;
+  if (tid < 4 * P * P) s_cw[tid] = c_spline_whole.coef[spline_offset(P) + tid];
   tz.load(a.sl.twz, Nz);
   ty.load(a.sl.twy, Ny);
   if (DEG == 2 && tid == 0) {
@@ -995,22 +998,28 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
   const int pvol = a.PY * a.PZ;
   for (int e = tid; e < pvol; e += nthr) plane[e] = 0ull;
   __syncthreads();
-  // exclusive scan of the occupied slot counts (wavefront 0)
-  if (tid < 64) {
+  // exclusive scan of the occupied slot counts over the workgroup: consecutive
+  // segments per thread, wavefront prefix sums, then the wavefronts' totals
+  {
     const int len = nscan + 1;
-    const int seg = (len + 63) / 64;
+    const int seg = (len + nthr - 1) / nthr;
     const int s0 = min(tid * seg, len), s1 = min(s0 + seg, len);
     int acc = 0;
     for (int e = s0; e < s1; ++e) acc += s_off[e];
+    const int lane = tid & 63, wave = tid >> 6;
     int incl = acc;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int v = __shfl_up(incl, o, 64);
-      if (tid >= o) incl += v;
+      if (lane >= o) incl += v;
     }
-    int run = incl - acc;
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += s_wsum[w];
+    int run = before + incl - acc;
     for (int e = s0; e < s1; ++e) { const int v = s_off[e]; s_off[e] = run; run += v; }
-    if (tid == 63) s_off[len] = incl;
+    if (tid == nthr - 1) s_off[len] = before + incl;
   }
   __syncthreads();
   const int total = s_off[nscan + 1];
@@ -1058,19 +1067,12 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
     int ix = X - (pk & 1023) + lo;
     ix += (ix < 0) ? a.N[0] : 0;
     ix -= (ix >= a.N[0]) ? a.N[0] : 0;
-    // this plane's x weights (whole-number, times the fixed-point unit)
+    // this plane's x weights (whole-number, times the fixed-point unit): the
+    // column ix of spline_weights_whole, with the same Horner steps
     float x[D + 1];
-    {
-      float wx[D + 1][P];
-      spline_weights_whole<P, D>(h.x, wx);
+    weight_at_lds<P, D>(s_cw, ix, h.x, x);
 #pragma unroll
-      for (int d = 0; d <= D; ++d) {
-        float v = wx[d][0];
-#pragma unroll
-        for (int j = 1; j < P; ++j) v = (ix == j) ? wx[d][j] : v;
-        x[d] = v * scale;
-      }
-    }
+    for (int d = 0; d <= D; ++d) x[d] *= scale;
     // this x-plane's coefficients of the (y, z) derivative monomials
     float ax0, az1, az2 = 0.f, ay1, ay2 = 0.f, ayz = 0.f;
     if (DEG == 1) {
@@ -1109,27 +1111,38 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
     }
   };
 
-  // rounds of one scanned slot per thread: the anchors whose stencil covers the plane
-  // are listed; the list is drained (one atom per thread) when another round might
-  // not fit and after the last round
-  for (int r0 = 0; r0 < total; r0 += nthr) {
-    const int item = r0 + tid;
-    bool hit = false;
-    size_t ri = 0;
-    if (item < total) {
-      ri = record_of(item);
-      const int pk = __float_as_int(a.rec[ri * kRecWords + 3]);
-      int d = X - (pk & 1023) + lo;
-      d += (d < 0) ? a.N[0] : 0;
-      d -= (d >= a.N[0]) ? a.N[0] : 0;
-      hit = d < P;
+  // rounds of kSlotsPerThread scanned slots per thread (their anchor words loaded
+  // together): the atoms whose stencil covers the plane are listed; the list is
+  // drained (one atom per thread) when another round might not fit and after the
+  // last round
+  constexpr int U = kFusedSlotsPerThread;
+  for (int r0 = 0; r0 < total; r0 += U * nthr) {
+    size_t ri[U];
+    int pk[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int item = r0 + u * nthr + tid;
+      ri[u] = (item < total) ? record_of(item) : size_t(0);
     }
-    const int k = wave_compact(hit, &s_nh);
-    if (hit) s_hits[k] = int(ri);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      pk[u] = (r0 + u * nthr + tid < total) ? __float_as_int(a.rec[ri[u] * kRecWords + 3]) : -1;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      bool hit = false;
+      if (pk[u] >= 0) {
+        int d = X - (pk[u] & 1023) + lo;
+        d += (d < 0) ? a.N[0] : 0;
+        d -= (d >= a.N[0]) ? a.N[0] : 0;
+        hit = d < P;
+      }
+      const int k = wave_compact(hit, &s_nh);
+      if (hit) s_hits[k] = int(ri[u]);
+    }
     __syncthreads();
     const int nh = s_nh;
     __syncthreads();   // every thread has read the count before it changes
-    if (nh + nthr > a.hits_cap || r0 + nthr >= total) {
+    if (nh + U * nthr > a.hits_cap || r0 + U * nthr >= total) {
       for (int e = tid; e < nh; e += nthr) add_atom(size_t(uint32_t(s_hits[e])));
       if (tid == 0) s_nh = 0;
       __syncthreads();

@@ -166,25 +166,6 @@ __device__ __forceinline__ FastDiv make_fastdiv(int d) {
 //  3. Overflow records whose anchor lies in the tile, the same way.
 // Queue entries: the anchor header and, forward: q, mu, atom; Hessian-vector
 // product: q, mu, v_q, v_r, v_mu, atom (the tangent record carries them).
-// Weights of stencil point j (lane-dependent) for derivative orders 0..D, from an LDS
-// copy of the coefficients of N_P (an indexed constant table would be hoisted into
-// registers for the whole kernel).
-template <int P, int D>
-__device__ __forceinline__ void weight_at_lds(const float* tab, int j, float f, float (&w)[D + 1]) {
-  const int pc = P - 1 - j;
-#pragma unroll
-  for (int d = 0; d <= D; ++d) {
-    if (d > P - 1) {
-      w[d] = 0.0f;
-      continue;
-    }
-    const float* c = &tab[(d * P + pc) * P];
-    float acc = c[P - 1];
-#pragma unroll
-    for (int k = P - 2; k >= d; --k) acc = fmaf(acc, f, c[k]);
-    w[d] = acc;
-  }
-}
 
 // What the queue needs of a record: the anchor header and, forward: q, mu, atom;
 // Hessian-vector product: (q, mu), (v_q, v_r), (v_mu, atom).

@@ -64,7 +64,8 @@ constexpr int kFFTThreads = 256;    // pencil-pass workgroup
 constexpr int kSlabThreads = 1024;  // slab-pass workgroup (one x-plane)
 constexpr int kSlabLdsMax = 160 * 1024 - 2048;
 constexpr int kFusedMap = 4096;     // item -> bin map slots of a fused spread-slab workgroup
-constexpr int kFusedHits = 2048;    // its hit list (two rounds of one slot per thread)
+constexpr int kFusedSlotsPerThread = 4;   // scanned slots per thread and round
+constexpr int kFusedHits = 2 * kFusedSlotsPerThread * kSlabThreads;   // its hit list (two rounds)
 
 struct DevPlan {
   int N[3];                // mesh dims

@@ -266,6 +266,27 @@ __device__ __forceinline__ float from_fixed(long long v, double inv_scale) {
   return float(vd * inv_scale);
 }
 
+// Weights of stencil point j (lane-dependent) for derivative orders 0..D, from an LDS
+// copy of the coefficients of N_P (or of its whole-number table); the same Horner
+// steps as spline_weights, so the values are the same bit for bit (an indexed
+// constant table would be hoisted into registers for the whole kernel).
+template <int P, int D>
+__device__ __forceinline__ void weight_at_lds(const float* tab, int j, float f, float (&w)[D + 1]) {
+  const int pc = P - 1 - j;
+#pragma unroll
+  for (int d = 0; d <= D; ++d) {
+    if (d > P - 1) {
+      w[d] = 0.0f;
+      continue;
+    }
+    const float* c = &tab[(d * P + pc) * P];
+    float acc = c[P - 1];
+#pragma unroll
+    for (int k = P - 2; k >= d; --k) acc = fmaf(acc, f, c[k]);
+    w[d] = acc;
+  }
+}
+
 // m mod N in [0, N) for any int m
 __device__ __forceinline__ int wrapn(int m, int N) {
   m %= N;
