@@ -31,7 +31,7 @@ namespace {
 
 // Transform npen pencils (stride ps) held in x by stages [s0, s1) of the plan (all
 // by default); returns the buffer holding the result.
-__device__ float2* lds_fft(float2* x, float2* y, int npen, int ps, const AxisPlan& ax,
+__device__ __forceinline__ float2* lds_fft(float2* x, float2* y, int npen, int ps, const AxisPlan& ax,
                            const float2* tw, float s, int s0 = 0, int s1 = -1) {
   if (s1 < 0) s1 = ax.nst;
   for (int sti = s0; sti < s1; ++sti) {
@@ -958,7 +958,8 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
   __shared__ float s_cw[4 * P * P];           // whole-number spline pieces (x weights)
   __shared__ int s_wsum[kSlabThreads / 64];   // per-wavefront sums of the scan
   Twiddles<kSlabThreads> tz, ty;
-  if (tid < 4 * P * P) s_cw[tid] = c_spline_whole.coef[spline_offset(P) + tid];
+  constexpr int kTab = spline_offset(P);
+  if (tid < 4 * P * P) s_cw[tid] = c_spline_whole.coef[kTab + tid];
   tz.load(a.sl.twz, Nz);
   ty.load(a.sl.twy, Ny);
   if (DEG == 2 && tid == 0) {

@@ -4,8 +4,9 @@ the separate slab transform (PME_F_SEPARATE_SPREAD): every output of pme_forward
 pme_backward and the concurrent pme_step must be bitwise equal, since both add the
 same 64-bit fixed-point contributions and transform the same density.  The cases
 cover orders 4-7, odd, ragged and non-cubic meshes, a sheared cell, the benchmark
-box, a clustered box whose bins overflow, and a dense box whose scanned slots
-exceed the item map (binary search).  Parity with the oracle of the fused path
+box, a clustered box whose bins overflow, a dense box whose scanned slots exceed
+the item map (binary search), and a crowded box whose planes hold more atoms than
+the hit list (drained in batches).  Parity with the oracle of the fused path
 itself is checked by the PME tests, which use default plans."""
 import numpy as np
 import pytest
@@ -24,6 +25,13 @@ def _frame(case):
         pos = rng.uniform(0.0, 6.0, (n, 3))   # one corner: bins far over capacity
         q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
         return synth.Frame(pos=pos, q=q, mu=rng.normal(0, 0.1, (n, 3)), box=np.eye(3) * L)
+    if case == "crowded":
+        rng = np.random.default_rng(6)
+        n, L = 12000, 24.0
+        pos = rng.uniform(0.0, L, (n, 3))
+        pos[:, 0] = rng.uniform(0.0, 1.5, n)   # a few x-planes hold every atom
+        q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+        return synth.Frame(pos=pos, q=q, mu=rng.normal(0, 0.1, (n, 3)), box=np.eye(3) * L)
     if case == "sheared":
         f = synth.molten_box(1200, 8, L=32.0)
         box = f.box.copy()
@@ -39,7 +47,8 @@ def _frame(case):
 
 CASES = [("small", (24, 24, 24), 6), ("ragged", (30, 36, 40), 5), ("p7", (40, 40, 40), 7),
          ("p4", (20, 24, 30), 4), ("sheared", (27, 30, 32), 6), ("clustered", (24, 24, 24), 6),
-         ("dense", (48, 48, 48), 6), ("8k", (64, 64, 64), 6), ("32k", (100, 100, 100), 6)]
+         ("dense", (48, 48, 48), 6), ("crowded", (24, 24, 24), 6), ("8k", (64, 64, 64), 6),
+         ("32k", (100, 100, 100), 6)]
 
 
 @pytest.mark.parametrize("case,mesh,p", CASES, ids=[c[0] for c in CASES])
