@@ -81,6 +81,7 @@ struct pme_plan_s {
   hipStream_t aux = nullptr;
   hipEvent_t fork = nullptr;
   hipEvent_t join = nullptr;
+  hipEvent_t binned = nullptr;   // pme_step with plane spreads: the one binning is done
   // pme_step_capture: the capture stream, the graph of the captured steps and the
   // counter sets (set, tset) the graph starts from
   hipStream_t cap = nullptr;
@@ -351,12 +352,13 @@ void free_plan(pme_plan_s* pl) {
   if (pl->concurrent) {
     DevPlan& t = pl->dt;
     void* own[] = {t.count[0], t.count[1], t.ovf_count[0], t.ovf_count[1], t.cmax[0], t.cmax[1],
-                   t.rec, t.rho, t.spec};
+                   t.rec, t.rho, t.spec, t.cmax_fwd[0], t.cmax_fwd[1]};
     for (void* p : own)
       if (p) (void)hipFree(p);
   }
   if (pl->fork) (void)hipEventDestroy(pl->fork);
   if (pl->join) (void)hipEventDestroy(pl->join);
+  if (pl->binned) (void)hipEventDestroy(pl->binned);
   if (pl->aux) (void)hipStreamDestroy(pl->aux);
   DevPlan& d = pl->d;
   void* ptrs[] = {d.count[0], d.count[1], d.ovf_count[0], d.ovf_count[1], d.cmax[0],
@@ -535,6 +537,7 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
       ok(dev_alloc(&t.count[k], size_t(nbins), by));
       ok(dev_alloc(&t.ovf_count[k], 1, by));
       ok(dev_alloc(&t.cmax[k], 1, by));
+      ok(dev_alloc(&t.cmax_fwd[k], 1, by));
     }
     ok(dev_alloc(&t.rec, (size_t(t.ovf_base) + size_t(desc->max_atoms)) * 16, by));
     ok(dev_alloc(&t.rho, size_t(M), by));
@@ -543,10 +546,12 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
       ok(hipMemset(t.count[k], 0, sizeof(int) * nbins));
       ok(hipMemset(t.ovf_count[k], 0, sizeof(int)));
       ok(hipMemset(t.cmax[k], 0, sizeof(unsigned)));
+      ok(hipMemset(t.cmax_fwd[k], 0, sizeof(unsigned)));
     }
     ok(hipStreamCreateWithFlags(&pl->aux, hipStreamNonBlocking));
     ok(hipEventCreateWithFlags(&pl->fork, hipEventDisableTiming));
     ok(hipEventCreateWithFlags(&pl->join, hipEventDisableTiming));
+    ok(hipEventCreateWithFlags(&pl->binned, hipEventDisableTiming));
   }
   if (d.slab) ok(pme::enable_slab_lds(d.slab_lds));
   ok(pme::enable_spread_lds());
@@ -728,6 +733,38 @@ int pme_step(pme_plan_t plan, void* stream, int32_t n, const float* pos, const f
   pme::KTimer& tm = plan->timer;
   hipError_t e;
   mark_phi(plan, false);
+  if (d.fused) {
+    // One binning for both densities and the gather: the cotangent binning (its
+    // records carry q and mu; it also forms the forward coefficients' largest sum and
+    // the self-term sums) on the second stream, then the cotangent chain there; the
+    // forward plane spread reads the same records once they are written.
+    const int tset = plan->tset;
+    plan->tset ^= 1;
+    if ((e = hipEventRecord(plan->fork, s)) != hipSuccess) return hip_fail(e);
+    if ((e = hipStreamWaitEvent(s2, plan->fork, 0)) != hipSuccess) return hip_fail(e);
+    if ((e = pme::launch_bin(dt, s2, tset, n, pos, q, mu, box, v_pos, v_q, v_mu, true,
+                             energy != nullptr, tm.next(PME_K_BIN_TANGENT), true)) != hipSuccess)
+      return hip_fail(e);
+    if ((e = hipEventRecord(plan->binned, s2)) != hipSuccess) return hip_fail(e);
+    if ((e = spread_convolve(dt, s2, tset, true, box, dt.rho, false, tm)) != hipSuccess)
+      return hip_fail(e);
+    if ((e = hipStreamWaitEvent(s, plan->binned, 0)) != hipSuccess) return hip_fail(e);
+    const pme::RecordSource src{&dt, tset, dt.cmax_fwd[tset]};
+    if ((e = pme::launch_spread_slab(d, s, 0, false, box, tm.next(PME_K_SPREAD), &src)) !=
+        hipSuccess)
+      return hip_fail(e);
+    if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm, nullptr, true)) !=
+        hipSuccess)
+      return hip_fail(e);
+    if ((e = hipEventRecord(plan->join, s2)) != hipSuccess) return hip_fail(e);
+    if ((e = hipStreamWaitEvent(s, plan->join, 0)) != hipSuccess) return hip_fail(e);
+    const pme::GatherForward fwd{energy, dE_dpos, dE_dq, dE_dmu, pme::bin_blocks(n)};
+    if ((e = pme::launch_gather_hvp(dt, s, tset, n, pos, q, mu, box, v_pos, v_q, v_mu, g_pos,
+                                    g_q, g_mu, tm.next(PME_K_GATHER_HVP), &fwd)) != hipSuccess)
+      return hip_fail(e);
+    mark_phi(plan, true);
+    return PME_OK;
+  }
   const int set = plan->set;
   plan->set ^= 1;
   const int tset = plan->tset;

@@ -932,9 +932,13 @@ struct SpreadSlabArgs {
   int hits_cap;            // entries of the hit list (>= 2 kFusedSlotsPerThread blockDim)
 };
 
-template <int P, int DEG>
+// TREC: the records are tangent records (q, mu, v_q, v_r, v_mu) and the density is
+// the forward one (DEG 1): its coefficients q, J mu are formed from them as the
+// forward binning forms them.
+template <int P, int DEG, bool TREC>
 __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const int X,
                                                  const double* box) {
+  static_assert(!TREC || DEG == 1, "tangent records serve the forward density");
   constexpr int NC = (DEG == 1) ? 4 : 10;
   constexpr int D = (DEG == 1) ? 1 : 2;       // highest weight derivative needed
   constexpr int lo = (P - 1) / 2;
@@ -953,7 +957,7 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
   int* s_bin = s_off + a.nscan_max + 2;
   uint16_t* s_map = reinterpret_cast<uint16_t*>(s_bin + a.nscan_max + 2);
   int* s_hits = reinterpret_cast<int*>(s_map + a.map_cap);
-  __shared__ float s_J[DEG == 2 ? 9 : 1];
+  __shared__ float s_J[(DEG == 2 || TREC) ? 9 : 1];
   __shared__ int s_nh;
   __shared__ float s_cw[4 * P * P];           // whole-number spline pieces (x weights)
   __shared__ int s_wsum[kSlabThreads / 64];   // per-wavefront sums of the scan
@@ -962,7 +966,7 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
   if (tid < 4 * P * P) s_cw[tid] = c_spline_whole.coef[kTab + tid];
   tz.load(a.sl.twz, Nz);
   ty.load(a.sl.twy, Ny);
-  if (DEG == 2 && tid == 0) {
+  if ((DEG == 2 || TREC) && tid == 0) {
     float J[3][3];
     jacobian(cell_from_box(box), a.N, J);
 #pragma unroll
@@ -1060,6 +1064,12 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
       for (int i = 0; i < 9; ++i) Jt[i / 3][i % 3] = s_J[i];
       tangent_coeffs(Jt, c0v.x, make_float3(c0v.y, c0v.z, c0v.w), c1v.x,
                      make_float3(c1v.y, c1v.z, c1v.w), make_float3(f[12], f[13], f[14]), co);
+    } else if constexpr (TREC) {
+      float Jt[3][3];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Jt[i / 3][i % 3] = s_J[i];
+      const float3 d = jmul(Jt, make_float3(c0v.y, c0v.z, c0v.w));
+      co[0] = c0v.x; co[1] = d.x; co[2] = d.y; co[3] = d.z;
     } else {
       co[0] = c0v.x; co[1] = c0v.y; co[2] = c0v.z; co[3] = c0v.w;
     }
@@ -1166,9 +1176,9 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
   slab_fwd_run(a.sl, X, value, tz, ty, twz, twy, A, B);
 }
 
-template <int P, int DEG>
+template <int P, int DEG, bool TREC>
 __global__ void __launch_bounds__(kSlabThreads) k_spread_slab(SpreadSlabArgs a, const double* box) {
-  spread_slab_body<P, DEG>(a, xcd_item(blockIdx.x, gridDim.x), box);
+  spread_slab_body<P, DEG, TREC>(a, xcd_item(blockIdx.x, gridDim.x), box);
 }
 
 }  // namespace
@@ -1329,14 +1339,18 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
 }
 
 hipError_t launch_spread_slab(const DevPlan& d, hipStream_t s, int set, bool tangent,
-                              const double* box, const LaunchEvents* ev) {
-  if (!d.fused) return hipErrorInvalidValue;
+                              const double* box, const LaunchEvents* ev, const RecordSource* from) {
+  if (!d.fused || (from && (tangent || !from->d || !from->cmax))) return hipErrorInvalidValue;
   SpreadSlabArgs a;
   a.sl = make_slab_args(d, nullptr);
   for (int k = 0; k < 3; ++k) { a.N[k] = d.N[k]; a.B[k] = d.B[k]; a.nb[k] = d.nb[k]; }
-  a.cap = d.cap;
-  a.count = d.count[set]; a.ovf_count = d.ovf_count[set]; a.cmax = d.cmax[set];
-  a.rec = d.rec; a.ovf_base = d.ovf_base;
+  // the bins (same geometry in both views of a plan) and the scale
+  const DevPlan& r = from ? *from->d : d;
+  const int rs = from ? from->set : set;
+  a.cap = r.cap;
+  a.count = r.count[rs]; a.ovf_count = r.ovf_count[rs];
+  a.cmax = from ? from->cmax : d.cmax[set];
+  a.rec = r.rec; a.ovf_base = r.ovf_base;
   a.PY = d.N[1] + d.p - 1;
   a.PZ = d.N[2] + d.p - 1;
   a.abuf = d.fused_abuf;
@@ -1345,10 +1359,11 @@ hipError_t launch_spread_slab(const DevPlan& d, hipStream_t s, int set, bool tan
   a.hits_cap = kFusedHits;
   const dim3 g(d.N[0]), b(kSlabThreads);
   const size_t sh = d.fused_lds;
-#define PME_F(P)                                                            \
-  case P:                                                                   \
-    if (tangent) launch_k(ev, k_spread_slab<P, 2>, g, b, sh, s, a, box);    \
-    else launch_k(ev, k_spread_slab<P, 1>, g, b, sh, s, a, box);            \
+#define PME_F(P)                                                                   \
+  case P:                                                                          \
+    if (tangent) launch_k(ev, k_spread_slab<P, 2, false>, g, b, sh, s, a, box);     \
+    else if (from) launch_k(ev, k_spread_slab<P, 1, true>, g, b, sh, s, a, box);    \
+    else launch_k(ev, k_spread_slab<P, 1, false>, g, b, sh, s, a, box);             \
     break;
   switch (d.p) {
     PME_F(1) PME_F(2) PME_F(3) PME_F(4) PME_F(5) PME_F(6) PME_F(7)
@@ -1367,8 +1382,9 @@ hipError_t enable_slab_lds(size_t bytes) {
                        reinterpret_cast<const void*>(k_slab_fwd_batch),
                        reinterpret_cast<const void*>(k_slab_inv_batch),
 #define PME_F(P)                                                   \
-  reinterpret_cast<const void*>(k_spread_slab<P, 1>),              \
-      reinterpret_cast<const void*>(k_spread_slab<P, 2>),
+  reinterpret_cast<const void*>(k_spread_slab<P, 1, false>),       \
+      reinterpret_cast<const void*>(k_spread_slab<P, 1, true>),    \
+      reinterpret_cast<const void*>(k_spread_slab<P, 2, false>),
                        PME_F(1) PME_F(2) PME_F(3) PME_F(4) PME_F(5) PME_F(6) PME_F(7)
 #undef PME_F
   };

@@ -123,6 +123,9 @@ struct DevPlan {
   double* vpart;           // cell gradient: [6 per x-pass block] then [9 per tile]
   double* escr;            // [3] energy of a cell-gradient call that asks for none
   int* status;             // bit 0: non-finite input seen
+  // the cotangent view of a concurrent plan: the largest forward coefficient sum of
+  // each counter set's records, for the forward plane spread of pme_step
+  unsigned* cmax_fwd[2];
 };
 
 // Events into which a launch records its kernel's own begin and end timestamps
@@ -239,10 +242,13 @@ inline int bin_blocks(int n) { return n > 0 ? (n + 255) / 256 : 1; }
 
 // Binning: stencil anchor, bin slot, per-atom record (forward: q and the x-space
 // dipole; tangent: the 10 monomial coefficients of the tangent density).
+// fwd_max (tangent binning of a concurrent step): also the largest forward
+// coefficient sum into d.cmax_fwd[set], so that the forward plane spread can read
+// these records.
 hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                       const float* q, const float* mu, const double* box, const float* v_pos,
                       const float* v_q, const float* v_mu, bool tangent, bool self_sums,
-                      const LaunchEvents* ev);
+                      const LaunchEvents* ev, bool fwd_max = false);
 // Owner-computes spread of the binned records (counter set `set`) into d.rho.
 hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
                          const double* box, const LaunchEvents* ev);
@@ -267,9 +273,18 @@ hipError_t launch_gather_quad(const DevPlan& d, hipStream_t s, int set, int n, c
 hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, float* out,
                            bool energy, KTimer* tm, double* vpart = nullptr,
                            bool from_spec = false);
-// Spread fused with the forward slab transform (d.fused): writes d.spec directly
+// Spread fused with the forward slab transform (d.fused): writes d.spec directly.
+// from: the binned records and fixed-point scale to read instead of d's own (the
+// forward density of pme_step from the cotangent binning: tangent records, which
+// carry q and mu, and its cmax_fwd)
+struct RecordSource {
+  const DevPlan* d;   // counts, records, overflow list
+  int set;
+  const unsigned* cmax;
+};
 hipError_t launch_spread_slab(const DevPlan& d, hipStream_t s, int set, bool tangent,
-                              const double* box, const LaunchEvents* ev);
+                              const double* box, const LaunchEvents* ev,
+                              const RecordSource* from = nullptr);
 // Raise the dynamic LDS limit of the spread (kBigLds) and gather (kGatherLds) kernels.
 hipError_t enable_spread_lds();
 hipError_t enable_gather_lds();

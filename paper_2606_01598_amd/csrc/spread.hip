@@ -53,6 +53,10 @@ struct BinArgs {
   int* count_other;    // the other set, cleared here
   int* ovf_other;
   unsigned* cmax_other;
+  // tangent binning of a concurrent step: also the largest forward coefficient sum
+  // |q| + |J mu|_1 (the forward plane spread reads these records), and its other set
+  unsigned* cmax_fwd;
+  unsigned* cmax_fwd_other;
   int nbins;
   float* rec;
   long long ovf_base;      // record index of the overflow list
@@ -85,7 +89,7 @@ __device__ __forceinline__ void quad_coeffs(const float (&J)[3][3], const float 
 template <int P, bool TANGENT, bool QUAD = false>
 __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
   __shared__ double red[8];
-  __shared__ unsigned s_wmax[4];
+  __shared__ unsigned s_wmax[8];
   const int i = blk * 256 + threadIdx.x;
   const bool live = i < a.n;
   // every per-atom input is loaded first, so that their latencies overlap with
@@ -108,7 +112,7 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
   }
   const Cell c = cell_from_box(a.box);
   double sq = 0.0, smu = 0.0, sqt = 0.0, stt = 0.0;
-  float amax = 0.0f;
+  float amax = 0.0f, fmax = 0.0f;
   if (live) {
     int base[3];
     float f[3];
@@ -143,6 +147,13 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
       if (!isfinite(amax)) {
         atomicOr(a.status, 1);
         amax = 0.0f;
+      }
+      if (TANGENT && a.cmax_fwd) {
+        // the forward binning's sum of the same atom (q, J mu)
+        const float c4[4] = {q, d.x, d.y, d.z};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) fmax += fabsf(c4[k]);
+        if (!isfinite(fmax)) fmax = 0.0f;
       }
       // every atom takes one slot of its bin or of the overflow list (which holds
       // max_atoms records)
@@ -180,6 +191,7 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
   if (blk == 0 && threadIdx.x == 0) {
     *a.ovf_other = 0;
     *a.cmax_other = 0u;
+    if (TANGENT && a.cmax_fwd_other) *a.cmax_fwd_other = 0u;
   }
   // the largest coefficient sum: wavefront maxima, then the workgroup's (the sums
   // are non-negative, so their float bits order as unsigned integers)
@@ -187,12 +199,22 @@ __device__ __forceinline__ void bin_body(const BinArgs& a, const int blk) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) um = max(um, unsigned(__shfl_xor(int(um), o, 64)));
   if ((threadIdx.x & 63) == 0) s_wmax[threadIdx.x >> 6] = um;
+  if (TANGENT && a.cmax_fwd) {
+    unsigned uf = __float_as_uint(fmax);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) uf = max(uf, unsigned(__shfl_xor(int(uf), o, 64)));
+    if ((threadIdx.x & 63) == 0) s_wmax[4 + (threadIdx.x >> 6)] = uf;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned m = max(max(s_wmax[0], s_wmax[1]), max(s_wmax[2], s_wmax[3]));
     if (m) atomicMax(a.cmax, m);
+    if (TANGENT && a.cmax_fwd) {
+      const unsigned mf = max(max(s_wmax[4], s_wmax[5]), max(s_wmax[6], s_wmax[7]));
+      if (mf) atomicMax(a.cmax_fwd, mf);
+    }
   }
-  if (!TANGENT && a.spart) {
+  if (a.spart) {
     const double s1 = block_sum(sq, red);
     const double s2 = block_sum(smu, red);
     if (threadIdx.x == 0) {
@@ -741,6 +763,8 @@ BinArgs make_bin_args(const DevPlan& d, int set, int n, const float* pos, const 
   a.count = d.count[set]; a.ovf_count = d.ovf_count[set]; a.cmax = d.cmax[set];
   a.count_other = d.count[1 - set]; a.ovf_other = d.ovf_count[1 - set];
   a.cmax_other = d.cmax[1 - set];
+  a.cmax_fwd = nullptr;
+  a.cmax_fwd_other = nullptr;
   a.nbins = d.nb[0] * d.nb[1] * d.nb[2];
   a.rec = d.rec; a.ovf_base = d.ovf_base;
   a.spart = self_sums ? d.spart : nullptr;
@@ -836,8 +860,13 @@ hipError_t upload(void** dst, const void* src, size_t bytes) {
 hipError_t launch_bin(const DevPlan& d, hipStream_t s, int set, int n, const float* pos,
                       const float* q, const float* mu, const double* box, const float* v_pos,
                       const float* v_q, const float* v_mu, bool tangent, bool self_sums,
-                      const LaunchEvents* ev) {
-  const BinArgs a = make_bin_args(d, set, n, pos, q, mu, box, v_pos, v_q, v_mu, self_sums);
+                      const LaunchEvents* ev, bool fwd_max) {
+  BinArgs a = make_bin_args(d, set, n, pos, q, mu, box, v_pos, v_q, v_mu, self_sums);
+  if (tangent && fwd_max) {
+    if (!d.cmax_fwd[0] || !d.cmax_fwd[1]) return hipErrorInvalidValue;
+    a.cmax_fwd = d.cmax_fwd[set];
+    a.cmax_fwd_other = d.cmax_fwd[1 - set];
+  }
   const dim3 g(bin_blocks(n));
   return tangent ? bin_dispatch<true>(d.p, g, s, a, ev) : bin_dispatch<false>(d.p, g, s, a, ev);
 }
