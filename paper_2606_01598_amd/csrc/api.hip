@@ -352,7 +352,7 @@ void free_plan(pme_plan_s* pl) {
   if (pl->concurrent) {
     DevPlan& t = pl->dt;
     void* own[] = {t.count[0], t.count[1], t.ovf_count[0], t.ovf_count[1], t.cmax[0], t.cmax[1],
-                   t.rec, t.rho, t.spec, t.cmax_fwd[0], t.cmax_fwd[1]};
+                   t.rec, t.rho, t.spec, t.cmax_fwd[0], t.cmax_fwd[1], t.gcache, t.gkey};
     for (void* p : own)
       if (p) (void)hipFree(p);
   }
@@ -365,7 +365,7 @@ void free_plan(pme_plan_s* pl) {
                   d.cmax[1], d.rec, d.twiddle[0], d.twiddle[1], d.twiddle[2],
                   d.deconv[0], d.deconv[1], d.deconv[2], d.rho, d.spec, d.phi, d.epart,
                   d.spart, d.vpart, d.escr, d.status, d.alias[0], d.alias[1], d.alias[2],
-                  d.gcache, d.gbox, d.gvalid};
+                  d.gcache, d.gkey};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete pl;
@@ -467,11 +467,9 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
     ok(dev_alloc(&d.deconv[a], size_t(d.N[a]), by));
     if (d.opt) ok(dev_alloc(&d.alias[a], size_t(3 * d.N[a]), by));
   }
-  if (d.opt) {
-    ok(dev_alloc(&d.gcache, size_t(d.N[0]) * d.N[1] * d.H, by));
-    ok(dev_alloc(&d.gbox, 9, by));
-    ok(dev_alloc(&d.gvalid, 1, by));
-  }
+  const size_t xblocks = size_t(pme::fftx_blocks(d));
+  ok(dev_alloc(&d.gcache, xblocks * d.N[0] * d.ktile, by));
+  ok(dev_alloc(&d.gkey, 9 * xblocks, by));
   ok(dev_alloc(&d.rho, size_t(M), by));
   ok(dev_alloc(&d.spec, size_t(d.N[0]) * d.N[1] * d.H, by));
   ok(dev_alloc(&d.phi, size_t(M), by));
@@ -521,7 +519,7 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
     ok(hipMemset(d.cmax[k], 0, sizeof(unsigned)));
   }
   ok(hipMemset(d.status, 0, sizeof(int)));
-  if (d.gvalid) ok(hipMemset(d.gvalid, 0, sizeof(int)));
+  ok(hipMemset(d.gkey, 0xff, sizeof(double) * 9 * xblocks));   // NaN: no table made yet
   ok(hipMemset(d.phi, 0, sizeof(float) * M));
   if (e == hipSuccess && (desc->flags & PME_F_CONCURRENT)) {
     pl->concurrent = true;
@@ -533,6 +531,8 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
     t.rec = nullptr;
     t.rho = nullptr;
     t.spec = nullptr;
+    t.gcache = nullptr;
+    t.gkey = nullptr;
     for (int k = 0; k < 2; ++k) {
       ok(dev_alloc(&t.count[k], size_t(nbins), by));
       ok(dev_alloc(&t.ovf_count[k], 1, by));
@@ -542,6 +542,11 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
     ok(dev_alloc(&t.rec, (size_t(t.ovf_base) + size_t(desc->max_atoms)) * 16, by));
     ok(dev_alloc(&t.rho, size_t(M), by));
     ok(dev_alloc(&t.spec, size_t(d.N[0]) * d.N[1] * d.H, by));
+    // the cotangent chain's x passes keep their own g tables: the two chains' passes
+    // run at the same time
+    ok(dev_alloc(&t.gcache, xblocks * d.N[0] * d.ktile, by));
+    ok(dev_alloc(&t.gkey, 9 * xblocks, by));
+    if (e == hipSuccess) ok(hipMemset(t.gkey, 0xff, sizeof(double) * 9 * xblocks));
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
       ok(hipMemset(t.count[k], 0, sizeof(int) * nbins));
       ok(hipMemset(t.ovf_count[k], 0, sizeof(int)));

@@ -507,10 +507,9 @@ struct XArgs {
   const float* alx;
   const float* aly;
   const float* alz;
-  // and the cache of g for an unchanged box ([N_y][N_x][H]; see DevPlan)
+  // the per-workgroup cache of g and its keys (DevPlan::gcache, gkey; may be null)
   float* gcache;
-  const double* gbox;
-  const int* gvalid;
+  double* gkey;
 };
 
 __device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) / 2) ? k - N : k; }
@@ -520,9 +519,11 @@ __device__ __forceinline__ int signed_freq(int k, int N) { return (k >= (N + 1) 
 //   g(k) = (4 pi / k^2) exp(-k^2 / (4 alpha^2)) dcx(kx) dcy(ky) dcz(kz),
 //   k^2 = f^T M f, M = 4 pi^2 C^-1 C^-T (reciprocal metric), f = signed frequencies;
 // g is 0 at k = 0; a Nyquist bin takes the mean of g over the bin and its Hermitian
-// partner.  g is tabulated for the workgroup's points while the line loads are in
-// flight; the product itself sits between the last forward and the first inverse
-// stage, in registers (x_middle).
+// partner.  g depends on the box only (the mesh, order, alpha and influence are the
+// plan's): a workgroup keeps its table in the plan's cache, with the box as key, and
+// when the key equals the box it loads the table with the lines instead of making it.
+// Otherwise g is tabulated while the line loads are in flight.  The product itself
+// sits between the last forward and the first inverse stage, in registers (x_middle).
 // MODE 0: the influence function of Eq. influence; 1: the same, also forming the
 // cell-gradient partials; 2: the optimal influence function (aliasing sums).
 template <int MODE = 0>
@@ -566,6 +567,19 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
       const float* src = (i < 3 * Nx) ? a.alx + i
                                       : a.alz + min(m, 2) * Nz + min(kz0 + l, H - 1);
       alv[k] = *src;
+    }
+  }
+  // the workgroup's cached g table, loaded before the lines whether or not its key
+  // matches (the decision waits for the key; the loads need not)
+  const int KN = Nx * kt;
+  float* gblk = a.gcache ? a.gcache + size_t(blk) * KN : nullptr;
+  constexpr int GU = 14;   // Nx kt <= GU blockDim (the plan bounds kt (Nx + 1) by 3500)
+  float gv[GU];
+  if (gblk) {
+#pragma unroll
+    for (int k = 0; k < GU; ++k) {
+      const int e = int(threadIdx.x) + k * int(blockDim.x);
+      gv[k] = (e < KN) ? gblk[e] : 0.0f;
     }
   }
   auto store_dc = [&]() {
@@ -617,14 +631,9 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
       return float(4.0 * M_PI / k2) * expf(-float(k2 * inv4a2));
     };
     float aly3[3] = {0.0f, 0.0f, 0.0f};
-    // OPT: g from the cache when it holds this box (a uniform decision)
-    bool cached = false;
     if constexpr (OPT) {
 #pragma unroll
       for (int m = 0; m < 3; ++m) aly3[m] = a.aly[m * Ny + y];
-      cached = *a.gvalid != 0;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) cached = cached && a.gbox[k] == box[k];
     }
     for (int e = threadIdx.x; e < Nx * kt; e += blockDim.x) {
       const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
@@ -635,7 +644,6 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
         const bool nx = ((Nx & 1) == 0) && (2 * xx == Nx);
         const bool nz = ((Nz & 1) == 0) && (2 * kz == Nz);
         if constexpr (OPT) {
-          float* gc = a.gcache + (size_t(y) * Nx + xx) * H + kz;
           // sum over the aliases f + m N of U^2 G; a partner frequency s f (s = -1 on
           // the flipped axes) takes the weight of alias -m of f, as sinc is even
           auto gopt = [&](int sx, int sy, int sz) {
@@ -656,14 +664,9 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
             }
             return num;
           };
-          if (cached) {
-            g = *gc;
-          } else {
-            g = gopt(1, 1, 1);
-            if (nx || nyq_y || nz) g = 0.5f * (g + gopt(nx ? 1 : -1, nyq_y ? 1 : -1, nz ? 1 : -1));
-            g *= s_dc[xx] * dcy * s_dc[Nx + l];
-            *gc = g;
-          }
+          g = gopt(1, 1, 1);
+          if (nx || nyq_y || nz) g = 0.5f * (g + gopt(nx ? 1 : -1, nyq_y ? 1 : -1, nz ? 1 : -1));
+          g *= s_dc[xx] * dcy * s_dc[Nx + l];
         } else {
           g = gk(fx, fy, fz);
           if (nx || nyq_y || nz)   // Hermitian partner: the non-Nyquist components change sign
@@ -672,6 +675,30 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
         }
       }
       s_g[l * Nx + xx] = g;
+      if (gblk) gblk[e] = g;
+    }
+  };
+  // the g table into LDS: from the cache when the block's key is this box (a uniform
+  // decision), else made (and cached with its key)
+  auto gfill = [&]() {
+    bool cached = gblk != nullptr;
+    if (cached) {
+      const double* key = a.gkey + size_t(blk) * 9;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) cached = cached && key[k] == box[k];
+    }
+    if (cached) {
+#pragma unroll
+      for (int k = 0; k < GU; ++k) {
+        const int e = int(threadIdx.x) + k * int(blockDim.x);
+        if (e < KN) {
+          const int xx = int(fdiv(uint32_t(e), a.ktd)), l = e - xx * kt;
+          s_g[l * Nx + xx] = gv[k];
+        }
+      }
+    } else {
+      gtable();
+      if (gblk && threadIdx.x < 9) a.gkey[size_t(blk) * 9 + threadIdx.x] = box[threadIdx.x];
     }
   };
   const int last = a.ax.nst - 1;
@@ -697,7 +724,7 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
         for (int r = 0; r < Rr; ++r) v[r] = base[size_t(jc + r * x0.NR) * xstride + kc];
       }
       store_dc();
-      gtable();
+      gfill();
       if (act) {
         if (kz >= H) {
 #pragma unroll
@@ -725,7 +752,7 @@ __device__ __forceinline__ void fftx_body(const XArgs& a, const int blk, const d
       }
     }
     store_dc();
-    gtable();
+    gfill();
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int e = threadIdx.x + u * kFFTThreads;
@@ -861,15 +888,6 @@ __global__ void __launch_bounds__(kSlabThreads) k_slab_inv(SlabArgs a) {
 template <int MODE>
 __global__ void __launch_bounds__(kFFTThreads) k_fftx_fused(XArgs a) {
   fftx_body<MODE>(a, xcd_item(blockIdx.x, gridDim.x), a.box, a.epart);
-}
-
-// After an optimal-influence x pass (every workgroup has written or read the g of
-// its points): the cache now holds g of this box.  A concurrent x pass of the same
-// box that reads the new key reads a complete table, one that reads the old key
-// recomputes the same values.
-__global__ void k_gcache_commit(const double* box, double* gbox, int* gvalid) {
-  if (threadIdx.x < 9) gbox[threadIdx.x] = box[threadIdx.x];
-  if (threadIdx.x == 0) *gvalid = 1;
 }
 
 // Batched passes: work item (box, x-plane) or (box, x-pass workgroup); per-box
@@ -1196,7 +1214,7 @@ XArgs make_x_args(const DevPlan& d, const double* box, bool energy) {
   x.epart = energy ? d.epart : nullptr;
   x.vpart = nullptr;
   x.alx = d.alias[0]; x.aly = d.alias[1]; x.alz = d.alias[2];
-  x.gcache = d.gcache; x.gbox = d.gbox; x.gvalid = d.gvalid;
+  x.gcache = d.gcache; x.gkey = d.gkey;
   return x;
 }
 
@@ -1294,10 +1312,7 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
       if ((err = hipGetLastError()) != hipSuccess) return err;
     }
     if (vpart) launch_k(ex, k_fftx_fused<1>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
-    else if (d.opt) {
-      launch_k(ex, k_fftx_fused<2>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
-      hipLaunchKernelGGL(k_gcache_commit, dim3(1), dim3(64), 0, s, box, d.gbox, d.gvalid);
-    }
+    else if (d.opt) launch_k(ex, k_fftx_fused<2>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
     else launch_k(ex, k_fftx_fused<0>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     launch_k(ei, k_slab_inv, dim3(d.N[0]), dim3(kSlabThreads), d.slab_lds, s, sa);
@@ -1323,10 +1338,7 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   if ((err = hipGetLastError()) != hipSuccess) return err;
 
   if (vpart) launch_k(ex, k_fftx_fused<1>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
-  else if (d.opt) {
-    launch_k(ex, k_fftx_fused<2>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
-    hipLaunchKernelGGL(k_gcache_commit, dim3(1), dim3(64), 0, s, box, d.gbox, d.gvalid);
-  }
+  else if (d.opt) launch_k(ex, k_fftx_fused<2>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
   else launch_k(ex, k_fftx_fused<0>, dim3(fftx_blocks(d)), dim3(kFFTThreads), xsh, s, x);
   if ((err = hipGetLastError()) != hipSuccess) return err;
 

@@ -97,11 +97,12 @@ struct DevPlan {
                            // influence 1 / (sum_m sinc^{2p}((f + m N_a)/N_a))^2
   bool opt;                // optimal influence function (aliasing sums)
   float* alias[3];         // optimal influence: [3][N_a] sinc^{2p}((f + m N_a)/N_a), m = -1, 0, 1
-  // optimal influence: g of every half-spectrum point [N_y][N_x][H] for the box in
-  // gbox, valid when *gvalid (the x pass reads it when the box is unchanged)
+  // the x pass's g tables, one block per x-pass workgroup ([fftx_blocks][N_x kt], in
+  // the order the workgroup makes them), and the box each block was made for
+  // ([fftx_blocks][9], NaN until made): a workgroup reads its block when the key
+  // equals the caller's box, else it makes the table and stores both
   float* gcache;
-  double* gbox;            // [9]
-  int* gvalid;             // [1]
+  double* gkey;
   bool slab;               // y-z planes transformed in LDS (z and y passes fused)
   size_t slab_lds;         // dynamic LDS bytes of a slab workgroup
   // spread fused with the forward slab transform (one x-plane per workgroup), when
