@@ -467,9 +467,18 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
     ok(dev_alloc(&d.deconv[a], size_t(d.N[a]), by));
     if (d.opt) ok(dev_alloc(&d.alias[a], size_t(3 * d.N[a]), by));
   }
+  // the x pass's g tables: where its workgroups fit in one round (at most four per
+  // CU) the pass is latency-bound and loading a table beats making it; on larger
+  // meshes the strided line traffic bounds it and the table's extra bytes cost more
+  // than the arithmetic they save, except for the optimal influence function
   const size_t xblocks = size_t(pme::fftx_blocks(d));
-  ok(dev_alloc(&d.gcache, xblocks * d.N[0] * d.ktile, by));
-  ok(dev_alloc(&d.gkey, 9 * xblocks, by));
+  const bool gtables = d.opt || xblocks <= 1024;
+  d.gcache = nullptr;
+  d.gkey = nullptr;
+  if (gtables) {
+    ok(dev_alloc(&d.gcache, xblocks * d.N[0] * d.ktile, by));
+    ok(dev_alloc(&d.gkey, 9 * xblocks, by));
+  }
   ok(dev_alloc(&d.rho, size_t(M), by));
   ok(dev_alloc(&d.spec, size_t(d.N[0]) * d.N[1] * d.H, by));
   ok(dev_alloc(&d.phi, size_t(M), by));
@@ -519,7 +528,7 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
     ok(hipMemset(d.cmax[k], 0, sizeof(unsigned)));
   }
   ok(hipMemset(d.status, 0, sizeof(int)));
-  ok(hipMemset(d.gkey, 0xff, sizeof(double) * 9 * xblocks));   // NaN: no table made yet
+  if (d.gkey) ok(hipMemset(d.gkey, 0xff, sizeof(double) * 9 * xblocks));   // NaN: none made yet
   ok(hipMemset(d.phi, 0, sizeof(float) * M));
   if (e == hipSuccess && (desc->flags & PME_F_CONCURRENT)) {
     pl->concurrent = true;
@@ -544,9 +553,11 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
     ok(dev_alloc(&t.spec, size_t(d.N[0]) * d.N[1] * d.H, by));
     // the cotangent chain's x passes keep their own g tables: the two chains' passes
     // run at the same time
-    ok(dev_alloc(&t.gcache, xblocks * d.N[0] * d.ktile, by));
-    ok(dev_alloc(&t.gkey, 9 * xblocks, by));
-    if (e == hipSuccess) ok(hipMemset(t.gkey, 0xff, sizeof(double) * 9 * xblocks));
+    if (gtables) {
+      ok(dev_alloc(&t.gcache, xblocks * d.N[0] * d.ktile, by));
+      ok(dev_alloc(&t.gkey, 9 * xblocks, by));
+      if (e == hipSuccess) ok(hipMemset(t.gkey, 0xff, sizeof(double) * 9 * xblocks));
+    }
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
       ok(hipMemset(t.count[k], 0, sizeof(int) * nbins));
       ok(hipMemset(t.ovf_count[k], 0, sizeof(int)));
