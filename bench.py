@@ -63,15 +63,20 @@ KERNEL_SYMBOL = {
 
 # The spread kinds where the spread is fused with the forward slab transform (one
 # x-plane per workgroup; the default on meshes whose padded plane fits in LDS)
-FUSED_SYMBOL = {"spread": "k_spread_slab<6, 1>", "spread_tangent": "k_spread_slab<6, 2>"}
+FUSED_SYMBOL = {"spread": "k_spread_slab<6, 1, false>", "spread_tangent": "k_spread_slab<6, 2, false>"}
+# under pme_step's concurrent chains the forward plane spread takes the tangent records
+FUSED_STEP_SPREAD = "k_spread_slab<6, 1, true>"
 
 
 def kernel_symbol(kind: str, step: bool = False, fused: bool = False) -> str:
     """Profiler name of a timer kind's kernel; under pme_step the Hessian-vector
     gather is the variant that also forms the forward outputs; with the fused
-    plane spread the spread kinds name the fused kernel."""
+    plane spread the spread kinds name the fused kernel (whose forward variant reads
+    the tangent records under pme_step)."""
     if kind == "gather_hvp" and step:
         return "k_gather_hvp<6, true>"
+    if fused and kind == "spread" and step:
+        return FUSED_STEP_SPREAD
     if fused and kind in FUSED_SYMBOL:
         return FUSED_SYMBOL[kind]
     return KERNEL_SYMBOL[kind]
