@@ -82,8 +82,10 @@ extern "C" {
  * this flag, a plan whose y-z plane, padded by p - 1 rows and columns, fits in LDS
  * beside a transform buffer (meshes up to about 110 points in y and z, and N >= p
  * plus the bin size on every axis) spreads by x-planes and transforms each plane
- * in the same workgroup (Sec. 2.3.2 and Eq. fft).  Both give the same density and
- * spectrum bit for bit; the flag exists for comparison and measurement. */
+ * in the same workgroup (Sec. 2.3.2 and Eq. fft); a larger mesh with N >= p plus
+ * the bin size on every axis and p <= 7 spreads by bands of y-rows of each x-plane
+ * and transforms in separate passes.  All three give the same density and spectrum
+ * bit for bit; the flag exists for comparison and measurement. */
 #define PME_F_SEPARATE_SPREAD 8
 
 /* ---- mesh strategies for pme_mesh_dims (Sec. 2.3.1) ------------------- */
@@ -324,6 +326,15 @@ const char* pme_last_hip_error(void);
  * PME_F_SEPARATE_SPREAD) never stores the density: pme_plan_rho returns NULL. */
 const float* pme_plan_phi(pme_plan_t plan);
 const float* pme_plan_rho(pme_plan_t plan);
+
+/* How a plan spreads the density (Sec. 2.3.2, Eq. charge_dipole_assign): by mesh
+ * tiles, by bands of y-rows of each x-plane, or by x-planes fused with the
+ * transform (see PME_F_SEPARATE_SPREAD).  Returns one of the values below, or
+ * PME_EINVAL for a NULL plan.  For inspection, tests and measurement. */
+#define PME_SPREAD_TILE  0
+#define PME_SPREAD_BAND  1
+#define PME_SPREAD_FUSED 2
+int pme_plan_spread_kind(pme_plan_t plan);
 
 /* ---- batches of boxes ---------------------------------------------------
  * The training loss of Sec. 2.4 (Eq. loss) sums energy and force errors over a

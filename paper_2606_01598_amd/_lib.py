@@ -29,6 +29,10 @@ PME_F_CONCURRENT = 2
 PME_F_OPT_INFLUENCE = 4
 PME_F_SEPARATE_SPREAD = 8
 
+PME_SPREAD_TILE = 0
+PME_SPREAD_BAND = 1
+PME_SPREAD_FUSED = 2
+
 PME_MESH_POW2 = 0
 PME_MESH_SMOOTH = 1
 PME_MESH_CEIL = 2
@@ -37,7 +41,8 @@ PME_MESH_CEIL = 2
 EXPORTS = ("pme_mesh_dims", "pme_plan", "pme_plan_destroy", "pme_plan_workspace_bytes",
            "pme_plan_phi_id", "pme_plan_drop_phi", "pme_forward_noalloc",
            "pme_forward", "pme_forward_cell", "pme_forward_quad", "pme_backward", "pme_step", "pme_step_capture", "pme_step_replay", "pme_status", "pme_strerror", "pme_last_hip_error",
-           "pme_plan_phi", "pme_plan_rho", "pme_plan_timer", "pme_plan_timer_read",
+           "pme_plan_phi", "pme_plan_rho", "pme_plan_spread_kind", "pme_plan_timer",
+           "pme_plan_timer_read",
            "pol_plan_create", "pol_plan_destroy", "pol_real", "pol_real_mixed", "pol_model",
            "pol_model_hvp", "pol_scf", "dip_plan_create", "dip_plan_destroy", "dip_features",
            "dip_forward", "dip_backward", "dip_position_vjp", "dip_features_jvp", "dip_charges",
@@ -155,6 +160,8 @@ def load():
     lib.pme_plan_phi.restype = vp
     lib.pme_plan_rho.argtypes = [vp]
     lib.pme_plan_rho.restype = vp
+    lib.pme_plan_spread_kind.argtypes = [vp]
+    lib.pme_plan_spread_kind.restype = ctypes.c_int
     lib.pme_plan_timer.argtypes = [vp, ctypes.c_int]
     lib.pme_plan_timer.restype = ctypes.c_int
     lib.pme_plan_timer_read.argtypes = [vp, ctypes.POINTER(ctypes.c_int64),

@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -305,6 +306,44 @@ int plan_geometry(const pme_desc_t& desc, DevPlan& d, long& nbins_out) {
         d.fused_nscan = int(nscan);
       }
     }
+    // band spread where the plane spread is not fused with the transform: the most
+    // rows per band (at most 64) whose band, scan arrays, item map and hit list fit
+    // the slab LDS limit, then bands of equal height; worth it from 8 rows.  When
+    // that grid is four or more rounds of workgroups deep, bands sized for two
+    // workgroups per CU instead (one's latency phases overlap the other's adds)
+    d.band = false;
+    if (!d.fused && !(desc.flags & PME_F_SEPARATE_SPREAD) && p <= 7) {
+      bool ok = true;
+      for (int a = 0; a < 3; ++a)
+        if (d.N[a] < p + d.B[a]) ok = false;
+      const long PZ = d.N[2] + p - 1;
+      const long lx = std::min<long>(d.nb[0], (p - 1) / d.B[0] + 2);
+      auto scan_of = [&](long rows) {
+        return lx * std::min<long>(d.nb[1], (rows + p - 2) / d.B[1] + 2) * d.nb[2];
+      };
+      auto bytes_of = [&](long rows) {
+        return 8 * rows * PZ + 8 * (scan_of(rows) + 2) + 2L * pme::kFusedMap +
+               4L * pme::kBandHits;
+      };
+      auto fit_rows = [&](long budget) {
+        for (long rows = std::min(d.N[1], 64); rows >= 1; --rows)
+          if (scan_of(rows) < 65535 && bytes_of(rows) <= budget) return rows;
+        return 0L;
+      };
+      long fit = fit_rows(pme::kSlabLdsMax);
+      if (fit && d.N[0] * ((d.N[1] + fit - 1) / fit) >= 4L * pme::kNumCUs) {
+        const long fit2 = fit_rows(pme::kBandLdsPair);
+        if (fit2 >= std::min(d.N[1], 8)) fit = fit2;
+      }
+      if (ok && fit >= std::min(d.N[1], 8)) {
+        const long nband = (d.N[1] + fit - 1) / fit;
+        const long rows = (d.N[1] + nband - 1) / nband;
+        d.band = true;
+        d.band_rows = int(rows);
+        d.band_nscan = int(scan_of(rows));
+        d.band_lds = size_t(bytes_of(rows));
+      }
+    }
     // pencil passes: about 1024 complex points per workgroup
     int pairs = (1024 + d.N[2] - 1) / d.N[2];
     if (pairs > 32) pairs = 32;
@@ -570,6 +609,7 @@ int pme_plan(const pme_desc_t* desc, pme_plan_t* out) {
     ok(hipEventCreateWithFlags(&pl->binned, hipEventDisableTiming));
   }
   if (d.slab) ok(pme::enable_slab_lds(d.slab_lds));
+  if (d.band) ok(pme::enable_band_lds());
   ok(pme::enable_spread_lds());
   ok(pme::enable_gather_lds());
   ok(hipDeviceSynchronize());
@@ -600,6 +640,11 @@ int pme_plan_drop_phi(pme_plan_t plan) {
 }
 const float* pme_plan_rho(pme_plan_t plan) {
   return (plan && !plan->d.fused) ? plan->d.rho : nullptr;
+}
+
+int pme_plan_spread_kind(pme_plan_t plan) {
+  if (!plan) return PME_EINVAL;
+  return plan->d.fused ? PME_SPREAD_FUSED : (plan->d.band ? PME_SPREAD_BAND : PME_SPREAD_TILE);
 }
 
 }  // extern "C"

@@ -66,6 +66,9 @@ constexpr int kSlabLdsMax = 160 * 1024 - 2048;
 constexpr int kFusedMap = 4096;     // item -> bin map slots of a fused spread-slab workgroup
 constexpr int kFusedSlotsPerThread = 4;   // scanned slots per thread and round
 constexpr int kFusedHits = 2 * kFusedSlotsPerThread * kSlabThreads;   // its hit list (two rounds)
+constexpr int kBandHits = kFusedSlotsPerThread * kSlabThreads;       // band spread's (one round)
+constexpr int kBandLdsPair = 78 * 1024;   // band workgroup's LDS budget, two per CU
+constexpr int kNumCUs = 256;               // compute units of the MI355X
 
 struct DevPlan {
   int N[3];                // mesh dims
@@ -111,6 +114,12 @@ struct DevPlan {
   size_t fused_lds;        // its dynamic LDS bytes
   int fused_abuf;          // float2 words before the plane
   int fused_nscan;         // bins a plane may scan
+  // band spread (meshes without the fused plane spread): one workgroup per band of
+  // band_rows y-rows of an x-plane, the band in LDS (band_rows x (N_z + p - 1) words)
+  bool band;
+  int band_rows;
+  int band_nscan;          // bins a band may scan
+  size_t band_lds;         // its dynamic LDS bytes
   int rows_per_block;      // z-pass rows per block (even)
   int ktile;               // half-spectrum z columns per y/x-pass block (y and x pass)
   // meshes
@@ -286,6 +295,10 @@ struct RecordSource {
 hipError_t launch_spread_slab(const DevPlan& d, hipStream_t s, int set, bool tangent,
                               const double* box, const LaunchEvents* ev,
                               const RecordSource* from = nullptr);
+// The band spread of binning `set` into d.rho (d.band plans).
+hipError_t launch_spread_band(const DevPlan& d, hipStream_t s, int set, bool tangent,
+                              const double* box, const LaunchEvents* ev);
+hipError_t enable_band_lds();
 // Raise the dynamic LDS limit of the spread (kBigLds) and gather (kGatherLds) kernels.
 hipError_t enable_spread_lds();
 hipError_t enable_gather_lds();

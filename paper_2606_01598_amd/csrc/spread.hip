@@ -890,6 +890,7 @@ hipError_t launch_spread_quad(const DevPlan& d, hipStream_t s, int set, const do
 
 hipError_t launch_spread(const DevPlan& d, hipStream_t s, int set, bool tangent,
                          const double* box, const LaunchEvents* ev) {
+  if (d.band) return launch_spread_band(d, s, set, tangent, box, ev);
   const SpreadArgs a = make_spread_args(d, set, tangent);
   const size_t sh = spread_lds(d, tangent);
   const dim3 g(d.nt[0] * d.nt[1] * d.nt[2]);

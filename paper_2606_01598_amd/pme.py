@@ -265,6 +265,13 @@ class Plan:
         """Copy of the potential mesh of the last forward (N_x, N_y, N_z)."""
         return self._mesh_copy(self._lib.pme_plan_phi(self.handle))
 
+    @property
+    def spread_kind(self) -> str:
+        """How the plan spreads the density: "tile", "band" or "fused"."""
+        k = self._lib.pme_plan_spread_kind(self.handle)
+        return {_lib.PME_SPREAD_TILE: "tile", _lib.PME_SPREAD_BAND: "band",
+                _lib.PME_SPREAD_FUSED: "fused"}[k]
+
     def rho(self) -> torch.Tensor:
         """Copy of the last density spread (forward density or tangent density).
         A plan with the fused plane spread keeps no density mesh."""

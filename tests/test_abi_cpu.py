@@ -113,6 +113,7 @@ def test_null_arguments():
     assert lib.pme_status(None, None) == _lib.PME_EINVAL
     lib.pme_plan_destroy(None)
     assert lib.pme_plan_workspace_bytes(None) == 0
+    assert lib.pme_plan_spread_kind(None) == _lib.PME_EINVAL
 
 
 def test_teacher_and_head_calls_reject_a_missing_plan():
