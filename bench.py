@@ -66,9 +66,27 @@ KERNEL_SYMBOL = {
 FUSED_SYMBOL = {"spread": "k_spread_slab<6, 1, false>", "spread_tangent": "k_spread_slab<6, 2, false>"}
 # under pme_step's concurrent chains the forward plane spread takes the tangent records
 FUSED_STEP_SPREAD = "k_spread_slab<6, 1, true>"
+# ... and where a plan spreads by bands of y-rows of each x-plane (meshes whose
+# padded plane does not fit in LDS beside the slab transform)
+BAND_SYMBOL = {"spread": "k_spread_band<6, 1>", "spread_tangent": "k_spread_band<6, 2>"}
 
 
-def kernel_symbol(kind: str, step: bool = False, fused: bool = False) -> str:
+# The transform kinds of a pencil-layout plan (a y-z plane of the half spectrum too
+# large for LDS): each spans two launches (the z pass and a y pass)
+PENCIL_SYMBOL = {"fft_r2c": "k_fftz_r2c+k_ffty", "fft_c2r": "k_ffty+k_fftz_c2r"}
+SLAB_LDS_MAX = 160 * 1024 - 2048     # kSlabLdsMax of the library
+
+
+def is_slab(mesh) -> bool:
+    """Whether the library transforms this mesh by y-z planes in LDS (its slab test)."""
+    ny, nz = mesh[1], mesh[2]
+    h = nz // 2 + 1
+    buf = max((ny + 1) // 2 * nz, h * (ny + 1))
+    return 8 * (2 * buf + ny + nz) <= SLAB_LDS_MAX
+
+
+def kernel_symbol(kind: str, step: bool = False, fused: bool = False, band: bool = False,
+                  slab: bool = True) -> str:
     """Profiler name of a timer kind's kernel; under pme_step the Hessian-vector
     gather is the variant that also forms the forward outputs; with the fused
     plane spread the spread kinds name the fused kernel (whose forward variant reads
@@ -79,6 +97,10 @@ def kernel_symbol(kind: str, step: bool = False, fused: bool = False) -> str:
         return FUSED_STEP_SPREAD
     if fused and kind in FUSED_SYMBOL:
         return FUSED_SYMBOL[kind]
+    if band and kind in BAND_SYMBOL:
+        return BAND_SYMBOL[kind]
+    if not slab and kind in PENCIL_SYMBOL:
+        return PENCIL_SYMBOL[kind]
     return KERNEL_SYMBOL[kind]
 
 
@@ -123,8 +145,8 @@ def step_bytes(n: int, m: int, step: bool = True) -> int:
 # only while they are unchanged)
 KERNEL_SOURCES = {
     "bin": ("spread.hip",), "bin_tangent": ("spread.hip",),
-    "spread": ("spread.hip", "fft.hip", "fft_radix.h"),
-    "spread_tangent": ("spread.hip", "fft.hip", "fft_radix.h"), "fft_r2c": ("fft.hip", "fft_radix.h"),
+    "spread": ("spread.hip", "band.hip", "fft.hip", "fft_radix.h"),
+    "spread_tangent": ("spread.hip", "band.hip", "fft.hip", "fft_radix.h"), "fft_r2c": ("fft.hip", "fft_radix.h"),
     "fft_x": ("fft.hip", "fft_radix.h"), "fft_c2r": ("fft.hip", "fft_radix.h"),
     "gather": ("gather.hip",), "gather_hvp": ("gather.hip",),
 }
@@ -346,7 +368,8 @@ def main(argv=None):
     ab = alg_bytes(dominant, n, m, not args.sequential, spec)
     achieved = ab / dur_s / 1e9
     traffic = read_traffic(dominant, args.workload)
-    sym = kernel_symbol(dominant, not args.sequential, fused)
+    band = plan.spread_kind == "band"
+    sym = kernel_symbol(dominant, not args.sequential, fused, band, is_slab(mesh))
     rp_us = read_kernel_stats(args.workload + ("_sequential" if args.sequential else ""), sym)
     copy_bw = copy_bandwidth(dev)
     lds = lds_peak(dev)
@@ -395,7 +418,8 @@ def main(argv=None):
         "replays": replays,
         "kernels_us": kernels_us,
         "spread": ("fused with the forward slab transform (one x-plane per workgroup)" if fused
-                   else "mesh tiles, separate slab transform"),
+                   else ("bands of y-rows of each x-plane, separate transform" if band
+                         else "mesh tiles, separate transform")),
         "step_model_bytes": step_bytes(n, m, not args.sequential),
     }
     if args.cell:
@@ -925,7 +949,8 @@ def traffic_summary(args) -> int:
     write = _counter_means(args.traffic_summary[1], "WRITE_SIZE")
     kind = args.kernel or "spread_tangent"
     fused = any(FUSED_SYMBOL.get(kind, "?") in k for k in fetch)
-    sym = kernel_symbol(kind, not args.sequential, fused)
+    band = any(BAND_SYMBOL.get(kind, "?") in k for k in fetch)
+    sym = kernel_symbol(kind, not args.sequential, fused, band)
 
     def find(table, key):
         hits = [k for k in table if key in k]
@@ -1054,6 +1079,7 @@ def counter_summary(args) -> int:
     lds_lines = []
     order = [KERNEL_SYMBOL[k] for k in ("bin", "bin_tangent", "spread", "spread_tangent")]
     order += [FUSED_SYMBOL[k] for k in ("spread", "spread_tangent")]
+    order += [BAND_SYMBOL[k] for k in ("spread", "spread_tangent")]
     order += [KERNEL_SYMBOL[k] for k in ("fft_r2c", "fft_x", "fft_c2r", "gather", "gather_hvp")]
     for k in order:
         if k not in merged:
@@ -1106,7 +1132,8 @@ def kernel_stats_summary(args) -> int:
                     d = json.loads(ln)
                     step = "pme_step" in d["config"].get("call", "")
                     fz = "fft_r2c" not in d["kernels_us"]
-                    bench_us = {kernel_symbol(k, step, fz): v for k, v in d["kernels_us"].items()}
+                    bd = d.get("spread", "").startswith("bands")
+                    bench_us = {kernel_symbol(k, step, fz, bd): v for k, v in d["kernels_us"].items()}
                     bench_val = (d["value"], d["unit"], d["roofline"]["kernel"],
                                  d["roofline"]["avg_launch_us"])
                     break
@@ -1115,6 +1142,10 @@ def kernel_stats_summary(args) -> int:
     n, _, mesh, p, _ = WORKLOADS[args.workload]
     call = "pme_forward; pme_backward" if args.sequential else "pme_step (concurrent chains)"
     seq = " --sequential 1" if args.sequential else ""
+    # off the benchmark workload the unprofiled run skips the host baseline and the
+    # side legs, as the profiled one does
+    extra = "" if args.workload == "32k" else (" --steps 20 --warmup 5 --cpu-baseline 0 "
+                                               "--batched 0 --learned 0")
     lines = [
         f"# rocprofv3 kernel statistics: PME forward + Hessian-vector product ({call}),",
         f"# {n}-ion molten-salt box, mesh {mesh[0]}^3, p = {p}, one MI355X",
@@ -1122,7 +1153,7 @@ def kernel_stats_summary(args) -> int:
         "#   rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- \\",
         f"#       python -u bench.py --steps 20 --warmup 5 --cpu-baseline 0 --batched 0 "
         f"--learned 0 --workload {args.workload}{seq}",
-        f"#   python -u bench.py --workload {args.workload}{seq} > <log>   (no profiler)",
+        f"#   python -u bench.py --workload {args.workload}{seq}{extra} > <log>   (no profiler)",
         f"#   python bench.py --kernel-stats <dir>/run_kernel_stats.csv --bench-line <log> "
         f"--workload {args.workload}{seq}",
         "# (5 warm-up, 10 per kernel kind breakdown and 20 eager timed steps, then twice",
@@ -1193,8 +1224,10 @@ def sweep_summary(logs) -> int:
         n, mesh = c["atoms"], c["mesh"]
         m = mesh[0] * mesh[1] * mesh[2]
         gbs = step_bytes(n, m) / (d["ms_per_step"] * 1e-3) / 1e9
+        sym = kernel_symbol(r["kind"], True, "fft_r2c" not in d["kernels_us"],
+                            d.get("spread", "").startswith("bands"), is_slab(mesh))
         lines.append(f"{n:8d} {mesh[0]:5d} {d['ms_per_step']:9.4f} {d['value']:14.2f} "
-                     f"{gbs:11.1f} {100 * gbs / HBM_PEAK_GBS:6.2f}  {r['kernel']} "
+                     f"{gbs:11.1f} {100 * gbs / HBM_PEAK_GBS:6.2f}  {sym} "
                      f"{r['avg_launch_us']:.1f} us, {100 * r['frac']:.2f}%")
     lines += ["", "per-kernel average launch durations (us, the bench's breakdown pass):",
               f"{'atoms':>8s} " + " ".join(f"{k:>14s}" for k in kinds)]
