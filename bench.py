@@ -68,7 +68,8 @@ FUSED_SYMBOL = {"spread": "k_spread_slab<6, 1, false>", "spread_tangent": "k_spr
 FUSED_STEP_SPREAD = "k_spread_slab<6, 1, true>"
 # ... and where a plan spreads by bands of y-rows of each x-plane (meshes whose
 # padded plane does not fit in LDS beside the slab transform)
-BAND_SYMBOL = {"spread": "k_spread_band<6, 1>", "spread_tangent": "k_spread_band<6, 2>"}
+BAND_SYMBOL = {"spread": "k_spread_band<6, 1, false>", "spread_tangent": "k_spread_band<6, 2, false>"}
+BAND_STEP_SPREAD = "k_spread_band<6, 1, true>"
 
 
 # The transform kinds of a pencil-layout plan (a y-z plane of the half spectrum too
@@ -97,6 +98,8 @@ def kernel_symbol(kind: str, step: bool = False, fused: bool = False, band: bool
         return FUSED_STEP_SPREAD
     if fused and kind in FUSED_SYMBOL:
         return FUSED_SYMBOL[kind]
+    if band and kind == "spread" and step:
+        return BAND_STEP_SPREAD
     if band and kind in BAND_SYMBOL:
         return BAND_SYMBOL[kind]
     if not slab and kind in PENCIL_SYMBOL:

@@ -794,11 +794,11 @@ int pme_step(pme_plan_t plan, void* stream, int32_t n, const float* pos, const f
   pme::KTimer& tm = plan->timer;
   hipError_t e;
   mark_phi(plan, false);
-  if (d.fused) {
+  if (d.fused || d.band) {
     // One binning for both densities and the gather: the cotangent binning (its
     // records carry q and mu; it also forms the forward coefficients' largest sum and
     // the self-term sums) on the second stream, then the cotangent chain there; the
-    // forward plane spread reads the same records once they are written.
+    // forward plane or band spread reads the same records once they are written.
     const int tset = plan->tset;
     plan->tset ^= 1;
     if ((e = hipEventRecord(plan->fork, s)) != hipSuccess) return hip_fail(e);
@@ -811,10 +811,10 @@ int pme_step(pme_plan_t plan, void* stream, int32_t n, const float* pos, const f
       return hip_fail(e);
     if ((e = hipStreamWaitEvent(s, plan->binned, 0)) != hipSuccess) return hip_fail(e);
     const pme::RecordSource src{&dt, tset, dt.cmax_fwd[tset]};
-    if ((e = pme::launch_spread_slab(d, s, 0, false, box, tm.next(PME_K_SPREAD), &src)) !=
-        hipSuccess)
-      return hip_fail(e);
-    if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm, nullptr, true)) !=
+    e = d.fused ? pme::launch_spread_slab(d, s, 0, false, box, tm.next(PME_K_SPREAD), &src)
+                : pme::launch_spread_band(d, s, 0, false, box, tm.next(PME_K_SPREAD), &src);
+    if (e != hipSuccess) return hip_fail(e);
+    if ((e = pme::launch_convolve(d, s, box, d.phi, energy != nullptr, &tm, nullptr, d.fused)) !=
         hipSuccess)
       return hip_fail(e);
     if ((e = hipEventRecord(plan->join, s2)) != hipSuccess) return hip_fail(e);

@@ -20,6 +20,9 @@
 // Against the owner-computes tiles this spends a workgroup's lanes on stencil
 // points that are all inside the band except in the p - 1 edge rows, and makes each
 // atom's weights once per plane and band instead of once per tile.
+//
+// TREC: the density from the tangent records (q and mu; q and J mu are formed here,
+// with the same expressions as the forward binning), so that pme_step bins once.
 #include "kernels.h"
 #include "pme_common.h"
 
@@ -60,8 +63,9 @@ __device__ __forceinline__ void bin_run(int first, int len, int N, int B, int nb
   n = min(n, nb);
 }
 
-template <int P, int DEG>
+template <int P, int DEG, bool TREC>
 __global__ void __launch_bounds__(kSlabThreads) k_spread_band(BandArgs a, const double* box) {
+  static_assert(!TREC || DEG == 1, "tangent records serve the forward density");
   constexpr int NC = (DEG == 1) ? 4 : 10;
   constexpr int D = (DEG == 1) ? 1 : 2;       // highest weight derivative needed
   constexpr int lo = (P - 1) / 2;
@@ -78,13 +82,13 @@ __global__ void __launch_bounds__(kSlabThreads) k_spread_band(BandArgs a, const 
   int* s_bin = s_off + a.nscan_max + 2;
   uint16_t* s_map = reinterpret_cast<uint16_t*>(s_bin + a.nscan_max + 2);
   int* s_hits = reinterpret_cast<int*>(s_map + a.map_cap);
-  __shared__ float s_J[DEG == 2 ? 9 : 1];
+  __shared__ float s_J[(DEG == 2 || TREC) ? 9 : 1];
   __shared__ int s_nh;
   __shared__ float s_cw[4 * P * P];           // whole-number spline pieces (x weights)
   __shared__ int s_wsum[kSlabThreads / 64];   // per-wavefront sums of the scan
   constexpr int kTab = spline_offset(P);
   if (tid < 4 * P * P) s_cw[tid] = c_spline_whole.coef[kTab + tid];
-  if (DEG == 2 && tid == 0) {
+  if ((DEG == 2 || TREC) && tid == 0) {
     float J[3][3];
     jacobian(cell_from_box(box), a.N, J);
 #pragma unroll
@@ -191,6 +195,12 @@ __global__ void __launch_bounds__(kSlabThreads) k_spread_band(BandArgs a, const 
       for (int i = 0; i < 9; ++i) Jt[i / 3][i % 3] = s_J[i];
       tangent_coeffs(Jt, c0v.x, make_float3(c0v.y, c0v.z, c0v.w), c1v.x,
                      make_float3(c1v.y, c1v.z, c1v.w), make_float3(f[12], f[13], f[14]), co);
+    } else if constexpr (TREC) {
+      float Jt[3][3];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Jt[i / 3][i % 3] = s_J[i];
+      const float3 d = jmul(Jt, make_float3(c0v.y, c0v.z, c0v.w));
+      co[0] = c0v.x; co[1] = d.x; co[2] = d.y; co[3] = d.z;
     } else {
       co[0] = c0v.x; co[1] = c0v.y; co[2] = c0v.z; co[3] = c0v.w;
     }
@@ -302,13 +312,17 @@ __global__ void __launch_bounds__(kSlabThreads) k_spread_band(BandArgs a, const 
 }  // namespace
 
 hipError_t launch_spread_band(const DevPlan& d, hipStream_t s, int set, bool tangent,
-                              const double* box, const LaunchEvents* ev) {
-  if (!d.band) return hipErrorInvalidValue;
+                              const double* box, const LaunchEvents* ev, const RecordSource* from) {
+  if (!d.band || (from && (tangent || !from->d || !from->cmax))) return hipErrorInvalidValue;
   BandArgs a;
   for (int k = 0; k < 3; ++k) { a.N[k] = d.N[k]; a.B[k] = d.B[k]; a.nb[k] = d.nb[k]; }
-  a.cap = d.cap;
-  a.count = d.count[set]; a.ovf_count = d.ovf_count[set]; a.cmax = d.cmax[set];
-  a.rec = d.rec; a.ovf_base = d.ovf_base;
+  // the bins (same geometry in both views of a plan) and the scale
+  const DevPlan& r = from ? *from->d : d;
+  const int rs = from ? from->set : set;
+  a.cap = r.cap;
+  a.count = r.count[rs]; a.ovf_count = r.ovf_count[rs];
+  a.cmax = from ? from->cmax : d.cmax[set];
+  a.rec = r.rec; a.ovf_base = r.ovf_base;
   a.PZ = d.N[2] + d.p - 1;
   a.rows = d.band_rows;
   a.nband = (d.N[1] + d.band_rows - 1) / d.band_rows;
@@ -318,10 +332,11 @@ hipError_t launch_spread_band(const DevPlan& d, hipStream_t s, int set, bool tan
   a.rho = d.rho;
   const dim3 g(d.N[0] * a.nband), b(kSlabThreads);
   const size_t sh = d.band_lds;
-#define PME_B(P)                                                       \
-  case P:                                                              \
-    if (tangent) launch_k(ev, k_spread_band<P, 2>, g, b, sh, s, a, box); \
-    else launch_k(ev, k_spread_band<P, 1>, g, b, sh, s, a, box);        \
+#define PME_B(P)                                                              \
+  case P:                                                                     \
+    if (tangent) launch_k(ev, k_spread_band<P, 2, false>, g, b, sh, s, a, box); \
+    else if (from) launch_k(ev, k_spread_band<P, 1, true>, g, b, sh, s, a, box); \
+    else launch_k(ev, k_spread_band<P, 1, false>, g, b, sh, s, a, box);        \
     break;
   switch (d.p) {
     PME_B(1) PME_B(2) PME_B(3) PME_B(4) PME_B(5) PME_B(6) PME_B(7)
@@ -334,8 +349,9 @@ hipError_t launch_spread_band(const DevPlan& d, hipStream_t s, int set, bool tan
 hipError_t enable_band_lds() {
   const void* fns[] = {
 #define PME_B(P)                                                   \
-  reinterpret_cast<const void*>(k_spread_band<P, 1>),              \
-      reinterpret_cast<const void*>(k_spread_band<P, 2>),
+  reinterpret_cast<const void*>(k_spread_band<P, 1, false>),       \
+      reinterpret_cast<const void*>(k_spread_band<P, 1, true>),    \
+      reinterpret_cast<const void*>(k_spread_band<P, 2, false>),
       PME_B(1) PME_B(2) PME_B(3) PME_B(4) PME_B(5) PME_B(6) PME_B(7)
 #undef PME_B
   };

@@ -295,9 +295,11 @@ struct RecordSource {
 hipError_t launch_spread_slab(const DevPlan& d, hipStream_t s, int set, bool tangent,
                               const double* box, const LaunchEvents* ev,
                               const RecordSource* from = nullptr);
-// The band spread of binning `set` into d.rho (d.band plans).
+// The band spread of binning `set` into d.rho (d.band plans); with `from`, the
+// forward density from another view's tangent records (as launch_spread_slab).
 hipError_t launch_spread_band(const DevPlan& d, hipStream_t s, int set, bool tangent,
-                              const double* box, const LaunchEvents* ev);
+                              const double* box, const LaunchEvents* ev,
+                              const RecordSource* from = nullptr);
 hipError_t enable_band_lds();
 // Raise the dynamic LDS limit of the spread (kBigLds) and gather (kGatherLds) kernels.
 hipError_t enable_spread_lds();
