@@ -349,8 +349,12 @@ int plan_geometry(const pme_desc_t& desc, DevPlan& d, long& nbins_out) {
     if (pairs > 32) pairs = 32;
     d.rows_per_block = 2 * pairs;
     const int nmax = d.N[0] > d.N[1] ? d.N[0] : d.N[1];
-    int kt = nmax <= 64 ? 16 : (nmax <= 160 ? 24 : 4);
-    if (desc.fft_lines > 0) kt = desc.fft_lines;
+    const int kt0 = nmax <= 64 ? 16 : (nmax <= 160 ? 24 : 4);
+    int kt = desc.fft_lines > 0 ? desc.fft_lines : kt0;
+    // the pencil y pass holds no g table: on meshes above 160 points it takes twice
+    // the x pass's default lines (64-byte segments of its strided lines); on smaller
+    // meshes, and with lines given in the descriptor, the x pass's
+    int kty = desc.fft_lines > 0 ? desc.fft_lines : 2 * kt0;
     // LDS of a line workgroup within 56 KB: twiddles, two line buffers and (x pass)
     // the kt N_x table of g and the deconvolution factors:
     // 8 N + kt (16 (N + 1) + 4 N) + 4 (N + kt) bytes
@@ -361,10 +365,21 @@ int plan_geometry(const pme_desc_t& desc, DevPlan& d, long& nbins_out) {
     if (kt > lds_cap) kt = lds_cap;
     if (kt < 1) kt = 1;
     if (kt > d.H) kt = d.H;
+    // the y pass: twiddles and two line buffers within the same 56 KB
+    const int ycap = (7000 - nmax) / (2 * (nmax + 1));
+    if (kty > ycap) kty = ycap;
+    if (kty < 1) kty = 1;
+    if (kty > d.H) kty = d.H;
     // equal chunks of the H columns (no mostly-empty last chunk)
     const int nchunk = (d.H + kt - 1) / kt;
     kt = (d.H + nchunk - 1) / nchunk;
     d.ktile = kt;
+    if (nmax <= 160 || desc.fft_lines > 0) {
+      d.ytile = kt;
+    } else {
+      const int nchunk_y = (d.H + kty - 1) / kty;
+      d.ytile = (d.H + nchunk_y - 1) / nchunk_y;
+    }
   }
   nbins_out = nbins;
   return PME_OK;

@@ -1327,9 +1327,9 @@ hipError_t launch_convolve(const DevPlan& d, hipStream_t s, const double* box, f
   const int zb = fftz_blocks(d);
   const size_t zsh_f = sizeof(float2) * (d.N[2] + d.rows_per_block * d.N[2]);
   YArgs y;
-  y.ax = d.ax[1]; y.tw = d.twiddle[1]; y.Ny = d.N[1]; y.H = d.H; y.kt = d.ktile; y.spec = d.spec;
-  y.ktd = make_fast_div(d.ktile);
-  const size_t ysh = sizeof(float2) * (d.N[1] + 2 * d.ktile * (d.N[1] + 1));
+  y.ax = d.ax[1]; y.tw = d.twiddle[1]; y.Ny = d.N[1]; y.H = d.H; y.kt = d.ytile; y.spec = d.spec;
+  y.ktd = make_fast_div(d.ytile);
+  const size_t ysh = sizeof(float2) * (d.N[1] + 2 * d.ytile * (d.N[1] + 1));
 
   launch_k(er ? &er0 : nullptr, k_fftz_r2c, dim3(zb), dim3(kFFTThreads), zsh_f, s, z);
   if ((err = hipGetLastError()) != hipSuccess) return err;

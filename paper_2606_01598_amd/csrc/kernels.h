@@ -121,7 +121,8 @@ struct DevPlan {
   int band_nscan;          // bins a band may scan
   size_t band_lds;         // its dynamic LDS bytes
   int rows_per_block;      // z-pass rows per block (even)
-  int ktile;               // half-spectrum z columns per y/x-pass block (y and x pass)
+  int ktile;               // half-spectrum z columns per x-pass block
+  int ytile;               // half-spectrum z columns per y-pass block (pencil layout)
   // meshes
   float* rho;              // [M] density (also the tangent density / its potential)
   float2* spec;            // [N_x N_y H]
@@ -243,7 +244,7 @@ hipError_t launch_gather_batch(const GatherBatch& t, hipStream_t s, int set, boo
 hipError_t upload(void** dst, const void* src, size_t bytes);
 
 inline int fftx_blocks(const DevPlan& d) { return d.N[1] * ((d.H + d.ktile - 1) / d.ktile); }
-inline int ffty_blocks(const DevPlan& d) { return d.N[0] * ((d.H + d.ktile - 1) / d.ktile); }
+inline int ffty_blocks(const DevPlan& d) { return d.N[0] * ((d.H + d.ytile - 1) / d.ytile); }
 inline int fftz_blocks(const DevPlan& d) {
   const int rows = d.N[0] * d.N[1];
   return (rows + d.rows_per_block - 1) / d.rows_per_block;
