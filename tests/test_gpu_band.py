@@ -3,7 +3,7 @@ meshes whose padded y-z plane does not fit in LDS beside the slab transform)
 against the tile spread (PME_F_SEPARATE_SPREAD): every output of pme_forward,
 pme_backward and the concurrent pme_step must be bitwise equal, since both add the
 same 64-bit fixed-point contributions to each mesh point.  The cases cover orders
-4-7, slab and pencil layouts, bands that do not divide N_y, a sheared cell, a
+1-7, slab and pencil layouts, bands that do not divide N_y, a sheared cell, a
 clustered box whose bins overflow, a crowded box whose bands scan more slots than
 the item map holds and list more atoms than the hit list (drained in batches), and
 a grid deep enough for the bands sized for two workgroups per CU.  The oracle parity of the band path itself is checked by the PME tests
@@ -43,6 +43,9 @@ CASES = [("slab", (40, 128, 128), 6, (40.0, 128.0, 128.0), "plain"),
          ("p4", (32, 150, 120), 4, (32.0, 150.0, 120.0), "sheared"),
          ("clustered", (40, 128, 128), 6, (40.0, 128.0, 128.0), "clustered"),
          ("crowded", (40, 128, 128), 6, (40.0, 128.0, 128.0), "crowded"),
+         ("p1", (24, 128, 120), 1, (24.0, 128.0, 120.0), "plain"),
+         ("p2", (24, 128, 120), 2, (24.0, 128.0, 120.0), "plain"),
+         ("p3", (24, 150, 125), 3, (24.0, 150.0, 125.0), "sheared"),
          # 256 planes of 4 bands: a grid of 1024 workgroups, so bands sized for two
          # workgroups per CU
          ("pair", (256, 200, 200), 6, (256.0, 200.0, 200.0), "plain")]
