@@ -1214,6 +1214,7 @@ int scratch_address(unsigned char** out) {
     if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return hip_fail(e);
     if (!p) return PME_EHIP;
     if ((e = pme::enable_slab_lds(pme::kSlabLdsMax)) != hipSuccess) return hip_fail(e);
+    if ((e = pme::enable_band_lds()) != hipSuccess) return hip_fail(e);
     if ((e = pme::enable_spread_lds()) != hipSuccess) return hip_fail(e);
     if ((e = pme::enable_gather_lds()) != hipSuccess) return hip_fail(e);
     g_scratch[dev] = static_cast<unsigned char*>(p);

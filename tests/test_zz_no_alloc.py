@@ -99,3 +99,24 @@ def test_noalloc_host_rejections():
     opt = _desc((16, 16, 16), 6, 0.3, flags=_lib.PME_F_OPT_INFLUENCE)
     assert lib.pme_forward_noalloc(ctypes.byref(opt), *args) == _lib.PME_EINVAL
     assert lib.pme_forward_noalloc(None, *args) == _lib.PME_EINVAL
+
+
+def test_noalloc_forward_band_mesh():
+    # a mesh whose padded y-z plane does not fit beside the slab transform: the
+    # band spread, in the fixed scratch array as in a plan
+    from paper_2606_01598_amd.pme import Plan
+    mesh, p, alpha = (24, 128, 120), 6, 0.3
+    print(f"case: pme_forward_noalloc band mesh {mesh} p={p}", flush=True)
+    rng = np.random.default_rng(31)
+    n = 2000
+    diag = np.array([24.0, 128.0, 120.0])
+    f = synth.Frame(pos=rng.uniform(0.0, 1.0, (n, 3)) * diag,
+                    q=np.where(np.arange(n) % 2 == 0, 1.0, -1.0),
+                    mu=rng.normal(0.0, 0.1, (n, 3)), box=np.diag(diag))
+    got = _noalloc(f, mesh, p, alpha)   # before any plan: the entry point's own set-up
+    assert Plan(mesh, p, alpha, max_atoms=n).spread_kind == "band"
+    ref = _plan_forward(f, mesh, p, alpha)
+    assert _compare("band mesh", got, ref)
+    o = oracle_forward(f, mesh, p, alpha)
+    assert rel(host(got["energy"]).sum(), o.energy) <= E_REL_TOL
+    assert rms_rel(host(got["dE_dpos"]), o.dE_dpos) <= RMS_REL_TOL
