@@ -25,6 +25,7 @@
 #include "fft_radix.h"
 #include "kernels.h"
 #include "pme_common.h"
+#include "plane_spread.h"
 
 namespace pme {
 namespace {
@@ -957,8 +958,6 @@ template <int P, int DEG, bool TREC>
 __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const int X,
                                                  const double* box) {
   static_assert(!TREC || DEG == 1, "tangent records serve the forward density");
-  constexpr int NC = (DEG == 1) ? 4 : 10;
-  constexpr int D = (DEG == 1) ? 1 : 2;       // highest weight derivative needed
   constexpr int lo = (P - 1) / 2;
   extern __shared__ float2 sm[];
   const int tid = threadIdx.x;
@@ -1000,17 +999,14 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
   nl = min(nl, a.nb[0]);
   const int nyz = a.nb[1] * a.nb[2];
   const int nscan = nl * nyz;                 // <= a.nscan_max (host guarantees)
-  for (int e = tid; e < nscan; e += nthr) {
-    const int li = e / nyz;
-    const int bin = ((k0 + li) % a.nb[0]) * nyz + (e - li * nyz);
-    s_bin[e] = bin;
-    s_off[e] = min(a.count[bin], a.cap);
-  }
-  if (tid == 0) {
-    s_bin[nscan] = -1;                        // pseudo-bin: the overflow list
-    s_off[nscan] = *a.ovf_count;
-    s_nh = 0;
-  }
+  load_slot_counts(
+      nscan,
+      [&](int e) {
+        const int li = e / nyz;
+        return ((k0 + li) % a.nb[0]) * nyz + (e - li * nyz);
+      },
+      a.count, a.cap, a.ovf_count, s_off, s_bin);
+  if (tid == 0) s_nh = 0;
   // the fixed-point unit of the tile spread (the same bound and the same scale)
   constexpr float kWhole3 = float(spline_norm(P)) * float(spline_norm(P)) * float(spline_norm(P));
   float scale = 1.0f;
@@ -1021,123 +1017,16 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
   const int pvol = a.PY * a.PZ;
   for (int e = tid; e < pvol; e += nthr) plane[e] = 0ull;
   __syncthreads();
-  // exclusive scan of the occupied slot counts over the workgroup: consecutive
-  // segments per thread, wavefront prefix sums, then the wavefronts' totals
-  {
-    const int len = nscan + 1;
-    const int seg = (len + nthr - 1) / nthr;
-    const int s0 = min(tid * seg, len), s1 = min(s0 + seg, len);
-    int acc = 0;
-    for (int e = s0; e < s1; ++e) acc += s_off[e];
-    const int lane = tid & 63, wave = tid >> 6;
-    int incl = acc;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int v = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += v;
-    }
-    if (lane == 63) s_wsum[wave] = incl;
-    __syncthreads();
-    int before = 0;
-    for (int w = 0; w < wave; ++w) before += s_wsum[w];
-    int run = before + incl - acc;
-    for (int e = s0; e < s1; ++e) { const int v = s_off[e]; s_off[e] = run; run += v; }
-    if (tid == nthr - 1) s_off[len] = before + incl;
-  }
-  __syncthreads();
-  const int total = s_off[nscan + 1];
-  const bool mapped = total <= a.map_cap;
-  if (mapped)
-    for (int e = tid; e <= nscan; e += nthr)
-      for (int k = s_off[e]; k < s_off[e + 1]; ++k) s_map[k] = uint16_t(e);
-  __syncthreads();
-
-  // record index of scanned slot `item`: the bin is the last one whose offset is <= item
+  int total;
+  const bool mapped = scan_slot_counts(nscan, s_off, s_wsum, s_map, a.map_cap, total);
   auto record_of = [&](int item) {
-    int lb = 0;
-    if (mapped) {
-      lb = s_map[item];
-    } else {
-      int hb = nscan;
-      while (lb < hb) {
-        const int mid = (lb + hb + 1) >> 1;
-        if (s_off[mid] <= item) lb = mid; else hb = mid - 1;
-      }
-    }
-    const int bin = s_bin[lb];
-    const int slot = item - s_off[lb];
-    return (bin >= 0) ? size_t(bin) * a.cap + slot : size_t(a.ovf_base) + slot;
+    return scanned_record(item, mapped, nscan, s_off, s_bin, s_map, a.cap, a.ovf_base);
   };
-  // one atom: its footprint in the plane, with the tile spread's arithmetic
+  // one atom: its footprint in the padded plane (stencil row iy of an atom anchored at
+  // b_y in padded row b_y + iy)
   auto add_atom = [&](size_t ri) {
-    const float4* r = reinterpret_cast<const float4*>(a.rec + ri * kRecWords);
-    const float4 h = r[0];
-    const float4 c0v = r[1];
-    float co[NC];
-    if constexpr (DEG == 2) {
-      const float4 c1v = r[2];
-      const float* f = a.rec + ri * kRecWords;   // v_mu
-      float Jt[3][3];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) Jt[i / 3][i % 3] = s_J[i];
-      tangent_coeffs(Jt, c0v.x, make_float3(c0v.y, c0v.z, c0v.w), c1v.x,
-                     make_float3(c1v.y, c1v.z, c1v.w), make_float3(f[12], f[13], f[14]), co);
-    } else if constexpr (TREC) {
-      float Jt[3][3];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) Jt[i / 3][i % 3] = s_J[i];
-      const float3 d = jmul(Jt, make_float3(c0v.y, c0v.z, c0v.w));
-      co[0] = c0v.x; co[1] = d.x; co[2] = d.y; co[3] = d.z;
-    } else {
-      co[0] = c0v.x; co[1] = c0v.y; co[2] = c0v.z; co[3] = c0v.w;
-    }
-    const int pk = __float_as_int(h.w);
-    const int by = (pk >> 10) & 1023, bz = (pk >> 20) & 1023;
-    int ix = X - (pk & 1023) + lo;
-    ix += (ix < 0) ? a.N[0] : 0;
-    ix -= (ix >= a.N[0]) ? a.N[0] : 0;
-    // this plane's x weights (whole-number, times the fixed-point unit): the
-    // column ix of spline_weights_whole, with the same Horner steps
-    float x[D + 1];
-    weight_at_lds<P, D>(s_cw, ix, h.x, x);
-#pragma unroll
-    for (int d = 0; d <= D; ++d) x[d] *= scale;
-    // this x-plane's coefficients of the (y, z) derivative monomials
-    float ax0, az1, az2 = 0.f, ay1, ay2 = 0.f, ayz = 0.f;
-    if (DEG == 1) {
-      ax0 = co[0] * x[0] + co[1] * x[1];   // W_y W_z
-      ay1 = co[2] * x[0];                  // W_y' W_z
-      az1 = co[3] * x[0];                  // W_y W_z'
-    } else {
-      ax0 = co[0] * x[0] + co[1] * x[1] + co[4] * x[2];
-      ay1 = co[2] * x[0] + co[7] * x[1];
-      az1 = co[3] * x[0] + co[8] * x[1];
-      ay2 = co[5] * x[0];
-      az2 = co[6] * x[0];
-      ayz = co[9] * x[0];
-    }
-    float wy[D + 1][P], wz[D + 1][P];
-    spline_weights_whole<P, D>(h.y, wy);
-    spline_weights_whole<P, D>(h.z, wz);
-    unsigned long long* base = plane + by * a.PZ + bz;
-#pragma unroll
-    for (int iy = 0; iy < P; ++iy) {
-      const float y0 = wy[0][iy], y1 = wy[1][iy];
-      float c0 = ax0 * y0 + ay1 * y1, c1 = az1 * y0, c2 = 0.f;
-      if (D == 2) {
-        const float y2 = wy[2][iy];
-        c0 += ay2 * y2;
-        c1 += ayz * y1;
-        c2 = az2 * y0;
-      }
-      unsigned long long* row = base + iy * a.PZ;
-#pragma unroll
-      for (int iz = 0; iz < P; ++iz) {
-        float v = c0 * wz[0][iz] + c1 * wz[1][iz];
-        if (D == 2) v += c2 * wz[2][iz];
-        atomicAdd(row + iz, to_fixed(v));
-      }
-    }
+    add_atom_plane<P, DEG, TREC>(a.rec, ri, s_J, s_cw, X, a.N[0], scale, plane, a.PZ,
+                                 [](int by, int iy) { return by + iy; }, 0x7fffffff);
   };
 
   // rounds of kSlotsPerThread scanned slots per thread (their anchor words loaded
