@@ -1066,19 +1066,31 @@ __device__ __forceinline__ void spread_slab_body(const SpreadSlabArgs& a, const 
       __syncthreads();
     }
   }
-  // the plane's value at (y, z): the fixed-point words of its periodic images
+  // the extra columns, then the extra rows, added into their periodic images: mesh
+  // point (y, z) sits at padded (y + lo, z + lo), and padded column c < lo is column
+  // c + N_z, column c >= lo + N_z is c - N_z (rows alike).  Each image word takes one
+  // word per pass (N >= p keeps the two image ranges apart), and 64-bit sums do not
+  // depend on their order.
+  {
+    constexpr int ne = P - 1;
+    for (int e = tid; e < a.PY * ne; e += nthr) {
+      const int py = e / ne, c = e - py * ne;
+      const int src = (c < lo) ? c : c + Nz;
+      unsigned long long* row = plane + py * a.PZ;
+      row[(c < lo) ? src + Nz : src - Nz] += row[src];
+    }
+    __syncthreads();
+    for (int e = tid; e < ne * Nz; e += nthr) {
+      const int r = e / Nz, z = e - r * Nz + lo;
+      const int src = (r < lo) ? r : r + Ny;
+      plane[((r < lo) ? src + Ny : src - Ny) * a.PZ + z] += plane[src * a.PZ + z];
+    }
+    __syncthreads();
+  }
+  // the plane's value at (y, z)
   const double inv_scale = 1.0 / (double(scale) * double(kWhole3));
   auto value = [&](int y, int z) {
-    const int py = y + lo, pz = z + lo;
-    const int py2 = (py + Ny < a.PY) ? py + Ny : ((py >= Ny) ? py - Ny : -1);
-    const int pz2 = (pz + Nz < a.PZ) ? pz + Nz : ((pz >= Nz) ? pz - Nz : -1);
-    unsigned long long acc = plane[py * a.PZ + pz];
-    if (pz2 >= 0) acc += plane[py * a.PZ + pz2];
-    if (py2 >= 0) {
-      acc += plane[py2 * a.PZ + pz];
-      if (pz2 >= 0) acc += plane[py2 * a.PZ + pz2];
-    }
-    return from_fixed((long long)acc, inv_scale);
+    return from_fixed((long long)plane[(y + lo) * a.PZ + z + lo], inv_scale);
   };
   slab_fwd_run(a.sl, X, value, tz, ty, twz, twy, A, B);
 }
