@@ -204,6 +204,9 @@ def _args(argv=None):
     ap.add_argument("--counter-summary", nargs="+", default=None, metavar="DIR",
                     help="write profiles/kernels_<workload>_counters.txt from rocprofv3 counter "
                          "directories (one per COUNTER_PASSES entry) and exit")
+    ap.add_argument("--counter-step", type=int, default=0,
+                    help="with --counter-summary: passes over the concurrent pme_step "
+                         "(profiles/kernels_<workload>_step_counters.txt)")
     ap.add_argument("--kernel-stats", default=None, metavar="STATS_CSV",
                     help="write profiles/<workload> kernel-statistics summary from a "
                          "rocprofv3 --stats kernel_stats.csv")
@@ -951,8 +954,9 @@ def traffic_summary(args) -> int:
     fetch = _counter_means(args.traffic_summary[0], "FETCH_SIZE")
     write = _counter_means(args.traffic_summary[1], "WRITE_SIZE")
     kind = args.kernel or "spread_tangent"
-    fused = any(FUSED_SYMBOL.get(kind, "?") in k for k in fetch)
-    band = any(BAND_SYMBOL.get(kind, "?") in k for k in fetch)
+    step = not args.sequential
+    fused = any(kernel_symbol(kind, step, True) in k for k in fetch)
+    band = not fused and any(kernel_symbol(kind, step, False, True) in k for k in fetch)
     sym = kernel_symbol(kind, not args.sequential, fused, band)
 
     def find(table, key):
@@ -977,7 +981,7 @@ def traffic_summary(args) -> int:
     with open(out, "w") as fh:
         fh.write(f"# HBM traffic of {sym} ({kind}), workload {args.workload}\n")
         fh.write("# commands (from the repository root):\n")
-        flags = COUNTER_FLAGS if args.sequential else PMC_FLAGS
+        flags = COUNTER_FLAGS if args.sequential else STEP_COUNTER_FLAGS
         seq = " --sequential 1" if args.sequential else ""
         for ctr, d in (("FETCH_SIZE", "<D1>"), ("WRITE_SIZE", "<D2>")):
             fh.write(f"#   rocprofv3 --pmc {ctr} --output-format csv -d {d} -o run -- "
@@ -1020,6 +1024,9 @@ COUNTER_PASSES = (
 COUNTER_FLAGS = ("--steps 3 --warmup 2 --cpu-baseline 0 --batched 0 --learned 0 --cell 0 "
                  "--influence 0 --quad 0 --copy-calibration 1 --breakdown-steps 1 --sequential 1 "
                  "--graph 0 --replays 0")
+# the same passes over the concurrent pme_step (its kernel variants: the forward
+# spread from the tangent records, the gather that also forms the forward outputs)
+STEP_COUNTER_FLAGS = COUNTER_FLAGS.replace(" --sequential 1", "")
 
 
 def _pass_rows(path):
@@ -1054,17 +1061,22 @@ def counter_summary(args) -> int:
     f_scale = COPY_BYTES / (merged[copy]["FETCH_SIZE"] * 1024.0)
     w_scale = COPY_BYTES / (merged[copy]["WRITE_SIZE"] * 1024.0)
     n, _, mesh, p, _ = WORKLOADS[args.workload]
-    out = os.path.join(ROOT, "profiles", f"kernels_{args.workload}_counters.txt")
+    step = bool(args.counter_step)
+    out = os.path.join(ROOT, "profiles", f"kernels_{args.workload}{'_step' if step else ''}_counters.txt")
+    flags = STEP_COUNTER_FLAGS if step else COUNTER_FLAGS
+    call = ("concurrent pme_step (under the counters each kernel runs alone on the GPU)" if step
+            else "two-call step (pme_forward; pme_backward, each kernel alone on the GPU)")
     lines = [
-        f"# rocprofv3 counters of the PME kernels, two-call step (pme_forward; pme_backward, each",
-        f"# kernel alone on the GPU), {n}-ion molten-salt box, mesh {mesh[0]}^3, p = {p}, one MI355X",
+        f"# rocprofv3 counters of the PME kernels, {call},",
+        f"# {n}-ion molten-salt box, mesh {mesh[0]}^3, p = {p}, one MI355X",
         "# commands (repository root), one run per counter pass:",
     ]
     for i, ps in enumerate(COUNTER_PASSES):
         lines.append(f"#   rocprofv3 --pmc {ps} --output-format csv -d <D{i + 1}> -o run -- "
-                     f"python -u bench.py {COUNTER_FLAGS} --workload {args.workload}")
+                     f"python -u bench.py {flags} --workload {args.workload}")
     lines += [
-        "#   python bench.py --counter-summary <D1> <D2> <D3> <D4> <D5> --workload " + args.workload,
+        "#   python bench.py --counter-summary <D1> <D2> <D3> <D4> <D5> --workload " + args.workload
+        + (" --counter-step 1" if step else ""),
         "# per wave: instructions issued per wavefront (SQ_INSTS_* / SQ_WAVES);",
         "# lds_bytes = 64 * (SQ_INSTS_LDS_{LOAD,STORE,ATOMIC}_BANDWIDTH) per launch;",
         "# bank_conflict = SQ_LDS_BANK_CONFLICT / (SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT)",
@@ -1083,7 +1095,9 @@ def counter_summary(args) -> int:
     order = [KERNEL_SYMBOL[k] for k in ("bin", "bin_tangent", "spread", "spread_tangent")]
     order += [FUSED_SYMBOL[k] for k in ("spread", "spread_tangent")]
     order += [BAND_SYMBOL[k] for k in ("spread", "spread_tangent")]
+    order += [FUSED_STEP_SPREAD, BAND_STEP_SPREAD]
     order += [KERNEL_SYMBOL[k] for k in ("fft_r2c", "fft_x", "fft_c2r", "gather", "gather_hvp")]
+    order += ["k_gather_hvp<6, true>"]
     for k in order:
         if k not in merged:
             continue
@@ -1498,19 +1512,23 @@ def read_kernel_stats(workload: str, symbol: str):
 
 
 def read_lds_bytes(workload: str, symbol: str):
-    """LDS bytes per launch of `symbol` from the committed counter summary of the
-    workload, when it was taken on the current sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"kernels_{workload}_counters.txt")
-    if not os.path.exists(path):
-        return None
-    digest, val = None, None
-    with open(path) as fh:
-        for ln in fh:
-            if "source digest" in ln:
-                digest = ln.rsplit(":", 1)[1].strip()
-            elif ln.startswith("lds_bytes_per_launch " + symbol):
-                val = float(ln.rsplit(None, 1)[1])
-    return val if digest == source_digest() else None
+    """LDS bytes per launch of `symbol` from the committed counter summaries of the
+    workload (two-call step, then concurrent step), when taken on the current sources;
+    else None."""
+    for name in (f"kernels_{workload}_counters.txt", f"kernels_{workload}_step_counters.txt"):
+        path = os.path.join(ROOT, "profiles", name)
+        if not os.path.exists(path):
+            continue
+        digest, val = None, None
+        with open(path) as fh:
+            for ln in fh:
+                if "source digest" in ln:
+                    digest = ln.rsplit(":", 1)[1].strip()
+                elif ln.startswith("lds_bytes_per_launch " + symbol + " "):
+                    val = float(ln.rsplit(None, 1)[1])
+        if val is not None and digest == source_digest():
+            return val
+    return None
 
 
 if __name__ == "__main__":
