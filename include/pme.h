@@ -76,7 +76,7 @@ extern "C" {
  * sinc^(-2 gamma p) deconvolution of Eq. influence (influence_power is then
  * unused):  g(f) = sum_m U^2(f + m N) G(k(f + m N)) / (sum_m U^2(f + m N))^2,
  * U(f) = prod_a sinc(f_a / N_a)^p, m in {-1, 0, 1}^3.  Not with pme_forward_cell
- * or batches (PME_EINVAL). */
+ * (PME_EINVAL); in a batch, every box or none. */
 #define PME_F_OPT_INFLUENCE 4
 /* Spread the density by mesh tiles and transform it in a separate pass.  Without
  * this flag, a plan whose y-z plane, padded by p - 1 rows and columns, fits in LDS
@@ -350,12 +350,14 @@ int pme_plan_spread_kind(pme_plan_t plan);
 typedef struct pme_batch_s* pme_batch_t;
 
 /* The plan of a batch (Sec. 2.3.1 per box, Sec. 2.4 for the batch): descs[b]
- * describes box b (its flags are ignored: the backward always reuses the
- * potential of the preceding pme_batch_forward); n_atoms[b] >= 0 is its atom
- * count.  Host arrays of nbox entries, read during the call; *out receives the
- * batch (NULL on failure), released by pme_batch_destroy.  PME_EORDER if the
- * orders differ, PME_EMESH if a mesh does not fit, PME_EINVAL for the optimal
- * influence function or more than 2^31 - 1 atoms in all, PME_ENOMEM/PME_EHIP. */
+ * describes box b (of its flags only PME_F_OPT_INFLUENCE counts, and it must be
+ * set on every box or none; the backward always reuses the potential of the
+ * preceding pme_batch_forward); n_atoms[b] >= 0 is its atom count.  Host arrays
+ * of nbox entries, read during the call; *out receives the batch (NULL on
+ * failure), released by pme_batch_destroy.  PME_EORDER if the orders differ,
+ * PME_EMESH if a mesh does not fit, PME_EINVAL if the boxes disagree on the
+ * optimal influence function or hold more than 2^31 - 1 atoms in all,
+ * PME_ENOMEM/PME_EHIP. */
 int pme_batch_plan(const pme_desc_t* descs, int32_t nbox, const int32_t* n_atoms,
                      pme_batch_t* out);
 void pme_batch_destroy(pme_batch_t batch);

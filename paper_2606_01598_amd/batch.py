@@ -18,7 +18,8 @@ from .pme import _ptr, _stream
 
 class Batch:
     def __init__(self, meshes, n_atoms, order: int, alpha: float, influence_power: float = 1.0,
-                 prefactor: float = 1.0, tiles=None, device=None, fft_lines=None):
+                 prefactor: float = 1.0, tiles=None, device=None, fft_lines=None,
+                 optimal_influence: bool = False):
         self._lib = _lib.load()
         self.device = torch.device("cuda", 0) if device is None else torch.device(device)
         nbox = len(meshes)
@@ -31,7 +32,7 @@ class Batch:
             d.fft_lines = 0 if fft_lines is None else int(fft_lines[b])
             d.order = int(order)
             d.max_atoms = max(1, int(n_atoms[b]))
-            d.flags = _lib.PME_F_KEEP_PHI
+            d.flags = _lib.PME_F_KEEP_PHI | (_lib.PME_F_OPT_INFLUENCE if optimal_influence else 0)
             d.alpha = float(alpha)
             d.influence_power = float(influence_power)
             d.prefactor = float(prefactor)

@@ -1066,7 +1066,7 @@ int pme_batch_plan(const pme_desc_t* descs, int32_t nbox, const int32_t* n_atoms
   for (int b = 0; b < nbox; ++b) {
     if (n_atoms[b] < 0) return PME_EINVAL;
     if (descs[b].order != descs[0].order) return PME_EORDER;
-    if (descs[b].flags & PME_F_OPT_INFLUENCE) return PME_EINVAL;
+    if ((descs[b].flags ^ descs[0].flags) & PME_F_OPT_INFLUENCE) return PME_EINVAL;
   }
   pme_batch_s* bt = new (std::nothrow) pme_batch_s();
   if (!bt) return PME_ENOMEM;
@@ -1078,7 +1078,7 @@ int pme_batch_plan(const pme_desc_t* descs, int32_t nbox, const int32_t* n_atoms
   std::vector<DevPlan> dp(nbox);
   for (int b = 0; b < nbox; ++b) {
     pme_desc_t d = descs[b];
-    d.flags = PME_F_KEEP_PHI;
+    d.flags = PME_F_KEEP_PHI | (descs[0].flags & PME_F_OPT_INFLUENCE);
     d.max_atoms = n_atoms[b] > 0 ? n_atoms[b] : 1;
     const int rc = pme_plan(&d, &bt->plans[b]);
     if (rc != PME_OK) {

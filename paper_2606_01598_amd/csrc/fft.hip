@@ -911,12 +911,13 @@ __global__ void __launch_bounds__(kSlabThreads) k_slab_inv_batch(const SlabArgs*
   }
 }
 
+template <int MODE>
 __global__ void __launch_bounds__(kFFTThreads) k_fftx_batch(const XArgs* args, const int2* items,
                                                             int n, const double* box, int energy) {
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const int2 w = items[it];
     const XArgs& a = args[w.x];
-    fftx_body(a, w.y, box + 9 * w.x, energy ? a.epart : nullptr);
+    fftx_body<MODE>(a, w.y, box + 9 * w.x, energy ? a.epart : nullptr);
     __syncthreads();
   }
 }
@@ -1143,9 +1144,10 @@ hipError_t fft_batch_build(const DevPlan* plans, int nbox, FFTBatch& t) {
   std::vector<SlabArgs> s0(nbox), s1(nbox);
   std::vector<XArgs> xa(nbox);
   std::vector<int2> si, xi;
+  t.opt = nbox > 0 && plans[0].opt;
   for (int b = 0; b < nbox; ++b) {
     const DevPlan& d = plans[b];
-    if (!d.slab) return hipErrorInvalidValue;
+    if (!d.slab || d.opt != t.opt) return hipErrorInvalidValue;
     s0[b] = make_slab_args(d, d.phi);
     s1[b] = make_slab_args(d, d.rho);
     xa[b] = make_x_args(d, nullptr, true);
@@ -1181,9 +1183,14 @@ hipError_t launch_convolve_batch(const FFTBatch& t, hipStream_t s, const double*
                      t.slab_lds, s, sa, t.slab_items, t.n_slab_items);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fftx_batch, fft_batch_grid(t.n_x_items, 2048), dim3(kFFTThreads), t.x_lds,
-                     s, static_cast<const XArgs*>(t.x), t.x_items, t.n_x_items, box,
-                     energy ? 1 : 0);
+  if (t.opt)
+    hipLaunchKernelGGL(k_fftx_batch<2>, fft_batch_grid(t.n_x_items, 2048), dim3(kFFTThreads),
+                       t.x_lds, s, static_cast<const XArgs*>(t.x), t.x_items, t.n_x_items, box,
+                       energy ? 1 : 0);
+  else
+    hipLaunchKernelGGL(k_fftx_batch<0>, fft_batch_grid(t.n_x_items, 2048), dim3(kFFTThreads),
+                       t.x_lds, s, static_cast<const XArgs*>(t.x), t.x_items, t.n_x_items, box,
+                       energy ? 1 : 0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_slab_inv_batch, fft_batch_grid(t.n_slab_items, 512), dim3(kSlabThreads),
                      t.slab_lds, s, sa, t.slab_items, t.n_slab_items);

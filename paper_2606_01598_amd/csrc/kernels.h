@@ -211,6 +211,7 @@ struct FFTBatch {
   int2* x_items = nullptr;
   int n_x_items = 0;
   size_t slab_lds = 0, x_lds = 0;
+  bool opt = false;                     // every box with the optimal influence function
 };
 struct GatherBatch {
   int p = 0;

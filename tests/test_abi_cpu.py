@@ -168,3 +168,14 @@ def test_halo_probe_rejects_bad_arguments():
     ]
     for kind, n, t, p, reg, mesh in cases:
         assert lib.pme_halo_probe(None, kind, n, t, p, reg, mesh) == _lib.PME_EINVAL
+
+
+def test_batch_plan_rejects_mixed_influence_functions():
+    # every box uses the optimal influence function or none; the check comes before
+    # any device work
+    lib = _lib_or_skip()
+    descs = (_lib.PMEDesc * 2)(_desc(), _desc(flags=_lib.PME_F_OPT_INFLUENCE))
+    n = (ctypes.c_int32 * 2)(10, 10)
+    h = ctypes.c_void_p()
+    assert lib.pme_batch_plan(descs, 2, n, ctypes.byref(h)) == _lib.PME_EINVAL
+    assert not h.value

@@ -43,12 +43,13 @@ def _close(a, b):
     return float(np.abs(a - b).max() / scale)
 
 
-def _batch_step(frames, meshes, seed, tiles=None, lines=None):
+def _batch_step(frames, meshes, seed, tiles=None, lines=None, opt=False):
     """forward, H v and force-loss H v of the batch and of one plan per box"""
     from paper_2606_01598_amd.batch import Batch
     from paper_2606_01598_amd.pme import Plan
     pos, q, mu, box, vr, vq, vm, vf = _pack(frames, seed)
-    bt = Batch(meshes, [f.n for f in frames], 6, 0.3, tiles=tiles, fft_lines=lines)
+    bt = Batch(meshes, [f.n for f in frames], 6, 0.3, tiles=tiles, fft_lines=lines,
+               optimal_influence=opt)
     fo = bt.forward(pos, q, mu, box)
     bo = bt.backward(pos, q, mu, box, vr, vq, vm)
     bf = bt.backward(pos, q, mu, box, vf, None, None)
@@ -58,7 +59,7 @@ def _batch_step(frames, meshes, seed, tiles=None, lines=None):
         s0, s1 = int(bt.offsets[b]), int(bt.offsets[b + 1])
         c = lambda t: t[s0:s1].contiguous()
         pl = Plan(m, 6, 0.3, max_atoms=max(1, f.n), tile=None if tiles is None else tiles[b],
-                  fft_lines=None if lines is None else lines[b])
+                  fft_lines=None if lines is None else lines[b], optimal_influence=opt)
         o = pl.forward(c(pos), c(q), c(mu), box[b].contiguous())
         ob = pl.backward(c(pos), c(q), c(mu), box[b].contiguous(), c(vr), c(vq), c(vm))
         of = pl.backward(c(pos), c(q), c(mu), box[b].contiguous(), c(vf), None, None)
@@ -87,6 +88,32 @@ def test_batch_equals_single_plans_64_boxes():
                       flush=True)
     print("batch vs single plans, 64 boxes: outputs differing", nbits, flush=True)
     assert nbits == 0
+
+
+def test_batch_optimal_influence_equals_single_plans_and_oracle():
+    """The optimal influence function in a batch (each box with its own g tables):
+    every output of every box equals that of one plan per box with the same influence
+    function, bit for bit; box 0 matches the oracle with that influence; a second
+    forward with the boxes unchanged (tables read back) repeats the first."""
+    frames, meshes = _boxes(6, seed=9)
+    print("case: batch with the optimal influence function, 6 boxes", flush=True)
+    bt, (pos, q, mu, box, *_), (fo, bo, bf), single = _batch_step(frames, meshes, seed=5,
+                                                                 opt=True)
+    for b, (o, ob, of) in enumerate(single):
+        s0, s1 = int(bt.offsets[b]), int(bt.offsets[b + 1])
+        assert torch.equal(fo["energy"][b], o["energy"]), b
+        for k in ("dE_dpos", "dE_dq", "dE_dmu"):
+            assert torch.equal(fo[k][s0:s1], o[k]), (b, k)
+        for k in ("g_pos", "g_q", "g_mu"):
+            assert torch.equal(bo[k][s0:s1], ob[k]), (b, k)
+            assert torch.equal(bf[k][s0:s1], of[k]), (b, "f" + k)
+    ref = oracle_forward(frames[0], meshes[0], 6, 0.3, gamma="optimal")
+    s0, s1 = int(bt.offsets[0]), int(bt.offsets[1])
+    assert rel(host(fo["energy"][0]).sum(), ref.energy) <= E_REL_TOL
+    assert rms_rel(host(fo["dE_dpos"][s0:s1]), ref.dE_dpos) <= RMS_REL_TOL
+    fo2 = bt.forward(pos, q, mu, box)
+    for k in fo:
+        assert torch.equal(fo2[k], fo[k]), k
 
 
 def test_batch_with_tuned_geometry_equals_single_plans_and_oracle():
