@@ -64,6 +64,7 @@ def test_fused_spread_equals_tile_spread(case, mesh, p):
     outs = []
     for separate in (False, True):
         plan = Plan(mesh, p, alpha, max_atoms=len(f.q), separate_spread=separate)
+        assert plan.spread_kind == ("tile" if separate else "fused"), (case, plan.spread_kind)
         plan.timer("fft_r2c")
         o = {k: x.clone() for k, x in plan.forward(pos, q, mu, box).items()}
         launches, _ = plan.timer_read()
